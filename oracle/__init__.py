@@ -1,0 +1,118 @@
+"""CPU oracle for the sort library -- TEST INFRASTRUCTURE ONLY.
+
+A ctypes view of ``liboracle.so`` (built from ``bcf_oracle.c`` by
+``oracle/build.py``).  It is imported only by the tests, by the smoke check and
+by the benchmark's CPU-baseline leg; the GPU path neither imports nor links it.
+
+Each function follows the problem statement it names (Sitchinava & Weichert,
+Sec. 3: sort n keys ascending; Sec. 3.2: merge sorted sequences); see the C file
+for the algorithm.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"oracle library not built: {LIB_PATH} (run oracle/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_sort_u32.argtypes = [u32p, u32p, ctypes.c_uint64]
+    lib.oracle_sort_u32.restype = ctypes.c_int
+    lib.oracle_sort_pairs_u32.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_uint64]
+    lib.oracle_sort_pairs_u32.restype = ctypes.c_int
+    lib.oracle_merge_runs.argtypes = [u32p, u32p, u64p, ctypes.c_uint32, u32p, u32p]
+    lib.oracle_merge_runs.restype = ctypes.c_int
+    lib.oracle_segmented_sort.argtypes = [u32p, u32p, u64p, ctypes.c_uint32]
+    lib.oracle_segmented_sort.restype = ctypes.c_int
+    lib.oracle_multiset_hash.argtypes = [u32p, u32p, ctypes.c_uint64, u64p, u64p]
+    lib.oracle_multiset_hash.restype = None
+    lib.oracle_is_sorted_u32.argtypes = [u32p, ctypes.c_uint64]
+    lib.oracle_is_sorted_u32.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p32(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _p64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _u32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+
+
+def sort_u32(keys) -> np.ndarray:
+    """Ascending sort of u32 keys (top-down merge sort)."""
+    k = _u32(keys)
+    out = np.empty_like(k)
+    if k.size and _load().oracle_sort_u32(_p32(k), _p32(out), k.size) != 0:
+        raise MemoryError("oracle_sort_u32")
+    return out
+
+
+def sort_pairs_u32(keys, vals):
+    """Stable sort of (key, value) pairs by key."""
+    k, v = _u32(keys), _u32(vals)
+    assert k.shape == v.shape
+    ko, vo = np.empty_like(k), np.empty_like(v)
+    if k.size and _load().oracle_sort_pairs_u32(_p32(k), _p32(v), _p32(ko), _p32(vo), k.size) != 0:
+        raise MemoryError("oracle_sort_pairs_u32")
+    return ko, vo
+
+
+def merge_runs(keys, offsets, vals=None):
+    """Stable k-way merge of the sorted runs [off[r], off[r+1])."""
+    k = _u32(keys)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    nr = off.size - 1
+    ko = np.empty_like(k)
+    v = _u32(vals) if vals is not None else None
+    vo = np.empty_like(v) if v is not None else None
+    if nr > 0 and _load().oracle_merge_runs(_p32(k), _p32(v), _p64(off), nr, _p32(ko), _p32(vo)) != 0:
+        raise ValueError("oracle_merge_runs: bad offsets")
+    return (ko, vo) if v is not None else ko
+
+
+def segmented_sort(keys, offsets) -> np.ndarray:
+    """Sort every segment [off[s], off[s+1]) independently."""
+    k = _u32(keys)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    ko = np.empty_like(k)
+    ns = off.size - 1
+    if ns > 0 and _load().oracle_segmented_sort(_p32(k), _p32(ko), _p64(off), ns) != 0:
+        raise ValueError("oracle_segmented_sort: bad offsets")
+    return ko
+
+
+def multiset_hash(keys, vals=None):
+    """(sum, xor) order-independent hash of the (key, value) multiset."""
+    k = _u32(keys)
+    v = _u32(vals) if vals is not None else None
+    s, x = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _load().oracle_multiset_hash(_p32(k), _p32(v), k.size, ctypes.byref(s), ctypes.byref(x))
+    return int(s.value), int(x.value)
+
+
+def is_sorted_u32(keys) -> bool:
+    k = _u32(keys)
+    return bool(_load().oracle_is_sorted_u32(_p32(k), k.size))

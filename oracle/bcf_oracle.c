@@ -1,0 +1,237 @@
+/*
+ * CPU oracle for the bank-conflict-free sort library -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously correct C.  Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg load this library; the GPU path never calls
+ * it and shares no code with it.
+ *
+ * What it computes (Sitchinava & Weichert, "Bank Conflict Free Comparison-based
+ * Sorting On GPUs", problem statement of Sec. 3 and the pseudocode appendix,
+ * which sort ascending; the binary merge of Sec. 3.2):
+ *   - oracle_sort_u32         the nondecreasing permutation of n u32 keys;
+ *   - oracle_sort_pairs_u32   key/value pairs ordered by key, equal keys kept in
+ *                             input order (stable): lexicographic order on
+ *                             (key, original index);
+ *   - oracle_merge_runs       the stable sort of the concatenation of k sorted
+ *                             runs, i.e. a k-way merge where ties go to the
+ *                             lower run index and then the earlier position;
+ *   - oracle_segmented_sort   oracle_sort_u32 applied to every segment.
+ * Keys compare as unsigned 32-bit integers (the paper does not fix signedness).
+ *
+ * Algorithm: top-down merge sort (split in halves, sort each, merge taking the
+ * left element on ties), with a scratch buffer.  No blocking, no networks.
+ *
+ * Also: an order-independent multiset hash used to check that an output is a
+ * permutation of its input at sizes where element-wise comparison is costly.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- keys only ---------------------------------------------------------- */
+
+/* merge src[lo,mid) and src[mid,hi) into dst[lo,hi); left wins ties */
+static void merge_keys(const uint32_t *src, uint32_t *dst, size_t lo, size_t mid, size_t hi)
+{
+    size_t i = lo, j = mid, o = lo;
+    while (i < mid && j < hi) {
+        if (src[i] <= src[j])
+            dst[o++] = src[i++];
+        else
+            dst[o++] = src[j++];
+    }
+    while (i < mid)
+        dst[o++] = src[i++];
+    while (j < hi)
+        dst[o++] = src[j++];
+}
+
+/* sort a[lo,hi) in place, using tmp[lo,hi) as scratch */
+static void msort_keys(uint32_t *a, uint32_t *tmp, size_t lo, size_t hi)
+{
+    if (hi - lo < 2)
+        return;
+    size_t mid = lo + (hi - lo) / 2;
+    msort_keys(a, tmp, lo, mid);
+    msort_keys(a, tmp, mid, hi);
+    merge_keys(a, tmp, lo, mid, hi);
+    memcpy(a + lo, tmp + lo, (hi - lo) * sizeof(uint32_t));
+}
+
+/* out may alias in.  Returns 0 on success, -1 if scratch cannot be allocated. */
+int oracle_sort_u32(const uint32_t *in, uint32_t *out, uint64_t n)
+{
+    if (n == 0)
+        return 0;
+    uint32_t *tmp = (uint32_t *)malloc(n * sizeof(uint32_t));
+    if (!tmp)
+        return -1;
+    if (out != in)
+        memcpy(out, in, n * sizeof(uint32_t));
+    msort_keys(out, tmp, 0, n);
+    free(tmp);
+    return 0;
+}
+
+/* ---- key/value pairs (stable) ------------------------------------------- */
+
+static void merge_pairs(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv,
+                        size_t lo, size_t mid, size_t hi)
+{
+    size_t i = lo, j = mid, o = lo;
+    while (i < mid && j < hi) {
+        if (sk[i] <= sk[j]) {
+            dk[o] = sk[i];
+            dv[o] = sv[i];
+            i++;
+        } else {
+            dk[o] = sk[j];
+            dv[o] = sv[j];
+            j++;
+        }
+        o++;
+    }
+    while (i < mid) {
+        dk[o] = sk[i];
+        dv[o] = sv[i];
+        i++;
+        o++;
+    }
+    while (j < hi) {
+        dk[o] = sk[j];
+        dv[o] = sv[j];
+        j++;
+        o++;
+    }
+}
+
+static void msort_pairs(uint32_t *k, uint32_t *v, uint32_t *tk, uint32_t *tv, size_t lo, size_t hi)
+{
+    if (hi - lo < 2)
+        return;
+    size_t mid = lo + (hi - lo) / 2;
+    msort_pairs(k, v, tk, tv, lo, mid);
+    msort_pairs(k, v, tk, tv, mid, hi);
+    merge_pairs(k, v, tk, tv, lo, mid, hi);
+    memcpy(k + lo, tk + lo, (hi - lo) * sizeof(uint32_t));
+    memcpy(v + lo, tv + lo, (hi - lo) * sizeof(uint32_t));
+}
+
+int oracle_sort_pairs_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                          uint32_t *vout, uint64_t n)
+{
+    if (n == 0)
+        return 0;
+    uint32_t *tk = (uint32_t *)malloc(n * sizeof(uint32_t));
+    uint32_t *tv = (uint32_t *)malloc(n * sizeof(uint32_t));
+    if (!tk || !tv) {
+        free(tk);
+        free(tv);
+        return -1;
+    }
+    if (kout != kin)
+        memcpy(kout, kin, n * sizeof(uint32_t));
+    if (vout != vin)
+        memcpy(vout, vin, n * sizeof(uint32_t));
+    msort_pairs(kout, vout, tk, tv, 0, n);
+    free(tk);
+    free(tv);
+    return 0;
+}
+
+/* ---- k-way merge of sorted runs ------------------------------------------ */
+
+/*
+ * Runs r = 0..k-1 occupy [off[r], off[r+1]) of kin (and vin when not NULL).
+ * Repeatedly emits the smallest head key; among equal heads the lowest run
+ * index wins, and within a run elements leave in order, so the result is the
+ * stable sort of the concatenation.  O(n*k).  Returns -1 on bad offsets.
+ */
+int oracle_merge_runs(const uint32_t *kin, const uint32_t *vin, const uint64_t *off, uint32_t k,
+                      uint32_t *kout, uint32_t *vout)
+{
+    if (k == 0)
+        return 0;
+    if (off[0] != 0)
+        return -1;
+    for (uint32_t r = 0; r < k; r++)
+        if (off[r + 1] < off[r])
+            return -1;
+    uint64_t n = off[k];
+    uint64_t *cur = (uint64_t *)malloc((size_t)k * sizeof(uint64_t));
+    if (!cur)
+        return -1;
+    for (uint32_t r = 0; r < k; r++)
+        cur[r] = off[r];
+    for (uint64_t o = 0; o < n; o++) {
+        int64_t best = -1;
+        for (uint32_t r = 0; r < k; r++) {
+            if (cur[r] == off[r + 1])
+                continue;
+            if (best < 0 || kin[cur[r]] < kin[cur[best]])
+                best = (int64_t)r;
+        }
+        kout[o] = kin[cur[best]];
+        if (vin && vout)
+            vout[o] = vin[cur[best]];
+        cur[best]++;
+    }
+    free(cur);
+    return 0;
+}
+
+/* ---- segmented sort -------------------------------------------------------- */
+
+int oracle_segmented_sort(const uint32_t *kin, uint32_t *kout, const uint64_t *off, uint32_t nseg)
+{
+    if (nseg == 0)
+        return 0;
+    if (off[0] != 0)
+        return -1;
+    for (uint32_t s = 0; s < nseg; s++) {
+        if (off[s + 1] < off[s])
+            return -1;
+        int rc = oracle_sort_u32(kin + off[s], kout + off[s], off[s + 1] - off[s]);
+        if (rc)
+            return rc;
+    }
+    return 0;
+}
+
+/* ---- checks ----------------------------------------------------------------- */
+
+/* SplitMix64 output function, used only as a hash mixer */
+static uint64_t mix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/*
+ * Order-independent multiset hash of (key, value) elements (value 0 when vals is
+ * NULL): sum and xor of mix64(key ^ (value * golden)), modulo 2^64.
+ */
+void oracle_multiset_hash(const uint32_t *keys, const uint32_t *vals, uint64_t n, uint64_t *sum_out,
+                          uint64_t *xor_out)
+{
+    uint64_t s = 0, x = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t v = vals ? (uint64_t)vals[i] : 0;
+        uint64_t h = mix64((uint64_t)keys[i] ^ (v * 0x9E3779B97F4A7C15ull));
+        s += h;
+        x ^= h;
+    }
+    *sum_out = s;
+    *xor_out = x;
+}
+
+/* 1 if keys[0..n) is nondecreasing */
+int oracle_is_sorted_u32(const uint32_t *keys, uint64_t n)
+{
+    for (uint64_t i = 1; i < n; i++)
+        if (keys[i - 1] > keys[i])
+            return 0;
+    return 1;
+}

@@ -1,0 +1,264 @@
+"""Pins for the CPU oracle: checks against what the mathematics fixes, not
+against the oracle's own formula.
+
+* brute force over every permutation of small distinct inputs and every word
+  over {0,1,2}, compared with the order-statistic definition of sorting
+  (output[i] is the value v with #{x < v} <= i < #{x <= v});
+* library special cases (numpy.sort, numpy.argsort(kind="stable"), Python's
+  sorted on (key, index) tuples);
+* invariants (nondecreasing, permutation-preserving, stability);
+* merge of sorted runs == stable sort of their concatenation (the paper's
+  binary merge of Sec. 3.2 generalised to k runs), k = 1 is the identity;
+* planted mistakes: mutated copies of the oracle source, built here on the CPU,
+  must each fail at least one of these pins.
+"""
+
+import ctypes
+import itertools
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def order_statistics(xs):
+    """Sorted output by the counting definition (no sort routine involved)."""
+    xs = list(xs)
+    n = len(xs)
+    out = [None] * n
+    for v in set(xs):
+        lt = sum(1 for x in xs if x < v)
+        le = sum(1 for x in xs if x <= v)
+        for i in range(lt, le):
+            out[i] = v
+    return out
+
+
+# ---------------------------------------------------------------- sort_u32
+
+
+@pytest.mark.parametrize("n", range(0, 8))
+def test_sort_every_permutation(oracle_mod, n):
+    ident = np.arange(n, dtype=np.uint32)
+    for perm in itertools.permutations(range(n)):
+        got = oracle_mod.sort_u32(np.array(perm, dtype=np.uint32))
+        assert np.array_equal(got, ident), perm
+
+
+def test_sort_every_permutation_of_8_sampled_keys(oracle_mod):
+    keys = np.array([0, 7, 0xFFFFFFFF, 3, 0x80000000, 12, 0x7FFFFFFF, 1], dtype=np.uint32)
+    want = np.array(order_statistics(keys.tolist()), dtype=np.uint32)
+    for perm in itertools.permutations(range(8)):
+        got = oracle_mod.sort_u32(keys[list(perm)])
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_sort_every_ternary_word(oracle_mod, n):
+    for word in itertools.product((0, 1, 2), repeat=n):
+        got = oracle_mod.sort_u32(np.array(word, dtype=np.uint32)).tolist()
+        assert got == order_statistics(word), word
+
+
+def test_sort_unsigned_order_extremes(oracle_mod):
+    keys = np.array([0xFFFFFFFF, 0, 0x80000000, 0x7FFFFFFF, 0xFFFFFFFF, 1, 0], dtype=np.uint32)
+    got = oracle_mod.sort_u32(keys).tolist()
+    assert got == [0, 0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFF, 0xFFFFFFFF]
+
+
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS + workloads.PAPER_DISTRIBUTIONS)
+@pytest.mark.parametrize("n", [1, 2, 3, 100, 4095, 4097, 1 << 16])
+def test_sort_matches_numpy(oracle_mod, dist, n):
+    keys = workloads.keys_u32(dist, n, seed=3)
+    assert np.array_equal(oracle_mod.sort_u32(keys), np.sort(keys, kind="stable"))
+
+
+def test_sort_matches_numpy_large(oracle_mod):
+    keys = workloads.keys_u32("uniform", 1 << 20, seed=11)
+    got = oracle_mod.sort_u32(keys)
+    assert np.array_equal(got, np.sort(keys))
+    assert oracle_mod.is_sorted_u32(got)
+    assert oracle_mod.multiset_hash(got) == oracle_mod.multiset_hash(keys)
+
+
+# ---------------------------------------------------------------- pairs (stable)
+
+
+@pytest.mark.parametrize("n", range(0, 8))
+def test_pairs_every_ternary_word_stable(oracle_mod, n):
+    for word in itertools.product((0, 1, 2), repeat=n):
+        keys = np.array(word, dtype=np.uint32)
+        vals = np.arange(n, dtype=np.uint32) * 7 + 5
+        ko, vo = oracle_mod.sort_pairs_u32(keys, vals)
+        want = sorted(zip(word, range(n)))  # lexicographic (key, original index)
+        assert ko.tolist() == [k for k, _ in want]
+        assert vo.tolist() == [int(vals[i]) for _, i in want]
+
+
+@pytest.mark.parametrize("dist", ["uniform", "distinct16", "zipf", "paper_01", "paper_dups"])
+def test_pairs_match_numpy_stable_argsort(oracle_mod, dist):
+    keys, vals = workloads.pairs_u32(dist, 50_000, seed=5)
+    vals = vals ^ np.uint32(0xA5A5A5A5)  # values need not be indices
+    ko, vo = oracle_mod.sort_pairs_u32(keys, vals)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(ko, keys[order])
+    assert np.array_equal(vo, vals[order])
+
+
+# ---------------------------------------------------------------- merge of runs
+
+
+def _stable_concat_sort(keys, vals):
+    order = np.argsort(keys, kind="stable")
+    return keys[order], vals[order]
+
+
+@pytest.mark.parametrize("sizes", [[5], [0], [3, 4], [0, 6], [6, 0], [1, 1, 1],
+                                   [4, 0, 3, 0, 5], [2] * 17, list(range(17))])
+def test_merge_runs_small(oracle_mod, sizes):
+    keys, offs = workloads.sorted_runs(sizes, seed=2, dist="dups")
+    vals = np.arange(keys.size, dtype=np.uint32)
+    ko, vo = oracle_mod.merge_runs(keys, offs, vals)
+    ek, ev = _stable_concat_sort(keys, vals)
+    assert np.array_equal(ko, ek) and np.array_equal(vo, ev)
+
+
+def test_merge_runs_bruteforce_two_runs(oracle_mod):
+    # every pair of sorted ternary runs of lengths <= 4: result must be the
+    # order-statistic sort, and equal keys must leave run 0 before run 1.
+    runs = [tuple(sorted(w)) for m in range(5) for w in itertools.product((0, 1, 2), repeat=m)]
+    runs = sorted(set(runs))
+    for a in runs:
+        for b in runs:
+            keys = np.array(a + b, dtype=np.uint32)
+            offs = np.array([0, len(a), len(a) + len(b)], dtype=np.uint64)
+            vals = np.arange(keys.size, dtype=np.uint32)
+            ko, vo = oracle_mod.merge_runs(keys, offs, vals)
+            assert ko.tolist() == order_statistics(a + b)
+            want = [i for _, i in sorted(zip(a + b, range(len(a + b))))]
+            assert vo.tolist() == want
+
+
+def test_merge_single_run_is_identity(oracle_mod):
+    keys, offs = workloads.sorted_runs([1000], seed=4)
+    assert np.array_equal(oracle_mod.merge_runs(keys, offs), keys)
+
+
+def test_merge_runs_rejects_bad_offsets(oracle_mod):
+    keys = np.arange(10, dtype=np.uint32)
+    with pytest.raises(ValueError):
+        oracle_mod.merge_runs(keys, np.array([0, 6, 4, 10], dtype=np.uint64))
+
+
+# ---------------------------------------------------------------- segmented
+
+
+def test_segmented_sort(oracle_mod):
+    sizes = [0, 1, 2, 0, 37, 4096, 5000, 1]
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    keys = workloads.keys_u32("uniform", int(offs[-1]), seed=9)
+    got = oracle_mod.segmented_sort(keys, offs)
+    for s in range(len(sizes)):
+        lo, hi = int(offs[s]), int(offs[s + 1])
+        assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi]))
+
+
+# ---------------------------------------------------------------- multiset hash
+
+
+def test_multiset_hash_permutation_invariant_and_sensitive(oracle_mod):
+    keys, vals = workloads.pairs_u32("zipf", 10_000, seed=8)
+    h = oracle_mod.multiset_hash(keys, vals)
+    perm = np.random.Generator(np.random.PCG64(1)).permutation(keys.size)
+    assert oracle_mod.multiset_hash(keys[perm], vals[perm]) == h
+    k2 = keys.copy()
+    k2[17] ^= 1
+    assert oracle_mod.multiset_hash(k2, vals) != h
+    v2 = vals.copy()
+    v2[3], v2[4] = v2[4], v2[3]  # swapping values between different keys
+    if keys[3] != keys[4]:
+        assert oracle_mod.multiset_hash(keys, v2) != h
+
+
+# ---------------------------------------------------------------- planted mistakes
+
+MUTANTS = {
+    # ties in the pair merge taken from the right: no longer stable
+    "unstable_pairs": ("if (sk[i] <= sk[j]) {", "if (sk[i] < sk[j]) {"),
+    # right tail of a merge dropped: elements lost
+    "drop_tail": ("    while (j < hi)\n        dst[o++] = src[j++];\n", ""),
+    # merge_runs ties go to the highest run
+    "merge_ties_high_run": ("kin[cur[r]] < kin[cur[best]]", "kin[cur[r]] <= kin[cur[best]]"),
+    # descending comparison
+    "descending": ("if (src[i] <= src[j])", "if (src[i] >= src[j])"),
+    # right half sorted from one past the split: its first element is skipped
+    "skip_split_element": ("msort_keys(a, tmp, mid, hi);", "msort_keys(a, tmp, mid + 1, hi);"),
+}
+
+
+def _pins_pass(lib) -> bool:
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+
+    def p(a):
+        return a.ctypes.data_as(u32p)
+
+    ok = True
+    # sort pin: ternary words of length 6 against order statistics
+    for word in itertools.product((0, 1, 2), repeat=6):
+        k = np.array(word, dtype=np.uint32)
+        o = np.empty_like(k)
+        lib.oracle_sort_u32(p(k), p(o), ctypes.c_uint64(k.size))
+        if o.tolist() != order_statistics(word):
+            ok = False
+            break
+    # stability pin
+    if ok:
+        keys, vals = workloads.pairs_u32("distinct16", 2000, seed=1)
+        ko, vo = np.empty_like(keys), np.empty_like(vals)
+        lib.oracle_sort_pairs_u32(p(keys), p(vals), p(ko), p(vo), ctypes.c_uint64(keys.size))
+        order = np.argsort(keys, kind="stable")
+        ok = np.array_equal(ko, keys[order]) and np.array_equal(vo, vals[order])
+    # merge pin
+    if ok:
+        keys, offs = workloads.sorted_runs([7, 0, 9, 4], seed=3, dist="dups")
+        vals = np.arange(keys.size, dtype=np.uint32)
+        ko, vo = np.empty_like(keys), np.empty_like(vals)
+        lib.oracle_merge_runs(p(keys), p(vals), offs.ctypes.data_as(u64p), ctypes.c_uint32(4), p(ko), p(vo))
+        ek, ev = _stable_concat_sort(keys, vals)
+        ok = np.array_equal(ko, ek) and np.array_equal(vo, ev)
+    return ok
+
+
+def _build_variant(tmp_path, name, src_text):
+    import oracle.build as ob
+
+    src = tmp_path / f"{name}.c"
+    src.write_text(src_text)
+    out = tmp_path / f"lib{name}.so"
+    ob.build(out=str(out), src=str(src))
+    lib = ctypes.CDLL(str(out))
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_sort_u32.argtypes = [u32p, u32p, ctypes.c_uint64]
+    lib.oracle_sort_pairs_u32.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_uint64]
+    lib.oracle_merge_runs.argtypes = [u32p, u32p, u64p, ctypes.c_uint32, u32p, u32p]
+    return lib
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_planted_mistakes_are_caught(tmp_path):
+    here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "bcf_oracle.c")
+    text = open(here).read()
+    assert _pins_pass(_build_variant(tmp_path, "pristine", text))
+    for name, (old, new) in MUTANTS.items():
+        assert old in text, f"mutant {name} no longer applies"
+        lib = _build_variant(tmp_path, name, text.replace(old, new, 1))
+        assert not _pins_pass(lib), f"planted mistake {name!r} was not caught"

@@ -1,0 +1,58 @@
+"""Seeded generators: deterministic, slice-consistent, and shaped as stated."""
+
+import numpy as np
+import pytest
+
+import workloads
+
+
+def test_splitmix64_reference_values():
+    # SplitMix64 with state 0: the first outputs of the published reference
+    # generator (state += gamma; mix) are 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4.
+    x = np.array([0, 0x9E3779B97F4A7C15], dtype=np.uint64)
+    got = workloads.splitmix64(x)
+    assert int(got[0]) == 0xE220A8397B1DCDAF
+    assert int(got[1]) == 0x6E789E6AA1B965F4
+
+
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS + workloads.PAPER_DISTRIBUTIONS)
+def test_deterministic(dist):
+    a = workloads.keys_u32(dist, 5000, seed=7)
+    b = workloads.keys_u32(dist, 5000, seed=7)
+    c = workloads.keys_u32(dist, 5000, seed=8)
+    assert a.dtype == np.uint32 and a.shape == (5000,)
+    assert np.array_equal(a, b)
+    if dist not in ("paper_01",):
+        assert not np.array_equal(a, c)
+
+
+def test_slices_consistent():
+    full = workloads.draws_u32(3, 10000)
+    part = workloads.draws_u32(3, 100, start=5000)
+    assert np.array_equal(full[5000:5100], part)
+
+
+def test_shapes_of_distributions():
+    n = 1 << 16
+    s = workloads.keys_u32("sorted", n)
+    assert np.all(s[1:] > s[:-1])
+    r = workloads.keys_u32("reverse", n)
+    assert np.array_equal(r, s[::-1])
+    assert len(np.unique(workloads.keys_u32("distinct16", n))) == 16
+    z = workloads.keys_u32("zipf", n)
+    _, counts = np.unique(z, return_counts=True)
+    # rank 1 has probability 1/H(1.2, 2^20) ~ 0.20
+    assert 0.15 < counts.max() / n < 0.25
+    assert set(np.unique(workloads.keys_u32("paper_01", n)).tolist()) == {0, 1}
+    d = workloads.keys_u32("paper_distinct", n)
+    assert np.array_equal(np.sort(d), np.arange(1, n + 1, dtype=np.uint32))
+    assert workloads.keys_u32("paper_random", n).max() <= 10**6
+
+
+def test_segment_sizes_and_runs():
+    sz = workloads.segment_sizes(10000)
+    assert sz.min() >= 32 and sz.max() <= 1 << 20
+    keys, offs = workloads.sorted_runs([5, 0, 7], seed=1)
+    assert offs.tolist() == [0, 5, 5, 12]
+    assert np.all(np.diff(keys[:5].astype(np.int64)) >= 0)
+    assert np.all(np.diff(keys[5:].astype(np.int64)) >= 0)
