@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark: sort throughput of 2^26 u32 keys on one MI355X.
+
+One step = one full sort (block sort + every merge pass) of a 2^26-key array
+resident in HBM; the timed steps cycle through the five seeded distributions
+(uniform, sorted, reverse, 16 distinct values, Zipf(1.2) over 2^20 ranks).
+Inputs, outputs and scratch are allocated before timing; no host transfer is
+inside the timed region.
+
+Prints ONE JSON line with the headline value (Gkeys/s), the roofline of the
+dominant kernel (merge pass, HBM bound) measured live with HIP events on the
+launch stream, and the CPU oracle timed on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+N_KEYS = 1 << 26
+KERNEL_SOURCES = [
+    os.path.join(ROOT, "paper_1306_5076_amd", "csrc", f)
+    for f in ("bcf_device.hpp", "bcf_kernels.hip", "bcf_internal.hpp")
+]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_counters(name: str):
+    """Counter summary committed under profiles/ for the current kernel sources, else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec
+
+
+def cpu_baseline(keys_np):
+    """The CPU oracle (single-threaded merge sort) on one full 2^26-key array."""
+    import oracle
+
+    reps = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        oracle.sort_u32(keys_np)
+        reps.append(time.perf_counter() - t0)
+    t = sorted(reps)[len(reps) // 2]
+    return {
+        "value": round(keys_np.size / t / 1e9, 4),
+        "unit": "Gkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one {keys_np.size}-key uniform u32 array (seed 1), top-down merge sort, "
+        f"best of {len(reps)} runs = {min(reps):.2f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=N_KEYS)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(
+            "bench.py measures one GPU only: this build has no multi-GPU path "
+            "(the sort of one array runs on one MI355X); run with --gpus 1.",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1306_5076_amd as bcf
+    import workloads
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    dists = list(workloads.DISTRIBUTIONS)
+    host = {d: workloads.keys_u32(d, n, seed=1) for d in dists}
+    src = {d: torch.from_numpy(host[d]).to(dev) for d in dists}
+    out = torch.empty(n, dtype=torch.uint32, device=dev)
+    ws = bcf.Workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(i):
+        bcf.sort_u32(src[dists[i % len(dists)]], out=out, stream=stream, workspace=ws)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n * args.steps / elapsed / 1e9
+
+    # per-distribution time (events on the launch stream)
+    per_dist = {}
+    for d in dists:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record(stream)
+        for _ in range(reps):
+            bcf.sort_u32(src[d], out=out, stream=stream, workspace=ws)
+        e1.record(stream)
+        e1.synchronize()
+        per_dist[d] = round(e0.elapsed_time(e1) / reps, 4)
+
+    # roofline of the dominant kernel: per-launch HIP events around each launch
+    bcf.profile_collect()
+    bcf.profile_enable(True)
+    for i in range(args.profile_steps):
+        step(i)
+    bcf.profile_enable(False)
+    stats = bcf.profile_collect()
+    dominant = max(stats, key=lambda k: stats[k]["total_ms"])
+    st = stats[dominant]
+    avg_ms = st["total_ms"] / st["launches"]
+    bytes_per_launch = st["bytes"] / st["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernels = {
+        k: {
+            "launches": v["launches"],
+            "avg_us": round(1e3 * v["total_ms"] / v["launches"], 2),
+            "GB_per_s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1),
+        }
+        for k, v in stats.items()
+    }
+    traffic_rec = committed_counters("traffic_merge_keys_2p26.json")
+    conflicts_rec = committed_counters("lds_conflicts_2p26.json")
+
+    rec = {
+        "metric": "Gkeys/s + HBM GB/s frac at 2^26 uint32; LDS bank conflicts; p99 served latency",
+        "value": round(value, 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sort 2^26 uint32 keys (one array per step, cycling uniform / sorted / reverse / "
+            "16-distinct / zipf1.2 over 2^20 ranks, seed 1)",
+            "n": n,
+            "distributions": dists,
+            "tile_keys": bcf.tile_keys(),
+            "launches_per_sort": bcf.sort_launches(n),
+        },
+        "per_distribution_ms": per_dist,
+        "roofline": {
+            "kernel": dominant,
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_rec["bytes_per_launch"] if traffic_rec else None,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": round(avg_ms * 1e3, 2),
+        },
+        "kernels": kernels,
+        "overall_hbm_frac": round(
+            sum(v["bytes"] for v in stats.values()) / (sum(v["total_ms"] for v in stats.values()) * 1e-3) / 1e9
+            / HBM_PEAK_GBS,
+            4,
+        ),
+        "lds_bank_conflicts": conflicts_rec["per_kernel"] if conflicts_rec else None,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(host["uniform"])
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

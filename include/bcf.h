@@ -1,0 +1,134 @@
+/*
+ * bcf.h -- C ABI of the MI355X (gfx950) bank-conflict-free comparison sort.
+ *
+ * Operations follow the problem statements of Sitchinava & Weichert, "Bank
+ * Conflict Free Comparison-based Sorting On GPUs": sort n keys ascending
+ * (Sec. 3, base case plus merging phase), merge sorted sequences larger than
+ * on-chip memory (Sec. 3.2, binary merging), extended to key/value pairs
+ * (stable) and to many independent segments in one call.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Keys are uint32_t compared as unsigned integers; order is ascending.
+ *  - Key/value arrays are device pointers (HBM) owned by the caller.  Offset
+ *    arrays (run_offsets, seg_offsets) are HOST pointers: the library plans the
+ *    launches on the host from them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    call only enqueues work on that stream and returns; it never synchronises
+ *    the device.  Faults of earlier asynchronous work can surface as
+ *    BCF_ERR_DEVICE on a later call.
+ *  - Temporary storage: call once with temp == NULL to receive the number of
+ *    bytes needed in *temp_bytes (nothing is launched, BCF_OK is returned);
+ *    then pass a device buffer of at least that many bytes, 256-byte aligned,
+ *    with *temp_bytes holding its size.  A smaller buffer yields
+ *    BCF_ERR_TEMP_TOO_SMALL.  The library performs no device allocation.  The
+ *    temp buffer must not be touched by other work until the call's kernels
+ *    have finished (stream order guarantees this for same-stream users).
+ *  - Inputs are never modified.  keys_out may equal keys_in (and vals_out may
+ *    equal vals_in); any other overlap between inputs, outputs and temp is
+ *    undefined.
+ *  - n == 0 (or k == 0 / nseg == 0) is a no-op returning BCF_OK.  Sizes above
+ *    2^32 - 1 elements return BCF_ERR_INVALID.
+ *  - Offsets: off[0] == 0, nondecreasing, off[last] == total length.  Empty
+ *    runs / segments are allowed.  Violations return BCF_ERR_INVALID.
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef BCF_H
+#define BCF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BCF_OK = 0,
+    BCF_ERR_INVALID = 1,        /* bad argument: NULL pointer, size, offsets */
+    BCF_ERR_TEMP_TOO_SMALL = 2, /* *temp_bytes smaller than required */
+    BCF_ERR_NOMEM = 3,          /* host-side staging could not be allocated */
+    BCF_ERR_DEVICE = 4,         /* a HIP runtime call or a kernel launch failed */
+    BCF_ERR_UNSORTED_RUN = 5    /* merge_runs with BCF_CHECK=1: an input run is not sorted */
+} bcf_status;
+
+/*
+ * Sort n keys ascending (the paper's BCFMergesort: base case of tile sorts in
+ * LDS, Sec. 3.1, then binary merge passes over HBM, Sec. 3.2).
+ *   keys_in   device, n u32, read only
+ *   keys_out  device, n u32, receives the sorted keys (may equal keys_in)
+ *   temp      device scratch (see conventions) or NULL to query *temp_bytes
+ */
+bcf_status bcf_sort_u32(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n, void *temp,
+                        uint64_t *temp_bytes, void *stream);
+
+/*
+ * Stable sort of key/value pairs by key: equal keys keep their input order,
+ * i.e. the result is ordered by (key, original index).  An extension of the
+ * paper, whose data sets are keys only.
+ *   keys_in, vals_in    device, n u32 each, read only
+ *   keys_out, vals_out  device, n u32 each (may equal the inputs)
+ */
+bcf_status bcf_sort_pairs_u32(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                              uint32_t *vals_out, uint64_t n, void *temp, uint64_t *temp_bytes,
+                              void *stream);
+
+/*
+ * Merge k sorted runs into one sorted sequence (the paper's binary merging of
+ * sorted sequences larger than on-chip memory, Sec. 3.2, applied pairwise in
+ * ceil(log2 k) passes).  Stable: among equal keys, lower run index first, then
+ * earlier position.
+ *   keys_in      device, run r occupies [run_offsets[r], run_offsets[r+1])
+ *   vals_in      device values carried with the keys, or NULL for keys only
+ *   run_offsets  HOST, k+1 entries
+ *   keys_out     device, run_offsets[k] u32
+ *   vals_out     device (ignored when vals_in is NULL)
+ * Every run must be sorted ascending (precondition).  With the environment
+ * variable BCF_CHECK=1 the library checks it and returns BCF_ERR_UNSORTED_RUN
+ * (this check synchronises the stream).
+ */
+bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+                          uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp,
+                          uint64_t *temp_bytes, void *stream);
+
+/*
+ * Sort every segment [seg_offsets[s], seg_offsets[s+1]) of keys_in
+ * independently, with one block-sort launch for all segments and one launch
+ * per merge level shared by all segments still being merged.
+ *   seg_offsets  HOST, nseg+1 entries
+ */
+bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
+                              uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *bcf_status_string(bcf_status s);
+
+/* Keys per tile of the block sort and of one merge-pass work item, for keys
+ * only (pairs = 0) or key/value pairs (pairs = 1). */
+uint32_t bcf_tile_keys(int pairs);
+
+/* Number of kernel launches (block sort + merge passes) a sort of n keys uses. */
+uint32_t bcf_sort_launches(uint64_t n);
+
+/*
+ * Per-kernel timing.  While enabled, every launch the library makes is
+ * bracketed by two HIP events recorded on the launch's stream.
+ * bcf_profile_collect synchronises on those events, fills up to `max` records
+ * (one per kernel name) and clears the accumulators.  `bytes` is the
+ * algorithmic HBM traffic the launches were planned to move (inputs read once,
+ * outputs written once).  Returns the number of records, or -1 on error.
+ */
+typedef struct {
+    char name[48];
+    uint64_t launches;
+    double total_ms;
+    double bytes;
+} bcf_kernel_stat;
+
+void bcf_profile_enable(int on);
+int bcf_profile_collect(bcf_kernel_stat *out, int max);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCF_H */

@@ -1,0 +1,27 @@
+"""MI355X (gfx950) bank-conflict-free comparison sort.
+
+HIP kernels behind a C ABI (include/bcf.h, libbcf.so); this package adds the
+torch-tensor front end.  Importing it does not touch the GPU.
+"""
+
+import importlib
+
+from ._native import EXPORTED, LIB_PATH, BcfError  # noqa: F401
+
+_API = (
+    "Workspace",
+    "sort_u32",
+    "sort_pairs_u32",
+    "merge_runs",
+    "segmented_sort",
+    "tile_keys",
+    "sort_launches",
+    "profile_enable",
+    "profile_collect",
+)
+
+
+def __getattr__(name):
+    if name in _API:
+        return getattr(importlib.import_module(__name__ + ".api"), name)
+    raise AttributeError(name)

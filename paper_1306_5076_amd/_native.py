@@ -1,0 +1,97 @@
+"""ctypes view of libbcf.so (the C ABI declared in include/bcf.h).
+
+Only argument marshalling lives here: every step of a sort runs in the HIP
+kernels of the library.  There is no fallback: if the library is missing or a
+call fails, an exception is raised.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbcf.so")
+
+BCF_OK = 0
+STATUS_NAMES = {
+    0: "BCF_OK",
+    1: "BCF_ERR_INVALID",
+    2: "BCF_ERR_TEMP_TOO_SMALL",
+    3: "BCF_ERR_NOMEM",
+    4: "BCF_ERR_DEVICE",
+    5: "BCF_ERR_UNSORTED_RUN",
+}
+
+# every symbol include/bcf.h declares
+EXPORTED = (
+    "bcf_sort_u32",
+    "bcf_sort_pairs_u32",
+    "bcf_merge_runs",
+    "bcf_segmented_sort",
+    "bcf_status_string",
+    "bcf_tile_keys",
+    "bcf_sort_launches",
+    "bcf_profile_enable",
+    "bcf_profile_collect",
+)
+
+
+class BcfError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed: {msg}")
+        self.status = status
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 48),
+        ("launches", ctypes.c_uint64),
+        ("total_ms", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (after torch, so that both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library not built: {path}. Run __graft_entry__.build() (hipcc, gfx950) first."
+        )
+    try:  # torch first: its libamdhip64 then also serves libbcf.so
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.bcf_sort_u32.argtypes = [vp, vp, u64, vp, u64p, vp]
+    lib.bcf_sort_pairs_u32.argtypes = [vp, vp, vp, vp, u64, vp, u64p, vp]
+    lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
+    lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
+    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_segmented_sort"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.bcf_status_string.argtypes = [ctypes.c_int]
+    lib.bcf_status_string.restype = ctypes.c_char_p
+    lib.bcf_tile_keys.argtypes = [ctypes.c_int]
+    lib.bcf_tile_keys.restype = u32
+    lib.bcf_sort_launches.argtypes = [u64]
+    lib.bcf_sort_launches.restype = u32
+    lib.bcf_profile_enable.argtypes = [ctypes.c_int]
+    lib.bcf_profile_enable.restype = None
+    lib.bcf_profile_collect.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int]
+    lib.bcf_profile_collect.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(fn: str, status: int):
+    if status != BCF_OK:
+        msg = load().bcf_status_string(status).decode()
+        raise BcfError(fn, status, msg)

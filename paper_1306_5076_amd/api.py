@@ -1,0 +1,223 @@
+"""Torch-tensor front end of the C ABI (include/bcf.h).
+
+Tensors must be contiguous uint32 (or int32, reinterpreted bit-for-bit) CUDA
+tensors on the same device.  Work is enqueued on ``stream`` (default: torch's
+current stream); the calls return without synchronising.  Temporary storage
+comes from torch's caching allocator through :class:`Workspace`.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._native import KernelStat, check, load
+
+__all__ = [
+    "Workspace",
+    "sort_u32",
+    "sort_pairs_u32",
+    "merge_runs",
+    "segmented_sort",
+    "tile_keys",
+    "sort_launches",
+    "profile_enable",
+    "profile_collect",
+]
+
+_U32 = (torch.uint32, torch.int32)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+def _stream(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return stream, ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_tensor(t, name, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype not in _U32:
+        raise TypeError(f"{name} must be uint32 or int32, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _offsets(off, total=None):
+    a = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
+    if a.ndim != 1 or a.size < 1:
+        raise ValueError("offsets must be a 1-D sequence with at least one entry")
+    if total is not None and int(a[-1]) != total:
+        raise ValueError(f"last offset {int(a[-1])} != number of keys {total}")
+    return a
+
+
+class Workspace:
+    """A reusable device scratch buffer (grows on demand, never shrinks)."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device) if device is not None else None
+        self.buf = None
+
+    def get(self, nbytes: int, device, stream=None):
+        if nbytes == 0:
+            return None
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        if stream is not None and stream != torch.cuda.current_stream(device):
+            self.buf.record_stream(stream)
+        return self.buf
+
+
+def _temp(ws, nbytes, device, stream):
+    if nbytes == 0:
+        return None, ctypes.c_uint64(0)
+    if ws is None:
+        buf = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        if stream != torch.cuda.current_stream(device):
+            buf.record_stream(stream)
+    else:
+        buf = ws.get(nbytes, device, stream)
+    return buf, ctypes.c_uint64(buf.numel())
+
+
+def tile_keys(pairs: bool = False) -> int:
+    """Keys per block-sort tile (and per merge work item)."""
+    return int(load().bcf_tile_keys(1 if pairs else 0))
+
+
+def sort_launches(n: int) -> int:
+    """Kernel launches (block sort + merge passes) of a sort of n keys."""
+    return int(load().bcf_sort_launches(n))
+
+
+def sort_u32(keys, out=None, stream=None, workspace=None):
+    """Ascending sort of u32 keys; returns ``out``."""
+    lib = load()
+    _check_tensor(keys, "keys")
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_tensor(out, "out", keys.device)
+    if out.numel() != n:
+        raise ValueError("out must have as many elements as keys")
+    stream, sh = _stream(stream, keys.device)
+    need = ctypes.c_uint64(0)
+    check("bcf_sort_u32", lib.bcf_sort_u32(None, None, n, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        check(
+            "bcf_sort_u32",
+            lib.bcf_sort_u32(_ptr(keys), _ptr(out), n, _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh),
+        )
+    return out
+
+
+def sort_pairs_u32(keys, vals, keys_out=None, vals_out=None, stream=None, workspace=None):
+    """Stable sort of (key, value) pairs by key; returns (keys_out, vals_out)."""
+    lib = load()
+    _check_tensor(keys, "keys")
+    _check_tensor(vals, "vals", keys.device)
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and vals must have the same length")
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    _check_tensor(keys_out, "keys_out", keys.device)
+    _check_tensor(vals_out, "vals_out", keys.device)
+    stream, sh = _stream(stream, keys.device)
+    need = ctypes.c_uint64(0)
+    check("bcf_sort_pairs_u32", lib.bcf_sort_pairs_u32(None, None, None, None, n, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        check(
+            "bcf_sort_pairs_u32",
+            lib.bcf_sort_pairs_u32(
+                _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), n,
+                _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh,
+            ),
+        )
+    return keys_out, vals_out
+
+
+def merge_runs(keys, run_offsets, vals=None, keys_out=None, vals_out=None, stream=None, workspace=None):
+    """Stable merge of the sorted runs [off[r], off[r+1]) of ``keys``.
+
+    ``run_offsets`` is a host sequence of k+1 offsets.  Returns ``keys_out``,
+    or ``(keys_out, vals_out)`` when ``vals`` is given.
+    """
+    lib = load()
+    _check_tensor(keys, "keys")
+    n = keys.numel()
+    off = _offsets(run_offsets, n)
+    k = off.size - 1
+    if vals is not None:
+        _check_tensor(vals, "vals", keys.device)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    stream, sh = _stream(stream, keys.device)
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    need = ctypes.c_uint64(0)
+    vdummy = ctypes.c_void_p(1) if vals is not None else None
+    check("bcf_merge_runs", lib.bcf_merge_runs(None, vdummy, offp, k, None, None, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        check(
+            "bcf_merge_runs",
+            lib.bcf_merge_runs(
+                _ptr(keys), _ptr(vals), offp, k, _ptr(keys_out), _ptr(vals_out),
+                _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh,
+            ),
+        )
+    return (keys_out, vals_out) if vals is not None else keys_out
+
+
+def segmented_sort(keys, seg_offsets, out=None, stream=None, workspace=None):
+    """Sort every segment [off[s], off[s+1]) of ``keys`` independently."""
+    lib = load()
+    _check_tensor(keys, "keys")
+    n = keys.numel()
+    off = _offsets(seg_offsets, n)
+    nseg = off.size - 1
+    out = torch.empty_like(keys) if out is None else out
+    stream, sh = _stream(stream, keys.device)
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    need = ctypes.c_uint64(0)
+    check("bcf_segmented_sort", lib.bcf_segmented_sort(None, None, offp, nseg, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        check(
+            "bcf_segmented_sort",
+            lib.bcf_segmented_sort(
+                _ptr(keys), _ptr(out), offp, nseg, _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh
+            ),
+        )
+    return out
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library launch with HIP events (see bcf_profile_collect)."""
+    load().bcf_profile_enable(1 if on else 0)
+
+
+def profile_collect():
+    """Per-kernel {name: {launches, total_ms, bytes}} since the last collect."""
+    buf = (KernelStat * 32)()
+    n = load().bcf_profile_collect(buf, 32)
+    if n < 0:
+        raise RuntimeError("bcf_profile_collect failed")
+    return {
+        buf[i].name.decode(): {"launches": int(buf[i].launches), "total_ms": buf[i].total_ms, "bytes": buf[i].bytes}
+        for i in range(n)
+    }

@@ -1,0 +1,553 @@
+// C ABI of the bank-conflict-free sort: argument checking, host-side pass
+// planning, descriptor upload and kernel launches.  See include/bcf.h.
+//
+// Plan of a sort of n keys (BCFMergesort, paper Sec. 3 and Lemma 2):
+//   one block-sort launch turns [0, n) into ceil(n / 4096) sorted runs, then
+//   ceil(log2(#runs)) binary merge passes double the run length until one run
+//   remains.  Passes ping-pong between the output and the temp buffer; the
+//   block sort writes to whichever buffer makes the last pass end in the
+//   output.  Every launch is enqueued on the caller's stream; nothing
+//   synchronises the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bcf.h"
+#include "bcf_device.hpp"
+#include "bcf_internal.hpp"
+
+using namespace bcf;
+
+namespace {
+
+constexpr uint64_t kMaxN = 0xFFFFFFFFull;
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+uint32_t ceil_log2(uint64_t x)
+{
+    uint32_t p = 0;
+    while ((uint64_t(1) << p) < x)
+        ++p;
+    return p;
+}
+
+uint64_t tiles_of(uint64_t n) { return (n + kTile - 1) / kTile; }
+
+// ------------------------------------------------------------------ profiling
+
+struct ProfRec {
+    hipEvent_t a, b;
+    double bytes;
+};
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, std::vector<ProfRec>> g_prof;
+
+struct ProfScope {
+    const char *name;
+    hipStream_t s;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on;
+    ProfScope(const char *nm, hipStream_t st, double by) : name(nm), s(st), bytes(by)
+    {
+        {
+            std::lock_guard<std::mutex> g(g_prof_mu);
+            on = g_prof_on;
+        }
+        if (on) {
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                on = false;
+                return;
+            }
+            (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope()
+    {
+        if (!on)
+            return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        g_prof[name].push_back({a, b, bytes});
+    }
+};
+
+// ------------------------------------------------------- descriptor staging
+
+// Pinned host buffers holding descriptor tables while their host-to-device
+// copy is in flight.  A buffer is reused once the event recorded after its
+// copy has completed.
+struct Staging {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+std::mutex g_stage_mu;
+std::vector<Staging> g_stage;
+
+// Copy `bytes` from host memory `src` to device `dst` on stream `s` through a
+// pinned staging buffer.
+bcf_status upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0)
+        return BCF_OK;
+    std::lock_guard<std::mutex> g(g_stage_mu);
+    Staging *slot = nullptr;
+    for (auto &st : g_stage) {
+        if (st.cap >= bytes && hipEventQuery(st.done) == hipSuccess) {
+            slot = &st;
+            break;
+        }
+    }
+    if (!slot) {
+        Staging st;
+        st.cap = std::max<size_t>(bytes, 1 << 20);
+        if (hipHostMalloc(&st.ptr, st.cap, hipHostMallocDefault) != hipSuccess)
+            return BCF_ERR_NOMEM;
+        if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess)
+            return BCF_ERR_DEVICE;
+        g_stage.push_back(st);
+        slot = &g_stage.back();
+    }
+    std::memcpy(slot->ptr, src, bytes);
+    if (hipMemcpyAsync(dst, slot->ptr, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        return BCF_ERR_DEVICE;
+    if (hipEventRecord(slot->done, s) != hipSuccess)
+        return BCF_ERR_DEVICE;
+    return BCF_OK;
+}
+
+bcf_status dev_status(hipError_t e) { return e == hipSuccess ? BCF_OK : BCF_ERR_DEVICE; }
+
+#define BCF_TRY(x)                          \
+    do {                                    \
+        bcf_status st_ = (x);               \
+        if (st_ != BCF_OK)                  \
+            return st_;                     \
+    } while (0)
+
+bool offsets_valid(const uint64_t *off, uint32_t k)
+{
+    if (!off || off[0] != 0)
+        return false;
+    for (uint32_t r = 0; r < k; ++r)
+        if (off[r + 1] < off[r])
+            return false;
+    return off[k] <= kMaxN;
+}
+
+// ---------------------------------------------------- full sort (regular)
+
+// Sort keys (and values) with the regular plan.  temp holds the ping-pong
+// key buffer followed by the value buffer.
+bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                     uint64_t n, void *temp, uint64_t *temp_bytes, hipStream_t s)
+{
+    if (!temp_bytes || n > kMaxN)
+        return BCF_ERR_INVALID;
+    const uint64_t tiles = tiles_of(n);
+    const uint32_t passes = n ? ceil_log2(tiles) : 0;
+    const uint64_t need = passes ? align256(n * 4) * (pairs ? 2 : 1) : 0;
+    if (!temp) {
+        *temp_bytes = need;
+        return BCF_OK;
+    }
+    if (n == 0)
+        return BCF_OK;
+    if (!kin || !kout || (pairs && (!vin || !vout)))
+        return BCF_ERR_INVALID;
+    if (*temp_bytes < need)
+        return BCF_ERR_TEMP_TOO_SMALL;
+    uint32_t *kt = static_cast<uint32_t *>(temp);
+    uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + align256(n * 4)) : nullptr;
+    // X_j = buffer after pass j; X_passes = out.
+    auto kbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? kout : kt; };
+    auto vbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? vout : vt; };
+    const double elem_bytes = pairs ? 8.0 : 4.0;
+    {
+        ProfScope p(kname_block_sort(pairs, false), s, 2.0 * elem_bytes * n);
+        BCF_TRY(dev_status(launch_block_sort_regular(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, s)));
+    }
+    uint64_t run = kTile;
+    for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
+        ProfScope p(kname_merge(pairs, false), s, 2.0 * elem_bytes * n);
+        BCF_TRY(dev_status(launch_merge_regular(pairs, kbuf(j - 1), pairs ? vbuf(j - 1) : nullptr, kbuf(j),
+                                                pairs ? vbuf(j) : nullptr, n, run, s)));
+    }
+    return BCF_OK;
+}
+
+// ---------------------------------------------------- table-driven plans
+
+struct MergePass {
+    std::vector<MergeJob> jobs;
+    std::vector<uint32_t> tile_job;
+};
+
+// Add one binary merge job A=[a, a+na), B=[a+na, a+na+nb) to a pass.
+void add_job(MergePass &mp, uint64_t a, uint64_t na, uint64_t nb, uint32_t src, uint32_t dst)
+{
+    const uint64_t tot = na + nb;
+    if (tot == 0)
+        return;
+    MergeJob j;
+    j.a_start = a;
+    j.na = (uint32_t)na;
+    j.nb = (uint32_t)nb;
+    j.first_tile = (uint32_t)mp.tile_job.size();
+    j.src = (uint16_t)src;
+    j.dst = (uint16_t)dst;
+    const uint32_t id = (uint32_t)mp.jobs.size();
+    mp.jobs.push_back(j);
+    for (uint64_t t = 0; t < tiles_of(tot); ++t)
+        mp.tile_job.push_back(id);
+}
+
+// Device layout of the descriptor tables inside temp, after the data buffers.
+struct TableLayout {
+    uint64_t block_off = 0, block_bytes = 0;
+    std::vector<uint64_t> jobs_off, map_off;
+    uint64_t total = 0;
+};
+
+TableLayout layout_tables(uint64_t base, size_t nblock, const std::vector<MergePass> &passes)
+{
+    TableLayout L;
+    uint64_t o = base;
+    L.block_off = o;
+    L.block_bytes = nblock * sizeof(BlockTile);
+    o = align256(o + L.block_bytes);
+    for (const auto &mp : passes) {
+        L.jobs_off.push_back(o);
+        o = align256(o + mp.jobs.size() * sizeof(MergeJob));
+        L.map_off.push_back(o);
+        o = align256(o + mp.tile_job.size() * sizeof(uint32_t));
+    }
+    L.total = o;
+    return L;
+}
+
+// Pack every table into one host image and upload it with one copy.
+bcf_status upload_tables(char *temp, const TableLayout &L, const std::vector<BlockTile> &blocks,
+                         const std::vector<MergePass> &passes, hipStream_t s)
+{
+    const uint64_t lo = L.block_off;
+    const uint64_t bytes = L.total - lo;
+    if (bytes == 0)
+        return BCF_OK;
+    std::vector<char> img(bytes, 0);
+    if (!blocks.empty())
+        std::memcpy(img.data() + (L.block_off - lo), blocks.data(), L.block_bytes);
+    for (size_t p = 0; p < passes.size(); ++p) {
+        if (!passes[p].jobs.empty())
+            std::memcpy(img.data() + (L.jobs_off[p] - lo), passes[p].jobs.data(),
+                        passes[p].jobs.size() * sizeof(MergeJob));
+        if (!passes[p].tile_job.empty())
+            std::memcpy(img.data() + (L.map_off[p] - lo), passes[p].tile_job.data(),
+                        passes[p].tile_job.size() * sizeof(uint32_t));
+    }
+    return upload(temp + lo, img.data(), bytes, s);
+}
+
+bcf_status run_tables(bool pairs, Bufs kb, Bufs vb, char *temp, const TableLayout &L,
+                      const std::vector<BlockTile> &blocks, const std::vector<MergePass> &passes,
+                      uint64_t n, hipStream_t s)
+{
+    BCF_TRY(upload_tables(temp, L, blocks, passes, s));
+    const double eb = pairs ? 8.0 : 4.0;
+    if (!blocks.empty()) {
+        double moved = 0;
+        for (const auto &b : blocks)
+            moved += 2.0 * eb * b.count;
+        ProfScope p(kname_block_sort(pairs, true), s, moved);
+        BCF_TRY(dev_status(launch_block_sort_table(pairs, kb, vb, reinterpret_cast<const BlockTile *>(temp + L.block_off),
+                                                   (uint32_t)blocks.size(), s)));
+    }
+    for (size_t p = 0; p < passes.size(); ++p) {
+        const auto &mp = passes[p];
+        if (mp.tile_job.empty())
+            continue;
+        double moved = 0;
+        for (const auto &j : mp.jobs)
+            moved += 2.0 * eb * (double(j.na) + j.nb);
+        ProfScope ps(kname_merge(pairs, true), s, moved);
+        BCF_TRY(dev_status(launch_merge_table(pairs, kb, vb, reinterpret_cast<const MergeJob *>(temp + L.jobs_off[p]),
+                                              reinterpret_cast<const uint32_t *>(temp + L.map_off[p]),
+                                              (uint32_t)mp.tile_job.size(), s)));
+    }
+    (void)n;
+    return BCF_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char *bcf_status_string(bcf_status s)
+{
+    switch (s) {
+    case BCF_OK: return "BCF_OK";
+    case BCF_ERR_INVALID: return "BCF_ERR_INVALID: invalid argument";
+    case BCF_ERR_TEMP_TOO_SMALL: return "BCF_ERR_TEMP_TOO_SMALL: temp buffer smaller than required";
+    case BCF_ERR_NOMEM: return "BCF_ERR_NOMEM: host staging allocation failed";
+    case BCF_ERR_DEVICE: return "BCF_ERR_DEVICE: HIP runtime or launch failure";
+    case BCF_ERR_UNSORTED_RUN: return "BCF_ERR_UNSORTED_RUN: an input run is not sorted";
+    }
+    return "BCF_ERR_UNKNOWN";
+}
+
+uint32_t bcf_tile_keys(int pairs)
+{
+    (void)pairs;
+    return (uint32_t)kTile;
+}
+
+uint32_t bcf_sort_launches(uint64_t n)
+{
+    if (n == 0)
+        return 0;
+    return 1 + ceil_log2(tiles_of(n));
+}
+
+bcf_status bcf_sort_u32(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n, void *temp,
+                        uint64_t *temp_bytes, void *stream)
+{
+    return sort_impl(false, keys_in, nullptr, keys_out, nullptr, n, temp, temp_bytes,
+                     static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_sort_pairs_u32(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                              uint32_t *vals_out, uint64_t n, void *temp, uint64_t *temp_bytes, void *stream)
+{
+    return sort_impl(true, keys_in, vals_in, keys_out, vals_out, n, temp, temp_bytes,
+                     static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+                          uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp, uint64_t *temp_bytes,
+                          void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!temp_bytes)
+        return BCF_ERR_INVALID;
+    if (k == 0) {
+        if (!temp)
+            *temp_bytes = 0;
+        return BCF_OK;
+    }
+    if (!offsets_valid(run_offsets, k))
+        return BCF_ERR_INVALID;
+    const bool pairs = vals_in != nullptr;
+    const uint64_t n = run_offsets[k];
+    // nonempty runs, in order (empty runs change nothing, stability included)
+    std::vector<std::pair<uint64_t, uint64_t>> runs;
+    for (uint32_t r = 0; r < k; ++r)
+        if (run_offsets[r + 1] > run_offsets[r])
+            runs.push_back({run_offsets[r], run_offsets[r + 1] - run_offsets[r]});
+    const uint32_t P = runs.size() > 1 ? ceil_log2(runs.size()) : 0;
+    // In place with an odd pass count would make pass 1 read and write the
+    // output; then every pass is shifted by one buffer and a final copy moves
+    // the result from temp to the output.
+    const bool inplace = keys_in == keys_out;
+    const bool shift = inplace && (P % 2 == 1);
+    // buffer after pass j (j >= 1): counted back from the last pass
+    auto buf_after = [&](uint32_t j) -> uint32_t {
+        const bool at_out = ((P - j) % 2 == 0) != shift;
+        return at_out ? kBufOut : kBufTemp;
+    };
+    std::vector<MergePass> passes(P);
+    std::vector<std::pair<uint64_t, uint64_t>> cur = runs;
+    for (uint32_t j = 1; j <= P; ++j) {
+        const uint32_t src = j == 1 ? kBufIn : buf_after(j - 1);
+        const uint32_t dst = buf_after(j);
+        std::vector<std::pair<uint64_t, uint64_t>> next;
+        for (size_t i = 0; i < cur.size(); i += 2) {
+            const uint64_t a = cur[i].first, na = cur[i].second;
+            const uint64_t nb = i + 1 < cur.size() ? cur[i + 1].second : 0;
+            add_job(passes[j - 1], a, na, nb, src, dst);
+            next.push_back({a, na + nb});
+        }
+        cur.swap(next);
+    }
+    const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
+    TableLayout L = layout_tables(P ? data : 0, 0, passes);
+    // small area for the optional sortedness check: run offsets and a flag
+    const uint64_t check_off = L.total;
+    const uint64_t need = check_off + align256((uint64_t(k) + 1) * sizeof(uint64_t)) + 256;
+    if (!temp) {
+        *temp_bytes = need;
+        return BCF_OK;
+    }
+    if (n == 0)
+        return BCF_OK;
+    if (!keys_in || !keys_out || (pairs && !vals_out))
+        return BCF_ERR_INVALID;
+    if (*temp_bytes < need)
+        return BCF_ERR_TEMP_TOO_SMALL;
+    char *tb = static_cast<char *>(temp);
+    uint32_t *kt = reinterpret_cast<uint32_t *>(tb);
+    uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(tb + align256(n * 4)) : nullptr;
+
+    if (std::getenv("BCF_CHECK") && std::atoi(std::getenv("BCF_CHECK")) == 1) {
+        // sortedness of every run (synchronises the stream)
+        uint64_t *offs_d = reinterpret_cast<uint64_t *>(tb + check_off);
+        uint32_t *flag_d =
+            reinterpret_cast<uint32_t *>(tb + check_off + align256((uint64_t(k) + 1) * sizeof(uint64_t)));
+        uint32_t flag = 0;
+        BCF_TRY(upload(offs_d, run_offsets, (k + 1) * sizeof(uint64_t), s));
+        if (hipMemsetAsync(flag_d, 0, sizeof(uint32_t), s) != hipSuccess ||
+            launch_check_runs(keys_in, offs_d, k, n, flag_d, s) != hipSuccess ||
+            hipMemcpyAsync(&flag, flag_d, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return BCF_ERR_DEVICE;
+        if (flag)
+            return BCF_ERR_UNSORTED_RUN;
+    }
+
+    if (P == 0) {
+        // zero or one nonempty run: the merge is a copy
+        if (keys_out != keys_in && hipMemcpyAsync(keys_out, keys_in, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return BCF_ERR_DEVICE;
+        if (pairs && vals_out != vals_in &&
+            hipMemcpyAsync(vals_out, vals_in, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return BCF_ERR_DEVICE;
+        return BCF_OK;
+    }
+    Bufs kb{keys_in, keys_out, kt};
+    Bufs vb{vals_in, vals_out, vt};
+    BCF_TRY(run_tables(pairs, kb, vb, tb, L, {}, passes, n, s));
+    if (shift) {
+        if (hipMemcpyAsync(keys_out, kt, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return BCF_ERR_DEVICE;
+        if (pairs && hipMemcpyAsync(vals_out, vt, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return BCF_ERR_DEVICE;
+    }
+    return BCF_OK;
+}
+
+bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
+                              uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!temp_bytes)
+        return BCF_ERR_INVALID;
+    if (nseg == 0) {
+        if (!temp)
+            *temp_bytes = 0;
+        return BCF_OK;
+    }
+    if (!offsets_valid(seg_offsets, nseg))
+        return BCF_ERR_INVALID;
+    const uint64_t n = seg_offsets[nseg];
+    // per segment: tiles, merge passes; X_j(s) = buffer after pass j of segment s
+    std::vector<BlockTile> blocks;
+    uint32_t pmax = 0;
+    std::vector<uint32_t> ps(nseg, 0);
+    for (uint32_t sg = 0; sg < nseg; ++sg) {
+        const uint64_t len = seg_offsets[sg + 1] - seg_offsets[sg];
+        if (len == 0)
+            continue;
+        ps[sg] = ceil_log2(tiles_of(len));
+        pmax = std::max(pmax, ps[sg]);
+    }
+    auto bufsel = [&](uint32_t sg, uint32_t j) -> uint32_t {
+        return ((ps[sg] - j) % 2 == 0) ? kBufOut : kBufTemp;
+    };
+    for (uint32_t sg = 0; sg < nseg; ++sg) {
+        const uint64_t a = seg_offsets[sg], len = seg_offsets[sg + 1] - a;
+        for (uint64_t t = 0; t * kTile < len; ++t) {
+            BlockTile b;
+            b.start = a + t * kTile;
+            b.count = (uint32_t)std::min<uint64_t>(kTile, len - t * kTile);
+            b.dst = bufsel(sg, 0);
+            blocks.push_back(b);
+        }
+    }
+    std::vector<MergePass> passes(pmax);
+    for (uint32_t j = 1; j <= pmax; ++j) {
+        const uint64_t run = uint64_t(kTile) << (j - 1);
+        for (uint32_t sg = 0; sg < nseg; ++sg) {
+            if (ps[sg] < j)
+                continue;
+            const uint64_t a = seg_offsets[sg], len = seg_offsets[sg + 1] - a;
+            for (uint64_t o = 0; o < len; o += 2 * run) {
+                const uint64_t na = std::min(run, len - o);
+                const uint64_t nb = std::min(run, len - o - na);
+                add_job(passes[j - 1], a + o, na, nb, bufsel(sg, j - 1), bufsel(sg, j));
+            }
+        }
+    }
+    const uint64_t data = pmax ? align256(n * 4) : 0;
+    TableLayout L = layout_tables(data, blocks.size(), passes);
+    if (!temp) {
+        *temp_bytes = L.total;
+        return BCF_OK;
+    }
+    if (n == 0)
+        return BCF_OK;
+    if (!keys_in || !keys_out)
+        return BCF_ERR_INVALID;
+    if (*temp_bytes < L.total)
+        return BCF_ERR_TEMP_TOO_SMALL;
+    char *tb = static_cast<char *>(temp);
+    Bufs kb{keys_in, keys_out, reinterpret_cast<uint32_t *>(tb)};
+    Bufs vb{nullptr, nullptr, nullptr};
+    return run_tables(false, kb, vb, tb, L, blocks, passes, n, s);
+}
+
+void bcf_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+}
+
+int bcf_profile_collect(bcf_kernel_stat *out, int max)
+{
+    std::map<std::string, std::vector<ProfRec>> recs;
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    int n = 0;
+    int rc = 0;
+    for (auto &kv : recs) {
+        double ms_sum = 0, bytes = 0;
+        uint64_t launches = 0;
+        for (auto &r : kv.second) {
+            if (hipEventSynchronize(r.b) != hipSuccess)
+                rc = -1;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+                rc = -1;
+            ms_sum += ms;
+            bytes += r.bytes;
+            ++launches;
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        if (out && n < max) {
+            std::memset(&out[n], 0, sizeof(out[n]));
+            std::snprintf(out[n].name, sizeof(out[n].name), "%s", kv.first.c_str());
+            out[n].launches = launches;
+            out[n].total_ms = ms_sum;
+            out[n].bytes = bytes;
+        }
+        ++n;
+    }
+    return rc ? rc : std::min(n, max);
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+// Device building blocks of the bank-conflict-free sort for gfx950 (CDNA4, wave64).
+//
+// The paper (Sitchinava & Weichert, Sec. 2.1) views a block of shared memory as
+// a matrix whose rows are the memory banks, filled column-major, and processes
+// it so that every thread of a warp owns one bank row; a conflict-free
+// transposition turns columns into rows.  Its sort (Sec. 3.1) keeps one line of
+// the w x w tile in registers per thread (Sec. 3.3, "use of registers") and
+// sorts lines with Batcher's odd-even merge sort.
+//
+// Re-derived for gfx950 (measured: 32 banks x 4 bytes; a wave64 b32 LDS
+// instruction is serviced as two independent 32-lane halves):
+//   * a tile is a 64 x 64 matrix of keys, w = 64 = wave width, so one wave owns
+//     w^2 = 4096 keys, 64 per lane, held in registers with compile-time indices;
+//   * two register layouts of tile position p in [0, 4096):
+//       STRIDED  lane = p mod 64, register = p / 64   (global loads/stores are
+//                coalesced: register r of all lanes is 64 consecutive keys)
+//       BLOCKED  lane = p / 64,   register = p mod 64 (lane owns a run of 64)
+//   * switching layouts goes through LDS with one pad word per 64
+//     (address = p + p/64): STRIDED accesses hit word 65r + lane, BLOCKED ones
+//     65 lane + r, so every 32-lane half touches 32 distinct banks and the
+//     lane-dependent part of the address is a base register while the
+//     register-dependent part is an immediate offset;
+//   * compare-exchanges only ever happen between two registers of one lane, so
+//     the sorting networks themselves issue no LDS traffic at all.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcf {
+
+constexpr int kWave = 64;              // lanes per wavefront (w)
+constexpr int kLine = 64;              // keys per lane (one line of the w x w tile)
+constexpr int kTile = kWave * kLine;   // 4096 keys per wave tile (w^2)
+constexpr int kLdsStride = kLine + 1;  // 65 words per LDS row: one pad word per 64
+constexpr int kLdsWords = kWave * kLdsStride;
+constexpr uint32_t kMaxKey = 0xFFFFFFFFu;
+constexpr uint32_t kPadIdx = 0xFFFFFFFFu;
+
+// A wave's tile in registers.  For key/value pairs every element also carries
+// a tie-break rank `i` (its position in the input order of the tile) and its
+// value `v`; elements compare by (k, i), which makes every network stable.
+template <bool PAIRS>
+struct Lines {
+    uint32_t k[kLine];
+    uint32_t i[PAIRS ? kLine : 1];
+    uint32_t v[PAIRS ? kLine : 1];
+};
+
+// ---------------------------------------------------------------- comparators
+
+// Put the smaller element in register a, the larger in register b.
+template <bool P>
+__device__ __forceinline__ void cx(Lines<P> &t, int a, int b)
+{
+    if constexpr (!P) {
+        const uint32_t x = t.k[a], y = t.k[b];
+        t.k[a] = min(x, y);
+        t.k[b] = max(x, y);
+    } else {
+        const uint32_t ka = t.k[a], kb = t.k[b], ia = t.i[a], ib = t.i[b];
+        const uint32_t va = t.v[a], vb = t.v[b];
+        const bool sw = (ka > kb) || ((ka == kb) && (ia > ib));
+        t.k[a] = sw ? kb : ka;
+        t.k[b] = sw ? ka : kb;
+        t.i[a] = sw ? ib : ia;
+        t.i[b] = sw ? ia : ib;
+        t.v[a] = sw ? vb : va;
+        t.v[b] = sw ? va : vb;
+    }
+}
+
+// Reverse the order of every element of a lane when `bit` is 1: (k, i) is
+// replaced by its bitwise complement, an order-reversing bijection, so an
+// ascending network run on complemented data sorts descending.  Used where
+// the direction of a merge depends on the lane (BLOCKED layout).
+template <bool P>
+__device__ __forceinline__ void flip(Lines<P> &t, uint32_t bit)
+{
+    const uint32_t m = 0u - (bit & 1u);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        t.k[r] ^= m;
+        if constexpr (P)
+            t.i[r] ^= m;
+    }
+}
+
+// ---------------------------------------------------- register-local networks
+
+// One bitonic half-cleaner step at register distance D: registers r and r+D
+// (r with bit D clear) are compare-exchanged, ascending, or descending where
+// register bit DB of r is set (DB < 0: ascending everywhere).
+template <int D, int DB, bool P>
+__device__ __forceinline__ void half_clean_step(Lines<P> &t)
+{
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        if (r & D)
+            continue;
+        if (DB >= 0 && ((r >> (DB < 0 ? 0 : DB)) & 1))
+            cx(t, r + D, r);
+        else
+            cx(t, r, r + D);
+    }
+}
+
+// Half-cleaner cascade D, D/2, ..., 1: sorts every aligned group of 2D
+// registers that holds a bitonic sequence.
+template <int D, int DB, bool P>
+__device__ __forceinline__ void half_clean(Lines<P> &t)
+{
+    half_clean_step<D, DB, P>(t);
+    if constexpr (D > 1)
+        half_clean<D / 2, DB, P>(t);
+}
+
+// Batcher's odd-even merge of registers LO..HI (inclusive) whose two halves
+// are sorted, considering every R-th register (Batcher 1968; the recursive
+// formulation in Knuth, TAOCP vol. 3, Sec. 5.3.4).
+template <int LO, int HI, int R, bool P>
+__device__ __forceinline__ void oe_merge(Lines<P> &t)
+{
+    constexpr int STEP = 2 * R;
+    if constexpr (STEP < HI - LO) {
+        oe_merge<LO, HI, STEP, P>(t);
+        oe_merge<LO + R, HI, STEP, P>(t);
+#pragma unroll
+        for (int i = LO + R; i < HI - R; i += STEP)
+            cx(t, i, i + R);
+    } else {
+        cx(t, LO, LO + R);
+    }
+}
+
+// Batcher's odd-even merge sort of registers LO..HI (inclusive), ascending:
+// the per-thread line sort of the paper (Sec. 3.1; 543 comparators for 64).
+template <int LO, int HI, bool P>
+__device__ __forceinline__ void oe_sort(Lines<P> &t)
+{
+    if constexpr (HI - LO >= 1) {
+        constexpr int MID = LO + (HI - LO) / 2;
+        oe_sort<LO, MID, P>(t);
+        oe_sort<MID + 1, HI, P>(t);
+        oe_merge<LO, HI, 1, P>(t);
+    }
+}
+
+// ------------------------------------------------------------ LDS transposes
+
+// Orders this wave's LDS accesses in the compiler: a wave's LDS instructions
+// execute in issue order, so no hardware wait is needed between a lane's
+// write and another lane's later read of the same word.
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// x[r] -> lds[wbase + WS*r], then x[r] <- lds[rbase + RS*r].
+template <int WS, int RS>
+__device__ __forceinline__ void exchange(uint32_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
+                                         uint32_t rbase)
+{
+    uint32_t *w = lds + wbase;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        w[WS * r] = x[r];
+    wave_lds_fence();
+    const uint32_t *rd = lds + rbase;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = rd[RS * r];
+    wave_lds_fence();
+}
+
+// STRIDED -> BLOCKED: write word 65r + lane, read word 65 lane + r.
+template <bool P>
+__device__ __forceinline__ void to_blocked(Lines<P> &t, uint32_t *lds, uint32_t lane)
+{
+    exchange<kLdsStride, 1>(t.k, lds, lane, kLdsStride * lane);
+    if constexpr (P) {
+        exchange<kLdsStride, 1>(t.i, lds, lane, kLdsStride * lane);
+        exchange<kLdsStride, 1>(t.v, lds, lane, kLdsStride * lane);
+    }
+}
+
+// BLOCKED -> STRIDED: write word 65 lane + r, read word 65r + lane.
+template <bool P>
+__device__ __forceinline__ void to_strided(Lines<P> &t, uint32_t *lds, uint32_t lane)
+{
+    exchange<1, kLdsStride>(t.k, lds, kLdsStride * lane, lane);
+    if constexpr (P) {
+        exchange<1, kLdsStride>(t.i, lds, kLdsStride * lane, lane);
+        exchange<1, kLdsStride>(t.v, lds, kLdsStride * lane, lane);
+    }
+}
+
+// ---------------------------------------------------------------- wave utils
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Co-rank (merge-path split) of the stable merge of sorted A and B: the number
+// of elements of A among the first d outputs when equal keys take A first.
+// It is the smallest i in [max(0, d-nb), min(d, na)] with A[i] > B[d-1-i].
+// Lanes 0..31 search for diagonal d of their half-wave, lanes 32..63 for
+// theirs; each round probes 32 evenly spaced candidates per half and keeps
+// the bracket between the last failing and the first passing probe, so a
+// search over 2^25 candidates takes 5 rounds of loads.
+__device__ __forceinline__ uint32_t corank_halfwave(const uint32_t *__restrict__ A, uint32_t na,
+                                                    const uint32_t *__restrict__ B, uint32_t nb,
+                                                    uint32_t d, uint32_t lane)
+{
+    const uint32_t k = lane & 31;
+    const uint32_t shift = lane & 32;  // 0 or 32: position of this half in the ballot
+    uint32_t lo = d > nb ? d - nb : 0;
+    uint32_t hi = d < na ? d : na;
+    while (true) {
+        const uint32_t span = hi - lo;
+        if (ballot(span != 0) == 0)
+            break;
+        // probe k of this half: lo + floor(span * k / 32) < hi when span > 0
+        const uint32_t i = lo + (uint32_t)(((uint64_t)span * k) >> 5);
+        bool pass = true;
+        if (span != 0)
+            pass = A[i] > B[d - 1 - i];
+        const uint32_t fails = (uint32_t)(ballot(!pass && span != 0) >> shift);
+        const uint32_t c = __popc(fails);  // probes 0..c-1 fail (the predicate is monotone)
+        if (span != 0) {
+            if (c == 0) {
+                hi = lo;
+            } else {
+                const uint32_t plast = lo + (uint32_t)(((uint64_t)span * (c - 1)) >> 5);
+                const uint32_t pnext = c < 32 ? lo + (uint32_t)(((uint64_t)span * c) >> 5) : hi;
+                lo = plast + 1;
+                hi = pnext;
+            }
+        }
+    }
+    return lo;
+}
+
+}  // namespace bcf

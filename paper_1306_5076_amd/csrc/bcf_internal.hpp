@@ -1,0 +1,62 @@
+// Internal interface between the host planner (bcf_api.hip) and the kernels
+// (bcf_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcf {
+
+// Buffer selector used by table-driven launches: kernels receive the three
+// candidate buffers {caller input, caller output, temp} and each work item
+// names which one it reads from and which one it writes to.
+enum BufSel : uint32_t { kBufIn = 0, kBufOut = 1, kBufTemp = 2 };
+
+struct Bufs {
+    const uint32_t *in;  // caller input (read only)
+    uint32_t *out;       // caller output
+    uint32_t *temp;      // library scratch
+};
+
+// One tile of the block sort: `count` (<= kTile) keys starting at element
+// `start` of the input, sorted into buffer `dst` at the same offset.
+struct BlockTile {
+    uint64_t start;
+    uint32_t count;
+    uint32_t dst;
+};
+
+// One binary merge of two adjacent sorted runs A = [a_start, a_start + na)
+// and B = [a_start + na, a_start + na + nb) of buffer `src`, written to the
+// same range of buffer `dst`.  Its output is cut into ceil((na+nb)/kTile)
+// tiles numbered first_tile, first_tile + 1, ... in the launch.
+struct MergeJob {
+    uint64_t a_start;
+    uint32_t na;
+    uint32_t nb;
+    uint32_t first_tile;
+    uint16_t src;
+    uint16_t dst;
+};
+
+// Launchers (enqueue only; return the launch status).
+hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint32_t *vin,
+                                     uint32_t *kout, uint32_t *vout, uint64_t n, hipStream_t s);
+hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc,
+                                uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
+                                hipStream_t s);
+hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
+                                   uint32_t ntiles, hipStream_t s);
+hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs,
+                              const uint32_t *tile_job, uint32_t ntiles, hipStream_t s);
+hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
+                             uint64_t n, uint32_t *flag, hipStream_t s);
+
+// Names used for per-kernel timing records.
+const char *kname_block_sort(bool pairs, bool table);
+const char *kname_merge(bool pairs, bool table);
+
+// Work-group shape of the sort kernels: waves per work-group.
+constexpr int kWavesPerGroup = 2;
+
+}  // namespace bcf

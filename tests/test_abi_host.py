@@ -1,0 +1,108 @@
+"""C ABI checks that need no GPU: exported symbols, temp-size queries, pass
+planning and argument validation (all return before any HIP call)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bcf.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1306_5076_amd import _native
+
+    return _native.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bcf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1306_5076_amd._native import EXPORTED
+
+    assert sorted(EXPORTED) == names
+
+
+def q_sort(lib, n, pairs=False):
+    need = ctypes.c_uint64(123)
+    if pairs:
+        st = lib.bcf_sort_pairs_u32(None, None, None, None, n, None, ctypes.byref(need), None)
+    else:
+        st = lib.bcf_sort_u32(None, None, n, None, ctypes.byref(need), None)
+    return st, need.value
+
+
+def test_tile_and_launch_count(lib):
+    T = lib.bcf_tile_keys(0)
+    assert T == 4096 and lib.bcf_tile_keys(1) == 4096
+    assert lib.bcf_sort_launches(0) == 0
+    assert lib.bcf_sort_launches(1) == 1
+    assert lib.bcf_sort_launches(T) == 1
+    assert lib.bcf_sort_launches(T + 1) == 2
+    # Lemma 2: 1 + ceil(log2(n / M)) passes over the data
+    for n in [2**16, 2**20, 2**26, 2**28, 3 * T + 5]:
+        tiles = -(-n // T)
+        assert lib.bcf_sort_launches(n) == 1 + int(np.ceil(np.log2(tiles)))
+
+
+def test_temp_queries(lib):
+    assert q_sort(lib, 0) == (0, 0)
+    assert q_sort(lib, 4096) == (0, 0)  # one tile: no merge pass, no temp
+    st, need = q_sort(lib, 4097)
+    assert st == 0 and need >= 4097 * 4 and need % 256 == 0
+    st, need = q_sort(lib, 2**26, pairs=True)
+    assert st == 0 and need == 2 * 2**26 * 4
+    assert q_sort(lib, 2**32)[0] == 1  # above 2^32 - 1 keys: invalid
+
+
+def test_argument_errors(lib):
+    need = ctypes.c_uint64(16)
+    fake = ctypes.c_void_p(4096)
+    # temp too small (returns before any launch)
+    assert lib.bcf_sort_u32(fake, fake, 10**6, fake, ctypes.byref(need), None) == 2
+    # NULL temp_bytes
+    assert lib.bcf_sort_u32(fake, fake, 10, fake, None, None) == 1
+    # NULL keys with a real temp buffer
+    big = ctypes.c_uint64(1 << 40)
+    assert lib.bcf_sort_u32(None, fake, 10**6, fake, ctypes.byref(big), None) == 1
+    for s in range(6):
+        assert lib.bcf_status_string(s).startswith(b"BCF_")
+
+
+def _offs(a):
+    a = np.asarray(a, dtype=np.uint64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def test_merge_runs_validation_and_query(lib):
+    need = ctypes.c_uint64(0)
+    a, p = _offs([0, 5, 3, 9])  # decreasing offset
+    assert lib.bcf_merge_runs(None, None, p, 3, None, None, None, ctypes.byref(need), None) == 1
+    a, p = _offs([1, 5])  # off[0] != 0
+    assert lib.bcf_merge_runs(None, None, p, 1, None, None, None, ctypes.byref(need), None) == 1
+    a, p = _offs([0, 5000, 5000, 9000])
+    assert lib.bcf_merge_runs(None, None, p, 3, None, None, None, ctypes.byref(need), None) == 0
+    assert need.value >= 9000 * 4
+    # k == 0 is a no-op
+    assert lib.bcf_merge_runs(None, None, None, 0, None, None, None, ctypes.byref(need), None) == 0
+
+
+def test_segmented_validation_and_query(lib):
+    need = ctypes.c_uint64(0)
+    a, p = _offs([0, 10, 5])
+    assert lib.bcf_segmented_sort(None, None, p, 2, None, ctypes.byref(need), None) == 1
+    a, p = _offs([0, 0, 1, 4096, 4096 + 8193])
+    assert lib.bcf_segmented_sort(None, None, p, 4, None, ctypes.byref(need), None) == 0
+    assert need.value > 0

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer work, so the bar is bit-exact equality.  Small and medium sizes are
+compared element by element with the oracle; full-size configurations are
+checked by properties that determine the result completely (nondecreasing
+keys + equal multiset for keys; additionally nondecreasing values within equal
+keys when value = original index, i.e. stability, for pairs).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+T = 4096
+EDGE_SIZES = [1, 2, 3, 63, 64, 65, 127, 4095, 4096, 4097, 8191, 8192, 8193, 3 * 4096 + 123,
+              5 * 4096, 65535, 65536, 65537, 100_003]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def bcf():
+    import paper_1306_5076_amd as bcf
+    from paper_1306_5076_amd import _native
+
+    _native.load()
+    return bcf
+
+
+def to_dev(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def first_diff(got, want):
+    idx = np.flatnonzero(got != want)
+    return None if idx.size == 0 else (int(idx[0]), int(got[idx[0]]), int(want[idx[0]]))
+
+
+# ------------------------------------------------------------------ sort_u32
+
+
+@pytest.mark.parametrize("n", EDGE_SIZES)
+def test_sort_edge_sizes(torch_dev, bcf, n):
+    torch, dev = torch_dev
+    keys = workloads.keys_u32("uniform", n, seed=n)
+    got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+    assert first_diff(got, oracle.sort_u32(keys)) is None
+
+
+def test_sort_empty(torch_dev, bcf):
+    torch, dev = torch_dev
+    out = bcf.sort_u32(torch.empty(0, dtype=torch.uint32, device=dev))
+    assert out.numel() == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_sort_2p16_uniform(torch_dev, bcf, seed):
+    torch, dev = torch_dev
+    keys = workloads.keys_u32("uniform", 1 << 16, seed=seed)
+    got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+    assert first_diff(got, oracle.sort_u32(keys)) is None
+
+
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS + workloads.PAPER_DISTRIBUTIONS)
+def test_sort_distributions_1m(torch_dev, bcf, dist):
+    torch, dev = torch_dev
+    keys = workloads.keys_u32(dist, (1 << 20) + 77, seed=2)
+    got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+    assert first_diff(got, oracle.sort_u32(keys)) is None
+
+
+def test_sort_keys_equal_to_padding_value(torch_dev, bcf):
+    torch, dev = torch_dev
+    keys = workloads.keys_u32("uniform", 3 * T + 17, seed=4)
+    keys[::3] = 0xFFFFFFFF
+    keys[1::7] = 0
+    got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+    assert first_diff(got, oracle.sort_u32(keys)) is None
+
+
+def test_sort_in_place(torch_dev, bcf):
+    torch, dev = torch_dev
+    for n in (T - 1, 9 * T + 5, 1 << 18):
+        keys = workloads.keys_u32("zipf", n, seed=6)
+        t = to_dev(torch, dev, keys)
+        bcf.sort_u32(t, out=t)
+        assert first_diff(t.cpu().numpy(), oracle.sort_u32(keys)) is None
+
+
+def test_sort_on_side_stream(torch_dev, bcf):
+    torch, dev = torch_dev
+    keys = workloads.keys_u32("uniform", 300_000, seed=9)
+    s = torch.cuda.Stream(device=dev)
+    src = to_dev(torch, dev, keys)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        out = bcf.sort_u32(src, stream=s)
+    torch.cuda.current_stream(dev).wait_stream(s)
+    assert first_diff(out.cpu().numpy(), oracle.sort_u32(keys)) is None
+
+
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS)
+def test_sort_2p26_full_size(torch_dev, bcf, dist):
+    torch, dev = torch_dev
+    n = 1 << 26
+    keys = workloads.keys_u32(dist, n, seed=1)
+    got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+    if dist in ("uniform", "zipf"):
+        assert first_diff(got, oracle.sort_u32(keys)) is None
+    else:
+        assert oracle.is_sorted_u32(got)
+        assert oracle.multiset_hash(got) == oracle.multiset_hash(keys)
+
+
+# ------------------------------------------------------------------ pairs
+
+
+@pytest.mark.parametrize("n", [1, 5, 4095, 4096, 4097, 3 * 4096 + 123, 65536 + 3])
+@pytest.mark.parametrize("dist", ["uniform", "distinct16", "paper_01"])
+def test_pairs_vs_oracle(torch_dev, bcf, n, dist):
+    torch, dev = torch_dev
+    keys = workloads.keys_u32(dist, n, seed=n + 1)
+    vals = workloads.draws_u32(77, n)  # arbitrary values
+    ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, keys), to_dev(torch, dev, vals))
+    wk, wv = oracle.sort_pairs_u32(keys, vals)
+    assert first_diff(ko.cpu().numpy(), wk) is None
+    assert first_diff(vo.cpu().numpy(), wv) is None
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "distinct16", "paper_dups"])
+def test_pairs_1m_stable(torch_dev, bcf, dist):
+    torch, dev = torch_dev
+    keys, vals = workloads.pairs_u32(dist, (1 << 20) + 5, seed=3)
+    ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, keys), to_dev(torch, dev, vals))
+    wk, wv = oracle.sort_pairs_u32(keys, vals)
+    assert first_diff(ko.cpu().numpy(), wk) is None
+    assert first_diff(vo.cpu().numpy(), wv) is None
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_pairs_2p28_full_size(torch_dev, bcf, dist):
+    torch, dev = torch_dev
+    n = 1 << 28
+    keys, vals = workloads.pairs_u32(dist, n, seed=1)
+    ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, keys), to_dev(torch, dev, vals))
+    ko, vo = ko.cpu().numpy(), vo.cpu().numpy()
+    assert oracle.is_sorted_u32(ko)
+    # stability: value = original index, so within equal keys values increase
+    same = ko[1:] == ko[:-1]
+    assert np.all(vo[1:][same] > vo[:-1][same])
+    assert oracle.multiset_hash(ko, vo) == oracle.multiset_hash(keys, vals)
+    # sampled elements straight from the oracle's view: the pair at output i
+    # is input element vo[i]
+    idx = np.linspace(0, n - 1, 4097).astype(np.int64)
+    assert np.array_equal(keys[vo[idx]], ko[idx])
+
+
+# ------------------------------------------------------------------ merge_runs
+
+
+@pytest.mark.parametrize(
+    "sizes",
+    [[5000], [0, 0, 7], [4096, 4096], [1, 10000], [10000, 1], [3, 0, 9000, 0, 4097],
+     [700] * 17, [8192, 123, 5000, 4096 * 3 + 1, 0, 77, 4096], list(range(0, 3400, 200))],
+)
+@pytest.mark.parametrize("pairs", [False, True])
+def test_merge_runs_vs_oracle(torch_dev, bcf, sizes, pairs):
+    torch, dev = torch_dev
+    keys, offs = workloads.sorted_runs(sizes, seed=len(sizes), dist="dups")
+    vals = workloads.draws_u32(5, keys.size) if pairs else None
+    kd = to_dev(torch, dev, keys)
+    if pairs:
+        ko, vo = bcf.merge_runs(kd, offs, vals=to_dev(torch, dev, vals))
+        wk, wv = oracle.merge_runs(keys, offs, vals)
+        assert first_diff(ko.cpu().numpy(), wk) is None
+        assert first_diff(vo.cpu().numpy(), wv) is None
+    else:
+        ko = bcf.merge_runs(kd, offs)
+        assert first_diff(ko.cpu().numpy(), oracle.merge_runs(keys, offs)) is None
+
+
+def test_merge_runs_in_place(torch_dev, bcf):
+    torch, dev = torch_dev
+    for sizes in ([3000, 4000], [100, 200, 300], [5000] * 5):
+        keys, offs = workloads.sorted_runs(sizes, seed=2)
+        t = to_dev(torch, dev, keys)
+        bcf.merge_runs(t, offs, keys_out=t)
+        assert first_diff(t.cpu().numpy(), oracle.merge_runs(keys, offs)) is None
+
+
+def test_merge_runs_large(torch_dev, bcf):
+    torch, dev = torch_dev
+    sizes = workloads.segment_sizes(64, lo=1 << 10, hi=1 << 20, seed=4)
+    keys, offs = workloads.sorted_runs(sizes, seed=8)
+    got = bcf.merge_runs(to_dev(torch, dev, keys), offs).cpu().numpy()
+    assert first_diff(got, oracle.merge_runs(keys, offs)) is None
+
+
+# ------------------------------------------------------------------ segmented
+
+
+@pytest.mark.parametrize(
+    "sizes",
+    [[0], [1], [0, 1, 2, 0, 3], [4096, 4097, 1, 0, 8192], [12345], [31, 4096 * 5 + 3, 64, 100000, 0, 2],
+     [64] * 200],
+)
+def test_segmented_vs_oracle(torch_dev, bcf, sizes):
+    torch, dev = torch_dev
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    keys = workloads.keys_u32("uniform", int(offs[-1]), seed=len(sizes))
+    got = bcf.segmented_sort(to_dev(torch, dev, keys), offs).cpu().numpy()
+    assert first_diff(got, oracle.segmented_sort(keys, offs)) is None
+
+
+def test_segmented_log_uniform_batch(torch_dev, bcf):
+    torch, dev = torch_dev
+    sizes = workloads.segment_sizes(1000, lo=32, hi=1 << 16, seed=1)
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    keys = workloads.keys_u32("uniform", int(offs[-1]), seed=1)
+    got = bcf.segmented_sort(to_dev(torch, dev, keys), offs).cpu().numpy()
+    assert first_diff(got, oracle.segmented_sort(keys, offs)) is None
+
+
+# ------------------------------------------------------------------ profiling / errors
+
+
+def test_profile_records_every_launch(torch_dev, bcf):
+    torch, dev = torch_dev
+    n = 1 << 20
+    keys = to_dev(torch, dev, workloads.keys_u32("uniform", n))
+    bcf.profile_collect()
+    bcf.profile_enable(True)
+    bcf.sort_u32(keys)
+    bcf.profile_enable(False)
+    st = bcf.profile_collect()
+    assert st["block_sort_keys"]["launches"] == 1
+    assert st["merge_keys"]["launches"] == bcf.sort_launches(n) - 1
+    assert st["merge_keys"]["bytes"] == pytest.approx((bcf.sort_launches(n) - 1) * 8.0 * n)
+    assert all(v["total_ms"] > 0 for v in st.values())
+
+
+def test_errors_raise(torch_dev, bcf):
+    torch, dev = torch_dev
+    from paper_1306_5076_amd import BcfError
+
+    keys = to_dev(torch, dev, np.arange(10, dtype=np.uint32))
+    with pytest.raises(ValueError):
+        bcf.merge_runs(keys, [0, 5, 11])
+    with pytest.raises(TypeError):
+        bcf.sort_u32(torch.zeros(4, dtype=torch.float32, device=dev))
+    import os
+
+    os.environ["BCF_CHECK"] = "1"
+    try:
+        bad = to_dev(torch, dev, np.array([1, 2, 3, 9, 4, 5, 6], dtype=np.uint32))
+        with pytest.raises(BcfError) as ei:
+            bcf.merge_runs(bad, [0, 3, 7])  # second run 9,4,5,6 is not sorted
+            torch.cuda.synchronize()
+        assert ei.value.status == 5
+        good = to_dev(torch, dev, np.array([1, 2, 3, 9, 4, 5, 6], dtype=np.uint32))
+        got = bcf.merge_runs(good, [0, 4, 7]).cpu().numpy()
+        assert list(got) == [1, 2, 3, 4, 5, 6, 9]
+    finally:
+        del os.environ["BCF_CHECK"]

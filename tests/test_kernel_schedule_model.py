@@ -1,0 +1,297 @@
+"""CPU model of the HIP kernels' compare-exchange schedule and LDS addresses.
+
+This is a design check of the GPU path, not the oracle: it replays, with
+numpy, the exact sequence of register-local compare-exchanges, lane-dependent
+complements and STRIDED/BLOCKED transposes that the block-sort and merge
+kernels execute on a 64 x 64 tile (w = 64 lanes x 64 registers), and checks
+
+* that the schedule sorts (0-1 principle inputs, random inputs, duplicates);
+* that every LDS instruction of a transpose touches 32 distinct banks in each
+  32-lane half (gfx950 geometry: 32 banks x 4 bytes, halves serviced
+  independently, measured by the bank probe);
+* Batcher's network size (543 comparators for 64 keys) and that it sorts;
+* the paper's Fig. 1 view of shared memory (element k in bank k mod w,
+  column k div w) for the paper's w = 8 drawing.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+W = 64  # lanes
+E = 64  # registers per lane
+T = W * E
+STRIDE = E + 1  # LDS words per row (one pad word per 64)
+BANKS = 32
+HALF = 32
+
+
+# ------------------------------------------------------------ comparator lists
+
+
+def oe_merge(lo, hi, r):
+    step = 2 * r
+    if step < hi - lo:
+        yield from oe_merge(lo, hi, step)
+        yield from oe_merge(lo + r, hi, step)
+        for i in range(lo + r, hi - r, step):
+            yield (i, i + r)
+    else:
+        yield (lo, lo + r)
+
+
+def oe_sort(lo, hi):
+    if hi - lo >= 1:
+        mid = lo + (hi - lo) // 2
+        yield from oe_sort(lo, mid)
+        yield from oe_sort(mid + 1, hi)
+        yield from oe_merge(lo, hi, 1)
+
+
+def half_clean(d, db):
+    """(a, b) pairs: smaller goes to a.  Mirrors half_clean<D, DB>."""
+    out = []
+    while True:
+        for r in range(E):
+            if r & d:
+                continue
+            if db >= 0 and (r >> db) & 1:
+                out.append((r + d, r))
+            else:
+                out.append((r, r + d))
+        if d == 1:
+            break
+        d //= 2
+    return out
+
+
+def apply(regs, pairs):
+    """regs: (lanes, E) array; apply compare-exchanges on register pairs."""
+    for a, b in pairs:
+        x, y = regs[:, a].copy(), regs[:, b].copy()
+        regs[:, a] = np.minimum(x, y)
+        regs[:, b] = np.maximum(x, y)
+
+
+def flip(regs, bits):
+    m = np.where(bits & 1, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64(0)).astype(regs.dtype)
+    regs ^= m[:, None]
+
+
+# ---------------------------------------------------------------- layouts
+
+
+def strided_pos(lane, r):
+    return W * r + lane
+
+
+def blocked_pos(lane, r):
+    return E * lane + r
+
+
+def lds_addr(p):
+    return p + p // 64
+
+
+def to_blocked(regs):
+    lanes = np.arange(W)
+    lds = {}
+    for r in range(E):
+        for l in lanes:
+            lds[lds_addr(strided_pos(l, r))] = regs[l, r]
+    out = np.empty_like(regs)
+    for r in range(E):
+        for l in lanes:
+            out[l, r] = lds[lds_addr(blocked_pos(l, r))]
+    return out
+
+
+def to_strided(regs):
+    lanes = np.arange(W)
+    lds = {}
+    for r in range(E):
+        for l in lanes:
+            lds[lds_addr(blocked_pos(l, r))] = regs[l, r]
+    out = np.empty_like(regs)
+    for r in range(E):
+        for l in lanes:
+            out[l, r] = lds[lds_addr(strided_pos(l, r))]
+    return out
+
+
+def fast_to_blocked(regs):
+    # position p held at STRIDED (p % 64, p // 64) moves to BLOCKED (p // 64, p % 64)
+    return regs.T.copy()
+
+
+fast_to_strided = fast_to_blocked
+
+
+# ----------------------------------------------------------- kernel schedules
+
+OE64 = list(oe_sort(0, E - 1))
+
+
+def sort_tile_model(tile):
+    """tile: (T,) keys in input order; returns the kernel's output tile."""
+    lanes = np.arange(W)
+    regs = np.empty((W, E), dtype=tile.dtype)
+    for r in range(E):  # load_tile: STRIDED
+        regs[:, r] = tile[W * r + lanes]
+    # sort_tile: the loaded registers are read as BLOCKED lines
+    flip(regs, lanes)
+    apply(regs, OE64)
+    flip(regs, lanes)
+    for j in range(1, 7):
+        regs = fast_to_strided(regs)
+        apply(regs, half_clean(1 << (j - 1), j if j < 6 else -1))
+        regs = fast_to_blocked(regs)
+        if j < 6:
+            flip(regs, lanes >> j)
+        apply(regs, half_clean(E // 2, -1))
+        if j < 6:
+            flip(regs, lanes >> j)
+    regs = fast_to_strided(regs)
+    out = np.empty_like(tile)
+    for r in range(E):  # store_tile: STRIDED
+        out[W * r + lanes] = regs[:, r]
+    return out
+
+
+def merge_tile_model(a_piece, b_piece):
+    """A ascending at [0, na), B reversed at the end, padding between."""
+    na, nb = len(a_piece), len(b_piece)
+    pad = np.iinfo(a_piece.dtype).max
+    tile = np.full(T, pad, dtype=a_piece.dtype)
+    tile[:na] = a_piece
+    if nb:
+        tile[T - nb:] = b_piece[::-1]
+    lanes = np.arange(W)
+    regs = np.empty((W, E), dtype=tile.dtype)
+    for r in range(E):
+        regs[:, r] = tile[W * r + lanes]
+    apply(regs, half_clean(E // 2, -1))
+    regs = fast_to_blocked(regs)
+    apply(regs, half_clean(E // 2, -1))
+    regs = fast_to_strided(regs)
+    out = np.empty_like(tile)
+    for r in range(E):
+        out[W * r + lanes] = regs[:, r]
+    return out[: na + nb]
+
+
+# ---------------------------------------------------------------------- tests
+
+
+def test_batcher_64_size_and_sorts():
+    assert len(OE64) == 543
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        x = rng.integers(0, 4, size=(1, E)).astype(np.uint32)
+        y = x.copy()
+        apply(y, OE64)
+        assert np.array_equal(y[0], np.sort(x[0]))
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16])
+def test_batcher_sorts_every_01_input(n):
+    net = list(oe_sort(0, n - 1))
+    for bits in itertools.product((0, 1), repeat=n):
+        x = np.array([bits], dtype=np.uint32)
+        y = x.copy()
+        for a, b in net:
+            lo, hi = min(y[0, a], y[0, b]), max(y[0, a], y[0, b])
+            y[0, a], y[0, b] = lo, hi
+        assert list(y[0]) == sorted(bits)
+
+
+def test_transpose_model_matches_index_permutation():
+    regs = np.arange(T, dtype=np.uint32).reshape(W, E)
+    assert np.array_equal(to_blocked(regs), fast_to_blocked(regs))
+    assert np.array_equal(to_strided(regs), fast_to_strided(regs))
+
+
+def test_lds_transposes_conflict_free_on_gfx950_geometry():
+    lanes = np.arange(W)
+    for r in range(E):
+        for pos in (strided_pos, blocked_pos):
+            banks = lds_addr(pos(lanes, r)) % BANKS
+            for h in range(W // HALF):
+                b = banks[h * HALF:(h + 1) * HALF]
+                assert len(set(b.tolist())) == HALF, (pos.__name__, r, h)
+    # the unpadded layout would conflict 32-way for the BLOCKED accesses
+    banks = (blocked_pos(lanes, 0)) % BANKS
+    assert len(set(banks[:HALF].tolist())) == 1
+    # the padded address map is injective on the tile and fits the LDS array
+    addrs = lds_addr(np.arange(T))
+    assert len(set(addrs.tolist())) == T and addrs.max() < W * STRIDE
+
+
+@pytest.mark.parametrize("dist", ["random", "zero_one", "dups", "sorted", "reverse"])
+def test_block_sort_schedule_sorts(dist):
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        if dist == "random":
+            x = rng.integers(0, 2**32, size=T, dtype=np.uint64).astype(np.uint32)
+        elif dist == "zero_one":
+            x = rng.integers(0, 2, size=T).astype(np.uint32)
+        elif dist == "dups":
+            x = rng.integers(0, 5, size=T).astype(np.uint32) * np.uint32(0x40000000)
+        elif dist == "sorted":
+            x = np.sort(rng.integers(0, 2**32, size=T, dtype=np.uint64).astype(np.uint32))
+        else:
+            x = np.sort(rng.integers(0, 2**32, size=T, dtype=np.uint64).astype(np.uint32))[::-1].copy()
+        assert np.array_equal(sort_tile_model(x), np.sort(x))
+
+
+def test_block_sort_schedule_01_principle_sampled():
+    # 0-1 inputs with every possible count of ones at random positions
+    rng = np.random.default_rng(3)
+    for ones in list(range(0, 130)) + list(range(T - 130, T + 1)) + list(rng.integers(0, T, 60)):
+        x = np.zeros(T, dtype=np.uint32)
+        x[rng.permutation(T)[:ones]] = 1
+        assert np.array_equal(sort_tile_model(x), np.sort(x))
+
+
+def test_block_sort_schedule_stable_pairs():
+    # (key, rank) composite packed into 64 bits: the network sorts by it, so
+    # the order of equal keys follows the rank (load position).
+    rng = np.random.default_rng(5)
+    keys = rng.integers(0, 3, size=T).astype(np.uint64)
+    comp = (keys << np.uint64(32)) | np.arange(T, dtype=np.uint64)
+    out = sort_tile_model(comp)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(out & np.uint64(0xFFFFFFFF), order.astype(np.uint64))
+
+
+@pytest.mark.parametrize("na,nb", [(0, 4096), (4096, 0), (2048, 2048), (1, 4095), (4095, 1),
+                                   (1000, 3096), (3000, 0), (0, 17), (5, 7), (2047, 2049)])
+def test_merge_tile_schedule(na, nb):
+    rng = np.random.default_rng(na * 7919 + nb)
+    a = np.sort(rng.integers(0, 50, size=na).astype(np.uint32))
+    b = np.sort(rng.integers(0, 50, size=nb).astype(np.uint32))
+    assert np.array_equal(merge_tile_model(a, b), np.sort(np.concatenate([a, b])))
+
+
+def test_merge_tile_schedule_01_exhaustive_boundaries():
+    # 0-1 principle for merging: A = 0^x 1^(na-x), B = 0^y 1^(nb-y)
+    for na, nb in [(4096, 0), (2048, 2048), (1024, 3072)]:
+        for x in range(0, na + 1, max(1, na // 64)):
+            for y in range(0, nb + 1, max(1, nb // 64)):
+                a = np.array([0] * x + [1] * (na - x), dtype=np.uint32)
+                b = np.array([0] * y + [1] * (nb - y), dtype=np.uint32)
+                got = merge_tile_model(a, b)
+                assert got.sum() == (na - x) + (nb - y) and np.all(np.diff(got.astype(np.int64)) >= 0)
+
+
+def test_paper_fig1_bank_matrix_view():
+    # Fig. 1 (w = 8 banks): A_k sits in bank k mod 8, column k div 8.
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "fig1_bank_matrix_w8.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    for bank, *elems in rows:
+        for col, name in enumerate(elems):
+            k = int(name[2:])
+            assert k % 8 == int(bank) and k // 8 == col
