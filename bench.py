@@ -81,6 +81,13 @@ def main():
     ap.add_argument("--n", type=int, default=N_KEYS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--no-per-dist", action="store_true", help="skip the per-distribution timing")
+    ap.add_argument(
+        "--copy-calibration",
+        action="store_true",
+        help="first copy one n-key array device-to-device 3 times (a plain copy of known size, "
+        "used to scale HBM traffic counters)",
+    )
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -109,6 +116,11 @@ def main():
     def step(i):
         bcf.sort_u32(src[dists[i % len(dists)]], out=out, stream=stream, workspace=ws)
 
+    if args.copy_calibration:
+        for _ in range(3):
+            out.copy_(src["uniform"])
+        torch.cuda.synchronize()
+
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -122,7 +134,7 @@ def main():
 
     # per-distribution time (events on the launch stream)
     per_dist = {}
-    for d in dists:
+    for d in ([] if args.no_per_dist else dists):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = 3
         e0.record(stream)
@@ -135,7 +147,7 @@ def main():
     # roofline of the dominant kernel: per-launch HIP events around each launch
     bcf.profile_collect()
     bcf.profile_enable(True)
-    for i in range(args.profile_steps):
+    for i in range(max(1, args.profile_steps)):
         step(i)
     bcf.profile_enable(False)
     stats = bcf.profile_collect()

@@ -158,7 +158,9 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
         return BCF_ERR_INVALID;
     const uint64_t tiles = tiles_of(n);
     const uint32_t passes = n ? ceil_log2(tiles) : 0;
-    const uint64_t need = passes ? align256(n * 4) * (pairs ? 2 : 1) : 0;
+    // temp: ping-pong keys [, values], then one split per merge tile
+    const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
+    const uint64_t need = passes ? data + align256(tiles * 4) : 0;
     if (!temp) {
         *temp_bytes = need;
         return BCF_OK;
@@ -171,6 +173,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
         return BCF_ERR_TEMP_TOO_SMALL;
     uint32_t *kt = static_cast<uint32_t *>(temp);
     uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + align256(n * 4)) : nullptr;
+    uint32_t *splits = reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + data);
     // X_j = buffer after pass j; X_passes = out.
     auto kbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? kout : kt; };
     auto vbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? vout : vt; };
@@ -181,9 +184,13 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     }
     uint64_t run = kTile;
     for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
-        ProfScope p(kname_merge(pairs, false), s, 2.0 * elem_bytes * n);
-        BCF_TRY(dev_status(launch_merge_regular(pairs, kbuf(j - 1), pairs ? vbuf(j - 1) : nullptr, kbuf(j),
-                                                pairs ? vbuf(j) : nullptr, n, run, s)));
+        for (int phase = 0; phase < 2; ++phase) {
+            const bool part = phase == 0;
+            ProfScope p(part ? kname_partition(pairs, false) : kname_merge(pairs, false), s,
+                        part ? 0.0 : 2.0 * elem_bytes * n);
+            BCF_TRY(dev_status(launch_merge_regular(pairs, kbuf(j - 1), pairs ? vbuf(j - 1) : nullptr, kbuf(j),
+                                                    pairs ? vbuf(j) : nullptr, n, run, splits, part, s)));
+        }
     }
     return BCF_OK;
 }
@@ -218,6 +225,7 @@ void add_job(MergePass &mp, uint64_t a, uint64_t na, uint64_t nb, uint32_t src, 
 struct TableLayout {
     uint64_t block_off = 0, block_bytes = 0;
     std::vector<uint64_t> jobs_off, map_off;
+    uint64_t splits_off = 0;  // one u32 per tile of the largest pass (reused by every pass)
     uint64_t total = 0;
 };
 
@@ -228,12 +236,16 @@ TableLayout layout_tables(uint64_t base, size_t nblock, const std::vector<MergeP
     L.block_off = o;
     L.block_bytes = nblock * sizeof(BlockTile);
     o = align256(o + L.block_bytes);
+    size_t max_tiles = 0;
     for (const auto &mp : passes) {
         L.jobs_off.push_back(o);
         o = align256(o + mp.jobs.size() * sizeof(MergeJob));
         L.map_off.push_back(o);
         o = align256(o + mp.tile_job.size() * sizeof(uint32_t));
+        max_tiles = std::max(max_tiles, mp.tile_job.size());
     }
+    L.splits_off = o;
+    o = align256(o + max_tiles * sizeof(uint32_t));
     L.total = o;
     return L;
 }
@@ -243,7 +255,7 @@ bcf_status upload_tables(char *temp, const TableLayout &L, const std::vector<Blo
                          const std::vector<MergePass> &passes, hipStream_t s)
 {
     const uint64_t lo = L.block_off;
-    const uint64_t bytes = L.total - lo;
+    const uint64_t bytes = L.splits_off - lo;  // the splits area is written on the device
     if (bytes == 0)
         return BCF_OK;
     std::vector<char> img(bytes, 0);
@@ -281,10 +293,14 @@ bcf_status run_tables(bool pairs, Bufs kb, Bufs vb, char *temp, const TableLayou
         double moved = 0;
         for (const auto &j : mp.jobs)
             moved += 2.0 * eb * (double(j.na) + j.nb);
-        ProfScope ps(kname_merge(pairs, true), s, moved);
-        BCF_TRY(dev_status(launch_merge_table(pairs, kb, vb, reinterpret_cast<const MergeJob *>(temp + L.jobs_off[p]),
-                                              reinterpret_cast<const uint32_t *>(temp + L.map_off[p]),
-                                              (uint32_t)mp.tile_job.size(), s)));
+        for (int phase = 0; phase < 2; ++phase) {
+            const bool part = phase == 0;
+            ProfScope ps(part ? kname_partition(pairs, true) : kname_merge(pairs, true), s, part ? 0.0 : moved);
+            BCF_TRY(dev_status(launch_merge_table(pairs, kb, vb, reinterpret_cast<const MergeJob *>(temp + L.jobs_off[p]),
+                                                  reinterpret_cast<const uint32_t *>(temp + L.map_off[p]),
+                                                  (uint32_t)mp.tile_job.size(),
+                                                  reinterpret_cast<uint32_t *>(temp + L.splits_off), part, s)));
+        }
     }
     (void)n;
     return BCF_OK;

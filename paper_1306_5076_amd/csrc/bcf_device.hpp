@@ -199,6 +199,16 @@ __device__ __forceinline__ void to_strided(Lines<P> &t, uint32_t *lds, uint32_t 
 
 // ---------------------------------------------------------------- wave utils
 
+// The value of x, hidden from the optimiser.  Persistent kernels re-derive
+// their lane index through this at the top of every tile so that the 64
+// per-register address constants computed from it are not hoisted out of the
+// tile loop (which would keep them all live in registers).
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // Co-rank (merge-path split) of the stable merge of sorted A and B: the number

@@ -42,18 +42,23 @@ struct MergeJob {
 // Launchers (enqueue only; return the launch status).
 hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint32_t *vin,
                                      uint32_t *kout, uint32_t *vout, uint64_t n, hipStream_t s);
+// A merge pass is two launches: with partition = true the split of every
+// tile is written to `splits` (one u32 per tile of the pass); with
+// partition = false the tiles are merged using those splits.
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc,
                                 uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
-                                hipStream_t s);
+                                uint32_t *splits, bool partition, hipStream_t s);
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
                                    uint32_t ntiles, hipStream_t s);
 hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs,
-                              const uint32_t *tile_job, uint32_t ntiles, hipStream_t s);
+                              const uint32_t *tile_job, uint32_t ntiles, uint32_t *splits,
+                              bool partition, hipStream_t s);
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);
 
 // Names used for per-kernel timing records.
 const char *kname_block_sort(bool pairs, bool table);
+const char *kname_partition(bool pairs, bool table);
 const char *kname_merge(bool pairs, bool table);
 
 // Work-group shape of the sort kernels: waves per work-group.

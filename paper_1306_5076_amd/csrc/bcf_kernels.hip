@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
+
 #include "bcf_device.hpp"
 #include "bcf_internal.hpp"
 
@@ -136,161 +138,342 @@ __device__ __forceinline__ void sort_tile(Lines<P> &t, uint32_t *lds, uint32_t l
 
 // --------------------------------------------------------------- merge body
 
-// Merge the A-piece [0, na) and B-piece [0, nb) (na + nb = count <= kTile) of
-// a stable merge into one sorted STRIDED tile.  A goes to positions [0, na)
-// ascending, B to positions [kTile - nb, kTile) reversed, padding in between,
-// which makes the tile bitonic; ranks follow the order A then B so that equal
-// keys leave A first.
+// The inputs of one merge work item: the A-piece [0, pa) and B-piece [0, pb)
+// (pa + pb = count <= kTile) that produce `count` consecutive outputs.
 template <bool P>
-__device__ __forceinline__ void merge_tile(Lines<P> &t, const uint32_t *__restrict__ ka,
-                                           const uint32_t *__restrict__ va, uint32_t na,
-                                           const uint32_t *__restrict__ kb,
-                                           const uint32_t *__restrict__ vb, uint32_t nb,
-                                           uint32_t *lds, uint32_t lane)
+struct MergeTask {
+    const uint32_t *ka, *va, *kb, *vb;
+    uint32_t *kd, *vd;
+    uint32_t pa, pb, count;
+};
+
+// Load a merge work item as one bitonic STRIDED tile: A goes to positions
+// [0, pa) ascending, B to positions [kTile - pb, kTile) reversed, padding in
+// between.  Ranks follow the order A then B so that equal keys leave A first.
+// Register row r holds positions [64r, 64r + 64); all but at most two rows lie
+// entirely in A or entirely in B, which a wave-uniform branch detects, so
+// those rows are one coalesced load from a per-piece base pointer.
+template <bool P>
+__device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, uint32_t lane)
 {
+    const uint32_t na = m.pa, nb = m.pb;
     const uint32_t bstart = kTile - nb;
+    const uint32_t *ka = m.ka + lane;                 // ka[64r]  = A[p]
+    const uint32_t *kb = m.kb + (kTile - 1 - lane);   // kb[-64r] = B[kTile - 1 - p]
+    const uint32_t *va = P ? m.va + lane : nullptr;
+    const uint32_t *vb = P ? m.vb + (kTile - 1 - lane) : nullptr;
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
-        const uint32_t p = kWave * r + lane;
-        const bool in_a = p < na;
-        const bool in_b = p >= bstart;
-        const uint32_t qb = kTile - 1 - p;  // index into B when in_b
-        // every lane loads from a valid address; padding lanes re-read A[0] or B[0]
-        const uint32_t *kp = in_a ? ka + p : (in_b ? kb + qb : (na ? ka : kb));
-        const uint32_t key = (na | nb) ? *kp : kMaxKey;
-        t.k[r] = (in_a || in_b) ? key : kMaxKey;
-        if constexpr (P) {
-            const uint32_t *vp = in_a ? va + p : (in_b ? vb + qb : (na ? va : vb));
-            t.v[r] = (na | nb) ? *vp : 0u;
-            t.i[r] = in_a ? p : (in_b ? na + qb : kPadIdx);
+        const uint32_t p0 = kWave * r;
+        const uint32_t p = p0 + lane;
+        if (p0 + kWave <= na) {  // whole row in A
+            t.k[r] = ka[kWave * r];
+            if constexpr (P) {
+                t.v[r] = va[kWave * r];
+                t.i[r] = p;
+            }
+        } else if (p0 >= bstart) {  // whole row in B
+            t.k[r] = kb[-kWave * r];
+            if constexpr (P) {
+                t.v[r] = vb[-kWave * r];
+                t.i[r] = na + (kTile - 1 - p);
+            }
+        } else {  // row crossing A / padding / B
+            const bool in_a = p < na;
+            const bool in_b = p >= bstart;
+            const uint32_t qb = kTile - 1 - p;
+            // every lane loads from a valid address; padding lanes re-read A[0] or B[0]
+            const uint32_t *kp = in_a ? m.ka + p : (in_b ? m.kb + qb : (na ? m.ka : m.kb));
+            const uint32_t key = (na | nb) ? *kp : kMaxKey;
+            t.k[r] = (in_a || in_b) ? key : kMaxKey;
+            if constexpr (P) {
+                const uint32_t *vp = in_a ? m.va + p : (in_b ? m.vb + qb : (na ? m.va : m.vb));
+                t.v[r] = (na | nb) ? *vp : 0u;
+                t.i[r] = in_a ? p : (in_b ? na + qb : kPadIdx);
+            }
         }
     }
-    half_clean<kLine / 2, -1, P>(t);  // position bits 11..6 (registers, STRIDED)
+}
+
+// Sort a bitonic STRIDED tile: half-cleaners on position bits 11..6 (register
+// bits in STRIDED layout), transpose, bits 5..0 (register bits in BLOCKED
+// layout), transpose back.
+template <bool P>
+__device__ __forceinline__ void merge_network(Lines<P> &t, uint32_t *lds, uint32_t lane)
+{
+    half_clean<kLine / 2, -1, P>(t);
     to_blocked(t, lds, lane);
-    half_clean<kLine / 2, -1, P>(t);  // position bits 5..0 (registers, BLOCKED)
+    half_clean<kLine / 2, -1, P>(t);
     to_strided(t, lds, lane);
 }
 
-// ------------------------------------------------------------------- kernels
+// ----------------------------------------------------------- work sources
+//
+// A work source maps a tile number of a launch to the data it covers.
+// "Regular" sources compute it arithmetically for a sort of n keys; "table"
+// sources read host-planned descriptors.
 
-template <bool P>
-__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(const uint32_t *__restrict__ kin,
-                                                                      const uint32_t *__restrict__ vin,
-                                                                      uint32_t *__restrict__ kout,
-                                                                      uint32_t *__restrict__ vout,
-                                                                      uint64_t n)
-{
-    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = threadIdx.x / kWave;
-    const uint64_t tile = (uint64_t)blockIdx.x * kWavesPerGroup + wave;
-    const uint64_t start = tile * kTile;
-    if (start >= n)
-        return;
-    const uint64_t rem = n - start;
-    const uint32_t count = rem < (uint64_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
-    Lines<P> t;
-    load_tile<P>(t, kin + start, P ? vin + start : nullptr, count, lane);
-    sort_tile<P>(t, lds_all[wave], lane);
-    store_tile<P>(t, kout + start, P ? vout + start : nullptr, count, lane);
-}
+struct SortItem {
+    const uint32_t *ks, *vs;
+    uint32_t *kd, *vd;
+    uint32_t count;
+};
 
-template <bool P>
-__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort_table(Bufs kb, Bufs vb,
-                                                                            const BlockTile *__restrict__ tiles,
-                                                                            uint32_t ntiles)
-{
-    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t tile = blockIdx.x * kWavesPerGroup + wave;
-    if (tile >= ntiles)
-        return;
-    const BlockTile d = tiles[tile];
-    uint32_t *kdst = d.dst == kBufOut ? kb.out : kb.temp;
-    uint32_t *vdst = P ? (d.dst == kBufOut ? vb.out : vb.temp) : nullptr;
-    Lines<P> t;
-    load_tile<P>(t, kb.in + d.start, P ? vb.in + d.start : nullptr, d.count, lane);
-    sort_tile<P>(t, lds_all[wave], lane);
-    store_tile<P>(t, kdst + d.start, P ? vdst + d.start : nullptr, d.count, lane);
-}
-
-// Shared body of both merge kernels: the wave's output range is
-// [d0, d0 + count) of the merge of A (na) and B (nb).
-template <bool P>
-__device__ __forceinline__ void merge_range(const uint32_t *__restrict__ ka, const uint32_t *__restrict__ va,
-                                            uint32_t na, uint32_t nb, uint32_t d0, uint32_t count,
-                                            uint32_t *__restrict__ kdst, uint32_t *__restrict__ vdst,
-                                            uint32_t *lds, uint32_t lane)
-{
-    const uint32_t *kbp = ka + na;
-    const uint32_t *vbp = P ? va + na : nullptr;
-    // lanes 0..31: split at d0; lanes 32..63: split at d0 + count
-    const uint32_t d = lane < 32 ? d0 : d0 + count;
-    const uint32_t split = corank_halfwave(ka, na, kbp, nb, d, lane);
-    const uint32_t a0 = __shfl(split, 0);
-    const uint32_t a1 = __shfl(split, 32);
-    const uint32_t b0 = d0 - a0;
-    const uint32_t pa = a1 - a0;
-    const uint32_t pb = count - pa;
-    Lines<P> t;
-    merge_tile<P>(t, ka + a0, P ? va + a0 : nullptr, pa, kbp + b0, P ? vbp + b0 : nullptr, pb, lds, lane);
-    store_tile<P>(t, kdst + d0, P ? vdst + d0 : nullptr, count, lane);
-}
-
-// Regular pass: runs of length `run` (a multiple of kTile) cover [0, n);
-// runs 2s and 2s+1 are merged into [2s*run, min(2(s+1)*run, n)).
-template <bool P>
-__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(const uint32_t *__restrict__ ksrc,
-                                                                 const uint32_t *__restrict__ vsrc,
-                                                                 uint32_t *__restrict__ kdst,
-                                                                 uint32_t *__restrict__ vdst, uint64_t n,
-                                                                 uint64_t run)
-{
-    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = threadIdx.x / kWave;
-    const uint64_t gstart = ((uint64_t)blockIdx.x * kWavesPerGroup + wave) * kTile;
-    if (gstart >= n)
-        return;
-    const uint64_t base = gstart / (2 * run) * (2 * run);
-    const uint64_t rem = n - base;
-    const uint32_t na = (uint32_t)(rem < run ? rem : run);
-    const uint64_t remb = rem - na;
-    const uint32_t nb = (uint32_t)(remb < run ? remb : run);
-    const uint32_t d0 = (uint32_t)(gstart - base);
-    const uint32_t left = na + nb - d0;
-    const uint32_t count = left < (uint32_t)kTile ? left : (uint32_t)kTile;
-    merge_range<P>(ksrc + base, P ? vsrc + base : nullptr, na, nb, d0, count, kdst + base,
-                   P ? vdst + base : nullptr, lds_all[wave], lane);
-}
-
-template <bool P>
-__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge_table(Bufs kb, Bufs vb,
-                                                                       const MergeJob *__restrict__ jobs,
-                                                                       const uint32_t *__restrict__ tile_job,
-                                                                       uint32_t ntiles)
-{
-    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t tile = blockIdx.x * kWavesPerGroup + wave;
-    if (tile >= ntiles)
-        return;
-    const MergeJob j = jobs[tile_job[tile]];
-    const uint32_t d0 = (tile - j.first_tile) * (uint32_t)kTile;
-    const uint32_t left = j.na + j.nb - d0;
-    const uint32_t count = left < (uint32_t)kTile ? left : (uint32_t)kTile;
-    const uint32_t *ks = j.src == kBufIn ? kb.in : (j.src == kBufOut ? kb.out : kb.temp);
-    uint32_t *kd = j.dst == kBufOut ? kb.out : kb.temp;
-    const uint32_t *vs = nullptr;
-    uint32_t *vd = nullptr;
-    if constexpr (P) {
-        vs = j.src == kBufIn ? vb.in : (j.src == kBufOut ? vb.out : vb.temp);
-        vd = j.dst == kBufOut ? vb.out : vb.temp;
+struct RegularSortSrc {
+    const uint32_t *kin, *vin;
+    uint32_t *kout, *vout;
+    uint64_t n;
+    uint32_t ntiles;
+    __device__ SortItem get(uint32_t t) const
+    {
+        const uint64_t start = (uint64_t)t * kTile;
+        const uint64_t rem = n - start;
+        SortItem it;
+        it.ks = kin + start;
+        it.vs = vin ? vin + start : nullptr;
+        it.kd = kout + start;
+        it.vd = vout ? vout + start : nullptr;
+        it.count = rem < (uint64_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
+        return it;
     }
-    merge_range<P>(ks + j.a_start, P ? vs + j.a_start : nullptr, j.na, j.nb, d0, count, kd + j.a_start,
-                   P ? vd + j.a_start : nullptr, lds_all[wave], lane);
+};
+
+struct TableSortSrc {
+    Bufs kb, vb;
+    const BlockTile *tiles;
+    uint32_t ntiles;
+    __device__ SortItem get(uint32_t t) const
+    {
+        const BlockTile d = tiles[t];
+        SortItem it;
+        it.ks = kb.in + d.start;
+        it.vs = vb.in ? vb.in + d.start : nullptr;
+        it.kd = (d.dst == kBufOut ? kb.out : kb.temp) + d.start;
+        it.vd = vb.out ? (d.dst == kBufOut ? vb.out : vb.temp) + d.start : nullptr;
+        it.count = d.count;
+        return it;
+    }
+};
+
+// One merge work item before splitting: runs A = ka[0, na) and
+// B = ka[na, na + nb); outputs [d0, d0 + count) of their merge go to kd + d0.
+struct MergeItem {
+    const uint32_t *ka, *va;
+    uint32_t *kd, *vd;
+    uint32_t na, nb, d0, count;
+};
+
+// Runs of length `run` (a multiple of kTile) cover [0, n); runs 2s and 2s+1
+// are merged into [2s*run, min(2(s+1)*run, n)).
+struct RegularMergeSrc {
+    const uint32_t *ksrc, *vsrc;
+    uint32_t *kdst, *vdst;
+    uint64_t n, run;
+    uint32_t ntiles;
+    __device__ MergeItem get(uint32_t t) const
+    {
+        const uint64_t gstart = (uint64_t)t * kTile;
+        const uint64_t base = gstart / (2 * run) * (2 * run);
+        const uint64_t rem = n - base;
+        MergeItem m;
+        m.na = (uint32_t)(rem < run ? rem : run);
+        const uint64_t remb = rem - m.na;
+        m.nb = (uint32_t)(remb < run ? remb : run);
+        m.d0 = (uint32_t)(gstart - base);
+        const uint32_t left = m.na + m.nb - m.d0;
+        m.count = left < (uint32_t)kTile ? left : (uint32_t)kTile;
+        m.ka = ksrc + base;
+        m.va = vsrc ? vsrc + base : nullptr;
+        m.kd = kdst + base;
+        m.vd = vdst ? vdst + base : nullptr;
+        return m;
+    }
+};
+
+struct TableMergeSrc {
+    Bufs kb, vb;
+    const MergeJob *jobs;
+    const uint32_t *tile_job;
+    uint32_t ntiles;
+    __device__ MergeItem get(uint32_t t) const
+    {
+        const MergeJob j = jobs[tile_job[t]];
+        MergeItem m;
+        m.na = j.na;
+        m.nb = j.nb;
+        m.d0 = (t - j.first_tile) * (uint32_t)kTile;
+        const uint32_t left = j.na + j.nb - m.d0;
+        m.count = left < (uint32_t)kTile ? left : (uint32_t)kTile;
+        m.ka = (j.src == kBufIn ? kb.in : (j.src == kBufOut ? kb.out : kb.temp)) + j.a_start;
+        m.kd = (j.dst == kBufOut ? kb.out : kb.temp) + j.a_start;
+        m.va = nullptr;
+        m.vd = nullptr;
+        if (vb.out) {
+            m.va = (j.src == kBufIn ? vb.in : (j.src == kBufOut ? vb.out : vb.temp)) + j.a_start;
+            m.vd = (j.dst == kBufOut ? vb.out : vb.temp) + j.a_start;
+        }
+        return m;
+    }
+};
+
+// The A/B pieces of tile t from its split (co-rank at d0, computed by
+// k_partition) and the next tile's split, or the end of A when the tile ends
+// its merge.
+template <bool P, class Src>
+__device__ __forceinline__ MergeTask<P> merge_task(const Src &src, const uint32_t *__restrict__ splits, uint32_t t)
+{
+    const MergeItem m = src.get(t);
+    const uint32_t a0 = splits[t];
+    const uint32_t a1 = (m.d0 + m.count == m.na + m.nb) ? m.na : splits[t + 1];
+    const uint32_t b0 = m.d0 - a0;
+    MergeTask<P> k;
+    k.pa = a1 - a0;
+    k.pb = m.count - k.pa;
+    k.count = m.count;
+    k.ka = m.ka + a0;
+    k.kb = m.ka + m.na + b0;
+    k.kd = m.kd + m.d0;
+    k.va = P ? m.va + a0 : nullptr;
+    k.vb = P ? m.va + m.na + b0 : nullptr;
+    k.vd = P ? m.vd + m.d0 : nullptr;
+    return k;
+}
+
+// ------------------------------------------------------------------- kernels
+//
+// The sort and merge kernels are persistent: wave g of G handles tiles
+// g, g + G, g + 2G, ...  For keys, the loads of the next tile are issued
+// before the current tile is sorted/merged, so a wave's memory traffic
+// overlaps its own arithmetic (two tiles of registers are live; for pairs,
+// three arrays per tile would not fit, so pairs process one tile at a time).
+
+template <bool P, class Src>
+__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
+{
+    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint32_t *lds = lds_all[wave];
+    const uint32_t G = gridDim.x * kWavesPerGroup;
+    uint32_t t = blockIdx.x * kWavesPerGroup + wave;
+    if (t >= src.ntiles)
+        return;
+    if constexpr (P) {
+        for (; t < src.ntiles; t += G) {
+            const uint32_t ln = opaque(lane);
+            const SortItem it = src.get(t);
+            Lines<P> a;
+            load_tile<P>(a, it.ks, it.vs, it.count, ln);
+            sort_tile<P>(a, lds, ln);
+            store_tile<P>(a, it.kd, it.vd, it.count, ln);
+        }
+    } else {
+        Lines<P> a, b;
+        SortItem ia = src.get(t), ib;
+        load_tile<P>(a, ia.ks, ia.vs, ia.count, lane);
+        for (;;) {
+            uint32_t ln = opaque(lane);
+            const uint32_t tb = t + G;
+            const bool hb = tb < src.ntiles;
+            if (hb) {
+                ib = src.get(tb);
+                load_tile<P>(b, ib.ks, ib.vs, ib.count, ln);
+            }
+            sort_tile<P>(a, lds, ln);
+            store_tile<P>(a, ia.kd, ia.vd, ia.count, ln);
+            if (!hb)
+                break;
+            ln = opaque(lane);
+            t = tb + G;
+            const bool ha = t < src.ntiles;
+            if (ha) {
+                ia = src.get(t);
+                load_tile<P>(a, ia.ks, ia.vs, ia.count, ln);
+            }
+            sort_tile<P>(b, lds, ln);
+            store_tile<P>(b, ib.kd, ib.vd, ib.count, ln);
+            if (!ha)
+                break;
+        }
+    }
+}
+
+// Split of every merge tile: splits[t] = co-rank of the tile's first output
+// diagonal in its merge (paper Sec. 3.2: the rank of a splitter in each run,
+// here computed exactly for every tile boundary).  One half-wave per tile.
+template <class Src>
+__global__ __launch_bounds__(256) void k_partition(Src src, uint32_t *__restrict__ splits)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t t = (blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * 2 + (lane >> 5);
+    const bool valid = t < src.ntiles;
+    MergeItem m = src.get(valid ? t : src.ntiles - 1);
+    if (!valid)
+        m.na = m.nb = m.d0 = 0;
+    const uint32_t split = corank_halfwave(m.ka, m.na, m.ka + m.na, m.nb, m.d0, lane);
+    if (valid && (lane & 31) == 0)
+        splits[t] = split;
+}
+
+// MODE 0: persistent waves, next tile's loads issued before the current tile
+//         is merged (keys only; pairs fall back to MODE 1);
+// MODE 1: persistent waves, one tile at a time;
+// MODE 2: one tile per wave (grid covers every tile).
+template <bool P, class Src, int MODE>
+__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const uint32_t *__restrict__ splits)
+{
+    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint32_t *lds = lds_all[wave];
+    const uint32_t G = gridDim.x * kWavesPerGroup;
+    uint32_t t = blockIdx.x * kWavesPerGroup + wave;
+    if (t >= src.ntiles)
+        return;
+    if constexpr (MODE == 2) {
+        const MergeTask<P> m = merge_task<P>(src, splits, t);
+        Lines<P> a;
+        merge_load<P>(a, m, lane);
+        merge_network<P>(a, lds, lane);
+        store_tile<P>(a, m.kd, m.vd, m.count, lane);
+    } else if constexpr (P || MODE == 1) {
+        for (; t < src.ntiles; t += G) {
+            const uint32_t ln = opaque(lane);
+            const MergeTask<P> m = merge_task<P>(src, splits, t);
+            Lines<P> a;
+            merge_load<P>(a, m, ln);
+            merge_network<P>(a, lds, ln);
+            store_tile<P>(a, m.kd, m.vd, m.count, ln);
+        }
+    } else {
+        Lines<P> a, b;
+        MergeTask<P> ma = merge_task<P>(src, splits, t), mb;
+        merge_load<P>(a, ma, lane);
+        for (;;) {
+            uint32_t ln = opaque(lane);
+            const uint32_t tb = t + G;
+            const bool hb = tb < src.ntiles;
+            if (hb) {
+                mb = merge_task<P>(src, splits, tb);
+                merge_load<P>(b, mb, ln);
+            }
+            merge_network<P>(a, lds, ln);
+            store_tile<P>(a, ma.kd, ma.vd, ma.count, ln);
+            if (!hb)
+                break;
+            ln = opaque(lane);
+            t = tb + G;
+            const bool ha = t < src.ntiles;
+            if (ha) {
+                ma = merge_task<P>(src, splits, t);
+                merge_load<P>(a, ma, ln);
+            }
+            merge_network<P>(b, lds, ln);
+            store_tile<P>(b, mb.kd, mb.vd, mb.count, ln);
+            if (!ha)
+                break;
+        }
+    }
 }
 
 // Sortedness check of the runs of a merge input: sets *flag when some
@@ -318,55 +501,110 @@ __global__ void k_check_runs(const uint32_t *__restrict__ keys, const uint64_t *
 
 // ------------------------------------------------------------------ launchers
 
-static inline uint32_t groups_for(uint64_t tiles)
+// Work-groups of a persistent launch: enough to fill every CU at the
+// kernel's occupancy, never more than the tiles need.
+template <class K>
+static uint32_t persistent_groups(K kernel, uint64_t tiles)
 {
-    return (uint32_t)((tiles + kWavesPerGroup - 1) / kWavesPerGroup);
+    static int resident = 0;  // per kernel instantiation
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave * kWavesPerGroup, 0) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = 1, cus = 256;
+        resident = cus * per_cu;
+    }
+    const uint64_t need = (tiles + kWavesPerGroup - 1) / kWavesPerGroup;
+    return (uint32_t)(need < (uint64_t)resident ? need : (uint64_t)resident);
+}
+
+template <bool P, class Src>
+static hipError_t launch_sort(const Src &src, hipStream_t s)
+{
+    if (src.ntiles == 0)
+        return hipSuccess;
+    const dim3 grid(persistent_groups(k_block_sort<P, Src>, src.ntiles)), block(kWave * kWavesPerGroup);
+    hipLaunchKernelGGL((k_block_sort<P, Src>), grid, block, 0, s, src);
+    return hipGetLastError();
+}
+
+template <class Src>
+static hipError_t launch_partition(const Src &src, uint32_t *splits, hipStream_t s)
+{
+    if (src.ntiles == 0)
+        return hipSuccess;
+    const uint32_t pgroups = (src.ntiles + 2 * (256 / kWave) - 1) / (2 * (256 / kWave));
+    hipLaunchKernelGGL((k_partition<Src>), dim3(pgroups), dim3(256), 0, s, src, splits);
+    return hipGetLastError();
+}
+
+// Merge kernel variant: BCF_MERGE_MODE=0|1|2 (see k_merge), default 1.
+static int merge_mode()
+{
+    const char *e = std::getenv("BCF_MERGE_MODE");
+    return (e && e[0] >= '0' && e[0] <= '2') ? e[0] - '0' : 1;
+}
+
+template <bool P, class Src, int MODE>
+static hipError_t launch_merge_mode(const Src &src, const uint32_t *splits, hipStream_t s)
+{
+    const uint32_t groups = MODE == 2 ? (src.ntiles + kWavesPerGroup - 1) / kWavesPerGroup
+                                      : persistent_groups(k_merge<P, Src, MODE>, src.ntiles);
+    hipLaunchKernelGGL((k_merge<P, Src, MODE>), dim3(groups), dim3(kWave * kWavesPerGroup), 0, s, src, splits);
+    return hipGetLastError();
+}
+
+template <bool P, class Src>
+static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream_t s)
+{
+    if (src.ntiles == 0)
+        return hipSuccess;
+    switch (merge_mode()) {
+    case 0: return P ? launch_merge_mode<P, Src, 1>(src, splits, s) : launch_merge_mode<P, Src, 0>(src, splits, s);
+    case 2: return launch_merge_mode<P, Src, 2>(src, splits, s);
+    default: return launch_merge_mode<P, Src, 1>(src, splits, s);
+    }
 }
 
 hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
                                      uint32_t *vout, uint64_t n, hipStream_t s)
 {
-    const uint64_t tiles = (n + kTile - 1) / kTile;
-    const dim3 grid(groups_for(tiles)), block(kWave * kWavesPerGroup);
-    if (pairs)
-        hipLaunchKernelGGL(k_block_sort<true>, grid, block, 0, s, kin, vin, kout, vout, n);
-    else
-        hipLaunchKernelGGL(k_block_sort<false>, grid, block, 0, s, kin, vin, kout, vout, n);
-    return hipGetLastError();
+    RegularSortSrc src{kin, pairs ? vin : nullptr, kout, pairs ? vout : nullptr, n,
+                       (uint32_t)((n + kTile - 1) / kTile)};
+    return pairs ? launch_sort<true>(src, s) : launch_sort<false>(src, s);
 }
 
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc, uint32_t *kdst,
-                                uint32_t *vdst, uint64_t n, uint64_t run, hipStream_t s)
+                                uint32_t *vdst, uint64_t n, uint64_t run, uint32_t *splits, bool partition,
+                                hipStream_t s)
 {
-    const uint64_t tiles = (n + kTile - 1) / kTile;
-    const dim3 grid(groups_for(tiles)), block(kWave * kWavesPerGroup);
-    if (pairs)
-        hipLaunchKernelGGL(k_merge<true>, grid, block, 0, s, ksrc, vsrc, kdst, vdst, n, run);
-    else
-        hipLaunchKernelGGL(k_merge<false>, grid, block, 0, s, ksrc, vsrc, kdst, vdst, n, run);
-    return hipGetLastError();
+    RegularMergeSrc src{ksrc, pairs ? vsrc : nullptr, kdst, pairs ? vdst : nullptr, n, run,
+                        (uint32_t)((n + kTile - 1) / kTile)};
+    if (partition)
+        return launch_partition(src, splits, s);
+    return pairs ? launch_merge<true>(src, splits, s) : launch_merge<false>(src, splits, s);
 }
 
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles, uint32_t ntiles,
                                    hipStream_t s)
 {
-    const dim3 grid(groups_for(ntiles)), block(kWave * kWavesPerGroup);
-    if (pairs)
-        hipLaunchKernelGGL(k_block_sort_table<true>, grid, block, 0, s, kb, vb, tiles, ntiles);
-    else
-        hipLaunchKernelGGL(k_block_sort_table<false>, grid, block, 0, s, kb, vb, tiles, ntiles);
-    return hipGetLastError();
+    if (!pairs)
+        vb = Bufs{nullptr, nullptr, nullptr};
+    TableSortSrc src{kb, vb, tiles, ntiles};
+    return pairs ? launch_sort<true>(src, s) : launch_sort<false>(src, s);
 }
 
 hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs, const uint32_t *tile_job,
-                              uint32_t ntiles, hipStream_t s)
+                              uint32_t ntiles, uint32_t *splits, bool partition, hipStream_t s)
 {
-    const dim3 grid(groups_for(ntiles)), block(kWave * kWavesPerGroup);
-    if (pairs)
-        hipLaunchKernelGGL(k_merge_table<true>, grid, block, 0, s, kb, vb, jobs, tile_job, ntiles);
-    else
-        hipLaunchKernelGGL(k_merge_table<false>, grid, block, 0, s, kb, vb, jobs, tile_job, ntiles);
-    return hipGetLastError();
+    if (!pairs)
+        vb = Bufs{nullptr, nullptr, nullptr};
+    TableMergeSrc src{kb, vb, jobs, tile_job, ntiles};
+    if (partition)
+        return launch_partition(src, splits, s);
+    return pairs ? launch_merge<true>(src, splits, s) : launch_merge<false>(src, splits, s);
 }
 
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *offs_dev, uint32_t k, uint64_t n,
@@ -380,6 +618,12 @@ const char *kname_block_sort(bool pairs, bool table)
 {
     return pairs ? (table ? "block_sort_pairs_table" : "block_sort_pairs")
                  : (table ? "block_sort_keys_table" : "block_sort_keys");
+}
+
+const char *kname_partition(bool pairs, bool table)
+{
+    return pairs ? (table ? "partition_pairs_table" : "partition_pairs")
+                 : (table ? "partition_keys_table" : "partition_keys");
 }
 
 const char *kname_merge(bool pairs, bool table)

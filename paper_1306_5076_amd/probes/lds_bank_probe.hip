@@ -127,6 +127,101 @@ __global__ void copy_u32x4(const uint4 *__restrict__ in, uint4 *__restrict__ out
         out[i] = in[i];
 }
 
+// One wave copies one 4096-element tile, lane l moving elements 64r + l
+// (r = 0..63): the access pattern of the sort kernels' STRIDED tile I/O.
+template <bool NT>
+__global__ __launch_bounds__(128) void copy_tiles_strided(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                          size_t ntiles)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const size_t tile = (size_t)blockIdx.x * 2 + (threadIdx.x >> 6);
+    if (tile >= ntiles)
+        return;
+    const uint32_t *src = in + tile * 4096 + lane;
+    uint32_t *dst = out + tile * 4096 + lane;
+    uint32_t v[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r)
+        v[r] = NT ? __builtin_nontemporal_load(src + 64 * r) : src[64 * r];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) {
+        if (NT)
+            __builtin_nontemporal_store(v[r], dst + 64 * r);
+        else
+            dst[64 * r] = v[r];
+    }
+}
+
+// Same tiles, lane l moving 16-byte groups 256q + 4l .. +3 (q = 0..15).
+template <bool NT>
+__global__ __launch_bounds__(128) void copy_tiles_x4(const v4u *__restrict__ in, v4u *__restrict__ out, size_t ntiles)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const size_t tile = (size_t)blockIdx.x * 2 + (threadIdx.x >> 6);
+    if (tile >= ntiles)
+        return;
+    const v4u *src = in + tile * 1024 + lane;
+    v4u *dst = out + tile * 1024 + lane;
+    v4u v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = NT ? __builtin_nontemporal_load(src + 64 * q) : src[64 * q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        if (NT)
+            __builtin_nontemporal_store(v[q], dst + 64 * q);
+        else
+            dst[64 * q] = v[q];
+    }
+}
+
+template <class F>
+double time_ms(F launch, int reps)
+{
+    hipEvent_t a, b;
+    CHECK(hipEventCreate(&a));
+    CHECK(hipEventCreate(&b));
+    for (int w = 0; w < 3; ++w)
+        launch();
+    CHECK(hipEventRecord(a));
+    for (int r = 0; r < reps; ++r)
+        launch();
+    CHECK(hipEventRecord(b));
+    CHECK(hipEventSynchronize(b));
+    CHECK(hipGetLastError());
+    float ms;
+    CHECK(hipEventElapsedTime(&ms, a, b));
+    CHECK(hipEventDestroy(a));
+    CHECK(hipEventDestroy(b));
+    return ms / reps;
+}
+
+void copy_variants(int cus)
+{
+    for (int lg : {26, 28}) {
+        const size_t n = (size_t)1 << lg, ntiles = n / 4096;
+        uint32_t *in, *out;
+        CHECK(hipMalloc(&in, n * 4));
+        CHECK(hipMalloc(&out, n * 4));
+        CHECK(hipMemset(in, 1, n * 4));
+        const dim3 grid((unsigned)((ntiles + 1) / 2)), block(128);
+        struct V {
+            const char *name;
+            double ms;
+        } vs[6];
+        vs[0] = {"tile copy, dword per lane (64 loads)", time_ms([&] { hipLaunchKernelGGL(copy_tiles_strided<false>, grid, block, 0, 0, in, out, ntiles); }, 20)};
+        vs[1] = {"tile copy, dword per lane, nontemporal", time_ms([&] { hipLaunchKernelGGL(copy_tiles_strided<true>, grid, block, 0, 0, in, out, ntiles); }, 20)};
+        vs[2] = {"tile copy, dwordx4 per lane (16 loads)", time_ms([&] { hipLaunchKernelGGL(copy_tiles_x4<false>, grid, block, 0, 0, (const v4u *)in, (v4u *)out, ntiles); }, 20)};
+        vs[3] = {"tile copy, dwordx4 per lane, nontemporal", time_ms([&] { hipLaunchKernelGGL(copy_tiles_x4<true>, grid, block, 0, 0, (const v4u *)in, (v4u *)out, ntiles); }, 20)};
+        vs[4] = {"grid-stride dwordx4, 64 groups/CU", time_ms([&] { hipLaunchKernelGGL(copy_u32x4, dim3(cus * 64), dim3(256), 0, 0, (const uint4 *)in, (uint4 *)out, n / 4); }, 20)};
+        vs[5] = {"hipMemcpyAsync device to device", time_ms([&] { CHECK(hipMemcpyAsync(out, in, n * 4, hipMemcpyDeviceToDevice, 0)); }, 20)};
+        for (auto &v : vs)
+            std::printf("copy 2^%d u32 %-44s %8.1f us %8.1f GB/s\n", lg, v.name, v.ms * 1e3, 2.0 * n * 4 / (v.ms * 1e-3) / 1e9);
+        CHECK(hipFree(in));
+        CHECK(hipFree(out));
+    }
+}
+
 template <int P, int W>
 void run_one(uint32_t *sink, unsigned long long *cyc_d, std::vector<unsigned long long> &cyc_h, int cus,
              double clk_hz)
@@ -205,7 +300,9 @@ int main()
     CHECK(hipMalloc(&cyc_d, 16 * 8 * sizeof(unsigned long long)));
     CHECK(hipMemset(cyc_d, 0, 16 * 8 * sizeof(unsigned long long)));
     std::vector<unsigned long long> cyc_h(16 * 8);
-    run_all(std::make_integer_sequence<int, kPatterns>{}, sink, cyc_d, cyc_h, cus, clk);
+    const bool copy_only = std::getenv("PROBE_COPY_ONLY") != nullptr;
+    if (!copy_only)
+        run_all(std::make_integer_sequence<int, kPatterns>{}, sink, cyc_d, cyc_h, cus, clk);
 
     // streaming copy: achievable HBM rate
     for (int lg : {26, 28}) {
@@ -238,6 +335,7 @@ int main()
         CHECK(hipEventDestroy(a));
         CHECK(hipEventDestroy(b));
     }
+    copy_variants(cus);
     CHECK(hipFree(sink));
     CHECK(hipFree(cyc_d));
     std::printf("done\n");

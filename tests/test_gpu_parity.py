@@ -274,3 +274,17 @@ def test_errors_raise(torch_dev, bcf):
         assert list(got) == [1, 2, 3, 4, 5, 6, 9]
     finally:
         del os.environ["BCF_CHECK"]
+
+
+@pytest.mark.parametrize("mode", ["0", "1", "2"])
+def test_merge_kernel_variants(torch_dev, bcf, mode, monkeypatch):
+    torch, dev = torch_dev
+    monkeypatch.setenv("BCF_MERGE_MODE", mode)
+    for n, dist in [((1 << 20) + 3, "uniform"), (7 * 4096 + 5, "zipf")]:
+        keys = workloads.keys_u32(dist, n, seed=11)
+        got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+        assert first_diff(got, oracle.sort_u32(keys)) is None
+        kk, vv = workloads.pairs_u32(dist, n, seed=12)
+        ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, kk), to_dev(torch, dev, vv))
+        wk, wv = oracle.sort_pairs_u32(kk, vv)
+        assert first_diff(ko.cpu().numpy(), wk) is None and first_diff(vo.cpu().numpy(), wv) is None
