@@ -186,7 +186,8 @@ def main():
             "n": n,
             "distributions": dists,
             "tile_keys": bcf.tile_keys(),
-            "launches_per_sort": bcf.sort_launches(n),
+            "run_keys": bcf.run_keys(),
+            "passes_per_sort": bcf.sort_passes(n),
         },
         "per_distribution_ms": per_dist,
         "roofline": {

@@ -102,12 +102,20 @@ bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const
 /* Human-readable name of a status code (static storage). */
 const char *bcf_status_string(bcf_status s);
 
-/* Keys per tile of the block sort and of one merge-pass work item, for keys
- * only (pairs = 0) or key/value pairs (pairs = 1). */
-uint32_t bcf_tile_keys(int pairs);
+/* Keys per wave tile: one wave sorts (block sort) or produces (merge pass)
+ * 4096 = 64 x 64 keys at a time. */
+uint32_t bcf_tile_keys(void);
 
-/* Number of kernel launches (block sort + merge passes) a sort of n keys uses. */
-uint32_t bcf_sort_launches(uint64_t n);
+/* Length of the sorted runs the block sort of bcf_sort_u32 (pairs = 0) or
+ * bcf_sort_pairs_u32 (pairs = 1) hands to the merge passes: one work-group of
+ * several waves sorts that many keys in LDS. */
+uint32_t bcf_run_keys(int pairs);
+
+/* Passes over the data in HBM of a sort of n keys: the block sort plus
+ * ceil(log2(n / bcf_run_keys(pairs))) binary merge passes (the paper's Lemma 2:
+ * O(1 + log(N/M)) scans).  Each merge pass is preceded by a small partition
+ * launch that reads O(log n) keys per 4096-key output tile. */
+uint32_t bcf_sort_passes(uint64_t n, int pairs);
 
 /*
  * Per-kernel timing.  While enabled, every launch the library makes is

@@ -15,7 +15,8 @@ _API = (
     "merge_runs",
     "segmented_sort",
     "tile_keys",
-    "sort_launches",
+    "run_keys",
+    "sort_passes",
     "profile_enable",
     "profile_collect",
 )

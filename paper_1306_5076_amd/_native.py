@@ -31,7 +31,8 @@ EXPORTED = (
     "bcf_segmented_sort",
     "bcf_status_string",
     "bcf_tile_keys",
-    "bcf_sort_launches",
+    "bcf_run_keys",
+    "bcf_sort_passes",
     "bcf_profile_enable",
     "bcf_profile_collect",
 )
@@ -79,10 +80,12 @@ def load(path: str = LIB_PATH):
         getattr(lib, f).restype = ctypes.c_int
     lib.bcf_status_string.argtypes = [ctypes.c_int]
     lib.bcf_status_string.restype = ctypes.c_char_p
-    lib.bcf_tile_keys.argtypes = [ctypes.c_int]
+    lib.bcf_tile_keys.argtypes = []
     lib.bcf_tile_keys.restype = u32
-    lib.bcf_sort_launches.argtypes = [u64]
-    lib.bcf_sort_launches.restype = u32
+    lib.bcf_run_keys.argtypes = [ctypes.c_int]
+    lib.bcf_run_keys.restype = u32
+    lib.bcf_sort_passes.argtypes = [u64, ctypes.c_int]
+    lib.bcf_sort_passes.restype = u32
     lib.bcf_profile_enable.argtypes = [ctypes.c_int]
     lib.bcf_profile_enable.restype = None
     lib.bcf_profile_collect.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int]

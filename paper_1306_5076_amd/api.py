@@ -22,7 +22,8 @@ __all__ = [
     "merge_runs",
     "segmented_sort",
     "tile_keys",
-    "sort_launches",
+    "run_keys",
+    "sort_passes",
     "profile_enable",
     "profile_collect",
 ]
@@ -91,14 +92,19 @@ def _temp(ws, nbytes, device, stream):
     return buf, ctypes.c_uint64(buf.numel())
 
 
-def tile_keys(pairs: bool = False) -> int:
-    """Keys per block-sort tile (and per merge work item)."""
-    return int(load().bcf_tile_keys(1 if pairs else 0))
+def tile_keys() -> int:
+    """Keys per wave tile (block sort and merge work item): 4096."""
+    return int(load().bcf_tile_keys())
 
 
-def sort_launches(n: int) -> int:
-    """Kernel launches (block sort + merge passes) of a sort of n keys."""
-    return int(load().bcf_sort_launches(n))
+def run_keys(pairs: bool = False) -> int:
+    """Length of the sorted runs the block sort hands to the merge passes."""
+    return int(load().bcf_run_keys(1 if pairs else 0))
+
+
+def sort_passes(n: int, pairs: bool = False) -> int:
+    """Passes over HBM (block sort + merge passes) of a sort of n keys."""
+    return int(load().bcf_sort_passes(n, 1 if pairs else 0))
 
 
 def sort_u32(keys, out=None, stream=None, workspace=None):

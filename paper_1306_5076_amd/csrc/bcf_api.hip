@@ -157,7 +157,8 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     if (!temp_bytes || n > kMaxN)
         return BCF_ERR_INVALID;
     const uint64_t tiles = tiles_of(n);
-    const uint32_t passes = n ? ceil_log2(tiles) : 0;
+    const uint64_t run0 = group_run_keys(pairs);  // sorted run length after the block sort
+    const uint32_t passes = n ? ceil_log2((n + run0 - 1) / run0) : 0;
     // temp: ping-pong keys [, values], then one split per merge tile
     const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
     const uint64_t need = passes ? data + align256(tiles * 4) : 0;
@@ -180,9 +181,9 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     const double elem_bytes = pairs ? 8.0 : 4.0;
     {
         ProfScope p(kname_block_sort(pairs, false), s, 2.0 * elem_bytes * n);
-        BCF_TRY(dev_status(launch_block_sort_regular(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, s)));
+        BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, s)));
     }
-    uint64_t run = kTile;
+    uint64_t run = run0;
     for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
         for (int phase = 0; phase < 2; ++phase) {
             const bool part = phase == 0;
@@ -325,17 +326,16 @@ const char *bcf_status_string(bcf_status s)
     return "BCF_ERR_UNKNOWN";
 }
 
-uint32_t bcf_tile_keys(int pairs)
-{
-    (void)pairs;
-    return (uint32_t)kTile;
-}
+uint32_t bcf_tile_keys(void) { return (uint32_t)kTile; }
 
-uint32_t bcf_sort_launches(uint64_t n)
+uint32_t bcf_run_keys(int pairs) { return group_run_keys(pairs != 0); }
+
+uint32_t bcf_sort_passes(uint64_t n, int pairs)
 {
     if (n == 0)
         return 0;
-    return 1 + ceil_log2(tiles_of(n));
+    const uint64_t run0 = group_run_keys(pairs != 0);
+    return 1 + ceil_log2((n + run0 - 1) / run0);
 }
 
 bcf_status bcf_sort_u32(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n, void *temp,

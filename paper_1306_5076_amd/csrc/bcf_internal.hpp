@@ -39,7 +39,15 @@ struct MergeJob {
     uint16_t dst;
 };
 
+// Waves per work-group of the group block sort (keys / pairs); the sorted
+// runs it produces hold that many 4096-key tiles.
+constexpr int kGroupWavesKeys = 8;
+constexpr int kGroupWavesPairs = 4;
+uint32_t group_run_keys(bool pairs);
+
 // Launchers (enqueue only; return the launch status).
+hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin,
+                                   uint32_t *kout, uint32_t *vout, uint64_t n, hipStream_t s);
 hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint32_t *vin,
                                      uint32_t *kout, uint32_t *vout, uint64_t n, hipStream_t s);
 // A merge pass is two launches: with partition = true the split of every

@@ -38,7 +38,7 @@ namespace bcf {
 template <bool P>
 __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restrict__ ksrc,
                                           const uint32_t *__restrict__ vsrc, uint32_t count,
-                                          uint32_t lane)
+                                          uint32_t lane, uint32_t rank0 = 0)
 {
     const uint32_t *kp = ksrc + lane;
     const uint32_t *vp = P ? vsrc + lane : nullptr;
@@ -47,7 +47,7 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
         for (int r = 0; r < kLine; ++r) {
             t.k[r] = kp[kWave * r];
             if constexpr (P) {
-                t.i[r] = kWave * r + lane;
+                t.i[r] = rank0 + kWave * r + lane;
                 t.v[r] = vp[kWave * r];
             }
         }
@@ -60,7 +60,7 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
             const uint32_t key = count ? ksrc[q] : kMaxKey;
             t.k[r] = p < count ? key : kMaxKey;
             if constexpr (P) {
-                t.i[r] = p < count ? p : kPadIdx;
+                t.i[r] = p < count ? rank0 + p : kPadIdx;
                 t.v[r] = count ? vsrc[q] : 0u;
             }
         }
@@ -121,7 +121,7 @@ __device__ __forceinline__ void merge_round(Lines<P> &t, uint32_t *lds, uint32_t
 // tie-break ranks, are what the sort is defined on.  On exit the tile is
 // sorted in STRIDED layout.
 template <bool P>
-__device__ __forceinline__ void sort_tile(Lines<P> &t, uint32_t *lds, uint32_t lane)
+__device__ __forceinline__ void sort_tile_blocked(Lines<P> &t, uint32_t *lds, uint32_t lane)
 {
     // lines: even lanes ascending, odd lanes descending (run direction = bit 6)
     flip(t, lane);
@@ -133,7 +133,100 @@ __device__ __forceinline__ void sort_tile(Lines<P> &t, uint32_t *lds, uint32_t l
     merge_round<4, P>(t, lds, lane);
     merge_round<5, P>(t, lds, lane);
     merge_round<6, P>(t, lds, lane);
+}
+
+template <bool P>
+__device__ __forceinline__ void sort_tile(Lines<P> &t, uint32_t *lds, uint32_t lane)
+{
+    sort_tile_blocked<P>(t, lds, lane);
     to_strided(t, lds, lane);
+}
+
+// ------------------------------------------------------ group (multi-wave) sort
+//
+// NW waves of a work-group (NW = 2^LW) sort a group tile of NW * 4096 keys:
+// every wave sorts its 4096-key sub-tile (odd waves descending, by
+// complementing around the wave sort), then LW more bitonic rounds
+// (J = 7 .. 6+LW) merge across waves.  Wave w holds group positions with
+// bits 12.. equal to w.  A third layout brings the wave bits into registers:
+//   CROSS  lane = p bits 0..5, wave = p bits 6..5+LW, register = p bits 6+LW..11+LW
+// Round J: BLOCKED -> CROSS (shared LDS, barriers), stages on bits 5+J..6+LW
+// in registers, CROSS -> STRIDED, stages on bits 5+LW..6, STRIDED -> BLOCKED
+// (the wave's own LDS slice), stages on bits 5..0.  The LDS word of position
+// p is p + p/64 in all three layouts, so every access keeps the 65-word rows
+// of the single-wave transposes: each 32-lane half touches 32 distinct banks.
+
+// x[r] -> lds[wbase + WS*r]; barrier; x[r] <- lds[rbase + RS*r]; barrier.
+template <int WS, int RS>
+__device__ __forceinline__ void group_exchange(uint32_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
+                                               uint32_t rbase)
+{
+    uint32_t *w = lds + wbase;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        w[WS * r] = x[r];
+    __syncthreads();
+    const uint32_t *rd = lds + rbase;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = rd[RS * r];
+    __syncthreads();
+}
+
+// BLOCKED p = 4096w + 64 lane + r  ->  CROSS p = lane + 64w + 64*NW*r
+template <int NW, bool P>
+__device__ __forceinline__ void blocked_to_cross(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    const uint32_t wb = kLdsStride * (kWave * wave + lane), rb = kLdsStride * wave + lane;
+    group_exchange<1, kLdsStride * NW>(t.k, lds, wb, rb);
+    if constexpr (P) {
+        group_exchange<1, kLdsStride * NW>(t.i, lds, wb, rb);
+        group_exchange<1, kLdsStride * NW>(t.v, lds, wb, rb);
+    }
+}
+
+// CROSS p = lane + 64w + 64*NW*r  ->  STRIDED p = 4096w + 64r + lane
+template <int NW, bool P>
+__device__ __forceinline__ void cross_to_strided(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    const uint32_t wb = kLdsStride * wave + lane, rb = kLdsStride * kWave * wave + lane;
+    group_exchange<kLdsStride * NW, kLdsStride>(t.k, lds, wb, rb);
+    if constexpr (P) {
+        group_exchange<kLdsStride * NW, kLdsStride>(t.i, lds, wb, rb);
+        group_exchange<kLdsStride * NW, kLdsStride>(t.v, lds, wb, rb);
+    }
+}
+
+constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
+
+// Round J (7 .. 6+LW) of the group sort; on entry and exit the tile is
+// BLOCKED and every run of 2^(6+J) positions is sorted, descending where bit
+// 6+J is set (the last round sorts ascending).
+template <int NW, int J, bool P>
+__device__ __forceinline__ void group_round(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    constexpr int LW = log2i(NW);
+    constexpr bool last = J == 6 + LW;
+    blocked_to_cross<NW>(t, lds, lane, wave);
+    // bits 5+J .. 6+LW = CROSS register bits J-1-LW .. 0; direction bit 6+J = register bit J-LW
+    half_clean<(1 << (J - 1 - LW)), (last ? -1 : J - LW), P>(t);
+    cross_to_strided<NW>(t, lds, lane, wave);
+    // bits 5+LW .. 6 = STRIDED register bits LW-1 .. 0; direction bit 6+J = wave bit J-6
+    if constexpr (!last)
+        flip(t, wave >> (J - 6));
+    half_clean<(1 << (LW - 1)), -1, P>(t);
+    to_blocked(t, lds + kLdsWords * wave, lane);
+    half_clean<kLine / 2, -1, P>(t);
+    if constexpr (!last)
+        flip(t, wave >> (J - 6));
+}
+
+template <int NW, int J, bool P>
+__device__ __forceinline__ void group_rounds(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    group_round<NW, J, P>(t, lds, lane, wave);
+    if constexpr (J < 6 + log2i(NW))
+        group_rounds<NW, J + 1, P>(t, lds, lane, wave);
 }
 
 // --------------------------------------------------------------- merge body
@@ -398,6 +491,48 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
     }
 }
 
+struct RegularGroupSrc {
+    const uint32_t *kin, *vin;
+    uint32_t *kout, *vout;
+    uint64_t n;
+    uint32_t ngroups;
+    uint32_t group_keys;
+    // sub-tile of wave w of group g (count 0 past the end of the input)
+    __device__ SortItem get(uint32_t g, uint32_t w) const
+    {
+        const uint64_t start = (uint64_t)g * group_keys + (uint64_t)w * kTile;
+        const uint64_t rem = start < n ? n - start : 0;
+        SortItem it;
+        it.ks = kin + start;
+        it.vs = vin ? vin + start : nullptr;
+        it.kd = kout + start;
+        it.vd = vout ? vout + start : nullptr;
+        it.count = rem < (uint64_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
+        return it;
+    }
+};
+
+template <int NW, bool P, class Src>
+__global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
+{
+    __shared__ uint32_t lds[NW * kLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint32_t *own = lds + kLdsWords * wave;
+    for (uint32_t g = blockIdx.x; g < src.ngroups; g += gridDim.x) {
+        const uint32_t ln = opaque(lane);
+        const SortItem it = src.get(g, wave);
+        Lines<P> t;
+        load_tile<P>(t, it.ks, it.vs, it.count, ln, wave * kTile);
+        flip(t, wave);  // odd sub-tiles descending
+        sort_tile_blocked<P>(t, own, ln);
+        flip(t, wave);
+        group_rounds<NW, 7, P>(t, lds, ln, wave);
+        to_strided(t, own, ln);
+        store_tile<P>(t, it.kd, it.vd, it.count, ln);
+    }
+}
+
 // Split of every merge tile: splits[t] = co-rank of the tile's first output
 // diagonal in its merge (paper Sec. 3.2: the rank of a splitter in each run,
 // here computed exactly for every tile boundary).  One half-wave per tile.
@@ -574,6 +709,33 @@ hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint
     RegularSortSrc src{kin, pairs ? vin : nullptr, kout, pairs ? vout : nullptr, n,
                        (uint32_t)((n + kTile - 1) / kTile)};
     return pairs ? launch_sort<true>(src, s) : launch_sort<false>(src, s);
+}
+
+template <int NW, bool P>
+static hipError_t launch_group(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                               uint64_t n, hipStream_t s)
+{
+    constexpr uint32_t keys = NW * kTile;
+    RegularGroupSrc src{kin, P ? vin : nullptr, kout, P ? vout : nullptr, n, (uint32_t)((n + keys - 1) / keys), keys};
+    if (src.ngroups == 0)
+        return hipSuccess;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    // one group per CU fits the LDS (NW * 16.6 KiB); persistent over the groups
+    const uint32_t groups = src.ngroups < (uint32_t)cus ? src.ngroups : (uint32_t)cus;
+    hipLaunchKernelGGL((k_block_sort_group<NW, P, RegularGroupSrc>), dim3(groups), dim3(kWave * NW), 0, s, src);
+    return hipGetLastError();
+}
+
+uint32_t group_run_keys(bool pairs) { return pairs ? kGroupWavesPairs * kTile : kGroupWavesKeys * kTile; }
+
+hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                                   uint32_t *vout, uint64_t n, hipStream_t s)
+{
+    return pairs ? launch_group<kGroupWavesPairs, true>(kin, vin, kout, vout, n, s)
+                 : launch_group<kGroupWavesKeys, false>(kin, vin, kout, vout, n, s);
 }
 
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc, uint32_t *kdst,

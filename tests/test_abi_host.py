@@ -44,24 +44,27 @@ def q_sort(lib, n, pairs=False):
     return st, need.value
 
 
-def test_tile_and_launch_count(lib):
-    T = lib.bcf_tile_keys(0)
-    assert T == 4096 and lib.bcf_tile_keys(1) == 4096
-    assert lib.bcf_sort_launches(0) == 0
-    assert lib.bcf_sort_launches(1) == 1
-    assert lib.bcf_sort_launches(T) == 1
-    assert lib.bcf_sort_launches(T + 1) == 2
-    # Lemma 2: 1 + ceil(log2(n / M)) passes over the data
-    for n in [2**16, 2**20, 2**26, 2**28, 3 * T + 5]:
-        tiles = -(-n // T)
-        assert lib.bcf_sort_launches(n) == 1 + int(np.ceil(np.log2(tiles)))
+def test_tile_run_and_pass_count(lib):
+    assert lib.bcf_tile_keys() == 4096
+    assert lib.bcf_run_keys(0) == 32768 and lib.bcf_run_keys(1) == 16384
+    for pairs in (0, 1):
+        R = lib.bcf_run_keys(pairs)
+        assert lib.bcf_sort_passes(0, pairs) == 0
+        assert lib.bcf_sort_passes(1, pairs) == 1
+        assert lib.bcf_sort_passes(R, pairs) == 1
+        assert lib.bcf_sort_passes(R + 1, pairs) == 2
+        # Lemma 2: 1 + ceil(log2(n / M)) passes over the data
+        for n in [2**16, 2**20, 2**26, 2**28, 3 * R + 5]:
+            runs = -(-n // R)
+            assert lib.bcf_sort_passes(n, pairs) == 1 + int(np.ceil(np.log2(runs)))
 
 
 def test_temp_queries(lib):
     assert q_sort(lib, 0) == (0, 0)
-    assert q_sort(lib, 4096) == (0, 0)  # one tile: no merge pass, no temp
-    st, need = q_sort(lib, 4097)
-    assert st == 0 and need >= 4097 * 4 and need % 256 == 0
+    assert q_sort(lib, 32768) == (0, 0)  # one sorted run: no merge pass, no temp
+    assert q_sort(lib, 16384, pairs=True) == (0, 0)
+    st, need = q_sort(lib, 32769)
+    assert st == 0 and need >= 32769 * 4 and need % 256 == 0
     st, need = q_sort(lib, 2**26, pairs=True)
     # two ping-pong arrays (keys, values) plus one u32 split per merge tile
     assert st == 0 and need == 2 * 2**26 * 4 + (2**26 // 4096) * 4

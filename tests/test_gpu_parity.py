@@ -245,10 +245,28 @@ def test_profile_records_every_launch(torch_dev, bcf):
     bcf.sort_u32(keys)
     bcf.profile_enable(False)
     st = bcf.profile_collect()
+    merges = bcf.sort_passes(n) - 1
     assert st["block_sort_keys"]["launches"] == 1
-    assert st["merge_keys"]["launches"] == bcf.sort_launches(n) - 1
-    assert st["merge_keys"]["bytes"] == pytest.approx((bcf.sort_launches(n) - 1) * 8.0 * n)
+    assert st["merge_keys"]["launches"] == merges
+    assert st["partition_keys"]["launches"] == merges
+    assert st["merge_keys"]["bytes"] == pytest.approx(merges * 8.0 * n)
     assert all(v["total_ms"] > 0 for v in st.values())
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_group_tile_boundaries(torch_dev, bcf, pairs):
+    # sizes around one and several block-sort runs (group tiles)
+    torch, dev = torch_dev
+    R = bcf.run_keys(pairs)
+    for n in (R - 1, R, R + 1, 2 * R - 4096, 3 * R + 4097, 5 * R + 1):
+        keys, vals = workloads.pairs_u32("zipf", n, seed=n)
+        if pairs:
+            ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, keys), to_dev(torch, dev, vals))
+            wk, wv = oracle.sort_pairs_u32(keys, vals)
+            assert first_diff(ko.cpu().numpy(), wk) is None and first_diff(vo.cpu().numpy(), wv) is None
+        else:
+            got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+            assert first_diff(got, oracle.sort_u32(keys)) is None
 
 
 def test_errors_raise(torch_dev, bcf):

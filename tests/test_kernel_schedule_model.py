@@ -295,3 +295,107 @@ def test_paper_fig1_bank_matrix_view():
         for col, name in enumerate(elems):
             k = int(name[2:])
             assert k % 8 == int(bank) and k // 8 == col
+
+
+# ------------------------------------------------- group (multi-wave) sort
+
+
+def lds_word(p):
+    return p + p // 64
+
+
+def group_sort_model(x, nw):
+    """Replays k_block_sort_group<NW>: per-wave sorts, then cross-wave rounds
+    through the BLOCKED / CROSS / STRIDED layouts with the kernel's LDS words."""
+    lw = nw.bit_length() - 1
+    lanes = np.arange(W)
+    regs = []
+    for w in range(nw):
+        R = np.empty((W, E), dtype=x.dtype)
+        for r in range(E):
+            R[:, r] = x[T * w + W * r + lanes]
+        flip(R, np.full(W, w & 1))
+        flip(R, lanes)
+        apply(R, OE64)
+        flip(R, lanes)
+        for j in range(1, 7):
+            R = fast_to_strided(R)
+            apply(R, half_clean(1 << (j - 1), j if j < 6 else -1))
+            R = fast_to_blocked(R)
+            if j < 6:
+                flip(R, lanes >> j)
+            apply(R, half_clean(E // 2, -1))
+            if j < 6:
+                flip(R, lanes >> j)
+        flip(R, np.full(W, w & 1))
+        regs.append(R)
+
+    def move(src_pos, dst_pos):
+        lds = {}
+        for w in range(nw):
+            for r in range(E):
+                for l in range(W):
+                    lds[lds_word(src_pos(w, l, r))] = regs[w][l, r]
+        out = []
+        for w in range(nw):
+            R = np.empty((W, E), dtype=x.dtype)
+            for r in range(E):
+                for l in range(W):
+                    R[l, r] = lds[lds_word(dst_pos(w, l, r))]
+            out.append(R)
+        return out
+
+    blocked = lambda w, l, r: T * w + W * l + r
+    strided = lambda w, l, r: T * w + W * r + l
+    cross = lambda w, l, r: l + W * w + W * nw * r
+    for J in range(7, 7 + lw):
+        last = J == 6 + lw
+        regs = move(blocked, cross)
+        for R in regs:
+            apply(R, half_clean(1 << (J - 1 - lw), -1 if last else J - lw))
+        regs = move(cross, strided)
+        for w, R in enumerate(regs):
+            if not last:
+                flip(R, np.full(W, (w >> (J - 6)) & 1))
+            apply(R, half_clean(1 << (lw - 1), -1))
+            R2 = fast_to_blocked(R)
+            apply(R2, half_clean(E // 2, -1))
+            if not last:
+                flip(R2, np.full(W, (w >> (J - 6)) & 1))
+            regs[w] = R2
+    out = np.empty(nw * T, dtype=x.dtype)
+    for w in range(nw):
+        R = fast_to_strided(regs[w])
+        for r in range(E):
+            out[T * w + W * r + lanes] = R[:, r]
+    return out
+
+
+@pytest.mark.parametrize("nw", [4, 8])
+def test_group_sort_schedule_sorts(nw):
+    rng = np.random.default_rng(nw)
+    for x in (rng.integers(0, 2**32, size=nw * T, dtype=np.uint64).astype(np.uint32),
+              rng.integers(0, 2, size=nw * T).astype(np.uint32),
+              np.arange(nw * T, dtype=np.uint32)[::-1].copy()):
+        assert np.array_equal(group_sort_model(x, nw), np.sort(x))
+
+
+@pytest.mark.parametrize("nw", [4, 8])
+def test_group_layouts_conflict_free(nw):
+    lanes = np.arange(W)
+    layouts = {
+        "blocked": lambda w, l, r: T * w + W * l + r,
+        "strided": lambda w, l, r: T * w + W * r + l,
+        "cross": lambda w, l, r: l + W * w + W * nw * r,
+    }
+    for name, pos in layouts.items():
+        for w in range(nw):
+            for r in range(E):
+                banks = lds_word(pos(w, lanes, r)) % BANKS
+                for h in range(W // HALF):
+                    assert len(set(banks[h * HALF:(h + 1) * HALF].tolist())) == HALF, (name, w, r)
+    # every layout is a bijection onto the group tile, inside the LDS array
+    for pos in layouts.values():
+        ps = {pos(w, l, r) for w in range(nw) for l in range(W) for r in range(E)}
+        assert ps == set(range(nw * T))
+    assert lds_word(nw * T - 1) < nw * W * STRIDE
