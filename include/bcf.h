@@ -99,6 +99,32 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
 bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
                               uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream);
 
+/*
+ * Stable segmented sort of key/value pairs: every segment is sorted by key,
+ * equal keys keeping their input order.  Same conventions as
+ * bcf_segmented_sort, with values carried alongside the keys.
+ */
+bcf_status bcf_segmented_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                                    uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg,
+                                    void *temp, uint64_t *temp_bytes, void *stream);
+
+/*
+ * The segmented sort split in two so that the device part can be captured in
+ * a hipGraph and replayed.  bcf_segmented_upload plans the launches for
+ * seg_offsets and copies the plan (tile and merge descriptors, a few bytes
+ * per 4096 keys) into temp with one host-to-device copy on `stream`; keys are
+ * not touched.  bcf_segmented_execute then only enqueues kernels that read the
+ * plan from temp: it performs no copy and no allocation.  Both calls must get
+ * the same seg_offsets, nseg, pairs flag (vals_in != NULL) and temp buffer,
+ * and temp must keep the plan between them (and across graph replays).
+ * Temp-size queries (temp == NULL) behave as in bcf_segmented_sort[_pairs].
+ */
+bcf_status bcf_segmented_upload(const uint64_t *seg_offsets, uint32_t nseg, int pairs, void *temp,
+                                uint64_t *temp_bytes, void *stream);
+bcf_status bcf_segmented_execute(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                                 uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg, void *temp,
+                                 uint64_t *temp_bytes, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *bcf_status_string(bcf_status s);
 

@@ -14,6 +14,7 @@ _API = (
     "sort_pairs_u32",
     "merge_runs",
     "segmented_sort",
+    "SegmentedPlan",
     "tile_keys",
     "run_keys",
     "sort_passes",

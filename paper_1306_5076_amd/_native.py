@@ -29,6 +29,9 @@ EXPORTED = (
     "bcf_sort_pairs_u32",
     "bcf_merge_runs",
     "bcf_segmented_sort",
+    "bcf_segmented_sort_pairs",
+    "bcf_segmented_upload",
+    "bcf_segmented_execute",
     "bcf_status_string",
     "bcf_tile_keys",
     "bcf_run_keys",
@@ -76,7 +79,11 @@ def load(path: str = LIB_PATH):
     lib.bcf_sort_pairs_u32.argtypes = [vp, vp, vp, vp, u64, vp, u64p, vp]
     lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
     lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
-    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_segmented_sort"):
+    lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
+    lib.bcf_segmented_upload.argtypes = [u64p, u32, ctypes.c_int, vp, u64p, vp]
+    lib.bcf_segmented_execute.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
+    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_segmented_sort",
+              "bcf_segmented_sort_pairs", "bcf_segmented_upload", "bcf_segmented_execute"):
         getattr(lib, f).restype = ctypes.c_int
     lib.bcf_status_string.argtypes = [ctypes.c_int]
     lib.bcf_status_string.restype = ctypes.c_char_p

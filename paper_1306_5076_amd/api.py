@@ -21,6 +21,7 @@ __all__ = [
     "sort_pairs_u32",
     "merge_runs",
     "segmented_sort",
+    "SegmentedPlan",
     "tile_keys",
     "run_keys",
     "sort_passes",
@@ -189,27 +190,95 @@ def merge_runs(keys, run_offsets, vals=None, keys_out=None, vals_out=None, strea
     return (keys_out, vals_out) if vals is not None else keys_out
 
 
-def segmented_sort(keys, seg_offsets, out=None, stream=None, workspace=None):
-    """Sort every segment [off[s], off[s+1]) of ``keys`` independently."""
+def segmented_sort(keys, seg_offsets, vals=None, keys_out=None, vals_out=None, stream=None, workspace=None,
+                   out=None):
+    """Sort every segment [off[s], off[s+1]) of ``keys`` independently.
+
+    With ``vals`` the sort is a stable key/value sort per segment and
+    ``(keys_out, vals_out)`` is returned; otherwise ``keys_out``.
+    """
     lib = load()
     _check_tensor(keys, "keys")
     n = keys.numel()
     off = _offsets(seg_offsets, n)
     nseg = off.size - 1
-    out = torch.empty_like(keys) if out is None else out
+    keys_out = out if keys_out is None else keys_out
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if vals is not None:
+        _check_tensor(vals, "vals", keys.device)
+        vals_out = torch.empty_like(vals) if vals_out is None else vals_out
     stream, sh = _stream(stream, keys.device)
     offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     need = ctypes.c_uint64(0)
-    check("bcf_segmented_sort", lib.bcf_segmented_sort(None, None, offp, nseg, None, ctypes.byref(need), None))
+    if vals is None:
+        check("bcf_segmented_sort", lib.bcf_segmented_sort(None, None, offp, nseg, None, ctypes.byref(need), None))
+    else:
+        check("bcf_segmented_sort_pairs", lib.bcf_segmented_sort_pairs(
+            None, None, None, None, offp, nseg, None, ctypes.byref(need), None))
     temp, tb = _temp(workspace, need.value, keys.device, stream)
     if n:
-        check(
-            "bcf_segmented_sort",
-            lib.bcf_segmented_sort(
-                _ptr(keys), _ptr(out), offp, nseg, _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh
-            ),
-        )
-    return out
+        tp = _ptr(temp) or ctypes.c_void_p(1)
+        if vals is None:
+            check("bcf_segmented_sort", lib.bcf_segmented_sort(
+                _ptr(keys), _ptr(keys_out), offp, nseg, tp, ctypes.byref(tb), sh))
+        else:
+            check("bcf_segmented_sort_pairs", lib.bcf_segmented_sort_pairs(
+                _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), offp, nseg, tp, ctypes.byref(tb), sh))
+    return (keys_out, vals_out) if vals is not None else keys_out
+
+
+class SegmentedPlan:
+    """A segmented sort planned once for fixed segment offsets.
+
+    The constructor uploads the launch plan into a device buffer owned by the
+    plan; :meth:`run` then enqueues kernels only (no copy, no allocation), so
+    it can be captured in a graph (:meth:`capture`) and replayed.
+    """
+
+    def __init__(self, seg_offsets, device, pairs: bool = False, stream=None):
+        lib = load()
+        self.device = torch.device(device)
+        self.off = _offsets(seg_offsets)
+        self.nseg = self.off.size - 1
+        self.n = int(self.off[-1]) if self.off.size else 0
+        self.pairs = bool(pairs)
+        self._offp = self.off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        need = ctypes.c_uint64(0)
+        check("bcf_segmented_upload", lib.bcf_segmented_upload(
+            self._offp, self.nseg, int(self.pairs), None, ctypes.byref(need), None))
+        self.temp = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=self.device)
+        self._tb = ctypes.c_uint64(self.temp.numel())
+        stream, sh = _stream(stream, self.device)
+        if self.n:
+            check("bcf_segmented_upload", lib.bcf_segmented_upload(
+                self._offp, self.nseg, int(self.pairs), _ptr(self.temp), ctypes.byref(self._tb), sh))
+
+    def run(self, keys, keys_out, vals=None, vals_out=None, stream=None):
+        lib = load()
+        _check_tensor(keys, "keys", self.device)
+        _check_tensor(keys_out, "keys_out", self.device)
+        if keys.numel() != self.n or keys_out.numel() != self.n:
+            raise ValueError("keys do not match the planned segments")
+        if (vals is not None) != self.pairs:
+            raise ValueError("values must be given exactly when the plan is for pairs")
+        stream, sh = _stream(stream, self.device)
+        if self.n:
+            check("bcf_segmented_execute", lib.bcf_segmented_execute(
+                _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), self._offp, self.nseg,
+                _ptr(self.temp), ctypes.byref(self._tb), sh))
+        return (keys_out, vals_out) if self.pairs else keys_out
+
+    def capture(self, keys, keys_out, vals=None, vals_out=None):
+        """Capture :meth:`run` on fixed buffers into a torch CUDA (HIP) graph."""
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):  # warm-up outside capture
+            self.run(keys, keys_out, vals, vals_out, stream=s)
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(keys, keys_out, vals, vals_out)
+        return g
 
 
 def profile_enable(on: bool = True):

@@ -224,19 +224,23 @@ void add_job(MergePass &mp, uint64_t a, uint64_t na, uint64_t nb, uint32_t src, 
 
 // Device layout of the descriptor tables inside temp, after the data buffers.
 struct TableLayout {
-    uint64_t block_off = 0, block_bytes = 0;
+    uint64_t block_off = 0, block_bytes = 0;    // single-wave tiles
+    uint64_t group_off = 0, group_bytes = 0;    // multi-wave group tiles
     std::vector<uint64_t> jobs_off, map_off;
     uint64_t splits_off = 0;  // one u32 per tile of the largest pass (reused by every pass)
     uint64_t total = 0;
 };
 
-TableLayout layout_tables(uint64_t base, size_t nblock, const std::vector<MergePass> &passes)
+TableLayout layout_tables(uint64_t base, size_t nblock, size_t ngroup, const std::vector<MergePass> &passes)
 {
     TableLayout L;
     uint64_t o = base;
     L.block_off = o;
     L.block_bytes = nblock * sizeof(BlockTile);
     o = align256(o + L.block_bytes);
+    L.group_off = o;
+    L.group_bytes = ngroup * sizeof(BlockTile);
+    o = align256(o + L.group_bytes);
     size_t max_tiles = 0;
     for (const auto &mp : passes) {
         L.jobs_off.push_back(o);
@@ -251,44 +255,62 @@ TableLayout layout_tables(uint64_t base, size_t nblock, const std::vector<MergeP
     return L;
 }
 
+// A host-planned launch sequence: block-sort tiles, then merge passes.
+struct TablePlan {
+    std::vector<BlockTile> single, group;
+    std::vector<MergePass> passes;
+    TableLayout L;
+    bool pairs = false;
+};
+
 // Pack every table into one host image and upload it with one copy.
-bcf_status upload_tables(char *temp, const TableLayout &L, const std::vector<BlockTile> &blocks,
-                         const std::vector<MergePass> &passes, hipStream_t s)
+bcf_status upload_tables(char *temp, const TablePlan &P, hipStream_t s)
 {
+    const TableLayout &L = P.L;
     const uint64_t lo = L.block_off;
     const uint64_t bytes = L.splits_off - lo;  // the splits area is written on the device
     if (bytes == 0)
         return BCF_OK;
     std::vector<char> img(bytes, 0);
-    if (!blocks.empty())
-        std::memcpy(img.data() + (L.block_off - lo), blocks.data(), L.block_bytes);
-    for (size_t p = 0; p < passes.size(); ++p) {
-        if (!passes[p].jobs.empty())
-            std::memcpy(img.data() + (L.jobs_off[p] - lo), passes[p].jobs.data(),
-                        passes[p].jobs.size() * sizeof(MergeJob));
-        if (!passes[p].tile_job.empty())
-            std::memcpy(img.data() + (L.map_off[p] - lo), passes[p].tile_job.data(),
-                        passes[p].tile_job.size() * sizeof(uint32_t));
+    if (!P.single.empty())
+        std::memcpy(img.data() + (L.block_off - lo), P.single.data(), L.block_bytes);
+    if (!P.group.empty())
+        std::memcpy(img.data() + (L.group_off - lo), P.group.data(), L.group_bytes);
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        if (!P.passes[p].jobs.empty())
+            std::memcpy(img.data() + (L.jobs_off[p] - lo), P.passes[p].jobs.data(),
+                        P.passes[p].jobs.size() * sizeof(MergeJob));
+        if (!P.passes[p].tile_job.empty())
+            std::memcpy(img.data() + (L.map_off[p] - lo), P.passes[p].tile_job.data(),
+                        P.passes[p].tile_job.size() * sizeof(uint32_t));
     }
     return upload(temp + lo, img.data(), bytes, s);
 }
 
-bcf_status run_tables(bool pairs, Bufs kb, Bufs vb, char *temp, const TableLayout &L,
-                      const std::vector<BlockTile> &blocks, const std::vector<MergePass> &passes,
-                      uint64_t n, hipStream_t s)
+// Enqueue the kernels of a plan whose tables are already in temp.
+bcf_status launch_tables(Bufs kb, Bufs vb, char *temp, const TablePlan &P, hipStream_t s)
 {
-    BCF_TRY(upload_tables(temp, L, blocks, passes, s));
+    const bool pairs = P.pairs;
+    const TableLayout &L = P.L;
     const double eb = pairs ? 8.0 : 4.0;
-    if (!blocks.empty()) {
+    if (!P.single.empty()) {
         double moved = 0;
-        for (const auto &b : blocks)
+        for (const auto &b : P.single)
             moved += 2.0 * eb * b.count;
         ProfScope p(kname_block_sort(pairs, true), s, moved);
         BCF_TRY(dev_status(launch_block_sort_table(pairs, kb, vb, reinterpret_cast<const BlockTile *>(temp + L.block_off),
-                                                   (uint32_t)blocks.size(), s)));
+                                                   (uint32_t)P.single.size(), s)));
     }
-    for (size_t p = 0; p < passes.size(); ++p) {
-        const auto &mp = passes[p];
+    if (!P.group.empty()) {
+        double moved = 0;
+        for (const auto &b : P.group)
+            moved += 2.0 * eb * b.count;
+        ProfScope p(kname_block_sort(pairs, true), s, moved);
+        BCF_TRY(dev_status(launch_block_sort_group_table(
+            pairs, kb, vb, reinterpret_cast<const BlockTile *>(temp + L.group_off), (uint32_t)P.group.size(), s)));
+    }
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+        const auto &mp = P.passes[p];
         if (mp.tile_job.empty())
             continue;
         double moved = 0;
@@ -303,8 +325,111 @@ bcf_status run_tables(bool pairs, Bufs kb, Bufs vb, char *temp, const TableLayou
                                                   reinterpret_cast<uint32_t *>(temp + L.splits_off), part, s)));
         }
     }
-    (void)n;
     return BCF_OK;
+}
+
+// Segments at least this long are block-sorted in multi-wave group tiles
+// (fewer merge passes); shorter ones in 4096-key wave tiles.
+uint64_t group_min_keys(bool pairs)
+{
+    const char *e = std::getenv("BCF_SEG_GROUP_MIN");
+    if (e && *e)
+        return std::strtoull(e, nullptr, 10);
+    return group_run_keys(pairs) / 2;
+}
+
+// Plan of a segmented sort: every segment is block-sorted into runs that
+// never cross its boundaries, then merged pairwise until one run remains.
+// X_j(s), the buffer holding segment s after its pass j, alternates so that
+// its last pass lands in the output.
+bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, TablePlan &P)
+{
+    P.pairs = pairs;
+    const uint64_t n = off[nseg];
+    const uint64_t gmin = group_min_keys(pairs);
+    const uint64_t grun = group_run_keys(pairs);
+    std::vector<uint32_t> ps(nseg, 0);
+    std::vector<uint64_t> run0(nseg, kTile);
+    uint32_t pmax = 0;
+    for (uint32_t sg = 0; sg < nseg; ++sg) {
+        const uint64_t len = off[sg + 1] - off[sg];
+        if (len == 0)
+            continue;
+        if (len > (uint64_t)kTile && len >= gmin)
+            run0[sg] = grun;
+        ps[sg] = ceil_log2((len + run0[sg] - 1) / run0[sg]);
+        pmax = std::max(pmax, ps[sg]);
+    }
+    auto bufsel = [&](uint32_t sg, uint32_t j) -> uint32_t { return ((ps[sg] - j) % 2 == 0) ? kBufOut : kBufTemp; };
+    for (uint32_t sg = 0; sg < nseg; ++sg) {
+        const uint64_t a = off[sg], len = off[sg + 1] - a;
+        const uint64_t r0 = run0[sg];
+        auto &dst = r0 == (uint64_t)kTile ? P.single : P.group;
+        for (uint64_t o = 0; o < len; o += r0) {
+            BlockTile b;
+            b.start = a + o;
+            b.count = (uint32_t)std::min<uint64_t>(r0, len - o);
+            b.dst = bufsel(sg, 0);
+            dst.push_back(b);
+        }
+    }
+    P.passes.assign(pmax, MergePass{});
+    for (uint32_t j = 1; j <= pmax; ++j) {
+        for (uint32_t sg = 0; sg < nseg; ++sg) {
+            if (ps[sg] < j)
+                continue;
+            const uint64_t run = run0[sg] << (j - 1);
+            const uint64_t a = off[sg], len = off[sg + 1] - a;
+            for (uint64_t o = 0; o < len; o += 2 * run) {
+                const uint64_t na = std::min(run, len - o);
+                const uint64_t nb = std::min(run, len - o - na);
+                add_job(P.passes[j - 1], a + o, na, nb, bufsel(sg, j - 1), bufsel(sg, j));
+            }
+        }
+    }
+    const uint64_t data = pmax ? align256(n * 4) * (pairs ? 2 : 1) : 0;
+    P.L = layout_tables(data, P.single.size(), P.group.size(), P.passes);
+    return BCF_OK;
+}
+
+enum SegMode { kSegFull, kSegUpload, kSegExecute };
+
+bcf_status segmented_impl(SegMode mode, bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                          uint32_t *vout, const uint64_t *off, uint32_t nseg, void *temp, uint64_t *temp_bytes,
+                          hipStream_t s)
+{
+    if (!temp_bytes)
+        return BCF_ERR_INVALID;
+    if (nseg == 0) {
+        if (!temp)
+            *temp_bytes = 0;
+        return BCF_OK;
+    }
+    if (!offsets_valid(off, nseg))
+        return BCF_ERR_INVALID;
+    TablePlan P;
+    BCF_TRY(plan_segmented(off, nseg, pairs, P));
+    const uint64_t n = off[nseg];
+    if (!temp) {
+        *temp_bytes = P.L.total;
+        return BCF_OK;
+    }
+    if (n == 0)
+        return BCF_OK;
+    if (*temp_bytes < P.L.total)
+        return BCF_ERR_TEMP_TOO_SMALL;
+    char *tb = static_cast<char *>(temp);
+    if (mode != kSegExecute)
+        BCF_TRY(upload_tables(tb, P, s));
+    if (mode == kSegUpload)
+        return BCF_OK;
+    if (!kin || !kout || (pairs && (!vin || !vout)))
+        return BCF_ERR_INVALID;
+    Bufs kb{kin, kout, reinterpret_cast<uint32_t *>(tb)};
+    Bufs vb{nullptr, nullptr, nullptr};
+    if (pairs)
+        vb = Bufs{vin, vout, reinterpret_cast<uint32_t *>(tb + align256(n * 4))};
+    return launch_tables(kb, vb, tb, P, s);
 }
 
 }  // namespace
@@ -399,7 +524,11 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
         cur.swap(next);
     }
     const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
-    TableLayout L = layout_tables(P ? data : 0, 0, passes);
+    TablePlan TP;
+    TP.pairs = pairs;
+    TP.passes = passes;
+    TP.L = layout_tables(P ? data : 0, 0, 0, TP.passes);
+    const TableLayout &L = TP.L;
     // small area for the optional sortedness check: run offsets and a flag
     const uint64_t check_off = L.total;
     const uint64_t need = check_off + align256((uint64_t(k) + 1) * sizeof(uint64_t)) + 256;
@@ -444,7 +573,8 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
     }
     Bufs kb{keys_in, keys_out, kt};
     Bufs vb{vals_in, vals_out, vt};
-    BCF_TRY(run_tables(pairs, kb, vb, tb, L, {}, passes, n, s));
+    BCF_TRY(upload_tables(tb, TP, s));
+    BCF_TRY(launch_tables(kb, vb, tb, TP, s));
     if (shift) {
         if (hipMemcpyAsync(keys_out, kt, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return BCF_ERR_DEVICE;
@@ -457,71 +587,31 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
 bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
                               uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream)
 {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!temp_bytes)
-        return BCF_ERR_INVALID;
-    if (nseg == 0) {
-        if (!temp)
-            *temp_bytes = 0;
-        return BCF_OK;
-    }
-    if (!offsets_valid(seg_offsets, nseg))
-        return BCF_ERR_INVALID;
-    const uint64_t n = seg_offsets[nseg];
-    // per segment: tiles, merge passes; X_j(s) = buffer after pass j of segment s
-    std::vector<BlockTile> blocks;
-    uint32_t pmax = 0;
-    std::vector<uint32_t> ps(nseg, 0);
-    for (uint32_t sg = 0; sg < nseg; ++sg) {
-        const uint64_t len = seg_offsets[sg + 1] - seg_offsets[sg];
-        if (len == 0)
-            continue;
-        ps[sg] = ceil_log2(tiles_of(len));
-        pmax = std::max(pmax, ps[sg]);
-    }
-    auto bufsel = [&](uint32_t sg, uint32_t j) -> uint32_t {
-        return ((ps[sg] - j) % 2 == 0) ? kBufOut : kBufTemp;
-    };
-    for (uint32_t sg = 0; sg < nseg; ++sg) {
-        const uint64_t a = seg_offsets[sg], len = seg_offsets[sg + 1] - a;
-        for (uint64_t t = 0; t * kTile < len; ++t) {
-            BlockTile b;
-            b.start = a + t * kTile;
-            b.count = (uint32_t)std::min<uint64_t>(kTile, len - t * kTile);
-            b.dst = bufsel(sg, 0);
-            blocks.push_back(b);
-        }
-    }
-    std::vector<MergePass> passes(pmax);
-    for (uint32_t j = 1; j <= pmax; ++j) {
-        const uint64_t run = uint64_t(kTile) << (j - 1);
-        for (uint32_t sg = 0; sg < nseg; ++sg) {
-            if (ps[sg] < j)
-                continue;
-            const uint64_t a = seg_offsets[sg], len = seg_offsets[sg + 1] - a;
-            for (uint64_t o = 0; o < len; o += 2 * run) {
-                const uint64_t na = std::min(run, len - o);
-                const uint64_t nb = std::min(run, len - o - na);
-                add_job(passes[j - 1], a + o, na, nb, bufsel(sg, j - 1), bufsel(sg, j));
-            }
-        }
-    }
-    const uint64_t data = pmax ? align256(n * 4) : 0;
-    TableLayout L = layout_tables(data, blocks.size(), passes);
-    if (!temp) {
-        *temp_bytes = L.total;
-        return BCF_OK;
-    }
-    if (n == 0)
-        return BCF_OK;
-    if (!keys_in || !keys_out)
-        return BCF_ERR_INVALID;
-    if (*temp_bytes < L.total)
-        return BCF_ERR_TEMP_TOO_SMALL;
-    char *tb = static_cast<char *>(temp);
-    Bufs kb{keys_in, keys_out, reinterpret_cast<uint32_t *>(tb)};
-    Bufs vb{nullptr, nullptr, nullptr};
-    return run_tables(false, kb, vb, tb, L, blocks, passes, n, s);
+    return segmented_impl(kSegFull, false, keys_in, nullptr, keys_out, nullptr, seg_offsets, nseg, temp, temp_bytes,
+                          static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_segmented_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                                    uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg, void *temp,
+                                    uint64_t *temp_bytes, void *stream)
+{
+    return segmented_impl(kSegFull, true, keys_in, vals_in, keys_out, vals_out, seg_offsets, nseg, temp, temp_bytes,
+                          static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_segmented_upload(const uint64_t *seg_offsets, uint32_t nseg, int pairs, void *temp,
+                                uint64_t *temp_bytes, void *stream)
+{
+    return segmented_impl(kSegUpload, pairs != 0, nullptr, nullptr, nullptr, nullptr, seg_offsets, nseg, temp,
+                          temp_bytes, static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_segmented_execute(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                                 uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg, void *temp,
+                                 uint64_t *temp_bytes, void *stream)
+{
+    return segmented_impl(kSegExecute, vals_in != nullptr, keys_in, vals_in, keys_out, vals_out, seg_offsets, nseg,
+                          temp, temp_bytes, static_cast<hipStream_t>(stream));
 }
 
 void bcf_profile_enable(int on)

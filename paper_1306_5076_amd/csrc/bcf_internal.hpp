@@ -58,6 +58,9 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
                                 uint32_t *splits, bool partition, hipStream_t s);
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
                                    uint32_t ntiles, hipStream_t s);
+// Group tiles (count <= group_run_keys(pairs)) sorted by a multi-wave work-group.
+hipError_t launch_block_sort_group_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
+                                         uint32_t ngroups, hipStream_t s);
 hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs,
                               const uint32_t *tile_job, uint32_t ntiles, uint32_t *splits,
                               bool partition, hipStream_t s);

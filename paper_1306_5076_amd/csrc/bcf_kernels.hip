@@ -512,6 +512,27 @@ struct RegularGroupSrc {
     }
 };
 
+// Group tiles of a table launch: tiles[g] covers `count` (<= NW * 4096) keys.
+struct TableGroupSrc {
+    Bufs kb, vb;
+    const BlockTile *tiles;
+    uint32_t ngroups;
+    __device__ SortItem get(uint32_t g, uint32_t w) const
+    {
+        const BlockTile d = tiles[g];
+        const uint64_t off = (uint64_t)w * kTile;
+        const uint64_t rem = off < d.count ? d.count - off : 0;
+        const uint64_t start = d.start + off;
+        SortItem it;
+        it.ks = kb.in + start;
+        it.vs = vb.in ? vb.in + start : nullptr;
+        it.kd = (d.dst == kBufOut ? kb.out : kb.temp) + start;
+        it.vd = vb.out ? (d.dst == kBufOut ? vb.out : vb.temp) + start : nullptr;
+        it.count = rem < (uint64_t)kTile ? (uint32_t)rem : (uint32_t)kTile;
+        return it;
+    }
+};
+
 template <int NW, bool P, class Src>
 __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
 {
@@ -711,22 +732,46 @@ hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint
     return pairs ? launch_sort<true>(src, s) : launch_sort<false>(src, s);
 }
 
+static uint32_t cu_count()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cus = c;
+    }
+    return (uint32_t)cus;
+}
+
+template <int NW, bool P, class Src>
+static hipError_t launch_group_src(const Src &src, hipStream_t s)
+{
+    if (src.ngroups == 0)
+        return hipSuccess;
+    // one group per CU fits the LDS (NW * 16.6 KiB); persistent over the groups
+    const uint32_t groups = src.ngroups < cu_count() ? src.ngroups : cu_count();
+    hipLaunchKernelGGL((k_block_sort_group<NW, P, Src>), dim3(groups), dim3(kWave * NW), 0, s, src);
+    return hipGetLastError();
+}
+
 template <int NW, bool P>
 static hipError_t launch_group(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                                uint64_t n, hipStream_t s)
 {
     constexpr uint32_t keys = NW * kTile;
     RegularGroupSrc src{kin, P ? vin : nullptr, kout, P ? vout : nullptr, n, (uint32_t)((n + keys - 1) / keys), keys};
-    if (src.ngroups == 0)
-        return hipSuccess;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 256;
-    // one group per CU fits the LDS (NW * 16.6 KiB); persistent over the groups
-    const uint32_t groups = src.ngroups < (uint32_t)cus ? src.ngroups : (uint32_t)cus;
-    hipLaunchKernelGGL((k_block_sort_group<NW, P, RegularGroupSrc>), dim3(groups), dim3(kWave * NW), 0, s, src);
-    return hipGetLastError();
+    return launch_group_src<NW, P>(src, s);
+}
+
+hipError_t launch_block_sort_group_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles, uint32_t ngroups,
+                                         hipStream_t s)
+{
+    if (!pairs)
+        vb = Bufs{nullptr, nullptr, nullptr};
+    TableGroupSrc src{kb, vb, tiles, ngroups};
+    return pairs ? launch_group_src<kGroupWavesPairs, true>(src, s) : launch_group_src<kGroupWavesKeys, false>(src, s);
 }
 
 uint32_t group_run_keys(bool pairs) { return pairs ? kGroupWavesPairs * kTile : kGroupWavesKeys * kTile; }

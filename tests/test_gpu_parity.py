@@ -306,3 +306,73 @@ def test_merge_kernel_variants(torch_dev, bcf, mode, monkeypatch):
         ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, kk), to_dev(torch, dev, vv))
         wk, wv = oracle.sort_pairs_u32(kk, vv)
         assert first_diff(ko.cpu().numpy(), wk) is None and first_diff(vo.cpu().numpy(), wv) is None
+
+
+# ------------------------------------------------------------------ segmented pairs / plans / graphs
+
+
+@pytest.mark.parametrize(
+    "sizes",
+    [[0, 1, 2, 0, 3], [4096, 4097, 1, 0, 8192], [31, 4096 * 5 + 3, 64, 100000, 0, 2], [20000, 40000, 70000]],
+)
+def test_segmented_pairs_vs_oracle(torch_dev, bcf, sizes):
+    torch, dev = torch_dev
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    n = int(offs[-1])
+    keys = workloads.keys_u32("distinct16", n, seed=3)
+    vals = workloads.draws_u32(9, n)
+    ko, vo = bcf.segmented_sort(to_dev(torch, dev, keys), offs, vals=to_dev(torch, dev, vals))
+    ko, vo = ko.cpu().numpy(), vo.cpu().numpy()
+    for s in range(len(sizes)):
+        lo, hi = int(offs[s]), int(offs[s + 1])
+        wk, wv = oracle.sort_pairs_u32(keys[lo:hi], vals[lo:hi])
+        assert first_diff(ko[lo:hi], wk) is None and first_diff(vo[lo:hi], wv) is None
+
+
+@pytest.mark.parametrize("group_min", ["4097", "1000000000"])
+def test_segmented_group_threshold(torch_dev, bcf, group_min, monkeypatch):
+    # the same segments block-sorted in group tiles or in wave tiles
+    torch, dev = torch_dev
+    monkeypatch.setenv("BCF_SEG_GROUP_MIN", group_min)
+    sizes = [5000, 40000, 100000, 4096, 32768, 32769]
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    keys = workloads.keys_u32("zipf", int(offs[-1]), seed=2)
+    got = bcf.segmented_sort(to_dev(torch, dev, keys), offs).cpu().numpy()
+    assert first_diff(got, oracle.segmented_sort(keys, offs)) is None
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_segmented_plan_graph_replay(torch_dev, bcf, pairs):
+    torch, dev = torch_dev
+    sizes = workloads.segment_sizes(300, lo=32, hi=1 << 16, seed=5)
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    n = int(offs[-1])
+    plan = bcf.SegmentedPlan(offs, dev, pairs=pairs)
+    kin = torch.empty(n, dtype=torch.uint32, device=dev)
+    kout = torch.empty_like(kin)
+    vin = torch.empty_like(kin) if pairs else None
+    vout = torch.empty_like(kin) if pairs else None
+    graph = plan.capture(kin, kout, vin, vout)
+    for rep in range(3):  # new data each replay, eager work in between
+        keys = workloads.keys_u32("uniform", n, seed=100 + rep)
+        vals = workloads.draws_u32(200 + rep, n)
+        kin.copy_(torch.from_numpy(keys))
+        if pairs:
+            vin.copy_(torch.from_numpy(vals))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        eager = bcf.segmented_sort(kin, offs, vals=vin) if pairs else bcf.segmented_sort(kin, offs)
+        torch.cuda.synchronize()
+        if pairs:
+            assert torch.equal(kout, eager[0]) and torch.equal(vout, eager[1])
+            wk = np.concatenate([oracle.sort_pairs_u32(keys[int(offs[s]):int(offs[s + 1])],
+                                                       vals[int(offs[s]):int(offs[s + 1])])[1]
+                                 for s in range(len(sizes))])
+            assert first_diff(vout.cpu().numpy(), wk) is None
+        else:
+            assert torch.equal(kout, eager)
+            assert first_diff(kout.cpu().numpy(), oracle.segmented_sort(keys, offs)) is None
