@@ -159,9 +159,12 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     const uint64_t tiles = tiles_of(n);
     const uint64_t run0 = group_run_keys(pairs);  // sorted run length after the block sort
     const uint32_t passes = n ? ceil_log2((n + run0 - 1) / run0) : 0;
-    // temp: ping-pong keys [, values], then one split per merge tile
+    // temp: ping-pong keys [, values], one split per merge tile, then two
+    // sets of key samples (each pass reads one set and writes the other)
     const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
-    const uint64_t need = passes ? data + align256(tiles * 4) : 0;
+    const uint64_t blocks64 = (n + kLine - 1) / kLine;
+    const uint64_t set_bytes = 2 * align256(blocks64 * 4) + 2 * align256(tiles * 4);
+    const uint64_t need = passes ? data + align256(tiles * 4) + 2 * set_bytes : 0;
     if (!temp) {
         *temp_bytes = need;
         return BCF_OK;
@@ -175,13 +178,25 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     uint32_t *kt = static_cast<uint32_t *>(temp);
     uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + align256(n * 4)) : nullptr;
     uint32_t *splits = reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + data);
+    auto sample_set = [&](uint32_t k) {
+        char *b = static_cast<char *>(temp) + data + align256(tiles * 4) + k * set_bytes;
+        SampleSet ss;
+        ss.f = reinterpret_cast<uint32_t *>(b);
+        ss.l = reinterpret_cast<uint32_t *>(b + align256(blocks64 * 4));
+        ss.cf = reinterpret_cast<uint32_t *>(b + 2 * align256(blocks64 * 4));
+        ss.cl = reinterpret_cast<uint32_t *>(b + 2 * align256(blocks64 * 4) + align256(tiles * 4));
+        return ss;
+    };
+    const SampleSet none{nullptr, nullptr, nullptr, nullptr};
+    const bool sampled = std::getenv("BCF_NO_SAMPLES") == nullptr;  // searches from samples (default)
     // X_j = buffer after pass j; X_passes = out.
     auto kbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? kout : kt; };
     auto vbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? vout : vt; };
     const double elem_bytes = pairs ? 8.0 : 4.0;
     {
         ProfScope p(kname_block_sort(pairs, false), s, 2.0 * elem_bytes * n);
-        BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, s)));
+        BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n,
+                                                   (passes && sampled) ? sample_set(0) : none, s)));
     }
     uint64_t run = run0;
     for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
@@ -189,8 +204,11 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
             const bool part = phase == 0;
             ProfScope p(part ? kname_partition(pairs, false) : kname_merge(pairs, false), s,
                         part ? 0.0 : 2.0 * elem_bytes * n);
+            const SampleSet in_smp = sampled ? sample_set((j - 1) & 1) : none;
+            const SampleSet out_smp = (sampled && j < passes) ? sample_set(j & 1) : none;
             BCF_TRY(dev_status(launch_merge_regular(pairs, kbuf(j - 1), pairs ? vbuf(j - 1) : nullptr, kbuf(j),
-                                                    pairs ? vbuf(j) : nullptr, n, run, splits, part, s)));
+                                                    pairs ? vbuf(j) : nullptr, n, run, splits, in_smp, out_smp,
+                                                    part, s)));
         }
     }
     return BCF_OK;

@@ -18,6 +18,14 @@ struct Bufs {
     uint32_t *temp;      // library scratch
 };
 
+// Key samples of a sorted array, written by the pass that produces it and
+// read by the partition of the next merge pass: the key at every position
+// 64j (f) and 64j + 63 (l), and at every position 4096t (cf) and
+// 4096t + 4095 (cl).  f == nullptr means "no samples".
+struct SampleSet {
+    uint32_t *f, *l, *cf, *cl;
+};
+
 // One tile of the block sort: `count` (<= kTile) keys starting at element
 // `start` of the input, sorted into buffer `dst` at the same offset.
 struct BlockTile {
@@ -47,15 +55,19 @@ uint32_t group_run_keys(bool pairs);
 
 // Launchers (enqueue only; return the launch status).
 hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin,
-                                   uint32_t *kout, uint32_t *vout, uint64_t n, hipStream_t s);
+                                   uint32_t *kout, uint32_t *vout, uint64_t n, SampleSet out_smp,
+                                   hipStream_t s);
 hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint32_t *vin,
                                      uint32_t *kout, uint32_t *vout, uint64_t n, hipStream_t s);
 // A merge pass is two launches: with partition = true the split of every
 // tile is written to `splits` (one u32 per tile of the pass); with
 // partition = false the tiles are merged using those splits.
+// The regular partition reads the samples of its input (in_smp, written by
+// the previous launch); the regular merge writes those of its output (out_smp).
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc,
                                 uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
-                                uint32_t *splits, bool partition, hipStream_t s);
+                                uint32_t *splits, SampleSet in_smp, SampleSet out_smp,
+                                bool partition, hipStream_t s);
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
                                    uint32_t ntiles, hipStream_t s);
 // Group tiles (count <= group_run_keys(pairs)) sorted by a multi-wave work-group.

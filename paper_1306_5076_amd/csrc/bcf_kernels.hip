@@ -237,6 +237,7 @@ template <bool P>
 struct MergeTask {
     const uint32_t *ka, *va, *kb, *vb;
     uint32_t *kd, *vd;
+    uint64_t gpos;  // array position of the first output
     uint32_t pa, pb, count;
 };
 
@@ -292,12 +293,44 @@ __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, u
 // bits in STRIDED layout), transpose, bits 5..0 (register bits in BLOCKED
 // layout), transpose back.
 template <bool P>
-__device__ __forceinline__ void merge_network(Lines<P> &t, uint32_t *lds, uint32_t lane)
+__device__ __forceinline__ void write_samples(const Lines<P> &t, const SampleSet &s, uint64_t gpos, uint32_t count,
+                                              uint32_t lane);
+
+// Sort a bitonic STRIDED tile: half-cleaners on position bits 11..6 (register
+// bits in STRIDED layout), transpose, bits 5..0 (register bits in BLOCKED
+// layout), transpose back.  In BLOCKED layout the sorted tile's samples are
+// written (when `smp` has any).
+template <bool P>
+__device__ __forceinline__ void merge_network(Lines<P> &t, uint32_t *lds, uint32_t lane, const SampleSet &smp,
+                                              uint64_t gpos, uint32_t count)
 {
     half_clean<kLine / 2, -1, P>(t);
     to_blocked(t, lds, lane);
     half_clean<kLine / 2, -1, P>(t);
+    write_samples<P>(t, smp, gpos, count, lane);
     to_strided(t, lds, lane);
+}
+
+// Samples of a sorted tile in BLOCKED layout starting at global position gpos
+// (a multiple of 4096): lane l holds positions 64l .. 64l + 63, so register 0
+// and register 63 of all lanes are the tile's 64-block samples (one coalesced
+// store each); lane 0 / lane 63 hold the tile's first / last key.
+template <bool P>
+__device__ __forceinline__ void write_samples(const Lines<P> &t, const SampleSet &s, uint64_t gpos, uint32_t count,
+                                              uint32_t lane)
+{
+    if (s.f == nullptr || count == 0)
+        return;
+    const uint64_t b = gpos / kLine + lane;
+    if (lane * kLine < count) {
+        s.f[b] = t.k[0];
+        s.l[b] = t.k[kLine - 1];
+    }
+    const uint64_t c = gpos / kTile;
+    if (lane == 0)
+        s.cf[c] = t.k[0];
+    if (lane == kWave - 1)
+        s.cl[c] = t.k[kLine - 1];
 }
 
 // ----------------------------------------------------------- work sources
@@ -353,6 +386,7 @@ struct TableSortSrc {
 struct MergeItem {
     const uint32_t *ka, *va;
     uint32_t *kd, *vd;
+    uint64_t base;  // array position of A[0]
     uint32_t na, nb, d0, count;
 };
 
@@ -363,6 +397,7 @@ struct RegularMergeSrc {
     uint32_t *kdst, *vdst;
     uint64_t n, run;
     uint32_t ntiles;
+    SampleSet in_smp, out_smp;
     __device__ MergeItem get(uint32_t t) const
     {
         const uint64_t gstart = (uint64_t)t * kTile;
@@ -375,6 +410,7 @@ struct RegularMergeSrc {
         m.d0 = (uint32_t)(gstart - base);
         const uint32_t left = m.na + m.nb - m.d0;
         m.count = left < (uint32_t)kTile ? left : (uint32_t)kTile;
+        m.base = base;
         m.ka = ksrc + base;
         m.va = vsrc ? vsrc + base : nullptr;
         m.kd = kdst + base;
@@ -388,6 +424,8 @@ struct TableMergeSrc {
     const MergeJob *jobs;
     const uint32_t *tile_job;
     uint32_t ntiles;
+    SampleSet out_smp;  // always empty: table runs start anywhere
+
     __device__ MergeItem get(uint32_t t) const
     {
         const MergeJob j = jobs[tile_job[t]];
@@ -397,6 +435,7 @@ struct TableMergeSrc {
         m.d0 = (t - j.first_tile) * (uint32_t)kTile;
         const uint32_t left = j.na + j.nb - m.d0;
         m.count = left < (uint32_t)kTile ? left : (uint32_t)kTile;
+        m.base = j.a_start;
         m.ka = (j.src == kBufIn ? kb.in : (j.src == kBufOut ? kb.out : kb.temp)) + j.a_start;
         m.kd = (j.dst == kBufOut ? kb.out : kb.temp) + j.a_start;
         m.va = nullptr;
@@ -426,6 +465,7 @@ __device__ __forceinline__ MergeTask<P> merge_task(const Src &src, const uint32_
     k.ka = m.ka + a0;
     k.kb = m.ka + m.na + b0;
     k.kd = m.kd + m.d0;
+    k.gpos = m.base + m.d0;
     k.va = P ? m.va + a0 : nullptr;
     k.vb = P ? m.va + m.na + b0 : nullptr;
     k.vd = P ? m.vd + m.d0 : nullptr;
@@ -497,6 +537,8 @@ struct RegularGroupSrc {
     uint64_t n;
     uint32_t ngroups;
     uint32_t group_keys;
+    SampleSet out_smp;
+    __device__ uint64_t pos(uint32_t g, uint32_t w) const { return (uint64_t)g * group_keys + (uint64_t)w * kTile; }
     // sub-tile of wave w of group g (count 0 past the end of the input)
     __device__ SortItem get(uint32_t g, uint32_t w) const
     {
@@ -517,6 +559,8 @@ struct TableGroupSrc {
     Bufs kb, vb;
     const BlockTile *tiles;
     uint32_t ngroups;
+    SampleSet out_smp;  // always empty
+    __device__ uint64_t pos(uint32_t, uint32_t) const { return 0; }
     __device__ SortItem get(uint32_t g, uint32_t w) const
     {
         const BlockTile d = tiles[g];
@@ -549,6 +593,7 @@ __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
         sort_tile_blocked<P>(t, own, ln);
         flip(t, wave);
         group_rounds<NW, 7, P>(t, lds, ln, wave);
+        write_samples<P>(t, src.out_smp, src.pos(g, wave), it.count, ln);
         to_strided(t, own, ln);
         store_tile<P>(t, it.kd, it.vd, it.count, ln);
     }
@@ -575,6 +620,66 @@ __global__ __launch_bounds__(256) void k_partition(Src src, uint32_t *__restrict
 //         is merged (keys only; pairs fall back to MODE 1);
 // MODE 1: persistent waves, one tile at a time;
 // MODE 2: one tile per wave (grid covers every tile).
+// One level of the co-rank search: the answer i* (smallest i in [lo, hi] with
+// A[i] > B[d-1-i], hi counting as true) is narrowed to a bracket of width
+// at most G by a 64-ary search over the candidates i = G*c in [lo, hi).
+// pred(i) evaluates the predicate for such a candidate.
+template <uint32_t G, class Pred>
+__device__ __forceinline__ void corank_level(uint32_t &lo, uint32_t &hi, uint32_t lane, const Pred &pred)
+{
+    uint32_t c0 = (lo + G - 1) / G;                // first candidate
+    uint32_t c1 = hi > 0 ? (hi - 1) / G + 1 : 0;   // one past the last
+    while (c0 < c1) {
+        const uint32_t span = c1 - c0;
+        const uint32_t c = c0 + (uint32_t)(((uint64_t)span * lane) >> 6);  // probe of this lane
+        const bool fail = !pred(G * c);
+        const uint64_t fails = __ballot(fail);
+        const uint32_t cnt = __popcll(fails);  // probes 0..cnt-1 fail (monotone)
+        if (cnt == 0) {
+            hi = min(hi, G * c0);
+            break;
+        }
+        const uint32_t cf = c0 + (uint32_t)(((uint64_t)span * (cnt - 1)) >> 6);
+        lo = max(lo, G * cf + 1);
+        if (cnt < 64) {
+            const uint32_t cn = c0 + (uint32_t)(((uint64_t)span * cnt) >> 6);
+            hi = min(hi, G * cn);
+            c1 = cn;
+        }
+        c0 = cf + 1;
+    }
+}
+
+// Co-rank of every merge tile of a regular pass from the samples the
+// previous launch wrote: one wave per tile, three exact levels (tile
+// samples, 64-block samples, keys).  Tile diagonals are multiples of 4096
+// and runs start at multiples of 4096, so for a candidate i that is a
+// multiple of 64 (4096), A[i] is a first-of-block sample and B[d-1-i] a
+// last-of-block sample.
+__global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, uint32_t *__restrict__ splits)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    if (t >= src.ntiles)
+        return;
+    const MergeItem m = src.get(t);
+    const uint32_t d = m.d0, na = m.na, nb = m.nb;
+    uint32_t lo = d > nb ? d - nb : 0;
+    uint32_t hi = d < na ? d : na;
+    const uint64_t apos = m.base, bpos = m.base + na;
+    const SampleSet &sm = src.in_smp;
+    const uint32_t *A = m.ka, *B = m.ka + na;
+    corank_level<kTile>(lo, hi, lane, [&](uint32_t i) {
+        return sm.cf[(apos + i) / kTile] > sm.cl[(bpos + d - 1 - i) / kTile];
+    });
+    corank_level<kLine>(lo, hi, lane, [&](uint32_t i) {
+        return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine];
+    });
+    corank_level<1>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
+    if (lane == 0)
+        splits[t] = lo;
+}
+
 template <bool P, class Src, int MODE>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const uint32_t *__restrict__ splits)
 {
@@ -590,7 +695,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
         const MergeTask<P> m = merge_task<P>(src, splits, t);
         Lines<P> a;
         merge_load<P>(a, m, lane);
-        merge_network<P>(a, lds, lane);
+        merge_network<P>(a, lds, lane, src.out_smp, m.gpos, m.count);
         store_tile<P>(a, m.kd, m.vd, m.count, lane);
     } else if constexpr (P || MODE == 1) {
         for (; t < src.ntiles; t += G) {
@@ -598,7 +703,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
             const MergeTask<P> m = merge_task<P>(src, splits, t);
             Lines<P> a;
             merge_load<P>(a, m, ln);
-            merge_network<P>(a, lds, ln);
+            merge_network<P>(a, lds, ln, src.out_smp, m.gpos, m.count);
             store_tile<P>(a, m.kd, m.vd, m.count, ln);
         }
     } else {
@@ -613,7 +718,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
                 mb = merge_task<P>(src, splits, tb);
                 merge_load<P>(b, mb, ln);
             }
-            merge_network<P>(a, lds, ln);
+            merge_network<P>(a, lds, ln, src.out_smp, ma.gpos, ma.count);
             store_tile<P>(a, ma.kd, ma.vd, ma.count, ln);
             if (!hb)
                 break;
@@ -624,7 +729,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
                 ma = merge_task<P>(src, splits, t);
                 merge_load<P>(a, ma, ln);
             }
-            merge_network<P>(b, lds, ln);
+            merge_network<P>(b, lds, ln, src.out_smp, mb.gpos, mb.count);
             store_tile<P>(b, mb.kd, mb.vd, mb.count, ln);
             if (!ha)
                 break;
@@ -758,10 +863,11 @@ static hipError_t launch_group_src(const Src &src, hipStream_t s)
 
 template <int NW, bool P>
 static hipError_t launch_group(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
-                               uint64_t n, hipStream_t s)
+                               uint64_t n, SampleSet smp, hipStream_t s)
 {
     constexpr uint32_t keys = NW * kTile;
-    RegularGroupSrc src{kin, P ? vin : nullptr, kout, P ? vout : nullptr, n, (uint32_t)((n + keys - 1) / keys), keys};
+    RegularGroupSrc src{kin, P ? vin : nullptr, kout, P ? vout : nullptr, n, (uint32_t)((n + keys - 1) / keys), keys,
+                        smp};
     return launch_group_src<NW, P>(src, s);
 }
 
@@ -770,27 +876,35 @@ hipError_t launch_block_sort_group_table(bool pairs, Bufs kb, Bufs vb, const Blo
 {
     if (!pairs)
         vb = Bufs{nullptr, nullptr, nullptr};
-    TableGroupSrc src{kb, vb, tiles, ngroups};
+    TableGroupSrc src{kb, vb, tiles, ngroups, SampleSet{nullptr, nullptr, nullptr, nullptr}};
     return pairs ? launch_group_src<kGroupWavesPairs, true>(src, s) : launch_group_src<kGroupWavesKeys, false>(src, s);
 }
 
 uint32_t group_run_keys(bool pairs) { return pairs ? kGroupWavesPairs * kTile : kGroupWavesKeys * kTile; }
 
 hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
-                                   uint32_t *vout, uint64_t n, hipStream_t s)
+                                   uint32_t *vout, uint64_t n, SampleSet out_smp, hipStream_t s)
 {
-    return pairs ? launch_group<kGroupWavesPairs, true>(kin, vin, kout, vout, n, s)
-                 : launch_group<kGroupWavesKeys, false>(kin, vin, kout, vout, n, s);
+    return pairs ? launch_group<kGroupWavesPairs, true>(kin, vin, kout, vout, n, out_smp, s)
+                 : launch_group<kGroupWavesKeys, false>(kin, vin, kout, vout, n, out_smp, s);
 }
 
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc, uint32_t *kdst,
-                                uint32_t *vdst, uint64_t n, uint64_t run, uint32_t *splits, bool partition,
-                                hipStream_t s)
+                                uint32_t *vdst, uint64_t n, uint64_t run, uint32_t *splits, SampleSet in_smp,
+                                SampleSet out_smp, bool partition, hipStream_t s)
 {
     RegularMergeSrc src{ksrc, pairs ? vsrc : nullptr, kdst, pairs ? vdst : nullptr, n, run,
-                        (uint32_t)((n + kTile - 1) / kTile)};
-    if (partition)
-        return launch_partition(src, splits, s);
+                        (uint32_t)((n + kTile - 1) / kTile), in_smp, out_smp};
+    if (partition) {
+        if (in_smp.f == nullptr)
+            return launch_partition(src, splits, s);
+        // runs must start at multiples of 4096 for the sample predicates
+        if (run % kTile != 0)
+            return hipErrorInvalidValue;
+        const uint32_t groups = (src.ntiles + (256 / kWave) - 1) / (256 / kWave);
+        hipLaunchKernelGGL(k_partition_sampled, dim3(groups), dim3(256), 0, s, src, splits);
+        return hipGetLastError();
+    }
     return pairs ? launch_merge<true>(src, splits, s) : launch_merge<false>(src, splits, s);
 }
 
@@ -808,7 +922,7 @@ hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs
 {
     if (!pairs)
         vb = Bufs{nullptr, nullptr, nullptr};
-    TableMergeSrc src{kb, vb, jobs, tile_job, ntiles};
+    TableMergeSrc src{kb, vb, jobs, tile_job, ntiles, SampleSet{nullptr, nullptr, nullptr, nullptr}};
     if (partition)
         return launch_partition(src, splits, s);
     return pairs ? launch_merge<true>(src, splits, s) : launch_merge<false>(src, splits, s);

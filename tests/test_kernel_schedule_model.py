@@ -399,3 +399,68 @@ def test_group_layouts_conflict_free(nw):
         ps = {pos(w, l, r) for w in range(nw) for l in range(W) for r in range(E)}
         assert ps == set(range(nw * T))
     assert lds_word(nw * T - 1) < nw * W * STRIDE
+
+
+# -------------------------------------------- co-rank search from samples
+
+
+def corank_brute(a, b, d):
+    """Elements of A among the first d outputs of the stable merge (A first on ties)."""
+    i = max(0, d - len(b))
+    while i < min(d, len(a)) and not (a[i] > b[d - 1 - i]):
+        i += 1
+    return i
+
+
+def corank_level(lo, hi, g, pred):
+    """Mirror of corank_level<G>: 64 probes per round over candidates g*c in [lo, hi)."""
+    c0 = (lo + g - 1) // g
+    c1 = (hi - 1) // g + 1 if hi > 0 else 0
+    while c0 < c1:
+        span = c1 - c0
+        probes = [c0 + (span * k >> 6) for k in range(64)]
+        fails = [not pred(g * c) for c in probes]
+        cnt = sum(fails)
+        assert fails == [True] * cnt + [False] * (64 - cnt)  # monotone
+        if cnt == 0:
+            hi = min(hi, g * c0)
+            break
+        cf = probes[cnt - 1]
+        lo = max(lo, g * cf + 1)
+        if cnt < 64:
+            cn = probes[cnt]
+            hi = min(hi, g * cn)
+            c1 = cn
+        c0 = cf + 1
+    return lo, hi
+
+
+def corank_sampled(arr, apos, na, nb, d):
+    """The three levels of k_partition_sampled on one array holding A then B."""
+    f = arr[::64]
+    l = arr[63::64]
+    cf = arr[::4096]
+    cl = arr[4095::4096]
+    bpos = apos + na
+    lo, hi = max(0, d - nb), min(d, na)
+    lo, hi = corank_level(lo, hi, 4096, lambda i: cf[(apos + i) // 4096] > cl[(bpos + d - 1 - i) // 4096])
+    assert hi - lo <= 4096
+    lo, hi = corank_level(lo, hi, 64, lambda i: f[(apos + i) // 64] > l[(bpos + d - 1 - i) // 64])
+    assert hi - lo <= 64
+    lo, hi = corank_level(lo, hi, 1, lambda i: arr[apos + i] > arr[bpos + d - 1 - i])
+    assert lo == hi
+    return lo
+
+
+@pytest.mark.parametrize("na,nb,levels", [(32768, 32768, 3), (32768, 5000, 7), (65536, 65536, 2), (32768, 0, 1),
+                                          (32768, 32768, 40000)])
+def test_corank_from_samples_matches_brute_force(na, nb, levels):
+    rng = np.random.default_rng(na + nb + levels)
+    apos = 3 * 65536  # runs start at multiples of 4096
+    arr = np.zeros(apos + na + nb + 4096, dtype=np.int64)
+    a = np.sort(rng.integers(0, levels, size=na))
+    b = np.sort(rng.integers(0, levels, size=nb))
+    arr[apos:apos + na] = a
+    arr[apos + na:apos + na + nb] = b
+    for d in range(0, na + nb, 4096):
+        assert corank_sampled(arr, apos, na, nb, d) == corank_brute(a, b, d), d
