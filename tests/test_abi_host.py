@@ -66,8 +66,10 @@ def test_temp_queries(lib):
     st, need = q_sort(lib, 32769)
     assert st == 0 and need >= 32769 * 4 and need % 256 == 0
     st, need = q_sort(lib, 2**26, pairs=True)
-    # two ping-pong arrays (keys, values) plus one u32 split per merge tile
-    assert st == 0 and need == 2 * 2**26 * 4 + (2**26 // 4096) * 4
+    # two ping-pong arrays (keys, values), one u32 split per merge tile, and
+    # two sets of key samples (every 64-block: first and last; every tile: first and last)
+    tiles, blocks = 2**26 // 4096, 2**26 // 64
+    assert st == 0 and need == 2 * 2**26 * 4 + tiles * 4 + 2 * (2 * blocks * 4 + 2 * tiles * 4)
     assert q_sort(lib, 2**32)[0] == 1  # above 2^32 - 1 keys: invalid
 
 
