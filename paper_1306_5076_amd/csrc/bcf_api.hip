@@ -178,6 +178,8 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     uint32_t *kt = static_cast<uint32_t *>(temp);
     uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + align256(n * 4)) : nullptr;
     uint32_t *splits = reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + data);
+    const char *ts_env = std::getenv("BCF_TILE_SAMPLES");
+    const bool tile_samples = !(ts_env && ts_env[0] == '0');
     auto sample_set = [&](uint32_t k) {
         char *b = static_cast<char *>(temp) + data + align256(tiles * 4) + k * set_bytes;
         SampleSet ss;
@@ -185,6 +187,8 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
         ss.l = reinterpret_cast<uint32_t *>(b + align256(blocks64 * 4));
         ss.cf = reinterpret_cast<uint32_t *>(b + 2 * align256(blocks64 * 4));
         ss.cl = reinterpret_cast<uint32_t *>(b + 2 * align256(blocks64 * 4) + align256(tiles * 4));
+        if (!tile_samples)
+            ss.cf = ss.cl = nullptr;
         return ss;
     };
     const SampleSet none{nullptr, nullptr, nullptr, nullptr};

@@ -32,6 +32,25 @@ namespace bcf {
 
 // ------------------------------------------------------------------ tile I/O
 
+// Global load / store, optionally with the nontemporal hint (streamed data
+// that is not re-read by this launch).
+template <bool NT>
+__device__ __forceinline__ uint32_t ld(const uint32_t *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st(uint32_t *p, uint32_t v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // Load `count` elements starting at `src` into STRIDED layout (position
 // p = 64r + lane); positions >= count become padding (max key, max rank).
 // For pairs the tie-break rank is the position in the input order.
@@ -68,7 +87,7 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
 }
 
 // Store the first `count` positions of a STRIDED tile.
-template <bool P>
+template <bool P, bool NT = false>
 __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restrict__ kdst,
                                            uint32_t *__restrict__ vdst, uint32_t count, uint32_t lane)
 {
@@ -77,17 +96,17 @@ __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restri
     if (count >= (uint32_t)kTile) {
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
-            kp[kWave * r] = t.k[r];
+            st<NT>(kp + kWave * r, t.k[r]);
             if constexpr (P)
-                vp[kWave * r] = t.v[r];
+                st<NT>(vp + kWave * r, t.v[r]);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
             if (kWave * r + lane < count) {
-                kp[kWave * r] = t.k[r];
+                st<NT>(kp + kWave * r, t.k[r]);
                 if constexpr (P)
-                    vp[kWave * r] = t.v[r];
+                    st<NT>(vp + kWave * r, t.v[r]);
             }
         }
     }
@@ -247,7 +266,7 @@ struct MergeTask {
 // Register row r holds positions [64r, 64r + 64); all but at most two rows lie
 // entirely in A or entirely in B, which a wave-uniform branch detects, so
 // those rows are one coalesced load from a per-piece base pointer.
-template <bool P>
+template <bool P, bool NT = false>
 __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, uint32_t lane)
 {
     const uint32_t na = m.pa, nb = m.pb;
@@ -261,15 +280,15 @@ __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, u
         const uint32_t p0 = kWave * r;
         const uint32_t p = p0 + lane;
         if (p0 + kWave <= na) {  // whole row in A
-            t.k[r] = ka[kWave * r];
+            t.k[r] = ld<NT>(ka + kWave * r);
             if constexpr (P) {
-                t.v[r] = va[kWave * r];
+                t.v[r] = ld<NT>(va + kWave * r);
                 t.i[r] = p;
             }
         } else if (p0 >= bstart) {  // whole row in B
-            t.k[r] = kb[-kWave * r];
+            t.k[r] = ld<NT>(kb - kWave * r);
             if constexpr (P) {
-                t.v[r] = vb[-kWave * r];
+                t.v[r] = ld<NT>(vb - kWave * r);
                 t.i[r] = na + (kTile - 1 - p);
             }
         } else {  // row crossing A / padding / B
@@ -326,6 +345,8 @@ __device__ __forceinline__ void write_samples(const Lines<P> &t, const SampleSet
         s.f[b] = t.k[0];
         s.l[b] = t.k[kLine - 1];
     }
+    if (s.cf == nullptr)
+        return;
     const uint64_t c = gpos / kTile;
     if (lane == 0)
         s.cf[c] = t.k[0];
@@ -669,9 +690,14 @@ __global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, 
     const uint64_t apos = m.base, bpos = m.base + na;
     const SampleSet &sm = src.in_smp;
     const uint32_t *A = m.ka, *B = m.ka + na;
-    corank_level<kTile>(lo, hi, lane, [&](uint32_t i) {
-        return sm.cf[(apos + i) / kTile] > sm.cl[(bpos + d - 1 - i) / kTile];
-    });
+    if (sm.cf != nullptr)
+        corank_level<kTile>(lo, hi, lane, [&](uint32_t i) {
+            return sm.cf[(apos + i) / kTile] > sm.cl[(bpos + d - 1 - i) / kTile];
+        });
+    else  // tile samples are every 64th block sample
+        corank_level<kTile>(lo, hi, lane, [&](uint32_t i) {
+            return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine];
+        });
     corank_level<kLine>(lo, hi, lane, [&](uint32_t i) {
         return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine];
     });
@@ -680,7 +706,7 @@ __global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, 
         splits[t] = lo;
 }
 
-template <bool P, class Src, int MODE>
+template <bool P, class Src, int MODE, bool NT = false>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const uint32_t *__restrict__ splits)
 {
     __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
@@ -702,9 +728,9 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
             const uint32_t ln = opaque(lane);
             const MergeTask<P> m = merge_task<P>(src, splits, t);
             Lines<P> a;
-            merge_load<P>(a, m, ln);
+            merge_load<P, NT>(a, m, ln);
             merge_network<P>(a, lds, ln, src.out_smp, m.gpos, m.count);
-            store_tile<P>(a, m.kd, m.vd, m.count, ln);
+            store_tile<P, NT>(a, m.kd, m.vd, m.count, ln);
         }
     } else {
         Lines<P> a, b;
@@ -808,13 +834,20 @@ static int merge_mode()
     return (e && e[0] >= '0' && e[0] <= '2') ? e[0] - '0' : 1;
 }
 
-template <bool P, class Src, int MODE>
+template <bool P, class Src, int MODE, bool NT = false>
 static hipError_t launch_merge_mode(const Src &src, const uint32_t *splits, hipStream_t s)
 {
     const uint32_t groups = MODE == 2 ? (src.ntiles + kWavesPerGroup - 1) / kWavesPerGroup
-                                      : persistent_groups(k_merge<P, Src, MODE>, src.ntiles);
-    hipLaunchKernelGGL((k_merge<P, Src, MODE>), dim3(groups), dim3(kWave * kWavesPerGroup), 0, s, src, splits);
+                                      : persistent_groups(k_merge<P, Src, MODE, NT>, src.ntiles);
+    hipLaunchKernelGGL((k_merge<P, Src, MODE, NT>), dim3(groups), dim3(kWave * kWavesPerGroup), 0, s, src, splits);
     return hipGetLastError();
+}
+
+// Nontemporal hints on the merge pass's tile traffic: BCF_NT=1.
+static bool merge_nt()
+{
+    const char *e = std::getenv("BCF_NT");
+    return e && e[0] == '1';
 }
 
 template <bool P, class Src>
@@ -825,7 +858,9 @@ static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream
     switch (merge_mode()) {
     case 0: return P ? launch_merge_mode<P, Src, 1>(src, splits, s) : launch_merge_mode<P, Src, 0>(src, splits, s);
     case 2: return launch_merge_mode<P, Src, 2>(src, splits, s);
-    default: return launch_merge_mode<P, Src, 1>(src, splits, s);
+    default:
+        return merge_nt() ? launch_merge_mode<P, Src, 1, true>(src, splits, s)
+                          : launch_merge_mode<P, Src, 1>(src, splits, s);
     }
 }
 

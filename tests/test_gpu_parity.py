@@ -376,3 +376,18 @@ def test_segmented_plan_graph_replay(torch_dev, bcf, pairs):
         else:
             assert torch.equal(kout, eager)
             assert first_diff(kout.cpu().numpy(), oracle.segmented_sort(keys, offs)) is None
+
+
+@pytest.mark.parametrize("env", [{"BCF_TILE_SAMPLES": "0"}, {"BCF_NT": "1"}, {"BCF_NO_SAMPLES": "1"}])
+def test_sort_switches(torch_dev, bcf, env, monkeypatch):
+    torch, dev = torch_dev
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    for n, dist in [((1 << 21) + 3, "uniform"), (9 * 32768 + 5, "zipf"), (1 << 20, "distinct16")]:
+        keys = workloads.keys_u32(dist, n, seed=21)
+        got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+        assert first_diff(got, oracle.sort_u32(keys)) is None
+        kk, vv = workloads.pairs_u32(dist, n, seed=22)
+        ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, kk), to_dev(torch, dev, vv))
+        wk, wv = oracle.sort_pairs_u32(kk, vv)
+        assert first_diff(ko.cpu().numpy(), wk) is None and first_diff(vo.cpu().numpy(), wv) is None
