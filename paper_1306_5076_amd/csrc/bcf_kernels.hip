@@ -263,54 +263,32 @@ struct MergeTask {
 // Load a merge work item as one bitonic STRIDED tile: A goes to positions
 // [0, pa) ascending, B to positions [kTile - pb, kTile) reversed, padding in
 // between.  Ranks follow the order A then B so that equal keys leave A first.
-// Register row r holds positions [64r, 64r + 64); all but at most two rows lie
-// entirely in A or entirely in B, which a wave-uniform branch detects, so
-// those rows are one coalesced load from a per-piece base pointer.
+// Every lane computes a 32-bit element offset from the A-piece (the B-piece
+// lies dB elements after it in the same array) and issues one unconditional
+// load per register row, so all 64 loads of a tile are in flight together;
+// padding lanes re-read element 0, which is always valid.
 template <bool P, bool NT = false>
 __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, uint32_t lane)
 {
     const uint32_t na = m.pa, nb = m.pb;
     const uint32_t bstart = kTile - nb;
-    const uint32_t *ka = m.ka + lane;                 // ka[64r]  = A[p]
-    const uint32_t *kb = m.kb + (kTile - 1 - lane);   // kb[-64r] = B[kTile - 1 - p]
-    const uint32_t *va = P ? m.va + lane : nullptr;
-    const uint32_t *vb = P ? m.vb + (kTile - 1 - lane) : nullptr;
+    const uint32_t dB = (uint32_t)(m.kb - m.ka);   // B-piece start relative to the A-piece
+    const uint32_t bend = dB + (kTile - 1);        // offset of position p in B is bend - p
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
-        const uint32_t p0 = kWave * r;
-        const uint32_t p = p0 + lane;
-        if (p0 + kWave <= na) {  // whole row in A
-            t.k[r] = ld<NT>(ka + kWave * r);
-            if constexpr (P) {
-                t.v[r] = ld<NT>(va + kWave * r);
-                t.i[r] = p;
-            }
-        } else if (p0 >= bstart) {  // whole row in B
-            t.k[r] = ld<NT>(kb - kWave * r);
-            if constexpr (P) {
-                t.v[r] = ld<NT>(vb - kWave * r);
-                t.i[r] = na + (kTile - 1 - p);
-            }
-        } else {  // row crossing A / padding / B
-            const bool in_a = p < na;
-            const bool in_b = p >= bstart;
-            const uint32_t qb = kTile - 1 - p;
-            // every lane loads from a valid address; padding lanes re-read A[0] or B[0]
-            const uint32_t *kp = in_a ? m.ka + p : (in_b ? m.kb + qb : (na ? m.ka : m.kb));
-            const uint32_t key = (na | nb) ? *kp : kMaxKey;
-            t.k[r] = (in_a || in_b) ? key : kMaxKey;
-            if constexpr (P) {
-                const uint32_t *vp = in_a ? m.va + p : (in_b ? m.vb + qb : (na ? m.va : m.vb));
-                t.v[r] = (na | nb) ? *vp : 0u;
-                t.i[r] = in_a ? p : (in_b ? na + qb : kPadIdx);
-            }
+        const uint32_t p = kWave * r + lane;
+        const bool in_a = p < na;
+        const bool in_b = p >= bstart;
+        const uint32_t off = in_a ? p : (in_b ? bend - p : 0u);
+        const uint32_t key = ld<NT>(m.ka + off);
+        t.k[r] = (in_a || in_b) ? key : kMaxKey;
+        if constexpr (P) {
+            t.v[r] = ld<NT>(m.va + off);
+            t.i[r] = in_a ? p : (in_b ? na + (kTile - 1 - p) : kPadIdx);
         }
     }
 }
 
-// Sort a bitonic STRIDED tile: half-cleaners on position bits 11..6 (register
-// bits in STRIDED layout), transpose, bits 5..0 (register bits in BLOCKED
-// layout), transpose back.
 template <bool P>
 __device__ __forceinline__ void write_samples(const Lines<P> &t, const SampleSet &s, uint64_t gpos, uint32_t count,
                                               uint32_t lane);
