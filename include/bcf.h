@@ -82,9 +82,9 @@ bcf_status bcf_sort_pairs_u32(const uint32_t *keys_in, const uint32_t *vals_in, 
  *   run_offsets  HOST, k+1 entries
  *   keys_out     device, run_offsets[k] u32
  *   vals_out     device (ignored when vals_in is NULL)
- * Every run must be sorted ascending (precondition).  With the environment
- * variable BCF_CHECK=1 the library checks it and returns BCF_ERR_UNSORTED_RUN
- * (this check synchronises the stream).
+ * Every run must be sorted ascending (precondition).  With the tuning knob
+ * check_runs set (environment BCF_CHECK=1) the library checks it and returns
+ * BCF_ERR_UNSORTED_RUN (this check synchronises the stream).
  */
 bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
                           uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp,
@@ -142,6 +142,31 @@ uint32_t bcf_run_keys(int pairs);
  * O(1 + log(N/M)) scans).  Each merge pass is preceded by a small partition
  * launch that reads O(log n) keys per 4096-key output tile. */
 uint32_t bcf_sort_passes(uint64_t n, int pairs);
+
+/*
+ * Process-wide tuning knobs (read by every later call; not per stream).
+ * Initial values come from environment variables read once, at the first
+ * call into the library: BCF_MERGE_MODE, BCF_NT, BCF_NO_SAMPLES,
+ * BCF_TILE_SAMPLES, BCF_SEG_GROUP_MIN, BCF_CHECK.  The autotuner sets them
+ * through bcf_set_tuning.  Calls that are in flight on other threads when the
+ * knobs change may use either setting; results are identical either way.
+ */
+typedef struct {
+    int32_t merge_variant;     /* merge-pass kernel: 0 persistent waves with next-tile
+                                  prefetch, 1 persistent waves (default), 2 one tile per wave */
+    int32_t nontemporal;       /* 1: nontemporal hints on merge-pass tile loads and stores */
+    int32_t sampled_partition; /* 1 (default): a pass's co-rank search starts from the key samples
+                                  the previous pass wrote (sorts); 0: search the keys only */
+    int32_t tile_samples;      /* 1 (default): keep one sample per 4096-key tile besides the
+                                  64-key block samples */
+    uint64_t group_min_keys;   /* segmented sorts: segments of at least this many keys are
+                                  block-sorted by multi-wave work-groups; 0 = library default */
+    int32_t check_runs;        /* 1: bcf_merge_runs checks that every run is sorted */
+} bcf_tuning;
+
+void bcf_get_tuning(bcf_tuning *out);
+/* BCF_ERR_INVALID for a NULL pointer or an out-of-range merge_variant. */
+bcf_status bcf_set_tuning(const bcf_tuning *in);
 
 /*
  * Per-kernel timing.  While enabled, every launch the library makes is

@@ -20,6 +20,9 @@ _API = (
     "sort_passes",
     "profile_enable",
     "profile_collect",
+    "get_tuning",
+    "set_tuning",
+    "tuning",
 )
 
 

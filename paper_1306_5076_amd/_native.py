@@ -36,6 +36,8 @@ EXPORTED = (
     "bcf_tile_keys",
     "bcf_run_keys",
     "bcf_sort_passes",
+    "bcf_get_tuning",
+    "bcf_set_tuning",
     "bcf_profile_enable",
     "bcf_profile_collect",
 )
@@ -45,6 +47,19 @@ class BcfError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn} failed: {msg}")
         self.status = status
+
+
+class Tuning(ctypes.Structure):
+    """Mirror of bcf_tuning (include/bcf.h)."""
+
+    _fields_ = [
+        ("merge_variant", ctypes.c_int32),
+        ("nontemporal", ctypes.c_int32),
+        ("sampled_partition", ctypes.c_int32),
+        ("tile_samples", ctypes.c_int32),
+        ("group_min_keys", ctypes.c_uint64),
+        ("check_runs", ctypes.c_int32),
+    ]
 
 
 class KernelStat(ctypes.Structure):
@@ -93,6 +108,10 @@ def load(path: str = LIB_PATH):
     lib.bcf_run_keys.restype = u32
     lib.bcf_sort_passes.argtypes = [u64, ctypes.c_int]
     lib.bcf_sort_passes.restype = u32
+    lib.bcf_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.bcf_get_tuning.restype = None
+    lib.bcf_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.bcf_set_tuning.restype = ctypes.c_int
     lib.bcf_profile_enable.argtypes = [ctypes.c_int]
     lib.bcf_profile_enable.restype = None
     lib.bcf_profile_collect.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int]

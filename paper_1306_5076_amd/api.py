@@ -13,7 +13,9 @@ import ctypes
 import numpy as np
 import torch
 
-from ._native import KernelStat, check, load
+import contextlib
+
+from ._native import KernelStat, Tuning, check, load
 
 __all__ = [
     "Workspace",
@@ -27,6 +29,9 @@ __all__ = [
     "sort_passes",
     "profile_enable",
     "profile_collect",
+    "get_tuning",
+    "set_tuning",
+    "tuning",
 ]
 
 _U32 = (torch.uint32, torch.int32)
@@ -296,3 +301,34 @@ def profile_collect():
         buf[i].name.decode(): {"launches": int(buf[i].launches), "total_ms": buf[i].total_ms, "bytes": buf[i].bytes}
         for i in range(n)
     }
+
+
+_TUNING_FIELDS = [f[0] for f in Tuning._fields_]
+
+
+def get_tuning() -> dict:
+    """The library's process-wide tuning knobs (see bcf_tuning in include/bcf.h)."""
+    t = Tuning()
+    load().bcf_get_tuning(ctypes.byref(t))
+    return {f: int(getattr(t, f)) for f in _TUNING_FIELDS}
+
+
+def set_tuning(**knobs) -> dict:
+    """Change some knobs; returns the previous setting."""
+    prev = get_tuning()
+    unknown = set(knobs) - set(_TUNING_FIELDS)
+    if unknown:
+        raise KeyError(f"unknown tuning knobs {sorted(unknown)}")
+    t = Tuning(**{**prev, **knobs})
+    check("bcf_set_tuning", load().bcf_set_tuning(ctypes.byref(t)))
+    return prev
+
+
+@contextlib.contextmanager
+def tuning(**knobs):
+    """Temporarily change tuning knobs."""
+    prev = set_tuning(**knobs)
+    try:
+        yield
+    finally:
+        set_tuning(**prev)

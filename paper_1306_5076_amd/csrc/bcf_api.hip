@@ -130,6 +130,35 @@ bcf_status upload(void *dst, const void *src, size_t bytes, hipStream_t s)
 
 bcf_status dev_status(hipError_t e) { return e == hipSuccess ? BCF_OK : BCF_ERR_DEVICE; }
 
+// ------------------------------------------------------------------- tuning
+
+std::mutex g_tune_mu;
+bool g_tune_init = false;
+Tuning g_tune;
+
+int env_int(const char *name, int dflt)
+{
+    const char *e = std::getenv(name);
+    return (e && *e) ? std::atoi(e) : dflt;
+}
+
+Tuning &tuning_locked()
+{
+    if (!g_tune_init) {
+        g_tune.merge_variant = env_int("BCF_MERGE_MODE", 1);
+        if (g_tune.merge_variant < 0 || g_tune.merge_variant > 2)
+            g_tune.merge_variant = 1;
+        g_tune.nontemporal = env_int("BCF_NT", 1) != 0;
+        g_tune.sampled_partition = std::getenv("BCF_NO_SAMPLES") == nullptr;
+        g_tune.tile_samples = env_int("BCF_TILE_SAMPLES", 1) != 0;
+        const char *e = std::getenv("BCF_SEG_GROUP_MIN");
+        g_tune.group_min_keys = (e && *e) ? std::strtoull(e, nullptr, 10) : 0;
+        g_tune.check_runs = env_int("BCF_CHECK", 0) == 1;
+        g_tune_init = true;
+    }
+    return g_tune;
+}
+
 #define BCF_TRY(x)                          \
     do {                                    \
         bcf_status st_ = (x);               \
@@ -178,8 +207,8 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     uint32_t *kt = static_cast<uint32_t *>(temp);
     uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + align256(n * 4)) : nullptr;
     uint32_t *splits = reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + data);
-    const char *ts_env = std::getenv("BCF_TILE_SAMPLES");
-    const bool tile_samples = !(ts_env && ts_env[0] == '0');
+    const Tuning tu = tuning();
+    const bool tile_samples = tu.tile_samples;
     auto sample_set = [&](uint32_t k) {
         char *b = static_cast<char *>(temp) + data + align256(tiles * 4) + k * set_bytes;
         SampleSet ss;
@@ -192,7 +221,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
         return ss;
     };
     const SampleSet none{nullptr, nullptr, nullptr, nullptr};
-    const bool sampled = std::getenv("BCF_NO_SAMPLES") == nullptr;  // searches from samples (default)
+    const bool sampled = tu.sampled_partition;  // searches start from samples
     // X_j = buffer after pass j; X_passes = out.
     auto kbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? kout : kt; };
     auto vbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? vout : vt; };
@@ -354,10 +383,8 @@ bcf_status launch_tables(Bufs kb, Bufs vb, char *temp, const TablePlan &P, hipSt
 // (fewer merge passes); shorter ones in 4096-key wave tiles.
 uint64_t group_min_keys(bool pairs)
 {
-    const char *e = std::getenv("BCF_SEG_GROUP_MIN");
-    if (e && *e)
-        return std::strtoull(e, nullptr, 10);
-    return group_run_keys(pairs) / 2;
+    const uint64_t g = tuning().group_min_keys;
+    return g ? g : group_run_keys(pairs) / 2;
 }
 
 // Plan of a segmented sort: every segment is block-sorted into runs that
@@ -455,6 +482,14 @@ bcf_status segmented_impl(SegMode mode, bool pairs, const uint32_t *kin, const u
 }
 
 }  // namespace
+
+namespace bcf {
+Tuning tuning()
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return tuning_locked();
+}
+}  // namespace bcf
 
 // ======================================================================= ABI
 
@@ -568,7 +603,7 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
     uint32_t *kt = reinterpret_cast<uint32_t *>(tb);
     uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(tb + align256(n * 4)) : nullptr;
 
-    if (std::getenv("BCF_CHECK") && std::atoi(std::getenv("BCF_CHECK")) == 1) {
+    if (tuning().check_runs) {
         // sortedness of every run (synchronises the stream)
         uint64_t *offs_d = reinterpret_cast<uint64_t *>(tb + check_off);
         uint32_t *flag_d =
@@ -634,6 +669,35 @@ bcf_status bcf_segmented_execute(const uint32_t *keys_in, const uint32_t *vals_i
 {
     return segmented_impl(kSegExecute, vals_in != nullptr, keys_in, vals_in, keys_out, vals_out, seg_offsets, nseg,
                           temp, temp_bytes, static_cast<hipStream_t>(stream));
+}
+
+void bcf_get_tuning(bcf_tuning *out)
+{
+    if (!out)
+        return;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const Tuning &t = tuning_locked();
+    out->merge_variant = t.merge_variant;
+    out->nontemporal = t.nontemporal;
+    out->sampled_partition = t.sampled_partition;
+    out->tile_samples = t.tile_samples;
+    out->group_min_keys = t.group_min_keys;
+    out->check_runs = t.check_runs;
+}
+
+bcf_status bcf_set_tuning(const bcf_tuning *in)
+{
+    if (!in || in->merge_variant < 0 || in->merge_variant > 2)
+        return BCF_ERR_INVALID;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    Tuning &t = tuning_locked();
+    t.merge_variant = in->merge_variant;
+    t.nontemporal = in->nontemporal != 0;
+    t.sampled_partition = in->sampled_partition != 0;
+    t.tile_samples = in->tile_samples != 0;
+    t.group_min_keys = in->group_min_keys;
+    t.check_runs = in->check_runs != 0;
+    return BCF_OK;
 }
 
 void bcf_profile_enable(int on)

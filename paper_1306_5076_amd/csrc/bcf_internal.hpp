@@ -79,6 +79,17 @@ hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);
 
+// Current process-wide tuning (see bcf_tuning in bcf.h); a copy.
+struct Tuning {
+    int merge_variant;
+    bool nontemporal;
+    bool sampled_partition;
+    bool tile_samples;
+    uint64_t group_min_keys;
+    bool check_runs;
+};
+Tuning tuning();
+
 // Names used for per-kernel timing records.
 const char *kname_block_sort(bool pairs, bool table);
 const char *kname_partition(bool pairs, bool table);

@@ -23,8 +23,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <cstdlib>
-
 #include "bcf_device.hpp"
 #include "bcf_internal.hpp"
 
@@ -805,13 +803,6 @@ static hipError_t launch_partition(const Src &src, uint32_t *splits, hipStream_t
     return hipGetLastError();
 }
 
-// Merge kernel variant: BCF_MERGE_MODE=0|1|2 (see k_merge), default 1.
-static int merge_mode()
-{
-    const char *e = std::getenv("BCF_MERGE_MODE");
-    return (e && e[0] >= '0' && e[0] <= '2') ? e[0] - '0' : 1;
-}
-
 template <bool P, class Src, int MODE, bool NT = false>
 static hipError_t launch_merge_mode(const Src &src, const uint32_t *splits, hipStream_t s)
 {
@@ -821,24 +812,18 @@ static hipError_t launch_merge_mode(const Src &src, const uint32_t *splits, hipS
     return hipGetLastError();
 }
 
-// Nontemporal hints on the merge pass's tile traffic: BCF_NT=1.
-static bool merge_nt()
-{
-    const char *e = std::getenv("BCF_NT");
-    return e && e[0] == '1';
-}
-
 template <bool P, class Src>
 static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream_t s)
 {
     if (src.ntiles == 0)
         return hipSuccess;
-    switch (merge_mode()) {
+    const Tuning tu = tuning();
+    switch (tu.merge_variant) {
     case 0: return P ? launch_merge_mode<P, Src, 1>(src, splits, s) : launch_merge_mode<P, Src, 0>(src, splits, s);
     case 2: return launch_merge_mode<P, Src, 2>(src, splits, s);
     default:
-        return merge_nt() ? launch_merge_mode<P, Src, 1, true>(src, splits, s)
-                          : launch_merge_mode<P, Src, 1>(src, splits, s);
+        return tu.nontemporal ? launch_merge_mode<P, Src, 1, true>(src, splits, s)
+                              : launch_merge_mode<P, Src, 1>(src, splits, s);
     }
 }
 

@@ -1,0 +1,371 @@
+"""Continuous-batching sort service on one GPU, and its one-call-per-request baseline.
+
+:class:`SortServer` accepts sort requests (u32 keys, or u32/u32 pairs sorted
+stably by key) from any thread.  A scheduler thread
+
+* admits waiting requests in arrival order while their device bytes fit the
+  HBM budget (a request larger than the whole budget is rejected);
+* packs every admitted request of one kind into a single batch and sorts the
+  batch with ONE segmented launch sequence (``bcf_segmented_sort`` /
+  ``bcf_segmented_sort_pairs``): each request is a segment;
+* runs batches as a three-stage pipeline on separate streams (host-to-device
+  copy, sort, device-to-host copy), so a batch's copies overlap the previous
+  batch's kernels, and requests that arrive meanwhile join the next batch;
+* keeps its device buffers and pinned host staging resident between batches
+  (they grow on demand and are reused, never freed per request);
+* completes a request when its batch's device-to-host copy has finished and
+  records its latency from arrival to completion.
+
+:func:`serve_serial` is the baseline: one request at a time, in arrival order,
+each with its own copy in, ``bcf_sort_u32`` / ``bcf_sort_pairs_u32`` call and
+copy out, synchronised.
+"""
+
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import api
+
+__all__ = ["SortServer", "serve_serial", "serve_batched", "latency_stats", "make_requests", "run_serving_benchmark"]
+
+
+@dataclass
+class _Request:
+    keys: np.ndarray
+    vals: np.ndarray | None
+    arrival: float
+    future: Future = field(default_factory=Future)
+    finished: float = 0.0
+
+    @property
+    def n(self) -> int:
+        return int(self.keys.size)
+
+    @property
+    def pairs(self) -> bool:
+        return self.vals is not None
+
+    def device_bytes(self) -> int:
+        words = 2 if self.pairs else 1
+        # input + output arrays, plus merge scratch of the same size and a margin for descriptors
+        return self.n * 4 * words * 3 + 64 * 1024
+
+
+class _Grow:
+    """A tensor that grows on demand and is reused (device or pinned host)."""
+
+    def __init__(self, device=None, pinned=False):
+        self.device, self.pinned, self.t = device, pinned, None
+
+    def get(self, n: int):
+        if self.t is None or self.t.numel() < n:
+            cap = max(n, 1 << 16)
+            if self.pinned:
+                self.t = torch.empty(cap, dtype=torch.uint32, pin_memory=True)
+            else:
+                self.t = torch.empty(cap, dtype=torch.uint32, device=self.device)
+        return self.t[:n]
+
+
+class _Slot:
+    """Resident buffers of one in-flight batch."""
+
+    def __init__(self, device):
+        self.hk, self.hv = _Grow(pinned=True), _Grow(pinned=True)      # host in
+        self.ok, self.ov = _Grow(pinned=True), _Grow(pinned=True)      # host out
+        self.dk, self.dv = _Grow(device), _Grow(device)                # device in
+        self.rk, self.rv = _Grow(device), _Grow(device)                # device out
+        self.ws = api.Workspace(device)
+        self.done = None
+        self.reqs = []
+        self.offs = None
+
+
+class SortServer:
+    """Continuous-batching sort server (see module docstring)."""
+
+    def __init__(self, device="cuda:0", hbm_budget: int = 16 << 30, max_batch_keys: int = 1 << 26,
+                 slots: int = 3):
+        self.device = torch.device(device)
+        self.budget = int(hbm_budget)
+        self.max_batch_keys = int(max_batch_keys)
+        self.h2d = torch.cuda.Stream(self.device)
+        self.compute = torch.cuda.Stream(self.device)
+        self.d2h = torch.cuda.Stream(self.device)
+        self.slots = [_Slot(self.device) for _ in range(slots)]
+        self.free_slots = collections.deque(self.slots)
+        self.busy = collections.deque()
+        self.pending = collections.deque()
+        self.used = 0
+        self.peak_used = 0
+        self.batches = 0
+        self.batch_sizes = []
+        self.cv = threading.Condition()
+        self.stop = False
+        self.error = None
+        self.thread = threading.Thread(target=self._run, name="bcf-sort-server", daemon=True)
+        self.thread.start()
+
+    # ---------------------------------------------------------------- client side
+
+    def submit(self, keys, vals=None, arrival: float | None = None) -> Future:
+        keys = np.ascontiguousarray(np.asarray(keys, dtype=np.uint32))
+        if vals is not None:
+            vals = np.ascontiguousarray(np.asarray(vals, dtype=np.uint32))
+            if vals.shape != keys.shape:
+                raise ValueError("keys and vals must have the same length")
+        r = _Request(keys, vals, time.perf_counter() if arrival is None else arrival)
+        if r.device_bytes() > self.budget:
+            r.future.set_exception(MemoryError(f"request of {r.n} keys exceeds the HBM budget"))
+            return r.future
+        with self.cv:
+            self.pending.append(r)
+            self.cv.notify()
+        return r.future
+
+    def close(self):
+        with self.cv:
+            self.stop = True
+            self.cv.notify()
+        self.thread.join()
+        if self.error:
+            raise self.error
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---------------------------------------------------------------- scheduler
+
+    def _run(self):
+        try:
+            torch.cuda.set_device(self.device)
+            while True:
+                with self.cv:
+                    while not self.stop and not self.pending and not self.busy:
+                        self.cv.wait()
+                    if self.stop and not self.pending and not self.busy:
+                        return
+                self._complete()
+                launched = self._admit_and_launch()
+                if not launched and self.busy:
+                    time.sleep(20e-6)  # waiting for the device; poll completions again
+        except BaseException as e:  # surface in close()
+            self.error = e
+            with self.cv:
+                for r in self.pending:
+                    if not r.future.done():
+                        r.future.set_exception(e)
+
+    def _complete(self):
+        while self.busy and self.busy[0].done.query():
+            slot = self.busy.popleft()
+            now = time.perf_counter()
+            offs = slot.offs
+            for i, r in enumerate(slot.reqs):
+                lo, hi = int(offs[i]), int(offs[i + 1])
+                k = slot.ok.t[lo:hi].numpy().copy()
+                v = slot.ov.t[lo:hi].numpy().copy() if r.pairs else None
+                r.finished = now
+                r.future._bcf_finished = now
+                r.future.set_result((k, v) if r.pairs else k)
+                self.used -= r.device_bytes()
+            slot.reqs = []
+            self.free_slots.append(slot)
+
+    def _admit_and_launch(self) -> bool:
+        if not self.free_slots:
+            return False
+        with self.cv:
+            if not self.pending:
+                return False
+            kind = self.pending[0].pairs
+            batch, keys = [], 0
+            while self.pending and self.pending[0].pairs == kind:
+                r = self.pending[0]
+                if batch and keys + r.n > self.max_batch_keys:
+                    break
+                if self.used + r.device_bytes() > self.budget:
+                    break  # admission by free-HBM budget: wait for completions
+                self.pending.popleft()
+                batch.append(r)
+                keys += r.n
+                self.used += r.device_bytes()
+            if not batch:
+                return False
+        self.peak_used = max(self.peak_used, self.used)
+        slot = self.free_slots.popleft()
+        self._launch(slot, batch, kind)
+        self.busy.append(slot)
+        self.batches += 1
+        self.batch_sizes.append(len(batch))
+        return True
+
+    def _launch(self, slot: _Slot, batch, pairs: bool):
+        sizes = [r.n for r in batch]
+        offs = np.zeros(len(batch) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum(sizes)
+        n = int(offs[-1])
+        slot.reqs, slot.offs = batch, offs
+        hk = slot.hk.get(n)
+        hkn = hk.numpy()
+        for i, r in enumerate(batch):
+            hkn[int(offs[i]):int(offs[i + 1])] = r.keys
+        dk, rk = slot.dk.get(n), slot.rk.get(n)
+        if pairs:
+            hv = slot.hv.get(n)
+            hvn = hv.numpy()
+            for i, r in enumerate(batch):
+                hvn[int(offs[i]):int(offs[i + 1])] = r.vals
+            dv, rv = slot.dv.get(n), slot.rv.get(n)
+        # stage 1: host -> device
+        with torch.cuda.stream(self.h2d):
+            dk.copy_(hk, non_blocking=True)
+            if pairs:
+                dv.copy_(hv, non_blocking=True)
+        # stage 2: one segmented sort over the whole batch
+        self.compute.wait_stream(self.h2d)
+        with torch.cuda.stream(self.compute):
+            if pairs:
+                api.segmented_sort(dk, offs, vals=dv, keys_out=rk, vals_out=rv, stream=self.compute,
+                                   workspace=slot.ws)
+            else:
+                api.segmented_sort(dk, offs, keys_out=rk, stream=self.compute, workspace=slot.ws)
+        # stage 3: device -> host
+        self.d2h.wait_stream(self.compute)
+        ok = slot.ok.get(n)
+        with torch.cuda.stream(self.d2h):
+            ok.copy_(rk, non_blocking=True)
+            if pairs:
+                slot.ov.get(n).copy_(rv, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.d2h)
+        slot.done = ev
+
+
+def serve_serial(requests, device="cuda:0", realtime: bool = True):
+    """Baseline: each request alone (copy in, sort, copy out, synchronise), FIFO.
+
+    ``requests`` is a list of ``(arrival_offset_s, keys, vals_or_None)``; with
+    ``realtime`` a request is not started before its arrival time.  Returns
+    ``(results, latencies_s, wall_s)``.
+    """
+    dev = torch.device(device)
+    ws = api.Workspace(dev)
+    hk, hv = _Grow(pinned=True), _Grow(pinned=True)
+    dk, dv, rk, rv = _Grow(dev), _Grow(dev), _Grow(dev), _Grow(dev)
+    out, lat = [], []
+    t0 = time.perf_counter()
+    for arr, keys, vals in requests:
+        if realtime:
+            while time.perf_counter() - t0 < arr:
+                pass
+        arrival = t0 + arr if realtime else time.perf_counter()
+        n = keys.size
+        hkn = hk.get(n)
+        hkn.numpy()[:] = keys
+        dkk, rkk = dk.get(n), rk.get(n)
+        dkk.copy_(hkn, non_blocking=True)
+        if vals is not None:
+            hvn = hv.get(n)
+            hvn.numpy()[:] = vals
+            dvv, rvv = dv.get(n), rv.get(n)
+            dvv.copy_(hvn, non_blocking=True)
+            api.sort_pairs_u32(dkk, dvv, rkk, rvv, workspace=ws)
+            res = (rkk.cpu().numpy(), rvv.cpu().numpy())
+        else:
+            api.sort_u32(dkk, out=rkk, workspace=ws)
+            res = rkk.cpu().numpy()
+        torch.cuda.synchronize(dev)
+        lat.append(time.perf_counter() - arrival)
+        out.append(res)
+    return out, lat, time.perf_counter() - t0
+
+
+def latency_stats(lat_s):
+    a = np.asarray(lat_s, dtype=np.float64) * 1e3
+    return {"p50_ms": round(float(np.percentile(a, 50)), 3), "p99_ms": round(float(np.percentile(a, 99)), 3),
+            "mean_ms": round(float(a.mean()), 3), "max_ms": round(float(a.max()), 3)}
+
+
+def make_requests(count: int, lo: int = 1 << 10, hi: int = 1 << 24, seed: int = 1, pool_keys: int = 1 << 25):
+    """Seeded serving workload: (arrival_at_qps_1, keys, vals_or_None) per request.
+
+    Sizes are log-uniform in [lo, hi]; half the requests are key/value pairs
+    (value = position in the request); keys are slices of one seeded uniform
+    pool so that the request set is cheap to build.
+    """
+    import workloads
+
+    pool = workloads.keys_u32("uniform", pool_keys, seed=seed)
+    spec = workloads.request_stream(count, qps=1.0, lo=lo, hi=hi, seed=seed)
+    offs = workloads.draws_u64(seed ^ 0x0FF, count) % np.uint64(max(1, pool_keys - hi))
+    reqs = []
+    for i, (t, size, pairs, _) in enumerate(spec):
+        size = min(size, pool_keys)
+        o = int(offs[i])
+        keys = pool[o:o + size]
+        vals = np.arange(size, dtype=np.uint32) if pairs else None
+        reqs.append((t, keys, vals))
+    return reqs
+
+
+def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 << 30):
+    """Submit ``requests`` at their arrival times (scaled to ``qps``) to a
+    :class:`SortServer`; returns (results, latencies_s, wall_s, server stats)."""
+    server = SortServer(device, hbm_budget=hbm_budget)
+    futs, arrivals = [], []
+    t0 = time.perf_counter()
+    for t, keys, vals in requests:
+        at = t0 + t / qps
+        while time.perf_counter() < at:
+            pass
+        arrivals.append(at)
+        futs.append(server.submit(keys, vals, arrival=at))
+    results = [f.result() for f in futs]
+    wall = time.perf_counter() - t0
+    server.close()
+    lat = []
+    for f, a in zip(futs, arrivals):
+        lat.append(f._bcf_finished - a if hasattr(f, "_bcf_finished") else 0.0)
+    stats = {"batches": server.batches, "mean_batch": round(float(np.mean(server.batch_sizes)), 2),
+             "peak_hbm_bytes": server.peak_used, "hbm_budget": hbm_budget}
+    return results, lat, wall, stats
+
+
+def run_serving_benchmark(count: int = 300, fracs=(0.5, 0.8, 0.95), seed: int = 1, device="cuda:0",
+                          hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24):
+    """p50/p99 latency and Gkeys/s of the batched server and of the serial
+    baseline at fractions of the baseline's saturation request rate."""
+    reqs = make_requests(count, lo=lo, hi=hi, seed=seed)
+    total_keys = sum(k.size for _, k, _ in reqs)
+    # warm up both paths (library load, allocations)
+    serve_serial(reqs[:4], device, realtime=False)
+    serve_batched(reqs[:4], qps=1e9, device=device, hbm_budget=hbm_budget)
+    _, _, sat_wall = serve_serial(reqs, device, realtime=False)
+    sat_qps = count / sat_wall
+    out = {"requests": count, "total_keys": int(total_keys), "sizes": [lo, hi], "pairs_fraction": 0.5,
+           "hbm_budget_bytes": hbm_budget, "serial_saturation_qps": round(sat_qps, 2), "runs": []}
+    base_t = [t for t, _, _ in reqs]
+    for frac in fracs:
+        qps = frac * sat_qps
+        timed = [(t / qps, k, v) for t, k, v in reqs]
+        _, slat, swall = serve_serial(timed, device, realtime=True)
+        _, blat, bwall, bst = serve_batched(reqs, qps=qps, device=device, hbm_budget=hbm_budget)
+        out["runs"].append({
+            "qps": round(qps, 2), "frac_of_serial_saturation": frac,
+            "serial": {**latency_stats(slat), "gkeys_per_s": round(total_keys / swall / 1e9, 4)},
+            "batched": {**latency_stats(blat), "gkeys_per_s": round(total_keys / bwall / 1e9, 4), **bst},
+        })
+    del base_t
+    return out

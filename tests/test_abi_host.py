@@ -112,3 +112,20 @@ def test_segmented_validation_and_query(lib):
     a, p = _offs([0, 0, 1, 4096, 4096 + 8193])
     assert lib.bcf_segmented_sort(None, None, p, 4, None, ctypes.byref(need), None) == 0
     assert need.value > 0
+
+
+def test_tuning_roundtrip():
+    import paper_1306_5076_amd as bcf
+
+    before = bcf.get_tuning()
+    assert set(before) == {"merge_variant", "nontemporal", "sampled_partition", "tile_samples",
+                           "group_min_keys", "check_runs"}
+    with bcf.tuning(merge_variant=2, group_min_keys=12345, check_runs=1):
+        t = bcf.get_tuning()
+        assert t["merge_variant"] == 2 and t["group_min_keys"] == 12345 and t["check_runs"] == 1
+    assert bcf.get_tuning() == before
+    from paper_1306_5076_amd import BcfError
+
+    with pytest.raises(BcfError):
+        bcf.set_tuning(merge_variant=7)
+    assert bcf.get_tuning() == before

@@ -278,10 +278,7 @@ def test_errors_raise(torch_dev, bcf):
         bcf.merge_runs(keys, [0, 5, 11])
     with pytest.raises(TypeError):
         bcf.sort_u32(torch.zeros(4, dtype=torch.float32, device=dev))
-    import os
-
-    os.environ["BCF_CHECK"] = "1"
-    try:
+    with bcf.tuning(check_runs=1):
         bad = to_dev(torch, dev, np.array([1, 2, 3, 9, 4, 5, 6], dtype=np.uint32))
         with pytest.raises(BcfError) as ei:
             bcf.merge_runs(bad, [0, 3, 7])  # second run 9,4,5,6 is not sorted
@@ -290,14 +287,17 @@ def test_errors_raise(torch_dev, bcf):
         good = to_dev(torch, dev, np.array([1, 2, 3, 9, 4, 5, 6], dtype=np.uint32))
         got = bcf.merge_runs(good, [0, 4, 7]).cpu().numpy()
         assert list(got) == [1, 2, 3, 4, 5, 6, 9]
-    finally:
-        del os.environ["BCF_CHECK"]
 
 
-@pytest.mark.parametrize("mode", ["0", "1", "2"])
-def test_merge_kernel_variants(torch_dev, bcf, mode, monkeypatch):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("nt", [0, 1])
+def test_merge_kernel_variants(torch_dev, bcf, mode, nt):
     torch, dev = torch_dev
-    monkeypatch.setenv("BCF_MERGE_MODE", mode)
+    with bcf.tuning(merge_variant=mode, nontemporal=nt):
+        _check_sorts(torch, dev, bcf)
+
+
+def _check_sorts(torch, dev, bcf):
     for n, dist in [((1 << 20) + 3, "uniform"), (7 * 4096 + 5, "zipf")]:
         keys = workloads.keys_u32(dist, n, seed=11)
         got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
@@ -330,16 +330,16 @@ def test_segmented_pairs_vs_oracle(torch_dev, bcf, sizes):
         assert first_diff(ko[lo:hi], wk) is None and first_diff(vo[lo:hi], wv) is None
 
 
-@pytest.mark.parametrize("group_min", ["4097", "1000000000"])
-def test_segmented_group_threshold(torch_dev, bcf, group_min, monkeypatch):
+@pytest.mark.parametrize("group_min", [4097, 1000000000, 0])
+def test_segmented_group_threshold(torch_dev, bcf, group_min):
     # the same segments block-sorted in group tiles or in wave tiles
     torch, dev = torch_dev
-    monkeypatch.setenv("BCF_SEG_GROUP_MIN", group_min)
     sizes = [5000, 40000, 100000, 4096, 32768, 32769]
     offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
     offs[1:] = np.cumsum(sizes)
     keys = workloads.keys_u32("zipf", int(offs[-1]), seed=2)
-    got = bcf.segmented_sort(to_dev(torch, dev, keys), offs).cpu().numpy()
+    with bcf.tuning(group_min_keys=group_min):
+        got = bcf.segmented_sort(to_dev(torch, dev, keys), offs).cpu().numpy()
     assert first_diff(got, oracle.segmented_sort(keys, offs)) is None
 
 
@@ -378,11 +378,14 @@ def test_segmented_plan_graph_replay(torch_dev, bcf, pairs):
             assert first_diff(kout.cpu().numpy(), oracle.segmented_sort(keys, offs)) is None
 
 
-@pytest.mark.parametrize("env", [{"BCF_TILE_SAMPLES": "0"}, {"BCF_NT": "1"}, {"BCF_NO_SAMPLES": "1"}])
-def test_sort_switches(torch_dev, bcf, env, monkeypatch):
+@pytest.mark.parametrize("knobs", [{"tile_samples": 0}, {"nontemporal": 0}, {"sampled_partition": 0}])
+def test_sort_switches(torch_dev, bcf, knobs):
     torch, dev = torch_dev
-    for k, v in env.items():
-        monkeypatch.setenv(k, v)
+    with bcf.tuning(**knobs):
+        _check_sorts_2(torch, dev, bcf)
+
+
+def _check_sorts_2(torch, dev, bcf):
     for n, dist in [((1 << 21) + 3, "uniform"), (9 * 32768 + 5, "zipf"), (1 << 20, "distinct16")]:
         keys = workloads.keys_u32(dist, n, seed=21)
         got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()

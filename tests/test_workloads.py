@@ -56,3 +56,17 @@ def test_segment_sizes_and_runs():
     assert offs.tolist() == [0, 5, 5, 12]
     assert np.all(np.diff(keys[:5].astype(np.int64)) >= 0)
     assert np.all(np.diff(keys[5:].astype(np.int64)) >= 0)
+
+
+def test_torch_twin_bit_identical():
+    import torch
+
+    for seed, n, start in [(1, 1000, 0), (7, 4097, 123), (2**31 + 5, 333, 10**9)]:
+        a = workloads.draws_u32(seed, n, start=start)
+        b = workloads.draws_u32_torch(seed, n, "cpu", start=start, chunk=1000).numpy()
+        assert np.array_equal(a, b)
+    assert np.array_equal(workloads.segment_offsets([3, 0, 2]), np.array([0, 3, 3, 5], dtype=np.uint64))
+    for dist in ("uniform", "zipf"):
+        a = workloads.keys_u32(dist, 5000, seed=4)
+        b = workloads.keys_u32_torch(dist, 5000, "cpu", seed=4, chunk=1024).numpy()
+        assert np.array_equal(a, b), dist

@@ -197,3 +197,72 @@ def request_stream(count: int, qps: float, lo: int = 1 << 10, hi: int = 1 << 24,
     sizes = np.floor(np.exp(math.log(lo) + u1 * (math.log(hi) - math.log(lo)))).astype(np.int64)
     pairs = (d[:, 2] >> np.uint64(63)).astype(bool)
     return [(float(t[i]), int(sizes[i]), bool(pairs[i]), seed * 100003 + i) for i in range(count)]
+
+
+# ------------------------------------------------------------ torch (device) twins
+#
+# The same counter-based draws computed with torch int64 arithmetic, so large
+# inputs can be generated directly in device memory.  torch has no logical
+# right shift on int64, so shifts are masked; products wrap modulo 2^64 like
+# the numpy uint64 version.  Bit-identical to draws_u32 / keys_u32("uniform").
+
+
+def _t_srl(z, s):
+    import torch
+
+    return torch.bitwise_and(torch.bitwise_right_shift(z, s), (1 << (64 - s)) - 1)
+
+
+def _t_u64(x: int):
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def draws_u64_torch(seed: int, n: int, device, start: int = 0):
+    """int64 tensor on ``device`` holding the bits of draws_u64(seed, n, start)."""
+    import torch
+
+    base = ((int(seed) & 0xFFFFFFFF) << 32) + start
+    g, m1, m2 = _t_u64(0x9E3779B97F4A7C15), _t_u64(0xBF58476D1CE4E5B9), _t_u64(0x94D049BB133111EB)
+    z = torch.arange(0, n, dtype=torch.int64, device=device) + _t_u64(base % (1 << 64))
+    z = z + g
+    z = torch.bitwise_xor(z, _t_srl(z, 30)) * m1
+    z = torch.bitwise_xor(z, _t_srl(z, 27)) * m2
+    return torch.bitwise_xor(z, _t_srl(z, 31))
+
+
+def draws_u32_torch(seed: int, n: int, device, start: int = 0, chunk: int = 1 << 26):
+    """torch.uint32 tensor on ``device`` equal to draws_u32(seed, n, start)."""
+    import torch
+
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        out[lo:hi] = _t_srl(draws_u64_torch(seed, hi - lo, device, start + lo), 32).to(torch.int32)
+    return out.view(torch.uint32)
+
+
+def keys_u32_torch(dist: str, n: int, device, seed: int = 1, chunk: int = 1 << 26):
+    """Device twin of keys_u32 for the "uniform" and "zipf" distributions."""
+    import torch
+
+    if dist == "uniform":
+        return draws_u32_torch(seed, n, device, chunk=chunk)
+    if dist != "zipf":
+        raise ValueError(f"no device generator for {dist!r}")
+    if "cdf" not in _ZIPF_CACHE:
+        _ZIPF_CACHE["cdf"] = _zipf_cdf()
+    cdf = torch.from_numpy(_ZIPF_CACHE["cdf"]).to(device)
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        u = _t_srl(draws_u64_torch(seed, hi - lo, device, lo), 11).to(torch.float64) * (2.0 ** -53)
+        r = torch.searchsorted(cdf, u, right=True).clamp_(max=cdf.numel() - 1)
+        out[lo:hi] = ((r * 2654435761) & 0xFFFFFFFF).to(torch.int32)
+    return out.view(torch.uint32)
+
+
+def segment_offsets(sizes) -> np.ndarray:
+    """Exclusive prefix sums (uint64) of segment sizes, with the total last."""
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(np.asarray(sizes, dtype=np.uint64))
+    return offs
