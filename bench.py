@@ -73,6 +73,77 @@ def cpu_baseline(keys_np):
     }
 
 
+def _kernel_table(stats):
+    return {
+        k: {
+            "launches": v["launches"],
+            "avg_us": round(1e3 * v["total_ms"] / v["launches"], 2),
+            "GB_per_s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1),
+        }
+        for k, v in stats.items()
+    }
+
+
+def bench_pairs(bcf, workloads, torch, dev, n=1 << 28, steps=5, warmup=2):
+    """2^28 stable key/value sorts (value = original index), uniform and Zipf keys."""
+    from paper_1306_5076_amd import autotune
+
+    out = {}
+    vals = torch.arange(n, dtype=torch.int32, device=dev).view(torch.uint32)
+    ko = torch.empty(n, dtype=torch.uint32, device=dev)
+    vo = torch.empty_like(ko)
+    ws = bcf.Workspace(dev)
+    for dist in ("uniform", "zipf"):
+        keys = workloads.keys_u32_torch(dist, n, dev, seed=1)
+        fn = lambda: bcf.sort_pairs_u32(keys, vals, ko, vo, workspace=ws)
+        ms = autotune.time_ms(fn, reps=steps, warmup=warmup)
+        bcf.profile_collect()
+        bcf.profile_enable(True)
+        fn()
+        bcf.profile_enable(False)
+        out[dist] = {"ms": round(ms, 3), "Gpairs_per_s": round(n / ms / 1e6, 3),
+                     "kernels": _kernel_table(bcf.profile_collect())}
+        del keys
+    return {"n": n, "value": "original index", "stable": True, **out}
+
+
+def bench_segmented(bcf, workloads, torch, dev, count=10000, lo=32, hi=1 << 20, seed=1, reps=3):
+    """One batched segmented sort (eager and graph-replayed, autotuned knobs)
+    against one bcf_sort_u32 call per array, same arrays, same stream."""
+    from paper_1306_5076_amd import autotune
+
+    sizes = workloads.segment_sizes(count, lo=lo, hi=hi, seed=seed)
+    offs = workloads.segment_offsets(sizes)
+    n = int(offs[-1])
+    keys = workloads.draws_u32_torch(seed, n, dev)
+    out = torch.empty_like(keys)
+    ws = bcf.Workspace(dev)
+    eager = lambda: bcf.segmented_sort(keys, offs, keys_out=out, workspace=ws)
+    sig = autotune.signature("segmented", n, extra=f"{count}x[{lo},{hi}]")
+    knobs, table = autotune.tuned(sig, eager, autotune.SEGMENTED_SPACE, path=None)
+    res = {"arrays": count, "sizes": [lo, hi], "total_keys": n, "autotuned": knobs,
+           "autotune_table": table}
+    with bcf.tuning(**knobs):
+        ms_eager = autotune.time_ms(eager, reps=reps)
+        plan = bcf.SegmentedPlan(offs, dev)
+        graph = plan.capture(keys, out)
+        ms_graph = autotune.time_ms(graph.replay, reps=reps)
+        views = [(int(offs[i]), int(offs[i + 1])) for i in range(count)]
+        wsa = bcf.Workspace(dev)
+
+        def per_array():
+            for a, b in views:
+                bcf.sort_u32(keys[a:b], out=out[a:b], workspace=wsa)
+
+        ms_per = autotune.time_ms(per_array, reps=1, warmup=1)
+    res["per_array_calls"] = {"ms": round(ms_per, 3), "Gkeys_per_s": round(n / ms_per / 1e6, 3)}
+    res["batched_eager"] = {"ms": round(ms_eager, 3), "Gkeys_per_s": round(n / ms_eager / 1e6, 3)}
+    res["batched_graph"] = {"ms": round(ms_graph, 3), "Gkeys_per_s": round(n / ms_graph / 1e6, 3)}
+    res["speedup_graph_vs_per_array"] = round(ms_per / ms_graph, 2)
+    del keys, out, plan, graph
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-per-dist", action="store_true", help="skip the per-distribution timing")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline only: skip the pairs, segmented and serving sections")
     ap.add_argument(
         "--copy-calibration",
         action="store_true",
@@ -156,14 +229,7 @@ def main():
     avg_ms = st["total_ms"] / st["launches"]
     bytes_per_launch = st["bytes"] / st["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kernels = {
-        k: {
-            "launches": v["launches"],
-            "avg_us": round(1e3 * v["total_ms"] / v["launches"], 2),
-            "GB_per_s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1),
-        }
-        for k, v in stats.items()
-    }
+    kernels = _kernel_table(stats)
     traffic_rec = committed_counters("traffic_merge_keys_2p26.json")
     conflicts_rec = committed_counters("lds_conflicts_2p26.json")
 
@@ -210,6 +276,21 @@ def main():
         "lds_bank_conflicts": conflicts_rec["per_kernel"] if conflicts_rec else None,
         "kernel_source_hash": kernel_source_hash(),
     }
+    rec["tuning"] = bcf.get_tuning()
+    if not args.quick:
+        del src, out
+        torch.cuda.empty_cache()
+        t0s = time.perf_counter()
+        rec["pairs_2p28"] = bench_pairs(bcf, workloads, torch, dev)
+        torch.cuda.empty_cache()
+        rec["segmented"] = bench_segmented(bcf, workloads, torch, dev)
+        rec["segmented_2p17"] = bench_segmented(bcf, workloads, torch, dev, hi=1 << 17)
+        rec["segmented_2p17"].pop("autotune_table", None)
+        torch.cuda.empty_cache()
+        from paper_1306_5076_amd import serve
+
+        rec["serving"] = serve.run_serving_benchmark(count=200, device=str(dev))
+        rec["sections_s"] = round(time.perf_counter() - t0s, 1)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(host["uniform"])
     print(json.dumps(rec), flush=True)
