@@ -196,8 +196,31 @@ double time_ms(F launch, int reps)
     return ms / reps;
 }
 
+// Copy bandwidth as a function of the working set (in + out bytes), to see
+// where the 256 MB last-level cache (MALL) stops holding both buffers.
+void copy_working_set(int cus)
+{
+    for (int lg = 20; lg <= 27; ++lg) {
+        const size_t n = (size_t)1 << lg, ntiles = n / 4096;
+        uint32_t *in, *out;
+        CHECK(hipMalloc(&in, n * 4));
+        CHECK(hipMalloc(&out, n * 4));
+        CHECK(hipMemset(in, 1, n * 4));
+        const dim3 grid((unsigned)((ntiles + 1) / 2)), block(128);
+        const int reps = lg <= 24 ? 200 : 20;
+        const double plain = time_ms([&] { hipLaunchKernelGGL(copy_tiles_strided<false>, grid, block, 0, 0, in, out, ntiles); }, reps);
+        const double nt = time_ms([&] { hipLaunchKernelGGL(copy_tiles_strided<true>, grid, block, 0, 0, in, out, ntiles); }, reps);
+        std::printf("working set %7.1f MiB (2^%d u32 in + out): plain %8.1f GB/s  nontemporal %8.1f GB/s\n",
+                    2.0 * n * 4 / 1048576.0, lg, 2.0 * n * 4 / (plain * 1e-3) / 1e9, 2.0 * n * 4 / (nt * 1e-3) / 1e9);
+        CHECK(hipFree(in));
+        CHECK(hipFree(out));
+    }
+    (void)cus;
+}
+
 void copy_variants(int cus)
 {
+    copy_working_set(cus);
     for (int lg : {26, 28}) {
         const size_t n = (size_t)1 << lg, ntiles = n / 4096;
         uint32_t *in, *out;
