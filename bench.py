@@ -217,6 +217,36 @@ def main():
         e1.synchronize()
         per_dist[d] = round(e0.elapsed_time(e1) / reps, 4)
 
+    # the same sorts replayed from a captured graph (one graph per distribution)
+    graph_ms = {}
+    try:
+        ws.get(1, dev)  # scratch allocated before capture
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            for d in dists:
+                bcf.sort_u32(src[d], out=out, stream=side, workspace=ws)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graphs = {}
+        for d in dists:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                bcf.sort_u32(src[d], out=out, workspace=ws)
+            graphs[d] = g
+        for d in dists:
+            graphs[d].replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            graphs[dists[i % len(dists)]].replay()
+        torch.cuda.synchronize()
+        graph_ms = {"ms_per_step": round((time.perf_counter() - t0) * 1e3 / args.steps, 4)}
+        graph_ms["value_gkeys_per_s"] = round(n / graph_ms["ms_per_step"] / 1e6, 4)
+        del graphs
+    except Exception as e:  # reported, never fatal for the headline
+        graph_ms = {"error": repr(e)[:200]}
+
     # roofline of the dominant kernel: per-launch HIP events around each launch
     bcf.profile_collect()
     bcf.profile_enable(True)
@@ -256,6 +286,7 @@ def main():
             "passes_per_sort": bcf.sort_passes(n),
         },
         "per_distribution_ms": per_dist,
+        "graph_replay": graph_ms,
         "roofline": {
             "kernel": dominant,
             "bound": "hbm",
