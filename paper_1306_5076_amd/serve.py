@@ -5,9 +5,10 @@ stably by key) from any thread.  A scheduler thread
 
 * admits waiting requests in arrival order while their device bytes fit the
   HBM budget (a request larger than the whole budget is rejected);
-* packs every admitted request of one kind into a single batch and sorts the
-  batch with ONE segmented launch sequence (``bcf_segmented_sort`` /
-  ``bcf_segmented_sort_pairs``): each request is a segment;
+* packs every admitted request into one batch, keys-only requests first and
+  key/value requests after them, and sorts the batch with at most two
+  segmented launch sequences (``bcf_segmented_sort`` for the keys-only part,
+  ``bcf_segmented_sort_pairs`` for the rest): each request is a segment;
 * runs batches as a three-stage pipeline on separate streams (host-to-device
   copy, sort, device-to-host copy), so a batch's copies overlap the previous
   batch's kernels, and requests that arrive meanwhile join the next batch;
@@ -24,6 +25,7 @@ copy out, synchronised.
 from __future__ import annotations
 
 import collections
+import contextlib
 import threading
 import time
 from concurrent.futures import Future
@@ -86,7 +88,7 @@ class _Slot:
         self.ws = api.Workspace(device)
         self.done = None
         self.reqs = []
-        self.offs = None
+        self.loc = []       # per request: (key lo, key hi, value lo) in the batch buffers
 
 
 class SortServer:
@@ -110,6 +112,7 @@ class SortServer:
         self.batch_sizes = []
         self.cv = threading.Condition()
         self.stop = False
+        self.holds = 0
         self.error = None
         self.thread = threading.Thread(target=self._run, name="bcf-sort-server", daemon=True)
         self.thread.start()
@@ -130,6 +133,19 @@ class SortServer:
             self.pending.append(r)
             self.cv.notify()
         return r.future
+
+    @contextlib.contextmanager
+    def held(self):
+        """Admit nothing new while inside the block (requests still queue up);
+        on exit everything that queued meanwhile is admitted together."""
+        with self.cv:
+            self.holds += 1
+        try:
+            yield self
+        finally:
+            with self.cv:
+                self.holds -= 1
+                self.cv.notify()
 
     def close(self):
         with self.cv:
@@ -152,7 +168,7 @@ class SortServer:
             torch.cuda.set_device(self.device)
             while True:
                 with self.cv:
-                    while not self.stop and not self.pending and not self.busy:
+                    while not self.stop and not self.busy and (not self.pending or self.holds):
                         self.cv.wait()
                     if self.stop and not self.pending and not self.busy:
                         return
@@ -171,32 +187,28 @@ class SortServer:
         while self.busy and self.busy[0].done.query():
             slot = self.busy.popleft()
             now = time.perf_counter()
-            offs = slot.offs
-            for i, r in enumerate(slot.reqs):
-                lo, hi = int(offs[i]), int(offs[i + 1])
-                k = slot.ok.t[lo:hi].numpy().copy()
-                v = slot.ov.t[lo:hi].numpy().copy() if r.pairs else None
+            ok, ov = slot.ok.t, slot.ov.t
+            for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
+                k = ok[lo:hi].numpy().copy()
+                v = ov[vlo:vlo + (hi - lo)].numpy().copy() if r.pairs else None
                 r.finished = now
                 r.future._bcf_finished = now
                 r.future.set_result((k, v) if r.pairs else k)
                 self.used -= r.device_bytes()
-            slot.reqs = []
+            slot.reqs, slot.loc = [], []
             self.free_slots.append(slot)
 
     def _admit_and_launch(self) -> bool:
         if not self.free_slots:
             return False
         with self.cv:
-            if not self.pending:
-                return False
-            kind = self.pending[0].pairs
             batch, keys = [], 0
-            while self.pending and self.pending[0].pairs == kind:
+            while self.pending and (not self.holds or self.stop):
                 r = self.pending[0]
                 if batch and keys + r.n > self.max_batch_keys:
                     break
                 if self.used + r.device_bytes() > self.budget:
-                    break  # admission by free-HBM budget: wait for completions
+                    break  # admission by free-HBM budget, in arrival order: wait for completions
                 self.pending.popleft()
                 batch.append(r)
                 keys += r.n
@@ -205,49 +217,59 @@ class SortServer:
                 return False
         self.peak_used = max(self.peak_used, self.used)
         slot = self.free_slots.popleft()
-        self._launch(slot, batch, kind)
+        self._launch(slot, batch)
         self.busy.append(slot)
         self.batches += 1
         self.batch_sizes.append(len(batch))
         return True
 
-    def _launch(self, slot: _Slot, batch, pairs: bool):
-        sizes = [r.n for r in batch]
-        offs = np.zeros(len(batch) + 1, dtype=np.uint64)
-        offs[1:] = np.cumsum(sizes)
-        n = int(offs[-1])
-        slot.reqs, slot.offs = batch, offs
+    def _launch(self, slot: _Slot, batch):
+        # keys-only requests occupy [0, nk) of the batch's key buffers, key/value
+        # requests [nk, n); values only exist for the second part
+        parts = [[r for r in batch if not r.pairs], [r for r in batch if r.pairs]]
+        offs = []
+        for part in parts:
+            o = np.zeros(len(part) + 1, dtype=np.uint64)
+            o[1:] = np.cumsum([r.n for r in part])
+            offs.append(o)
+        nk, npairs = int(offs[0][-1]), int(offs[1][-1])
+        n = nk + npairs
+        slot.reqs, slot.loc = parts[0] + parts[1], []
+        for i, r in enumerate(parts[0]):
+            slot.loc.append((int(offs[0][i]), int(offs[0][i + 1]), 0))
+        for i, r in enumerate(parts[1]):
+            slot.loc.append((nk + int(offs[1][i]), nk + int(offs[1][i + 1]), int(offs[1][i])))
         hk = slot.hk.get(n)
         hkn = hk.numpy()
-        for i, r in enumerate(batch):
-            hkn[int(offs[i]):int(offs[i + 1])] = r.keys
+        for r, (lo, hi, _) in zip(slot.reqs, slot.loc):
+            hkn[lo:hi] = r.keys
         dk, rk = slot.dk.get(n), slot.rk.get(n)
-        if pairs:
-            hv = slot.hv.get(n)
-            hvn = hv.numpy()
-            for i, r in enumerate(batch):
-                hvn[int(offs[i]):int(offs[i + 1])] = r.vals
-            dv, rv = slot.dv.get(n), slot.rv.get(n)
+        hv = slot.hv.get(npairs)
+        hvn = hv.numpy()
+        for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
+            if r.pairs:
+                hvn[vlo:vlo + (hi - lo)] = r.vals
+        dv, rv = slot.dv.get(npairs), slot.rv.get(npairs)
         # stage 1: host -> device
         with torch.cuda.stream(self.h2d):
             dk.copy_(hk, non_blocking=True)
-            if pairs:
+            if npairs:
                 dv.copy_(hv, non_blocking=True)
-        # stage 2: one segmented sort over the whole batch
+        # stage 2: one segmented sort per part of the batch
         self.compute.wait_stream(self.h2d)
         with torch.cuda.stream(self.compute):
-            if pairs:
-                api.segmented_sort(dk, offs, vals=dv, keys_out=rk, vals_out=rv, stream=self.compute,
-                                   workspace=slot.ws)
-            else:
-                api.segmented_sort(dk, offs, keys_out=rk, stream=self.compute, workspace=slot.ws)
+            if nk:
+                api.segmented_sort(dk[:nk], offs[0], keys_out=rk[:nk], stream=self.compute, workspace=slot.ws)
+            if npairs:
+                api.segmented_sort(dk[nk:], offs[1], vals=dv, keys_out=rk[nk:], vals_out=rv,
+                                   stream=self.compute, workspace=slot.ws)
         # stage 3: device -> host
         self.d2h.wait_stream(self.compute)
-        ok = slot.ok.get(n)
+        ok, ov = slot.ok.get(n), slot.ov.get(npairs)
         with torch.cuda.stream(self.d2h):
             ok.copy_(rk, non_blocking=True)
-            if pairs:
-                slot.ov.get(n).copy_(rv, non_blocking=True)
+            if npairs:
+                ov.copy_(rv, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.d2h)
         slot.done = ev

@@ -36,10 +36,11 @@ def test_mix_equals_alone(serve):
     reqs = _requests(40, seed=3)
     alone, _, _ = serve.serve_serial(reqs, realtime=False)
     with serve.SortServer(hbm_budget=1 << 30) as srv:
-        futs = [srv.submit(k, v) for _, k, v in reqs]
+        with srv.held():  # everything queues first, then is admitted as one mixed batch
+            futs = [srv.submit(k, v) for _, k, v in reqs]
         mixed = [f.result(timeout=120) for f in futs]
         batches = srv.batches
-    assert batches < len(reqs)  # requests were batched
+    assert batches == 1
     for (_, k, v), a, m in zip(reqs, alone, mixed):
         if v is None:
             assert np.array_equal(a, m)
