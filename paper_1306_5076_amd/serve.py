@@ -62,14 +62,16 @@ class _Request:
 
 
 class _Grow:
-    """A tensor that grows on demand and is reused (device or pinned host)."""
+    """A tensor that grows on demand (to the next power of two) and is reused,
+    on the device or in pinned host memory."""
 
     def __init__(self, device=None, pinned=False):
         self.device, self.pinned, self.t = device, pinned, None
 
     def get(self, n: int):
         if self.t is None or self.t.numel() < n:
-            cap = max(n, 1 << 16)
+            cap = 1 << max(16, (max(n, 1) - 1).bit_length())
+            self.t = None  # release the old buffer before taking the new one
             if self.pinned:
                 self.t = torch.empty(cap, dtype=torch.uint32, pin_memory=True)
             else:
@@ -80,11 +82,13 @@ class _Grow:
 class _Slot:
     """Resident buffers of one in-flight batch."""
 
-    def __init__(self, device):
+    def __init__(self, device, reserve_keys: int = 0):
         self.hk, self.hv = _Grow(pinned=True), _Grow(pinned=True)      # host in
         self.ok, self.ov = _Grow(pinned=True), _Grow(pinned=True)      # host out
         self.dk, self.dv = _Grow(device), _Grow(device)                # device in
         self.rk, self.rv = _Grow(device), _Grow(device)                # device out
+        for g in (self.hk, self.hv, self.ok, self.ov, self.dk, self.dv, self.rk, self.rv):
+            g.get(reserve_keys)
         self.ws = api.Workspace(device)
         self.done = None
         self.reqs = []
@@ -94,15 +98,15 @@ class _Slot:
 class SortServer:
     """Continuous-batching sort server (see module docstring)."""
 
-    def __init__(self, device="cuda:0", hbm_budget: int = 16 << 30, max_batch_keys: int = 1 << 26,
-                 slots: int = 3):
+    def __init__(self, device="cuda:0", hbm_budget: int = 16 << 30, max_batch_keys: int = 1 << 24,
+                 slots: int = 3, reserve_keys: int = 0):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
         self.max_batch_keys = int(max_batch_keys)
         self.h2d = torch.cuda.Stream(self.device)
         self.compute = torch.cuda.Stream(self.device)
         self.d2h = torch.cuda.Stream(self.device)
-        self.slots = [_Slot(self.device) for _ in range(slots)]
+        self.slots = [_Slot(self.device, reserve_keys) for _ in range(slots)]
         self.free_slots = collections.deque(self.slots)
         self.busy = collections.deque()
         self.pending = collections.deque()
@@ -147,6 +151,11 @@ class SortServer:
                 self.holds -= 1
                 self.cv.notify()
 
+    def reset_stats(self):
+        """Zero the batch counters and the peak of admitted device bytes."""
+        with self.cv:
+            self.batches, self.batch_sizes, self.peak_used = 0, [], self.used
+
     def close(self):
         with self.cv:
             self.stop = True
@@ -189,8 +198,8 @@ class SortServer:
             now = time.perf_counter()
             ok, ov = slot.ok.t, slot.ov.t
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
-                k = ok[lo:hi].numpy().copy()
-                v = ov[vlo:vlo + (hi - lo)].numpy().copy() if r.pairs else None
+                k = ok[lo:hi].clone().numpy()
+                v = ov[vlo:vlo + (hi - lo)].clone().numpy() if r.pairs else None
                 r.finished = now
                 r.future._bcf_finished = now
                 r.future.set_result((k, v) if r.pairs else k)
@@ -239,16 +248,13 @@ class SortServer:
             slot.loc.append((int(offs[0][i]), int(offs[0][i + 1]), 0))
         for i, r in enumerate(parts[1]):
             slot.loc.append((nk + int(offs[1][i]), nk + int(offs[1][i + 1]), int(offs[1][i])))
-        hk = slot.hk.get(n)
-        hkn = hk.numpy()
-        for r, (lo, hi, _) in zip(slot.reqs, slot.loc):
-            hkn[lo:hi] = r.keys
-        dk, rk = slot.dk.get(n), slot.rk.get(n)
-        hv = slot.hv.get(npairs)
-        hvn = hv.numpy()
+        # pack into the slot's pinned buffers (torch copies: multi-threaded, GIL released)
+        hk, hv = slot.hk.get(n), slot.hv.get(npairs)
         for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
+            hk[lo:hi].copy_(torch.from_numpy(r.keys))
             if r.pairs:
-                hvn[vlo:vlo + (hi - lo)] = r.vals
+                hv[vlo:vlo + (hi - lo)].copy_(torch.from_numpy(r.vals))
+        dk, rk = slot.dk.get(n), slot.rk.get(n)
         dv, rv = slot.dv.get(npairs), slot.rv.get(npairs)
         # stage 1: host -> device
         with torch.cuda.stream(self.h2d):
@@ -279,39 +285,50 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True):
     """Baseline: each request alone (copy in, sort, copy out, synchronise), FIFO.
 
     ``requests`` is a list of ``(arrival_offset_s, keys, vals_or_None)``; with
-    ``realtime`` a request is not started before its arrival time.  Returns
+    ``realtime`` a request is not started before its arrival time.  Host
+    staging is pinned and resident, as in :class:`SortServer`.  Returns
     ``(results, latencies_s, wall_s)``.
     """
     dev = torch.device(device)
     ws = api.Workspace(dev)
-    hk, hv = _Grow(pinned=True), _Grow(pinned=True)
-    dk, dv, rk, rv = _Grow(dev), _Grow(dev), _Grow(dev), _Grow(dev)
+    hk, hv, ok, ov = (_Grow(pinned=True) for _ in range(4))
+    dk, dv, rk, rv = (_Grow(dev) for _ in range(4))
     out, lat = [], []
     t0 = time.perf_counter()
     for arr, keys, vals in requests:
         if realtime:
-            while time.perf_counter() - t0 < arr:
-                pass
+            _wait_until(t0 + arr)
         arrival = t0 + arr if realtime else time.perf_counter()
         n = keys.size
-        hkn = hk.get(n)
-        hkn.numpy()[:] = keys
-        dkk, rkk = dk.get(n), rk.get(n)
-        dkk.copy_(hkn, non_blocking=True)
+        hkk, dkk, rkk, okk = hk.get(n), dk.get(n), rk.get(n), ok.get(n)
+        hkk.copy_(torch.from_numpy(keys))
+        dkk.copy_(hkk, non_blocking=True)
         if vals is not None:
-            hvn = hv.get(n)
-            hvn.numpy()[:] = vals
-            dvv, rvv = dv.get(n), rv.get(n)
-            dvv.copy_(hvn, non_blocking=True)
+            hvv, dvv, rvv, ovv = hv.get(n), dv.get(n), rv.get(n), ov.get(n)
+            hvv.copy_(torch.from_numpy(vals))
+            dvv.copy_(hvv, non_blocking=True)
             api.sort_pairs_u32(dkk, dvv, rkk, rvv, workspace=ws)
-            res = (rkk.cpu().numpy(), rvv.cpu().numpy())
+            okk.copy_(rkk, non_blocking=True)
+            ovv.copy_(rvv, non_blocking=True)
         else:
             api.sort_u32(dkk, out=rkk, workspace=ws)
-            res = rkk.cpu().numpy()
+            okk.copy_(rkk, non_blocking=True)
         torch.cuda.synchronize(dev)
+        res = (okk.clone().numpy(), ovv.clone().numpy()) if vals is not None else okk.clone().numpy()
         lat.append(time.perf_counter() - arrival)
         out.append(res)
     return out, lat, time.perf_counter() - t0
+
+
+def _wait_until(at: float):
+    """Sleep, then spin for the last half millisecond (a spinning thread holds
+    the GIL, so long waits must sleep to let the scheduler thread run)."""
+    while True:
+        left = at - time.perf_counter()
+        if left <= 0:
+            return
+        if left > 1e-3:
+            time.sleep(left - 5e-4)
 
 
 def latency_stats(lat_s):
@@ -342,52 +359,57 @@ def make_requests(count: int, lo: int = 1 << 10, hi: int = 1 << 24, seed: int = 
     return reqs
 
 
-def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 << 30):
+def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 << 30, server=None):
     """Submit ``requests`` at their arrival times (scaled to ``qps``) to a
-    :class:`SortServer`; returns (results, latencies_s, wall_s, server stats)."""
-    server = SortServer(device, hbm_budget=hbm_budget)
+    :class:`SortServer` (``server``, else a new one); returns
+    (results, latencies_s, wall_s, server stats)."""
+    own = server is None
+    if own:
+        server = SortServer(device, hbm_budget=hbm_budget)
+    server.reset_stats()
     futs, arrivals = [], []
     t0 = time.perf_counter()
     for t, keys, vals in requests:
         at = t0 + t / qps
-        while time.perf_counter() < at:
-            pass
+        _wait_until(at)
         arrivals.append(at)
         futs.append(server.submit(keys, vals, arrival=at))
     results = [f.result() for f in futs]
     wall = time.perf_counter() - t0
-    server.close()
-    lat = []
-    for f, a in zip(futs, arrivals):
-        lat.append(f._bcf_finished - a if hasattr(f, "_bcf_finished") else 0.0)
     stats = {"batches": server.batches, "mean_batch": round(float(np.mean(server.batch_sizes)), 2),
-             "peak_hbm_bytes": server.peak_used, "hbm_budget": hbm_budget}
+             "peak_hbm_bytes": server.peak_used, "hbm_budget": server.budget,
+             "max_batch_keys": server.max_batch_keys}
+    if own:
+        server.close()
+    lat = [f._bcf_finished - a for f, a in zip(futs, arrivals)]
     return results, lat, wall, stats
 
 
 def run_serving_benchmark(count: int = 300, fracs=(0.5, 0.8, 0.95), seed: int = 1, device="cuda:0",
-                          hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24):
+                          hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24,
+                          max_batch_keys: int = 1 << 24):
     """p50/p99 latency and Gkeys/s of the batched server and of the serial
     baseline at fractions of the baseline's saturation request rate."""
     reqs = make_requests(count, lo=lo, hi=hi, seed=seed)
     total_keys = sum(k.size for _, k, _ in reqs)
-    # warm up both paths (library load, allocations)
-    serve_serial(reqs[:4], device, realtime=False)
-    serve_batched(reqs[:4], qps=1e9, device=device, hbm_budget=hbm_budget)
-    _, _, sat_wall = serve_serial(reqs, device, realtime=False)
-    sat_qps = count / sat_wall
     out = {"requests": count, "total_keys": int(total_keys), "sizes": [lo, hi], "pairs_fraction": 0.5,
-           "hbm_budget_bytes": hbm_budget, "serial_saturation_qps": round(sat_qps, 2), "runs": []}
-    base_t = [t for t, _, _ in reqs]
-    for frac in fracs:
-        qps = frac * sat_qps
-        timed = [(t / qps, k, v) for t, k, v in reqs]
-        _, slat, swall = serve_serial(timed, device, realtime=True)
-        _, blat, bwall, bst = serve_batched(reqs, qps=qps, device=device, hbm_budget=hbm_budget)
-        out["runs"].append({
-            "qps": round(qps, 2), "frac_of_serial_saturation": frac,
-            "serial": {**latency_stats(slat), "gkeys_per_s": round(total_keys / swall / 1e9, 4)},
-            "batched": {**latency_stats(blat), "gkeys_per_s": round(total_keys / bwall / 1e9, 4), **bst},
-        })
-    del base_t
+           "hbm_budget_bytes": hbm_budget, "runs": []}
+    with SortServer(device, hbm_budget=hbm_budget, max_batch_keys=max_batch_keys,
+                    reserve_keys=min(max(hi, max_batch_keys), total_keys)) as server:
+        # warm up both paths over the whole request set (library load, buffer growth)
+        _, _, sat_wall = serve_serial(reqs, device, realtime=False)
+        serve_batched(reqs, qps=1e9, server=server)
+        _, _, sat_wall = serve_serial(reqs, device, realtime=False)
+        sat_qps = count / sat_wall
+        out["serial_saturation_qps"] = round(sat_qps, 2)
+        for frac in fracs:
+            qps = frac * sat_qps
+            timed = [(t / qps, k, v) for t, k, v in reqs]
+            _, slat, swall = serve_serial(timed, device, realtime=True)
+            _, blat, bwall, bst = serve_batched(reqs, qps=qps, server=server)
+            out["runs"].append({
+                "qps": round(qps, 2), "frac_of_serial_saturation": frac,
+                "serial": {**latency_stats(slat), "gkeys_per_s": round(total_keys / swall / 1e9, 4)},
+                "batched": {**latency_stats(blat), "gkeys_per_s": round(total_keys / bwall / 1e9, 4), **bst},
+            })
     return out
