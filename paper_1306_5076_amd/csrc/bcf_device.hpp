@@ -37,15 +37,36 @@ constexpr int kLdsWords = kWave * kLdsStride;
 constexpr uint32_t kMaxKey = 0xFFFFFFFFu;
 constexpr uint32_t kPadIdx = 0xFFFFFFFFu;
 
-// A wave's tile in registers.  For key/value pairs every element also carries
-// a tie-break rank `i` (its position in the input order of the tile) and its
-// value `v`; elements compare by (k, i), which makes every network stable.
+// A wave's tile in registers.  Keys only: one 32-bit key per position.  Key/
+// value pairs: one 64-bit element per position, the key in the high half and
+// a tie-break rank in the low half (the element's position in the input
+// order of the tile), so elements compare as 64-bit integers by (key, rank),
+// which makes every network stable.  Values do not travel through the
+// networks: after the last network the rank names the input position whose
+// value goes with the key, and the value is fetched by it (from LDS in the
+// block sort, from global memory in a merge).
 template <bool PAIRS>
 struct Lines {
     uint32_t k[kLine];
-    uint32_t i[PAIRS ? kLine : 1];
-    uint32_t v[PAIRS ? kLine : 1];
 };
+template <>
+struct Lines<true> {
+    uint64_t e[kLine];
+};
+
+template <bool P>
+__device__ __forceinline__ uint32_t key_of(const Lines<P> &t, int r)
+{
+    if constexpr (P)
+        return (uint32_t)(t.e[r] >> 32);
+    else
+        return t.k[r];
+}
+
+__device__ __forceinline__ uint64_t make_elem(uint32_t key, uint32_t rank)
+{
+    return ((uint64_t)key << 32) | rank;
+}
 
 // ---------------------------------------------------------------- comparators
 
@@ -58,20 +79,15 @@ __device__ __forceinline__ void cx(Lines<P> &t, int a, int b)
         t.k[a] = min(x, y);
         t.k[b] = max(x, y);
     } else {
-        const uint32_t ka = t.k[a], kb = t.k[b], ia = t.i[a], ib = t.i[b];
-        const uint32_t va = t.v[a], vb = t.v[b];
-        const bool sw = (ka > kb) || ((ka == kb) && (ia > ib));
-        t.k[a] = sw ? kb : ka;
-        t.k[b] = sw ? ka : kb;
-        t.i[a] = sw ? ib : ia;
-        t.i[b] = sw ? ia : ib;
-        t.v[a] = sw ? vb : va;
-        t.v[b] = sw ? va : vb;
+        const uint64_t x = t.e[a], y = t.e[b];
+        const bool sw = x > y;
+        t.e[a] = sw ? y : x;
+        t.e[b] = sw ? x : y;
     }
 }
 
-// Reverse the order of every element of a lane when `bit` is 1: (k, i) is
-// replaced by its bitwise complement, an order-reversing bijection, so an
+// Reverse the order of every element of a lane when `bit` is 1: the element
+// is replaced by its bitwise complement, an order-reversing bijection, so an
 // ascending network run on complemented data sorts descending.  Used where
 // the direction of a merge depends on the lane (BLOCKED layout).
 template <bool P>
@@ -80,9 +96,10 @@ __device__ __forceinline__ void flip(Lines<P> &t, uint32_t bit)
     const uint32_t m = 0u - (bit & 1u);
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
-        t.k[r] ^= m;
         if constexpr (P)
-            t.i[r] ^= m;
+            t.e[r] ^= make_elem(m, m);
+        else
+            t.k[r] ^= m;
     }
 }
 
@@ -175,26 +192,53 @@ __device__ __forceinline__ void exchange(uint32_t (&x)[kLine], uint32_t *lds, ui
     wave_lds_fence();
 }
 
+// The same for 64-bit elements, one 32-bit half at a time (each half keeps the
+// conflict-free word pattern of the 32-bit exchange).
+template <int WS, int RS>
+__device__ __forceinline__ void exchange(uint64_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
+                                         uint32_t rbase)
+{
+    uint32_t *w = lds + wbase;
+    const uint32_t *rd = lds + rbase;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        w[WS * r] = (uint32_t)(x[r] >> 32);
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = ((uint64_t)rd[RS * r] << 32) | (uint32_t)x[r];
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        w[WS * r] = (uint32_t)x[r];
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = (x[r] & 0xFFFFFFFF00000000ull) | rd[RS * r];
+    wave_lds_fence();
+}
+
+template <bool P>
+__device__ __forceinline__ auto &elems(Lines<P> &t)
+{
+    if constexpr (P)
+        return t.e;
+    else
+        return t.k;
+}
+
 // STRIDED -> BLOCKED: write word 65r + lane, read word 65 lane + r.
 template <bool P>
 __device__ __forceinline__ void to_blocked(Lines<P> &t, uint32_t *lds, uint32_t lane)
 {
-    exchange<kLdsStride, 1>(t.k, lds, lane, kLdsStride * lane);
-    if constexpr (P) {
-        exchange<kLdsStride, 1>(t.i, lds, lane, kLdsStride * lane);
-        exchange<kLdsStride, 1>(t.v, lds, lane, kLdsStride * lane);
-    }
+    exchange<kLdsStride, 1>(elems(t), lds, lane, kLdsStride * lane);
 }
 
 // BLOCKED -> STRIDED: write word 65 lane + r, read word 65r + lane.
 template <bool P>
 __device__ __forceinline__ void to_strided(Lines<P> &t, uint32_t *lds, uint32_t lane)
 {
-    exchange<1, kLdsStride>(t.k, lds, kLdsStride * lane, lane);
-    if constexpr (P) {
-        exchange<1, kLdsStride>(t.i, lds, kLdsStride * lane, lane);
-        exchange<1, kLdsStride>(t.v, lds, kLdsStride * lane, lane);
-    }
+    exchange<1, kLdsStride>(elems(t), lds, kLdsStride * lane, lane);
 }
 
 // ---------------------------------------------------------------- wave utils

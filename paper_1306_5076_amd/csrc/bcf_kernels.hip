@@ -49,24 +49,23 @@ __device__ __forceinline__ void st(uint32_t *p, uint32_t v)
         *p = v;
 }
 
-// Load `count` elements starting at `src` into STRIDED layout (position
+// Load `count` keys starting at `ksrc` into STRIDED layout (position
 // p = 64r + lane); positions >= count become padding (max key, max rank).
-// For pairs the tie-break rank is the position in the input order.
+// For pairs the element's rank is rank0 + p, its position in the input order;
+// values are not loaded here (see permute_values_lds / gather_values).
 template <bool P>
-__device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restrict__ ksrc,
-                                          const uint32_t *__restrict__ vsrc, uint32_t count,
+__device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restrict__ ksrc, uint32_t count,
                                           uint32_t lane, uint32_t rank0 = 0)
 {
     const uint32_t *kp = ksrc + lane;
-    const uint32_t *vp = P ? vsrc + lane : nullptr;
     if (count >= (uint32_t)kTile) {
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
-            t.k[r] = kp[kWave * r];
-            if constexpr (P) {
-                t.i[r] = rank0 + kWave * r + lane;
-                t.v[r] = vp[kWave * r];
-            }
+            const uint32_t key = kp[kWave * r];
+            if constexpr (P)
+                t.e[r] = make_elem(key, rank0 + kWave * r + lane);
+            else
+                t.k[r] = key;
         }
     } else {
         const uint32_t last = count ? count - 1 : 0;
@@ -75,16 +74,16 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
             const uint32_t p = kWave * r + lane;
             const uint32_t q = p < count ? p : last;  // clamped: always a valid address
             const uint32_t key = count ? ksrc[q] : kMaxKey;
-            t.k[r] = p < count ? key : kMaxKey;
-            if constexpr (P) {
-                t.i[r] = p < count ? rank0 + p : kPadIdx;
-                t.v[r] = count ? vsrc[q] : 0u;
-            }
+            if constexpr (P)
+                t.e[r] = p < count ? make_elem(key, rank0 + p) : make_elem(kMaxKey, kPadIdx);
+            else
+                t.k[r] = p < count ? key : kMaxKey;
         }
     }
 }
 
-// Store the first `count` positions of a STRIDED tile.
+// Store the first `count` positions of a STRIDED tile.  For pairs the low
+// half of each element holds the value by now (after the value step).
 template <bool P, bool NT = false>
 __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restrict__ kdst,
                                            uint32_t *__restrict__ vdst, uint32_t count, uint32_t lane)
@@ -94,20 +93,48 @@ __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restri
     if (count >= (uint32_t)kTile) {
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
-            st<NT>(kp + kWave * r, t.k[r]);
+            st<NT>(kp + kWave * r, key_of(t, r));
             if constexpr (P)
-                st<NT>(vp + kWave * r, t.v[r]);
+                st<NT>(vp + kWave * r, (uint32_t)t.e[r]);
         }
     } else {
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
             if (kWave * r + lane < count) {
-                st<NT>(kp + kWave * r, t.k[r]);
+                st<NT>(kp + kWave * r, key_of(t, r));
                 if constexpr (P)
-                    st<NT>(vp + kWave * r, t.v[r]);
+                    st<NT>(vp + kWave * r, (uint32_t)t.e[r]);
             }
         }
     }
+}
+
+// Value step of a block sort (pairs): the tile is sorted, in STRIDED layout,
+// and every element's low half is the rank of its input position in
+// [0, count).  The values of those `count` input positions are staged in LDS
+// (`vals`, coalesced global reads, conflict-free consecutive LDS words) and
+// each element's rank is replaced by its value, read from LDS.  Callers
+// separate this from other LDS use by the fence or barrier `sync`.
+template <class Sync>
+__device__ __forceinline__ void permute_values_lds(Lines<true> &t, const uint32_t *__restrict__ vsrc,
+                                                   uint32_t count, uint32_t *vals, uint32_t stage_off,
+                                                   uint32_t stage_count, uint32_t lane, const Sync &sync)
+{
+    // stage input positions [stage_off, stage_off + stage_count) of this wave
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t p = kWave * r + lane;
+        if (p < stage_count)
+            vals[stage_off + p] = vsrc[stage_off + p];
+    }
+    sync();
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t rank = (uint32_t)t.e[r];
+        const uint32_t v = rank < count ? vals[rank] : 0u;
+        t.e[r] = (t.e[r] & 0xFFFFFFFF00000000ull) | v;
+    }
+    sync();
 }
 
 // ----------------------------------------------------------- block sort body
@@ -190,16 +217,37 @@ __device__ __forceinline__ void group_exchange(uint32_t (&x)[kLine], uint32_t *l
     __syncthreads();
 }
 
+// The same for 64-bit elements, one 32-bit half at a time.
+template <int WS, int RS>
+__device__ __forceinline__ void group_exchange(uint64_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
+                                               uint32_t rbase)
+{
+    uint32_t *w = lds + wbase;
+    const uint32_t *rd = lds + rbase;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        w[WS * r] = (uint32_t)(x[r] >> 32);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = ((uint64_t)rd[RS * r] << 32) | (uint32_t)x[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        w[WS * r] = (uint32_t)x[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = (x[r] & 0xFFFFFFFF00000000ull) | rd[RS * r];
+    __syncthreads();
+}
+
 // BLOCKED p = 4096w + 64 lane + r  ->  CROSS p = lane + 64w + 64*NW*r
 template <int NW, bool P>
 __device__ __forceinline__ void blocked_to_cross(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
 {
     const uint32_t wb = kLdsStride * (kWave * wave + lane), rb = kLdsStride * wave + lane;
-    group_exchange<1, kLdsStride * NW>(t.k, lds, wb, rb);
-    if constexpr (P) {
-        group_exchange<1, kLdsStride * NW>(t.i, lds, wb, rb);
-        group_exchange<1, kLdsStride * NW>(t.v, lds, wb, rb);
-    }
+    group_exchange<1, kLdsStride * NW>(elems(t), lds, wb, rb);
 }
 
 // CROSS p = lane + 64w + 64*NW*r  ->  STRIDED p = 4096w + 64r + lane
@@ -207,11 +255,7 @@ template <int NW, bool P>
 __device__ __forceinline__ void cross_to_strided(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
 {
     const uint32_t wb = kLdsStride * wave + lane, rb = kLdsStride * kWave * wave + lane;
-    group_exchange<kLdsStride * NW, kLdsStride>(t.k, lds, wb, rb);
-    if constexpr (P) {
-        group_exchange<kLdsStride * NW, kLdsStride>(t.i, lds, wb, rb);
-        group_exchange<kLdsStride * NW, kLdsStride>(t.v, lds, wb, rb);
-    }
+    group_exchange<kLdsStride * NW, kLdsStride>(elems(t), lds, wb, rb);
 }
 
 constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
@@ -260,7 +304,8 @@ struct MergeTask {
 
 // Load a merge work item as one bitonic STRIDED tile: A goes to positions
 // [0, pa) ascending, B to positions [kTile - pb, kTile) reversed, padding in
-// between.  Ranks follow the order A then B so that equal keys leave A first.
+// between.  For pairs the rank of A[j] is j and that of B[j] is pa + j, so
+// equal keys leave A first and the rank also names the element's source.
 // Every lane computes a 32-bit element offset from the A-piece (the B-piece
 // lies dB elements after it in the same array) and issues one unconditional
 // load per register row, so all 64 loads of a tile are in flight together;
@@ -279,11 +324,30 @@ __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, u
         const bool in_b = p >= bstart;
         const uint32_t off = in_a ? p : (in_b ? bend - p : 0u);
         const uint32_t key = ld<NT>(m.ka + off);
-        t.k[r] = (in_a || in_b) ? key : kMaxKey;
-        if constexpr (P) {
-            t.v[r] = ld<NT>(m.va + off);
-            t.i[r] = in_a ? p : (in_b ? na + (kTile - 1 - p) : kPadIdx);
-        }
+        if constexpr (P)
+            t.e[r] = (in_a || in_b) ? make_elem(key, in_a ? p : na + (kTile - 1 - p)) : make_elem(kMaxKey, kPadIdx);
+        else
+            t.k[r] = (in_a || in_b) ? key : kMaxKey;
+    }
+}
+
+// Value step of a merge (pairs): the merged tile is in STRIDED layout and the
+// low half of each of its first `count` elements is a rank r (r < pa: A[r],
+// else B[r - pa]).  Replace it by that element's value.  The 64 outputs of a
+// register row come from one contiguous stretch of A and one of B, so each
+// gather touches few cache lines.
+template <bool NT = false>
+__device__ __forceinline__ void gather_values(Lines<true> &t, const MergeTask<true> &m, uint32_t lane)
+{
+    const uint32_t na = m.pa;
+    const uint32_t dBm = (uint32_t)(m.vb - m.va) - na;  // offset of B[r - pa] is r + dBm
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t p = kWave * r + lane;
+        const uint32_t rank = (uint32_t)t.e[r];
+        const uint32_t off = p < m.count ? (rank < na ? rank : rank + dBm) : 0u;
+        const uint32_t v = ld<NT>(m.va + off);
+        t.e[r] = (t.e[r] & 0xFFFFFFFF00000000ull) | v;
     }
 }
 
@@ -318,16 +382,16 @@ __device__ __forceinline__ void write_samples(const Lines<P> &t, const SampleSet
         return;
     const uint64_t b = gpos / kLine + lane;
     if (lane * kLine < count) {
-        s.f[b] = t.k[0];
-        s.l[b] = t.k[kLine - 1];
+        s.f[b] = key_of(t, 0);
+        s.l[b] = key_of(t, kLine - 1);
     }
     if (s.cf == nullptr)
         return;
     const uint64_t c = gpos / kTile;
     if (lane == 0)
-        s.cf[c] = t.k[0];
+        s.cf[c] = key_of(t, 0);
     if (lane == kWave - 1)
-        s.cl[c] = t.k[kLine - 1];
+        s.cl[c] = key_of(t, kLine - 1);
 }
 
 // ----------------------------------------------------------- work sources
@@ -474,8 +538,9 @@ __device__ __forceinline__ MergeTask<P> merge_task(const Src &src, const uint32_
 // The sort and merge kernels are persistent: wave g of G handles tiles
 // g, g + G, g + 2G, ...  For keys, the loads of the next tile are issued
 // before the current tile is sorted/merged, so a wave's memory traffic
-// overlaps its own arithmetic (two tiles of registers are live; for pairs,
-// three arrays per tile would not fit, so pairs process one tile at a time).
+// overlaps its own arithmetic (two tiles of registers are live; a pairs tile
+// holds 64-bit elements, twice the registers, so pairs process one tile at a
+// time).
 
 template <bool P, class Src>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
@@ -493,21 +558,22 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
             const uint32_t ln = opaque(lane);
             const SortItem it = src.get(t);
             Lines<P> a;
-            load_tile<P>(a, it.ks, it.vs, it.count, ln);
+            load_tile<P>(a, it.ks, it.count, ln);
             sort_tile<P>(a, lds, ln);
+            permute_values_lds(a, it.vs, it.count, lds, 0, it.count, ln, wave_lds_fence);
             store_tile<P>(a, it.kd, it.vd, it.count, ln);
         }
     } else {
         Lines<P> a, b;
         SortItem ia = src.get(t), ib;
-        load_tile<P>(a, ia.ks, ia.vs, ia.count, lane);
+        load_tile<P>(a, ia.ks, ia.count, lane);
         for (;;) {
             uint32_t ln = opaque(lane);
             const uint32_t tb = t + G;
             const bool hb = tb < src.ntiles;
             if (hb) {
                 ib = src.get(tb);
-                load_tile<P>(b, ib.ks, ib.vs, ib.count, ln);
+                load_tile<P>(b, ib.ks, ib.count, ln);
             }
             sort_tile<P>(a, lds, ln);
             store_tile<P>(a, ia.kd, ia.vd, ia.count, ln);
@@ -518,7 +584,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
             const bool ha = t < src.ntiles;
             if (ha) {
                 ia = src.get(t);
-                load_tile<P>(a, ia.ks, ia.vs, ia.count, ln);
+                load_tile<P>(a, ia.ks, ia.count, ln);
             }
             sort_tile<P>(b, lds, ln);
             store_tile<P>(b, ib.kd, ib.vd, ib.count, ln);
@@ -536,6 +602,11 @@ struct RegularGroupSrc {
     uint32_t group_keys;
     SampleSet out_smp;
     __device__ uint64_t pos(uint32_t g, uint32_t w) const { return (uint64_t)g * group_keys + (uint64_t)w * kTile; }
+    __device__ uint32_t group_count(uint32_t g) const
+    {
+        const uint64_t rem = n - (uint64_t)g * group_keys;
+        return rem < group_keys ? (uint32_t)rem : group_keys;
+    }
     // sub-tile of wave w of group g (count 0 past the end of the input)
     __device__ SortItem get(uint32_t g, uint32_t w) const
     {
@@ -558,6 +629,7 @@ struct TableGroupSrc {
     uint32_t ngroups;
     SampleSet out_smp;  // always empty
     __device__ uint64_t pos(uint32_t, uint32_t) const { return 0; }
+    __device__ uint32_t group_count(uint32_t g) const { return tiles[g].count; }
     __device__ SortItem get(uint32_t g, uint32_t w) const
     {
         const BlockTile d = tiles[g];
@@ -585,13 +657,21 @@ __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
         const uint32_t ln = opaque(lane);
         const SortItem it = src.get(g, wave);
         Lines<P> t;
-        load_tile<P>(t, it.ks, it.vs, it.count, ln, wave * kTile);
+        load_tile<P>(t, it.ks, it.count, ln, wave * kTile);
         flip(t, wave);  // odd sub-tiles descending
         sort_tile_blocked<P>(t, own, ln);
         flip(t, wave);
         group_rounds<NW, 7, P>(t, lds, ln, wave);
         write_samples<P>(t, src.out_smp, src.pos(g, wave), it.count, ln);
         to_strided(t, own, ln);
+        if constexpr (P) {
+            // group ranks are 4096 * wave + position; wave w stages the values of
+            // its own sub-tile, the LDS is shared by all waves of the group
+            const SortItem i0 = src.get(g, 0);
+            __syncthreads();
+            permute_values_lds(t, i0.vs, src.group_count(g), lds, kTile * wave, it.count, ln,
+                               [] { __syncthreads(); });
+        }
         store_tile<P>(t, it.kd, it.vd, it.count, ln);
     }
 }
@@ -698,6 +778,8 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
         Lines<P> a;
         merge_load<P>(a, m, lane);
         merge_network<P>(a, lds, lane, src.out_smp, m.gpos, m.count);
+        if constexpr (P)
+            gather_values(a, m, lane);
         store_tile<P>(a, m.kd, m.vd, m.count, lane);
     } else if constexpr (P || MODE == 1) {
         for (; t < src.ntiles; t += G) {
@@ -706,6 +788,8 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
             Lines<P> a;
             merge_load<P, NT>(a, m, ln);
             merge_network<P>(a, lds, ln, src.out_smp, m.gpos, m.count);
+            if constexpr (P)
+                gather_values<NT>(a, m, ln);
             store_tile<P, NT>(a, m.kd, m.vd, m.count, ln);
         }
     } else {

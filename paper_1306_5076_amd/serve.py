@@ -1,21 +1,25 @@
 """Continuous-batching sort service on one GPU, and its one-call-per-request baseline.
 
 :class:`SortServer` accepts sort requests (u32 keys, or u32/u32 pairs sorted
-stably by key) from any thread.  A scheduler thread
+stably by key) from any thread.  A launch thread
 
 * admits waiting requests in arrival order while their device bytes fit the
-  HBM budget (a request larger than the whole budget is rejected);
-* packs every admitted request into one batch, keys-only requests first and
-  key/value requests after them, and sorts the batch with at most two
-  segmented launch sequences (``bcf_segmented_sort`` for the keys-only part,
-  ``bcf_segmented_sort_pairs`` for the rest): each request is a segment;
+  HBM budget (a request larger than the whole budget is rejected) and the
+  batch stays under ``max_batch_keys``;
+* packs the admitted requests into one batch: requests of at least
+  ``solo_keys`` keys are sorted alone (``bcf_sort_u32`` /
+  ``bcf_sort_pairs_u32``, no launch plan to build), the smaller ones of each
+  kind share one segmented sort (``bcf_segmented_sort`` /
+  ``bcf_segmented_sort_pairs``) in which each request is a segment;
 * runs batches as a three-stage pipeline on separate streams (host-to-device
   copy, sort, device-to-host copy), so a batch's copies overlap the previous
   batch's kernels, and requests that arrive meanwhile join the next batch;
 * keeps its device buffers and pinned host staging resident between batches
-  (they grow on demand and are reused, never freed per request);
-* completes a request when its batch's device-to-host copy has finished and
-  records its latency from arrival to completion.
+  (they grow on demand and are reused, never freed per request).
+
+A completion thread waits for each batch's device-to-host copy, hands every
+request its result, records its latency from arrival to completion and
+returns the batch's buffers and HBM budget share.
 
 :func:`serve_serial` is the baseline: one request at a time, in arrival order,
 each with its own copy in, ``bcf_sort_u32`` / ``bcf_sort_pairs_u32`` call and
@@ -99,10 +103,11 @@ class SortServer:
     """Continuous-batching sort server (see module docstring)."""
 
     def __init__(self, device="cuda:0", hbm_budget: int = 16 << 30, max_batch_keys: int = 1 << 24,
-                 slots: int = 3, reserve_keys: int = 0):
+                 slots: int = 3, reserve_keys: int = 0, solo_keys: int = 1 << 20):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
         self.max_batch_keys = int(max_batch_keys)
+        self.solo_keys = int(solo_keys)
         self.h2d = torch.cuda.Stream(self.device)
         self.compute = torch.cuda.Stream(self.device)
         self.d2h = torch.cuda.Stream(self.device)
@@ -116,10 +121,15 @@ class SortServer:
         self.batch_sizes = []
         self.cv = threading.Condition()
         self.stop = False
+        self.launcher_done = False
         self.holds = 0
         self.error = None
-        self.thread = threading.Thread(target=self._run, name="bcf-sort-server", daemon=True)
-        self.thread.start()
+        self.launcher = threading.Thread(target=self._guard, args=(self._launch_loop,), name="bcf-sort-launch",
+                                         daemon=True)
+        self.completer = threading.Thread(target=self._guard, args=(self._complete_loop,),
+                                          name="bcf-sort-complete", daemon=True)
+        self.launcher.start()
+        self.completer.start()
 
     # ---------------------------------------------------------------- client side
 
@@ -134,8 +144,10 @@ class SortServer:
             r.future.set_exception(MemoryError(f"request of {r.n} keys exceeds the HBM budget"))
             return r.future
         with self.cv:
+            if self.stop:
+                raise RuntimeError("server is closed")
             self.pending.append(r)
-            self.cv.notify()
+            self.cv.notify_all()
         return r.future
 
     @contextlib.contextmanager
@@ -149,7 +161,7 @@ class SortServer:
         finally:
             with self.cv:
                 self.holds -= 1
-                self.cv.notify()
+                self.cv.notify_all()
 
     def reset_stats(self):
         """Zero the batch counters and the peak of admitted device bytes."""
@@ -159,8 +171,9 @@ class SortServer:
     def close(self):
         with self.cv:
             self.stop = True
-            self.cv.notify()
-        self.thread.join()
+            self.cv.notify_all()
+        self.launcher.join()
+        self.completer.join()
         if self.error:
             raise self.error
 
@@ -172,29 +185,69 @@ class SortServer:
 
     # ---------------------------------------------------------------- scheduler
 
-    def _run(self):
+    def _guard(self, loop):
         try:
             torch.cuda.set_device(self.device)
-            while True:
-                with self.cv:
-                    while not self.stop and not self.busy and (not self.pending or self.holds):
-                        self.cv.wait()
-                    if self.stop and not self.pending and not self.busy:
-                        return
-                self._complete()
-                launched = self._admit_and_launch()
-                if not launched and self.busy:
-                    time.sleep(20e-6)  # waiting for the device; poll completions again
-        except BaseException as e:  # surface in close()
-            self.error = e
+            loop()
+        except BaseException as e:  # surface in close(); fail everything still queued
             with self.cv:
-                for r in self.pending:
+                self.error = self.error or e
+                self.stop = True
+                self.launcher_done = True
+                for r in list(self.pending) + [r for s in self.busy for r in s.reqs]:
                     if not r.future.done():
                         r.future.set_exception(e)
+                self.pending.clear()
+                self.cv.notify_all()
 
-    def _complete(self):
-        while self.busy and self.busy[0].done.query():
-            slot = self.busy.popleft()
+    def _take_batch(self):
+        """Admit requests in arrival order while they fit the batch and the HBM
+        budget (called with the lock held)."""
+        batch, keys = [], 0
+        while self.pending:
+            r = self.pending[0]
+            if batch and keys + r.n > self.max_batch_keys:
+                break
+            if self.used + r.device_bytes() > self.budget:
+                break  # admission by free-HBM budget: wait for completions
+            self.pending.popleft()
+            batch.append(r)
+            keys += r.n
+            self.used += r.device_bytes()
+        return batch
+
+    def _launch_loop(self):
+        while True:
+            with self.cv:
+                while True:
+                    if self.stop and not self.pending:
+                        self.launcher_done = True
+                        self.cv.notify_all()
+                        return
+                    batch = []
+                    if self.pending and self.free_slots and (not self.holds or self.stop):
+                        batch = self._take_batch()
+                    if batch:
+                        break
+                    self.cv.wait()
+                slot = self.free_slots.popleft()
+                self.peak_used = max(self.peak_used, self.used)
+                self.batches += 1
+                self.batch_sizes.append(len(batch))
+            self._launch(slot, batch)
+            with self.cv:
+                self.busy.append(slot)
+                self.cv.notify_all()
+
+    def _complete_loop(self):
+        while True:
+            with self.cv:
+                while not self.busy:
+                    if self.launcher_done:
+                        return
+                    self.cv.wait()
+                slot = self.busy[0]
+            slot.done.synchronize()  # releases the GIL while the device finishes the batch
             now = time.perf_counter()
             ok, ov = slot.ok.t, slot.ov.t
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
@@ -203,51 +256,27 @@ class SortServer:
                 r.finished = now
                 r.future._bcf_finished = now
                 r.future.set_result((k, v) if r.pairs else k)
-                self.used -= r.device_bytes()
-            slot.reqs, slot.loc = [], []
-            self.free_slots.append(slot)
-
-    def _admit_and_launch(self) -> bool:
-        if not self.free_slots:
-            return False
-        with self.cv:
-            batch, keys = [], 0
-            while self.pending and (not self.holds or self.stop):
-                r = self.pending[0]
-                if batch and keys + r.n > self.max_batch_keys:
-                    break
-                if self.used + r.device_bytes() > self.budget:
-                    break  # admission by free-HBM budget, in arrival order: wait for completions
-                self.pending.popleft()
-                batch.append(r)
-                keys += r.n
-                self.used += r.device_bytes()
-            if not batch:
-                return False
-        self.peak_used = max(self.peak_used, self.used)
-        slot = self.free_slots.popleft()
-        self._launch(slot, batch)
-        self.busy.append(slot)
-        self.batches += 1
-        self.batch_sizes.append(len(batch))
-        return True
+            with self.cv:
+                self.busy.popleft()
+                self.used -= sum(r.device_bytes() for r in slot.reqs)
+                slot.reqs, slot.loc = [], []
+                self.free_slots.append(slot)
+                self.cv.notify_all()
 
     def _launch(self, slot: _Slot, batch):
-        # keys-only requests occupy [0, nk) of the batch's key buffers, key/value
-        # requests [nk, n); values only exist for the second part
-        parts = [[r for r in batch if not r.pairs], [r for r in batch if r.pairs]]
-        offs = []
-        for part in parts:
-            o = np.zeros(len(part) + 1, dtype=np.uint64)
-            o[1:] = np.cumsum([r.n for r in part])
-            offs.append(o)
-        nk, npairs = int(offs[0][-1]), int(offs[1][-1])
-        n = nk + npairs
-        slot.reqs, slot.loc = parts[0] + parts[1], []
-        for i, r in enumerate(parts[0]):
-            slot.loc.append((int(offs[0][i]), int(offs[0][i + 1]), 0))
-        for i, r in enumerate(parts[1]):
-            slot.loc.append((nk + int(offs[1][i]), nk + int(offs[1][i + 1]), int(offs[1][i])))
+        # order in the batch buffers: small keys-only requests, large keys-only,
+        # small key/value, large key/value (values exist for the last two only),
+        # so that the small requests of each kind form one contiguous span
+        solo = lambda r: r.n >= self.solo_keys
+        slot.reqs = sorted(batch, key=lambda r: (r.pairs, solo(r)))
+        slot.loc = []
+        pos, vpos = 0, 0
+        for r in slot.reqs:
+            slot.loc.append((pos, pos + r.n, vpos))
+            pos += r.n
+            vpos += r.n if r.pairs else 0
+        n, npairs = pos, vpos
+        nk = n - npairs
         # pack into the slot's pinned buffers (torch copies: multi-threaded, GIL released)
         hk, hv = slot.hk.get(n), slot.hv.get(npairs)
         for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
@@ -261,14 +290,32 @@ class SortServer:
             dk.copy_(hk, non_blocking=True)
             if npairs:
                 dv.copy_(hv, non_blocking=True)
-        # stage 2: one segmented sort per part of the batch
+        # stage 2: large requests sort alone (no launch plan to build); the small
+        # ones of each kind share one segmented sort
         self.compute.wait_stream(self.h2d)
         with torch.cuda.stream(self.compute):
-            if nk:
-                api.segmented_sort(dk[:nk], offs[0], keys_out=rk[:nk], stream=self.compute, workspace=slot.ws)
-            if npairs:
-                api.segmented_sort(dk[nk:], offs[1], vals=dv, keys_out=rk[nk:], vals_out=rv,
-                                   stream=self.compute, workspace=slot.ws)
+            small = [[], []]
+            for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
+                if solo(r):
+                    if r.pairs:
+                        api.sort_pairs_u32(dk[lo:hi], dv[vlo:vlo + r.n], rk[lo:hi], rv[vlo:vlo + r.n],
+                                           stream=self.compute, workspace=slot.ws)
+                    else:
+                        api.sort_u32(dk[lo:hi], out=rk[lo:hi], stream=self.compute, workspace=slot.ws)
+                else:
+                    small[int(r.pairs)].append((lo, hi, vlo))
+            for pairs, segs in enumerate(small):
+                if not segs:
+                    continue
+                lo0, hi1, v0 = segs[0][0], segs[-1][1], segs[0][2]
+                offs = np.asarray([0] + [hi - lo0 for _, hi, _ in segs], dtype=np.uint64)
+                if pairs:
+                    v1 = v0 + (hi1 - lo0)
+                    api.segmented_sort(dk[lo0:hi1], offs, vals=dv[v0:v1], keys_out=rk[lo0:hi1],
+                                       vals_out=rv[v0:v1], stream=self.compute, workspace=slot.ws)
+                else:
+                    api.segmented_sort(dk[lo0:hi1], offs, keys_out=rk[lo0:hi1], stream=self.compute,
+                                       workspace=slot.ws)
         # stage 3: device -> host
         self.d2h.wait_stream(self.compute)
         ok, ov = slot.ok.get(n), slot.ov.get(npairs)
@@ -385,11 +432,13 @@ def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 <<
     return results, lat, wall, stats
 
 
-def run_serving_benchmark(count: int = 300, fracs=(0.5, 0.8, 0.95), seed: int = 1, device="cuda:0",
+def run_serving_benchmark(count: int = 300, fracs=(0.5, 0.9, 1.2), seed: int = 1, device="cuda:0",
                           hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24,
                           max_batch_keys: int = 1 << 24):
     """p50/p99 latency and Gkeys/s of the batched server and of the serial
-    baseline at fractions of the baseline's saturation request rate."""
+    baseline at fractions of the baseline's saturation request rate (above 1:
+    more requests per second than one-at-a-time serving can complete), and
+    both paths' saturation rates (all requests submitted at once)."""
     reqs = make_requests(count, lo=lo, hi=hi, seed=seed)
     total_keys = sum(k.size for _, k, _ in reqs)
     out = {"requests": count, "total_keys": int(total_keys), "sizes": [lo, hi], "pairs_fraction": 0.5,
@@ -401,7 +450,9 @@ def run_serving_benchmark(count: int = 300, fracs=(0.5, 0.8, 0.95), seed: int = 
         serve_batched(reqs, qps=1e9, server=server)
         _, _, sat_wall = serve_serial(reqs, device, realtime=False)
         sat_qps = count / sat_wall
+        _, _, bsat_wall, _ = serve_batched(reqs, qps=1e9, server=server)
         out["serial_saturation_qps"] = round(sat_qps, 2)
+        out["batched_saturation_qps"] = round(count / bsat_wall, 2)
         for frac in fracs:
             qps = frac * sat_qps
             timed = [(t / qps, k, v) for t, k, v in reqs]

@@ -35,7 +35,8 @@ def _requests(count, seed, hi=1 << 18):
 def test_mix_equals_alone(serve):
     reqs = _requests(40, seed=3)
     alone, _, _ = serve.serve_serial(reqs, realtime=False)
-    with serve.SortServer(hbm_budget=1 << 30) as srv:
+    # requests of 2^16 keys and more take the single-sort path, smaller ones share segmented sorts
+    with serve.SortServer(hbm_budget=1 << 30, solo_keys=1 << 16) as srv:
         with srv.held():  # everything queues first, then is admitted as one mixed batch
             futs = [srv.submit(k, v) for _, k, v in reqs]
         mixed = [f.result(timeout=120) for f in futs]
