@@ -317,6 +317,22 @@ __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, u
     const uint32_t bstart = kTile - nb;
     const uint32_t dB = (uint32_t)(m.kb - m.ka);   // B-piece start relative to the A-piece
     const uint32_t bend = dB + (kTile - 1);        // offset of position p in B is bend - p
+    if (m.count == (uint32_t)kTile) {
+        // full tile: every position is in A or in B and no register needs a
+        // select after its load (such selects make the compiler wait for the
+        // loads one by one)
+#pragma unroll
+        for (int r = 0; r < kLine; ++r) {
+            const uint32_t p = kWave * r + lane;
+            const bool in_a = p < na;
+            const uint32_t key = ld<NT>(m.ka + (in_a ? p : bend - p));
+            if constexpr (P)
+                t.e[r] = make_elem(key, in_a ? p : na + (kTile - 1 - p));
+            else
+                t.k[r] = key;
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
         const uint32_t p = kWave * r + lane;
@@ -646,33 +662,77 @@ struct TableGroupSrc {
     }
 };
 
+// Everything of a group tile after its wave's sub-tile is in registers.
+template <int NW, bool P, class Src>
+__device__ __forceinline__ void group_tile(Lines<P> &t, const SortItem &it, const Src &src, uint32_t g,
+                                           uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    uint32_t *own = lds + kLdsWords * wave;
+    flip(t, wave);  // odd sub-tiles descending
+    sort_tile_blocked<P>(t, own, lane);
+    flip(t, wave);
+    group_rounds<NW, 7, P>(t, lds, lane, wave);
+    write_samples<P>(t, src.out_smp, src.pos(g, wave), it.count, lane);
+    to_strided(t, own, lane);
+    if constexpr (P) {
+        // group ranks are 4096 * wave + position; wave w stages the values of
+        // its own sub-tile, the LDS is shared by all waves of the group
+        const SortItem i0 = src.get(g, 0);
+        __syncthreads();
+        permute_values_lds(t, i0.vs, src.group_count(g), lds, kTile * wave, it.count, lane,
+                           [] { __syncthreads(); });
+    }
+    store_tile<P>(t, it.kd, it.vd, it.count, lane);
+}
+
+// Persistent over group tiles (block b handles groups b, b + grid, ...).  For
+// keys the next group's sub-tile is loaded before the current group is
+// sorted (two tiles of registers); a pairs tile is twice as large, so pairs
+// take one group at a time.  Whether a next group exists is the same for all
+// waves of the block, so every wave reaches the same barriers.
 template <int NW, bool P, class Src>
 __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
 {
     __shared__ uint32_t lds[NW * kLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    uint32_t *own = lds + kLdsWords * wave;
-    for (uint32_t g = blockIdx.x; g < src.ngroups; g += gridDim.x) {
-        const uint32_t ln = opaque(lane);
-        const SortItem it = src.get(g, wave);
-        Lines<P> t;
-        load_tile<P>(t, it.ks, it.count, ln, wave * kTile);
-        flip(t, wave);  // odd sub-tiles descending
-        sort_tile_blocked<P>(t, own, ln);
-        flip(t, wave);
-        group_rounds<NW, 7, P>(t, lds, ln, wave);
-        write_samples<P>(t, src.out_smp, src.pos(g, wave), it.count, ln);
-        to_strided(t, own, ln);
-        if constexpr (P) {
-            // group ranks are 4096 * wave + position; wave w stages the values of
-            // its own sub-tile, the LDS is shared by all waves of the group
-            const SortItem i0 = src.get(g, 0);
-            __syncthreads();
-            permute_values_lds(t, i0.vs, src.group_count(g), lds, kTile * wave, it.count, ln,
-                               [] { __syncthreads(); });
+    uint32_t g = blockIdx.x;
+    if (g >= src.ngroups)
+        return;
+    if constexpr (P) {
+        for (; g < src.ngroups; g += gridDim.x) {
+            const uint32_t ln = opaque(lane);
+            const SortItem it = src.get(g, wave);
+            Lines<P> t;
+            load_tile<P>(t, it.ks, it.count, ln, wave * kTile);
+            group_tile<NW, P>(t, it, src, g, lds, ln, wave);
         }
-        store_tile<P>(t, it.kd, it.vd, it.count, ln);
+    } else {
+        Lines<P> a, b;
+        SortItem ia = src.get(g, wave), ib;
+        load_tile<P>(a, ia.ks, ia.count, lane);
+        for (;;) {
+            uint32_t ln = opaque(lane);
+            const uint32_t gb = g + gridDim.x;
+            const bool hb = gb < src.ngroups;
+            if (hb) {
+                ib = src.get(gb, wave);
+                load_tile<P>(b, ib.ks, ib.count, ln);
+            }
+            group_tile<NW, P>(a, ia, src, g, lds, ln, wave);
+            if (!hb)
+                break;
+            ln = opaque(lane);
+            g = gb + gridDim.x;
+            const bool ha = g < src.ngroups;
+            if (ha) {
+                ia = src.get(g, wave);
+                load_tile<P>(a, ia.ks, ia.count, ln);
+            }
+            group_tile<NW, P>(b, ib, src, gb, lds, ln, wave);
+            if (!ha)
+                break;
+        }
     }
 }
 
