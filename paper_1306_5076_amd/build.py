@@ -32,6 +32,10 @@ COMMON = [
     "-I", CSRC,
 ]
 SOURCES = ["bcf_kernels.hip", "bcf_api.hip"]
+# The key/value networks compare elements as doubles (v_min_f64 / v_max_f64)
+# that are never NaN; with the IEEE mode bit clear the compiler does not
+# quieten (canonicalise) every value read back from LDS before comparing it.
+EXTRA = {"bcf_kernels.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"]}
 
 
 def _run(cmd):
@@ -45,7 +49,7 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = [os.path.join(BUILD, s.replace(".hip", ".o")) for s in SOURCES]
-    jobs = [[HIPCC, *COMMON, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    jobs = [[HIPCC, *COMMON, *EXTRA.get(s, []), "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
     jobs.append([HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17",
                  "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", PROBE_SRC, "-o", PROBE_BIN])
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:

@@ -35,37 +35,61 @@ constexpr int kTile = kWave * kLine;   // 4096 keys per wave tile (w^2)
 constexpr int kLdsStride = kLine + 1;  // 65 words per LDS row: one pad word per 64
 constexpr int kLdsWords = kWave * kLdsStride;
 constexpr uint32_t kMaxKey = 0xFFFFFFFFu;
-constexpr uint32_t kPadIdx = 0xFFFFFFFFu;
 
-// A wave's tile in registers.  Keys only: one 32-bit key per position.  Key/
-// value pairs: one 64-bit element per position, the key in the high half and
-// a tie-break rank in the low half (the element's position in the input
-// order of the tile), so elements compare as 64-bit integers by (key, rank),
-// which makes every network stable.  Values do not travel through the
-// networks: after the last network the rank names the input position whose
-// value goes with the key, and the value is fetched by it (from LDS in the
-// block sort, from global memory in a merge).
+// A wave's tile in registers.  Keys only: one 32-bit key per position.
+//
+// Key/value pairs: one 64-bit element per position that orders by (key,
+// rank), where the rank is the element's position in the input order of the
+// tile; comparing ranks on equal keys makes every network stable.  The
+// element is a double in [1, 2) whose mantissa holds key * 2^15 + rank: such
+// doubles are finite, normal and positive, so they order exactly as that
+// 47-bit integer, and a compare-exchange is one v_min_f64 and one v_max_f64
+// (full-rate on CDNA4), the same two instructions as for keys.  Values do not
+// travel through the networks: after the last network the rank names the
+// input position whose value goes with the key, the value is fetched by it
+// (from LDS in the block sort, from global memory in a merge) and the element
+// is repacked as key (high half) and value (low half) for the store.
 template <bool PAIRS>
 struct Lines {
     uint32_t k[kLine];
 };
 template <>
 struct Lines<true> {
-    uint64_t e[kLine];
+    double e[kLine];
 };
 
+constexpr uint32_t kRankBits = 15;                    // group tiles of up to 32768 positions
+constexpr uint32_t kPadRank = (1u << kRankBits) - 1;  // rank of padding (never a real rank)
+constexpr int kRankShift = 52 - 32 - (int)kRankBits;  // payload in mantissa bits 51 .. 5
+constexpr uint64_t kElemOne = 0x3FF0000000000000ull;  // sign and exponent of 1.0
+constexpr uint64_t kPayloadMask = ((1ull << (32 + kRankBits)) - 1) << kRankShift;
+
+__device__ __forceinline__ uint64_t bits_of(double x) { return __builtin_bit_cast(uint64_t, x); }
+__device__ __forceinline__ double elem_of(uint64_t b) { return __builtin_bit_cast(double, b); }
+
+__device__ __forceinline__ double make_elem(uint32_t key, uint32_t rank)
+{
+    return elem_of(kElemOne | ((uint64_t)key << (kRankShift + kRankBits)) | ((uint64_t)rank << kRankShift));
+}
+__device__ __forceinline__ uint32_t elem_key(double e) { return (uint32_t)(bits_of(e) >> (kRankShift + kRankBits)); }
+__device__ __forceinline__ uint32_t elem_rank(double e) { return (uint32_t)(bits_of(e) >> kRankShift) & kPadRank; }
+
+// After the value step: key in the high half, value in the low half.
+__device__ __forceinline__ double make_out(uint32_t key, uint32_t value)
+{
+    return elem_of(((uint64_t)key << 32) | value);
+}
+__device__ __forceinline__ uint32_t out_key(double e) { return (uint32_t)(bits_of(e) >> 32); }
+__device__ __forceinline__ uint32_t out_value(double e) { return (uint32_t)bits_of(e); }
+
+// Key of register r of a tile that is still in element form.
 template <bool P>
 __device__ __forceinline__ uint32_t key_of(const Lines<P> &t, int r)
 {
     if constexpr (P)
-        return (uint32_t)(t.e[r] >> 32);
+        return elem_key(t.e[r]);
     else
         return t.k[r];
-}
-
-__device__ __forceinline__ uint64_t make_elem(uint32_t key, uint32_t rank)
-{
-    return ((uint64_t)key << 32) | rank;
 }
 
 // ---------------------------------------------------------------- comparators
@@ -79,16 +103,16 @@ __device__ __forceinline__ void cx(Lines<P> &t, int a, int b)
         t.k[a] = min(x, y);
         t.k[b] = max(x, y);
     } else {
-        const uint64_t x = t.e[a], y = t.e[b];
-        const bool sw = x > y;
-        t.e[a] = sw ? y : x;
-        t.e[b] = sw ? x : y;
+        const double x = t.e[a], y = t.e[b];
+        t.e[a] = __builtin_fmin(x, y);
+        t.e[b] = __builtin_fmax(x, y);
     }
 }
 
-// Reverse the order of every element of a lane when `bit` is 1: the element
-// is replaced by its bitwise complement, an order-reversing bijection, so an
-// ascending network run on complemented data sorts descending.  Used where
+// Reverse the order of every element of a lane when `bit` is 1: the key (or
+// the element's payload) is replaced by its bitwise complement, an
+// order-reversing bijection, so an ascending network run on complemented data
+// sorts descending.  Used where
 // the direction of a merge depends on the lane (BLOCKED layout).
 template <bool P>
 __device__ __forceinline__ void flip(Lines<P> &t, uint32_t bit)
@@ -96,8 +120,8 @@ __device__ __forceinline__ void flip(Lines<P> &t, uint32_t bit)
     const uint32_t m = 0u - (bit & 1u);
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
-        if constexpr (P)
-            t.e[r] ^= make_elem(m, m);
+        if constexpr (P)  // complement the payload only: the element stays in [1, 2)
+            t.e[r] = elem_of(bits_of(t.e[r]) ^ (kPayloadMask & ((uint64_t)m << 32 | m)));
         else
             t.k[r] ^= m;
     }
@@ -195,26 +219,25 @@ __device__ __forceinline__ void exchange(uint32_t (&x)[kLine], uint32_t *lds, ui
 // The same for 64-bit elements, one 32-bit half at a time (each half keeps the
 // conflict-free word pattern of the 32-bit exchange).
 template <int WS, int RS>
-__device__ __forceinline__ void exchange(uint64_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
-                                         uint32_t rbase)
+__device__ __forceinline__ void exchange(double (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
 {
     uint32_t *w = lds + wbase;
     const uint32_t *rd = lds + rbase;
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)(x[r] >> 32);
+        w[WS * r] = (uint32_t)(bits_of(x[r]) >> 32);
     wave_lds_fence();
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        x[r] = ((uint64_t)rd[RS * r] << 32) | (uint32_t)x[r];
+        x[r] = elem_of(((uint64_t)rd[RS * r] << 32) | (uint32_t)bits_of(x[r]));
     wave_lds_fence();
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)x[r];
+        w[WS * r] = (uint32_t)bits_of(x[r]);
     wave_lds_fence();
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        x[r] = (x[r] & 0xFFFFFFFF00000000ull) | rd[RS * r];
+        x[r] = elem_of((bits_of(x[r]) & 0xFFFFFFFF00000000ull) | rd[RS * r]);
     wave_lds_fence();
 }
 

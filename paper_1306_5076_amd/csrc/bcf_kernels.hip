@@ -75,15 +75,15 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
             const uint32_t q = p < count ? p : last;  // clamped: always a valid address
             const uint32_t key = count ? ksrc[q] : kMaxKey;
             if constexpr (P)
-                t.e[r] = p < count ? make_elem(key, rank0 + p) : make_elem(kMaxKey, kPadIdx);
+                t.e[r] = p < count ? make_elem(key, rank0 + p) : make_elem(kMaxKey, kPadRank);
             else
                 t.k[r] = p < count ? key : kMaxKey;
         }
     }
 }
 
-// Store the first `count` positions of a STRIDED tile.  For pairs the low
-// half of each element holds the value by now (after the value step).
+// Store the first `count` positions of a STRIDED tile.  A pairs tile is in
+// output form (key and value halves) by now, after its value step.
 template <bool P, bool NT = false>
 __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restrict__ kdst,
                                            uint32_t *__restrict__ vdst, uint32_t count, uint32_t lane)
@@ -93,28 +93,35 @@ __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restri
     if (count >= (uint32_t)kTile) {
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
-            st<NT>(kp + kWave * r, key_of(t, r));
-            if constexpr (P)
-                st<NT>(vp + kWave * r, (uint32_t)t.e[r]);
+            if constexpr (P) {
+                st<NT>(kp + kWave * r, out_key(t.e[r]));
+                st<NT>(vp + kWave * r, out_value(t.e[r]));
+            } else {
+                st<NT>(kp + kWave * r, t.k[r]);
+            }
         }
     } else {
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
             if (kWave * r + lane < count) {
-                st<NT>(kp + kWave * r, key_of(t, r));
-                if constexpr (P)
-                    st<NT>(vp + kWave * r, (uint32_t)t.e[r]);
+                if constexpr (P) {
+                    st<NT>(kp + kWave * r, out_key(t.e[r]));
+                    st<NT>(vp + kWave * r, out_value(t.e[r]));
+                } else {
+                    st<NT>(kp + kWave * r, t.k[r]);
+                }
             }
         }
     }
 }
 
 // Value step of a block sort (pairs): the tile is sorted, in STRIDED layout,
-// and every element's low half is the rank of its input position in
-// [0, count).  The values of those `count` input positions are staged in LDS
-// (`vals`, coalesced global reads, conflict-free consecutive LDS words) and
-// each element's rank is replaced by its value, read from LDS.  Callers
-// separate this from other LDS use by the fence or barrier `sync`.
+// and every element's rank is its input position in [0, count) (padding
+// ranks are larger).  The values of those `count` input positions are staged
+// in LDS (`vals`, coalesced global reads, conflict-free consecutive LDS
+// words) and each element is repacked as its key and the value read from LDS
+// at its rank.  Callers separate this from other LDS use by the fence or
+// barrier `sync`.
 template <class Sync>
 __device__ __forceinline__ void permute_values_lds(Lines<true> &t, const uint32_t *__restrict__ vsrc,
                                                    uint32_t count, uint32_t *vals, uint32_t stage_off,
@@ -130,9 +137,9 @@ __device__ __forceinline__ void permute_values_lds(Lines<true> &t, const uint32_
     sync();
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
-        const uint32_t rank = (uint32_t)t.e[r];
+        const uint32_t rank = elem_rank(t.e[r]);
         const uint32_t v = rank < count ? vals[rank] : 0u;
-        t.e[r] = (t.e[r] & 0xFFFFFFFF00000000ull) | v;
+        t.e[r] = make_out(elem_key(t.e[r]), v);
     }
     sync();
 }
@@ -219,26 +226,25 @@ __device__ __forceinline__ void group_exchange(uint32_t (&x)[kLine], uint32_t *l
 
 // The same for 64-bit elements, one 32-bit half at a time.
 template <int WS, int RS>
-__device__ __forceinline__ void group_exchange(uint64_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
-                                               uint32_t rbase)
+__device__ __forceinline__ void group_exchange(double (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
 {
     uint32_t *w = lds + wbase;
     const uint32_t *rd = lds + rbase;
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)(x[r] >> 32);
+        w[WS * r] = (uint32_t)(bits_of(x[r]) >> 32);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        x[r] = ((uint64_t)rd[RS * r] << 32) | (uint32_t)x[r];
+        x[r] = elem_of(((uint64_t)rd[RS * r] << 32) | (uint32_t)bits_of(x[r]));
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)x[r];
+        w[WS * r] = (uint32_t)bits_of(x[r]);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        x[r] = (x[r] & 0xFFFFFFFF00000000ull) | rd[RS * r];
+        x[r] = elem_of((bits_of(x[r]) & 0xFFFFFFFF00000000ull) | rd[RS * r]);
     __syncthreads();
 }
 
@@ -341,15 +347,15 @@ __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, u
         const uint32_t off = in_a ? p : (in_b ? bend - p : 0u);
         const uint32_t key = ld<NT>(m.ka + off);
         if constexpr (P)
-            t.e[r] = (in_a || in_b) ? make_elem(key, in_a ? p : na + (kTile - 1 - p)) : make_elem(kMaxKey, kPadIdx);
+            t.e[r] = (in_a || in_b) ? make_elem(key, in_a ? p : na + (kTile - 1 - p)) : make_elem(kMaxKey, kPadRank);
         else
             t.k[r] = (in_a || in_b) ? key : kMaxKey;
     }
 }
 
-// Value step of a merge (pairs): the merged tile is in STRIDED layout and the
-// low half of each of its first `count` elements is a rank r (r < pa: A[r],
-// else B[r - pa]).  Replace it by that element's value.  The 64 outputs of a
+// Value step of a merge (pairs): the merged tile is in STRIDED layout and each
+// of its first `count` elements has a rank r (r < pa: A[r], else B[r - pa]).
+// Repack it as its key and that source element's value.  The 64 outputs of a
 // register row come from one contiguous stretch of A and one of B, so each
 // gather touches few cache lines.
 template <bool NT = false>
@@ -360,10 +366,10 @@ __device__ __forceinline__ void gather_values(Lines<true> &t, const MergeTask<tr
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
         const uint32_t p = kWave * r + lane;
-        const uint32_t rank = (uint32_t)t.e[r];
+        const uint32_t rank = elem_rank(t.e[r]);
         const uint32_t off = p < m.count ? (rank < na ? rank : rank + dBm) : 0u;
         const uint32_t v = ld<NT>(m.va + off);
-        t.e[r] = (t.e[r] & 0xFFFFFFFF00000000ull) | v;
+        t.e[r] = make_out(elem_key(t.e[r]), v);
     }
 }
 
