@@ -153,7 +153,8 @@ uint32_t bcf_sort_passes(uint64_t n, int pairs);
  */
 typedef struct {
     int32_t merge_variant;     /* merge-pass kernel: 0 persistent waves with next-tile
-                                  prefetch, 1 persistent waves (default), 2 one tile per wave */
+                                  prefetch (keys), 1 persistent waves, 2 one tile per wave,
+                                  3 (default) 2 for keys and 1 for key/value pairs */
     int32_t nontemporal;       /* 1: nontemporal hints on merge-pass tile loads and stores */
     int32_t sampled_partition; /* 1 (default): a pass's co-rank search starts from the key samples
                                   the previous pass wrote (sorts); 0: search the keys only */

@@ -6,8 +6,8 @@ fastest, and caches the winner in a JSON file keyed by a workload signature
 (kind, size bucket, key/value or keys only).  The knobs it searches are the
 ones the kernels expose at run time:
 
-* merge_variant     -- persistent waves with / without next-tile prefetch, or
-                       one tile per wave;
+* merge_variant     -- persistent waves with / without next-tile prefetch, one
+                       tile per wave, or the per-kind default;
 * nontemporal       -- nontemporal hints on the merge passes' tile traffic;
 * group_min_keys    -- (segmented sorts) the segment length from which a
                        segment is block-sorted by multi-wave work-groups.
@@ -30,8 +30,8 @@ from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bcf_sort", "autotune.json")
 
-SORT_SPACE = {"merge_variant": [1, 2, 0], "nontemporal": [1, 0]}
-SEGMENTED_SPACE = {"merge_variant": [1, 2], "nontemporal": [1, 0],
+SORT_SPACE = {"merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0]}
+SEGMENTED_SPACE = {"merge_variant": [3, 1, 2], "nontemporal": [1, 0],
                    "group_min_keys": [4097, 16384, 65536, 1 << 40]}
 
 

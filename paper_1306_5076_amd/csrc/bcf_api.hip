@@ -145,9 +145,9 @@ int env_int(const char *name, int dflt)
 Tuning &tuning_locked()
 {
     if (!g_tune_init) {
-        g_tune.merge_variant = env_int("BCF_MERGE_MODE", 1);
-        if (g_tune.merge_variant < 0 || g_tune.merge_variant > 2)
-            g_tune.merge_variant = 1;
+        g_tune.merge_variant = env_int("BCF_MERGE_MODE", 3);
+        if (g_tune.merge_variant < 0 || g_tune.merge_variant > 3)
+            g_tune.merge_variant = 3;
         g_tune.nontemporal = env_int("BCF_NT", 1) != 0;
         g_tune.sampled_partition = std::getenv("BCF_NO_SAMPLES") == nullptr;
         g_tune.tile_samples = env_int("BCF_TILE_SAMPLES", 1) != 0;
@@ -687,7 +687,7 @@ void bcf_get_tuning(bcf_tuning *out)
 
 bcf_status bcf_set_tuning(const bcf_tuning *in)
 {
-    if (!in || in->merge_variant < 0 || in->merge_variant > 2)
+    if (!in || in->merge_variant < 0 || in->merge_variant > 3)
         return BCF_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_tune_mu);
     Tuning &t = tuning_locked();

@@ -968,7 +968,10 @@ static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream
     if (src.ntiles == 0)
         return hipSuccess;
     const Tuning tu = tuning();
-    switch (tu.merge_variant) {
+    // variant 3: one tile per wave for keys (the lighter kernel fits three
+    // waves' registers per SIMD), persistent waves for pairs
+    const int variant = tu.merge_variant == 3 ? (P ? 1 : 2) : tu.merge_variant;
+    switch (variant) {
     case 0: return P ? launch_merge_mode<P, Src, 1>(src, splits, s) : launch_merge_mode<P, Src, 0>(src, splits, s);
     case 2: return launch_merge_mode<P, Src, 2>(src, splits, s);
     default:

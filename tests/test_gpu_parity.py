@@ -289,7 +289,7 @@ def test_errors_raise(torch_dev, bcf):
         assert list(got) == [1, 2, 3, 4, 5, 6, 9]
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("nt", [0, 1])
 def test_merge_kernel_variants(torch_dev, bcf, mode, nt):
     torch, dev = torch_dev
