@@ -15,7 +15,6 @@ launch stream, and the CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -27,22 +26,18 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 N_KEYS = 1 << 26
-KERNEL_SOURCES = [
-    os.path.join(ROOT, "paper_1306_5076_amd", "csrc", f)
-    for f in ("bcf_device.hpp", "bcf_kernels.hip", "bcf_internal.hpp")
-]
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+def _source_hash():
+    from paper_1306_5076_amd.counters import kernel_source_hash
+
+    return kernel_source_hash()
 
 
 def committed_counters(name: str):
     """Counter summary committed under profiles/ for the current kernel sources, else None."""
+    from paper_1306_5076_amd.counters import kernel_source_hash
+
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -51,6 +46,17 @@ def committed_counters(name: str):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec
+
+
+def counted_kernel(rec, prefix: str):
+    """The per-kernel counter record of the most-dispatched kernel named prefix..."""
+    if not rec:
+        return None, None
+    cands = [(v.get("dispatches", 0), k) for k, v in rec["per_kernel"].items() if k.startswith(prefix)]
+    if not cands:
+        return None, None
+    _, name = max(cands)
+    return name, rec["per_kernel"][name]
 
 
 def cpu_baseline(keys_np):
@@ -260,8 +266,9 @@ def main():
     bytes_per_launch = st["bytes"] / st["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernels = _kernel_table(stats)
-    traffic_rec = committed_counters("traffic_merge_keys_2p26.json")
-    conflicts_rec = committed_counters("lds_conflicts_2p26.json")
+    traffic_name, traffic_rec = counted_kernel(committed_counters("traffic_sort_keys_2p26.json"),
+                                               "bcf::k_merge<false, bcf::RegularMergeSrc")
+    conflicts_rec = committed_counters("lds_sort_keys_2p26.json")
 
     rec = {
         "metric": "Gkeys/s + HBM GB/s frac at 2^26 uint32; LDS bank conflicts; p99 served latency",
@@ -294,7 +301,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_rec["bytes_per_launch"] if traffic_rec else None,
+            "traffic": traffic_rec["read_bytes"] + traffic_rec["write_bytes"] if traffic_rec else None,
+            "traffic_kernel": traffic_name,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(avg_ms * 1e3, 2),
         },
@@ -305,7 +313,7 @@ def main():
             4,
         ),
         "lds_bank_conflicts": conflicts_rec["per_kernel"] if conflicts_rec else None,
-        "kernel_source_hash": kernel_source_hash(),
+        "kernel_source_hash": _source_hash(),
     }
     rec["tuning"] = bcf.get_tuning()
     if not args.quick:

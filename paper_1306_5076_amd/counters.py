@@ -1,0 +1,211 @@
+"""Summaries of rocprofv3 runs of ``bench.py`` for the ``profiles/`` folder.
+
+Measurement tooling, not part of the sort path: it reads the CSV files that
+``rocprofv3 --kernel-trace --stats`` and ``rocprofv3 --pmc ...`` wrote and
+turns them into the short summaries that ``bench.py`` and the design notes
+quote.
+
+* ``trace``   -- per-kernel launch statistics and, for the merge passes of
+  one sort, the median duration at every pass position;
+* ``traffic`` -- HBM bytes per dispatch from a ``FETCH_SIZE`` run and a
+  ``WRITE_SIZE`` run.  The counters are in KiB per dispatch and are scaled by
+  what they read for a plain device-to-device copy of known size in the same
+  run (``bench.py --copy-calibration``): the scale makes that copy read and
+  write exactly its size;
+* ``lds``     -- ``SQ_LDS_BANK_CONFLICT`` and ``SQ_INSTS_LDS`` per dispatch.
+
+Every JSON summary records the hash of the kernel sources it was measured
+with; ``bench.py`` uses a summary only while the sources still hash the same.
+
+    python -m paper_1306_5076_amd.counters trace   DIR OUT.md  --command "..."
+    python -m paper_1306_5076_amd.counters traffic FETCH_DIR WRITE_DIR OUT.json --n N --command "..."
+    python -m paper_1306_5076_amd.counters lds     DIR OUT.json --command "..."
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(PKG, "csrc", f) for f in ("bcf_device.hpp", "bcf_kernels.hip", "bcf_internal.hpp")]
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def kernel_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the device sources."""
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """Kernel name without the return type and the argument list."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    depth = 0
+    for i, ch in enumerate(name):  # cut at the first '(' outside template brackets
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def _one_csv(directory: str, suffix: str) -> str:
+    found = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not found:
+        raise FileNotFoundError(f"no *{suffix} under {directory}")
+    return found[0]
+
+
+def _rows(directory: str, suffix: str):
+    with open(_one_csv(directory, suffix)) as f:
+        return list(csv.DictReader(f))
+
+
+def counter_per_kernel(directory: str, counter: str) -> dict:
+    """{kernel: [value of `counter` per dispatch]} from a --pmc run."""
+    out: dict[str, list[float]] = {}
+    for r in _rows(directory, "counter_collection.csv"):
+        if r["Counter_Name"] != counter:
+            continue
+        out.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_dir: str, write_dir: str, n_copy_keys: int, command: str = "") -> dict:
+    fetch = counter_per_kernel(fetch_dir, "FETCH_SIZE")
+    write = counter_per_kernel(write_dir, "WRITE_SIZE")
+    copy_bytes = 4.0 * n_copy_keys
+    cf, cw = fetch.get(COPY_KERNEL), write.get(COPY_KERNEL)
+    if not cf or not cw:
+        raise ValueError(f"no {COPY_KERNEL} dispatch to calibrate with (run bench.py --copy-calibration)")
+    fetch_scale = copy_bytes / (statistics.mean(cf) * 1024.0)
+    write_scale = copy_bytes / (statistics.mean(cw) * 1024.0)
+    per = {}
+    for k in sorted(set(fetch) & set(write)):
+        if k == COPY_KERNEL or not k.startswith("bcf::"):
+            continue
+        fk, wk = statistics.mean(fetch[k]), statistics.mean(write[k])
+        per[k] = {
+            "fetch_kib_raw": round(fk, 1),
+            "write_kib_raw": round(wk, 1),
+            "read_bytes": int(fk * 1024 * fetch_scale),
+            "write_bytes": int(wk * 1024 * write_scale),
+            "dispatches": len(fetch[k]),
+        }
+    return {
+        "kernel_source_hash": kernel_source_hash(),
+        "command": command,
+        "fetch_scale": round(fetch_scale, 4),
+        "write_scale": round(write_scale, 4),
+        "calibration": f"{COPY_KERNEL} of {n_copy_keys} u32 ({int(copy_bytes)} bytes read and written): "
+        "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled so that the copy reads and writes exactly its size",
+        "per_kernel": per,
+    }
+
+
+def lds(directory: str, command: str = "") -> dict:
+    conf = counter_per_kernel(directory, "SQ_LDS_BANK_CONFLICT")
+    insts = counter_per_kernel(directory, "SQ_INSTS_LDS")
+    per = {}
+    for k in sorted(set(conf) & set(insts)):
+        if not k.startswith("bcf::"):
+            continue
+        per[k] = {"SQ_LDS_BANK_CONFLICT": statistics.mean(conf[k]), "SQ_INSTS_LDS": statistics.mean(insts[k]),
+                  "dispatches": len(conf[k])}
+    return {"kernel_source_hash": kernel_source_hash(), "command": command, "per_kernel": per}
+
+
+def _is(kind: str, name: str) -> bool:
+    n = short_name(name)
+    if kind == "block":
+        return n.startswith("bcf::k_block_sort")
+    if kind == "merge":
+        return n.startswith("bcf::k_merge")
+    return False
+
+
+def trace_markdown(directory: str, command: str, title: str, n_keys: int | None = None) -> str:
+    stats = _rows(directory, "kernel_stats.csv")
+    lines = [f"# {title}", "", "Command (repository root on the GPU box, library built in-tree beforehand):", "",
+             "    " + command.replace("\n", "\n    "), "", f"Kernel source hash: `{kernel_source_hash()}`", "",
+             "## Per kernel (all launches of the run)", "",
+             "| kernel | calls | average us | min us | max us | share of GPU time |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} % |")
+    try:
+        trace = _rows(directory, "kernel_trace.csv")
+    except FileNotFoundError:
+        trace = []
+    if trace:
+        trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+        sorts, cur = [], None
+        for r in trace:
+            if _is("block", r["Kernel_Name"]):
+                cur = {"block": int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), "merges": []}
+                sorts.append(cur)
+            elif _is("merge", r["Kernel_Name"]) and cur is not None:
+                cur["merges"].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        if sorts:
+            npass = statistics.mode(len(s["merges"]) for s in sorts)
+            full = [s for s in sorts if len(s["merges"]) == npass]
+            lines += ["", f"## One sort, launch by launch (median over {len(full)} sorts)", "",
+                      "| launch | kernel | median us |" + (" algorithmic GB/s |" if n_keys else ""),
+                      "|---|---|---|" + ("---|" if n_keys else "")]
+            med = statistics.median(s["block"] for s in full) / 1e3
+            gbs = f" {2 * 4 * n_keys / (med * 1e-6) / 1e9:.0f} |" if n_keys else ""
+            lines.append(f"| 0 | block sort | {med:.1f} |{gbs}")
+            for i in range(npass):
+                med = statistics.median(s["merges"][i] for s in full) / 1e3
+                gbs = f" {2 * 4 * n_keys / (med * 1e-6) / 1e9:.0f} |" if n_keys else ""
+                lines.append(f"| {i + 1} | merge pass {i + 1} | {med:.1f} |{gbs}")
+    return "\n".join(lines) + "\n"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("out")
+    t.add_argument("--command", default="")
+    t.add_argument("--title", default="Kernel trace")
+    t.add_argument("--n", type=int, default=None, help="keys per sort, for algorithmic GB/s")
+    f = sub.add_parser("traffic")
+    f.add_argument("fetch_dir")
+    f.add_argument("write_dir")
+    f.add_argument("out")
+    f.add_argument("--n", type=int, required=True, help="u32 elements of the calibration copy")
+    f.add_argument("--command", default="")
+    ld = sub.add_parser("lds")
+    ld.add_argument("dir")
+    ld.add_argument("out")
+    ld.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    if a.what == "trace":
+        text = trace_markdown(a.dir, a.command, a.title, a.n)
+        with open(a.out, "w") as fh:
+            fh.write(text)
+    else:
+        rec = traffic(a.fetch_dir, a.write_dir, a.n, a.command) if a.what == "traffic" else lds(a.dir, a.command)
+        with open(a.out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
+    print(a.out)
+
+
+if __name__ == "__main__":
+    main()
