@@ -49,7 +49,11 @@ class _Request:
     vals: np.ndarray | None
     arrival: float
     future: Future = field(default_factory=Future)
-    finished: float = 0.0
+    submitted: float = 0.0  # perf_counter() when submit() queued it
+    admitted: float = 0.0   # ... when the launch thread took it into a batch
+    launched: float = 0.0   # ... when its batch's copies and kernels were enqueued
+    done: float = 0.0       # ... when its batch's device-to-host copy had finished
+    finished: float = 0.0   # ... when its result was handed out
 
     @property
     def n(self) -> int:
@@ -143,6 +147,7 @@ class SortServer:
         if r.device_bytes() > self.budget:
             r.future.set_exception(MemoryError(f"request of {r.n} keys exceeds the HBM budget"))
             return r.future
+        r.submitted = time.perf_counter()
         with self.cv:
             if self.stop:
                 raise RuntimeError("server is closed")
@@ -234,7 +239,13 @@ class SortServer:
                 self.peak_used = max(self.peak_used, self.used)
                 self.batches += 1
                 self.batch_sizes.append(len(batch))
+            now = time.perf_counter()
+            for r in batch:
+                r.admitted = now
             self._launch(slot, batch)
+            now = time.perf_counter()
+            for r in batch:
+                r.launched = now
             with self.cv:
                 self.busy.append(slot)
                 self.cv.notify_all()
@@ -248,13 +259,14 @@ class SortServer:
                     self.cv.wait()
                 slot = self.busy[0]
             slot.done.synchronize()  # releases the GIL while the device finishes the batch
-            now = time.perf_counter()
+            done = time.perf_counter()
             ok, ov = slot.ok.t, slot.ov.t
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
                 k = ok[lo:hi].clone().numpy()
                 v = ov[vlo:vlo + (hi - lo)].clone().numpy() if r.pairs else None
-                r.finished = now
-                r.future._bcf_finished = now
+                r.done = done
+                r.finished = time.perf_counter()
+                r.future._bcf_request = r
                 r.future.set_result((k, v) if r.pairs else k)
             with self.cv:
                 self.busy.popleft()
@@ -428,11 +440,22 @@ def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 <<
              "max_batch_keys": server.max_batch_keys}
     if own:
         server.close()
-    lat = [f._bcf_finished - a for f, a in zip(futs, arrivals)]
+    reqs = [f._bcf_request for f in futs]
+    lat = [r.finished - a for r, a in zip(reqs, arrivals)]
+    stats["stage_p50_ms"] = {
+        "queued": _p50([r.admitted - r.submitted for r in reqs]),
+        "pack_and_enqueue": _p50([r.launched - r.admitted for r in reqs]),
+        "device": _p50([r.done - r.launched for r in reqs]),
+        "unpack": _p50([r.finished - r.done for r in reqs]),
+    }
     return results, lat, wall, stats
 
 
-def run_serving_benchmark(count: int = 300, fracs=(0.5, 0.9, 1.2), seed: int = 1, device="cuda:0",
+def _p50(xs):
+    return round(float(np.median(xs)) * 1e3, 3) if xs else 0.0
+
+
+def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.9, 1.2, 1.6), seed: int = 1, device="cuda:0",
                           hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24,
                           max_batch_keys: int = 1 << 24):
     """p50/p99 latency and Gkeys/s of the batched server and of the serial
