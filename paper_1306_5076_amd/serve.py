@@ -7,13 +7,15 @@ stably by key) from any thread.  A launch thread
   HBM budget (a request larger than the whole budget is rejected) and the
   batch stays under ``max_batch_keys``;
 * packs the admitted requests into one batch: requests of at least
-  ``solo_keys`` keys are sorted alone (``bcf_sort_u32`` /
-  ``bcf_sort_pairs_u32``, no launch plan to build), the smaller ones of each
-  kind share one segmented sort (``bcf_segmented_sort`` /
-  ``bcf_segmented_sort_pairs``) in which each request is a segment;
-* runs batches as a three-stage pipeline on separate streams (host-to-device
-  copy, sort, device-to-host copy), so a batch's copies overlap the previous
-  batch's kernels, and requests that arrive meanwhile join the next batch;
+  ``solo_keys`` keys, and a request alone in its batch, are sorted on their
+  own (``bcf_sort_u32`` / ``bcf_sort_pairs_u32``, no launch plan to build),
+  the smaller ones of each kind share one segmented sort
+  (``bcf_segmented_sort`` / ``bcf_segmented_sort_pairs``) in which each
+  request is a segment;
+* runs each batch (host-to-device copy, sorts, device-to-host copy) on the
+  stream of one of ``slots`` buffer slots, so up to that many batches are in
+  flight and one batch's copies overlap another's kernels; requests that
+  arrive meanwhile join the next batch;
 * keeps its device buffers and pinned host staging resident between batches
   (they grow on demand and are reused, never freed per request).
 
@@ -98,6 +100,7 @@ class _Slot:
         for g in (self.hk, self.hv, self.ok, self.ov, self.dk, self.dv, self.rk, self.rv):
             g.get(reserve_keys)
         self.ws = api.Workspace(device)
+        self.stream = torch.cuda.Stream(device)
         self.done = None
         self.reqs = []
         self.loc = []       # per request: (key lo, key hi, value lo) in the batch buffers
@@ -112,9 +115,6 @@ class SortServer:
         self.budget = int(hbm_budget)
         self.max_batch_keys = int(max_batch_keys)
         self.solo_keys = int(solo_keys)
-        self.h2d = torch.cuda.Stream(self.device)
-        self.compute = torch.cuda.Stream(self.device)
-        self.d2h = torch.cuda.Stream(self.device)
         self.slots = [_Slot(self.device, reserve_keys) for _ in range(slots)]
         self.free_slots = collections.deque(self.slots)
         self.busy = collections.deque()
@@ -297,23 +297,25 @@ class SortServer:
                 hv[vlo:vlo + (hi - lo)].copy_(torch.from_numpy(r.vals))
         dk, rk = slot.dk.get(n), slot.rk.get(n)
         dv, rv = slot.dv.get(npairs), slot.rv.get(npairs)
-        # stage 1: host -> device
-        with torch.cuda.stream(self.h2d):
+        # copy in, sort, copy out, all on the slot's own stream: batches in
+        # different slots overlap (one batch's copies with another's kernels)
+        st = slot.stream
+        with torch.cuda.stream(st):
             dk.copy_(hk, non_blocking=True)
             if npairs:
                 dv.copy_(hv, non_blocking=True)
-        # stage 2: large requests sort alone (no launch plan to build); the small
-        # ones of each kind share one segmented sort
-        self.compute.wait_stream(self.h2d)
-        with torch.cuda.stream(self.compute):
+            # large requests, and a request alone in its batch, sort on their own
+            # (no launch plan to build); the small ones of each kind share one
+            # segmented sort
+            alone = len(slot.reqs) == 1
             small = [[], []]
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
-                if solo(r):
+                if alone or solo(r):
                     if r.pairs:
                         api.sort_pairs_u32(dk[lo:hi], dv[vlo:vlo + r.n], rk[lo:hi], rv[vlo:vlo + r.n],
-                                           stream=self.compute, workspace=slot.ws)
+                                           stream=st, workspace=slot.ws)
                     else:
-                        api.sort_u32(dk[lo:hi], out=rk[lo:hi], stream=self.compute, workspace=slot.ws)
+                        api.sort_u32(dk[lo:hi], out=rk[lo:hi], stream=st, workspace=slot.ws)
                 else:
                     small[int(r.pairs)].append((lo, hi, vlo))
             for pairs, segs in enumerate(small):
@@ -324,19 +326,15 @@ class SortServer:
                 if pairs:
                     v1 = v0 + (hi1 - lo0)
                     api.segmented_sort(dk[lo0:hi1], offs, vals=dv[v0:v1], keys_out=rk[lo0:hi1],
-                                       vals_out=rv[v0:v1], stream=self.compute, workspace=slot.ws)
+                                       vals_out=rv[v0:v1], stream=st, workspace=slot.ws)
                 else:
-                    api.segmented_sort(dk[lo0:hi1], offs, keys_out=rk[lo0:hi1], stream=self.compute,
-                                       workspace=slot.ws)
-        # stage 3: device -> host
-        self.d2h.wait_stream(self.compute)
-        ok, ov = slot.ok.get(n), slot.ov.get(npairs)
-        with torch.cuda.stream(self.d2h):
+                    api.segmented_sort(dk[lo0:hi1], offs, keys_out=rk[lo0:hi1], stream=st, workspace=slot.ws)
+            ok, ov = slot.ok.get(n), slot.ov.get(npairs)
             ok.copy_(rk, non_blocking=True)
             if npairs:
                 ov.copy_(rv, non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(self.d2h)
+            ev.record(st)
         slot.done = ev
 
 
