@@ -329,6 +329,7 @@ def main():
         from paper_1306_5076_amd import serve
 
         rec["serving"] = serve.run_serving_benchmark(count=400, device=str(dev))
+        rec["serving_device"] = serve.run_serving_benchmark(count=400, device=str(dev), resident="device")
         rec["sections_s"] = round(time.perf_counter() - t0s, 1)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(host["uniform"])

@@ -47,9 +47,10 @@ __all__ = ["SortServer", "serve_serial", "serve_batched", "latency_stats", "make
 
 @dataclass
 class _Request:
-    keys: np.ndarray
-    vals: np.ndarray | None
+    keys: object            # numpy array (host request) or CUDA tensor (device request)
+    vals: object | None
     arrival: float
+    ready: object = None    # device request: event recorded on the submitting stream
     future: Future = field(default_factory=Future)
     submitted: float = 0.0  # perf_counter() when submit() queued it
     admitted: float = 0.0   # ... when the launch thread took it into a batch
@@ -59,7 +60,11 @@ class _Request:
 
     @property
     def n(self) -> int:
-        return int(self.keys.size)
+        return int(self.keys.numel()) if self.on_device else int(self.keys.size)
+
+    @property
+    def on_device(self) -> bool:
+        return self.ready is not None
 
     @property
     def pairs(self) -> bool:
@@ -96,9 +101,9 @@ class _Slot:
         self.hk, self.hv = _Grow(pinned=True), _Grow(pinned=True)      # host in
         self.ok, self.ov = _Grow(pinned=True), _Grow(pinned=True)      # host out
         self.dk, self.dv = _Grow(device), _Grow(device)                # device in
-        self.rk, self.rv = _Grow(device), _Grow(device)                # device out
-        for g in (self.hk, self.hv, self.ok, self.ov, self.dk, self.dv, self.rk, self.rv):
+        for g in (self.hk, self.hv, self.ok, self.ov, self.dk, self.dv):
             g.get(reserve_keys)
+        self.out = None     # the batch's device outputs (keys, values)
         self.ws = api.Workspace(device)
         self.stream = torch.cuda.Stream(device)
         self.done = None
@@ -138,12 +143,33 @@ class SortServer:
     # ---------------------------------------------------------------- client side
 
     def submit(self, keys, vals=None, arrival: float | None = None) -> Future:
-        keys = np.ascontiguousarray(np.asarray(keys, dtype=np.uint32))
-        if vals is not None:
-            vals = np.ascontiguousarray(np.asarray(vals, dtype=np.uint32))
-            if vals.shape != keys.shape:
-                raise ValueError("keys and vals must have the same length")
-        r = _Request(keys, vals, time.perf_counter() if arrival is None else arrival)
+        """Queue one sort request; the future's result is the sorted keys, or
+        (keys, values) for a key/value request.
+
+        Host requests (array-likes) get numpy results.  Device requests (uint32
+        CUDA tensors on the server's device) are read on the device after the
+        work already enqueued on the submitting thread's current stream, and
+        get CUDA tensors back: views of the batch's output buffers, complete
+        when the future resolves (a consumer on another stream should call
+        ``record_stream`` on them).
+        """
+        ready = None
+        if isinstance(keys, torch.Tensor) and keys.is_cuda:
+            if keys.dtype != torch.uint32 or keys.device != self.device or not keys.is_contiguous():
+                raise ValueError("device keys must be a contiguous uint32 tensor on the server's device")
+            if vals is not None and (not isinstance(vals, torch.Tensor) or vals.dtype != torch.uint32
+                                     or vals.device != self.device or vals.shape != keys.shape
+                                     or not vals.is_contiguous()):
+                raise ValueError("device values must be a contiguous uint32 tensor shaped like the keys")
+            ready = torch.cuda.Event()
+            ready.record(torch.cuda.current_stream(self.device))
+        else:
+            keys = np.ascontiguousarray(np.asarray(keys, dtype=np.uint32))
+            if vals is not None:
+                vals = np.ascontiguousarray(np.asarray(vals, dtype=np.uint32))
+                if vals.shape != keys.shape:
+                    raise ValueError("keys and vals must have the same length")
+        r = _Request(keys, vals, time.perf_counter() if arrival is None else arrival, ready)
         if r.device_bytes() > self.budget:
             r.future.set_exception(MemoryError(f"request of {r.n} keys exceeds the HBM budget"))
             return r.future
@@ -261,9 +287,14 @@ class SortServer:
             slot.done.synchronize()  # releases the GIL while the device finishes the batch
             done = time.perf_counter()
             ok, ov = slot.ok.t, slot.ov.t
+            rk, rv = slot.out
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
-                k = ok[lo:hi].clone().numpy()
-                v = ov[vlo:vlo + (hi - lo)].clone().numpy() if r.pairs else None
+                if r.on_device:
+                    k = rk[lo:hi]
+                    v = rv[vlo:vlo + (hi - lo)] if r.pairs else None
+                else:
+                    k = ok[lo:hi].clone().numpy()
+                    v = ov[vlo:vlo + (hi - lo)].clone().numpy() if r.pairs else None
                 r.done = done
                 r.finished = time.perf_counter()
                 r.future._bcf_request = r
@@ -271,56 +302,70 @@ class SortServer:
             with self.cv:
                 self.busy.popleft()
                 self.used -= sum(r.device_bytes() for r in slot.reqs)
-                slot.reqs, slot.loc = [], []
+                slot.reqs, slot.loc, slot.out = [], [], None
                 self.free_slots.append(slot)
                 self.cv.notify_all()
 
     def _launch(self, slot: _Slot, batch):
-        # order in the batch buffers: small keys-only requests, large keys-only,
-        # small key/value, large key/value (values exist for the last two only),
-        # so that the small requests of each kind form one contiguous span
+        # order in the batch buffers: host requests before device requests, within
+        # each keys-only before key/value, small before large, so that the host
+        # part is one span (one copy each way) and the small requests of each
+        # (residence, kind) group are contiguous; values exist for key/value
+        # requests only and follow the same order
         solo = lambda r: r.n >= self.solo_keys
-        slot.reqs = sorted(batch, key=lambda r: (r.pairs, solo(r)))
+        slot.reqs = sorted(batch, key=lambda r: (r.on_device, r.pairs, solo(r)))
         slot.loc = []
-        pos, vpos = 0, 0
+        pos, vpos, nh, nvh = 0, 0, 0, 0
         for r in slot.reqs:
             slot.loc.append((pos, pos + r.n, vpos))
             pos += r.n
             vpos += r.n if r.pairs else 0
+            if not r.on_device:
+                nh, nvh = pos, vpos
         n, npairs = pos, vpos
-        nk = n - npairs
-        # pack into the slot's pinned buffers (torch copies: multi-threaded, GIL released)
-        hk, hv = slot.hk.get(n), slot.hv.get(npairs)
+        # pack host requests into the slot's pinned buffers (torch copies:
+        # multi-threaded, GIL released)
+        hk, hv = slot.hk.get(nh), slot.hv.get(nvh)
         for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
-            hk[lo:hi].copy_(torch.from_numpy(r.keys))
-            if r.pairs:
-                hv[vlo:vlo + (hi - lo)].copy_(torch.from_numpy(r.vals))
-        dk, rk = slot.dk.get(n), slot.rk.get(n)
-        dv, rv = slot.dv.get(npairs), slot.rv.get(npairs)
+            if not r.on_device:
+                hk[lo:hi].copy_(torch.from_numpy(r.keys))
+                if r.pairs:
+                    hv[vlo:vlo + (hi - lo)].copy_(torch.from_numpy(r.vals))
+        dk, dv = slot.dk.get(n), slot.dv.get(npairs)
         # copy in, sort, copy out, all on the slot's own stream: batches in
         # different slots overlap (one batch's copies with another's kernels)
         st = slot.stream
         with torch.cuda.stream(st):
-            dk.copy_(hk, non_blocking=True)
-            if npairs:
-                dv.copy_(hv, non_blocking=True)
-            # large requests, and a request alone in its batch, sort on their own
-            # (no launch plan to build); the small ones of each kind share one
-            # segmented sort
+            if nh:
+                dk[:nh].copy_(hk, non_blocking=True)
+            if nvh:
+                dv[:nvh].copy_(hv, non_blocking=True)
             alone = len(slot.reqs) == 1
-            small = [[], []]
+            for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
+                if r.on_device:
+                    st.wait_event(r.ready)
+                    if not (alone or solo(r)):  # sorted from its own buffer otherwise
+                        dk[lo:hi].copy_(r.keys, non_blocking=True)
+                        if r.pairs:
+                            dv[vlo:vlo + r.n].copy_(r.vals, non_blocking=True)
+            rk = torch.empty(n, dtype=torch.uint32, device=self.device)
+            rv = torch.empty(npairs, dtype=torch.uint32, device=self.device)
+            slot.out = (rk, rv)
+            # large requests, and a request alone in its batch, sort on their own
+            # (no launch plan to build); the small ones of each group share one
+            # segmented sort
+            groups = {}
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
                 if alone or solo(r):
+                    ki = r.keys if r.on_device else dk[lo:hi]
                     if r.pairs:
-                        api.sort_pairs_u32(dk[lo:hi], dv[vlo:vlo + r.n], rk[lo:hi], rv[vlo:vlo + r.n],
-                                           stream=st, workspace=slot.ws)
+                        vi = r.vals if r.on_device else dv[vlo:vlo + r.n]
+                        api.sort_pairs_u32(ki, vi, rk[lo:hi], rv[vlo:vlo + r.n], stream=st, workspace=slot.ws)
                     else:
-                        api.sort_u32(dk[lo:hi], out=rk[lo:hi], stream=st, workspace=slot.ws)
+                        api.sort_u32(ki, out=rk[lo:hi], stream=st, workspace=slot.ws)
                 else:
-                    small[int(r.pairs)].append((lo, hi, vlo))
-            for pairs, segs in enumerate(small):
-                if not segs:
-                    continue
+                    groups.setdefault((r.on_device, r.pairs), []).append((lo, hi, vlo))
+            for (_, pairs), segs in groups.items():
                 lo0, hi1, v0 = segs[0][0], segs[-1][1], segs[0][2]
                 offs = np.asarray([0] + [hi - lo0 for _, hi, _ in segs], dtype=np.uint64)
                 if pairs:
@@ -329,10 +374,10 @@ class SortServer:
                                        vals_out=rv[v0:v1], stream=st, workspace=slot.ws)
                 else:
                     api.segmented_sort(dk[lo0:hi1], offs, keys_out=rk[lo0:hi1], stream=st, workspace=slot.ws)
-            ok, ov = slot.ok.get(n), slot.ov.get(npairs)
-            ok.copy_(rk, non_blocking=True)
-            if npairs:
-                ov.copy_(rv, non_blocking=True)
+            if nh:
+                slot.ok.get(nh).copy_(rk[:nh], non_blocking=True)
+            if nvh:
+                slot.ov.get(nvh).copy_(rv[:nvh], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
         slot.done = ev
@@ -341,10 +386,11 @@ class SortServer:
 def serve_serial(requests, device="cuda:0", realtime: bool = True):
     """Baseline: each request alone (copy in, sort, copy out, synchronise), FIFO.
 
-    ``requests`` is a list of ``(arrival_offset_s, keys, vals_or_None)``; with
-    ``realtime`` a request is not started before its arrival time.  Host
-    staging is pinned and resident, as in :class:`SortServer`.  Returns
-    ``(results, latencies_s, wall_s)``.
+    ``requests`` is a list of ``(arrival_offset_s, keys, vals_or_None)``, keys
+    and values host arrays or CUDA tensors (no copies then); with ``realtime``
+    a request is not started before its arrival time.  Host staging is pinned
+    and resident, as in :class:`SortServer`.  Returns ``(results,
+    latencies_s, wall_s)``.
     """
     dev = torch.device(device)
     ws = api.Workspace(dev)
@@ -356,6 +402,18 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True):
         if realtime:
             _wait_until(t0 + arr)
         arrival = t0 + arr if realtime else time.perf_counter()
+        if isinstance(keys, torch.Tensor):  # device request: sort into fresh device outputs
+            ko = torch.empty_like(keys)
+            if vals is not None:
+                vo = torch.empty_like(vals)
+                api.sort_pairs_u32(keys, vals, ko, vo, workspace=ws)
+                res = (ko, vo)
+            else:
+                res = api.sort_u32(keys, out=ko, workspace=ws)
+            torch.cuda.synchronize(dev)
+            lat.append(time.perf_counter() - arrival)
+            out.append(res)
+            continue
         n = keys.size
         hkk, dkk, rkk, okk = hk.get(n), dk.get(n), rk.get(n), ok.get(n)
         hkk.copy_(torch.from_numpy(keys))
@@ -394,16 +452,22 @@ def latency_stats(lat_s):
             "mean_ms": round(float(a.mean()), 3), "max_ms": round(float(a.max()), 3)}
 
 
-def make_requests(count: int, lo: int = 1 << 10, hi: int = 1 << 24, seed: int = 1, pool_keys: int = 1 << 25):
+def make_requests(count: int, lo: int = 1 << 10, hi: int = 1 << 24, seed: int = 1, pool_keys: int = 1 << 25,
+                  device=None):
     """Seeded serving workload: (arrival_at_qps_1, keys, vals_or_None) per request.
 
     Sizes are log-uniform in [lo, hi]; half the requests are key/value pairs
     (value = position in the request); keys are slices of one seeded uniform
-    pool so that the request set is cheap to build.
+    pool so that the request set is cheap to build.  With ``device`` the keys
+    and values are CUDA tensors there (requests already resident in HBM),
+    else numpy arrays.
     """
     import workloads
 
-    pool = workloads.keys_u32("uniform", pool_keys, seed=seed)
+    if device is None:
+        pool = workloads.keys_u32("uniform", pool_keys, seed=seed)
+    else:
+        pool = workloads.keys_u32_torch("uniform", pool_keys, torch.device(device), seed=seed)
     spec = workloads.request_stream(count, qps=1.0, lo=lo, hi=hi, seed=seed)
     offs = workloads.draws_u64(seed ^ 0x0FF, count) % np.uint64(max(1, pool_keys - hi))
     reqs = []
@@ -411,7 +475,10 @@ def make_requests(count: int, lo: int = 1 << 10, hi: int = 1 << 24, seed: int = 
         size = min(size, pool_keys)
         o = int(offs[i])
         keys = pool[o:o + size]
-        vals = np.arange(size, dtype=np.uint32) if pairs else None
+        if device is None:
+            vals = np.arange(size, dtype=np.uint32) if pairs else None
+        else:
+            vals = torch.arange(size, dtype=torch.int32, device=device).view(torch.uint32) if pairs else None
         reqs.append((t, keys, vals))
     return reqs
 
@@ -455,19 +522,23 @@ def _p50(xs):
 
 def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.9, 1.2, 1.6), seed: int = 1, device="cuda:0",
                           hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24,
-                          max_batch_keys: int = 1 << 24):
+                          max_batch_keys: int = 1 << 24, resident: str = "host"):
     """p50/p99 latency and Gkeys/s of the batched server and of the serial
     baseline at fractions of the baseline's saturation request rate (above 1:
     more requests per second than one-at-a-time serving can complete), and
-    both paths' saturation rates (all requests submitted at once)."""
-    reqs = make_requests(count, lo=lo, hi=hi, seed=seed)
-    total_keys = sum(k.size for _, k, _ in reqs)
-    out = {"requests": count, "total_keys": int(total_keys), "sizes": [lo, hi], "pairs_fraction": 0.5,
-           "hbm_budget_bytes": hbm_budget, "runs": []}
-    with SortServer(device, hbm_budget=hbm_budget, max_batch_keys=max_batch_keys,
-                    reserve_keys=min(max(hi, max_batch_keys), total_keys)) as server:
+    both paths' saturation rates (all requests submitted at once).
+
+    ``resident="host"``: requests and results are host arrays (every request
+    crosses PCIe twice); ``"device"``: they are CUDA tensors already in HBM.
+    """
+    reqs = make_requests(count, lo=lo, hi=hi, seed=seed, device=device if resident == "device" else None)
+    total_keys = sum(int(k.numel()) if isinstance(k, torch.Tensor) else k.size for _, k, _ in reqs)
+    out = {"requests": count, "resident": resident, "total_keys": int(total_keys), "sizes": [lo, hi],
+           "pairs_fraction": 0.5, "hbm_budget_bytes": hbm_budget, "runs": []}
+    reserve = 0 if resident == "device" else min(max(hi, max_batch_keys), total_keys)
+    with SortServer(device, hbm_budget=hbm_budget, max_batch_keys=max_batch_keys, reserve_keys=reserve) as server:
         # warm up both paths over the whole request set (library load, buffer growth)
-        _, _, sat_wall = serve_serial(reqs, device, realtime=False)
+        serve_serial(reqs, device, realtime=False)
         serve_batched(reqs, qps=1e9, server=server)
         _, _, sat_wall = serve_serial(reqs, device, realtime=False)
         sat_qps = count / sat_wall

@@ -74,3 +74,38 @@ def test_serving_benchmark_small(serve):
     run = out["runs"][0]
     assert run["batched"]["p99_ms"] > 0 and run["serial"]["p99_ms"] > 0
     assert run["batched"]["peak_hbm_bytes"] <= out["hbm_budget_bytes"]
+
+
+def test_device_requests_mixed_with_host(serve):
+    """Device-resident requests (CUDA tensors in, CUDA tensors out) batched
+    together with host requests; every result equals the oracle's."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    reqs = _requests(24, seed=9)
+    with serve.SortServer(hbm_budget=1 << 30, solo_keys=1 << 16) as srv:
+        with srv.held():
+            futs = []
+            for i, (_, k, v) in enumerate(reqs):
+                if i % 2:
+                    kd = torch.from_numpy(k).to(dev)
+                    vd = torch.from_numpy(v).to(dev) if v is not None else None
+                    futs.append(srv.submit(kd, vd))
+                else:
+                    futs.append(srv.submit(k, v))
+        got = [f.result(timeout=120) for f in futs]
+        assert srv.batches == 1
+    for i, ((_, k, v), g) in enumerate(zip(reqs, got)):
+        if v is None:
+            g = g.cpu().numpy() if i % 2 else g
+            assert np.array_equal(g, oracle.sort_u32(k))
+        else:
+            gk, gv = (g[0].cpu().numpy(), g[1].cpu().numpy()) if i % 2 else g
+            wk, wv = oracle.sort_pairs_u32(k, v)
+            assert np.array_equal(gk, wk) and np.array_equal(gv, wv)
+
+
+def test_device_serving_benchmark_small(serve):
+    out = serve.run_serving_benchmark(count=40, fracs=(0.8,), lo=1 << 10, hi=1 << 18, resident="device")
+    run = out["runs"][0]
+    assert run["batched"]["p99_ms"] > 0 and run["serial"]["p99_ms"] > 0
