@@ -436,14 +436,15 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True):
 
 
 def _wait_until(at: float):
-    """Sleep, then spin for the last half millisecond (a spinning thread holds
-    the GIL, so long waits must sleep to let the scheduler thread run)."""
+    """Wait until perf_counter() reaches `at` without holding the GIL: sleep
+    most of the way, then poll with zero-length sleeps (each one lets the
+    server's threads take the GIL; a plain spin would hold it for a whole
+    switch interval, 5 ms by default, and stall them)."""
     while True:
         left = at - time.perf_counter()
         if left <= 0:
             return
-        if left > 1e-3:
-            time.sleep(left - 5e-4)
+        time.sleep(left - 1e-4 if left > 2e-4 else 0)
 
 
 def latency_stats(lat_s):
