@@ -90,6 +90,28 @@ def _kernel_table(stats):
     }
 
 
+def bench_small(bcf, workloads, torch, dev, n=1 << 16, reps=100, warmup=10):
+    """2^16 uniform u32 (fits in L2: latency-bound): median device time of one
+    sort over `reps` runs, each bracketed by HIP events."""
+    keys = workloads.keys_u32_torch("uniform", n, dev, seed=1)
+    out = torch.empty_like(keys)
+    ws = bcf.Workspace(dev)
+    for _ in range(warmup):
+        bcf.sort_u32(keys, out=out, workspace=ws)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        bcf.sort_u32(keys, out=out, workspace=ws)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e3)
+    times.sort()
+    med = times[len(times) // 2]
+    return {"n": n, "median_us": round(med, 2), "p10_us": round(times[reps // 10], 2),
+            "Gkeys_per_s": round(n / med / 1e3, 3), "passes": bcf.sort_passes(n)}
+
+
 def bench_pairs(bcf, workloads, torch, dev, n=1 << 28, steps=5, warmup=2):
     """2^28 stable key/value sorts (value = original index), uniform and Zipf keys."""
     from paper_1306_5076_amd import autotune
@@ -320,6 +342,7 @@ def main():
         del src, out
         torch.cuda.empty_cache()
         t0s = time.perf_counter()
+        rec["small_2p16"] = bench_small(bcf, workloads, torch, dev)
         rec["pairs_2p28"] = bench_pairs(bcf, workloads, torch, dev)
         torch.cuda.empty_cache()
         rec["segmented"] = bench_segmented(bcf, workloads, torch, dev)
@@ -329,7 +352,7 @@ def main():
         from paper_1306_5076_amd import serve
 
         rec["serving"] = serve.run_serving_benchmark(count=400, device=str(dev))
-        rec["serving_device"] = serve.run_serving_benchmark(count=400, device=str(dev), resident="device")
+        rec["serving_device"] = serve.run_serving_benchmark(count=2000, device=str(dev), resident="device")
         rec["sections_s"] = round(time.perf_counter() - t0s, 1)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(host["uniform"])

@@ -521,7 +521,7 @@ def _p50(xs):
     return round(float(np.median(xs)) * 1e3, 3) if xs else 0.0
 
 
-def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.9, 1.2, 1.6), seed: int = 1, device="cuda:0",
+def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.8, 0.95, 1.5), seed: int = 1, device="cuda:0",
                           hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24,
                           max_batch_keys: int = 1 << 24, resident: str = "host"):
     """p50/p99 latency and Gkeys/s of the batched server and of the serial
