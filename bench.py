@@ -112,6 +112,33 @@ def bench_small(bcf, workloads, torch, dev, n=1 << 16, reps=100, warmup=10):
             "Gkeys_per_s": round(n / med / 1e3, 3), "passes": bcf.sort_passes(n)}
 
 
+def bench_block_sorts(bcf, workloads, torch, dev, n=1 << 26, reps=5):
+    """Ablation of the block sort at 2^26 uniform keys: group tiles sorted by
+    merge rounds (default), wave tiles sorted by merge rounds, wave tiles sorted
+    by the paper's ShearSort (Sec. 3.1); whole sort and the block-sort kernel."""
+    from paper_1306_5076_amd import autotune
+
+    keys = workloads.keys_u32_torch("uniform", n, dev, seed=1)
+    out = torch.empty_like(keys)
+    ws = bcf.Workspace(dev)
+    res = {"n": n}
+    names = {0: "group_merge_rounds", 1: "wave_merge_rounds", 2: "wave_shearsort"}
+    for v, name in names.items():
+        with bcf.tuning(block_sort=v):
+            fn = lambda: bcf.sort_u32(keys, out=out, workspace=ws)
+            ms = autotune.time_ms(fn, reps=reps, warmup=1)
+            bcf.profile_collect()
+            bcf.profile_enable(True)
+            fn()
+            bcf.profile_enable(False)
+            st = bcf.profile_collect()
+            bs = st.get("block_sort_keys", {"total_ms": 0.0, "launches": 1})
+            res[name] = {"sort_ms": round(ms, 4), "Gkeys_per_s": round(n / ms / 1e6, 3),
+                         "run_keys": bcf.run_keys(), "passes": bcf.sort_passes(n),
+                         "block_sort_us": round(bs["total_ms"] * 1e3 / max(1, bs["launches"]), 1)}
+    return res
+
+
 def bench_pairs(bcf, workloads, torch, dev, n=1 << 28, steps=5, warmup=2):
     """2^28 stable key/value sorts (value = original index), uniform and Zipf keys."""
     from paper_1306_5076_amd import autotune
@@ -343,6 +370,7 @@ def main():
         torch.cuda.empty_cache()
         t0s = time.perf_counter()
         rec["small_2p16"] = bench_small(bcf, workloads, torch, dev)
+        rec["block_sort_ablation"] = bench_block_sorts(bcf, workloads, torch, dev)
         rec["pairs_2p28"] = bench_pairs(bcf, workloads, torch, dev)
         torch.cuda.empty_cache()
         rec["segmented"] = bench_segmented(bcf, workloads, torch, dev)

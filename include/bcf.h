@@ -133,8 +133,9 @@ const char *bcf_status_string(bcf_status s);
 uint32_t bcf_tile_keys(void);
 
 /* Length of the sorted runs the block sort of bcf_sort_u32 (pairs = 0) or
- * bcf_sort_pairs_u32 (pairs = 1) hands to the merge passes: one work-group of
- * several waves sorts that many keys in LDS. */
+ * bcf_sort_pairs_u32 (pairs = 1) hands to the merge passes under the current
+ * tuning: with the default block sort one work-group of several waves sorts
+ * that many keys in LDS (32768 keys, 16384 pairs); with wave tiles 4096. */
 uint32_t bcf_run_keys(int pairs);
 
 /* Passes over the data in HBM of a sort of n keys: the block sort plus
@@ -147,7 +148,7 @@ uint32_t bcf_sort_passes(uint64_t n, int pairs);
  * Process-wide tuning knobs (read by every later call; not per stream).
  * Initial values come from environment variables read once, at the first
  * call into the library: BCF_MERGE_MODE, BCF_NT, BCF_NO_SAMPLES,
- * BCF_TILE_SAMPLES, BCF_SEG_GROUP_MIN, BCF_CHECK.  The autotuner sets them
+ * BCF_TILE_SAMPLES, BCF_SEG_GROUP_MIN, BCF_CHECK, BCF_BLOCK_SORT.  The autotuner sets them
  * through bcf_set_tuning.  Calls that are in flight on other threads when the
  * knobs change may use either setting; results are identical either way.
  */
@@ -163,10 +164,15 @@ typedef struct {
     uint64_t group_min_keys;   /* segmented sorts: segments of at least this many keys are
                                   block-sorted by multi-wave work-groups; 0 = library default */
     int32_t check_runs;        /* 1: bcf_merge_runs checks that every run is sorted */
+    int32_t block_sort;        /* block sort of bcf_sort_u32 / bcf_sort_pairs_u32: 0 (default)
+                                  multi-wave group tiles sorted by merge rounds (runs of
+                                  bcf_run_keys); 1 wave tiles sorted by merge rounds; 2 wave
+                                  tiles sorted by the paper's ShearSort (Sec. 3.1); 1 and 2
+                                  hand runs of 4096 keys to the merge passes */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);
-/* BCF_ERR_INVALID for a NULL pointer or an out-of-range merge_variant. */
+/* BCF_ERR_INVALID for a NULL pointer or an out-of-range merge_variant or block_sort. */
 bcf_status bcf_set_tuning(const bcf_tuning *in);
 
 /*

@@ -59,6 +59,7 @@ class Tuning(ctypes.Structure):
         ("tile_samples", ctypes.c_int32),
         ("group_min_keys", ctypes.c_uint64),
         ("check_runs", ctypes.c_int32),
+        ("block_sort", ctypes.c_int32),
     ]
 
 

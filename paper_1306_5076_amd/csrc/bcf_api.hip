@@ -154,6 +154,9 @@ Tuning &tuning_locked()
         const char *e = std::getenv("BCF_SEG_GROUP_MIN");
         g_tune.group_min_keys = (e && *e) ? std::strtoull(e, nullptr, 10) : 0;
         g_tune.check_runs = env_int("BCF_CHECK", 0) == 1;
+        g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
+        if (g_tune.block_sort < 0 || g_tune.block_sort > 2)
+            g_tune.block_sort = 0;
         g_tune_init = true;
     }
     return g_tune;
@@ -180,13 +183,20 @@ bool offsets_valid(const uint64_t *off, uint32_t k)
 
 // Sort keys (and values) with the regular plan.  temp holds the ping-pong
 // key buffer followed by the value buffer.
+// Length of the sorted runs the block sort of a regular sort produces.
+uint64_t sort_run_keys(bool pairs, const Tuning &tu)
+{
+    return tu.block_sort == 0 ? group_run_keys(pairs) : (uint64_t)kTile;
+}
+
 bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                      uint64_t n, void *temp, uint64_t *temp_bytes, hipStream_t s)
 {
     if (!temp_bytes || n > kMaxN)
         return BCF_ERR_INVALID;
     const uint64_t tiles = tiles_of(n);
-    const uint64_t run0 = group_run_keys(pairs);  // sorted run length after the block sort
+    const Tuning tu = tuning();
+    const uint64_t run0 = sort_run_keys(pairs, tu);  // sorted run length after the block sort
     const uint32_t passes = n ? ceil_log2((n + run0 - 1) / run0) : 0;
     // temp: ping-pong keys [, values], one split per merge tile, then two
     // sets of key samples (each pass reads one set and writes the other)
@@ -207,7 +217,6 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     uint32_t *kt = static_cast<uint32_t *>(temp);
     uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + align256(n * 4)) : nullptr;
     uint32_t *splits = reinterpret_cast<uint32_t *>(static_cast<char *>(temp) + data);
-    const Tuning tu = tuning();
     const bool tile_samples = tu.tile_samples;
     auto sample_set = [&](uint32_t k) {
         char *b = static_cast<char *>(temp) + data + align256(tiles * 4) + k * set_bytes;
@@ -228,8 +237,12 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     const double elem_bytes = pairs ? 8.0 : 4.0;
     {
         ProfScope p(kname_block_sort(pairs, false), s, 2.0 * elem_bytes * n);
-        BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n,
-                                                   (passes && sampled) ? sample_set(0) : none, s)));
+        const SampleSet smp = (passes && sampled) ? sample_set(0) : none;
+        if (tu.block_sort == 0)
+            BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, smp, s)));
+        else
+            BCF_TRY(dev_status(launch_block_sort_regular(pairs, tu.block_sort == 2, kin, vin, kbuf(0),
+                                                         pairs ? vbuf(0) : nullptr, n, smp, s)));
     }
     uint64_t run = run0;
     for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
@@ -510,13 +523,13 @@ const char *bcf_status_string(bcf_status s)
 
 uint32_t bcf_tile_keys(void) { return (uint32_t)kTile; }
 
-uint32_t bcf_run_keys(int pairs) { return group_run_keys(pairs != 0); }
+uint32_t bcf_run_keys(int pairs) { return sort_run_keys(pairs != 0, tuning()); }
 
 uint32_t bcf_sort_passes(uint64_t n, int pairs)
 {
     if (n == 0)
         return 0;
-    const uint64_t run0 = group_run_keys(pairs != 0);
+    const uint64_t run0 = sort_run_keys(pairs != 0, tuning());
     return 1 + ceil_log2((n + run0 - 1) / run0);
 }
 
@@ -683,11 +696,12 @@ void bcf_get_tuning(bcf_tuning *out)
     out->tile_samples = t.tile_samples;
     out->group_min_keys = t.group_min_keys;
     out->check_runs = t.check_runs;
+    out->block_sort = t.block_sort;
 }
 
 bcf_status bcf_set_tuning(const bcf_tuning *in)
 {
-    if (!in || in->merge_variant < 0 || in->merge_variant > 3)
+    if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 2)
         return BCF_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_tune_mu);
     Tuning &t = tuning_locked();
@@ -697,6 +711,7 @@ bcf_status bcf_set_tuning(const bcf_tuning *in)
     t.tile_samples = in->tile_samples != 0;
     t.group_min_keys = in->group_min_keys;
     t.check_runs = in->check_runs != 0;
+    t.block_sort = in->block_sort;
     return BCF_OK;
 }
 

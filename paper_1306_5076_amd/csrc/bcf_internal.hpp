@@ -57,8 +57,11 @@ uint32_t group_run_keys(bool pairs);
 hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin,
                                    uint32_t *kout, uint32_t *vout, uint64_t n, SampleSet out_smp,
                                    hipStream_t s);
-hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint32_t *vin,
-                                     uint32_t *kout, uint32_t *vout, uint64_t n, hipStream_t s);
+// Wave tiles of 4096 keys (runs of 4096), sorted by merge rounds or, with
+// shear, by the paper's ShearSort; writes the samples of its output (out_smp).
+hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin, const uint32_t *vin,
+                                     uint32_t *kout, uint32_t *vout, uint64_t n, SampleSet out_smp,
+                                     hipStream_t s);
 // A merge pass is two launches: with partition = true the split of every
 // tile is written to `splits` (one u32 per tile of the pass); with
 // partition = false the tiles are merged using those splits.
@@ -81,6 +84,7 @@ hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev,
 
 // Current process-wide tuning (see bcf_tuning in bcf.h); a copy.
 struct Tuning {
+    int block_sort;  // 0 group tiles (merge rounds), 1 wave tiles (merge rounds), 2 wave tiles (ShearSort)
     int merge_variant;
     bool nontemporal;
     bool sampled_partition;

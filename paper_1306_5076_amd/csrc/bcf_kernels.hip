@@ -193,6 +193,32 @@ __device__ __forceinline__ void sort_tile(Lines<P> &t, uint32_t *lds, uint32_t l
     to_strided(t, lds, lane);
 }
 
+// The paper's base case (Sec. 3.1, Algorithm 1): ShearSort of the 64 x 64
+// tile, kept as an alternative to the merge rounds.  The grid's rows are the
+// lines lanes hold in BLOCKED layout, its columns the lines they hold in
+// STRIDED layout, so every line sort is Batcher's network on one lane's
+// registers and every switch between rows and columns is one conflict-free
+// transpose.  log2(64) = 6 iterations of (rows in snake order: odd rows
+// descending, by complementing; columns ascending) leave the grid sorted in
+// snake order except inside rows; a last ascending row sort then orders it
+// row-major.  13 line sorts of 543 comparators and 12 transposes, against
+// 8.5 line sorts' worth of comparators and 12 transposes for the merge rounds.
+// Entry: the loaded STRIDED registers re-read as BLOCKED; exit: BLOCKED.
+template <bool P>
+__device__ __forceinline__ void shear_sort_blocked(Lines<P> &t, uint32_t *lds, uint32_t lane)
+{
+#pragma unroll 1
+    for (int it = 0; it < 6; ++it) {
+        flip(t, lane);
+        oe_sort<0, kLine - 1, P>(t);
+        flip(t, lane);
+        to_strided(t, lds, lane);
+        oe_sort<0, kLine - 1, P>(t);
+        to_blocked(t, lds, lane);
+    }
+    oe_sort<0, kLine - 1, P>(t);
+}
+
 // ------------------------------------------------------ group (multi-wave) sort
 //
 // NW waves of a work-group (NW = 2^LW) sort a group tile of NW * 4096 keys:
@@ -433,6 +459,8 @@ struct RegularSortSrc {
     uint32_t *kout, *vout;
     uint64_t n;
     uint32_t ntiles;
+    SampleSet out_smp;
+    __device__ uint64_t pos(uint32_t t) const { return (uint64_t)t * kTile; }
     __device__ SortItem get(uint32_t t) const
     {
         const uint64_t start = (uint64_t)t * kTile;
@@ -451,6 +479,8 @@ struct TableSortSrc {
     Bufs kb, vb;
     const BlockTile *tiles;
     uint32_t ntiles;
+    SampleSet out_smp;  // always empty: table tiles start anywhere
+    __device__ uint64_t pos(uint32_t) const { return 0; }
     __device__ SortItem get(uint32_t t) const
     {
         const BlockTile d = tiles[t];
@@ -564,7 +594,24 @@ __device__ __forceinline__ MergeTask<P> merge_task(const Src &src, const uint32_
 // holds 64-bit elements, twice the registers, so pairs process one tile at a
 // time).
 
-template <bool P, class Src>
+// Everything of a wave tile after it is in registers: sort (merge rounds, or
+// the paper's ShearSort when SHEAR), samples, values, store.
+template <bool P, bool SHEAR, class Src>
+__device__ __forceinline__ void wave_tile(Lines<P> &a, const SortItem &it, const Src &src, uint32_t t, uint32_t *lds,
+                                          uint32_t lane)
+{
+    if constexpr (SHEAR)
+        shear_sort_blocked<P>(a, lds, lane);
+    else
+        sort_tile_blocked<P>(a, lds, lane);
+    write_samples<P>(a, src.out_smp, src.pos(t), it.count, lane);
+    to_strided(a, lds, lane);
+    if constexpr (P)
+        permute_values_lds(a, it.vs, it.count, lds, 0, it.count, lane, wave_lds_fence);
+    store_tile<P>(a, it.kd, it.vd, it.count, lane);
+}
+
+template <bool P, class Src, bool SHEAR = false>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
 {
     __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
@@ -581,9 +628,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
             const SortItem it = src.get(t);
             Lines<P> a;
             load_tile<P>(a, it.ks, it.count, ln);
-            sort_tile<P>(a, lds, ln);
-            permute_values_lds(a, it.vs, it.count, lds, 0, it.count, ln, wave_lds_fence);
-            store_tile<P>(a, it.kd, it.vd, it.count, ln);
+            wave_tile<P, SHEAR>(a, it, src, t, lds, ln);
         }
     } else {
         Lines<P> a, b;
@@ -597,8 +642,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
                 ib = src.get(tb);
                 load_tile<P>(b, ib.ks, ib.count, ln);
             }
-            sort_tile<P>(a, lds, ln);
-            store_tile<P>(a, ia.kd, ia.vd, ia.count, ln);
+            wave_tile<P, SHEAR>(a, ia, src, t, lds, ln);
             if (!hb)
                 break;
             ln = opaque(lane);
@@ -608,8 +652,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
                 ia = src.get(t);
                 load_tile<P>(a, ia.ks, ia.count, ln);
             }
-            sort_tile<P>(b, lds, ln);
-            store_tile<P>(b, ib.kd, ib.vd, ib.count, ln);
+            wave_tile<P, SHEAR>(b, ib, src, tb, lds, ln);
             if (!ha)
                 break;
         }
@@ -934,12 +977,17 @@ static uint32_t persistent_groups(K kernel, uint64_t tiles)
 }
 
 template <bool P, class Src>
-static hipError_t launch_sort(const Src &src, hipStream_t s)
+static hipError_t launch_sort(const Src &src, hipStream_t s, bool shear = false)
 {
     if (src.ntiles == 0)
         return hipSuccess;
-    const dim3 grid(persistent_groups(k_block_sort<P, Src>, src.ntiles)), block(kWave * kWavesPerGroup);
-    hipLaunchKernelGGL((k_block_sort<P, Src>), grid, block, 0, s, src);
+    if (shear) {
+        const dim3 grid(persistent_groups(k_block_sort<P, Src, true>, src.ntiles)), block(kWave * kWavesPerGroup);
+        hipLaunchKernelGGL((k_block_sort<P, Src, true>), grid, block, 0, s, src);
+    } else {
+        const dim3 grid(persistent_groups(k_block_sort<P, Src>, src.ntiles)), block(kWave * kWavesPerGroup);
+        hipLaunchKernelGGL((k_block_sort<P, Src>), grid, block, 0, s, src);
+    }
     return hipGetLastError();
 }
 
@@ -980,12 +1028,12 @@ static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream
     }
 }
 
-hipError_t launch_block_sort_regular(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
-                                     uint32_t *vout, uint64_t n, hipStream_t s)
+hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                                     uint32_t *vout, uint64_t n, SampleSet out_smp, hipStream_t s)
 {
     RegularSortSrc src{kin, pairs ? vin : nullptr, kout, pairs ? vout : nullptr, n,
-                       (uint32_t)((n + kTile - 1) / kTile)};
-    return pairs ? launch_sort<true>(src, s) : launch_sort<false>(src, s);
+                       (uint32_t)((n + kTile - 1) / kTile), out_smp};
+    return pairs ? launch_sort<true>(src, s, shear) : launch_sort<false>(src, s, shear);
 }
 
 static uint32_t cu_count()
@@ -1064,7 +1112,7 @@ hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile
 {
     if (!pairs)
         vb = Bufs{nullptr, nullptr, nullptr};
-    TableSortSrc src{kb, vb, tiles, ntiles};
+    TableSortSrc src{kb, vb, tiles, ntiles, SampleSet{nullptr, nullptr, nullptr, nullptr}};
     return pairs ? launch_sort<true>(src, s) : launch_sort<false>(src, s);
 }
 

@@ -383,14 +383,15 @@ class SortServer:
         slot.done = ev
 
 
-def serve_serial(requests, device="cuda:0", realtime: bool = True):
+def serve_serial(requests, device="cuda:0", realtime: bool = True, keep_results: bool = True):
     """Baseline: each request alone (copy in, sort, copy out, synchronise), FIFO.
 
     ``requests`` is a list of ``(arrival_offset_s, keys, vals_or_None)``, keys
     and values host arrays or CUDA tensors (no copies then); with ``realtime``
     a request is not started before its arrival time.  Host staging is pinned
     and resident, as in :class:`SortServer`.  Returns ``(results,
-    latencies_s, wall_s)``.
+    latencies_s, wall_s)``; without ``keep_results`` each result is dropped
+    once complete (a client that consumes its results; memory stays flat).
     """
     dev = torch.device(device)
     ws = api.Workspace(dev)
@@ -412,7 +413,7 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True):
                 res = api.sort_u32(keys, out=ko, workspace=ws)
             torch.cuda.synchronize(dev)
             lat.append(time.perf_counter() - arrival)
-            out.append(res)
+            out.append(res if keep_results else None)
             continue
         n = keys.size
         hkk, dkk, rkk, okk = hk.get(n), dk.get(n), rk.get(n), ok.get(n)
@@ -431,7 +432,7 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True):
         torch.cuda.synchronize(dev)
         res = (okk.clone().numpy(), ovv.clone().numpy()) if vals is not None else okk.clone().numpy()
         lat.append(time.perf_counter() - arrival)
-        out.append(res)
+        out.append(res if keep_results else None)
     return out, lat, time.perf_counter() - t0
 
 
@@ -484,10 +485,12 @@ def make_requests(count: int, lo: int = 1 << 10, hi: int = 1 << 24, seed: int = 
     return reqs
 
 
-def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 << 30, server=None):
+def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 << 30, server=None,
+                  keep_results: bool = True):
     """Submit ``requests`` at their arrival times (scaled to ``qps``) to a
     :class:`SortServer` (``server``, else a new one); returns
-    (results, latencies_s, wall_s, server stats)."""
+    (results, latencies_s, wall_s, server stats).  Without ``keep_results``
+    every result is dropped as soon as it is complete (results are None)."""
     own = server is None
     if own:
         server = SortServer(device, hbm_budget=hbm_budget)
@@ -498,7 +501,10 @@ def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 <<
         at = t0 + t / qps
         _wait_until(at)
         arrivals.append(at)
-        futs.append(server.submit(keys, vals, arrival=at))
+        f = server.submit(keys, vals, arrival=at)
+        if not keep_results:
+            f.add_done_callback(_drop_result)
+        futs.append(f)
     results = [f.result() for f in futs]
     wall = time.perf_counter() - t0
     stats = {"batches": server.batches, "mean_batch": round(float(np.mean(server.batch_sizes)), 2),
@@ -515,6 +521,11 @@ def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 <<
         "unpack": _p50([r.finished - r.done for r in reqs]),
     }
     return results, lat, wall, stats
+
+
+def _drop_result(f):
+    """Done-callback: release a completed future's result (its buffers)."""
+    f._result = None
 
 
 def _p50(xs):
@@ -539,18 +550,18 @@ def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.8, 0.95, 1.5), seed: i
     reserve = 0 if resident == "device" else min(max(hi, max_batch_keys), total_keys)
     with SortServer(device, hbm_budget=hbm_budget, max_batch_keys=max_batch_keys, reserve_keys=reserve) as server:
         # warm up both paths over the whole request set (library load, buffer growth)
-        serve_serial(reqs, device, realtime=False)
-        serve_batched(reqs, qps=1e9, server=server)
-        _, _, sat_wall = serve_serial(reqs, device, realtime=False)
+        serve_serial(reqs, device, realtime=False, keep_results=False)
+        serve_batched(reqs, qps=1e9, server=server, keep_results=False)
+        _, _, sat_wall = serve_serial(reqs, device, realtime=False, keep_results=False)
         sat_qps = count / sat_wall
-        _, _, bsat_wall, _ = serve_batched(reqs, qps=1e9, server=server)
+        _, _, bsat_wall, _ = serve_batched(reqs, qps=1e9, server=server, keep_results=False)
         out["serial_saturation_qps"] = round(sat_qps, 2)
         out["batched_saturation_qps"] = round(count / bsat_wall, 2)
         for frac in fracs:
             qps = frac * sat_qps
             timed = [(t / qps, k, v) for t, k, v in reqs]
-            _, slat, swall = serve_serial(timed, device, realtime=True)
-            _, blat, bwall, bst = serve_batched(reqs, qps=qps, server=server)
+            _, slat, swall = serve_serial(timed, device, realtime=True, keep_results=False)
+            _, blat, bwall, bst = serve_batched(reqs, qps=qps, server=server, keep_results=False)
             out["runs"].append({
                 "qps": round(qps, 2), "frac_of_serial_saturation": frac,
                 "serial": {**latency_stats(slat), "gkeys_per_s": round(total_keys / swall / 1e9, 4)},

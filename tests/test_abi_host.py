@@ -119,13 +119,20 @@ def test_tuning_roundtrip():
 
     before = bcf.get_tuning()
     assert set(before) == {"merge_variant", "nontemporal", "sampled_partition", "tile_samples",
-                           "group_min_keys", "check_runs"}
-    with bcf.tuning(merge_variant=2, group_min_keys=12345, check_runs=1):
+                           "group_min_keys", "check_runs", "block_sort"}
+    assert before["block_sort"] == 0 and before["merge_variant"] == 3
+    with bcf.tuning(merge_variant=2, group_min_keys=12345, check_runs=1, block_sort=2):
         t = bcf.get_tuning()
         assert t["merge_variant"] == 2 and t["group_min_keys"] == 12345 and t["check_runs"] == 1
+        assert t["block_sort"] == 2
+        # wave tiles hand runs of 4096 keys to the merge passes
+        assert bcf.run_keys() == 4096 and bcf.run_keys(pairs=True) == 4096
+        assert bcf.sort_passes(1 << 26) == 1 + 14
     assert bcf.get_tuning() == before
+    assert bcf.run_keys() == 32768 and bcf.sort_passes(1 << 26) == 1 + 11
     from paper_1306_5076_amd import BcfError
 
-    with pytest.raises(BcfError):
-        bcf.set_tuning(merge_variant=7)
+    for bad in ({"merge_variant": 7}, {"block_sort": 3}, {"block_sort": -1}):
+        with pytest.raises(BcfError):
+            bcf.set_tuning(**bad)
     assert bcf.get_tuning() == before

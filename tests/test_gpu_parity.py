@@ -297,6 +297,26 @@ def test_merge_kernel_variants(torch_dev, bcf, mode, nt):
         _check_sorts(torch, dev, bcf)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_block_sort_variants(torch_dev, bcf, variant):
+    """Wave-tile block sorts (merge rounds; the paper's ShearSort) against the
+    oracle: single partial tile, exact tile, ragged multi-tile, many passes,
+    keys and stable pairs, all distributions."""
+    torch, dev = torch_dev
+    with bcf.tuning(block_sort=variant):
+        assert bcf.run_keys() == 4096
+        for n in (1, 100, 4095, 4096, 4097, 3 * 4096 + 17, 40000):
+            for dist in ("uniform", "distinct16", "reverse"):
+                keys = workloads.keys_u32(dist, n, seed=n)
+                got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+                assert first_diff(got, oracle.sort_u32(keys)) is None, (n, dist)
+                kk, vv = workloads.pairs_u32(dist, n, seed=n + 1)
+                ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, kk), to_dev(torch, dev, vv))
+                wk, wv = oracle.sort_pairs_u32(kk, vv)
+                assert first_diff(ko.cpu().numpy(), wk) is None and first_diff(vo.cpu().numpy(), wv) is None
+        _check_sorts(torch, dev, bcf)
+
+
 def _check_sorts(torch, dev, bcf):
     for n, dist in [((1 << 20) + 3, "uniform"), (7 * 4096 + 5, "zipf")]:
         keys = workloads.keys_u32(dist, n, seed=11)

@@ -159,6 +159,29 @@ def sort_tile_model(tile):
     return out
 
 
+def shear_tile_model(tile):
+    """The ShearSort block sort (paper Sec. 3.1, Algorithm 1) as the kernel runs it:
+    rows are BLOCKED lines, columns STRIDED lines; six iterations of (snake row
+    sort, column sort) and a final ascending row sort."""
+    lanes = np.arange(W)
+    regs = np.empty((W, E), dtype=tile.dtype)
+    for r in range(E):
+        regs[:, r] = tile[W * r + lanes]
+    for _ in range(6):
+        flip(regs, lanes)  # odd rows descending (snake)
+        apply(regs, OE64)
+        flip(regs, lanes)
+        regs = fast_to_strided(regs)
+        apply(regs, OE64)  # columns ascending
+        regs = fast_to_blocked(regs)
+    apply(regs, OE64)  # final row sort, ascending: row-major order
+    regs = fast_to_strided(regs)
+    out = np.empty_like(tile)
+    for r in range(E):
+        out[W * r + lanes] = regs[:, r]
+    return out
+
+
 def merge_tile_model(a_piece, b_piece):
     """A ascending at [0, na), B reversed at the end, padding between."""
     na, nb = len(a_piece), len(b_piece)
@@ -464,3 +487,28 @@ def test_corank_from_samples_matches_brute_force(na, nb, levels):
     arr[apos + na:apos + na + nb] = b
     for d in range(0, na + nb, 4096):
         assert corank_sampled(arr, apos, na, nb, d) == corank_brute(a, b, d), d
+
+
+@pytest.mark.parametrize("dist", ["random", "zero_one", "dups", "reverse"])
+def test_shear_sort_schedule_sorts(dist):
+    rng = np.random.default_rng(17)
+    if dist == "random":
+        x = rng.integers(0, 2**32, size=T, dtype=np.uint64).astype(np.uint32)
+    elif dist == "zero_one":
+        x = rng.integers(0, 2, size=T).astype(np.uint32)
+    elif dist == "dups":
+        x = rng.integers(0, 5, size=T).astype(np.uint32)
+    else:
+        x = np.arange(T, dtype=np.uint32)[::-1].copy()
+    assert np.array_equal(shear_tile_model(x), np.sort(x))
+
+
+def test_shear_sort_schedule_01_principle_sampled():
+    # ShearSort needs ceil(log2 64) = 6 iterations plus the final row phase
+    # (2 log w + 1 line sorts, Sec. 3.1); 0-1 inputs with every count of ones
+    # near the ends and random counts in between
+    rng = np.random.default_rng(19)
+    for ones in list(range(0, 70)) + list(range(T - 70, T + 1)) + list(rng.integers(0, T, 40)):
+        x = np.zeros(T, dtype=np.uint32)
+        x[rng.permutation(T)[:ones]] = 1
+        assert np.array_equal(shear_tile_model(x), np.sort(x))
