@@ -122,7 +122,7 @@ def bench_block_sorts(bcf, workloads, torch, dev, n=1 << 26, reps=5):
     out = torch.empty_like(keys)
     ws = bcf.Workspace(dev)
     res = {"n": n}
-    names = {0: "group_merge_rounds", 1: "wave_merge_rounds", 2: "wave_shearsort"}
+    names = {3: "group_merge_rounds", 1: "wave_merge_rounds", 2: "wave_shearsort"}
     for v, name in names.items():
         with bcf.tuning(block_sort=v):
             fn = lambda: bcf.sort_u32(keys, out=out, workspace=ws)

@@ -132,10 +132,11 @@ const char *bcf_status_string(bcf_status s);
  * 4096 = 64 x 64 keys at a time. */
 uint32_t bcf_tile_keys(void);
 
-/* Length of the sorted runs the block sort of bcf_sort_u32 (pairs = 0) or
- * bcf_sort_pairs_u32 (pairs = 1) hands to the merge passes under the current
- * tuning: with the default block sort one work-group of several waves sorts
- * that many keys in LDS (32768 keys, 16384 pairs); with wave tiles 4096. */
+/* Length of the sorted runs the block sort of a large bcf_sort_u32 (pairs = 0)
+ * or bcf_sort_pairs_u32 (pairs = 1) hands to the merge passes under the current
+ * tuning: with group tiles one work-group of several waves sorts that many keys
+ * in LDS (32768 keys, 16384 pairs); with wave tiles 4096.  Under the default
+ * tuning, sorts of at most 2^19 keys use wave tiles (see bcf_tuning). */
 uint32_t bcf_run_keys(int pairs);
 
 /* Passes over the data in HBM of a sort of n keys: the block sort plus
@@ -165,10 +166,11 @@ typedef struct {
                                   block-sorted by multi-wave work-groups; 0 = library default */
     int32_t check_runs;        /* 1: bcf_merge_runs checks that every run is sorted */
     int32_t block_sort;        /* block sort of bcf_sort_u32 / bcf_sort_pairs_u32: 0 (default)
-                                  multi-wave group tiles sorted by merge rounds (runs of
-                                  bcf_run_keys); 1 wave tiles sorted by merge rounds; 2 wave
-                                  tiles sorted by the paper's ShearSort (Sec. 3.1); 1 and 2
-                                  hand runs of 4096 keys to the merge passes */
+                                  3 for sorts of more than 2^19 keys, else 1; 1 wave tiles
+                                  sorted by merge rounds; 2 wave tiles sorted by the paper's
+                                  ShearSort (Sec. 3.1); 3 multi-wave group tiles sorted by
+                                  merge rounds.  Wave tiles hand runs of 4096 keys to the
+                                  merge passes, group tiles runs of 32768 keys (16384 pairs) */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);

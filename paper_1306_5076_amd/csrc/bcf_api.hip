@@ -155,7 +155,7 @@ Tuning &tuning_locked()
         g_tune.group_min_keys = (e && *e) ? std::strtoull(e, nullptr, 10) : 0;
         g_tune.check_runs = env_int("BCF_CHECK", 0) == 1;
         g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
-        if (g_tune.block_sort < 0 || g_tune.block_sort > 2)
+        if (g_tune.block_sort < 0 || g_tune.block_sort > 3)
             g_tune.block_sort = 0;
         g_tune_init = true;
     }
@@ -183,10 +183,22 @@ bool offsets_valid(const uint64_t *off, uint32_t k)
 
 // Sort keys (and values) with the regular plan.  temp holds the ping-pong
 // key buffer followed by the value buffer.
-// Length of the sorted runs the block sort of a regular sort produces.
-uint64_t sort_run_keys(bool pairs, const Tuning &tu)
+// Sorts of at most this many keys take wave tiles under the default (auto)
+// block sort: a group tile occupies one CU for the whole block sort, so a
+// sort with fewer groups than CUs finishes sooner with 8x more, smaller
+// tiles and a few more (short) merge passes.
+constexpr uint64_t kAutoWaveTilesMaxN = 1ull << 19;
+
+// Whether the block sort of an n-key regular sort uses multi-wave group tiles.
+bool sort_uses_groups(uint64_t n, const Tuning &tu)
 {
-    return tu.block_sort == 0 ? group_run_keys(pairs) : (uint64_t)kTile;
+    return tu.block_sort == 3 || (tu.block_sort == 0 && n > kAutoWaveTilesMaxN);
+}
+
+// Length of the sorted runs the block sort of an n-key regular sort produces.
+uint64_t sort_run_keys(bool pairs, uint64_t n, const Tuning &tu)
+{
+    return sort_uses_groups(n, tu) ? group_run_keys(pairs) : (uint64_t)kTile;
 }
 
 bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
@@ -196,7 +208,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
         return BCF_ERR_INVALID;
     const uint64_t tiles = tiles_of(n);
     const Tuning tu = tuning();
-    const uint64_t run0 = sort_run_keys(pairs, tu);  // sorted run length after the block sort
+    const uint64_t run0 = sort_run_keys(pairs, n, tu);  // sorted run length after the block sort
     const uint32_t passes = n ? ceil_log2((n + run0 - 1) / run0) : 0;
     // temp: ping-pong keys [, values], one split per merge tile, then two
     // sets of key samples (each pass reads one set and writes the other)
@@ -238,7 +250,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     {
         ProfScope p(kname_block_sort(pairs, false), s, 2.0 * elem_bytes * n);
         const SampleSet smp = (passes && sampled) ? sample_set(0) : none;
-        if (tu.block_sort == 0)
+        if (sort_uses_groups(n, tu))
             BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, smp, s)));
         else
             BCF_TRY(dev_status(launch_block_sort_regular(pairs, tu.block_sort == 2, kin, vin, kbuf(0),
@@ -523,13 +535,13 @@ const char *bcf_status_string(bcf_status s)
 
 uint32_t bcf_tile_keys(void) { return (uint32_t)kTile; }
 
-uint32_t bcf_run_keys(int pairs) { return sort_run_keys(pairs != 0, tuning()); }
+uint32_t bcf_run_keys(int pairs) { return sort_run_keys(pairs != 0, ~0ull, tuning()); }
 
 uint32_t bcf_sort_passes(uint64_t n, int pairs)
 {
     if (n == 0)
         return 0;
-    const uint64_t run0 = sort_run_keys(pairs != 0, tuning());
+    const uint64_t run0 = sort_run_keys(pairs != 0, n, tuning());
     return 1 + ceil_log2((n + run0 - 1) / run0);
 }
 
@@ -701,7 +713,7 @@ void bcf_get_tuning(bcf_tuning *out)
 
 bcf_status bcf_set_tuning(const bcf_tuning *in)
 {
-    if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 2)
+    if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 3)
         return BCF_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_tune_mu);
     Tuning &t = tuning_locked();

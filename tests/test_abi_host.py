@@ -47,24 +47,26 @@ def q_sort(lib, n, pairs=False):
 def test_tile_run_and_pass_count(lib):
     assert lib.bcf_tile_keys() == 4096
     assert lib.bcf_run_keys(0) == 32768 and lib.bcf_run_keys(1) == 16384
+    small = 1 << 19  # default tuning: wave tiles (runs of 4096) up to 2^19 keys
     for pairs in (0, 1):
         R = lib.bcf_run_keys(pairs)
         assert lib.bcf_sort_passes(0, pairs) == 0
         assert lib.bcf_sort_passes(1, pairs) == 1
-        assert lib.bcf_sort_passes(R, pairs) == 1
-        assert lib.bcf_sort_passes(R + 1, pairs) == 2
-        # Lemma 2: 1 + ceil(log2(n / M)) passes over the data
-        for n in [2**16, 2**20, 2**26, 2**28, 3 * R + 5]:
-            runs = -(-n // R)
+        assert lib.bcf_sort_passes(4096, pairs) == 1
+        assert lib.bcf_sort_passes(4097, pairs) == 2
+        # Lemma 2: 1 + ceil(log2(n / M)) passes over the data, M the block-sort run
+        for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**26, 2**28, 3 * R + 5 + small]:
+            m = 4096 if n <= small else R
+            runs = -(-n // m)
             assert lib.bcf_sort_passes(n, pairs) == 1 + int(np.ceil(np.log2(runs)))
 
 
 def test_temp_queries(lib):
     assert q_sort(lib, 0) == (0, 0)
-    assert q_sort(lib, 32768) == (0, 0)  # one sorted run: no merge pass, no temp
-    assert q_sort(lib, 16384, pairs=True) == (0, 0)
-    st, need = q_sort(lib, 32769)
-    assert st == 0 and need >= 32769 * 4 and need % 256 == 0
+    assert q_sort(lib, 4096) == (0, 0)  # one sorted run: no merge pass, no temp
+    assert q_sort(lib, 4096, pairs=True) == (0, 0)
+    st, need = q_sort(lib, 4097)
+    assert st == 0 and need >= 4097 * 4 and need % 256 == 0
     st, need = q_sort(lib, 2**26, pairs=True)
     # two ping-pong arrays (keys, values), one u32 split per merge tile, and
     # two sets of key samples (every 64-block: first and last; every tile: first and last)
@@ -130,9 +132,13 @@ def test_tuning_roundtrip():
         assert bcf.sort_passes(1 << 26) == 1 + 14
     assert bcf.get_tuning() == before
     assert bcf.run_keys() == 32768 and bcf.sort_passes(1 << 26) == 1 + 11
+    # default block sort: wave tiles up to 2^19 keys, group tiles above
+    assert bcf.sort_passes(1 << 19) == 1 + 7 and bcf.sort_passes((1 << 19) + 1) == 1 + 5
+    with bcf.tuning(block_sort=3):
+        assert bcf.sort_passes(1 << 16) == 1 + 1 and bcf.sort_passes(1 << 15) == 1
     from paper_1306_5076_amd import BcfError
 
-    for bad in ({"merge_variant": 7}, {"block_sort": 3}, {"block_sort": -1}):
+    for bad in ({"merge_variant": 7}, {"block_sort": 4}, {"block_sort": -1}):
         with pytest.raises(BcfError):
             bcf.set_tuning(**bad)
     assert bcf.get_tuning() == before

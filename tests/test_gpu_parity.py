@@ -297,14 +297,14 @@ def test_merge_kernel_variants(torch_dev, bcf, mode, nt):
         _check_sorts(torch, dev, bcf)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_block_sort_variants(torch_dev, bcf, variant):
-    """Wave-tile block sorts (merge rounds; the paper's ShearSort) against the
-    oracle: single partial tile, exact tile, ragged multi-tile, many passes,
-    keys and stable pairs, all distributions."""
+    """Block sorts (wave tiles by merge rounds, wave tiles by the paper's
+    ShearSort, group tiles) against the oracle: single partial tile, exact
+    tile, ragged multi-tile, many passes, keys and stable pairs."""
     torch, dev = torch_dev
     with bcf.tuning(block_sort=variant):
-        assert bcf.run_keys() == 4096
+        assert bcf.run_keys() == (32768 if variant == 3 else 4096)
         for n in (1, 100, 4095, 4096, 4097, 3 * 4096 + 17, 40000):
             for dist in ("uniform", "distinct16", "reverse"):
                 keys = workloads.keys_u32(dist, n, seed=n)
