@@ -15,11 +15,14 @@
 //       STRIDED  lane = p mod 64, register = p / 64   (global loads/stores are
 //                coalesced: register r of all lanes is 64 consecutive keys)
 //       BLOCKED  lane = p / 64,   register = p mod 64 (lane owns a run of 64)
-//   * switching layouts goes through LDS with one pad word per 64
-//     (address = p + p/64): STRIDED accesses hit word 65r + lane, BLOCKED ones
-//     65 lane + r, so every 32-lane half touches 32 distinct banks and the
-//     lane-dependent part of the address is a base register while the
-//     register-dependent part is an immediate offset;
+//   * switching layouts goes through LDS with four pad words per 64
+//     (address = p + 4 (p/64)): STRIDED accesses are 4-byte reads and writes
+//     of word 68r + lane, so every 32-lane half touches 32 distinct banks;
+//     BLOCKED accesses move four consecutive registers at once, 16 bytes at
+//     word 68 lane + r (r a multiple of 4): lane l's first bank is
+//     4l + r mod 32, so any 8 consecutive lanes (one pass of 128 bytes) cover
+//     the 32 banks once.  The lane-dependent part of an address is a base
+//     register and the register-dependent part an immediate offset;
 //   * compare-exchanges only ever happen between two registers of one lane, so
 //     the sorting networks themselves issue no LDS traffic at all.
 #pragma once
@@ -32,8 +35,10 @@ namespace bcf {
 constexpr int kWave = 64;              // lanes per wavefront (w)
 constexpr int kLine = 64;              // keys per lane (one line of the w x w tile)
 constexpr int kTile = kWave * kLine;   // 4096 keys per wave tile (w^2)
-constexpr int kLdsStride = kLine + 1;  // 65 words per LDS row: one pad word per 64
+constexpr int kLdsPad = 4;                   // pad words per 64-word LDS row
+constexpr int kLdsStride = kLine + kLdsPad;  // 68 words per LDS row
 constexpr int kLdsWords = kWave * kLdsStride;
+
 constexpr uint32_t kMaxKey = 0xFFFFFFFFu;
 
 // A wave's tile in registers.  Keys only: one 32-bit key per position.
@@ -199,21 +204,49 @@ __device__ __forceinline__ void wave_lds_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// x[r] -> w[S*r] for r = 0..63.  With S = 1 (the BLOCKED side: a lane's
+// registers are consecutive words and the row starts 16-byte aligned) the
+// compiler merges every four registers into one 16-byte store.
+template <int S>
+__device__ __forceinline__ void lds_put(uint32_t *w, const uint32_t (&x)[kLine])
+{
+    if constexpr (S == 1)
+        w = static_cast<uint32_t *>(__builtin_assume_aligned(w, 16));
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        w[S * r] = x[r];
+}
+
+// x[r] <- rd[S*r] for r = 0..63 (S = 1: 16-byte loads).
+template <int S>
+__device__ __forceinline__ void lds_get(uint32_t (&x)[kLine], const uint32_t *rd)
+{
+    if constexpr (S == 1)
+        rd = static_cast<const uint32_t *>(__builtin_assume_aligned(rd, 16));
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = rd[S * r];
+}
+
 // x[r] -> lds[wbase + WS*r], then x[r] <- lds[rbase + RS*r].
 template <int WS, int RS>
 __device__ __forceinline__ void exchange(uint32_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
                                          uint32_t rbase)
 {
-    uint32_t *w = lds + wbase;
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        w[WS * r] = x[r];
+    lds_put<WS>(lds + wbase, x);
     wave_lds_fence();
-    const uint32_t *rd = lds + rbase;
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        x[r] = rd[RS * r];
+    lds_get<RS>(x, lds + rbase);
     wave_lds_fence();
+}
+
+// The 32-bit halves of 64-bit elements.
+__device__ __forceinline__ void split_halves(const double (&x)[kLine], uint32_t (&hi)[kLine], uint32_t (&lo)[kLine])
+{
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        hi[r] = (uint32_t)(bits_of(x[r]) >> 32);
+        lo[r] = (uint32_t)bits_of(x[r]);
+    }
 }
 
 // The same for 64-bit elements, one 32-bit half at a time (each half keeps the
@@ -221,24 +254,13 @@ __device__ __forceinline__ void exchange(uint32_t (&x)[kLine], uint32_t *lds, ui
 template <int WS, int RS>
 __device__ __forceinline__ void exchange(double (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
 {
-    uint32_t *w = lds + wbase;
-    const uint32_t *rd = lds + rbase;
+    uint32_t hi[kLine], lo[kLine];
+    split_halves(x, hi, lo);
+    exchange<WS, RS>(hi, lds, wbase, rbase);
+    exchange<WS, RS>(lo, lds, wbase, rbase);
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)(bits_of(x[r]) >> 32);
-    wave_lds_fence();
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        x[r] = elem_of(((uint64_t)rd[RS * r] << 32) | (uint32_t)bits_of(x[r]));
-    wave_lds_fence();
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)bits_of(x[r]);
-    wave_lds_fence();
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        x[r] = elem_of((bits_of(x[r]) & 0xFFFFFFFF00000000ull) | rd[RS * r]);
-    wave_lds_fence();
+        x[r] = elem_of(((uint64_t)hi[r] << 32) | lo[r]);
 }
 
 template <bool P>

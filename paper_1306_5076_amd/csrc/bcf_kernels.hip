@@ -230,23 +230,19 @@ __device__ __forceinline__ void shear_sort_blocked(Lines<P> &t, uint32_t *lds, u
 // Round J: BLOCKED -> CROSS (shared LDS, barriers), stages on bits 5+J..6+LW
 // in registers, CROSS -> STRIDED, stages on bits 5+LW..6, STRIDED -> BLOCKED
 // (the wave's own LDS slice), stages on bits 5..0.  The LDS word of position
-// p is p + p/64 in all three layouts, so every access keeps the 65-word rows
-// of the single-wave transposes: each 32-lane half touches 32 distinct banks.
+// p is p + 4 (p/64) in all three layouts, so every access keeps the 68-word
+// rows of the single-wave transposes: lane-consecutive 4-byte accesses (CROSS,
+// STRIDED) touch 32 distinct banks per 32-lane half, and BLOCKED accesses are
+// 16-byte, four registers at a time, 8 lanes covering the 32 banks.
 
 // x[r] -> lds[wbase + WS*r]; barrier; x[r] <- lds[rbase + RS*r]; barrier.
 template <int WS, int RS>
 __device__ __forceinline__ void group_exchange(uint32_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
                                                uint32_t rbase)
 {
-    uint32_t *w = lds + wbase;
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        w[WS * r] = x[r];
+    lds_put<WS>(lds + wbase, x);
     __syncthreads();
-    const uint32_t *rd = lds + rbase;
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        x[r] = rd[RS * r];
+    lds_get<RS>(x, lds + rbase);
     __syncthreads();
 }
 
@@ -254,24 +250,13 @@ __device__ __forceinline__ void group_exchange(uint32_t (&x)[kLine], uint32_t *l
 template <int WS, int RS>
 __device__ __forceinline__ void group_exchange(double (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
 {
-    uint32_t *w = lds + wbase;
-    const uint32_t *rd = lds + rbase;
+    uint32_t hi[kLine], lo[kLine];
+    split_halves(x, hi, lo);
+    group_exchange<WS, RS>(hi, lds, wbase, rbase);
+    group_exchange<WS, RS>(lo, lds, wbase, rbase);
 #pragma unroll
     for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)(bits_of(x[r]) >> 32);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        x[r] = elem_of(((uint64_t)rd[RS * r] << 32) | (uint32_t)bits_of(x[r]));
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        w[WS * r] = (uint32_t)bits_of(x[r]);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        x[r] = elem_of((bits_of(x[r]) & 0xFFFFFFFF00000000ull) | rd[RS * r]);
-    __syncthreads();
+        x[r] = elem_of(((uint64_t)hi[r] << 32) | lo[r]);
 }
 
 // BLOCKED p = 4096w + 64 lane + r  ->  CROSS p = lane + 64w + 64*NW*r
@@ -614,7 +599,7 @@ __device__ __forceinline__ void wave_tile(Lines<P> &a, const SortItem &it, const
 template <bool P, class Src, bool SHEAR = false>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
 {
-    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
+    __shared__ __align__(16) uint32_t lds_all[kWavesPerGroup][kLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint32_t *lds = lds_all[wave];
@@ -742,7 +727,7 @@ __device__ __forceinline__ void group_tile(Lines<P> &t, const SortItem &it, cons
 template <int NW, bool P, class Src>
 __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
 {
-    __shared__ uint32_t lds[NW * kLdsWords];
+    __shared__ __align__(16) uint32_t lds[NW * kLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint32_t g = blockIdx.x;
@@ -874,7 +859,7 @@ __global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, 
 template <bool P, class Src, int MODE, bool NT = false>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const uint32_t *__restrict__ splits)
 {
-    __shared__ uint32_t lds_all[kWavesPerGroup][kLdsWords];
+    __shared__ __align__(16) uint32_t lds_all[kWavesPerGroup][kLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint32_t *lds = lds_all[wave];

@@ -53,16 +53,17 @@ __host__ __device__ constexpr uint32_t pattern_addr(int p, uint32_t l)
     case 11: return 0;                             // broadcast
     case 12: return 128 * l;                       // stride 128
     case 13: return (l & 15) + 2048 * (l >> 4);    // 16-lane groups on the same banks
+    case 14: return 17 * l;                        // stride 17 (b128: 68 words, four pad words per 64)
     default: return l;
     }
 }
-constexpr int kPatterns = 14;
+constexpr int kPatterns = 15;
 const char *pattern_name(int p)
 {
     static const char *n[] = {"stride1", "stride2", "stride4", "stride8", "stride16",
                               "stride32", "stride64", "stride65", "stride33",
                               "half_alias(l&31)+2048*(l>>5)", "interleave 2*(l&31)+(l>>5)",
-                              "broadcast", "stride128", "quarter_alias(l&15)+2048*(l>>4)"};
+                              "broadcast", "stride128", "quarter_alias(l&15)+2048*(l>>4)", "stride17"};
     return n[p];
 }
 
@@ -291,7 +292,7 @@ void run_pattern(uint32_t *sink, unsigned long long *cyc_d, std::vector<unsigned
                  double clk)
 {
     run_one<P, 1>(sink, cyc_d, cyc_h, cus, clk);
-    if constexpr (P != 7 && P != 8 && P != 10 && P != 9 && P != 13) {
+    if constexpr (P != 7 && P != 10 && P != 9 && P != 13) {
         run_one<P, 2>(sink, cyc_d, cyc_h, cus, clk);
         run_one<P, 4>(sink, cyc_d, cyc_h, cus, clk);
     }

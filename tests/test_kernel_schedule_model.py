@@ -6,9 +6,11 @@ complements and STRIDED/BLOCKED transposes that the block-sort and merge
 kernels execute on a 64 x 64 tile (w = 64 lanes x 64 registers), and checks
 
 * that the schedule sorts (0-1 principle inputs, random inputs, duplicates);
-* that every LDS instruction of a transpose touches 32 distinct banks in each
-  32-lane half (gfx950 geometry: 32 banks x 4 bytes, halves serviced
-  independently, measured by the bank probe);
+* that every LDS instruction of a transpose is conflict-free on the measured
+  gfx950 geometry (32 banks x 4 bytes): 4-byte accesses (STRIDED, CROSS)
+  touch 32 distinct banks in each 32-lane half; 16-byte accesses (BLOCKED,
+  four registers per instruction) touch the 32 banks once in each group of 8
+  consecutive lanes (one 128-byte pass);
 * Batcher's network size (543 comparators for 64 keys) and that it sorts;
 * the paper's Fig. 1 view of shared memory (element k in bank k mod w,
   column k div w) for the paper's w = 8 drawing.
@@ -22,7 +24,8 @@ import pytest
 W = 64  # lanes
 E = 64  # registers per lane
 T = W * E
-STRIDE = E + 1  # LDS words per row (one pad word per 64)
+PAD = 4  # LDS pad words per 64-word row
+STRIDE = E + PAD  # LDS words per row
 BANKS = 32
 HALF = 32
 
@@ -91,7 +94,7 @@ def blocked_pos(lane, r):
 
 
 def lds_addr(p):
-    return p + p // 64
+    return p + PAD * (p // 64)
 
 
 def to_blocked(regs):
@@ -235,14 +238,33 @@ def test_transpose_model_matches_index_permutation():
     assert np.array_equal(to_strided(regs), fast_to_strided(regs))
 
 
+def b32_conflict_free(words):
+    """4-byte accesses of 64 lanes: 32 distinct banks in each 32-lane half."""
+    banks = np.asarray(words) % BANKS
+    return all(len(set(banks[h * HALF:(h + 1) * HALF].tolist())) == HALF for h in range(W // HALF))
+
+
+def b128_conflict_free(words):
+    """16-byte accesses (words w..w+3, w a multiple of 4) of 64 lanes: every group
+    of 8 consecutive lanes covers the 32 banks exactly once."""
+    words = np.asarray(words)
+    if np.any(words % 4):
+        return False  # not 16-byte aligned
+    for g in range(W // 8):
+        banks = sorted(int((w + k) % BANKS) for w in words[8 * g:8 * g + 8] for k in range(4))
+        if banks != list(range(BANKS)):
+            return False
+    return True
+
+
 def test_lds_transposes_conflict_free_on_gfx950_geometry():
     lanes = np.arange(W)
     for r in range(E):
-        for pos in (strided_pos, blocked_pos):
-            banks = lds_addr(pos(lanes, r)) % BANKS
-            for h in range(W // HALF):
-                b = banks[h * HALF:(h + 1) * HALF]
-                assert len(set(b.tolist())) == HALF, (pos.__name__, r, h)
+        assert b32_conflict_free(lds_addr(strided_pos(lanes, r))), r
+    for r in range(0, E, 4):  # BLOCKED side: four consecutive registers per 16-byte access
+        assert b128_conflict_free(lds_addr(blocked_pos(lanes, r))), r
+    # 4-byte BLOCKED accesses would conflict 4-way on this layout (the kernels never issue them)
+    assert not b32_conflict_free(lds_addr(blocked_pos(lanes, 0)))
     # the unpadded layout would conflict 32-way for the BLOCKED accesses
     banks = (blocked_pos(lanes, 0)) % BANKS
     assert len(set(banks[:HALF].tolist())) == 1
@@ -324,7 +346,7 @@ def test_paper_fig1_bank_matrix_view():
 
 
 def lds_word(p):
-    return p + p // 64
+    return p + PAD * (p // 64)
 
 
 def group_sort_model(x, nw):
@@ -413,10 +435,12 @@ def test_group_layouts_conflict_free(nw):
     }
     for name, pos in layouts.items():
         for w in range(nw):
-            for r in range(E):
-                banks = lds_word(pos(w, lanes, r)) % BANKS
-                for h in range(W // HALF):
-                    assert len(set(banks[h * HALF:(h + 1) * HALF].tolist())) == HALF, (name, w, r)
+            if name == "blocked":  # 16-byte accesses, four registers each
+                for r in range(0, E, 4):
+                    assert b128_conflict_free(lds_word(pos(w, lanes, r))), (name, w, r)
+            else:
+                for r in range(E):
+                    assert b32_conflict_free(lds_word(pos(w, lanes, r))), (name, w, r)
     # every layout is a bijection onto the group tile, inside the LDS array
     for pos in layouts.values():
         ps = {pos(w, l, r) for w in range(nw) for l in range(W) for r in range(E)}
