@@ -42,7 +42,15 @@ import torch
 
 from . import api
 
-__all__ = ["SortServer", "serve_serial", "serve_batched", "latency_stats", "make_requests", "run_serving_benchmark"]
+__all__ = ["SortServer", "SortFuture", "serve_serial", "serve_batched", "latency_stats", "make_requests", "run_serving_benchmark"]
+
+
+class SortFuture(Future):
+    """Future of one request; ``timing`` holds the request's timestamps
+    (time.perf_counter(): submitted, admitted, launched, done, finished)
+    once it has completed."""
+
+    timing = None
 
 
 @dataclass
@@ -51,7 +59,7 @@ class _Request:
     vals: object | None
     arrival: float
     ready: object = None    # device request: event recorded on the submitting stream
-    future: Future = field(default_factory=Future)
+    future: SortFuture = field(default_factory=SortFuture)
     submitted: float = 0.0  # perf_counter() when submit() queued it
     admitted: float = 0.0   # ... when the launch thread took it into a batch
     launched: float = 0.0   # ... when its batch's copies and kernels were enqueued
@@ -297,7 +305,8 @@ class SortServer:
                     v = ov[vlo:vlo + (hi - lo)].clone().numpy() if r.pairs else None
                 r.done = done
                 r.finished = time.perf_counter()
-                r.future._bcf_request = r
+                r.future.timing = {"submitted": r.submitted, "admitted": r.admitted, "launched": r.launched,
+                                   "done": r.done, "finished": r.finished}
                 r.future.set_result((k, v) if r.pairs else k)
             with self.cv:
                 self.busy.popleft()
@@ -495,37 +504,51 @@ def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 <<
     if own:
         server = SortServer(device, hbm_budget=hbm_budget)
     server.reset_stats()
-    futs, arrivals = [], []
+    arrivals, timings = [], [None] * len(requests)
+    results = [None] * len(requests)
+    remaining = [len(requests)]
+    all_done = threading.Event()
+    lock = threading.Lock()
+
+    def on_done(i, f):
+        # runs on the server's completion thread: keep the timestamps (and the
+        # result only if asked: a consumer that drops results keeps memory flat)
+        try:
+            if f.exception() is None:
+                timings[i] = f.timing
+                if keep_results:
+                    results[i] = f.result()
+        finally:
+            with lock:
+                remaining[0] -= 1
+                if remaining[0] == 0:
+                    all_done.set()
+
     t0 = time.perf_counter()
-    for t, keys, vals in requests:
+    if not requests:
+        all_done.set()
+    for i, (t, keys, vals) in enumerate(requests):
         at = t0 + t / qps
         _wait_until(at)
         arrivals.append(at)
-        f = server.submit(keys, vals, arrival=at)
-        if not keep_results:
-            f.add_done_callback(_drop_result)
-        futs.append(f)
-    results = [f.result() for f in futs]
+        server.submit(keys, vals, arrival=at).add_done_callback(lambda f, i=i: on_done(i, f))
+    all_done.wait()
     wall = time.perf_counter() - t0
     stats = {"batches": server.batches, "mean_batch": round(float(np.mean(server.batch_sizes)), 2),
              "peak_hbm_bytes": server.peak_used, "hbm_budget": server.budget,
              "max_batch_keys": server.max_batch_keys}
     if own:
         server.close()
-    reqs = [f._bcf_request for f in futs]
-    lat = [r.finished - a for r, a in zip(reqs, arrivals)]
+    if any(tm is None for tm in timings):  # a request failed: its future holds the error
+        raise RuntimeError("a request of the serving run failed")
+    lat = [tm["finished"] - a for tm, a in zip(timings, arrivals)]
     stats["stage_p50_ms"] = {
-        "queued": _p50([r.admitted - r.submitted for r in reqs]),
-        "pack_and_enqueue": _p50([r.launched - r.admitted for r in reqs]),
-        "device": _p50([r.done - r.launched for r in reqs]),
-        "unpack": _p50([r.finished - r.done for r in reqs]),
+        "queued": _p50([tm["admitted"] - tm["submitted"] for tm in timings]),
+        "pack_and_enqueue": _p50([tm["launched"] - tm["admitted"] for tm in timings]),
+        "device": _p50([tm["done"] - tm["launched"] for tm in timings]),
+        "unpack": _p50([tm["finished"] - tm["done"] for tm in timings]),
     }
     return results, lat, wall, stats
-
-
-def _drop_result(f):
-    """Done-callback: release a completed future's result (its buffers)."""
-    f._result = None
 
 
 def _p50(xs):
