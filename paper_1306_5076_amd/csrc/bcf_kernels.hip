@@ -58,15 +58,27 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
                                           uint32_t lane, uint32_t rank0 = 0)
 {
     const uint32_t *kp = ksrc + lane;
-    if (count >= (uint32_t)kTile) {
+    if constexpr (P) {
+        // all 64 loads first, then the conversions: left to itself the
+        // scheduler converts each key right after its load and so waits for
+        // the loads one at a time
+        uint32_t key[kLine];
+        const uint32_t last = count ? count - 1 : 0;
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
-            const uint32_t key = kp[kWave * r];
-            if constexpr (P)
-                t.e[r] = make_elem(key, rank0 + kWave * r + lane);
-            else
-                t.k[r] = key;
+            const uint32_t p = kWave * r + lane;
+            key[r] = ksrc[p < count ? p : last];  // clamped: always a valid address
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < kLine; ++r) {
+            const uint32_t p = kWave * r + lane;
+            t.e[r] = p < count ? make_elem(key[r], rank0 + p) : make_elem(kMaxKey, kPadRank);
+        }
+    } else if (count >= (uint32_t)kTile) {
+#pragma unroll
+        for (int r = 0; r < kLine; ++r)
+            t.k[r] = kp[kWave * r];
     } else {
         const uint32_t last = count ? count - 1 : 0;
 #pragma unroll
@@ -74,10 +86,7 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
             const uint32_t p = kWave * r + lane;
             const uint32_t q = p < count ? p : last;  // clamped: always a valid address
             const uint32_t key = count ? ksrc[q] : kMaxKey;
-            if constexpr (P)
-                t.e[r] = p < count ? make_elem(key, rank0 + p) : make_elem(kMaxKey, kPadRank);
-            else
-                t.k[r] = p < count ? key : kMaxKey;
+            t.k[r] = p < count ? key : kMaxKey;
         }
     }
 }
@@ -115,6 +124,9 @@ __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restri
     }
 }
 
+typedef __attribute__((address_space(1))) const void global_cvoid;
+typedef __attribute__((address_space(3))) void lds_void;
+
 // Value step of a block sort (pairs): the tile is sorted, in STRIDED layout,
 // and every element's rank is its input position in [0, count) (padding
 // ranks are larger).  The values of those `count` input positions are staged
@@ -128,12 +140,16 @@ __device__ __forceinline__ void permute_values_lds(Lines<true> &t, const uint32_
                                                    uint32_t stage_count, uint32_t lane, const Sync &sync)
 {
     // stage input positions [stage_off, stage_off + stage_count) of this wave
+    // with direct global-to-LDS loads (lanes past the end re-read the first
+    // position; their LDS words are never read)
+    const uint32_t *src = vsrc + stage_off;
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
         const uint32_t p = kWave * r + lane;
-        if (p < stage_count)
-            vals[stage_off + p] = vsrc[stage_off + p];
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(src + (p < stage_count ? p : 0u)),
+                                         (lds_void *)(vals + stage_off + kWave * r), 4, 0, 0);
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     sync();
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
@@ -334,52 +350,76 @@ __device__ __forceinline__ void merge_load(Lines<P> &t, const MergeTask<P> &m, u
     const uint32_t bstart = kTile - nb;
     const uint32_t dB = (uint32_t)(m.kb - m.ka);   // B-piece start relative to the A-piece
     const uint32_t bend = dB + (kTile - 1);        // offset of position p in B is bend - p
-    if (m.count == (uint32_t)kTile) {
+    if constexpr (P) {
+        // all 64 loads first, then the conversions to (key, rank) elements
+        uint32_t key[kLine];
+#pragma unroll
+        for (int r = 0; r < kLine; ++r) {
+            const uint32_t p = kWave * r + lane;
+            key[r] = ld<NT>(m.ka + (p < na ? p : (p >= bstart ? bend - p : 0u)));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < kLine; ++r) {
+            const uint32_t p = kWave * r + lane;
+            const bool in_a = p < na, in_b = p >= bstart;
+            t.e[r] = (in_a || in_b) ? make_elem(key[r], in_a ? p : na + (kTile - 1 - p)) : make_elem(kMaxKey, kPadRank);
+        }
+    } else if (m.count == (uint32_t)kTile) {
         // full tile: every position is in A or in B and no register needs a
         // select after its load (such selects make the compiler wait for the
         // loads one by one)
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
             const uint32_t p = kWave * r + lane;
-            const bool in_a = p < na;
-            const uint32_t key = ld<NT>(m.ka + (in_a ? p : bend - p));
-            if constexpr (P)
-                t.e[r] = make_elem(key, in_a ? p : na + (kTile - 1 - p));
-            else
-                t.k[r] = key;
+            t.k[r] = ld<NT>(m.ka + (p < na ? p : bend - p));
         }
-        return;
+    } else {
+#pragma unroll
+        for (int r = 0; r < kLine; ++r) {
+            const uint32_t p = kWave * r + lane;
+            const bool in_a = p < na;
+            const bool in_b = p >= bstart;
+            const uint32_t off = in_a ? p : (in_b ? bend - p : 0u);
+            const uint32_t key = ld<NT>(m.ka + off);
+            t.k[r] = (in_a || in_b) ? key : kMaxKey;
+        }
     }
+}
+
+// Values of a merge work item (pairs), staged in LDS in the tile's position
+// order (word p holds the value of the element merge_load put at position p)
+// by direct global-to-LDS loads: they take no registers and are in flight
+// together with the key loads, while the keys go through the network.
+__device__ __forceinline__ void stage_merge_values(const MergeTask<true> &m, uint32_t *vals, uint32_t lane)
+{
+    const uint32_t na = m.pa, nb = m.pb;
+    const uint32_t bstart = kTile - nb;
+    const uint32_t bend = (uint32_t)(m.vb - m.va) + (kTile - 1);
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
         const uint32_t p = kWave * r + lane;
-        const bool in_a = p < na;
-        const bool in_b = p >= bstart;
-        const uint32_t off = in_a ? p : (in_b ? bend - p : 0u);
-        const uint32_t key = ld<NT>(m.ka + off);
-        if constexpr (P)
-            t.e[r] = (in_a || in_b) ? make_elem(key, in_a ? p : na + (kTile - 1 - p)) : make_elem(kMaxKey, kPadRank);
-        else
-            t.k[r] = (in_a || in_b) ? key : kMaxKey;
+        const uint32_t off = p < na ? p : (p >= bstart ? bend - p : 0u);
+        __builtin_amdgcn_global_load_lds((global_cvoid *)(m.va + off), (lds_void *)(vals + kWave * r), 4, 0, 0);
     }
 }
 
 // Value step of a merge (pairs): the merged tile is in STRIDED layout and each
-// of its first `count` elements has a rank r (r < pa: A[r], else B[r - pa]).
-// Repack it as its key and that source element's value.  The 64 outputs of a
-// register row come from one contiguous stretch of A and one of B, so each
-// gather touches few cache lines.
-template <bool NT = false>
-__device__ __forceinline__ void gather_values(Lines<true> &t, const MergeTask<true> &m, uint32_t lane)
+// of its first `count` elements has a rank r (r < pa: A[r], loaded at
+// position r; else B[r - pa], loaded at position 4095 - (r - pa)).  Repack it
+// as its key and the value staged in LDS at that position.
+__device__ __forceinline__ void gather_values(Lines<true> &t, const MergeTask<true> &m, const uint32_t *vals,
+                                              uint32_t lane)
 {
+    // the staged values have landed in LDS once this wave's loads are done
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     const uint32_t na = m.pa;
-    const uint32_t dBm = (uint32_t)(m.vb - m.va) - na;  // offset of B[r - pa] is r + dBm
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
         const uint32_t p = kWave * r + lane;
         const uint32_t rank = elem_rank(t.e[r]);
-        const uint32_t off = p < m.count ? (rank < na ? rank : rank + dBm) : 0u;
-        const uint32_t v = ld<NT>(m.va + off);
+        const uint32_t pos = rank < na ? rank : (kTile - 1) - (rank - na);
+        const uint32_t v = p < m.count ? vals[pos] : 0u;
         t.e[r] = make_out(elem_key(t.e[r]), v);
     }
 }
@@ -859,10 +899,13 @@ __global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, 
 template <bool P, class Src, int MODE, bool NT = false>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const uint32_t *__restrict__ splits)
 {
-    __shared__ __align__(16) uint32_t lds_all[kWavesPerGroup][kLdsWords];
+    // per wave: the transpose area, then (pairs) the tile's staged values
+    constexpr int kWaveWords = kLdsWords + (P ? kTile : 0);
+    __shared__ __align__(16) uint32_t lds_all[kWavesPerGroup][kWaveWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint32_t *lds = lds_all[wave];
+    uint32_t *vals = lds + kLdsWords;
     const uint32_t G = gridDim.x * kWavesPerGroup;
     uint32_t t = blockIdx.x * kWavesPerGroup + wave;
     if (t >= src.ntiles)
@@ -871,9 +914,11 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
         const MergeTask<P> m = merge_task<P>(src, splits, t);
         Lines<P> a;
         merge_load<P>(a, m, lane);
+        if constexpr (P)
+            stage_merge_values(m, vals, lane);
         merge_network<P>(a, lds, lane, src.out_smp, m.gpos, m.count);
         if constexpr (P)
-            gather_values(a, m, lane);
+            gather_values(a, m, vals, lane);
         store_tile<P>(a, m.kd, m.vd, m.count, lane);
     } else if constexpr (P || MODE == 1) {
         for (; t < src.ntiles; t += G) {
@@ -881,9 +926,11 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
             const MergeTask<P> m = merge_task<P>(src, splits, t);
             Lines<P> a;
             merge_load<P, NT>(a, m, ln);
+            if constexpr (P)
+                stage_merge_values(m, vals, ln);
             merge_network<P>(a, lds, ln, src.out_smp, m.gpos, m.count);
             if constexpr (P)
-                gather_values<NT>(a, m, ln);
+                gather_values(a, m, vals, ln);
             store_tile<P, NT>(a, m.kd, m.vd, m.count, ln);
         }
     } else {
