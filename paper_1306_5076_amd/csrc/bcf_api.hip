@@ -154,6 +154,7 @@ Tuning &tuning_locked()
         const char *e = std::getenv("BCF_SEG_GROUP_MIN");
         g_tune.group_min_keys = (e && *e) ? std::strtoull(e, nullptr, 10) : 0;
         g_tune.check_runs = env_int("BCF_CHECK", 0) == 1;
+        g_tune.partition_half = env_int("BCF_PARTITION_HALF", 1) != 0;
         g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
         if (g_tune.block_sort < 0 || g_tune.block_sort > 3)
             g_tune.block_sort = 0;

@@ -85,6 +85,7 @@ hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev,
 // Current process-wide tuning (see bcf_tuning in bcf.h); a copy.
 struct Tuning {
     int block_sort;  // 0 auto, 1 wave tiles (merge rounds), 2 wave tiles (ShearSort), 3 group tiles
+    bool partition_half;  // sampled partition: one half-wave (else one wave) per tile (env BCF_PARTITION_HALF)
     int merge_variant;
     bool nontemporal;
     bool sampled_partition;

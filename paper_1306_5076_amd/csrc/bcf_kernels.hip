@@ -861,39 +861,87 @@ __device__ __forceinline__ void corank_level(uint32_t &lo, uint32_t &hi, uint32_
     }
 }
 
+// corank_level for a half-wave: lanes 0..31 and 32..63 each narrow their own
+// bracket (two independent searches per wave) with 32 probes per round.
+template <uint32_t G, class Pred>
+__device__ __forceinline__ void corank_level_half(uint32_t &lo, uint32_t &hi, uint32_t lane, const Pred &pred)
+{
+    const uint32_t k = lane & 31;
+    const uint32_t shift = lane & 32;
+    uint32_t c0 = (lo + G - 1) / G;
+    uint32_t c1 = hi > 0 ? (hi - 1) / G + 1 : 0;
+    while (__ballot(c0 < c1) != 0) {
+        const bool act = c0 < c1;
+        const uint32_t span = act ? c1 - c0 : 0;
+        const uint32_t c = c0 + (uint32_t)(((uint64_t)span * k) >> 5);  // probe of this lane
+        const bool fail = act && !pred(G * c);
+        const uint32_t cnt = __popc((uint32_t)(__ballot(fail) >> shift));  // probes 0..cnt-1 fail
+        if (act) {
+            if (cnt == 0) {
+                hi = min(hi, G * c0);
+                c1 = c0;
+            } else {
+                const uint32_t cf = c0 + (uint32_t)(((uint64_t)span * (cnt - 1)) >> 5);
+                lo = max(lo, G * cf + 1);
+                if (cnt < 32) {
+                    const uint32_t cn = c0 + (uint32_t)(((uint64_t)span * cnt) >> 5);
+                    hi = min(hi, G * cn);
+                    c1 = cn;
+                }
+                c0 = cf + 1;
+            }
+        }
+    }
+}
+
 // Co-rank of every merge tile of a regular pass from the samples the
-// previous launch wrote: one wave per tile, three exact levels (tile
-// samples, 64-block samples, keys).  Tile diagonals are multiples of 4096
-// and runs start at multiples of 4096, so for a candidate i that is a
+// previous launch wrote: three exact levels (tile samples, 64-block samples,
+// keys), by one wave per tile (HALF = false: 64 probes per round) or by one
+// half-wave per tile (HALF = true: 32 probes per round, half the waves, so a
+// launch's searches are all resident at once).  Tile diagonals are multiples
+// of 4096 and runs start at multiples of 4096, so for a candidate i that is a
 // multiple of 64 (4096), A[i] is a first-of-block sample and B[d-1-i] a
 // last-of-block sample.
+template <bool HALF>
 __global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, uint32_t *__restrict__ splits)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
-    if (t >= src.ntiles)
-        return;
-    const MergeItem m = src.get(t);
+    const uint32_t w = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    const uint32_t t = HALF ? 2 * w + (lane >> 5) : w;
+    if ((HALF ? 2 * w : w) >= src.ntiles)
+        return;  // the whole wave is past the last tile
+    const bool valid = t < src.ntiles;
+    const MergeItem m = src.get(valid ? t : src.ntiles - 1);
     const uint32_t d = m.d0, na = m.na, nb = m.nb;
     uint32_t lo = d > nb ? d - nb : 0;
     uint32_t hi = d < na ? d : na;
+    if (!valid)
+        lo = hi = 0;  // no search in this half
     const uint64_t apos = m.base, bpos = m.base + na;
     const SampleSet &sm = src.in_smp;
     const uint32_t *A = m.ka, *B = m.ka + na;
-    if (sm.cf != nullptr)
-        corank_level<kTile>(lo, hi, lane, [&](uint32_t i) {
-            return sm.cf[(apos + i) / kTile] > sm.cl[(bpos + d - 1 - i) / kTile];
-        });
-    else  // tile samples are every 64th block sample
-        corank_level<kTile>(lo, hi, lane, [&](uint32_t i) {
-            return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine];
-        });
-    corank_level<kLine>(lo, hi, lane, [&](uint32_t i) {
-        return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine];
-    });
-    corank_level<1>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
-    if (lane == 0)
-        splits[t] = lo;
+    auto tile_pred = [&](uint32_t i) { return sm.cf[(apos + i) / kTile] > sm.cl[(bpos + d - 1 - i) / kTile]; };
+    auto block_pred = [&](uint32_t i) { return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine]; };
+    auto key_pred = [&](uint32_t i) { return A[i] > B[d - 1 - i]; };
+    if constexpr (HALF) {
+        if (sm.cf != nullptr)
+            corank_level_half<kTile>(lo, hi, lane, tile_pred);
+        else  // tile samples are every 64th block sample
+            corank_level_half<kTile>(lo, hi, lane, block_pred);
+        corank_level_half<kLine>(lo, hi, lane, block_pred);
+        corank_level_half<1>(lo, hi, lane, key_pred);
+        if (valid && (lane & 31) == 0)
+            splits[t] = lo;
+    } else {
+        if (sm.cf != nullptr)
+            corank_level<kTile>(lo, hi, lane, tile_pred);
+        else
+            corank_level<kTile>(lo, hi, lane, block_pred);
+        corank_level<kLine>(lo, hi, lane, block_pred);
+        corank_level<1>(lo, hi, lane, key_pred);
+        if (lane == 0)
+            splits[t] = lo;
+    }
 }
 
 template <bool P, class Src, int MODE, bool NT = false>
@@ -1132,8 +1180,13 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
         // runs must start at multiples of 4096 for the sample predicates
         if (run % kTile != 0)
             return hipErrorInvalidValue;
-        const uint32_t groups = (src.ntiles + (256 / kWave) - 1) / (256 / kWave);
-        hipLaunchKernelGGL(k_partition_sampled, dim3(groups), dim3(256), 0, s, src, splits);
+        if (tuning().partition_half) {
+            const uint32_t groups = (src.ntiles + 2 * (256 / kWave) - 1) / (2 * (256 / kWave));
+            hipLaunchKernelGGL(k_partition_sampled<true>, dim3(groups), dim3(256), 0, s, src, splits);
+        } else {
+            const uint32_t groups = (src.ntiles + (256 / kWave) - 1) / (256 / kWave);
+            hipLaunchKernelGGL(k_partition_sampled<false>, dim3(groups), dim3(256), 0, s, src, splits);
+        }
         return hipGetLastError();
     }
     return pairs ? launch_merge<true>(src, splits, s) : launch_merge<false>(src, splits, s);

@@ -459,22 +459,25 @@ def corank_brute(a, b, d):
     return i
 
 
-def corank_level(lo, hi, g, pred):
-    """Mirror of corank_level<G>: 64 probes per round over candidates g*c in [lo, hi)."""
+def corank_level(lo, hi, g, pred, probes_per_round=64):
+    """Mirror of corank_level<G> (64 probes per round) and corank_level_half<G>
+    (32) over candidates g*c in [lo, hi)."""
+    P = probes_per_round
+    sh = P.bit_length() - 1
     c0 = (lo + g - 1) // g
     c1 = (hi - 1) // g + 1 if hi > 0 else 0
     while c0 < c1:
         span = c1 - c0
-        probes = [c0 + (span * k >> 6) for k in range(64)]
+        probes = [c0 + (span * k >> sh) for k in range(P)]
         fails = [not pred(g * c) for c in probes]
         cnt = sum(fails)
-        assert fails == [True] * cnt + [False] * (64 - cnt)  # monotone
+        assert fails == [True] * cnt + [False] * (P - cnt)  # monotone
         if cnt == 0:
             hi = min(hi, g * c0)
             break
         cf = probes[cnt - 1]
         lo = max(lo, g * cf + 1)
-        if cnt < 64:
+        if cnt < P:
             cn = probes[cnt]
             hi = min(hi, g * cn)
             c1 = cn
@@ -482,19 +485,20 @@ def corank_level(lo, hi, g, pred):
     return lo, hi
 
 
-def corank_sampled(arr, apos, na, nb, d):
+def corank_sampled(arr, apos, na, nb, d, probes_per_round=64):
     """The three levels of k_partition_sampled on one array holding A then B."""
     f = arr[::64]
     l = arr[63::64]
     cf = arr[::4096]
     cl = arr[4095::4096]
     bpos = apos + na
+    P = probes_per_round
     lo, hi = max(0, d - nb), min(d, na)
-    lo, hi = corank_level(lo, hi, 4096, lambda i: cf[(apos + i) // 4096] > cl[(bpos + d - 1 - i) // 4096])
+    lo, hi = corank_level(lo, hi, 4096, lambda i: cf[(apos + i) // 4096] > cl[(bpos + d - 1 - i) // 4096], P)
     assert hi - lo <= 4096
-    lo, hi = corank_level(lo, hi, 64, lambda i: f[(apos + i) // 64] > l[(bpos + d - 1 - i) // 64])
+    lo, hi = corank_level(lo, hi, 64, lambda i: f[(apos + i) // 64] > l[(bpos + d - 1 - i) // 64], P)
     assert hi - lo <= 64
-    lo, hi = corank_level(lo, hi, 1, lambda i: arr[apos + i] > arr[bpos + d - 1 - i])
+    lo, hi = corank_level(lo, hi, 1, lambda i: arr[apos + i] > arr[bpos + d - 1 - i], P)
     assert lo == hi
     return lo
 
@@ -510,7 +514,9 @@ def test_corank_from_samples_matches_brute_force(na, nb, levels):
     arr[apos:apos + na] = a
     arr[apos + na:apos + na + nb] = b
     for d in range(0, na + nb, 4096):
-        assert corank_sampled(arr, apos, na, nb, d) == corank_brute(a, b, d), d
+        want = corank_brute(a, b, d)
+        assert corank_sampled(arr, apos, na, nb, d) == want, d
+        assert corank_sampled(arr, apos, na, nb, d, probes_per_round=32) == want, d
 
 
 @pytest.mark.parametrize("dist", ["random", "zero_one", "dups", "reverse"])
