@@ -155,6 +155,7 @@ Tuning &tuning_locked()
         g_tune.group_min_keys = (e && *e) ? std::strtoull(e, nullptr, 10) : 0;
         g_tune.check_runs = env_int("BCF_CHECK", 0) == 1;
         g_tune.partition_half = env_int("BCF_PARTITION_HALF", 1) != 0;
+        g_tune.fused_partition = env_int("BCF_FUSED", 0) != 0;
         g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
         if (g_tune.block_sort < 0 || g_tune.block_sort > 3)
             g_tune.block_sort = 0;
@@ -261,6 +262,8 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
         for (int phase = 0; phase < 2; ++phase) {
             const bool part = phase == 0;
+            if (part && merge_fuses_partition(pairs, sampled ? sample_set((j - 1) & 1) : none))
+                continue;  // the merge launch searches its own splits
             ProfScope p(part ? kname_partition(pairs, false) : kname_merge(pairs, false), s,
                         part ? 0.0 : 2.0 * elem_bytes * n);
             const SampleSet in_smp = sampled ? sample_set((j - 1) & 1) : none;

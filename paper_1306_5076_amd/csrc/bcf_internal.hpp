@@ -67,6 +67,10 @@ hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin
 // partition = false the tiles are merged using those splits.
 // The regular partition reads the samples of its input (in_smp, written by
 // the previous launch); the regular merge writes those of its output (out_smp).
+// Whether a regular merge pass is one launch (its merge kernel searches the
+// splits from the samples in in_smp) instead of a partition launch and a merge
+// launch; then the partition call of launch_merge_regular enqueues nothing.
+bool merge_fuses_partition(bool pairs, const SampleSet &in_smp);
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc,
                                 uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
                                 uint32_t *splits, SampleSet in_smp, SampleSet out_smp,
@@ -86,6 +90,7 @@ hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev,
 struct Tuning {
     int block_sort;  // 0 auto, 1 wave tiles (merge rounds), 2 wave tiles (ShearSort), 3 group tiles
     bool partition_half;  // sampled partition: one half-wave (else one wave) per tile (env BCF_PARTITION_HALF)
+    bool fused_partition; // one-tile-per-wave merges of regular passes search their own splits (env BCF_FUSED)
     int merge_variant;
     bool nontemporal;
     bool sampled_partition;

@@ -589,12 +589,9 @@ struct TableMergeSrc {
 // The A/B pieces of tile t from its split (co-rank at d0, computed by
 // k_partition) and the next tile's split, or the end of A when the tile ends
 // its merge.
-template <bool P, class Src>
-__device__ __forceinline__ MergeTask<P> merge_task(const Src &src, const uint32_t *__restrict__ splits, uint32_t t)
+template <bool P>
+__device__ __forceinline__ MergeTask<P> merge_task_at(const MergeItem &m, uint32_t a0, uint32_t a1)
 {
-    const MergeItem m = src.get(t);
-    const uint32_t a0 = splits[t];
-    const uint32_t a1 = (m.d0 + m.count == m.na + m.nb) ? m.na : splits[t + 1];
     const uint32_t b0 = m.d0 - a0;
     MergeTask<P> k;
     k.pa = a1 - a0;
@@ -608,6 +605,15 @@ __device__ __forceinline__ MergeTask<P> merge_task(const Src &src, const uint32_
     k.vb = P ? m.va + m.na + b0 : nullptr;
     k.vd = P ? m.vd + m.d0 : nullptr;
     return k;
+}
+
+template <bool P, class Src>
+__device__ __forceinline__ MergeTask<P> merge_task(const Src &src, const uint32_t *__restrict__ splits, uint32_t t)
+{
+    const MergeItem m = src.get(t);
+    const uint32_t a0 = splits[t];
+    const uint32_t a1 = (m.d0 + m.count == m.na + m.nb) ? m.na : splits[t + 1];
+    return merge_task_at<P>(m, a0, a1);
 }
 
 // ------------------------------------------------------------------- kernels
@@ -894,6 +900,25 @@ __device__ __forceinline__ void corank_level_half(uint32_t &lo, uint32_t &hi, ui
     }
 }
 
+// Three-level sampled co-rank search of diagonal d of merge item m by a
+// half-wave (see k_partition_sampled); [lo, hi] is the initial bracket.
+__device__ __forceinline__ void corank_sampled_half(const SampleSet &sm, const MergeItem &m, uint32_t d,
+                                                    uint32_t lane, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t na = m.na;
+    const uint64_t apos = m.base, bpos = m.base + na;
+    const uint32_t *A = m.ka, *B = m.ka + na;
+    auto tile_pred = [&](uint32_t i) { return sm.cf[(apos + i) / kTile] > sm.cl[(bpos + d - 1 - i) / kTile]; };
+    auto block_pred = [&](uint32_t i) { return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine]; };
+    auto key_pred = [&](uint32_t i) { return A[i] > B[d - 1 - i]; };
+    if (sm.cf != nullptr)
+        corank_level_half<kTile>(lo, hi, lane, tile_pred);
+    else  // tile samples are every 64th block sample
+        corank_level_half<kTile>(lo, hi, lane, block_pred);
+    corank_level_half<kLine>(lo, hi, lane, block_pred);
+    corank_level_half<1>(lo, hi, lane, key_pred);
+}
+
 // Co-rank of every merge tile of a regular pass from the samples the
 // previous launch wrote: three exact levels (tile samples, 64-block samples,
 // keys), by one wave per tile (HALF = false: 64 probes per round) or by one
@@ -924,12 +949,7 @@ __global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, 
     auto block_pred = [&](uint32_t i) { return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine]; };
     auto key_pred = [&](uint32_t i) { return A[i] > B[d - 1 - i]; };
     if constexpr (HALF) {
-        if (sm.cf != nullptr)
-            corank_level_half<kTile>(lo, hi, lane, tile_pred);
-        else  // tile samples are every 64th block sample
-            corank_level_half<kTile>(lo, hi, lane, block_pred);
-        corank_level_half<kLine>(lo, hi, lane, block_pred);
-        corank_level_half<1>(lo, hi, lane, key_pred);
+        corank_sampled_half(sm, m, d, lane, lo, hi);
         if (valid && (lane & 31) == 0)
             splits[t] = lo;
     } else {
@@ -944,7 +964,26 @@ __global__ __launch_bounds__(256) void k_partition_sampled(RegularMergeSrc src, 
     }
 }
 
-template <bool P, class Src, int MODE, bool NT = false>
+// The split of merge tile t computed in the merge kernel itself from the
+// samples of its input (regular passes): lanes 0..31 search the tile's first
+// diagonal, lanes 32..63 its end, at the same time.
+__device__ __forceinline__ void fused_splits(const RegularMergeSrc &src, const MergeItem &m, uint32_t lane,
+                                             uint32_t &a0, uint32_t &a1)
+{
+    const uint32_t d = lane < 32 ? m.d0 : m.d0 + m.count;
+    uint32_t lo = d > m.nb ? d - m.nb : 0;
+    uint32_t hi = d < m.na ? d : m.na;
+    corank_sampled_half(src.in_smp, m, d, lane, lo, hi);
+    a0 = __builtin_amdgcn_readlane(lo, 0);
+    a1 = __builtin_amdgcn_readlane(lo, 32);
+}
+
+template <class Src>
+__device__ __forceinline__ void fused_splits(const Src &, const MergeItem &, uint32_t, uint32_t &, uint32_t &)
+{
+}
+
+template <bool P, class Src, int MODE, bool NT = false, bool FUSED = false>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const uint32_t *__restrict__ splits)
 {
     // per wave: the transpose area, then (pairs) the tile's staged values
@@ -959,7 +998,15 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
     if (t >= src.ntiles)
         return;
     if constexpr (MODE == 2) {
-        const MergeTask<P> m = merge_task<P>(src, splits, t);
+        MergeTask<P> m;
+        if constexpr (FUSED) {
+            const MergeItem mi = src.get(t);
+            uint32_t a0, a1;
+            fused_splits(src, mi, lane, a0, a1);
+            m = merge_task_at<P>(mi, a0, a1);
+        } else {
+            m = merge_task<P>(src, splits, t);
+        }
         Lines<P> a;
         merge_load<P>(a, m, lane);
         if constexpr (P)
@@ -1081,12 +1128,13 @@ static hipError_t launch_partition(const Src &src, uint32_t *splits, hipStream_t
     return hipGetLastError();
 }
 
-template <bool P, class Src, int MODE, bool NT = false>
+template <bool P, class Src, int MODE, bool NT = false, bool FUSED = false>
 static hipError_t launch_merge_mode(const Src &src, const uint32_t *splits, hipStream_t s)
 {
     const uint32_t groups = MODE == 2 ? (src.ntiles + kWavesPerGroup - 1) / kWavesPerGroup
-                                      : persistent_groups(k_merge<P, Src, MODE, NT>, src.ntiles);
-    hipLaunchKernelGGL((k_merge<P, Src, MODE, NT>), dim3(groups), dim3(kWave * kWavesPerGroup), 0, s, src, splits);
+                                      : persistent_groups(k_merge<P, Src, MODE, NT, FUSED>, src.ntiles);
+    hipLaunchKernelGGL((k_merge<P, Src, MODE, NT, FUSED>), dim3(groups), dim3(kWave * kWavesPerGroup), 0, s, src,
+                       splits);
     return hipGetLastError();
 }
 
@@ -1106,6 +1154,12 @@ static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream
         return tu.nontemporal ? launch_merge_mode<P, Src, 1, true>(src, splits, s)
                               : launch_merge_mode<P, Src, 1>(src, splits, s);
     }
+}
+
+bool merge_fuses_partition(bool pairs, const SampleSet &in_smp)
+{
+    const Tuning tu = tuning();
+    return in_smp.f != nullptr && tu.fused_partition && (tu.merge_variant == 2 || (tu.merge_variant == 3 && !pairs));
 }
 
 hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
@@ -1174,6 +1228,15 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
 {
     RegularMergeSrc src{ksrc, pairs ? vsrc : nullptr, kdst, pairs ? vdst : nullptr, n, run,
                         (uint32_t)((n + kTile - 1) / kTile), in_smp, out_smp};
+    if (merge_fuses_partition(pairs, in_smp)) {
+        // one launch per pass: the merge kernel searches its own splits
+        if (partition)
+            return hipSuccess;
+        if (run % kTile != 0)
+            return hipErrorInvalidValue;
+        return pairs ? launch_merge_mode<true, RegularMergeSrc, 2, false, true>(src, splits, s)
+                     : launch_merge_mode<false, RegularMergeSrc, 2, false, true>(src, splits, s);
+    }
     if (partition) {
         if (in_smp.f == nullptr)
             return launch_partition(src, splits, s);
