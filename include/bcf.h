@@ -141,15 +141,16 @@ uint32_t bcf_run_keys(int pairs);
 
 /* Passes over the data in HBM of a sort of n keys: the block sort plus
  * ceil(log2(n / bcf_run_keys(pairs))) binary merge passes (the paper's Lemma 2:
- * O(1 + log(N/M)) scans).  Each merge pass is preceded by a small partition
- * launch that reads O(log n) keys per 4096-key output tile. */
+ * O(1 + log(N/M)) scans).  Each merge pass finds the split of every 4096-key
+ * output tile by reading O(log n) key samples and keys, in a small partition
+ * launch before it or (see bcf_tuning.fused_partition) in the merge kernel. */
 uint32_t bcf_sort_passes(uint64_t n, int pairs);
 
 /*
  * Process-wide tuning knobs (read by every later call; not per stream).
  * Initial values come from environment variables read once, at the first
  * call into the library: BCF_MERGE_MODE, BCF_NT, BCF_NO_SAMPLES,
- * BCF_TILE_SAMPLES, BCF_SEG_GROUP_MIN, BCF_CHECK, BCF_BLOCK_SORT.  The autotuner sets them
+ * BCF_TILE_SAMPLES, BCF_SEG_GROUP_MIN, BCF_CHECK, BCF_BLOCK_SORT, BCF_FUSED.  The autotuner sets them
  * through bcf_set_tuning.  Calls that are in flight on other threads when the
  * knobs change may use either setting; results are identical either way.
  */
@@ -171,6 +172,10 @@ typedef struct {
                                   ShearSort (Sec. 3.1); 3 multi-wave group tiles sorted by
                                   merge rounds.  Wave tiles hand runs of 4096 keys to the
                                   merge passes, group tiles runs of 32768 keys (16384 pairs) */
+    int32_t fused_partition;   /* 1 (default): a merge pass of bcf_sort_u32 / bcf_sort_pairs_u32
+                                  run by the one-tile-per-wave kernel finds each tile's split
+                                  itself from the samples (one launch per pass); 0: a separate
+                                  partition launch first */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);

@@ -60,6 +60,7 @@ class Tuning(ctypes.Structure):
         ("group_min_keys", ctypes.c_uint64),
         ("check_runs", ctypes.c_int32),
         ("block_sort", ctypes.c_int32),
+        ("fused_partition", ctypes.c_int32),
     ]
 
 

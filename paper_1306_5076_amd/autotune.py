@@ -9,6 +9,9 @@ ones the kernels expose at run time:
 * merge_variant     -- persistent waves with / without next-tile prefetch, one
                        tile per wave, or the per-kind default;
 * nontemporal       -- nontemporal hints on the merge passes' tile traffic;
+* fused_partition   -- whether one-tile-per-wave merge passes search their
+                       own splits (one launch per pass) or a partition
+                       launch does;
 * group_min_keys    -- (segmented sorts) the segment length from which a
                        segment is block-sorted by multi-wave work-groups.
 
@@ -30,7 +33,7 @@ from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bcf_sort", "autotune.json")
 
-SORT_SPACE = {"merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0]}
+SORT_SPACE = {"merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0], "fused_partition": [1, 0]}
 SEGMENTED_SPACE = {"merge_variant": [3, 1, 2], "nontemporal": [1, 0],
                    "group_min_keys": [4097, 16384, 65536, 1 << 40]}
 

@@ -155,7 +155,7 @@ Tuning &tuning_locked()
         g_tune.group_min_keys = (e && *e) ? std::strtoull(e, nullptr, 10) : 0;
         g_tune.check_runs = env_int("BCF_CHECK", 0) == 1;
         g_tune.partition_half = env_int("BCF_PARTITION_HALF", 1) != 0;
-        g_tune.fused_partition = env_int("BCF_FUSED", 0) != 0;
+        g_tune.fused_partition = env_int("BCF_FUSED", 1) != 0;
         g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
         if (g_tune.block_sort < 0 || g_tune.block_sort > 3)
             g_tune.block_sort = 0;
@@ -713,6 +713,7 @@ void bcf_get_tuning(bcf_tuning *out)
     out->group_min_keys = t.group_min_keys;
     out->check_runs = t.check_runs;
     out->block_sort = t.block_sort;
+    out->fused_partition = t.fused_partition;
 }
 
 bcf_status bcf_set_tuning(const bcf_tuning *in)
@@ -728,6 +729,7 @@ bcf_status bcf_set_tuning(const bcf_tuning *in)
     t.group_min_keys = in->group_min_keys;
     t.check_runs = in->check_runs != 0;
     t.block_sort = in->block_sort;
+    t.fused_partition = in->fused_partition != 0;
     return BCF_OK;
 }
 

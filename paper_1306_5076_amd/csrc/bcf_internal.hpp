@@ -90,7 +90,7 @@ hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev,
 struct Tuning {
     int block_sort;  // 0 auto, 1 wave tiles (merge rounds), 2 wave tiles (ShearSort), 3 group tiles
     bool partition_half;  // sampled partition: one half-wave (else one wave) per tile (env BCF_PARTITION_HALF)
-    bool fused_partition; // one-tile-per-wave merges of regular passes search their own splits (env BCF_FUSED)
+    bool fused_partition; // one-tile-per-wave merges of regular passes search their own splits
     int merge_variant;
     bool nontemporal;
     bool sampled_partition;

@@ -121,8 +121,10 @@ def test_tuning_roundtrip():
 
     before = bcf.get_tuning()
     assert set(before) == {"merge_variant", "nontemporal", "sampled_partition", "tile_samples",
-                           "group_min_keys", "check_runs", "block_sort"}
-    assert before["block_sort"] == 0 and before["merge_variant"] == 3
+                           "group_min_keys", "check_runs", "block_sort", "fused_partition"}
+    assert before["block_sort"] == 0 and before["merge_variant"] == 3 and before["fused_partition"] == 1
+    with bcf.tuning(fused_partition=0):
+        assert bcf.get_tuning()["fused_partition"] == 0
     with bcf.tuning(merge_variant=2, group_min_keys=12345, check_runs=1, block_sort=2):
         t = bcf.get_tuning()
         assert t["merge_variant"] == 2 and t["group_min_keys"] == 12345 and t["check_runs"] == 1

@@ -236,21 +236,42 @@ def test_segmented_log_uniform_batch(torch_dev, bcf):
 # ------------------------------------------------------------------ profiling / errors
 
 
-def test_profile_records_every_launch(torch_dev, bcf):
+@pytest.mark.parametrize("fused", [1, 0])
+def test_profile_records_every_launch(torch_dev, bcf, fused):
     torch, dev = torch_dev
     n = 1 << 20
     keys = to_dev(torch, dev, workloads.keys_u32("uniform", n))
-    bcf.profile_collect()
-    bcf.profile_enable(True)
-    bcf.sort_u32(keys)
-    bcf.profile_enable(False)
-    st = bcf.profile_collect()
-    merges = bcf.sort_passes(n) - 1
+    with bcf.tuning(fused_partition=fused):
+        bcf.profile_collect()
+        bcf.profile_enable(True)
+        bcf.sort_u32(keys)
+        bcf.profile_enable(False)
+        st = bcf.profile_collect()
+        merges = bcf.sort_passes(n) - 1
     assert st["block_sort_keys"]["launches"] == 1
     assert st["merge_keys"]["launches"] == merges
-    assert st["partition_keys"]["launches"] == merges
+    # keys take the one-tile-per-wave merge by default: with fused partitions
+    # it searches its own splits and there is no partition launch
+    assert st.get("partition_keys", {"launches": 0})["launches"] == (0 if fused else merges)
     assert st["merge_keys"]["bytes"] == pytest.approx(merges * 8.0 * n)
     assert all(v["total_ms"] > 0 for v in st.values())
+
+
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("variant", [2, 3])
+def test_fused_partition_parity(torch_dev, bcf, fused, variant):
+    """Merge passes with in-kernel split searches against the oracle (keys and
+    pairs, duplicates, ragged sizes spanning many passes)."""
+    torch, dev = torch_dev
+    with bcf.tuning(fused_partition=fused, merge_variant=variant):
+        for n, dist in [((1 << 21) + 4097, "uniform"), ((1 << 20) + 3, "distinct16"), (600001, "zipf")]:
+            keys = workloads.keys_u32(dist, n, seed=n)
+            got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+            assert first_diff(got, oracle.sort_u32(keys)) is None, (n, dist)
+            kk, vv = workloads.pairs_u32(dist, n, seed=n + 1)
+            ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, kk), to_dev(torch, dev, vv))
+            wk, wv = oracle.sort_pairs_u32(kk, vv)
+            assert first_diff(ko.cpu().numpy(), wk) is None and first_diff(vo.cpu().numpy(), wv) is None
 
 
 @pytest.mark.parametrize("pairs", [False, True])
