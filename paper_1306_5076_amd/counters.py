@@ -20,6 +20,7 @@ with; ``bench.py`` uses a summary only while the sources still hash the same.
     python -m paper_1306_5076_amd.counters trace   DIR OUT.md  --command "..."
     python -m paper_1306_5076_amd.counters traffic FETCH_DIR WRITE_DIR OUT.json --n N --command "..."
     python -m paper_1306_5076_amd.counters lds     DIR OUT.json --command "..."
+    python -m paper_1306_5076_amd.counters summary TRAFFIC.json LDS.json OUT.md --algorithmic-bytes B
 """
 
 from __future__ import annotations
@@ -128,6 +129,28 @@ def lds(directory: str, command: str = "") -> dict:
     return {"kernel_source_hash": kernel_source_hash(), "command": command, "per_kernel": per}
 
 
+def counters_markdown(traffic_json: str, lds_json: str, algorithmic_bytes: float) -> str:
+    """One page from a traffic summary and an LDS summary (both JSON)."""
+    with open(traffic_json) as f:
+        t = json.load(f)
+    with open(lds_json) as f:
+        ld = json.load(f)
+    out = [f"# Counters (kernel source hash {t['kernel_source_hash']})", "",
+           "Commands (repository root on the GPU box, library built in-tree; each counter set in its own run):",
+           "", "    " + ld.get("command", ""), "", "    " + t.get("command", ""), "",
+           "## LDS bank conflicts (per dispatch, averaged)", "",
+           "| kernel | dispatches | SQ_INSTS_LDS | SQ_LDS_BANK_CONFLICT |", "|---|---|---|---|"]
+    for k, v in ld["per_kernel"].items():
+        out.append(f"| `{k}` | {v['dispatches']} | {v['SQ_INSTS_LDS']:.0f} | {v['SQ_LDS_BANK_CONFLICT']:.0f} |")
+    out += ["", f"## HBM traffic per dispatch (FETCH_SIZE x {t['fetch_scale']}, WRITE_SIZE x {t['write_scale']})", "",
+            t["calibration"] + ".", "",
+            "| kernel | dispatches | read MB | written MB | algorithmic MB (read + write) |", "|---|---|---|---|---|"]
+    for k, v in t["per_kernel"].items():
+        alg = f"{algorithmic_bytes / 1e6:.1f}" if k.startswith(("bcf::k_merge", "bcf::k_block_sort")) else "-"
+        out.append(f"| `{k}` | {v['dispatches']} | {v['read_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | {alg} |")
+    return "\n".join(out) + "\n"
+
+
 def _is(kind: str, name: str) -> bool:
     n = short_name(name)
     if kind == "block":
@@ -194,8 +217,17 @@ def main(argv=None):
     ld.add_argument("dir")
     ld.add_argument("out")
     ld.add_argument("--command", default="")
+    sm = sub.add_parser("summary")
+    sm.add_argument("traffic_json")
+    sm.add_argument("lds_json")
+    sm.add_argument("out")
+    sm.add_argument("--algorithmic-bytes", type=float, required=True,
+                    help="read + write bytes one merge or block-sort launch must move")
     a = ap.parse_args(argv)
-    if a.what == "trace":
+    if a.what == "summary":
+        with open(a.out, "w") as fh:
+            fh.write(counters_markdown(a.traffic_json, a.lds_json, a.algorithmic_bytes))
+    elif a.what == "trace":
         text = trace_markdown(a.dir, a.command, a.title, a.n)
         with open(a.out, "w") as fh:
             fh.write(text)
