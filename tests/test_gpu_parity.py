@@ -165,6 +165,98 @@ def test_pairs_2p28_full_size(torch_dev, bcf, dist):
     assert np.array_equal(keys[vo[idx]], ko[idx])
 
 
+# --------------------------------------------------- the largest size the ABI takes
+#
+# n = 2^32 - 1 keys (16 GiB; pairs 32 GiB) fits in the GPU's HBM with the
+# output and the scratch.  The oracle cannot sort this many keys on the host
+# in a test, so the checks are properties that fix the result, computed on the
+# device chunk by chunk: the output is nondecreasing; it is a permutation of the
+# input (per-bucket counts of the top 16 bits, sum and sum of squares modulo
+# 2^64); sampled outputs equal the order statistics of the input by their
+# definition (count of smaller and of not-larger keys); for pairs, every output
+# key is the input key at the output value's index (value = original index)
+# and equal keys keep increasing values (stability).
+
+N_MAX = (1 << 32) - 1
+CH = 1 << 28
+
+
+def _signed(x, torch):
+    """uint32 -> int32 with the unsigned order (flip the sign bit)."""
+    return x.view(torch.int32) ^ torch.tensor(-(1 << 31), dtype=torch.int32, device=x.device)
+
+
+def _chunks(n):
+    return [(lo, min(n, lo + CH)) for lo in range(0, n, CH)]
+
+
+def _multiset_digest(x, torch):
+    hist = torch.zeros(65536, dtype=torch.int64, device=x.device)
+    s1 = torch.zeros((), dtype=torch.int64, device=x.device)
+    s2 = torch.zeros((), dtype=torch.int64, device=x.device)
+    for lo, hi in _chunks(x.numel()):
+        v = x[lo:hi].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        hist += torch.bincount(v >> 16, minlength=65536)
+        s1 += v.sum()
+        s2 += (v * v).sum()  # wraps modulo 2^64
+    return hist.cpu().numpy(), int(s1), int(s2)
+
+
+def _need_bytes(torch, nbytes):
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < nbytes:
+        pytest.skip(f"needs {nbytes / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+
+
+def test_max_size_keys(torch_dev, bcf):
+    torch, dev = torch_dev
+    n = N_MAX
+    _need_bytes(torch, 3 * 4 * n + (4 << 30))
+    keys = workloads.draws_u32_torch(7, n, dev)
+    out = bcf.sort_u32(keys)
+    torch.cuda.synchronize()
+    for lo, hi in _chunks(n):
+        s = _signed(out[lo:min(n, hi + 1)], torch)
+        assert bool((s[1:] >= s[:-1]).all()), lo
+    assert [np.array_equal(a, b) if isinstance(a, np.ndarray) else a == b
+            for a, b in zip(_multiset_digest(out, torch), _multiset_digest(keys, torch))] == [True] * 3
+    # order statistics at sampled ranks, by definition
+    sk = _signed(keys, torch)
+    for i in (0, 1, 12345, n // 3, n // 2 + 7, n - 2, n - 1):
+        v = _signed(out[i:i + 1], torch)
+        less = int((sk < v).sum())
+        not_larger = int((sk <= v).sum())
+        assert less <= i < not_larger, i
+
+
+def test_max_size_pairs(torch_dev, bcf):
+    torch, dev = torch_dev
+    n = N_MAX
+    _need_bytes(torch, 6 * 4 * n + (4 << 30))
+    keys = workloads.keys_u32_torch("zipf", n, dev, seed=5)  # heavy duplicates: stability matters
+    vals = torch.empty(n, dtype=torch.int32, device=dev)
+    for lo, hi in _chunks(n):  # value = original index
+        vals[lo:hi] = torch.arange(lo, hi, dtype=torch.int64, device=dev).to(torch.int32)
+    vals = vals.view(torch.uint32)
+    ko, vo = bcf.sort_pairs_u32(keys, vals)
+    torch.cuda.synchronize()
+    sk_in = keys.view(torch.int32)
+    for lo, hi in _chunks(n):
+        k = _signed(ko[lo:min(n, hi + 1)], torch)
+        v = vo[lo:min(n, hi + 1)].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        assert bool((k[1:] >= k[:-1]).all()), lo
+        same = k[1:] == k[:-1]
+        assert bool((v[1:][same] > v[:-1][same]).all()), lo  # stable
+        # output pair (k, v) is input element v
+        assert bool((sk_in.index_select(0, v) == ko[lo:min(n, hi + 1)].view(torch.int32)).all()), lo
+    # the values are a permutation of 0 .. n-1: counts per top-16-bit bucket, sums
+    hist, s1, s2 = _multiset_digest(vo, torch)
+    assert np.all(hist[:-1] == 65536) and hist[-1] == 65535
+    assert s1 == n * (n - 1) // 2
+    assert s2 == ((n - 1) * n * (2 * n - 1) // 6 + (1 << 63)) % (1 << 64) - (1 << 63)
+
+
 # ------------------------------------------------------------------ merge_runs
 
 
