@@ -158,7 +158,9 @@ typedef struct {
     int32_t merge_variant;     /* merge-pass kernel: 0 persistent waves with next-tile
                                   prefetch (keys), 1 persistent waves, 2 one tile per wave,
                                   3 (default) 2 for keys and 1 for key/value pairs */
-    int32_t nontemporal;       /* 1: nontemporal hints on merge-pass tile loads and stores */
+    int32_t nontemporal;       /* 1 (default): nontemporal hints on merge-pass tile loads and
+                                  stores (in the one-tile-per-wave kernel of a sort only when a
+                                  pass streams more than the 256 MiB last-level cache) */
     int32_t sampled_partition; /* 1 (default): a pass's co-rank search starts from the key samples
                                   the previous pass wrote (sorts); 0: search the keys only */
     int32_t tile_samples;      /* 1 (default): keep one sample per 4096-key tile besides the

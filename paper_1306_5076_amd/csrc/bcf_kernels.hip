@@ -1008,13 +1008,13 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
             m = merge_task<P>(src, splits, t);
         }
         Lines<P> a;
-        merge_load<P>(a, m, lane);
+        merge_load<P, NT>(a, m, lane);
         if constexpr (P)
             stage_merge_values(m, vals, lane);
         merge_network<P>(a, lds, lane, src.out_smp, m.gpos, m.count);
         if constexpr (P)
             gather_values(a, m, vals, lane);
-        store_tile<P>(a, m.kd, m.vd, m.count, lane);
+        store_tile<P, NT>(a, m.kd, m.vd, m.count, lane);
     } else if constexpr (P || MODE == 1) {
         for (; t < src.ntiles; t += G) {
             const uint32_t ln = opaque(lane);
@@ -1156,6 +1156,9 @@ static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream
     }
 }
 
+// MI355X's last-level cache (Infinity Cache): 256 MiB.
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
+
 bool merge_fuses_partition(bool pairs, const SampleSet &in_smp)
 {
     const Tuning tu = tuning();
@@ -1234,6 +1237,11 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
             return hipSuccess;
         if (run % kTile != 0)
             return hipErrorInvalidValue;
+        // nontemporal tile traffic only when a pass streams more than the
+        // last-level cache holds (below that the hint makes the next pass miss)
+        if (tuning().nontemporal && n * (pairs ? 8.0 : 4.0) * 2 > kLastLevelCacheBytes)
+            return pairs ? launch_merge_mode<true, RegularMergeSrc, 2, true, true>(src, splits, s)
+                         : launch_merge_mode<false, RegularMergeSrc, 2, true, true>(src, splits, s);
         return pairs ? launch_merge_mode<true, RegularMergeSrc, 2, false, true>(src, splits, s)
                      : launch_merge_mode<false, RegularMergeSrc, 2, false, true>(src, splits, s);
     }
