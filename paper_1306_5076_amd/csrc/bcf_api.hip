@@ -260,9 +260,11 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     }
     uint64_t run = run0;
     for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
+        // decided once per pass from this call's tuning snapshot: both launches agree
+        const bool fused = merge_fuses_partition(pairs, sampled ? sample_set((j - 1) & 1) : none, tu);
         for (int phase = 0; phase < 2; ++phase) {
             const bool part = phase == 0;
-            if (part && merge_fuses_partition(pairs, sampled ? sample_set((j - 1) & 1) : none))
+            if (part && fused)
                 continue;  // the merge launch searches its own splits
             ProfScope p(part ? kname_partition(pairs, false) : kname_merge(pairs, false), s,
                         part ? 0.0 : 2.0 * elem_bytes * n);
@@ -270,7 +272,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
             const SampleSet out_smp = (sampled && j < passes) ? sample_set(j & 1) : none;
             BCF_TRY(dev_status(launch_merge_regular(pairs, kbuf(j - 1), pairs ? vbuf(j - 1) : nullptr, kbuf(j),
                                                     pairs ? vbuf(j) : nullptr, n, run, splits, in_smp, out_smp,
-                                                    part, s)));
+                                                    part, fused, s)));
         }
     }
     return BCF_OK;

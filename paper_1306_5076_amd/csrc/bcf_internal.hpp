@@ -67,14 +67,17 @@ hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin
 // partition = false the tiles are merged using those splits.
 // The regular partition reads the samples of its input (in_smp, written by
 // the previous launch); the regular merge writes those of its output (out_smp).
-// Whether a regular merge pass is one launch (its merge kernel searches the
-// splits from the samples in in_smp) instead of a partition launch and a merge
-// launch; then the partition call of launch_merge_regular enqueues nothing.
-bool merge_fuses_partition(bool pairs, const SampleSet &in_smp);
+struct Tuning;
+// Whether, under tuning tu, a regular merge pass is one launch (its merge
+// kernel searches the splits from the samples in in_smp) instead of a
+// partition launch and a merge launch.  The caller decides once per pass and
+// passes the answer to both launch_merge_regular calls (with fused = true the
+// partition call enqueues nothing).
+bool merge_fuses_partition(bool pairs, const SampleSet &in_smp, const Tuning &tu);
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc,
                                 uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
                                 uint32_t *splits, SampleSet in_smp, SampleSet out_smp,
-                                bool partition, hipStream_t s);
+                                bool partition, bool fused, hipStream_t s);
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
                                    uint32_t ntiles, hipStream_t s);
 // Group tiles (count <= group_run_keys(pairs)) sorted by a multi-wave work-group.

@@ -1159,9 +1159,8 @@ static hipError_t launch_merge(const Src &src, const uint32_t *splits, hipStream
 // MI355X's last-level cache (Infinity Cache): 256 MiB.
 constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
 
-bool merge_fuses_partition(bool pairs, const SampleSet &in_smp)
+bool merge_fuses_partition(bool pairs, const SampleSet &in_smp, const Tuning &tu)
 {
-    const Tuning tu = tuning();
     return in_smp.f != nullptr && tu.fused_partition && (tu.merge_variant == 2 || (tu.merge_variant == 3 && !pairs));
 }
 
@@ -1227,15 +1226,15 @@ hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32
 
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc, uint32_t *kdst,
                                 uint32_t *vdst, uint64_t n, uint64_t run, uint32_t *splits, SampleSet in_smp,
-                                SampleSet out_smp, bool partition, hipStream_t s)
+                                SampleSet out_smp, bool partition, bool fused, hipStream_t s)
 {
     RegularMergeSrc src{ksrc, pairs ? vsrc : nullptr, kdst, pairs ? vdst : nullptr, n, run,
                         (uint32_t)((n + kTile - 1) / kTile), in_smp, out_smp};
-    if (merge_fuses_partition(pairs, in_smp)) {
+    if (fused) {
         // one launch per pass: the merge kernel searches its own splits
         if (partition)
             return hipSuccess;
-        if (run % kTile != 0)
+        if (run % kTile != 0 || in_smp.f == nullptr)
             return hipErrorInvalidValue;
         // nontemporal tile traffic only when a pass streams more than the
         // last-level cache holds (below that the hint makes the next pass miss)
