@@ -2,7 +2,8 @@
 // planning, descriptor upload and kernel launches.  See include/bcf.h.
 //
 // Plan of a sort of n keys (BCFMergesort, paper Sec. 3 and Lemma 2):
-//   one block-sort launch turns [0, n) into ceil(n / 4096) sorted runs, then
+//   one block-sort launch turns [0, n) into sorted runs of 4096 keys (wave
+//   tiles) or 32768 keys (16384 pairs; multi-wave group tiles), then
 //   ceil(log2(#runs)) binary merge passes double the run length until one run
 //   remains.  Passes ping-pong between the output and the temp buffer; the
 //   block sort writes to whichever buffer makes the last pass end in the
@@ -65,7 +66,12 @@ struct ProfScope {
             on = g_prof_on;
         }
         if (on) {
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            if (hipEventCreate(&a) != hipSuccess) {
+                on = false;
+                return;
+            }
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
                 on = false;
                 return;
             }
@@ -115,8 +121,10 @@ bcf_status upload(void *dst, const void *src, size_t bytes, hipStream_t s)
         st.cap = std::max<size_t>(bytes, 1 << 20);
         if (hipHostMalloc(&st.ptr, st.cap, hipHostMallocDefault) != hipSuccess)
             return BCF_ERR_NOMEM;
-        if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(st.ptr);
             return BCF_ERR_DEVICE;
+        }
         g_stage.push_back(st);
         slot = &g_stage.back();
     }
@@ -587,10 +595,10 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
         if (run_offsets[r + 1] > run_offsets[r])
             runs.push_back({run_offsets[r], run_offsets[r + 1] - run_offsets[r]});
     const uint32_t P = runs.size() > 1 ? ceil_log2(runs.size()) : 0;
-    // In place with an odd pass count would make pass 1 read and write the
-    // output; then every pass is shifted by one buffer and a final copy moves
-    // the result from temp to the output.
-    const bool inplace = keys_in == keys_out;
+    // In place (keys or values) with an odd pass count would make pass 1 read
+    // and write the same buffer; then every pass is shifted by one buffer and
+    // a final copy moves the result from temp to the output.
+    const bool inplace = keys_in == keys_out || (pairs && vals_in == vals_out);
     const bool shift = inplace && (P % 2 == 1);
     // buffer after pass j (j >= 1): counted back from the last pass
     auto buf_after = [&](uint32_t j) -> uint32_t {

@@ -290,6 +290,23 @@ def test_merge_runs_in_place(torch_dev, bcf):
         assert first_diff(t.cpu().numpy(), oracle.merge_runs(keys, offs)) is None
 
 
+@pytest.mark.parametrize("alias", ["keys", "vals", "both"])
+def test_merge_runs_pairs_in_place(torch_dev, bcf, alias):
+    """Key/value merges where the keys, the values or both are merged in place;
+    2 and 5 runs take an odd number of passes, 3 runs an even number."""
+    torch, dev = torch_dev
+    for sizes in ([3000, 4000], [100, 200, 300], [5000] * 5):
+        keys, offs = workloads.sorted_runs(sizes, seed=3, dist="dups")
+        vals = workloads.draws_u32(11, keys.size)
+        kd, vd = to_dev(torch, dev, keys), to_dev(torch, dev, vals)
+        ko = kd if alias in ("keys", "both") else torch.empty_like(kd)
+        vo = vd if alias in ("vals", "both") else torch.empty_like(vd)
+        bcf.merge_runs(kd, offs, vals=vd, keys_out=ko, vals_out=vo)
+        wk, wv = oracle.merge_runs(keys, offs, vals)
+        assert first_diff(ko.cpu().numpy(), wk) is None
+        assert first_diff(vo.cpu().numpy(), wv) is None
+
+
 def test_merge_runs_large(torch_dev, bcf):
     torch, dev = torch_dev
     sizes = workloads.segment_sizes(64, lo=1 << 10, hi=1 << 20, seed=4)
