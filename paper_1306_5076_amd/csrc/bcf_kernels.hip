@@ -61,13 +61,17 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
     if constexpr (P) {
         // all 64 loads first, then the conversions: left to itself the
         // scheduler converts each key right after its load and so waits for
-        // the loads one at a time
-        uint32_t key[kLine];
-        const uint32_t last = count ? count - 1 : 0;
+        // the loads one at a time.  With count == 0 (a group tile's sub-tile
+        // past the end of its input; ksrc may point past the end of the
+        // array) nothing is loaded and every position is padding.
+        uint32_t key[kLine] = {};
+        if (count != 0) {
+            const uint32_t last = count - 1;
 #pragma unroll
-        for (int r = 0; r < kLine; ++r) {
-            const uint32_t p = kWave * r + lane;
-            key[r] = ksrc[p < count ? p : last];  // clamped: always a valid address
+            for (int r = 0; r < kLine; ++r) {
+                const uint32_t p = kWave * r + lane;
+                key[r] = ksrc[p < count ? p : last];  // clamped: always a valid address
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -141,13 +145,17 @@ __device__ __forceinline__ void permute_values_lds(Lines<true> &t, const uint32_
 {
     // stage input positions [stage_off, stage_off + stage_count) of this wave
     // with direct global-to-LDS loads (lanes past the end re-read the first
-    // position; their LDS words are never read)
+    // position; their LDS words are never read).  A wave with nothing to
+    // stage (a group tile's sub-tile past the end of the input, where src
+    // points past the end of the array) issues no load.
     const uint32_t *src = vsrc + stage_off;
+    if (stage_count != 0) {
 #pragma unroll
-    for (int r = 0; r < kLine; ++r) {
-        const uint32_t p = kWave * r + lane;
-        __builtin_amdgcn_global_load_lds((global_cvoid *)(src + (p < stage_count ? p : 0u)),
-                                         (lds_void *)(vals + stage_off + kWave * r), 4, 0, 0);
+        for (int r = 0; r < kLine; ++r) {
+            const uint32_t p = kWave * r + lane;
+            __builtin_amdgcn_global_load_lds((global_cvoid *)(src + (p < stage_count ? p : 0u)),
+                                             (lds_void *)(vals + stage_off + kWave * r), 4, 0, 0);
+        }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     sync();

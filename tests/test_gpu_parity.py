@@ -480,6 +480,38 @@ def test_segmented_pairs_vs_oracle(torch_dev, bcf, sizes):
         assert first_diff(ko[lo:hi], wk) is None and first_diff(vo[lo:hi], wv) is None
 
 
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("sizes", [[3000, 16384 + 100], [20000, 40000, 3 * 16384 + 1]])
+def test_segmented_tail_at_allocation_end(torch_dev, bcf, sizes, pairs):
+    """Inputs that end exactly where their 16 MiB device allocations end, with
+    the last segment's last group tile only partly filled: the waves whose
+    sub-tiles lie past the end of the input must not read past it."""
+    torch, dev = torch_dev
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    n = int(offs[-1])
+    keys = workloads.keys_u32("uniform", n, seed=21)
+    vals = workloads.draws_u32(22, n)
+    cap = 1 << 22
+    kbuf = torch.zeros(cap, dtype=torch.int32, device=dev)
+    kbuf[cap - n:].copy_(torch.from_numpy(keys.view(np.int32)))
+    kd = kbuf.view(torch.uint32)[cap - n:]
+    if pairs:
+        vbuf = torch.zeros(cap, dtype=torch.int32, device=dev)
+        vbuf[cap - n:].copy_(torch.from_numpy(vals.view(np.int32)))
+        ko, vo = bcf.segmented_sort(kd, offs, vals=vbuf.view(torch.uint32)[cap - n:])
+        ko, vo = ko.cpu().numpy(), vo.cpu().numpy()
+    else:
+        ko = bcf.segmented_sort(kd, offs).cpu().numpy()
+    for sg in range(len(sizes)):
+        lo, hi = int(offs[sg]), int(offs[sg + 1])
+        if pairs:
+            wk, wv = oracle.sort_pairs_u32(keys[lo:hi], vals[lo:hi])
+            assert first_diff(ko[lo:hi], wk) is None and first_diff(vo[lo:hi], wv) is None
+        else:
+            assert first_diff(ko[lo:hi], oracle.sort_u32(keys[lo:hi])) is None
+
+
 @pytest.mark.parametrize("group_min", [4097, 1000000000, 0])
 def test_segmented_group_threshold(torch_dev, bcf, group_min):
     # the same segments block-sorted in group tiles or in wave tiles
