@@ -139,6 +139,29 @@ def bench_block_sorts(bcf, workloads, torch, dev, n=1 << 26, reps=5):
     return res
 
 
+def bench_fan_in(bcf, workloads, torch, dev, n=1 << 26, reps=5):
+    """Merge fan-in at 2^26 uniform keys: four-way passes (default) against
+    binary passes; whole sort and the per-launch time of each merge kernel."""
+    from paper_1306_5076_amd import autotune
+
+    keys = workloads.keys_u32_torch("uniform", n, dev, seed=1)
+    out = torch.empty_like(keys)
+    ws = bcf.Workspace(dev)
+    res = {"n": n}
+    for k in (4, 2):
+        with bcf.tuning(merge_fan_in=k):
+            fn = lambda: bcf.sort_u32(keys, out=out, workspace=ws)
+            ms = autotune.time_ms(fn, reps=reps, warmup=1)
+            bcf.profile_collect()
+            bcf.profile_enable(True)
+            fn()
+            bcf.profile_enable(False)
+            st = bcf.profile_collect()
+            res[f"fan_in_{k}"] = {"sort_ms": round(ms, 4), "Gkeys_per_s": round(n / ms / 1e6, 3),
+                                  "passes": bcf.sort_passes(n), "kernels": _kernel_table(st)}
+    return res
+
+
 def bench_pairs(bcf, workloads, torch, dev, n=1 << 28, steps=5, warmup=2):
     """2^28 stable key/value sorts (value = original index), uniform and Zipf keys."""
     from paper_1306_5076_amd import autotune
@@ -315,8 +338,10 @@ def main():
     bytes_per_launch = st["bytes"] / st["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernels = _kernel_table(stats)
-    traffic_name, traffic_rec = counted_kernel(committed_counters("traffic_sort_keys_2p26.json"),
-                                               "bcf::k_merge<false, bcf::RegularMergeSrc")
+    # the rocprofv3 name of the dominant launch record
+    prefix = {"merge_keys": "bcf::k_merge<false, bcf::RegularMergeSrc", "merge4_keys": "bcf::k_merge4<",
+              "block_sort_keys": "bcf::k_block_sort"}.get(dominant, "-")
+    traffic_name, traffic_rec = counted_kernel(committed_counters("traffic_sort_keys_2p26.json"), prefix)
     conflicts_rec = committed_counters("lds_sort_keys_2p26.json")
 
     rec = {
@@ -371,6 +396,7 @@ def main():
         t0s = time.perf_counter()
         rec["small_2p16"] = bench_small(bcf, workloads, torch, dev)
         rec["block_sort_ablation"] = bench_block_sorts(bcf, workloads, torch, dev)
+        rec["fan_in_ablation"] = bench_fan_in(bcf, workloads, torch, dev)
         rec["pairs_2p28"] = bench_pairs(bcf, workloads, torch, dev)
         torch.cuda.empty_cache()
         rec["segmented"] = bench_segmented(bcf, workloads, torch, dev)

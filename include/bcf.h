@@ -139,18 +139,23 @@ uint32_t bcf_tile_keys(void);
  * tuning, sorts of at most 2^19 keys use wave tiles (see bcf_tuning). */
 uint32_t bcf_run_keys(int pairs);
 
-/* Passes over the data in HBM of a sort of n keys: the block sort plus
- * ceil(log2(n / bcf_run_keys(pairs))) binary merge passes (the paper's Lemma 2:
- * O(1 + log(N/M)) scans).  Each merge pass finds the split of every 4096-key
- * output tile by reading O(log n) key samples and keys, in a small partition
- * launch before it or (see bcf_tuning.fused_partition) in the merge kernel. */
+/* Passes over the data in HBM of a sort of n keys under the current tuning:
+ * the block sort plus the merge passes (the paper's Lemma 2: O(1 + log(N/M))
+ * scans).  With merge_fan_in 2 (and for pairs) every merge pass is binary:
+ * ceil(log2(R)) passes for R = ceil(n / bcf_run_keys(pairs)) runs.  With
+ * fan-in 4 (keys-only sorts) a pass merges groups of four runs while more than
+ * two remain, two levels of the paper's binary merging (Sec. 3.2) per read
+ * and write of the data, and a last binary pass merges the final two runs if
+ * needed: 2^11 runs take 6 passes instead of 11.  Each merge pass finds its
+ * work split by reading O(log n) key samples and keys, in a small launch
+ * before it or (see bcf_tuning.fused_partition) in the merge kernel. */
 uint32_t bcf_sort_passes(uint64_t n, int pairs);
 
 /*
  * Process-wide tuning knobs (read by every later call; not per stream).
  * Initial values come from environment variables read once, at the first
  * call into the library: BCF_MERGE_MODE, BCF_NT, BCF_NO_SAMPLES,
- * BCF_TILE_SAMPLES, BCF_SEG_GROUP_MIN, BCF_CHECK, BCF_BLOCK_SORT, BCF_FUSED.  The autotuner sets them
+ * BCF_TILE_SAMPLES, BCF_SEG_GROUP_MIN, BCF_CHECK, BCF_BLOCK_SORT, BCF_FUSED, BCF_FAN_IN.  The autotuner sets them
  * through bcf_set_tuning.  Calls that are in flight on other threads when the
  * knobs change may use either setting; results are identical either way.
  */
@@ -178,10 +183,15 @@ typedef struct {
                                   run by the one-tile-per-wave kernel finds each tile's split
                                   itself from the samples (one launch per pass); 0: a separate
                                   partition launch first */
+    int32_t merge_fan_in;      /* runs merged per group by a merge pass of bcf_sort_u32: 4
+                                  (default; needs sampled_partition, else 2 is used) or 2.
+                                  Key/value sorts, bcf_merge_runs and segmented sorts always
+                                  merge pairs of runs */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);
-/* BCF_ERR_INVALID for a NULL pointer or an out-of-range merge_variant or block_sort. */
+/* BCF_ERR_INVALID for a NULL pointer, an out-of-range merge_variant or block_sort, or a
+ * merge_fan_in other than 2 or 4. */
 bcf_status bcf_set_tuning(const bcf_tuning *in);
 
 /*

@@ -61,6 +61,7 @@ class Tuning(ctypes.Structure):
         ("check_runs", ctypes.c_int32),
         ("block_sort", ctypes.c_int32),
         ("fused_partition", ctypes.c_int32),
+        ("merge_fan_in", ctypes.c_int32),
     ]
 
 

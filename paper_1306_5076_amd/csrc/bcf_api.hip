@@ -167,6 +167,7 @@ Tuning &tuning_locked()
         g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
         if (g_tune.block_sort < 0 || g_tune.block_sort > 3)
             g_tune.block_sort = 0;
+        g_tune.merge_fan_in = env_int("BCF_FAN_IN", 4) == 2 ? 2 : 4;
         g_tune_init = true;
     }
     return g_tune;
@@ -211,6 +212,24 @@ uint64_t sort_run_keys(bool pairs, uint64_t n, const Tuning &tu)
     return sort_uses_groups(n, tu) ? group_run_keys(pairs) : (uint64_t)kTile;
 }
 
+// Fan-in of every merge pass of an n-key regular sort, first pass first:
+// four-way passes while more than two runs remain (keys only; their work
+// split is searched from key samples), then at most one binary pass.
+std::vector<uint32_t> sort_fan_ins(bool pairs, uint64_t n, const Tuning &tu)
+{
+    std::vector<uint32_t> fi;
+    if (n == 0)
+        return fi;
+    const uint64_t run0 = sort_run_keys(pairs, n, tu);
+    const bool four = !pairs && tu.merge_fan_in == 4 && tu.sampled_partition;
+    for (uint64_t runs = (n + run0 - 1) / run0; runs > 1;) {
+        const uint32_t k = (four && runs > 2) ? 4 : 2;
+        fi.push_back(k);
+        runs = (runs + k - 1) / k;
+    }
+    return fi;
+}
+
 bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                      uint64_t n, void *temp, uint64_t *temp_bytes, hipStream_t s)
 {
@@ -219,13 +238,17 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     const uint64_t tiles = tiles_of(n);
     const Tuning tu = tuning();
     const uint64_t run0 = sort_run_keys(pairs, n, tu);  // sorted run length after the block sort
-    const uint32_t passes = n ? ceil_log2((n + run0 - 1) / run0) : 0;
-    // temp: ping-pong keys [, values], one split per merge tile, then two
-    // sets of key samples (each pass reads one set and writes the other)
+    const std::vector<uint32_t> fan_in = sort_fan_ins(pairs, n, tu);
+    const uint32_t passes = (uint32_t)fan_in.size();
+    // temp: ping-pong keys [, values], one split per merge tile, two sets of
+    // key samples (each pass reads one set and writes the other), then (keys)
+    // the cut list of a four-way pass.  The layout does not depend on the
+    // tuning, so a size queried before a tuning change stays valid.
     const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
     const uint64_t blocks64 = (n + kLine - 1) / kLine;
     const uint64_t set_bytes = 2 * align256(blocks64 * 4) + 2 * align256(tiles * 4);
-    const uint64_t need = passes ? data + align256(tiles * 4) + 2 * set_bytes : 0;
+    const uint64_t cut_bytes = pairs ? 0 : align256(merge4_cut_bytes_max(n));
+    const uint64_t need = passes ? data + align256(tiles * 4) + 2 * set_bytes + cut_bytes : 0;
     if (!temp) {
         *temp_bytes = need;
         return BCF_OK;
@@ -266,8 +289,20 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
             BCF_TRY(dev_status(launch_block_sort_regular(pairs, tu.block_sort == 2, kin, vin, kbuf(0),
                                                          pairs ? vbuf(0) : nullptr, n, smp, s)));
     }
+    void *cuts = static_cast<char *>(temp) + data + align256(tiles * 4) + 2 * set_bytes;
     uint64_t run = run0;
-    for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
+    for (uint32_t j = 1; j <= passes; run *= fan_in[j - 1], ++j) {
+        if (fan_in[j - 1] == 4) {
+            const SampleSet in_smp = sample_set((j - 1) & 1);
+            const SampleSet out_smp = j < passes ? sample_set(j & 1) : none;
+            for (int phase = 0; phase < 2; ++phase) {
+                const bool cut = phase == 0;
+                ProfScope p(cut ? "cuts4_keys" : "merge4_keys", s, cut ? 0.0 : 2.0 * elem_bytes * n);
+                BCF_TRY(dev_status(launch_merge4_regular(kbuf(j - 1), kbuf(j), n, run, cuts, in_smp, out_smp, cut,
+                                                         s)));
+            }
+            continue;
+        }
         // decided once per pass from this call's tuning snapshot: both launches agree
         const bool fused = merge_fuses_partition(pairs, sampled ? sample_set((j - 1) & 1) : none, tu);
         for (int phase = 0; phase < 2; ++phase) {
@@ -555,8 +590,7 @@ uint32_t bcf_sort_passes(uint64_t n, int pairs)
 {
     if (n == 0)
         return 0;
-    const uint64_t run0 = sort_run_keys(pairs != 0, n, tuning());
-    return 1 + ceil_log2((n + run0 - 1) / run0);
+    return 1 + (uint32_t)sort_fan_ins(pairs != 0, n, tuning()).size();
 }
 
 bcf_status bcf_sort_u32(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n, void *temp,
@@ -724,11 +758,13 @@ void bcf_get_tuning(bcf_tuning *out)
     out->check_runs = t.check_runs;
     out->block_sort = t.block_sort;
     out->fused_partition = t.fused_partition;
+    out->merge_fan_in = t.merge_fan_in;
 }
 
 bcf_status bcf_set_tuning(const bcf_tuning *in)
 {
-    if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 3)
+    if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 3 ||
+        (in->merge_fan_in != 2 && in->merge_fan_in != 4))
         return BCF_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_tune_mu);
     Tuning &t = tuning_locked();
@@ -740,6 +776,7 @@ bcf_status bcf_set_tuning(const bcf_tuning *in)
     t.check_runs = in->check_runs != 0;
     t.block_sort = in->block_sort;
     t.fused_partition = in->fused_partition != 0;
+    t.merge_fan_in = in->merge_fan_in;
     return BCF_OK;
 }
 

@@ -272,18 +272,27 @@ __device__ __forceinline__ auto &elems(Lines<P> &t)
         return t.k;
 }
 
-// STRIDED -> BLOCKED: write word 65r + lane, read word 65 lane + r.
+// STRIDED -> BLOCKED: write word 68r + lane, read word 68 lane + r.
 template <bool P>
 __device__ __forceinline__ void to_blocked(Lines<P> &t, uint32_t *lds, uint32_t lane)
 {
     exchange<kLdsStride, 1>(elems(t), lds, lane, kLdsStride * lane);
 }
 
-// BLOCKED -> STRIDED: write word 65 lane + r, read word 65r + lane.
+// BLOCKED -> STRIDED: write word 68 lane + r, read word 68r + lane.  Afterwards
+// LDS word 68q + r holds tile position 64q + r.
 template <bool P>
 __device__ __forceinline__ void to_strided(Lines<P> &t, uint32_t *lds, uint32_t lane)
 {
     exchange<1, kLdsStride>(elems(t), lds, kLdsStride * lane, lane);
+}
+
+// BLOCKED -> STRIDED with the positions reversed (position p of the result
+// holds position 4095 - p): write word 68 lane + r, read word
+// 68(63 - r) + 63 - lane (consecutive lanes, consecutive words).
+__device__ __forceinline__ void to_strided_reversed(Lines<false> &t, uint32_t *lds, uint32_t lane)
+{
+    exchange<1, -kLdsStride>(t.k, lds, kLdsStride * lane, kLdsStride * (kLine - 1) + (kWave - 1) - lane);
 }
 
 // ---------------------------------------------------------------- wave utils

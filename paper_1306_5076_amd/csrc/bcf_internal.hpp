@@ -78,6 +78,15 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
                                 uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
                                 uint32_t *splits, SampleSet in_smp, SampleSet out_smp,
                                 bool partition, bool fused, hipStream_t s);
+// Fan-in 4 merge pass of a regular keys-only sort: groups of four runs of
+// `run` keys (a multiple of 4096) become runs of 4 run.  The cut phase
+// (cut_phase = true) searches the pass's work split from the samples of the
+// input (in_smp, required) into `cuts` (merge4_cut_bytes(n, run) bytes); the
+// merge phase then merges and writes the samples of its output (out_smp).
+uint64_t merge4_cut_bytes(uint64_t n, uint64_t run);
+uint64_t merge4_cut_bytes_max(uint64_t n);  // the largest over every plan of an n-key sort
+hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t n, uint64_t run, void *cuts,
+                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s);
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
                                    uint32_t ntiles, hipStream_t s);
 // Group tiles (count <= group_run_keys(pairs)) sorted by a multi-wave work-group.
@@ -100,6 +109,7 @@ struct Tuning {
     bool tile_samples;
     uint64_t group_min_keys;
     bool check_runs;
+    int merge_fan_in;  // 2 or 4: runs merged per group in the merge passes of a keys-only sort
 };
 Tuning tuning();
 

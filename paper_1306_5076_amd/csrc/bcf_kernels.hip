@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "bcf_device.hpp"
 #include "bcf_internal.hpp"
 
@@ -1067,6 +1069,285 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
     }
 }
 
+// ------------------------------------------------ fan-in 4 merge passes
+//
+// A fan-in 4 pass merges groups of four consecutive runs A, B, C, D of
+// length L (a multiple of 4096) into runs of 4L: two levels of the paper's
+// binary merging (Sec. 3.2; AB = merge(A, B), CD = merge(C, D), then
+// merge(AB, CD), equal keys in run order) for one read and one write of the
+// data instead of two of each.  Neither AB nor CD is ever written.
+//
+// Work split.  The four-way merge path of a group is cut at every multiple
+// of 4096 of AB and at every multiple of 4096 plus kCutOffset of CD.  An AB
+// cut at x takes the A/B split of x from the binary co-rank, reads the key
+// k = AB[x] and counts the C and D keys below k (C and D keys equal to k
+// come after it): two searches in single sorted runs, no search inside a
+// virtual sequence.  A CD cut is the same with the roles swapped (A and B
+// keys equal to k come before it).  Consecutive cuts bound one merge item:
+// at most 4096 elements of AB and at most 4096 of CD, found without any
+// nested search.  The offset puts the CD cuts between the AB cuts when the
+// runs interleave, so items hold about 4096 elements each.
+//
+// Positions in path order: an AB cut (x, y) comes after exactly the CD cuts
+// with 4096 c' + kCutOffset < y, a CD cut (x, y) after exactly the AB cuts
+// with 4096 c < x, so every cut computes its own slot in the group's list.
+
+constexpr uint32_t kCutOffset = 2048;
+
+// The runs of group g of a fan-in 4 pass over n keys with runs of L.
+struct Group4 {
+    uint64_t start;  // array position of A[0]
+    uint32_t n[4];   // lengths of A, B, C, D (runs past the end are empty)
+    uint32_t ab_cuts, cd_cuts;
+    __device__ Group4(uint64_t nkeys, uint64_t L, uint32_t g)
+    {
+        start = (uint64_t)g * 4 * L;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint64_t s = start + r * L;
+            const uint64_t rem = nkeys > s ? nkeys - s : 0;
+            n[r] = (uint32_t)(rem < L ? rem : L);
+        }
+        const uint32_t nab = n[0] + n[1], ncd = n[2] + n[3];
+        ab_cuts = (nab + kTile - 1) / kTile;
+        cd_cuts = ncd > kCutOffset ? (ncd - kCutOffset + kTile - 1) / kTile : 0;
+    }
+};
+
+struct Merge4Src {
+    const uint32_t *ksrc;
+    uint32_t *kdst;
+    uint64_t n, run;
+    uint32_t groups;
+    uint32_t per_group;  // cut searches per full group (L / 1024); merge items are one more
+    uint4 *cuts;         // per group: per_group + 2 cuts of (a, b, c, d)
+    SampleSet in_smp, out_smp;
+};
+
+// Number of keys of the sorted run R[0, nr) (at array position rpos, a
+// multiple of 4096) below k (strict: at most k), searched by each half-wave
+// for its own run and key: tile samples, block samples, keys.
+__device__ __forceinline__ uint32_t rank_half(const SampleSet &sm, const uint32_t *__restrict__ R, uint64_t rpos,
+                                              uint32_t nr, uint32_t k, bool strict, uint32_t lane)
+{
+    auto above = [&](uint32_t v) { return strict ? v > k : v >= k; };
+    auto tile_pred = [&](uint32_t i) { return above(sm.cf[(rpos + i) / kTile]); };
+    auto block_pred = [&](uint32_t i) { return above(sm.f[(rpos + i) / kLine]); };
+    auto key_pred = [&](uint32_t i) { return above(R[i]); };
+    uint32_t lo = 0, hi = nr;
+    if (sm.cf != nullptr)
+        corank_level_half<kTile>(lo, hi, lane, tile_pred);
+    else
+        corank_level_half<kTile>(lo, hi, lane, block_pred);
+    corank_level_half<kLine>(lo, hi, lane, block_pred);
+    corank_level_half<1>(lo, hi, lane, key_pred);
+    return lo;
+}
+
+// One wave per cut search; task j of group g is AB cut j (j < ab_cuts) or CD
+// cut j - ab_cuts.  The task with j == 0 also writes the group's first cut
+// (nothing taken) and last cut (everything taken).
+__global__ __launch_bounds__(256) void k_cuts4(Merge4Src src)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t task = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    const uint32_t g = task / src.per_group, j = task % src.per_group;
+    if (g >= src.groups)
+        return;
+    const Group4 G(src.n, src.run, g);
+    if (j >= G.ab_cuts + G.cd_cuts)
+        return;
+    const uint32_t *K = src.ksrc + G.start;
+    const uint64_t L = src.run;
+    const bool ab = j < G.ab_cuts;
+    // the binary split of the cut's own side: AB at x = 4096 j, or CD at
+    // y = 4096 j' + offset (a multiple of 64 only: block samples)
+    const uint32_t r0 = ab ? 0 : 2;  // first run of the cut's side
+    const uint32_t n0 = G.n[r0], n1 = G.n[r0 + 1];
+    const uint32_t d = ab ? j * kTile : (j - G.ab_cuts) * kTile + kCutOffset;
+    MergeItem m;
+    m.ka = K + r0 * L;
+    m.va = nullptr;
+    m.kd = nullptr;
+    m.vd = nullptr;
+    m.base = G.start + r0 * L;
+    m.na = n0;
+    m.nb = n1;
+    m.d0 = d;
+    m.count = 0;
+    SampleSet sm = src.in_smp;
+    if (!ab)
+        sm.cf = sm.cl = nullptr;  // tile samples need diagonals that are multiples of 4096
+    uint32_t lo = d > n1 ? d - n1 : 0, hi = d < n0 ? d : n0;
+    corank_sampled_half(sm, m, d, lane, lo, hi);  // both halves search the same diagonal
+    const uint32_t s0 = __builtin_amdgcn_readlane(lo, 0), s1 = d - s0;
+    const uint32_t *R0 = m.ka, *R1 = m.ka + L;
+    const uint32_t k = (s0 < n0 && (s1 >= n1 || R0[s0] <= R1[s1])) ? R0[s0] : R1[s1];
+    // the other side's two runs: lanes 0..31 count in its first, 32..63 in its second
+    const uint32_t ro = (ab ? 2 : 0) + (lane >> 5);
+    const uint32_t cnt = rank_half(src.in_smp, K + ro * L, G.start + ro * L, G.n[ro], k, !ab, lane);
+    const uint32_t o0 = __builtin_amdgcn_readlane(cnt, 0), o1 = __builtin_amdgcn_readlane(cnt, 32);
+    uint4 cut;
+    uint32_t slot;
+    if (ab) {
+        const uint32_t y = o0 + o1;
+        const uint32_t before = y > kCutOffset ? (y - kCutOffset + kTile - 1) / kTile : 0;
+        cut = make_uint4(s0, s1, o0, o1);
+        slot = 1 + j + (before < G.cd_cuts ? before : G.cd_cuts);
+    } else {
+        const uint32_t x = o0 + o1;
+        const uint32_t before = (x + kTile - 1) / kTile;
+        cut = make_uint4(o0, o1, s0, s1);
+        slot = 1 + (j - G.ab_cuts) + (before < G.ab_cuts ? before : G.ab_cuts);
+    }
+    uint4 *cuts = src.cuts + (uint64_t)g * (src.per_group + 2);
+    if (lane == 0)
+        cuts[slot] = cut;
+    if (j == 0 && lane == 1)
+        cuts[0] = make_uint4(0, 0, 0, 0);
+    if (j == 0 && lane == 2)
+        cuts[1 + G.ab_cuts + G.cd_cuts] = make_uint4(G.n[0], G.n[1], G.n[2], G.n[3]);
+}
+
+// The merge network of a bitonic STRIDED tile, ending in STRIDED order
+// (REV: with the positions reversed).
+template <bool REV>
+__device__ __forceinline__ void merge4_network(Lines<false> &t, uint32_t *lds, uint32_t lane)
+{
+    half_clean<kLine / 2, -1, false>(t);
+    to_blocked(t, lds, lane);
+    half_clean<kLine / 2, -1, false>(t);
+    if constexpr (REV)
+        to_strided_reversed(t, lds, lane);
+    else
+        to_strided(t, lds, lane);
+}
+
+// Store `count` sorted keys of a STRIDED tile at array position gpos and the
+// samples of the output that fall inside it: the first and last key of every
+// 64-key block and every 4096-key tile of the array.  The tile's last
+// to_strided left tile position 64q + r in LDS word 68q + r.
+template <bool NT>
+__device__ __forceinline__ void emit4(const Lines<false> &t, const uint32_t *lds, uint32_t *kdst, uint64_t gpos,
+                                      uint32_t count, const SampleSet &smp, uint32_t lane)
+{
+    if (smp.f != nullptr) {
+        const uint32_t bf = (uint32_t)((kLine - gpos % kLine) % kLine);  // first block start in the tile
+        const uint32_t bl = (bf + kLine - 1) % kLine;                    // first block end
+        const uint32_t pf = bf + kLine * lane, pl = bl + kLine * lane;
+        if (pf < count)
+            smp.f[(gpos + pf) / kLine] = lds[kLdsStride * lane + bf];
+        if (pl < count)
+            smp.l[(gpos + pl) / kLine] = lds[kLdsStride * lane + bl];
+        if (smp.cf != nullptr) {
+            const uint32_t tf = (uint32_t)((kTile - gpos % kTile) % kTile);
+            const uint32_t tl = (tf + kTile - 1) % kTile;
+            if (lane == 0 && tf < count)
+                smp.cf[(gpos + tf) / kTile] = lds[kLdsStride * (tf / kLine) + tf % kLine];
+            if (lane == 1 && tl < count)
+                smp.cl[(gpos + tl) / kTile] = lds[kLdsStride * (tl / kLine) + tl % kLine];
+        }
+    }
+    store_tile<false, NT>(t, kdst + gpos, nullptr, count, lane);
+}
+
+// The padding tile (every position the maximum key).
+__device__ __forceinline__ void pad_tile(Lines<false> &t)
+{
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        t.k[r] = kMaxKey;
+}
+
+constexpr int kMerge4Waves = 4;
+
+// One wave per merge item: the item's A and B pieces merge into T1 (sorted,
+// padding after), its C and D pieces into T2.  T1 followed by T2 reversed is
+// a bitonic sequence of 8192 slots; its first half-cleaner stage is an
+// elementwise min / max of T1 and reversed T2, and each half is then merged
+// by the 4096-slot network.  The high half holds keys only when the item has
+// more than 4096.  An item with one side empty is that side's merge.
+template <bool NT>
+__global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4(Merge4Src src)
+{
+    __shared__ __align__(16) uint32_t lds_all[kMerge4Waves][kLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint32_t *lds = lds_all[wave];
+    const uint32_t item = blockIdx.x * kMerge4Waves + wave;
+    const uint32_t per = src.per_group + 1;
+    const uint32_t g = item / per, i = item % per;
+    if (g >= src.groups)
+        return;
+    const Group4 G(src.n, src.run, g);
+    if (i > G.ab_cuts + G.cd_cuts)
+        return;
+    const uint4 *cuts = src.cuts + (uint64_t)g * (src.per_group + 2);
+    const uint4 c0 = cuts[i], c1 = cuts[i + 1];
+    // every piece inside its run and at most 4096 keys per side (holds for
+    // cuts written by k_cuts4; checked so that no cut can move a load or a
+    // store outside the group)
+    if (c0.x > c1.x || c0.y > c1.y || c0.z > c1.z || c0.w > c1.w || c1.x > G.n[0] || c1.y > G.n[1] ||
+        c1.z > G.n[2] || c1.w > G.n[3])
+        return;
+    const uint32_t pa = c1.x - c0.x, pb = c1.y - c0.y, pc = c1.z - c0.z, pd = c1.w - c0.w;
+    const uint32_t sx = pa + pb, sy = pc + pd, count = sx + sy;
+    if (count == 0 || sx > (uint32_t)kTile || sy > (uint32_t)kTile)
+        return;
+    const uint64_t L = src.run;
+    const uint32_t *K = src.ksrc + G.start;
+    const uint64_t gpos = G.start + c0.x + c0.y + c0.z + c0.w;
+    Lines<false> t1, t2;
+    // all loads of both halves first (A and B pieces: A ascending at the front,
+    // B reversed at the back; the same for C and D)
+    if (sx) {
+        MergeTask<false> m;
+        m.ka = K + c0.x;
+        m.kb = K + L + c0.y;
+        m.pa = pa;
+        m.pb = pb;
+        m.count = sx;
+        merge_load<false, NT>(t1, m, lane);
+    } else {
+        pad_tile(t1);
+    }
+    if (sy) {
+        MergeTask<false> m;
+        m.ka = K + 2 * L + c0.z;
+        m.kb = K + 3 * L + c0.w;
+        m.pa = pc;
+        m.pb = pd;
+        m.count = sy;
+        merge_load<false, NT>(t2, m, lane);
+    } else {
+        pad_tile(t2);
+    }
+    if (sy == 0) {
+        merge4_network<false>(t1, lds, lane);
+        emit4<NT>(t1, lds, src.kdst, gpos, count, src.out_smp, lane);
+        return;
+    }
+    if (sx == 0) {
+        merge4_network<false>(t2, lds, lane);
+        emit4<NT>(t2, lds, src.kdst, gpos, count, src.out_smp, lane);
+        return;
+    }
+    merge4_network<false>(t1, lds, lane);
+    merge4_network<true>(t2, lds, lane);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t a = t1.k[r], b = t2.k[r];
+        t1.k[r] = a < b ? a : b;
+        t2.k[r] = a < b ? b : a;
+    }
+    merge4_network<false>(t1, lds, lane);
+    emit4<NT>(t1, lds, src.kdst, gpos, count < (uint32_t)kTile ? count : (uint32_t)kTile, src.out_smp, lane);
+    if (count > (uint32_t)kTile) {
+        merge4_network<false>(t2, lds, lane);
+        emit4<NT>(t2, lds, src.kdst, gpos + kTile, count - kTile, src.out_smp, lane);
+    }
+}
+
 // Sortedness check of the runs of a merge input: sets *flag when some
 // keys[i] > keys[i+1] with i+1 not the start of a run.
 __global__ void k_check_runs(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ offs, uint32_t k,
@@ -1268,6 +1549,50 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
         return hipGetLastError();
     }
     return pairs ? launch_merge<true>(src, splits, s) : launch_merge<false>(src, splits, s);
+}
+
+uint64_t merge4_cut_bytes(uint64_t n, uint64_t run)
+{
+    if (run == 0 || run % kTile != 0)
+        return 0;
+    const uint64_t groups = (n + 4 * run - 1) / (4 * run);
+    return groups * (run / 1024 + 2) * sizeof(uint4);
+}
+
+uint64_t merge4_cut_bytes_max(uint64_t n)
+{
+    // four-way passes run while more than two runs remain (n > 2 run), on
+    // runs of 4096 * 4^i or 32768 * 4^i keys
+    uint64_t most = 0;
+    for (uint64_t run0 : {(uint64_t)kTile, (uint64_t)kGroupWavesKeys * kTile})
+        for (uint64_t run = run0; n > 2 * run; run *= 4)
+            most = std::max(most, merge4_cut_bytes(n, run));
+    return most;
+}
+
+hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t n, uint64_t run, void *cuts,
+                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s)
+{
+    // the cut searches read the samples of the input; runs start at multiples of 4096
+    if (n == 0 || run % kTile != 0 || in_smp.f == nullptr || in_smp.l == nullptr || cuts == nullptr)
+        return hipErrorInvalidValue;
+    const uint64_t groups = (n + 4 * run - 1) / (4 * run);
+    const uint64_t per_group = run / 1024;
+    Merge4Src src{ksrc, kdst, n, run, (uint32_t)groups, (uint32_t)per_group, static_cast<uint4 *>(cuts), in_smp,
+                  out_smp};
+    if (cut_phase) {
+        const uint64_t tasks = groups * per_group;
+        hipLaunchKernelGGL(k_cuts4, dim3((uint32_t)((tasks + 3) / 4)), dim3(256), 0, s, src);
+        return hipGetLastError();
+    }
+    const uint64_t items = groups * (per_group + 1);
+    const dim3 grid((uint32_t)((items + kMerge4Waves - 1) / kMerge4Waves)), block(kWave * kMerge4Waves);
+    // nontemporal tile traffic only when a pass streams more than the last-level cache
+    if (tuning().nontemporal && n * 4.0 * 2 > kLastLevelCacheBytes)
+        hipLaunchKernelGGL(k_merge4<true>, grid, block, 0, s, src);
+    else
+        hipLaunchKernelGGL(k_merge4<false>, grid, block, 0, s, src);
+    return hipGetLastError();
 }
 
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles, uint32_t ntiles,

@@ -54,11 +54,58 @@ def test_tile_run_and_pass_count(lib):
         assert lib.bcf_sort_passes(1, pairs) == 1
         assert lib.bcf_sort_passes(4096, pairs) == 1
         assert lib.bcf_sort_passes(4097, pairs) == 2
-        # Lemma 2: 1 + ceil(log2(n / M)) passes over the data, M the block-sort run
-        for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**26, 2**28, 3 * R + 5 + small]:
+        # Lemma 2: 1 + O(log(n / M)) passes over the data, M the block-sort run:
+        # binary passes for pairs; for keys four-way passes while more than two
+        # runs remain, then at most one binary pass
+        for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**26, 2**28, 3 * R + 5 + small, 2**32 - 1]:
             m = 4096 if n <= small else R
             runs = -(-n // m)
-            assert lib.bcf_sort_passes(n, pairs) == 1 + int(np.ceil(np.log2(runs)))
+            if pairs:
+                want = int(np.ceil(np.log2(runs)))
+            else:
+                want = 0
+                while runs > 1:
+                    runs = -(-runs // (4 if runs > 2 else 2))
+                    want += 1
+            assert lib.bcf_sort_passes(n, pairs) == 1 + want, (n, pairs)
+    assert lib.bcf_sort_passes(2**26, 0) == 1 + 6  # 2^11 runs: five four-way passes and one binary
+    assert lib.bcf_sort_passes(3 * 4096, 0) == 2  # three runs: one four-way pass
+
+
+def test_pass_count_binary_fan_in(lib):
+    from paper_1306_5076_amd._native import Tuning
+
+    t = Tuning()
+    lib.bcf_get_tuning(ctypes.byref(t))
+    old = Tuning.from_buffer_copy(t)
+    try:
+        t.merge_fan_in = 2
+        assert lib.bcf_set_tuning(ctypes.byref(t)) == 0
+        for n in [2**12 + 1, 2**20, 2**26, 2**32 - 1]:
+            m = 4096 if n <= 1 << 19 else 32768
+            assert lib.bcf_sort_passes(n, 0) == 1 + int(np.ceil(np.log2(-(-n // m))))
+        # the temp size does not depend on the fan-in
+        assert q_sort(lib, 2**26) == q_sort(lib, 2**26)
+        need2 = q_sort(lib, 2**26)[1]
+        t.merge_fan_in = 4
+        assert lib.bcf_set_tuning(ctypes.byref(t)) == 0
+        assert q_sort(lib, 2**26)[1] == need2
+        t.merge_fan_in = 3
+        assert lib.bcf_set_tuning(ctypes.byref(t)) == 1
+    finally:
+        assert lib.bcf_set_tuning(ctypes.byref(old)) == 0
+
+
+def merge4_cut_bytes_max(n):
+    """Cut lists of the four-way passes: per group of four runs of L keys,
+    L / 1024 + 2 cuts of 16 bytes; the largest over both block-sort run lengths."""
+    most = 0
+    for run0 in (4096, 32768):
+        run = run0
+        while n > 2 * run:
+            most = max(most, -(-n // (4 * run)) * (run // 1024 + 2) * 16)
+            run *= 4
+    return most
 
 
 def test_temp_queries(lib):
@@ -72,6 +119,11 @@ def test_temp_queries(lib):
     # two sets of key samples (every 64-block: first and last; every tile: first and last)
     tiles, blocks = 2**26 // 4096, 2**26 // 64
     assert st == 0 and need == 2 * 2**26 * 4 + tiles * 4 + 2 * (2 * blocks * 4 + 2 * tiles * 4)
+    # keys: one ping-pong array, the splits, the samples, and the four-way cut lists
+    st, need = q_sort(lib, 2**26)
+    cuts = -(-merge4_cut_bytes_max(2**26) // 256) * 256
+    assert st == 0 and need == 2**26 * 4 + tiles * 4 + 2 * (2 * blocks * 4 + 2 * tiles * 4) + cuts
+    assert cuts < 2**26 * 4 // 64
     assert q_sort(lib, 2**32)[0] == 1  # above 2^32 - 1 keys: invalid
 
 
@@ -121,26 +173,33 @@ def test_tuning_roundtrip():
 
     before = bcf.get_tuning()
     assert set(before) == {"merge_variant", "nontemporal", "sampled_partition", "tile_samples",
-                           "group_min_keys", "check_runs", "block_sort", "fused_partition"}
+                           "group_min_keys", "check_runs", "block_sort", "fused_partition", "merge_fan_in"}
     assert before["block_sort"] == 0 and before["merge_variant"] == 3 and before["fused_partition"] == 1
+    assert before["merge_fan_in"] == 4
     with bcf.tuning(fused_partition=0):
         assert bcf.get_tuning()["fused_partition"] == 0
-    with bcf.tuning(merge_variant=2, group_min_keys=12345, check_runs=1, block_sort=2):
+    with bcf.tuning(merge_variant=2, group_min_keys=12345, check_runs=1, block_sort=2, merge_fan_in=2):
         t = bcf.get_tuning()
         assert t["merge_variant"] == 2 and t["group_min_keys"] == 12345 and t["check_runs"] == 1
-        assert t["block_sort"] == 2
+        assert t["block_sort"] == 2 and t["merge_fan_in"] == 2
         # wave tiles hand runs of 4096 keys to the merge passes
         assert bcf.run_keys() == 4096 and bcf.run_keys(pairs=True) == 4096
         assert bcf.sort_passes(1 << 26) == 1 + 14
+    with bcf.tuning(block_sort=2):  # 2^14 runs: seven four-way passes
+        assert bcf.sort_passes(1 << 26) == 1 + 7 and bcf.sort_passes(1 << 26, pairs=True) == 1 + 14
     assert bcf.get_tuning() == before
-    assert bcf.run_keys() == 32768 and bcf.sort_passes(1 << 26) == 1 + 11
-    # default block sort: wave tiles up to 2^19 keys, group tiles above
-    assert bcf.sort_passes(1 << 19) == 1 + 7 and bcf.sort_passes((1 << 19) + 1) == 1 + 5
+    assert bcf.run_keys() == 32768 and bcf.sort_passes(1 << 26) == 1 + 6
+    with bcf.tuning(merge_fan_in=2):
+        assert bcf.sort_passes(1 << 26) == 1 + 11
+        # default block sort: wave tiles up to 2^19 keys, group tiles above
+        assert bcf.sort_passes(1 << 19) == 1 + 7 and bcf.sort_passes((1 << 19) + 1) == 1 + 5
+    # the same with four-way passes: 128 runs -> 32 -> 8 -> 2 -> 1; 17 runs -> 5 -> 2 -> 1
+    assert bcf.sort_passes(1 << 19) == 1 + 4 and bcf.sort_passes((1 << 19) + 1) == 1 + 3
     with bcf.tuning(block_sort=3):
         assert bcf.sort_passes(1 << 16) == 1 + 1 and bcf.sort_passes(1 << 15) == 1
     from paper_1306_5076_amd import BcfError
 
-    for bad in ({"merge_variant": 7}, {"block_sort": 4}, {"block_sort": -1}):
+    for bad in ({"merge_variant": 7}, {"block_sort": 4}, {"block_sort": -1}, {"merge_fan_in": 3}):
         with pytest.raises(BcfError):
             bcf.set_tuning(**bad)
     assert bcf.get_tuning() == before

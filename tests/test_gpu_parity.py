@@ -350,7 +350,7 @@ def test_profile_records_every_launch(torch_dev, bcf, fused):
     torch, dev = torch_dev
     n = 1 << 20
     keys = to_dev(torch, dev, workloads.keys_u32("uniform", n))
-    with bcf.tuning(fused_partition=fused):
+    with bcf.tuning(fused_partition=fused, merge_fan_in=2):
         bcf.profile_collect()
         bcf.profile_enable(True)
         bcf.sort_u32(keys)
@@ -364,6 +364,65 @@ def test_profile_records_every_launch(torch_dev, bcf, fused):
     assert st.get("partition_keys", {"launches": 0})["launches"] == (0 if fused else merges)
     assert st["merge_keys"]["bytes"] == pytest.approx(merges * 8.0 * n)
     assert all(v["total_ms"] > 0 for v in st.values())
+
+
+def test_profile_records_four_way_passes(torch_dev, bcf):
+    # 2^20 keys in 32 runs of 32768: four-way passes to 8 and 2 runs, then one binary pass
+    torch, dev = torch_dev
+    n = 1 << 20
+    keys = to_dev(torch, dev, workloads.keys_u32("uniform", n))
+    bcf.profile_collect()
+    bcf.profile_enable(True)
+    bcf.sort_u32(keys)
+    bcf.profile_enable(False)
+    st = bcf.profile_collect()
+    assert bcf.sort_passes(n) == 4
+    assert st["block_sort_keys"]["launches"] == 1
+    assert st["cuts4_keys"]["launches"] == 2 and st["merge4_keys"]["launches"] == 2
+    assert st["merge_keys"]["launches"] == 1
+    assert st["merge4_keys"]["bytes"] == pytest.approx(2 * 8.0 * n)
+
+
+# run counts around the four-way grouping: 3 runs (the fourth empty), 4, 5
+# (a four-way pass, then a binary one), ragged last groups of 1..4 runs, many
+# passes; with wave tiles (runs of 4096) and group tiles (runs of 32768)
+FOUR_WAY_CASES = [(3 * 4096, 1), (3 * 4096 - 7, 1), (4 * 4096, 1), (5 * 4096 + 1, 1), (16 * 4096 + 4095, 1),
+                  (17 * 4096, 1), (61 * 4096 + 100, 1), (300007, 1), (3 * 32768 + 5, 3), (9 * 32768, 3),
+                  ((1 << 20) + 3, 0), (5 * (1 << 19) + 77, 0), ((1 << 22) + 12345, 0)]
+
+
+@pytest.mark.parametrize("n,block_sort", FOUR_WAY_CASES)
+def test_four_way_merge_passes(torch_dev, bcf, n, block_sort):
+    """Sorts whose merge passes take four runs at a time (the default for keys)
+    against the oracle, over distributions with many, few and no ties."""
+    torch, dev = torch_dev
+    with bcf.tuning(block_sort=block_sort, merge_fan_in=4):
+        for dist in ("uniform", "distinct16", "sorted", "reverse", "zipf"):
+            keys = workloads.keys_u32(dist, n, seed=n % 1000 + 3)
+            got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+            assert first_diff(got, oracle.sort_u32(keys)) is None, (n, block_sort, dist)
+
+
+@pytest.mark.parametrize("nt", [0, 1])
+def test_four_way_same_as_binary(torch_dev, bcf, nt):
+    """Four-way and binary merge passes give the same bytes (keys, all equal
+    keys, two values, and a sort large enough for nontemporal traffic)."""
+    torch, dev = torch_dev
+    for n, make in [((1 << 21) + 999, lambda n: workloads.keys_u32("uniform", n, seed=9)),
+                    (400000, lambda n: np.full(n, 7, dtype=np.uint32)),
+                    (700001, lambda n: (workloads.draws_u32(4, n) & 1).astype(np.uint32)),
+                    ((1 << 26) + 4097, None)]:
+        if make is None:
+            kd = workloads.draws_u32_torch(12, n, dev)
+        else:
+            kd = to_dev(torch, dev, make(n))
+        with bcf.tuning(merge_fan_in=4, nontemporal=nt):
+            a = bcf.sort_u32(kd)
+        with bcf.tuning(merge_fan_in=2, nontemporal=nt):
+            b = bcf.sort_u32(kd)
+        assert bool(torch.equal(a, b)), n
+        if make is not None:
+            assert first_diff(a.cpu().numpy(), oracle.sort_u32(make(n))) is None, n
 
 
 @pytest.mark.parametrize("fused", [1, 0])

@@ -542,3 +542,204 @@ def test_shear_sort_schedule_01_principle_sampled():
         x = np.zeros(T, dtype=np.uint32)
         x[rng.permutation(T)[:ones]] = 1
         assert np.array_equal(shear_tile_model(x), np.sort(x))
+
+
+# ------------------------------------------------- fan-in 4 merge pass plan
+#
+# Model of the four-way merge pass: the merge of runs A, B, C, D (a group of
+# four consecutive runs of length L) is the binary merge of AB = merge(A, B)
+# and CD = merge(C, D).  The pass cuts the four-way merge path at every
+# multiple of 4096 of AB and at every multiple of 4096 plus CUT_OFFSET of CD;
+# each cut is found with binary co-ranks and single-run rank searches only,
+# and the span between consecutive cuts (one merge item) holds at most 4096
+# elements of AB and at most 4096 of CD.
+
+CUT_OFFSET = 2048
+
+
+def bitonic_tile_network(tile):
+    """The merge network of a bitonic 4096-slot tile (STRIDED in, STRIDED out)."""
+    lanes = np.arange(W)
+    regs = np.empty((W, E), dtype=tile.dtype)
+    for r in range(E):
+        regs[:, r] = tile[W * r + lanes]
+    apply(regs, half_clean(E // 2, -1))
+    regs = fast_to_blocked(regs)
+    apply(regs, half_clean(E // 2, -1))
+    regs = fast_to_strided(regs)
+    out = np.empty_like(tile)
+    for r in range(E):
+        out[W * r + lanes] = regs[:, r]
+    return out
+
+
+def rank_sampled(arr, rpos, nr, k, strict, probes_per_round=32):
+    """Elements of the sorted run arr[rpos:rpos+nr] below k (strict: at most
+    k): three levels over tile samples, block samples and keys."""
+    cf, f = arr[::4096], arr[::64]
+    pred = (lambda v: v > k) if strict else (lambda v: v >= k)
+    lo, hi = 0, nr
+    lo, hi = corank_level(lo, hi, 4096, lambda i: pred(cf[(rpos + i) // 4096]), probes_per_round)
+    assert hi - lo <= 4096
+    lo, hi = corank_level(lo, hi, 64, lambda i: pred(f[(rpos + i) // 64]), probes_per_round)
+    assert hi - lo <= 64
+    lo, hi = corank_level(lo, hi, 1, lambda i: pred(arr[rpos + i]), probes_per_round)
+    assert lo == hi
+    return lo
+
+
+def corank_blocks(arr, apos, na, nb, d, probes_per_round=64):
+    """corank_sampled for a diagonal that is a multiple of 64 only: the first
+    level steps 4096 candidates at a time but reads block samples."""
+    f, l = arr[::64], arr[63::64]
+    bpos = apos + na
+    lo, hi = max(0, d - nb), min(d, na)
+    bp = lambda i: f[(apos + i) // 64] > l[(bpos + d - 1 - i) // 64]
+    lo, hi = corank_level(lo, hi, 4096, bp, probes_per_round)
+    lo, hi = corank_level(lo, hi, 64, bp, probes_per_round)
+    lo, hi = corank_level(lo, hi, 1, lambda i: arr[apos + i] > arr[bpos + d - 1 - i], probes_per_round)
+    assert lo == hi
+    return lo
+
+
+def group_runs(n, L, g):
+    base = 4 * L * g
+    return base, [int(min(max(n - base - r * L, 0), L)) for r in range(4)]
+
+
+def ceil_div(a, b):
+    return -(-a // b)
+
+
+def cuts4_model(arr, n, L, g):
+    """Cut list of group g (start, every AB and CD cut in path order, end)."""
+    base, (na, nb, nc, nd) = group_runs(n, L, g)
+    A, B, C, D = (base + r * L for r in range(4))
+    nab_t, ncd_t = ceil_div(na + nb, 4096), ceil_div(max(nc + nd - CUT_OFFSET, 0), 4096)
+    cuts = [None] * (nab_t + ncd_t + 2)
+    cuts[0] = (0, 0, 0, 0)
+    cuts[-1] = (na, nb, nc, nd)
+    for j in range(nab_t):
+        x = 4096 * j
+        a = corank_sampled(arr, A, na, nb, x)
+        b = x - a
+        k = arr[A + a] if a < na and (b >= nb or arr[A + a] <= arr[B + b]) else arr[B + b]
+        c, e = rank_sampled(arr, C, nc, k, False), rank_sampled(arr, D, nd, k, False)
+        y = c + e
+        before = min(ceil_div(max(y - CUT_OFFSET, 0), 4096), ncd_t)
+        assert cuts[1 + j + before] is None
+        cuts[1 + j + before] = (a, b, c, e)
+    for j in range(ncd_t):
+        y = 4096 * j + CUT_OFFSET
+        c = corank_blocks(arr, C, nc, nd, y)
+        e = y - c
+        k = arr[C + c] if c < nc and (e >= nd or arr[C + c] <= arr[D + e]) else arr[D + e]
+        a, b = rank_sampled(arr, A, na, k, True), rank_sampled(arr, B, nb, k, True)
+        before = min(ceil_div(a + b, 4096), nab_t)
+        assert cuts[1 + j + before] is None
+        cuts[1 + j + before] = (a, b, c, e)
+    return cuts
+
+
+def merge4_item_model(arr, n, L, g, c0, c1, out, smp):
+    """One merge item: two half merges, the lo/hi split of their bitonic
+    concatenation, one network per output half, samples at global positions."""
+    base, _ = group_runs(n, L, g)
+    A, B, C, D = (base + r * L for r in range(4))
+    pa, pb, pc, pe = (c1[i] - c0[i] for i in range(4))
+    assert min(pa, pb, pc, pe) >= 0
+    sx, sy = pa + pb, pc + pe
+    assert sx <= 4096 and sy <= 4096
+    pad = np.iinfo(arr.dtype).max
+    t1 = np.full(T, pad, dtype=arr.dtype)
+    t2 = np.full(T, pad, dtype=arr.dtype)
+    if sx:
+        t1[:sx] = merge_tile_model(arr[A + c0[0]:A + c1[0]], arr[B + c0[1]:B + c1[1]])
+    if sy:
+        t2[:sy] = merge_tile_model(arr[C + c0[2]:C + c1[2]], arr[D + c0[3]:D + c1[3]])
+    cnt = sx + sy
+    obase = base + sum(c0)
+    if sy == 0:
+        halves = [t1]
+    elif sx == 0:
+        halves = [t2]
+    else:
+        r2 = t2[::-1]
+        halves = [bitonic_tile_network(np.minimum(t1, r2))]
+        if cnt > 4096:
+            halves.append(bitonic_tile_network(np.maximum(t1, r2)))
+    for h, tile in enumerate(halves):
+        hb, hc = obase + 4096 * h, min(cnt - 4096 * h, 4096)
+        out[hb:hb + hc] = tile[:hc]
+        for p in range(hc):  # the kernel writes exactly these sample words
+            gp = hb + p
+            if gp % 64 == 0:
+                smp["f"][gp // 64] = tile[p]
+            if gp % 64 == 63:
+                smp["l"][gp // 64] = tile[p]
+            if gp % 4096 == 0:
+                smp["cf"][gp // 4096] = tile[p]
+            if gp % 4096 == 4095:
+                smp["cl"][gp // 4096] = tile[p]
+
+
+def merge4_pass_model(arr, n, L):
+    """Every group's cuts and items; returns the output and its samples."""
+    out = np.full_like(arr, -1)
+    smp = {k: np.full(ceil_div(n, s), -1, dtype=arr.dtype) for k, s in (("f", 64), ("l", 64), ("cf", 4096),
+                                                                          ("cl", 4096))}
+    for g in range(ceil_div(n, 4 * L)):
+        cuts = cuts4_model(arr, n, L, g)
+        for i in range(len(cuts) - 1):
+            assert all(cuts[i][r] <= cuts[i + 1][r] for r in range(4)), (g, i)
+            merge4_item_model(arr, n, L, g, cuts[i], cuts[i + 1], out, smp)
+    return out, smp
+
+
+def _runs_input(n, L, dist, seed):
+    rng = np.random.default_rng(seed)
+    if dist == "random":
+        keys = rng.integers(0, 2**32, size=n, dtype=np.int64)
+    elif dist == "dups":
+        keys = rng.integers(0, 3, size=n, dtype=np.int64)
+    elif dist == "ascending":  # every run above the previous one
+        keys = np.arange(n, dtype=np.int64)
+    else:  # "descending": every run below the previous one
+        keys = (n - np.arange(n, dtype=np.int64)) // L * L + (np.arange(n) % L)
+    arr = np.zeros(ceil_div(n, 4096) * 4096 + 4096, dtype=np.int64)
+    for s in range(0, n, L):
+        arr[s:min(s + L, n)] = np.sort(keys[s:min(s + L, n)])
+    # the samples the previous pass wrote are these views of its output (the
+    # padding past n never reaches a search: brackets stay inside the runs)
+    return arr
+
+
+@pytest.mark.parametrize("n,L", [(4 * 8192, 8192), (4 * 8192 * 2 + 3 * 8192 + 100, 8192), (8192 + 5, 8192),
+                                 (2 * 16384 + 4096, 16384), (4 * 4096 * 3 + 4096 * 2 + 1, 4096)])
+@pytest.mark.parametrize("dist", ["random", "dups", "ascending", "descending"])
+def test_merge4_pass_plan(n, L, dist):
+    arr = _runs_input(n, L, dist, seed=n + L)
+    out, smp = merge4_pass_model(arr, n, L)
+    want = np.concatenate([np.sort(arr[s:min(s + 4 * L, n)], kind="stable") for s in range(0, n, 4 * L)])
+    assert np.array_equal(out[:n], want)
+    # every sample word the next pass reads was written, with the right key
+    # (last-of-block samples exist for full blocks: a search reads no other)
+    res = out[:n]
+    assert np.array_equal(smp["f"], res[::64])
+    assert np.array_equal(smp["cf"], res[::4096])
+    assert np.array_equal(smp["l"][: n // 64], res[63::64])
+    assert np.array_equal(smp["cl"][: n // 4096], res[4095::4096])
+
+
+def test_merge4_items_balanced_on_random_keys():
+    """With CD cuts offset by half a tile, random runs give items of about
+    4096 outputs (no item near 8192 next to a near-empty one)."""
+    n, L = 4 * 16384, 16384
+    arr = _runs_input(n, L, "random", seed=5)
+    sizes = []
+    cuts = cuts4_model(arr, n, L, 0)
+    for i in range(len(cuts) - 1):
+        sizes.append(sum(cuts[i + 1]) - sum(cuts[i]))
+    assert sum(sizes) == n
+    assert max(sizes) <= 8192
+    assert np.median(sizes) > 3000
