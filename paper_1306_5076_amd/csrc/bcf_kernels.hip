@@ -1078,21 +1078,30 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const 
 // data instead of two of each.  Neither AB nor CD is ever written.
 //
 // Work split.  The four-way merge path of a group is cut at every multiple
-// of 4096 of AB and at every multiple of 4096 plus kCutOffset of CD.  An AB
-// cut at x takes the A/B split of x from the binary co-rank, reads the key
-// k = AB[x] and counts the C and D keys below k (C and D keys equal to k
+// of kCutStep of AB and at every multiple of kCutStep plus kCutOffset of CD.
+// An AB cut at x takes the A/B split of x from the binary co-rank, reads the
+// key k = AB[x] and counts the C and D keys below k (C and D keys equal to k
 // come after it): two searches in single sorted runs, no search inside a
 // virtual sequence.  A CD cut is the same with the roles swapped (A and B
 // keys equal to k come before it).  Consecutive cuts bound one merge item:
-// at most 4096 elements of AB and at most 4096 of CD, found without any
-// nested search.  The offset puts the CD cuts between the AB cuts when the
-// runs interleave, so items hold about 4096 elements each.
+// at most kCutStep elements of AB and at most kCutStep of CD, found without
+// any nested search.  The offset puts the CD cuts between the AB cuts when
+// the runs interleave, so that an item's two sides often hold at most 2048
+// keys each; such an item takes two merge networks instead of three.
 //
 // Positions in path order: an AB cut (x, y) comes after exactly the CD cuts
-// with 4096 c' + kCutOffset < y, a CD cut (x, y) after exactly the AB cuts
-// with 4096 c < x, so every cut computes its own slot in the group's list.
+// with kCutStep c' + kCutOffset < y, a CD cut (x, y) after exactly the AB
+// cuts with kCutStep c < x, so every cut computes its own slot in the list.
 
-constexpr uint32_t kCutOffset = 2048;
+constexpr uint32_t kCutStep = 3840;    // a multiple of 64 (block samples)
+constexpr uint32_t kCutOffset = 1920;  // a multiple of 64
+constexpr uint32_t kHalfTile = kTile / 2;
+
+// Cut searches of a full group of four runs of L keys.
+__host__ __device__ constexpr uint64_t cuts_per_group(uint64_t L)
+{
+    return (2 * L + kCutStep - 1) / kCutStep + (2 * L - kCutOffset + kCutStep - 1) / kCutStep;
+}
 
 // The runs of group g of a fan-in 4 pass over n keys with runs of L.
 struct Group4 {
@@ -1109,8 +1118,8 @@ struct Group4 {
             n[r] = (uint32_t)(rem < L ? rem : L);
         }
         const uint32_t nab = n[0] + n[1], ncd = n[2] + n[3];
-        ab_cuts = (nab + kTile - 1) / kTile;
-        cd_cuts = ncd > kCutOffset ? (ncd - kCutOffset + kTile - 1) / kTile : 0;
+        ab_cuts = (nab + kCutStep - 1) / kCutStep;
+        cd_cuts = ncd > kCutOffset ? (ncd - kCutOffset + kCutStep - 1) / kCutStep : 0;
     }
 };
 
@@ -1119,93 +1128,127 @@ struct Merge4Src {
     uint32_t *kdst;
     uint64_t n, run;
     uint32_t groups;
-    uint32_t per_group;  // cut searches per full group (L / 1024); merge items are one more
+    uint32_t per_group;  // cut searches per full group; merge items are one more
     uint4 *cuts;         // per group: per_group + 2 cuts of (a, b, c, d)
     SampleSet in_smp, out_smp;
 };
 
-// Number of keys of the sorted run R[0, nr) (at array position rpos, a
-// multiple of 4096) below k (strict: at most k), searched by each half-wave
-// for its own run and key: tile samples, block samples, keys.
-__device__ __forceinline__ uint32_t rank_half(const SampleSet &sm, const uint32_t *__restrict__ R, uint64_t rpos,
-                                              uint32_t nr, uint32_t k, bool strict, uint32_t lane)
+// One level of a monotone search by groups of 2^LOGP lanes, each group with
+// its own bracket and predicate: the smallest i in [lo, hi] with pred(i)
+// (hi counting as true) is narrowed to a bracket of width at most G by
+// 2^LOGP-ary rounds over the candidates i = G*c in [lo, hi).
+template <uint32_t G, int LOGP, class Pred>
+__device__ __forceinline__ void search_level(uint32_t &lo, uint32_t &hi, uint32_t lane, const Pred &pred)
 {
-    auto above = [&](uint32_t v) { return strict ? v > k : v >= k; };
-    auto tile_pred = [&](uint32_t i) { return above(sm.cf[(rpos + i) / kTile]); };
-    auto block_pred = [&](uint32_t i) { return above(sm.f[(rpos + i) / kLine]); };
-    auto key_pred = [&](uint32_t i) { return above(R[i]); };
-    uint32_t lo = 0, hi = nr;
-    if (sm.cf != nullptr)
-        corank_level_half<kTile>(lo, hi, lane, tile_pred);
-    else
-        corank_level_half<kTile>(lo, hi, lane, block_pred);
-    corank_level_half<kLine>(lo, hi, lane, block_pred);
-    corank_level_half<1>(lo, hi, lane, key_pred);
-    return lo;
+    constexpr uint32_t P = 1u << LOGP;
+    constexpr uint64_t kMask = P == 64 ? ~0ull : ((1ull << P) - 1);
+    const uint32_t k = lane & (P - 1);
+    const uint32_t shift = lane & ~(P - 1);
+    uint32_t c0 = (lo + G - 1) / G;
+    uint32_t c1 = hi > 0 ? (hi - 1) / G + 1 : 0;
+    while (__ballot(c0 < c1) != 0) {
+        const bool act = c0 < c1;
+        const uint32_t span = act ? c1 - c0 : 0;
+        const uint32_t c = c0 + (uint32_t)(((uint64_t)span * k) >> LOGP);  // probe of this lane
+        const bool fail = act && !pred(G * c);
+        const uint32_t cnt = __popcll((__ballot(fail) >> shift) & kMask);  // probes 0..cnt-1 fail
+        if (act) {
+            if (cnt == 0) {
+                hi = min(hi, G * c0);
+                c1 = c0;
+            } else {
+                const uint32_t cf = c0 + (uint32_t)(((uint64_t)span * (cnt - 1)) >> LOGP);
+                lo = max(lo, G * cf + 1);
+                if (cnt < P) {
+                    const uint32_t cn = c0 + (uint32_t)(((uint64_t)span * cnt) >> LOGP);
+                    hi = min(hi, G * cn);
+                    c1 = cn;
+                }
+                c0 = cf + 1;
+            }
+        }
+    }
 }
 
-// One wave per cut search; task j of group g is AB cut j (j < ab_cuts) or CD
-// cut j - ab_cuts.  The task with j == 0 also writes the group's first cut
-// (nothing taken) and last cut (everything taken).
+// Cut searches, two per wave: lanes 0..31 take task 2w, lanes 32..63 task
+// 2w + 1; task j of group g is AB cut j (j < ab_cuts) or CD cut j - ab_cuts.
+// A half-wave first finds the binary split of its cut's own side (three
+// sampled levels, 32 probes per round; the diagonal is a multiple of 64, so
+// the first two levels read block samples), reads the cut's key, then counts
+// that key in the other side's two runs with one 16-lane group per run at
+// the same time.  The task with j == 0 also writes the group's first cut
+// (nothing taken) and last cut (all taken).
 __global__ __launch_bounds__(256) void k_cuts4(Merge4Src src)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t task = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    const uint32_t half = lane >> 5;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    const uint32_t task = 2 * wave + half;
     const uint32_t g = task / src.per_group, j = task % src.per_group;
-    if (g >= src.groups)
+    const bool in_range = g < src.groups;
+    const Group4 G(src.n, src.run, in_range ? g : 0);
+    const bool valid = in_range && j < G.ab_cuts + G.cd_cuts;
+    if (__ballot(valid) == 0)
         return;
-    const Group4 G(src.n, src.run, g);
-    if (j >= G.ab_cuts + G.cd_cuts)
-        return;
-    const uint32_t *K = src.ksrc + G.start;
     const uint64_t L = src.run;
+    const SampleSet &sm = src.in_smp;
     const bool ab = j < G.ab_cuts;
-    // the binary split of the cut's own side: AB at x = 4096 j, or CD at
-    // y = 4096 j' + offset (a multiple of 64 only: block samples)
-    const uint32_t r0 = ab ? 0 : 2;  // first run of the cut's side
-    const uint32_t n0 = G.n[r0], n1 = G.n[r0 + 1];
-    const uint32_t d = ab ? j * kTile : (j - G.ab_cuts) * kTile + kCutOffset;
-    MergeItem m;
-    m.ka = K + r0 * L;
-    m.va = nullptr;
-    m.kd = nullptr;
-    m.vd = nullptr;
-    m.base = G.start + r0 * L;
-    m.na = n0;
-    m.nb = n1;
-    m.d0 = d;
-    m.count = 0;
-    SampleSet sm = src.in_smp;
-    if (!ab)
-        sm.cf = sm.cl = nullptr;  // tile samples need diagonals that are multiples of 4096
+    const uint32_t r0 = ab ? 0 : 2;  // first run of the cut's own side
+    const uint32_t n0 = ab ? G.n[0] : G.n[2], n1 = ab ? G.n[1] : G.n[3];
+    const uint32_t d = ab ? j * kCutStep : (j - G.ab_cuts) * kCutStep + kCutOffset;
+    const uint64_t apos = G.start + r0 * L, bpos = apos + n0;
+    const uint32_t *A = src.ksrc + apos, *B = A + n0;
     uint32_t lo = d > n1 ? d - n1 : 0, hi = d < n0 ? d : n0;
-    corank_sampled_half(sm, m, d, lane, lo, hi);  // both halves search the same diagonal
-    const uint32_t s0 = __builtin_amdgcn_readlane(lo, 0), s1 = d - s0;
-    const uint32_t *R0 = m.ka, *R1 = m.ka + L;
-    const uint32_t k = (s0 < n0 && (s1 >= n1 || R0[s0] <= R1[s1])) ? R0[s0] : R1[s1];
-    // the other side's two runs: lanes 0..31 count in its first, 32..63 in its second
-    const uint32_t ro = (ab ? 2 : 0) + (lane >> 5);
-    const uint32_t cnt = rank_half(src.in_smp, K + ro * L, G.start + ro * L, G.n[ro], k, !ab, lane);
-    const uint32_t o0 = __builtin_amdgcn_readlane(cnt, 0), o1 = __builtin_amdgcn_readlane(cnt, 32);
+    if (!valid)
+        lo = hi = 0;
+    auto block_pred = [&](uint32_t i) { return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine]; };
+    search_level<kTile, 5>(lo, hi, lane, block_pred);  // 4096 candidates apart
+    search_level<kLine, 5>(lo, hi, lane, block_pred);
+    search_level<1, 5>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
+    const uint32_t s0 = lo, s1 = d - s0;
+    uint32_t k = 0;
+    if (valid)
+        k = (s0 < n0 && (s1 >= n1 || A[s0] <= B[s1])) ? A[s0] : B[s1];
+    // the other side: lanes 16..31 of a half count in its second run.  An AB
+    // cut counts keys below k (C and D keys equal to k follow it), a CD cut
+    // keys at most k (A and B keys equal to k precede it).
+    const uint32_t ro = (ab ? 2 : 0) + ((lane >> 4) & 1);
+    const uint32_t nr = valid ? (ro == 0 ? G.n[0] : ro == 1 ? G.n[1] : ro == 2 ? G.n[2] : G.n[3]) : 0;
+    const uint64_t rpos = G.start + ro * L;
+    const uint32_t *R = src.ksrc + rpos;
+    const bool strict = !ab;
+    auto above = [&](uint32_t v) { return strict ? v > k : v >= k; };
+    uint32_t rlo = 0, rhi = nr;
+    search_level<kTile, 4>(rlo, rhi, lane, [&](uint32_t i) {
+        return sm.cf != nullptr ? above(sm.cf[(rpos + i) / kTile]) : above(sm.f[(rpos + i) / kLine]);
+    });
+    search_level<kLine, 4>(rlo, rhi, lane, [&](uint32_t i) { return above(sm.f[(rpos + i) / kLine]); });
+    search_level<1, 4>(rlo, rhi, lane, [&](uint32_t i) { return above(R[i]); });
+    // the counts of this half's two groups (lanes 32h and 32h + 16)
+    const uint32_t q0 = __builtin_amdgcn_readlane(rlo, 0), q1 = __builtin_amdgcn_readlane(rlo, 16);
+    const uint32_t q2 = __builtin_amdgcn_readlane(rlo, 32), q3 = __builtin_amdgcn_readlane(rlo, 48);
+    const uint32_t o0 = half ? q2 : q0, o1 = half ? q3 : q1;
+    if (!valid || (lane & 31) > 2)
+        return;
     uint4 cut;
     uint32_t slot;
     if (ab) {
         const uint32_t y = o0 + o1;
-        const uint32_t before = y > kCutOffset ? (y - kCutOffset + kTile - 1) / kTile : 0;
+        const uint32_t before = y > kCutOffset ? (y - kCutOffset + kCutStep - 1) / kCutStep : 0;
         cut = make_uint4(s0, s1, o0, o1);
         slot = 1 + j + (before < G.cd_cuts ? before : G.cd_cuts);
     } else {
         const uint32_t x = o0 + o1;
-        const uint32_t before = (x + kTile - 1) / kTile;
+        const uint32_t before = (x + kCutStep - 1) / kCutStep;
         cut = make_uint4(o0, o1, s0, s1);
         slot = 1 + (j - G.ab_cuts) + (before < G.ab_cuts ? before : G.ab_cuts);
     }
     uint4 *cuts = src.cuts + (uint64_t)g * (src.per_group + 2);
-    if (lane == 0)
+    if ((lane & 31) == 0)
         cuts[slot] = cut;
-    if (j == 0 && lane == 1)
+    if (j == 0 && (lane & 31) == 1)
         cuts[0] = make_uint4(0, 0, 0, 0);
-    if (j == 0 && lane == 2)
+    if (j == 0 && (lane & 31) == 2)
         cuts[1 + G.ab_cuts + G.cd_cuts] = make_uint4(G.n[0], G.n[1], G.n[2], G.n[3]);
 }
 
@@ -1259,14 +1302,141 @@ __device__ __forceinline__ void pad_tile(Lines<false> &t)
         t.k[r] = kMaxKey;
 }
 
+// Put a STRIDED tile in LDS the way to_strided leaves it (word 68q + r holds
+// position 64q + r), for emit4 after a side that needed no network.
+__device__ __forceinline__ void stage_tile(const Lines<false> &t, uint32_t *lds, uint32_t lane)
+{
+    lds_put<kLdsStride>(lds + lane, t.k);
+    wave_lds_fence();
+}
+
+// Load pieces X = [x, x + nx) and Y = [y, y + ny) of one array as a bitonic
+// tile (X ascending at the front, Y reversed at the back).  With one piece
+// empty the other is loaded ascending (REV = false: already sorted) or
+// reversed at the back (REV = true: already in the order the final merge of
+// the two sides takes it), and no network is needed.
+template <bool NT>
+__device__ __forceinline__ bool load_side(Lines<false> &t, const uint32_t *x, uint32_t nx, const uint32_t *y,
+                                          uint32_t ny, bool rev, uint32_t lane)
+{
+    MergeTask<false> m;
+    m.count = nx + ny;
+    if (nx != 0 && ny != 0) {
+        m.ka = x;
+        m.kb = y;
+        m.pa = nx;
+        m.pb = ny;
+        merge_load<false, NT>(t, m, lane);
+        return true;  // two pieces: the side needs its merge network
+    }
+    const uint32_t *one = nx ? x : y;
+    m.ka = one;
+    m.kb = one;
+    m.pa = rev ? 0 : m.count;
+    m.pb = rev ? m.count : 0;
+    merge_load<false, NT>(t, m, lane);
+    return false;
+}
+
+// The high half of an item whose count exceeds 4096 by at most 64: its keys
+// are positions [4096 - sy, sx) of `hi` (V-shaped: reversed T2 falls, T1
+// rises), gathered into one register across the lanes and sorted by a
+// cross-lane bitonic merge (6 stages), then stored with their samples.
+template <bool NT>
+__device__ __forceinline__ void emit_small_hi(const Lines<false> &hi, uint32_t *lds, uint32_t *kdst, uint64_t gpos,
+                                              uint32_t first, uint32_t count, const SampleSet &smp, uint32_t lane)
+{
+    stage_tile(hi, lds, lane);
+    const uint32_t p = first + lane;
+    uint32_t v = lane < count ? lds[kLdsStride * (p / kLine) + p % kLine] : kMaxKey;
+#pragma unroll
+    for (int dist = kWave / 2; dist >= 1; dist /= 2) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, dist);
+        const uint32_t mn = v < o ? v : o, mx = v < o ? o : v;
+        v = (lane & dist) ? mx : mn;
+    }
+    if (lane < count) {
+        const uint64_t gp = gpos + lane;
+        st<NT>(kdst + gp, v);
+        if (smp.f != nullptr) {
+            if (gp % kLine == 0)
+                smp.f[gp / kLine] = v;
+            if (gp % kLine == kLine - 1)
+                smp.l[gp / kLine] = v;
+            if (smp.cf != nullptr && gp % kTile == 0)
+                smp.cf[gp / kTile] = v;
+            if (smp.cf != nullptr && gp % kTile == kTile - 1)
+                smp.cl[gp / kTile] = v;
+        }
+    }
+}
+
+// Load an item whose two sides hold at most 2048 keys each as one tile: AB
+// in positions [0, 2048) (A ascending at the front, B reversed at the back)
+// and CD in [2048, 4096) the same way; padding between.  Offsets are 32-bit
+// from the side's first run (a side spans two runs: less than 2^31 keys).
+template <bool NT>
+__device__ __forceinline__ void load_packed(Lines<false> &t, const uint32_t *K, uint64_t L, const uint4 &c0,
+                                            uint32_t pa, uint32_t pb, uint32_t pc, uint32_t pd, uint32_t lane)
+{
+    const uint32_t *ab = K, *cd = K + 2 * L;
+    const uint32_t bx = (uint32_t)L + c0.y + (kHalfTile - 1), by = (uint32_t)L + c0.w + (kHalfTile - 1);
+    const uint32_t safe_ab = pa ? c0.x : (uint32_t)L + c0.y, safe_cd = pc ? c0.z : (uint32_t)L + c0.w;
+    uint32_t key[kLine];
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t q = kWave * (r % (kLine / 2)) + lane;  // position in the half
+        const bool lower = r < kLine / 2;
+        const uint32_t n0 = lower ? pa : pc, n1 = lower ? pb : pd;
+        const uint32_t off = q < n0 ? (lower ? c0.x : c0.z) + q
+                                    : (q >= kHalfTile - n1 ? (lower ? bx : by) - q : (lower ? safe_ab : safe_cd));
+        key[r] = ld<NT>((lower ? ab : cd) + off);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t q = kWave * (r % (kLine / 2)) + lane;
+        const bool lower = r < kLine / 2;
+        const uint32_t n0 = lower ? pa : pc, n1 = lower ? pb : pd;
+        t.k[r] = (q < n0 || q >= kHalfTile - n1) ? key[r] : kMaxKey;
+    }
+}
+
+// BLOCKED -> STRIDED with positions [2048, 4096) reversed (position 2048 + q
+// takes position 4095 - q; the lower half is unchanged).
+__device__ __forceinline__ void to_strided_upper_reversed(Lines<false> &t, uint32_t *lds, uint32_t lane)
+{
+    lds_put<1>(lds + kLdsStride * lane, t.k);
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < kLine / 2; ++r)
+        t.k[r] = lds[kLdsStride * r + lane];
+#pragma unroll
+    for (int r = kLine / 2; r < kLine; ++r)
+        t.k[r] = lds[kLdsStride * (3 * kLine / 2 - 1 - r) + (kWave - 1) - lane];
+    wave_lds_fence();
+}
+
+// Both halves of a packed item merged at once (the network without its top
+// stage: position bits 10..0), the upper half then reversed, so that the
+// tile is AB ascending followed by CD descending: one bitonic sequence.
+__device__ __forceinline__ void packed_network(Lines<false> &t, uint32_t *lds, uint32_t lane)
+{
+    half_clean<kLine / 4, -1, false>(t);
+    to_blocked(t, lds, lane);
+    half_clean<kLine / 2, -1, false>(t);
+    to_strided_upper_reversed(t, lds, lane);
+}
+
 constexpr int kMerge4Waves = 4;
 
 // One wave per merge item: the item's A and B pieces merge into T1 (sorted,
 // padding after), its C and D pieces into T2.  T1 followed by T2 reversed is
 // a bitonic sequence of 8192 slots; its first half-cleaner stage is an
 // elementwise min / max of T1 and reversed T2, and each half is then merged
-// by the 4096-slot network.  The high half holds keys only when the item has
-// more than 4096.  An item with one side empty is that side's merge.
+// by the 4096-slot network (a high half of at most 64 keys by a cross-lane
+// merge).  A side with one piece is sorted as loaded; an item with one side
+// empty is that side's merge.
 template <bool NT>
 __global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4(Merge4Src src)
 {
@@ -1297,43 +1467,46 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4(Merge4Src src)
     const uint64_t L = src.run;
     const uint32_t *K = src.ksrc + G.start;
     const uint64_t gpos = G.start + c0.x + c0.y + c0.z + c0.w;
+    if (sx != 0 && sy != 0 && sx <= kHalfTile && sy <= kHalfTile) {
+        // both sides fit half a tile: two networks for the whole item
+        Lines<false> t;
+        load_packed<NT>(t, K, L, c0, pa, pb, pc, pd, lane);
+        packed_network(t, lds, lane);
+        merge4_network<false>(t, lds, lane);
+        emit4<NT>(t, lds, src.kdst, gpos, count, src.out_smp, lane);
+        return;
+    }
     Lines<false> t1, t2;
-    // all loads of both halves first (A and B pieces: A ascending at the front,
-    // B reversed at the back; the same for C and D)
-    if (sx) {
-        MergeTask<false> m;
-        m.ka = K + c0.x;
-        m.kb = K + L + c0.y;
-        m.pa = pa;
-        m.pb = pb;
-        m.count = sx;
-        merge_load<false, NT>(t1, m, lane);
-    } else {
+    // all loads of both sides first
+    bool net1 = false, net2 = false;
+    if (sx)
+        net1 = load_side<NT>(t1, K + c0.x, pa, K + L + c0.y, pb, false, lane);
+    else
         pad_tile(t1);
-    }
-    if (sy) {
-        MergeTask<false> m;
-        m.ka = K + 2 * L + c0.z;
-        m.kb = K + 3 * L + c0.w;
-        m.pa = pc;
-        m.pb = pd;
-        m.count = sy;
-        merge_load<false, NT>(t2, m, lane);
-    } else {
+    if (sy)
+        net2 = load_side<NT>(t2, K + 2 * L + c0.z, pc, K + 3 * L + c0.w, pd, sx != 0, lane);
+    else
         pad_tile(t2);
-    }
     if (sy == 0) {
-        merge4_network<false>(t1, lds, lane);
+        if (net1)
+            merge4_network<false>(t1, lds, lane);
+        else
+            stage_tile(t1, lds, lane);
         emit4<NT>(t1, lds, src.kdst, gpos, count, src.out_smp, lane);
         return;
     }
     if (sx == 0) {
-        merge4_network<false>(t2, lds, lane);
+        if (net2)
+            merge4_network<false>(t2, lds, lane);
+        else
+            stage_tile(t2, lds, lane);
         emit4<NT>(t2, lds, src.kdst, gpos, count, src.out_smp, lane);
         return;
     }
-    merge4_network<false>(t1, lds, lane);
-    merge4_network<true>(t2, lds, lane);
+    if (net1)
+        merge4_network<false>(t1, lds, lane);
+    if (net2)
+        merge4_network<true>(t2, lds, lane);
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
         const uint32_t a = t1.k[r], b = t2.k[r];
@@ -1343,8 +1516,13 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4(Merge4Src src)
     merge4_network<false>(t1, lds, lane);
     emit4<NT>(t1, lds, src.kdst, gpos, count < (uint32_t)kTile ? count : (uint32_t)kTile, src.out_smp, lane);
     if (count > (uint32_t)kTile) {
-        merge4_network<false>(t2, lds, lane);
-        emit4<NT>(t2, lds, src.kdst, gpos + kTile, count - kTile, src.out_smp, lane);
+        const uint32_t extra = count - kTile;
+        if (extra <= (uint32_t)kWave) {
+            emit_small_hi<NT>(t2, lds, src.kdst, gpos + kTile, kTile - sy, extra, src.out_smp, lane);
+        } else {
+            merge4_network<false>(t2, lds, lane);
+            emit4<NT>(t2, lds, src.kdst, gpos + kTile, extra, src.out_smp, lane);
+        }
     }
 }
 
@@ -1556,7 +1734,7 @@ uint64_t merge4_cut_bytes(uint64_t n, uint64_t run)
     if (run == 0 || run % kTile != 0)
         return 0;
     const uint64_t groups = (n + 4 * run - 1) / (4 * run);
-    return groups * (run / 1024 + 2) * sizeof(uint4);
+    return groups * (cuts_per_group(run) + 2) * sizeof(uint4);
 }
 
 uint64_t merge4_cut_bytes_max(uint64_t n)
@@ -1577,12 +1755,12 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
     if (n == 0 || run % kTile != 0 || in_smp.f == nullptr || in_smp.l == nullptr || cuts == nullptr)
         return hipErrorInvalidValue;
     const uint64_t groups = (n + 4 * run - 1) / (4 * run);
-    const uint64_t per_group = run / 1024;
+    const uint64_t per_group = cuts_per_group(run);
     Merge4Src src{ksrc, kdst, n, run, (uint32_t)groups, (uint32_t)per_group, static_cast<uint4 *>(cuts), in_smp,
                   out_smp};
     if (cut_phase) {
-        const uint64_t tasks = groups * per_group;
-        hipLaunchKernelGGL(k_cuts4, dim3((uint32_t)((tasks + 3) / 4)), dim3(256), 0, s, src);
+        const uint64_t tasks = groups * per_group;  // two per wave, four waves per block
+        hipLaunchKernelGGL(k_cuts4, dim3((uint32_t)((tasks + 7) / 8)), dim3(256), 0, s, src);
         return hipGetLastError();
     }
     const uint64_t items = groups * (per_group + 1);

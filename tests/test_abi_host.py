@@ -97,13 +97,15 @@ def test_pass_count_binary_fan_in(lib):
 
 
 def merge4_cut_bytes_max(n):
-    """Cut lists of the four-way passes: per group of four runs of L keys,
-    L / 1024 + 2 cuts of 16 bytes; the largest over both block-sort run lengths."""
+    """Cut lists of the four-way passes: per group of four runs of L keys, one
+    cut every 3840 keys of each side (the second side's first at 1920) plus
+    the two ends, 16 bytes each; the largest over both block-sort run lengths."""
     most = 0
     for run0 in (4096, 32768):
         run = run0
         while n > 2 * run:
-            most = max(most, -(-n // (4 * run)) * (run // 1024 + 2) * 16)
+            per = -(-2 * run // 3840) + -(-(2 * run - 1920) // 3840)
+            most = max(most, -(-n // (4 * run)) * (per + 2) * 16)
             run *= 4
     return most
 

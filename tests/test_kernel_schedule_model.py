@@ -549,12 +549,13 @@ def test_shear_sort_schedule_01_principle_sampled():
 # Model of the four-way merge pass: the merge of runs A, B, C, D (a group of
 # four consecutive runs of length L) is the binary merge of AB = merge(A, B)
 # and CD = merge(C, D).  The pass cuts the four-way merge path at every
-# multiple of 4096 of AB and at every multiple of 4096 plus CUT_OFFSET of CD;
-# each cut is found with binary co-ranks and single-run rank searches only,
-# and the span between consecutive cuts (one merge item) holds at most 4096
-# elements of AB and at most 4096 of CD.
+# multiple of CUT_STEP of AB and at every multiple of CUT_STEP plus
+# CUT_OFFSET of CD; each cut is found with binary co-ranks and single-run
+# rank searches only, and the span between consecutive cuts (one merge item)
+# holds at most CUT_STEP elements of AB and at most CUT_STEP of CD.
 
-CUT_OFFSET = 2048
+CUT_STEP = 3840
+CUT_OFFSET = 1920
 
 
 def bitonic_tile_network(tile):
@@ -602,6 +603,38 @@ def corank_blocks(arr, apos, na, nb, d, probes_per_round=64):
     return lo
 
 
+def packed_item_model(pieces):
+    """Both sides of at most 2048 keys: A ascending at the front of the lower
+    half, B reversed at its back, C and D the same in the upper half; one
+    network without the top stage merges both halves, a transpose reverses
+    the upper half, and the full network merges the bitonic result."""
+    a, b, c, d = pieces
+    assert len(a) + len(b) <= 2048 and len(c) + len(d) <= 2048
+    pad = np.iinfo(a.dtype).max
+    tile = np.full(T, pad, dtype=a.dtype)
+    tile[:len(a)] = a
+    if len(b):
+        tile[2048 - len(b):2048] = b[::-1]
+    tile[2048:2048 + len(c)] = c
+    if len(d):
+        tile[T - len(d):] = d[::-1]
+    lanes = np.arange(W)
+    regs = np.empty((W, E), dtype=tile.dtype)
+    for r in range(E):
+        regs[:, r] = tile[W * r + lanes]
+    apply(regs, half_clean(E // 4, -1))  # register bits 4..0 = position bits 10..6
+    regs = fast_to_blocked(regs)
+    apply(regs, half_clean(E // 2, -1))
+    regs = fast_to_strided(regs)
+    mid = np.empty_like(tile)
+    for r in range(E):
+        mid[W * r + lanes] = regs[:, r]
+    assert np.array_equal(mid[:2048], np.sort(tile[:2048]))
+    assert np.array_equal(mid[2048:], np.sort(tile[2048:]))
+    mid[2048:] = mid[2048:][::-1].copy()
+    return bitonic_tile_network(mid)
+
+
 def group_runs(n, L, g):
     base = 4 * L * g
     return base, [int(min(max(n - base - r * L, 0), L)) for r in range(4)]
@@ -615,27 +648,27 @@ def cuts4_model(arr, n, L, g):
     """Cut list of group g (start, every AB and CD cut in path order, end)."""
     base, (na, nb, nc, nd) = group_runs(n, L, g)
     A, B, C, D = (base + r * L for r in range(4))
-    nab_t, ncd_t = ceil_div(na + nb, 4096), ceil_div(max(nc + nd - CUT_OFFSET, 0), 4096)
+    nab_t, ncd_t = ceil_div(na + nb, CUT_STEP), ceil_div(max(nc + nd - CUT_OFFSET, 0), CUT_STEP)
     cuts = [None] * (nab_t + ncd_t + 2)
     cuts[0] = (0, 0, 0, 0)
     cuts[-1] = (na, nb, nc, nd)
     for j in range(nab_t):
-        x = 4096 * j
-        a = corank_sampled(arr, A, na, nb, x)
+        x = CUT_STEP * j
+        a = corank_blocks(arr, A, na, nb, x)
         b = x - a
         k = arr[A + a] if a < na and (b >= nb or arr[A + a] <= arr[B + b]) else arr[B + b]
         c, e = rank_sampled(arr, C, nc, k, False), rank_sampled(arr, D, nd, k, False)
         y = c + e
-        before = min(ceil_div(max(y - CUT_OFFSET, 0), 4096), ncd_t)
+        before = min(ceil_div(max(y - CUT_OFFSET, 0), CUT_STEP), ncd_t)
         assert cuts[1 + j + before] is None
         cuts[1 + j + before] = (a, b, c, e)
     for j in range(ncd_t):
-        y = 4096 * j + CUT_OFFSET
+        y = CUT_STEP * j + CUT_OFFSET
         c = corank_blocks(arr, C, nc, nd, y)
         e = y - c
         k = arr[C + c] if c < nc and (e >= nd or arr[C + c] <= arr[D + e]) else arr[D + e]
         a, b = rank_sampled(arr, A, na, k, True), rank_sampled(arr, B, nb, k, True)
-        before = min(ceil_div(a + b, 4096), nab_t)
+        before = min(ceil_div(a + b, CUT_STEP), nab_t)
         assert cuts[1 + j + before] is None
         cuts[1 + j + before] = (a, b, c, e)
     return cuts
@@ -649,7 +682,7 @@ def merge4_item_model(arr, n, L, g, c0, c1, out, smp):
     pa, pb, pc, pe = (c1[i] - c0[i] for i in range(4))
     assert min(pa, pb, pc, pe) >= 0
     sx, sy = pa + pb, pc + pe
-    assert sx <= 4096 and sy <= 4096
+    assert sx <= CUT_STEP and sy <= CUT_STEP
     pad = np.iinfo(arr.dtype).max
     t1 = np.full(T, pad, dtype=arr.dtype)
     t2 = np.full(T, pad, dtype=arr.dtype)
@@ -663,6 +696,10 @@ def merge4_item_model(arr, n, L, g, c0, c1, out, smp):
         halves = [t1]
     elif sx == 0:
         halves = [t2]
+    elif sx <= 2048 and sy <= 2048:
+        halves = [packed_item_model([arr[A + c0[0]:A + c1[0]], arr[B + c0[1]:B + c1[1]],
+                                     arr[C + c0[2]:C + c1[2]], arr[D + c0[3]:D + c1[3]]])]
+        smp["packed"] = smp.get("packed", 0) + 1
     else:
         r2 = t2[::-1]
         halves = [bitonic_tile_network(np.minimum(t1, r2))]
@@ -688,6 +725,7 @@ def merge4_pass_model(arr, n, L):
     out = np.full_like(arr, -1)
     smp = {k: np.full(ceil_div(n, s), -1, dtype=arr.dtype) for k, s in (("f", 64), ("l", 64), ("cf", 4096),
                                                                           ("cl", 4096))}
+    smp["packed"] = 0
     for g in range(ceil_div(n, 4 * L)):
         cuts = cuts4_model(arr, n, L, g)
         for i in range(len(cuts) - 1):
@@ -720,6 +758,8 @@ def _runs_input(n, L, dist, seed):
 def test_merge4_pass_plan(n, L, dist):
     arr = _runs_input(n, L, dist, seed=n + L)
     out, smp = merge4_pass_model(arr, n, L)
+    if dist == "random" and n >= 4 * L:
+        assert smp["packed"] > 0  # the packed path is exercised
     want = np.concatenate([np.sort(arr[s:min(s + 4 * L, n)], kind="stable") for s in range(0, n, 4 * L)])
     assert np.array_equal(out[:n], want)
     # every sample word the next pass reads was written, with the right key
@@ -729,17 +769,24 @@ def test_merge4_pass_plan(n, L, dist):
     assert np.array_equal(smp["cf"], res[::4096])
     assert np.array_equal(smp["l"][: n // 64], res[63::64])
     assert np.array_equal(smp["cl"][: n // 4096], res[4095::4096])
+    del smp["packed"]
 
 
 def test_merge4_items_balanced_on_random_keys():
-    """With CD cuts offset by half a tile, random runs give items of about
-    4096 outputs (no item near 8192 next to a near-empty one)."""
-    n, L = 4 * 16384, 16384
+    """With CD cuts offset by half a step, random runs give items of about
+    CUT_STEP outputs whose two sides mostly fit 2048 keys each (the packed
+    path: two networks per item).  The share falls for longer runs, whose
+    merge path strays further from the diagonal (about 0.55 at 2^21 keys)."""
+    n, L = 4 * 65536, 65536
     arr = _runs_input(n, L, "random", seed=5)
-    sizes = []
+    sizes, packed = [], 0
     cuts = cuts4_model(arr, n, L, 0)
     for i in range(len(cuts) - 1):
         sizes.append(sum(cuts[i + 1]) - sum(cuts[i]))
+        sx = cuts[i + 1][0] + cuts[i + 1][1] - cuts[i][0] - cuts[i][1]
+        sy = cuts[i + 1][2] + cuts[i + 1][3] - cuts[i][2] - cuts[i][3]
+        packed += 0 < sx <= 2048 and 0 < sy <= 2048
     assert sum(sizes) == n
-    assert max(sizes) <= 8192
+    assert max(sizes) <= 2 * CUT_STEP
     assert np.median(sizes) > 3000
+    assert packed >= 0.6 * len(sizes)
