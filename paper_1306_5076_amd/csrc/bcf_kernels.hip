@@ -1428,7 +1428,7 @@ __device__ __forceinline__ void packed_network(Lines<false> &t, uint32_t *lds, u
     to_strided_upper_reversed(t, lds, lane);
 }
 
-constexpr int kMerge4Waves = 4;
+constexpr int kMerge4Waves = 2;
 
 // One wave per merge item: the item's A and B pieces merge into T1 (sorted,
 // padding after), its C and D pieces into T2.  T1 followed by T2 reversed is
