@@ -141,14 +141,15 @@ uint32_t bcf_run_keys(int pairs);
 
 /* Passes over the data in HBM of a sort of n keys under the current tuning:
  * the block sort plus the merge passes (the paper's Lemma 2: O(1 + log(N/M))
- * scans).  With merge_fan_in 2 (and for pairs) every merge pass is binary:
- * ceil(log2(R)) passes for R = ceil(n / bcf_run_keys(pairs)) runs.  With
- * fan-in 4 (keys-only sorts) a pass merges groups of four runs while more than
- * two remain, two levels of the paper's binary merging (Sec. 3.2) per read
- * and write of the data, and a last binary pass merges the final two runs if
- * needed: 2^11 runs take 6 passes instead of 11.  Each merge pass finds its
- * work split by reading O(log n) key samples and keys, in a small launch
- * before it or (see bcf_tuning.fused_partition) in the merge kernel. */
+ * scans).  With binary passes (pairs always; keys under fan-in 2, or below
+ * 2^25 keys under the default) there are ceil(log2(R)) merge passes for
+ * R = ceil(n / bcf_run_keys(pairs)) runs.  With fan-in 4 (keys-only sorts) a
+ * pass merges groups of four runs while more than two remain, two levels of
+ * the paper's binary merging (Sec. 3.2) per read and write of the data, and a
+ * last binary pass merges the final two runs if needed: 2^11 runs take 6
+ * passes instead of 11.  Each merge pass finds its work split by reading
+ * O(log n) key samples and keys, in a small launch before it or (see
+ * bcf_tuning.fused_partition) in the merge kernel. */
 uint32_t bcf_sort_passes(uint64_t n, int pairs);
 
 /*
@@ -183,15 +184,16 @@ typedef struct {
                                   run by the one-tile-per-wave kernel finds each tile's split
                                   itself from the samples (one launch per pass); 0: a separate
                                   partition launch first */
-    int32_t merge_fan_in;      /* runs merged per group by a merge pass of bcf_sort_u32: 4
-                                  (default; needs sampled_partition, else 2 is used) or 2.
-                                  Key/value sorts, bcf_merge_runs and segmented sorts always
-                                  merge pairs of runs */
+    int32_t merge_fan_in;      /* runs merged per group by a merge pass of bcf_sort_u32: 0
+                                  (default) 4 for sorts of at least 2^25 keys, else 2; 4 or 2
+                                  for every size.  Four-way passes need sampled_partition
+                                  (else 2 is used).  Key/value sorts, bcf_merge_runs and
+                                  segmented sorts always merge pairs of runs */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);
 /* BCF_ERR_INVALID for a NULL pointer, an out-of-range merge_variant or block_sort, or a
- * merge_fan_in other than 2 or 4. */
+ * merge_fan_in other than 0, 2 or 4. */
 bcf_status bcf_set_tuning(const bcf_tuning *in);
 
 /*

@@ -33,7 +33,7 @@ from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bcf_sort", "autotune.json")
 
-SORT_SPACE = {"merge_fan_in": [4, 2], "merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0], "fused_partition": [1, 0]}
+SORT_SPACE = {"merge_fan_in": [0, 4, 2], "merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0], "fused_partition": [1, 0]}
 SEGMENTED_SPACE = {"merge_variant": [3, 1, 2], "nontemporal": [1, 0],
                    "group_min_keys": [4097, 16384, 65536, 1 << 40]}
 

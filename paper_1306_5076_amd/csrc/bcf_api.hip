@@ -167,7 +167,9 @@ Tuning &tuning_locked()
         g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
         if (g_tune.block_sort < 0 || g_tune.block_sort > 3)
             g_tune.block_sort = 0;
-        g_tune.merge_fan_in = env_int("BCF_FAN_IN", 4) == 2 ? 2 : 4;
+        g_tune.merge_fan_in = env_int("BCF_FAN_IN", 0);
+        if (g_tune.merge_fan_in != 2 && g_tune.merge_fan_in != 4)
+            g_tune.merge_fan_in = 0;
         g_tune_init = true;
     }
     return g_tune;
@@ -212,6 +214,13 @@ uint64_t sort_run_keys(bool pairs, uint64_t n, const Tuning &tu)
     return sort_uses_groups(n, tu) ? group_run_keys(pairs) : (uint64_t)kTile;
 }
 
+// Sorts of at least this many keys take four-way merge passes under the
+// default (auto) fan-in.  Below it a pass's data mostly stays in the 256 MiB
+// last-level cache, binary passes stream from there, and halving their
+// number does not pay for the four-way pass's second launch and heavier
+// merge (measured: binary passes faster or equal up to 2^24 uniform keys).
+constexpr uint64_t kAutoFourWayMinN = 1ull << 25;
+
 // Fan-in of every merge pass of an n-key regular sort, first pass first:
 // four-way passes while more than two runs remain (keys only; their work
 // split is searched from key samples), then at most one binary pass.
@@ -221,7 +230,8 @@ std::vector<uint32_t> sort_fan_ins(bool pairs, uint64_t n, const Tuning &tu)
     if (n == 0)
         return fi;
     const uint64_t run0 = sort_run_keys(pairs, n, tu);
-    const bool four = !pairs && tu.merge_fan_in == 4 && tu.sampled_partition;
+    const bool want4 = tu.merge_fan_in == 4 || (tu.merge_fan_in == 0 && n >= kAutoFourWayMinN);
+    const bool four = !pairs && want4 && tu.sampled_partition;
     for (uint64_t runs = (n + run0 - 1) / run0; runs > 1;) {
         const uint32_t k = (four && runs > 2) ? 4 : 2;
         fi.push_back(k);
@@ -764,7 +774,7 @@ void bcf_get_tuning(bcf_tuning *out)
 bcf_status bcf_set_tuning(const bcf_tuning *in)
 {
     if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 3 ||
-        (in->merge_fan_in != 2 && in->merge_fan_in != 4))
+        (in->merge_fan_in != 0 && in->merge_fan_in != 2 && in->merge_fan_in != 4))
         return BCF_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_tune_mu);
     Tuning &t = tuning_locked();

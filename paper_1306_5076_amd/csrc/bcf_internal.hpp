@@ -109,7 +109,7 @@ struct Tuning {
     bool tile_samples;
     uint64_t group_min_keys;
     bool check_runs;
-    int merge_fan_in;  // 2 or 4: runs merged per group in the merge passes of a keys-only sort
+    int merge_fan_in;  // 0 auto, 2 or 4: runs merged per group in the merge passes of a keys-only sort
 };
 Tuning tuning();
 

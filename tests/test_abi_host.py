@@ -55,12 +55,14 @@ def test_tile_run_and_pass_count(lib):
         assert lib.bcf_sort_passes(4096, pairs) == 1
         assert lib.bcf_sort_passes(4097, pairs) == 2
         # Lemma 2: 1 + O(log(n / M)) passes over the data, M the block-sort run:
-        # binary passes for pairs; for keys four-way passes while more than two
-        # runs remain, then at most one binary pass
-        for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**26, 2**28, 3 * R + 5 + small, 2**32 - 1]:
+        # binary passes for pairs and (default) for keys below 2^25; from 2^25
+        # keys four-way passes while more than two runs remain, then at most
+        # one binary pass
+        for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**25 - 1, 2**25, 2**26, 2**28, 3 * R + 5 + small,
+                  2**32 - 1]:
             m = 4096 if n <= small else R
             runs = -(-n // m)
-            if pairs:
+            if pairs or n < 2**25:
                 want = int(np.ceil(np.log2(runs)))
             else:
                 want = 0
@@ -69,7 +71,7 @@ def test_tile_run_and_pass_count(lib):
                     want += 1
             assert lib.bcf_sort_passes(n, pairs) == 1 + want, (n, pairs)
     assert lib.bcf_sort_passes(2**26, 0) == 1 + 6  # 2^11 runs: five four-way passes and one binary
-    assert lib.bcf_sort_passes(3 * 4096, 0) == 2  # three runs: one four-way pass
+    assert lib.bcf_sort_passes(3 * 4096, 0) == 3  # three runs, default below 2^25 keys: two binary passes
 
 
 def test_pass_count_binary_fan_in(lib):
@@ -85,11 +87,12 @@ def test_pass_count_binary_fan_in(lib):
             m = 4096 if n <= 1 << 19 else 32768
             assert lib.bcf_sort_passes(n, 0) == 1 + int(np.ceil(np.log2(-(-n // m))))
         # the temp size does not depend on the fan-in
-        assert q_sort(lib, 2**26) == q_sort(lib, 2**26)
         need2 = q_sort(lib, 2**26)[1]
-        t.merge_fan_in = 4
+        t.merge_fan_in = 4  # four-way passes at every size
         assert lib.bcf_set_tuning(ctypes.byref(t)) == 0
         assert q_sort(lib, 2**26)[1] == need2
+        assert lib.bcf_sort_passes(3 * 4096, 0) == 2  # three runs: one four-way pass
+        assert lib.bcf_sort_passes(2**16, 0) == 1 + 2  # 16 runs of 4096: two four-way passes
         t.merge_fan_in = 3
         assert lib.bcf_set_tuning(ctypes.byref(t)) == 1
     finally:
@@ -177,7 +180,7 @@ def test_tuning_roundtrip():
     assert set(before) == {"merge_variant", "nontemporal", "sampled_partition", "tile_samples",
                            "group_min_keys", "check_runs", "block_sort", "fused_partition", "merge_fan_in"}
     assert before["block_sort"] == 0 and before["merge_variant"] == 3 and before["fused_partition"] == 1
-    assert before["merge_fan_in"] == 4
+    assert before["merge_fan_in"] == 0
     with bcf.tuning(fused_partition=0):
         assert bcf.get_tuning()["fused_partition"] == 0
     with bcf.tuning(merge_variant=2, group_min_keys=12345, check_runs=1, block_sort=2, merge_fan_in=2):
@@ -193,10 +196,11 @@ def test_tuning_roundtrip():
     assert bcf.run_keys() == 32768 and bcf.sort_passes(1 << 26) == 1 + 6
     with bcf.tuning(merge_fan_in=2):
         assert bcf.sort_passes(1 << 26) == 1 + 11
-        # default block sort: wave tiles up to 2^19 keys, group tiles above
-        assert bcf.sort_passes(1 << 19) == 1 + 7 and bcf.sort_passes((1 << 19) + 1) == 1 + 5
-    # the same with four-way passes: 128 runs -> 32 -> 8 -> 2 -> 1; 17 runs -> 5 -> 2 -> 1
-    assert bcf.sort_passes(1 << 19) == 1 + 4 and bcf.sort_passes((1 << 19) + 1) == 1 + 3
+    # default block sort: wave tiles up to 2^19 keys, group tiles above; binary
+    # passes below 2^25 keys
+    assert bcf.sort_passes(1 << 19) == 1 + 7 and bcf.sort_passes((1 << 19) + 1) == 1 + 5
+    with bcf.tuning(merge_fan_in=4):  # 128 runs -> 32 -> 8 -> 2 -> 1; 17 runs -> 5 -> 2 -> 1
+        assert bcf.sort_passes(1 << 19) == 1 + 4 and bcf.sort_passes((1 << 19) + 1) == 1 + 3
     with bcf.tuning(block_sort=3):
         assert bcf.sort_passes(1 << 16) == 1 + 1 and bcf.sort_passes(1 << 15) == 1
     from paper_1306_5076_amd import BcfError

@@ -371,12 +371,13 @@ def test_profile_records_four_way_passes(torch_dev, bcf):
     torch, dev = torch_dev
     n = 1 << 20
     keys = to_dev(torch, dev, workloads.keys_u32("uniform", n))
-    bcf.profile_collect()
-    bcf.profile_enable(True)
-    bcf.sort_u32(keys)
-    bcf.profile_enable(False)
-    st = bcf.profile_collect()
-    assert bcf.sort_passes(n) == 4
+    with bcf.tuning(merge_fan_in=4):
+        bcf.profile_collect()
+        bcf.profile_enable(True)
+        bcf.sort_u32(keys)
+        bcf.profile_enable(False)
+        st = bcf.profile_collect()
+        assert bcf.sort_passes(n) == 4
     assert st["block_sort_keys"]["launches"] == 1
     assert st["cuts4_keys"]["launches"] == 2 and st["merge4_keys"]["launches"] == 2
     assert st["merge_keys"]["launches"] == 1
