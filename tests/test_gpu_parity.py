@@ -404,6 +404,28 @@ def test_four_way_merge_passes(torch_dev, bcf, n, block_sort):
             assert first_diff(got, oracle.sort_u32(keys)) is None, (n, block_sort, dist)
 
 
+@pytest.mark.parametrize("knobs", [{"tile_samples": 0}, {"sampled_partition": 0}, {"merge_variant": 1},
+                                   {"merge_variant": 0}, {"fused_partition": 0}, {"block_sort": 2}])
+def test_four_way_with_other_knobs(torch_dev, bcf, knobs):
+    """Fan-in 4 forced together with other knobs: without tile samples the cut
+    searches start from block samples; without samples the passes are binary;
+    the last (binary) pass under every merge kernel; ShearSort runs of 4096."""
+    torch, dev = torch_dev
+    n = 5 * (1 << 18) + 4097  # 41 runs of 32768: four-way 41 -> 11 -> 3 -> 1
+    with bcf.tuning(merge_fan_in=4, **knobs):
+        passes = bcf.sort_passes(n)
+        for dist in ("uniform", "distinct16"):
+            keys = workloads.keys_u32(dist, n, seed=17)
+            got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()
+            assert first_diff(got, oracle.sort_u32(keys)) is None, (knobs, dist)
+    if knobs.get("sampled_partition") == 0:
+        assert passes == 1 + 6  # binary: 41 runs -> 6 passes
+    elif knobs.get("block_sort") == 2:
+        assert passes == 1 + 5  # 322 runs of 4096 -> 81 -> 21 -> 6 -> 2 -> 1
+    else:
+        assert passes == 1 + 3
+
+
 @pytest.mark.parametrize("nt", [0, 1])
 def test_four_way_same_as_binary(torch_dev, bcf, nt):
     """Four-way and binary merge passes give the same bytes (keys, all equal
