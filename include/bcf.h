@@ -9,7 +9,8 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  - Keys are uint32_t compared as unsigned integers; order is ascending.
+ *  - Keys are uint32_t compared as unsigned integers; order is ascending
+ *    (int32 and float keys: bcf_sort_i32 / bcf_sort_f32 and their pair forms).
  *  - Key/value arrays are device pointers (HBM) owned by the caller.  Offset
  *    arrays (run_offsets, seg_offsets) are HOST pointers: the library plans the
  *    launches on the host from them.
@@ -69,6 +70,30 @@ bcf_status bcf_sort_u32(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n,
  *   keys_out, vals_out  device, n u32 each (may equal the inputs)
  */
 bcf_status bcf_sort_pairs_u32(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                              uint32_t *vals_out, uint64_t n, void *temp, uint64_t *temp_bytes,
+                              void *stream);
+
+/*
+ * Sorts of other 32-bit key types (an extension: the paper's keys are
+ * unsigned 32-bit integers).  int32 keys ascend as signed integers; float
+ * keys ascend in IEEE 754 totalOrder: -NaN < -inf < negative values < -0.0 <
+ * +0.0 < positive values < +inf < +NaN (NaNs ordered by payload, negative ones
+ * reversed), i.e. the order of the values with -0.0 before +0.0 and NaNs at
+ * the ends by sign.  Keys are mapped to u32 by an order-preserving bit map
+ * into keys_out, sorted there in place by bcf_sort_u32's path, and mapped
+ * back: two more streaming passes over keys_out.  Same arguments, temp size
+ * (bcf_sort_u32's / bcf_sort_pairs_u32's) and conventions as the u32 calls;
+ * the pair variants are stable (equal keys keep their input order; for
+ * floats, equal means the same bit pattern).
+ */
+bcf_status bcf_sort_i32(const int32_t *keys_in, int32_t *keys_out, uint64_t n, void *temp,
+                        uint64_t *temp_bytes, void *stream);
+bcf_status bcf_sort_f32(const float *keys_in, float *keys_out, uint64_t n, void *temp,
+                        uint64_t *temp_bytes, void *stream);
+bcf_status bcf_sort_pairs_i32(const int32_t *keys_in, const uint32_t *vals_in, int32_t *keys_out,
+                              uint32_t *vals_out, uint64_t n, void *temp, uint64_t *temp_bytes,
+                              void *stream);
+bcf_status bcf_sort_pairs_f32(const float *keys_in, const uint32_t *vals_in, float *keys_out,
                               uint32_t *vals_out, uint64_t n, void *temp, uint64_t *temp_bytes,
                               void *stream);
 

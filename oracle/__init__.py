@@ -43,6 +43,8 @@ def _load():
     lib.oracle_multiset_hash.restype = None
     lib.oracle_is_sorted_u32.argtypes = [u32p, ctypes.c_uint64]
     lib.oracle_is_sorted_u32.restype = ctypes.c_int
+    lib.oracle_sort_typed.argtypes = [ctypes.c_int, u32p, u32p, u32p, u32p, ctypes.c_uint64]
+    lib.oracle_sort_typed.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -116,3 +118,23 @@ def multiset_hash(keys, vals=None):
 def is_sorted_u32(keys) -> bool:
     k = _u32(keys)
     return bool(_load().oracle_is_sorted_u32(_p32(k), k.size))
+
+
+def _sort_typed(kind, dtype, keys, vals):
+    k = np.ascontiguousarray(np.asarray(keys, dtype=dtype)).view(np.uint32)
+    v = _u32(vals) if vals is not None else None
+    ko = np.empty_like(k)
+    vo = np.empty_like(v) if v is not None else None
+    if k.size and _load().oracle_sort_typed(kind, _p32(k), _p32(v), _p32(ko), _p32(vo), k.size) != 0:
+        raise MemoryError("oracle_sort_typed")
+    return (ko.view(dtype), vo) if v is not None else ko.view(dtype)
+
+
+def sort_i32(keys, vals=None):
+    """Ascending sort of int32 keys (signed order), stable with values."""
+    return _sort_typed(1, np.int32, keys, vals)
+
+
+def sort_f32(keys, vals=None):
+    """Ascending sort of float32 keys in IEEE 754 totalOrder, stable with values."""
+    return _sort_typed(2, np.float32, keys, vals)

@@ -15,7 +15,9 @@
  *   - oracle_merge_runs       the stable sort of the concatenation of k sorted
  *                             runs, i.e. a k-way merge where ties go to the
  *                             lower run index and then the earlier position;
- *   - oracle_segmented_sort   oracle_sort_u32 applied to every segment.
+ *   - oracle_segmented_sort   oracle_sort_u32 applied to every segment;
+ *   - oracle_sort_typed       int32 keys (signed order) or float keys (IEEE 754
+ *                             totalOrder), stable, values optional.
  * Keys compare as unsigned 32-bit integers (the paper does not fix signedness).
  *
  * Algorithm: top-down merge sort (split in halves, sort each, merge taking the
@@ -134,6 +136,81 @@ int oracle_sort_pairs_u32(const uint32_t *kin, const uint32_t *vin, uint32_t *ko
     if (vout != vin)
         memcpy(vout, vin, n * sizeof(uint32_t));
     msort_pairs(kout, vout, tk, tv, 0, n);
+    free(tk);
+    free(tv);
+    return 0;
+}
+
+/* ---- other key types ------------------------------------------------------ */
+
+/*
+ * Stable sort of 32-bit keys under a key type's order, values (when not NULL)
+ * carried: kind 1 = int32 (signed order), kind 2 = IEEE 754 binary32 in
+ * totalOrder (IEEE 754-2008, 5.10): values of different sign order by sign
+ * (negative first); for two positive encodings the smaller magnitude field
+ * (exponent and significand, which already orders +0 < subnormals < normals
+ * < +inf < NaNs by payload) comes first, for two negative ones the larger.
+ * The same top-down merge sort, with the comparison as a function.
+ */
+static int le_i32(uint32_t a, uint32_t b) { return (int32_t)a <= (int32_t)b; }
+
+static int le_f32_total(uint32_t a, uint32_t b)
+{
+    const uint32_t sa = a >> 31, sb = b >> 31;
+    if (sa != sb)
+        return sa > sb; /* a negative, b positive */
+    const uint32_t ma = a & 0x7fffffffu, mb = b & 0x7fffffffu;
+    return sa ? ma >= mb : ma <= mb;
+}
+
+static void merge_typed(int (*le)(uint32_t, uint32_t), const uint32_t *sk, const uint32_t *sv, uint32_t *dk,
+                        uint32_t *dv, size_t lo, size_t mid, size_t hi)
+{
+    size_t i = lo, j = mid, o = lo;
+    while (i < mid || j < hi) {
+        int take_left = j >= hi || (i < mid && le(sk[i], sk[j]));
+        size_t s = take_left ? i++ : j++;
+        dk[o] = sk[s];
+        if (sv)
+            dv[o] = sv[s];
+        o++;
+    }
+}
+
+static void msort_typed(int (*le)(uint32_t, uint32_t), uint32_t *k, uint32_t *v, uint32_t *tk, uint32_t *tv,
+                        size_t lo, size_t hi)
+{
+    if (hi - lo < 2)
+        return;
+    size_t mid = lo + (hi - lo) / 2;
+    msort_typed(le, k, v, tk, tv, lo, mid);
+    msort_typed(le, k, v, tk, tv, mid, hi);
+    merge_typed(le, k, v, tk, tv, lo, mid, hi);
+    memcpy(k + lo, tk + lo, (hi - lo) * sizeof(uint32_t));
+    if (v)
+        memcpy(v + lo, tv + lo, (hi - lo) * sizeof(uint32_t));
+}
+
+int oracle_sort_typed(int kind, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                      uint64_t n)
+{
+    int (*le)(uint32_t, uint32_t) = kind == 1 ? le_i32 : kind == 2 ? le_f32_total : 0;
+    if (!le)
+        return -2;
+    if (n == 0)
+        return 0;
+    uint32_t *tk = (uint32_t *)malloc(n * sizeof(uint32_t));
+    uint32_t *tv = vin ? (uint32_t *)malloc(n * sizeof(uint32_t)) : 0;
+    if (!tk || (vin && !tv)) {
+        free(tk);
+        free(tv);
+        return -1;
+    }
+    if (kout != kin)
+        memcpy(kout, kin, n * sizeof(uint32_t));
+    if (vin && vout != vin)
+        memcpy(vout, vin, n * sizeof(uint32_t));
+    msort_typed(le, kout, vin ? vout : 0, tk, tv, 0, n);
     free(tk);
     free(tv);
     return 0;

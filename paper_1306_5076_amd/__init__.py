@@ -12,6 +12,10 @@ _API = (
     "Workspace",
     "sort_u32",
     "sort_pairs_u32",
+    "sort_i32",
+    "sort_f32",
+    "sort_pairs_i32",
+    "sort_pairs_f32",
     "merge_runs",
     "segmented_sort",
     "SegmentedPlan",

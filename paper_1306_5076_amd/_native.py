@@ -27,6 +27,10 @@ STATUS_NAMES = {
 EXPORTED = (
     "bcf_sort_u32",
     "bcf_sort_pairs_u32",
+    "bcf_sort_i32",
+    "bcf_sort_f32",
+    "bcf_sort_pairs_i32",
+    "bcf_sort_pairs_f32",
     "bcf_merge_runs",
     "bcf_segmented_sort",
     "bcf_segmented_sort_pairs",
@@ -95,6 +99,12 @@ def load(path: str = LIB_PATH):
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.bcf_sort_u32.argtypes = [vp, vp, u64, vp, u64p, vp]
     lib.bcf_sort_pairs_u32.argtypes = [vp, vp, vp, vp, u64, vp, u64p, vp]
+    for f in ("bcf_sort_i32", "bcf_sort_f32"):
+        getattr(lib, f).argtypes = [vp, vp, u64, vp, u64p, vp]
+        getattr(lib, f).restype = ctypes.c_int
+    for f in ("bcf_sort_pairs_i32", "bcf_sort_pairs_f32"):
+        getattr(lib, f).argtypes = [vp, vp, vp, vp, u64, vp, u64p, vp]
+        getattr(lib, f).restype = ctypes.c_int
     lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
     lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]

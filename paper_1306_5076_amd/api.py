@@ -21,6 +21,10 @@ __all__ = [
     "Workspace",
     "sort_u32",
     "sort_pairs_u32",
+    "sort_i32",
+    "sort_f32",
+    "sort_pairs_i32",
+    "sort_pairs_f32",
     "merge_runs",
     "segmented_sort",
     "SegmentedPlan",
@@ -160,6 +164,64 @@ def sort_pairs_u32(keys, vals, keys_out=None, vals_out=None, stream=None, worksp
             ),
         )
     return keys_out, vals_out
+
+
+def _sort_typed(kind, keys, vals, keys_out, vals_out, stream, workspace):
+    """int32 (kind "i32") or float32 ("f32") keys, optionally with u32 values."""
+    lib = load()
+    dtype = torch.int32 if kind == "i32" else torch.float32
+    for name, t in (("keys", keys), ("keys_out", keys_out)):
+        if t is not None and (not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda
+                              or not t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    n = keys.numel()
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if keys_out.numel() != n or keys_out.device != keys.device:
+        raise ValueError("keys_out must match keys")
+    pairs = vals is not None
+    if pairs:
+        _check_tensor(vals, "vals", keys.device)
+        if vals.numel() != n:
+            raise ValueError("keys and vals must have the same length")
+        vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+        _check_tensor(vals_out, "vals_out", keys.device)
+    fname = f"bcf_sort_{'pairs_' if pairs else ''}{kind}"
+    fn = getattr(lib, fname)
+    stream, sh = _stream(stream, keys.device)
+    need = ctypes.c_uint64(0)
+    if pairs:
+        check(fname, fn(None, None, None, None, n, None, ctypes.byref(need), None))
+    else:
+        check(fname, fn(None, None, n, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        tp = _ptr(temp) or ctypes.c_void_p(1)
+        if pairs:
+            check(fname, fn(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), n, tp, ctypes.byref(tb), sh))
+        else:
+            check(fname, fn(_ptr(keys), _ptr(keys_out), n, tp, ctypes.byref(tb), sh))
+    return (keys_out, vals_out) if pairs else keys_out
+
+
+def sort_i32(keys, out=None, stream=None, workspace=None):
+    """Ascending sort of int32 keys (signed order); returns ``out``."""
+    return _sort_typed("i32", keys, None, out, None, stream, workspace)
+
+
+def sort_f32(keys, out=None, stream=None, workspace=None):
+    """Ascending sort of float32 keys in IEEE 754 totalOrder (-0.0 before +0.0,
+    NaNs at the ends by sign); returns ``out``."""
+    return _sort_typed("f32", keys, None, out, None, stream, workspace)
+
+
+def sort_pairs_i32(keys, vals, keys_out=None, vals_out=None, stream=None, workspace=None):
+    """Stable sort of (int32 key, u32 value) pairs by key."""
+    return _sort_typed("i32", keys, vals, keys_out, vals_out, stream, workspace)
+
+
+def sort_pairs_f32(keys, vals, keys_out=None, vals_out=None, stream=None, workspace=None):
+    """Stable sort of (float32 key, u32 value) pairs by key (totalOrder)."""
+    return _sort_typed("f32", keys, vals, keys_out, vals_out, stream, workspace)
 
 
 def merge_runs(keys, run_offsets, vals=None, keys_out=None, vals_out=None, stream=None, workspace=None):

@@ -331,6 +331,37 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     return BCF_OK;
 }
 
+// ---------------------------------------------------- other key types
+
+// Sort of int32 (kind 1) or float (kind 2) keys: the keys are mapped in order
+// into the output, sorted there in place as u32, and mapped back.  The temp
+// size is that of the u32 sort; everything is checked before the first launch.
+bcf_status sort_typed(int kind, bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                      uint32_t *vout, uint64_t n, void *temp, uint64_t *temp_bytes, hipStream_t s)
+{
+    if (!temp_bytes || n > kMaxN)
+        return BCF_ERR_INVALID;
+    uint64_t need = 0;
+    BCF_TRY(sort_impl(pairs, nullptr, nullptr, nullptr, nullptr, n, nullptr, &need, s));
+    if (!temp) {
+        *temp_bytes = need;
+        return BCF_OK;
+    }
+    if (n == 0)
+        return BCF_OK;
+    if (!kin || !kout || (pairs && (!vin || !vout)))
+        return BCF_ERR_INVALID;
+    if (*temp_bytes < need)
+        return BCF_ERR_TEMP_TOO_SMALL;
+    {
+        ProfScope p("map_keys", s, 8.0 * n);
+        BCF_TRY(dev_status(launch_map_keys(kin, kout, n, kind, false, s)));
+    }
+    BCF_TRY(sort_impl(pairs, kout, vin, kout, vout, n, temp, temp_bytes, s));
+    ProfScope p("map_keys", s, 8.0 * n);
+    return dev_status(launch_map_keys(kout, kout, n, kind, true, s));
+}
+
 // ---------------------------------------------------- table-driven plans
 
 struct MergePass {
@@ -615,6 +646,38 @@ bcf_status bcf_sort_pairs_u32(const uint32_t *keys_in, const uint32_t *vals_in, 
 {
     return sort_impl(true, keys_in, vals_in, keys_out, vals_out, n, temp, temp_bytes,
                      static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_sort_i32(const int32_t *keys_in, int32_t *keys_out, uint64_t n, void *temp, uint64_t *temp_bytes,
+                        void *stream)
+{
+    return sort_typed(1, false, reinterpret_cast<const uint32_t *>(keys_in), nullptr,
+                      reinterpret_cast<uint32_t *>(keys_out), nullptr, n, temp, temp_bytes,
+                      static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_sort_f32(const float *keys_in, float *keys_out, uint64_t n, void *temp, uint64_t *temp_bytes,
+                        void *stream)
+{
+    return sort_typed(2, false, reinterpret_cast<const uint32_t *>(keys_in), nullptr,
+                      reinterpret_cast<uint32_t *>(keys_out), nullptr, n, temp, temp_bytes,
+                      static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_sort_pairs_i32(const int32_t *keys_in, const uint32_t *vals_in, int32_t *keys_out, uint32_t *vals_out,
+                              uint64_t n, void *temp, uint64_t *temp_bytes, void *stream)
+{
+    return sort_typed(1, true, reinterpret_cast<const uint32_t *>(keys_in), vals_in,
+                      reinterpret_cast<uint32_t *>(keys_out), vals_out, n, temp, temp_bytes,
+                      static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_sort_pairs_f32(const float *keys_in, const uint32_t *vals_in, float *keys_out, uint32_t *vals_out,
+                              uint64_t n, void *temp, uint64_t *temp_bytes, void *stream)
+{
+    return sort_typed(2, true, reinterpret_cast<const uint32_t *>(keys_in), vals_in,
+                      reinterpret_cast<uint32_t *>(keys_out), vals_out, n, temp, temp_bytes,
+                      static_cast<hipStream_t>(stream));
 }
 
 bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,

@@ -87,6 +87,9 @@ uint64_t merge4_cut_bytes(uint64_t n, uint64_t run);
 uint64_t merge4_cut_bytes_max(uint64_t n);  // the largest over every plan of an n-key sort
 hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t n, uint64_t run, void *cuts,
                                  SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s);
+// Order-preserving key map to u32 (inverse = false) or back (true), in place
+// allowed: kind 1 = int32, 2 = IEEE binary32 (totalOrder).
+hipError_t launch_map_keys(const uint32_t *in, uint32_t *out, uint64_t n, int kind, bool inverse, hipStream_t s);
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
                                    uint32_t ntiles, hipStream_t s);
 // Group tiles (count <= group_run_keys(pairs)) sorted by a multi-wave work-group.

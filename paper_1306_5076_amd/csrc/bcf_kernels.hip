@@ -1526,6 +1526,24 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4(Merge4Src src)
     }
 }
 
+// Order-preserving maps between other 32-bit key types and u32: signed
+// integers flip the sign bit; IEEE binary32 floats flip the sign bit of a
+// non-negative value and every bit of a negative one, which orders the bit
+// patterns by IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf
+// < +NaN).  With (sign, rest) = (0x80000000, 0) for i32 and (0x80000000,
+// 0x7fffffff) for f32 the map is x ^ (sign | (x >> 31 arithmetic) & rest) and
+// its inverse t ^ (sign | (~t >> 31 arithmetic) & rest).
+__global__ __launch_bounds__(256) void k_map_keys(const uint32_t *__restrict__ in, uint32_t *out, uint64_t n,
+                                                  uint32_t sign, uint32_t rest, uint32_t inverse)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = in[i];
+        const uint32_t s = (uint32_t)((int32_t)(inverse ? ~x : x) >> 31);
+        out[i] = x ^ (sign | (s & rest));
+    }
+}
+
 // Sortedness check of the runs of a merge input: sets *flag when some
 // keys[i] > keys[i+1] with i+1 not the start of a run.
 __global__ void k_check_runs(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ offs, uint32_t k,
@@ -1770,6 +1788,19 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
         hipLaunchKernelGGL(k_merge4<true>, grid, block, 0, s, src);
     else
         hipLaunchKernelGGL(k_merge4<false>, grid, block, 0, s, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_keys(const uint32_t *in, uint32_t *out, uint64_t n, int kind, bool inverse, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    if (kind != 1 && kind != 2)
+        return hipErrorInvalidValue;
+    const uint32_t rest = kind == 2 ? 0x7fffffffu : 0u;
+    const uint64_t want = (n + 255) / 256;
+    const uint32_t grid = (uint32_t)(want < 8 * 1024 ? want : 8 * 1024);
+    hipLaunchKernelGGL(k_map_keys, dim3(grid), dim3(256), 0, s, in, out, n, 0x80000000u, rest, inverse ? 1u : 0u);
     return hipGetLastError();
 }
 

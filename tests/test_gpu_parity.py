@@ -658,3 +658,54 @@ def _check_sorts_2(torch, dev, bcf):
         ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, kk), to_dev(torch, dev, vv))
         wk, wv = oracle.sort_pairs_u32(kk, vv)
         assert first_diff(ko.cpu().numpy(), wk) is None and first_diff(vo.cpu().numpy(), wv) is None
+
+
+# ------------------------------------------------------------ other key types
+
+F32_SPECIAL_BITS = np.array([0xFFC00000, 0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80000001, 0x80000000, 0x00000000,
+                             0x00000001, 0x3F800000, 0x7F7FFFFF, 0x7F800000, 0x7FC00000], dtype=np.uint32)
+
+
+def _typed_keys(kind, n, dist, seed):
+    bits = workloads.draws_u32(seed, n)
+    if dist == "special":  # special values only: heavy ties across -NaN .. +NaN, both zeros
+        bits = F32_SPECIAL_BITS[bits % F32_SPECIAL_BITS.size] if kind == "f32" else (bits % 9).astype(np.uint32) - 4
+    return bits.view(np.float32 if kind == "f32" else np.int32)
+
+
+@pytest.mark.parametrize("kind", ["i32", "f32"])
+@pytest.mark.parametrize("n", [1, 4097, 100003, (1 << 20) + 7, (1 << 25) + 5])
+def test_typed_sorts_vs_oracle(torch_dev, bcf, kind, n):
+    torch, dev = torch_dev
+    sort = bcf.sort_f32 if kind == "f32" else bcf.sort_i32
+    ref = oracle.sort_f32 if kind == "f32" else oracle.sort_i32
+    for dist in ("bits", "special"):
+        keys = _typed_keys(kind, n, dist, seed=n % 977)
+        got = sort(torch.from_numpy(keys).to(dev)).cpu().numpy()
+        assert first_diff(got.view(np.uint32), ref(keys).view(np.uint32)) is None, (kind, n, dist)
+
+
+@pytest.mark.parametrize("kind", ["i32", "f32"])
+@pytest.mark.parametrize("n", [3, 4096 * 3 + 1, (1 << 20) + 7])
+def test_typed_pairs_stable_vs_oracle(torch_dev, bcf, kind, n):
+    torch, dev = torch_dev
+    sort = bcf.sort_pairs_f32 if kind == "f32" else bcf.sort_pairs_i32
+    ref = oracle.sort_f32 if kind == "f32" else oracle.sort_i32
+    keys = _typed_keys(kind, n, "special", seed=7)
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = sort(torch.from_numpy(keys).to(dev), to_dev(torch, dev, vals))
+    wk, wv = ref(keys, vals)
+    assert first_diff(ko.cpu().numpy().view(np.uint32), wk.view(np.uint32)) is None
+    assert first_diff(vo.cpu().numpy(), wv) is None
+
+
+def test_typed_sort_in_place_and_errors(torch_dev, bcf):
+    torch, dev = torch_dev
+    keys = _typed_keys("f32", 50000, "bits", seed=3)
+    t = torch.from_numpy(keys).to(dev)
+    bcf.sort_f32(t, out=t)
+    assert first_diff(t.cpu().numpy().view(np.uint32), oracle.sort_f32(keys).view(np.uint32)) is None
+    with pytest.raises(TypeError):
+        bcf.sort_f32(torch.zeros(10, dtype=torch.int32, device=dev))
+    with pytest.raises(TypeError):
+        bcf.sort_i32(torch.zeros(10, dtype=torch.float32, device=dev))

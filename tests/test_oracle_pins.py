@@ -187,6 +187,71 @@ def test_multiset_hash_permutation_invariant_and_sensitive(oracle_mod):
         assert oracle_mod.multiset_hash(keys, v2) != h
 
 
+# ---------------------------------------------------- other key types
+
+
+def _f32_bits(xs):
+    return np.asarray(xs, dtype=np.float32).view(np.uint32)
+
+
+# IEEE 754 totalOrder of binary32 (IEEE 754-2008, 5.10), written out from the
+# standard's definition: negative NaNs (larger payload first), -inf, negative
+# normals and subnormals by decreasing magnitude, -0, +0, positive values by
+# increasing magnitude, +inf, positive NaNs (smaller payload first).
+TOTAL_ORDER_F32_BITS = [
+    0xFFC00001, 0xFFC00000, 0xFF800001,          # -NaN (quiet, payload 1), -qNaN, -sNaN
+    0xFF800000,                                  # -inf
+    0xFF7FFFFF, 0xBF800000, 0x80800000,          # -max, -1, -min normal
+    0x807FFFFF, 0x80000001,                      # -max subnormal, -min subnormal
+    0x80000000, 0x00000000,                      # -0, +0
+    0x00000001, 0x007FFFFF, 0x00800000,          # +min subnormal, +max subnormal, +min normal
+    0x3F800000, 0x7F7FFFFF, 0x7F800000,          # +1, +max, +inf
+    0x7F800001, 0x7FC00000, 0x7FC00001,          # +sNaN, +qNaN, +qNaN payload 1
+]
+
+
+def test_sort_i32_matches_numpy(oracle_mod):
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 17, 1000, 4099):
+        keys = rng.integers(-2**31, 2**31, size=n, dtype=np.int64).astype(np.int32)
+        keys[: min(n, 2)] = [-2**31, 2**31 - 1][: min(n, 2)]
+        assert np.array_equal(oracle_mod.sort_i32(keys), np.sort(keys))
+        vals = np.arange(n, dtype=np.uint32)
+        ko, vo = oracle_mod.sort_i32(keys % 7 - 3, vals)  # heavy ties: stability
+        order = np.argsort(keys % 7 - 3, kind="stable")
+        assert np.array_equal(ko, (keys % 7 - 3)[order]) and np.array_equal(vo, vals[order])
+
+
+def test_sort_i32_ternary_words_order_statistics(oracle_mod):
+    for word in itertools.product((-1, 0, 1), repeat=6):
+        assert oracle_mod.sort_i32(np.array(word, dtype=np.int32)).tolist() == order_statistics(word)
+
+
+def test_sort_f32_finite_matches_numpy(oracle_mod):
+    rng = np.random.default_rng(4)
+    for n in (1, 33, 5000):
+        keys = (rng.standard_normal(n) * 10.0 ** rng.integers(-30, 30, size=n)).astype(np.float32)
+        keys = keys[keys != 0]  # no zeros of either sign: numpy's order is then totalOrder
+        assert np.array_equal(oracle_mod.sort_f32(keys).view(np.uint32), np.sort(keys).view(np.uint32))
+
+
+def test_sort_f32_total_order_fixture(oracle_mod):
+    want = np.array(TOTAL_ORDER_F32_BITS, dtype=np.uint32)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        perm = rng.permutation(want.size)
+        got = oracle_mod.sort_f32(want[perm].view(np.float32)).view(np.uint32)
+        assert got.tolist() == want.tolist()
+
+
+def test_sort_f32_signed_zeros_stable(oracle_mod):
+    keys = np.array([0.0, -0.0, 0.0, -0.0, -0.0, 1.0, -1.0], dtype=np.float32)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    ko, vo = oracle_mod.sort_f32(keys, vals)
+    assert ko.view(np.uint32).tolist() == _f32_bits([-1.0, -0.0, -0.0, -0.0, 0.0, 0.0, 1.0]).tolist()
+    assert vo.tolist() == [6, 1, 3, 4, 0, 2, 5]
+
+
 # ---------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
@@ -200,6 +265,10 @@ MUTANTS = {
     "descending": ("if (src[i] <= src[j])", "if (src[i] >= src[j])"),
     # right half sorted from one past the split: its first element is skipped
     "skip_split_element": ("msort_keys(a, tmp, mid, hi);", "msort_keys(a, tmp, mid + 1, hi);"),
+    # int32 keys compared as unsigned
+    "i32_unsigned": ("return (int32_t)a <= (int32_t)b;", "return a <= b;"),
+    # negative floats ordered by increasing magnitude
+    "f32_negatives_ascending": ("return sa ? ma >= mb : ma <= mb;", "return ma <= mb;"),
 }
 
 
@@ -234,6 +303,18 @@ def _pins_pass(lib) -> bool:
         lib.oracle_merge_runs(p(keys), p(vals), offs.ctypes.data_as(u64p), ctypes.c_uint32(4), p(ko), p(vo))
         ek, ev = _stable_concat_sort(keys, vals)
         ok = np.array_equal(ko, ek) and np.array_equal(vo, ev)
+    # typed pins: int32 against numpy, float32 against the totalOrder fixture
+    if ok:
+        keys = np.array([5, -3, 2**31 - 1, -2**31, 0, -1, 7], dtype=np.int32).view(np.uint32)
+        ko = np.empty_like(keys)
+        lib.oracle_sort_typed(1, p(keys), None, p(ko), None, ctypes.c_uint64(keys.size))
+        ok = np.array_equal(ko.view(np.int32), np.sort(keys.view(np.int32)))
+    if ok:
+        want = np.array(TOTAL_ORDER_F32_BITS, dtype=np.uint32)
+        keys = want[::-1].copy()
+        ko = np.empty_like(keys)
+        lib.oracle_sort_typed(2, p(keys), None, p(ko), None, ctypes.c_uint64(keys.size))
+        ok = np.array_equal(ko, want)
     return ok
 
 
@@ -250,6 +331,7 @@ def _build_variant(tmp_path, name, src_text):
     lib.oracle_sort_u32.argtypes = [u32p, u32p, ctypes.c_uint64]
     lib.oracle_sort_pairs_u32.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_uint64]
     lib.oracle_merge_runs.argtypes = [u32p, u32p, u64p, ctypes.c_uint32, u32p, u32p]
+    lib.oracle_sort_typed.argtypes = [ctypes.c_int, u32p, u32p, u32p, u32p, ctypes.c_uint64]
     return lib
 
 
