@@ -132,6 +132,32 @@ def test_temp_queries(lib):
     assert q_sort(lib, 2**32)[0] == 1  # above 2^32 - 1 keys: invalid
 
 
+def test_typed_sort_queries_and_errors(lib):
+    """int32 / float keys: the temp size is the u32 sort's; errors are returned
+    before any launch (no device needed)."""
+    for n in (0, 4096, 4097, 2**20 + 3, 2**26):
+        need_u = ctypes.c_uint64(0)
+        assert lib.bcf_sort_u32(None, None, n, None, ctypes.byref(need_u), None) == 0
+        for f in (lib.bcf_sort_i32, lib.bcf_sort_f32):
+            need = ctypes.c_uint64(7)
+            assert f(None, None, n, None, ctypes.byref(need), None) == 0
+            assert need.value == need_u.value
+        need_p = ctypes.c_uint64(0)
+        assert lib.bcf_sort_pairs_u32(None, None, None, None, n, None, ctypes.byref(need_p), None) == 0
+        for f in (lib.bcf_sort_pairs_i32, lib.bcf_sort_pairs_f32):
+            need = ctypes.c_uint64(7)
+            assert f(None, None, None, None, n, None, ctypes.byref(need), None) == 0
+            assert need.value == need_p.value
+    fake = ctypes.c_void_p(4096)
+    small = ctypes.c_uint64(16)
+    assert lib.bcf_sort_f32(fake, fake, 10**6, fake, ctypes.byref(small), None) == 2  # temp too small
+    assert lib.bcf_sort_i32(fake, fake, 10, fake, None, None) == 1  # NULL temp_bytes
+    big = ctypes.c_uint64(1 << 40)
+    assert lib.bcf_sort_i32(None, fake, 10**6, fake, ctypes.byref(big), None) == 1  # NULL keys
+    assert lib.bcf_sort_pairs_f32(fake, None, fake, fake, 10**6, fake, ctypes.byref(big), None) == 1  # NULL vals
+    assert lib.bcf_sort_f32(fake, fake, 2**32, fake, ctypes.byref(big), None) == 1  # too many keys
+
+
 def test_argument_errors(lib):
     need = ctypes.c_uint64(16)
     fake = ctypes.c_void_p(4096)
