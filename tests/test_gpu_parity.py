@@ -705,6 +705,13 @@ def test_typed_sort_in_place_and_errors(torch_dev, bcf):
     t = torch.from_numpy(keys).to(dev)
     bcf.sort_f32(t, out=t)
     assert first_diff(t.cpu().numpy().view(np.uint32), oracle.sort_f32(keys).view(np.uint32)) is None
+    # a view that is not 16-byte aligned (scalar map kernel) and a size with a tail
+    base = torch.from_numpy(_typed_keys("i32", 70003, "bits", seed=4)).to(dev)
+    view = base[1:]
+    want = oracle.sort_i32(view.cpu().numpy())
+    out = torch.empty(70005, dtype=torch.int32, device=dev)[3:]  # 70002, like the view
+    bcf.sort_i32(view, out=out)
+    assert first_diff(out.cpu().numpy(), want) is None
     with pytest.raises(TypeError):
         bcf.sort_f32(torch.zeros(10, dtype=torch.int32, device=dev))
     with pytest.raises(TypeError):
