@@ -993,18 +993,28 @@ __device__ __forceinline__ void fused_splits(const Src &, const MergeItem &, uin
 {
 }
 
+// Work-groups of the one-tile-per-wave merge (MODE 2) hold a single wave: the
+// LDS of a wave (its transpose area) is then the unit of residency, and a CU
+// keeps nine such waves instead of eight in groups of two (measured: 102 vs
+// 107 us per binary pass at 2^26 keys).
+constexpr int kMergeTileWaves = 1;
+
+template <int MODE>
+constexpr int merge_group_waves() { return MODE == 2 ? kMergeTileWaves : kWavesPerGroup; }
+
 template <bool P, class Src, int MODE, bool NT = false, bool FUSED = false>
-__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_merge(Src src, const uint32_t *__restrict__ splits)
+__global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src src, const uint32_t *__restrict__ splits)
 {
+    constexpr int W = merge_group_waves<MODE>();  // waves per work-group
     // per wave: the transpose area, then (pairs) the tile's staged values
     constexpr int kWaveWords = kLdsWords + (P ? kTile : 0);
-    __shared__ __align__(16) uint32_t lds_all[kWavesPerGroup][kWaveWords];
+    __shared__ __align__(16) uint32_t lds_all[W][kWaveWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint32_t *lds = lds_all[wave];
     uint32_t *vals = lds + kLdsWords;
-    const uint32_t G = gridDim.x * kWavesPerGroup;
-    uint32_t t = blockIdx.x * kWavesPerGroup + wave;
+    const uint32_t G = gridDim.x * W;
+    uint32_t t = blockIdx.x * W + wave;
     if (t >= src.ntiles)
         return;
     if constexpr (MODE == 2) {
@@ -1428,7 +1438,7 @@ __device__ __forceinline__ void packed_network(Lines<false> &t, uint32_t *lds, u
     to_strided_upper_reversed(t, lds, lane);
 }
 
-constexpr int kMerge4Waves = 2;
+constexpr int kMerge4Waves = 1;  // one wave per work-group (see kMergeTileWaves)
 
 // One wave per merge item: the item's A and B pieces merge into T1 (sorted,
 // padding after), its C and D pieces into T2.  T1 followed by T2 reversed is
@@ -1631,10 +1641,10 @@ static hipError_t launch_partition(const Src &src, uint32_t *splits, hipStream_t
 template <bool P, class Src, int MODE, bool NT = false, bool FUSED = false>
 static hipError_t launch_merge_mode(const Src &src, const uint32_t *splits, hipStream_t s)
 {
-    const uint32_t groups = MODE == 2 ? (src.ntiles + kWavesPerGroup - 1) / kWavesPerGroup
+    constexpr int W = merge_group_waves<MODE>();
+    const uint32_t groups = MODE == 2 ? (src.ntiles + W - 1) / W
                                       : persistent_groups(k_merge<P, Src, MODE, NT, FUSED>, src.ntiles);
-    hipLaunchKernelGGL((k_merge<P, Src, MODE, NT, FUSED>), dim3(groups), dim3(kWave * kWavesPerGroup), 0, s, src,
-                       splits);
+    hipLaunchKernelGGL((k_merge<P, Src, MODE, NT, FUSED>), dim3(groups), dim3(kWave * W), 0, s, src, splits);
     return hipGetLastError();
 }
 
