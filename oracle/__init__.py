@@ -45,6 +45,9 @@ def _load():
     lib.oracle_is_sorted_u32.restype = ctypes.c_int
     lib.oracle_sort_typed.argtypes = [ctypes.c_int, u32p, u32p, u32p, u32p, ctypes.c_uint64]
     lib.oracle_sort_typed.restype = ctypes.c_int
+    lib.oracle_colored_prefix_sums.argtypes = [u32p, ctypes.POINTER(ctypes.c_uint8), u32p, ctypes.c_uint64,
+                                               ctypes.c_uint32]
+    lib.oracle_colored_prefix_sums.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -138,3 +141,15 @@ def sort_i32(keys, vals=None):
 def sort_f32(keys, vals=None):
     """Ascending sort of float32 keys in IEEE 754 totalOrder, stable with values."""
     return _sort_typed(2, np.float32, keys, vals)
+
+
+def colored_prefix_sums(values, colors, d):
+    """Per-color inclusive prefix sums (mod 2^32); colors >= d count as d - 1."""
+    v = _u32(values)
+    c = np.ascontiguousarray(np.asarray(colors, dtype=np.uint8))
+    assert v.shape == c.shape
+    out = np.empty_like(v)
+    if _load().oracle_colored_prefix_sums(_p32(v), c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _p32(out),
+                                          v.size, d) != 0:
+        raise ValueError("colored_prefix_sums: d must be in [1, 256]")
+    return out

@@ -17,7 +17,9 @@
  *                             lower run index and then the earlier position;
  *   - oracle_segmented_sort   oracle_sort_u32 applied to every segment;
  *   - oracle_sort_typed       int32 keys (signed order) or float keys (IEEE 754
- *                             totalOrder), stable, values optional.
+ *                             totalOrder), stable, values optional;
+ *   - oracle_colored_prefix_sums  per-color inclusive prefix sums (the paper's
+ *                             bank-conflict example, Sec. 1.2).
  * Keys compare as unsigned 32-bit integers (the paper does not fix signedness).
  *
  * Algorithm: top-down merge sort (split in halves, sort each, merge taking the
@@ -213,6 +215,29 @@ int oracle_sort_typed(int kind, const uint32_t *kin, const uint32_t *vin, uint32
     msort_typed(le, kout, vin ? vout : 0, tk, tv, 0, n);
     free(tk);
     free(tv);
+    return 0;
+}
+
+/* ---- colored prefix sums ----------------------------------------------- */
+
+/*
+ * The paper's motivating problem for bank conflicts (Sec. 1.2 and its
+ * appendix on colored prefix sums): every element i has a value and one of d
+ * colors; out[i] is the sum of the values of the elements j <= i of the same
+ * color (inclusive), modulo 2^32.  One pass with d running sums.  Colors at or
+ * above d count as color d - 1.
+ */
+int oracle_colored_prefix_sums(const uint32_t *values, const uint8_t *colors, uint32_t *out, uint64_t n, uint32_t d)
+{
+    if (d == 0 || d > 256)
+        return -2;
+    uint32_t run[256];
+    memset(run, 0, sizeof(run));
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t c = colors[i] < d ? colors[i] : d - 1;
+        run[c] += values[i];
+        out[i] = run[c];
+    }
     return 0;
 }
 

@@ -252,6 +252,41 @@ def test_sort_f32_signed_zeros_stable(oracle_mod):
     assert vo.tolist() == [6, 1, 3, 4, 0, 2, 5]
 
 
+# ------------------------------------------------- colored prefix sums
+
+
+def test_colored_prefix_sums_matches_numpy(oracle_mod):
+    """Against numpy: per color, a cumulative sum over the elements of that
+    color (uint32 wrap-around), scattered back to their positions."""
+    rng = np.random.default_rng(6)
+    for n, d in [(1, 1), (10, 3), (1000, 16), (5000, 32), (4097, 2)]:
+        vals = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+        cols = rng.integers(0, d, size=n).astype(np.uint8)
+        want = np.empty(n, dtype=np.uint32)
+        for c in range(d):
+            idx = np.flatnonzero(cols == c)
+            want[idx] = np.cumsum(vals[idx], dtype=np.uint32)
+        assert np.array_equal(oracle_mod.colored_prefix_sums(vals, cols, d), want)
+
+
+def test_colored_prefix_sums_special_cases(oracle_mod):
+    # one color: the ordinary inclusive prefix sum
+    vals = np.arange(1, 101, dtype=np.uint32)
+    assert oracle_mod.colored_prefix_sums(vals, np.zeros(100, np.uint8), 1).tolist() == \
+        [k * (k + 1) // 2 for k in range(1, 101)]
+    # every element its own color: the values themselves
+    assert oracle_mod.colored_prefix_sums(vals[:8], np.arange(8, dtype=np.uint8), 8).tolist() == list(range(1, 9))
+    # brute force on tiny inputs: out[i] = sum of v[j], j <= i, same color
+    for word in itertools.product((0, 1, 2), repeat=5):
+        cols = np.array(word, dtype=np.uint8)
+        v = np.array([3, 5, 7, 11, 13], dtype=np.uint32)
+        want = [int(sum(v[j] for j in range(i + 1) if cols[j] == cols[i])) for i in range(5)]
+        assert oracle_mod.colored_prefix_sums(v, cols, 3).tolist() == want
+    # colors at or above d count as d - 1
+    assert oracle_mod.colored_prefix_sums(np.ones(4, np.uint32), np.array([0, 5, 1, 9], np.uint8), 2).tolist() == \
+        [1, 1, 2, 3]
+
+
 # ---------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
@@ -269,6 +304,13 @@ MUTANTS = {
     "i32_unsigned": ("return (int32_t)a <= (int32_t)b;", "return a <= b;"),
     # negative floats ordered by increasing magnitude
     "f32_negatives_ascending": ("return sa ? ma >= mb : ma <= mb;", "return ma <= mb;"),
+    # colored prefix sums made exclusive (each output misses its own value)
+    "cps_exclusive": ("        run[c] += values[i];\n        out[i] = run[c];\n",
+                      "        out[i] = run[c];\n        run[c] += values[i];\n"),
+    # colors out of range folded into color 0 instead of d - 1
+    "cps_clamp_to_zero": ("colors[i] < d ? colors[i] : d - 1", "colors[i] < d ? colors[i] : 0"),
+    # one running total shared by every color
+    "cps_one_total": ("        run[c] += values[i];\n", "        run[0] += values[i];\n"),
 }
 
 
@@ -315,6 +357,21 @@ def _pins_pass(lib) -> bool:
         ko = np.empty_like(keys)
         lib.oracle_sort_typed(2, p(keys), None, p(ko), None, ctypes.c_uint64(keys.size))
         ok = np.array_equal(ko, want)
+    # colored prefix sums: brute force over ternary color words, with colors
+    # 2 and 3 folded into the last color of d = 2 half the time
+    if ok:
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        v = np.array([3, 5, 7, 11, 13], dtype=np.uint32)
+        for word in itertools.product((0, 1, 3), repeat=5):
+            cols = np.array(word, dtype=np.uint8)
+            for d in (2, 4):
+                eff = np.minimum(cols, d - 1)
+                want = [int(sum(v[j] for j in range(i + 1) if eff[j] == eff[i])) for i in range(5)]
+                o = np.empty_like(v)
+                lib.oracle_colored_prefix_sums(p(v), cols.ctypes.data_as(u8p), p(o), ctypes.c_uint64(5),
+                                               ctypes.c_uint32(d))
+                if o.tolist() != want:
+                    return False
     return ok
 
 
@@ -332,6 +389,8 @@ def _build_variant(tmp_path, name, src_text):
     lib.oracle_sort_pairs_u32.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_uint64]
     lib.oracle_merge_runs.argtypes = [u32p, u32p, u64p, ctypes.c_uint32, u32p, u32p]
     lib.oracle_sort_typed.argtypes = [ctypes.c_int, u32p, u32p, u32p, u32p, ctypes.c_uint64]
+    lib.oracle_colored_prefix_sums.argtypes = [u32p, ctypes.POINTER(ctypes.c_uint8), u32p, ctypes.c_uint64,
+                                               ctypes.c_uint32]
     return lib
 
 

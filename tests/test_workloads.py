@@ -70,3 +70,14 @@ def test_torch_twin_bit_identical():
         a = workloads.keys_u32(dist, 5000, seed=4)
         b = workloads.keys_u32_torch(dist, 5000, "cpu", seed=4, chunk=1024).numpy()
         assert np.array_equal(a, b), dist
+
+
+@pytest.mark.parametrize("m", [1, 5, 32, 40, 256])
+def test_colored_inputs_twins_and_range(m):
+    v, c = workloads.colored_u32(70001, m, seed=9)
+    assert v.dtype == np.uint32 and c.dtype == np.uint8
+    assert int(c.max()) < m
+    if m <= 40:  # every color drawn
+        assert np.unique(c).size == m
+    tv, tc = workloads.colored_u32_torch(70001, m, "cpu", seed=9, chunk=30000)
+    assert np.array_equal(tv.numpy(), v) and np.array_equal(tc.numpy(), c)

@@ -28,6 +28,10 @@ section; the MI355X workloads add sorted, reverse, 16-distinct and Zipf):
 * ``paper_01``       -- uniform 0/1 keys (the paper's "0-1" set).
 * ``paper_dups``     -- k copies of each of n/k keys, shuffled ("defined
                         duplicates").
+
+Colored prefix sums take u32 values uniform over [0, 2^32) and uint8 colors
+uniform over [0, m) by the multiply-shift map ``(draw * m) >> 32`` of a second
+stream; ``m = d`` normally, ``m > d`` to exercise colors out of range.
 """
 
 from __future__ import annotations
@@ -46,6 +50,7 @@ __all__ = [
     "segment_sizes",
     "sorted_runs",
     "request_stream",
+    "colored_u32",
 ]
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -259,6 +264,31 @@ def keys_u32_torch(dist: str, n: int, device, seed: int = 1, chunk: int = 1 << 2
         r = torch.searchsorted(cdf, u, right=True).clamp_(max=cdf.numel() - 1)
         out[lo:hi] = ((r * 2654435761) & 0xFFFFFFFF).to(torch.int32)
     return out.view(torch.uint32)
+
+
+_COLOR_SEED = 0xC0105
+
+
+def colored_u32(n: int, m: int, seed: int = 1):
+    """(values u32, colors uint8 uniform over [0, m)), m <= 256."""
+    assert 1 <= m <= 256
+    vals = draws_u32(seed, n)
+    cols = ((draws_u32(seed ^ _COLOR_SEED, n).astype(np.uint64) * np.uint64(m)) >> np.uint64(32)).astype(np.uint8)
+    return vals, cols
+
+
+def colored_u32_torch(n: int, m: int, device, seed: int = 1, chunk: int = 1 << 26):
+    """Device twin of colored_u32 (torch.uint32 values, torch.uint8 colors)."""
+    import torch
+
+    assert 1 <= m <= 256
+    vals = draws_u32_torch(seed, n, device, chunk=chunk)
+    cols = torch.empty(n, dtype=torch.uint8, device=device)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        draw = _t_srl(draws_u64_torch(seed ^ _COLOR_SEED, hi - lo, device, lo), 32)
+        cols[lo:hi] = _t_srl(draw * m, 32).to(torch.uint8)
+    return vals, cols
 
 
 def segment_offsets(sizes) -> np.ndarray:
