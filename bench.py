@@ -399,6 +399,10 @@ def main():
         rec["fan_in_ablation"] = bench_fan_in(bcf, workloads, torch, dev)
         rec["pairs_2p28"] = bench_pairs(bcf, workloads, torch, dev)
         torch.cuda.empty_cache()
+        from paper_1306_5076_amd import cps_demo
+
+        rec["colored_prefix_sums_2p29"] = cps_demo.sweep(reps=3, device=str(dev))
+        torch.cuda.empty_cache()
         rec["segmented"] = bench_segmented(bcf, workloads, torch, dev)
         rec["segmented_2p17"] = bench_segmented(bcf, workloads, torch, dev, hi=1 << 17)
         rec["segmented_2p17"].pop("autotune_table", None)

@@ -150,6 +150,25 @@ bcf_status bcf_segmented_execute(const uint32_t *keys_in, const uint32_t *vals_i
                                  uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg, void *temp,
                                  uint64_t *temp_bytes, void *stream);
 
+/*
+ * Colored prefix sums, the paper's demonstration that shared-memory bank
+ * conflicts decide runtimes (Sec. 1.2 and its appendix): element i has a value
+ * and a color below d; out[i] = the sum of values[j] over j <= i with
+ * colors[j] == colors[i] (inclusive, modulo 2^32).  Colors at or above d count
+ * as color d - 1.  Three phases (tile sums per color, their scan over the
+ * tiles, scan of every tile page by page with per-thread, per-color counters
+ * in LDS).  conflict_free = 0 keeps each thread's d counters consecutive in
+ * LDS (the layout whose bank conflicts grow with d); 1 stores them
+ * color-major, conflict-free for every d.  Results are identical.
+ *   values, out  device, n u32 (out may equal values); colors device, n bytes;
+ *                all three 16-byte aligned (else BCF_ERR_INVALID)
+ *   d            1..32 (else BCF_ERR_INVALID)
+ *   temp         as for the sorts (query with temp == NULL)
+ */
+bcf_status bcf_colored_prefix_sums(const uint32_t *values, const uint8_t *colors, uint32_t *out, uint64_t n,
+                                   uint32_t d, int conflict_free, void *temp, uint64_t *temp_bytes,
+                                   void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *bcf_status_string(bcf_status s);
 

@@ -16,6 +16,7 @@ _API = (
     "sort_f32",
     "sort_pairs_i32",
     "sort_pairs_f32",
+    "colored_prefix_sums",
     "merge_runs",
     "segmented_sort",
     "SegmentedPlan",

@@ -31,6 +31,7 @@ EXPORTED = (
     "bcf_sort_f32",
     "bcf_sort_pairs_i32",
     "bcf_sort_pairs_f32",
+    "bcf_colored_prefix_sums",
     "bcf_merge_runs",
     "bcf_segmented_sort",
     "bcf_segmented_sort_pairs",
@@ -105,6 +106,8 @@ def load(path: str = LIB_PATH):
     for f in ("bcf_sort_pairs_i32", "bcf_sort_pairs_f32"):
         getattr(lib, f).argtypes = [vp, vp, vp, vp, u64, vp, u64p, vp]
         getattr(lib, f).restype = ctypes.c_int
+    lib.bcf_colored_prefix_sums.argtypes = [vp, vp, vp, u64, u32, ctypes.c_int, vp, u64p, vp]
+    lib.bcf_colored_prefix_sums.restype = ctypes.c_int
     lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
     lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]

@@ -25,6 +25,7 @@ __all__ = [
     "sort_f32",
     "sort_pairs_i32",
     "sort_pairs_f32",
+    "colored_prefix_sums",
     "merge_runs",
     "segmented_sort",
     "SegmentedPlan",
@@ -222,6 +223,31 @@ def sort_pairs_i32(keys, vals, keys_out=None, vals_out=None, stream=None, worksp
 def sort_pairs_f32(keys, vals, keys_out=None, vals_out=None, stream=None, workspace=None):
     """Stable sort of (float32 key, u32 value) pairs by key (totalOrder)."""
     return _sort_typed("f32", keys, vals, keys_out, vals_out, stream, workspace)
+
+
+def colored_prefix_sums(values, colors, d, conflict_free=True, out=None, stream=None, workspace=None):
+    """Per-color inclusive prefix sums of u32 ``values`` (uint8 ``colors`` < d,
+    d <= 32); ``conflict_free`` picks the LDS counter layout.  Returns ``out``."""
+    lib = load()
+    _check_tensor(values, "values")
+    if not isinstance(colors, torch.Tensor) or colors.dtype != torch.uint8 or not colors.is_cuda \
+            or not colors.is_contiguous() or colors.device != values.device:
+        raise TypeError("colors must be a contiguous uint8 tensor on the values' device")
+    n = values.numel()
+    if colors.numel() != n:
+        raise ValueError("values and colors must have the same length")
+    out = torch.empty_like(values) if out is None else out
+    _check_tensor(out, "out", values.device)
+    stream, sh = _stream(stream, values.device)
+    need = ctypes.c_uint64(0)
+    check("bcf_colored_prefix_sums", lib.bcf_colored_prefix_sums(None, None, None, n, d, 1, None,
+                                                                 ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, values.device, stream)
+    if n:
+        check("bcf_colored_prefix_sums",
+              lib.bcf_colored_prefix_sums(_ptr(values), _ptr(colors), _ptr(out), n, d, 1 if conflict_free else 0,
+                                          _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh))
+    return out
 
 
 def merge_runs(keys, run_offsets, vals=None, keys_out=None, vals_out=None, stream=None, workspace=None):

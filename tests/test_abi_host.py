@@ -158,6 +158,32 @@ def test_typed_sort_queries_and_errors(lib):
     assert lib.bcf_sort_f32(fake, fake, 2**32, fake, ctypes.byref(big), None) == 1  # too many keys
 
 
+def test_colored_prefix_sums_queries_and_errors(lib):
+    """Temp = two 256-aligned arrays of tiles x d words, tiles <= 2048 of whole
+    8192-element pages; errors come back before any launch."""
+    f = lib.bcf_colored_prefix_sums
+    for n, d in ((1, 1), (8192, 5), (8193, 32), (2**22 + 5, 16), (2**29, 32), (2**32 - 1, 3)):
+        need = ctypes.c_uint64(7)
+        assert f(None, None, None, n, d, 1, None, ctypes.byref(need), None) == 0
+        pages = -(-n // 8192)
+        tile = -(-pages // 2048) * 8192
+        tiles = -(-n // tile)
+        assert tiles <= 2048 and (tiles - 1) * tile < n <= tiles * tile
+        assert need.value == 2 * (-(-(tiles * d * 4) // 256) * 256), (n, d)
+    need = ctypes.c_uint64(7)
+    assert f(None, None, None, 0, 4, 0, None, ctypes.byref(need), None) == 0 and need.value == 0
+    for d in (0, 33, 256):
+        assert f(None, None, None, 100, d, 1, None, ctypes.byref(need), None) == 1
+    assert f(None, None, None, 2**32, 4, 1, None, ctypes.byref(need), None) == 1
+    fake, odd = ctypes.c_void_p(4096), ctypes.c_void_p(4100)
+    big = ctypes.c_uint64(1 << 30)
+    assert f(fake, fake, fake, 100, 4, 1, fake, None, None) == 1  # NULL temp_bytes
+    assert f(None, fake, fake, 100, 4, 1, fake, ctypes.byref(big), None) == 1  # NULL values
+    assert f(fake, odd, fake, 100, 4, 1, fake, ctypes.byref(big), None) == 1  # colors not 16-byte aligned
+    small = ctypes.c_uint64(16)
+    assert f(fake, fake, fake, 10**6, 4, 1, fake, ctypes.byref(small), None) == 2  # temp too small
+
+
 def test_argument_errors(lib):
     need = ctypes.c_uint64(16)
     fake = ctypes.c_void_p(4096)
