@@ -48,6 +48,8 @@ def _load():
     lib.oracle_colored_prefix_sums.argtypes = [u32p, ctypes.POINTER(ctypes.c_uint8), u32p, ctypes.c_uint64,
                                                ctypes.c_uint32]
     lib.oracle_colored_prefix_sums.restype = ctypes.c_int
+    lib.oracle_sort_u64.argtypes = [u64p, u64p, ctypes.c_uint64]
+    lib.oracle_sort_u64.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -141,6 +143,15 @@ def sort_i32(keys, vals=None):
 def sort_f32(keys, vals=None):
     """Ascending sort of float32 keys in IEEE 754 totalOrder, stable with values."""
     return _sort_typed(2, np.float32, keys, vals)
+
+
+def sort_u64(keys) -> np.ndarray:
+    """Ascending sort of u64 keys (top-down merge sort)."""
+    k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
+    out = np.empty_like(k)
+    if k.size and _load().oracle_sort_u64(_p64(k), _p64(out), k.size) != 0:
+        raise MemoryError("oracle_sort_u64")
+    return out
 
 
 def colored_prefix_sums(values, colors, d):

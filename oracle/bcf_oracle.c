@@ -18,6 +18,7 @@
  *   - oracle_segmented_sort   oracle_sort_u32 applied to every segment;
  *   - oracle_sort_typed       int32 keys (signed order) or float keys (IEEE 754
  *                             totalOrder), stable, values optional;
+ *   - oracle_sort_u64            ascending sort of unsigned 64-bit keys.
  *   - oracle_colored_prefix_sums  per-color inclusive prefix sums (the paper's
  *                             bank-conflict example, Sec. 1.2).
  * Keys compare as unsigned 32-bit integers (the paper does not fix signedness).
@@ -238,6 +239,50 @@ int oracle_colored_prefix_sums(const uint32_t *values, const uint8_t *colors, ui
         run[c] += values[i];
         out[i] = run[c];
     }
+    return 0;
+}
+
+/* ---- 64-bit keys ---------------------------------------------------------- */
+
+/* merge src[lo,mid) and src[mid,hi) of u64 keys into dst[lo,hi); left wins ties */
+static void merge_u64(const uint64_t *src, uint64_t *dst, size_t lo, size_t mid, size_t hi)
+{
+    size_t i = lo, j = mid, o = lo;
+    while (i < mid && j < hi) {
+        const uint64_t x = src[i], y = src[j];
+        if (x <= y)
+            dst[o++] = src[i++];
+        else
+            dst[o++] = src[j++];
+    }
+    while (i < mid)
+        dst[o++] = src[i++];
+    while (j < hi)
+        dst[o++] = src[j++];
+}
+
+static void msort_u64(uint64_t *a, uint64_t *tmp, size_t lo, size_t hi)
+{
+    if (hi - lo < 2)
+        return;
+    const size_t mid = lo + (hi - lo) / 2;
+    msort_u64(a, tmp, lo, mid);
+    msort_u64(a, tmp, mid, hi);
+    merge_u64(a, tmp, lo, mid, hi);
+    memcpy(a + lo, tmp + lo, (hi - lo) * sizeof(uint64_t));
+}
+
+/* Ascending sort of unsigned 64-bit keys (top-down merge sort, as for u32). */
+int oracle_sort_u64(const uint64_t *in, uint64_t *out, uint64_t n)
+{
+    memcpy(out, in, n * sizeof(uint64_t));
+    if (n < 2)
+        return 0;
+    uint64_t *tmp = (uint64_t *)malloc(n * sizeof(uint64_t));
+    if (!tmp)
+        return -1;
+    msort_u64(out, tmp, 0, n);
+    free(tmp);
     return 0;
 }
 

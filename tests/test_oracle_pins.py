@@ -287,6 +287,28 @@ def test_colored_prefix_sums_special_cases(oracle_mod):
         [1, 1, 2, 3]
 
 
+# ------------------------------------------------------------------ u64 keys
+
+U64_PROBES = (0, 1, 2**32 - 1, 2**32, 2**32 + 1, 2**63, 2**64 - 1)
+
+
+def test_sort_u64_words_order_statistics(oracle_mod):
+    """Every word of length 4 over keys that differ only in the high half, only
+    in the low half, or in both, against the counting definition."""
+    for word in itertools.product(U64_PROBES, repeat=4):
+        assert oracle_mod.sort_u64(np.array(word, dtype=np.uint64)).tolist() == order_statistics(word)
+
+
+def test_sort_u64_matches_numpy(oracle_mod):
+    rng = np.random.default_rng(11)
+    for n in (0, 1, 2, 1000, 4097):
+        hi = rng.integers(0, 5, size=n, dtype=np.uint64)  # heavy ties in the high half
+        lo = rng.integers(0, 2**32, size=n, dtype=np.uint64)
+        for keys in ((hi << np.uint64(32)) | lo, (lo << np.uint64(32)) | hi,
+                     rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64, endpoint=True)):
+            assert np.array_equal(oracle_mod.sort_u64(keys), np.sort(keys))
+
+
 # ---------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
@@ -304,6 +326,10 @@ MUTANTS = {
     "i32_unsigned": ("return (int32_t)a <= (int32_t)b;", "return a <= b;"),
     # negative floats ordered by increasing magnitude
     "f32_negatives_ascending": ("return sa ? ma >= mb : ma <= mb;", "return ma <= mb;"),
+    # u64 keys compared by their low halves only
+    "u64_low_half_only": ("        if (x <= y)\n", "        if ((uint32_t)x <= (uint32_t)y)\n"),
+    # u64 keys compared by their high halves only
+    "u64_high_half_only": ("        if (x <= y)\n", "        if ((x >> 32) <= (y >> 32))\n"),
     # colored prefix sums made exclusive (each output misses its own value)
     "cps_exclusive": ("        run[c] += values[i];\n        out[i] = run[c];\n",
                       "        out[i] = run[c];\n        run[c] += values[i];\n"),
@@ -357,6 +383,15 @@ def _pins_pass(lib) -> bool:
         ko = np.empty_like(keys)
         lib.oracle_sort_typed(2, p(keys), None, p(ko), None, ctypes.c_uint64(keys.size))
         ok = np.array_equal(ko, want)
+    # u64 keys: words over keys differing in either half
+    if ok:
+        u64 = ctypes.POINTER(ctypes.c_uint64)
+        for word in itertools.product((1, 2**32, 2**32 + 2, 3), repeat=4):
+            k = np.array(word, dtype=np.uint64)
+            o = np.empty_like(k)
+            lib.oracle_sort_u64(k.ctypes.data_as(u64), o.ctypes.data_as(u64), ctypes.c_uint64(4))
+            if o.tolist() != order_statistics(word):
+                return False
     # colored prefix sums: brute force over ternary color words, with colors
     # 2 and 3 folded into the last color of d = 2 half the time
     if ok:
@@ -391,6 +426,7 @@ def _build_variant(tmp_path, name, src_text):
     lib.oracle_sort_typed.argtypes = [ctypes.c_int, u32p, u32p, u32p, u32p, ctypes.c_uint64]
     lib.oracle_colored_prefix_sums.argtypes = [u32p, ctypes.POINTER(ctypes.c_uint8), u32p, ctypes.c_uint64,
                                                ctypes.c_uint32]
+    lib.oracle_sort_u64.argtypes = [u64p, u64p, ctypes.c_uint64]
     return lib
 
 

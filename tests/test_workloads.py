@@ -81,3 +81,19 @@ def test_colored_inputs_twins_and_range(m):
         assert np.unique(c).size == m
     tv, tc = workloads.colored_u32_torch(70001, m, "cpu", seed=9, chunk=30000)
     assert np.array_equal(tv.numpy(), v) and np.array_equal(tc.numpy(), c)
+
+
+def test_u64_keys_distributions():
+    n = 50_000
+    for dist in workloads.U64_DISTRIBUTIONS:
+        k = workloads.keys_u64(dist, n, seed=4)
+        assert k.dtype == np.uint64 and k.size == n
+        assert np.array_equal(k, workloads.keys_u64(dist, n, seed=4))  # reproducible
+    hi = lambda a: a >> np.uint64(32)
+    lo = lambda a: a & np.uint64(0xFFFFFFFF)
+    assert np.unique(hi(workloads.keys_u64("hi16", n))).size == 16
+    assert np.unique(lo(workloads.keys_u64("lo16", n))).size == 16
+    s = workloads.keys_u64("sorted", n)
+    assert np.all(np.diff(hi(s).astype(np.int64)) > 0)
+    assert np.array_equal(hi(workloads.keys_u64("reverse", n)), hi(s)[::-1])
+    assert set(workloads.keys_u64("extremes", n).tolist()) == {0, 1, 2**32 - 1, 2**32, 2**63, 2**64 - 1}

@@ -29,6 +29,12 @@ section; the MI355X workloads add sorted, reverse, 16-distinct and Zipf):
 * ``paper_dups``     -- k copies of each of n/k keys, shuffled ("defined
                         duplicates").
 
+64-bit keys (``keys_u64``): ``uniform`` (a full 64-bit draw), ``hi16`` (high half
+one of 16 values, low half uniform: ties in the high half), ``lo16`` (the
+reverse), ``equal`` (one key), ``sorted`` / ``reverse`` (``sorted`` u32 in the high
+half, a uniform low half), ``extremes`` (drawn from 0, 1, 2^32 - 1, 2^32,
+2^63 and 2^64 - 1).
+
 Colored prefix sums take u32 values uniform over [0, 2^32) and uint8 colors
 uniform over [0, m) by the multiply-shift map ``(draw * m) >> 32`` of a second
 stream; ``m = d`` normally, ``m > d`` to exercise colors out of range.
@@ -51,6 +57,7 @@ __all__ = [
     "sorted_runs",
     "request_stream",
     "colored_u32",
+    "keys_u64",
 ]
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -264,6 +271,29 @@ def keys_u32_torch(dist: str, n: int, device, seed: int = 1, chunk: int = 1 << 2
         r = torch.searchsorted(cdf, u, right=True).clamp_(max=cdf.numel() - 1)
         out[lo:hi] = ((r * 2654435761) & 0xFFFFFFFF).to(torch.int32)
     return out.view(torch.uint32)
+
+
+U64_DISTRIBUTIONS = ("uniform", "hi16", "lo16", "equal", "sorted", "reverse", "extremes")
+_U64_EXTREMES = np.array([0, 1, 2**32 - 1, 2**32, 2**63, 2**64 - 1], dtype=np.uint64)
+
+
+def keys_u64(dist: str, n: int, seed: int = 1) -> np.ndarray:
+    """n unsigned 64-bit keys of the named distribution (see the module doc)."""
+    s32 = np.uint64(32)
+    if dist == "uniform":
+        return draws_u64(seed, n)
+    if dist in ("hi16", "lo16"):
+        few = ((draws_u32(seed, n) >> np.uint32(28)) * np.uint32(0x9E3779B9)).astype(np.uint64)  # odd: 16 values
+        many = draws_u32(seed ^ 0x64, n).astype(np.uint64)
+        return (few << s32) | many if dist == "hi16" else (many << s32) | few
+    if dist == "equal":
+        return np.full(n, 0x0123456789ABCDEF, dtype=np.uint64)
+    if dist in ("sorted", "reverse"):
+        k = (keys_u32(dist, n, seed).astype(np.uint64) << s32) | draws_u32(seed ^ 0x64, n).astype(np.uint64)
+        return k
+    if dist == "extremes":
+        return _U64_EXTREMES[draws_u32(seed, n) % np.uint32(_U64_EXTREMES.size)]
+    raise ValueError(f"unknown u64 distribution {dist!r}")
 
 
 _COLOR_SEED = 0xC0105
