@@ -162,6 +162,18 @@ def bench_fan_in(bcf, workloads, torch, dev, n=1 << 26, reps=5):
     return res
 
 
+def bench_u64(bcf, workloads, torch, dev, n=1 << 26, reps=5):
+    """Unsigned 64-bit keys at 2^26 (uniform 64-bit draws), inputs in HBM."""
+    from paper_1306_5076_amd import autotune
+
+    keys = workloads.draws_u64_torch(1, n, dev).view(torch.uint64)
+    out = torch.empty_like(keys)
+    ws = bcf.Workspace(dev)
+    ms = autotune.time_ms(lambda: bcf.sort_u64(keys, out=out, workspace=ws), reps=reps, warmup=1)
+    return {"n": n, "ms": round(ms, 4), "Gkeys_per_s": round(n / ms / 1e6, 3),
+            "method": "two stable 32-bit pair sorts, low halves first, plus split and join passes"}
+
+
 def bench_pairs(bcf, workloads, torch, dev, n=1 << 28, steps=5, warmup=2):
     """2^28 stable key/value sorts (value = original index), uniform and Zipf keys."""
     from paper_1306_5076_amd import autotune
@@ -398,6 +410,8 @@ def main():
         rec["block_sort_ablation"] = bench_block_sorts(bcf, workloads, torch, dev)
         rec["fan_in_ablation"] = bench_fan_in(bcf, workloads, torch, dev)
         rec["pairs_2p28"] = bench_pairs(bcf, workloads, torch, dev)
+        torch.cuda.empty_cache()
+        rec["u64_2p26"] = bench_u64(bcf, workloads, torch, dev)
         torch.cuda.empty_cache()
         from paper_1306_5076_amd import cps_demo
 

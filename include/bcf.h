@@ -98,6 +98,21 @@ bcf_status bcf_sort_pairs_f32(const float *keys_in, const uint32_t *vals_in, flo
                               void *stream);
 
 /*
+ * Sort of unsigned 64-bit keys (an extension: the paper's keys are 32-bit),
+ * ascending.  A key is two 32-bit digits, sorted least significant first by
+ * two stable pair sorts on bcf_sort_pairs_u32's path: by the low halves
+ * carrying the high halves, then by the high halves carrying the low halves
+ * (stability keeps equal high halves in low-half order); two streaming passes
+ * split the keys into halves and join them back.
+ *   keys_in, keys_out  device, n u64 each, 8-byte aligned (keys_out may equal keys_in)
+ *   n                  at most 2^32 - 1 (else BCF_ERR_INVALID)
+ *   temp               four arrays of n u32 (256-byte aligned each) plus the pair
+ *                      sort's temp for n; query with temp == NULL as for the other sorts
+ */
+bcf_status bcf_sort_u64(const uint64_t *keys_in, uint64_t *keys_out, uint64_t n, void *temp,
+                        uint64_t *temp_bytes, void *stream);
+
+/*
  * Merge k sorted runs into one sorted sequence (the paper's binary merging of
  * sorted sequences larger than on-chip memory, Sec. 3.2, applied pairwise in
  * ceil(log2 k) passes).  Stable: among equal keys, lower run index first, then

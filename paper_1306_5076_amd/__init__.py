@@ -17,6 +17,7 @@ _API = (
     "sort_pairs_i32",
     "sort_pairs_f32",
     "colored_prefix_sums",
+    "sort_u64",
     "merge_runs",
     "segmented_sort",
     "SegmentedPlan",

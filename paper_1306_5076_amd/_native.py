@@ -32,6 +32,7 @@ EXPORTED = (
     "bcf_sort_pairs_i32",
     "bcf_sort_pairs_f32",
     "bcf_colored_prefix_sums",
+    "bcf_sort_u64",
     "bcf_merge_runs",
     "bcf_segmented_sort",
     "bcf_segmented_sort_pairs",
@@ -108,6 +109,8 @@ def load(path: str = LIB_PATH):
         getattr(lib, f).restype = ctypes.c_int
     lib.bcf_colored_prefix_sums.argtypes = [vp, vp, vp, u64, u32, ctypes.c_int, vp, u64p, vp]
     lib.bcf_colored_prefix_sums.restype = ctypes.c_int
+    lib.bcf_sort_u64.argtypes = [vp, vp, u64, vp, u64p, vp]
+    lib.bcf_sort_u64.restype = ctypes.c_int
     lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
     lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]

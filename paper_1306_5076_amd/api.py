@@ -26,6 +26,7 @@ __all__ = [
     "sort_pairs_i32",
     "sort_pairs_f32",
     "colored_prefix_sums",
+    "sort_u64",
     "merge_runs",
     "segmented_sort",
     "SegmentedPlan",
@@ -223,6 +224,28 @@ def sort_pairs_i32(keys, vals, keys_out=None, vals_out=None, stream=None, worksp
 def sort_pairs_f32(keys, vals, keys_out=None, vals_out=None, stream=None, workspace=None):
     """Stable sort of (float32 key, u32 value) pairs by key (totalOrder)."""
     return _sort_typed("f32", keys, vals, keys_out, vals_out, stream, workspace)
+
+
+def sort_u64(keys, out=None, stream=None, workspace=None):
+    """Ascending sort of a contiguous torch.uint64 CUDA tensor (two stable
+    32-bit pair sorts, low halves first).  Returns ``out``."""
+    lib = load()
+    for name, t in (("keys", keys), ("out", out)):
+        if t is not None and (not isinstance(t, torch.Tensor) or t.dtype != torch.uint64 or not t.is_cuda
+                              or not t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous torch.uint64 CUDA tensor")
+    n = keys.numel()
+    out = torch.empty_like(keys) if out is None else out
+    if out.numel() != n or out.device != keys.device:
+        raise ValueError("out must match keys")
+    stream, sh = _stream(stream, keys.device)
+    need = ctypes.c_uint64(0)
+    check("bcf_sort_u64", lib.bcf_sort_u64(None, None, n, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        check("bcf_sort_u64", lib.bcf_sort_u64(_ptr(keys), _ptr(out), n, _ptr(temp) or ctypes.c_void_p(1),
+                                               ctypes.byref(tb), sh))
+    return out
 
 
 def colored_prefix_sums(values, colors, d, conflict_free=True, out=None, stream=None, workspace=None):

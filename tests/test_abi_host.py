@@ -184,6 +184,24 @@ def test_colored_prefix_sums_queries_and_errors(lib):
     assert f(fake, fake, fake, 10**6, 4, 1, fake, ctypes.byref(small), None) == 2  # temp too small
 
 
+def test_u64_sort_queries_and_errors(lib):
+    """Temp = four 256-aligned u32 arrays + the pair sort's temp; errors before any launch."""
+    f = lib.bcf_sort_u64
+    for n in (0, 1, 4097, 2**20 + 3, 2**26, 2**32 - 1):
+        need, pn = ctypes.c_uint64(7), ctypes.c_uint64(0)
+        assert f(None, None, n, None, ctypes.byref(need), None) == 0
+        assert lib.bcf_sort_pairs_u32(None, None, None, None, n, None, ctypes.byref(pn), None) == 0
+        assert need.value == (0 if n == 0 else 4 * (-(-4 * n // 256) * 256) + pn.value), n
+    need = ctypes.c_uint64(0)
+    assert f(None, None, 2**32, None, ctypes.byref(need), None) == 1  # too many keys
+    fake = ctypes.c_void_p(4096)
+    assert f(fake, fake, 10, fake, None, None) == 1  # NULL temp_bytes
+    big = ctypes.c_uint64(1 << 40)
+    assert f(None, fake, 10**6, fake, ctypes.byref(big), None) == 1  # NULL keys_in
+    small = ctypes.c_uint64(16)
+    assert f(fake, fake, 10**6, fake, ctypes.byref(small), None) == 2  # temp too small
+
+
 def test_argument_errors(lib):
     need = ctypes.c_uint64(16)
     fake = ctypes.c_void_p(4096)
