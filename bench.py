@@ -115,14 +115,15 @@ def bench_small(bcf, workloads, torch, dev, n=1 << 16, reps=100, warmup=10):
 def bench_block_sorts(bcf, workloads, torch, dev, n=1 << 26, reps=5):
     """Ablation of the block sort at 2^26 uniform keys: group tiles sorted by
     merge rounds (default), wave tiles sorted by merge rounds, wave tiles sorted
-    by the paper's ShearSort (Sec. 3.1); whole sort and the block-sort kernel."""
+    by the paper's ShearSort (Sec. 3.1), group tiles sorted by the paper's long
+    ShearSort over 8 waves; whole sort and the block-sort kernel."""
     from paper_1306_5076_amd import autotune
 
     keys = workloads.keys_u32_torch("uniform", n, dev, seed=1)
     out = torch.empty_like(keys)
     ws = bcf.Workspace(dev)
     res = {"n": n}
-    names = {3: "group_merge_rounds", 1: "wave_merge_rounds", 2: "wave_shearsort"}
+    names = {3: "group_merge_rounds", 1: "wave_merge_rounds", 2: "wave_shearsort", 4: "group_long_shearsort"}
     for v, name in names.items():
         with bcf.tuning(block_sort=v):
             fn = lambda: bcf.sort_u32(keys, out=out, workspace=ws)
@@ -245,6 +246,9 @@ def main():
     ap.add_argument("--no-per-dist", action="store_true", help="skip the per-distribution timing")
     ap.add_argument("--quick", action="store_true",
                     help="headline only: skip the pairs, segmented and serving sections")
+    ap.add_argument("--block-sort-ablation", action="store_true",
+                    help="only the block-sort ablation at 2^26 keys (one JSON object)")
+    ap.add_argument("--reps", type=int, default=5, help="repetitions of the ablation timings")
     ap.add_argument(
         "--copy-calibration",
         action="store_true",
@@ -260,6 +264,14 @@ def main():
             file=sys.stderr,
         )
         sys.exit(2)
+    if args.block_sort_ablation:
+        import torch
+
+        import paper_1306_5076_amd as bcf
+        import workloads
+
+        print(json.dumps(bench_block_sorts(bcf, workloads, torch, torch.device("cuda:0"), reps=args.reps)), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -237,8 +237,11 @@ typedef struct {
                                   3 for sorts of more than 2^19 keys, else 1; 1 wave tiles
                                   sorted by merge rounds; 2 wave tiles sorted by the paper's
                                   ShearSort (Sec. 3.1); 3 multi-wave group tiles sorted by
-                                  merge rounds.  Wave tiles hand runs of 4096 keys to the
-                                  merge passes, group tiles runs of 32768 keys (16384 pairs) */
+                                  merge rounds; 4 group tiles of keys sorted by the paper's
+                                  long ShearSort over the 8 waves of a work-group (Sec. 3.1,
+                                  w^2 h keys by h warps; pairs use 3).  Wave tiles hand runs
+                                  of 4096 keys to the merge passes, group tiles runs of
+                                  32768 keys (16384 pairs) */
     int32_t fused_partition;   /* 1 (default): a merge pass of bcf_sort_u32 / bcf_sort_pairs_u32
                                   run by the one-tile-per-wave kernel finds each tile's split
                                   itself from the samples (one launch per pass); 0: a separate

@@ -165,7 +165,7 @@ Tuning &tuning_locked()
         g_tune.partition_half = env_int("BCF_PARTITION_HALF", 1) != 0;
         g_tune.fused_partition = env_int("BCF_FUSED", 1) != 0;
         g_tune.block_sort = env_int("BCF_BLOCK_SORT", 0);
-        if (g_tune.block_sort < 0 || g_tune.block_sort > 3)
+        if (g_tune.block_sort < 0 || g_tune.block_sort > 4)
             g_tune.block_sort = 0;
         g_tune.merge_fan_in = env_int("BCF_FAN_IN", 0);
         if (g_tune.merge_fan_in != 2 && g_tune.merge_fan_in != 4)
@@ -205,7 +205,7 @@ constexpr uint64_t kAutoWaveTilesMaxN = 1ull << 19;
 // Whether the block sort of an n-key regular sort uses multi-wave group tiles.
 bool sort_uses_groups(uint64_t n, const Tuning &tu)
 {
-    return tu.block_sort == 3 || (tu.block_sort == 0 && n > kAutoWaveTilesMaxN);
+    return tu.block_sort >= 3 || (tu.block_sort == 0 && n > kAutoWaveTilesMaxN);
 }
 
 // Length of the sorted runs the block sort of an n-key regular sort produces.
@@ -293,7 +293,9 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     {
         ProfScope p(kname_block_sort(pairs, false), s, 2.0 * elem_bytes * n);
         const SampleSet smp = (passes && sampled) ? sample_set(0) : none;
-        if (sort_uses_groups(n, tu))
+        if (sort_uses_groups(n, tu) && tu.block_sort == 4 && !pairs)
+            BCF_TRY(dev_status(launch_block_sort_shear_group(kin, kbuf(0), n, smp, s)));
+        else if (sort_uses_groups(n, tu))
             BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, smp, s)));
         else
             BCF_TRY(dev_status(launch_block_sort_regular(pairs, tu.block_sort == 2, kin, vin, kbuf(0),
@@ -836,7 +838,7 @@ void bcf_get_tuning(bcf_tuning *out)
 
 bcf_status bcf_set_tuning(const bcf_tuning *in)
 {
-    if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 3 ||
+    if (!in || in->merge_variant < 0 || in->merge_variant > 3 || in->block_sort < 0 || in->block_sort > 4 ||
         (in->merge_fan_in != 0 && in->merge_fan_in != 2 && in->merge_fan_in != 4))
         return BCF_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_tune_mu);

@@ -57,6 +57,11 @@ uint32_t group_run_keys(bool pairs);
 hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin,
                                    uint32_t *kout, uint32_t *vout, uint64_t n, SampleSet out_smp,
                                    hipStream_t s);
+// Keys only: group tiles sorted by the paper's long ShearSort over the waves
+// of a work-group (block-sort ablation); same runs and samples as the group
+// sort of launch_block_sort_group.
+hipError_t launch_block_sort_shear_group(const uint32_t *kin, uint32_t *kout, uint64_t n, SampleSet out_smp,
+                                         hipStream_t s);
 // Wave tiles of 4096 keys (runs of 4096), sorted by merge rounds or, with
 // shear, by the paper's ShearSort; writes the samples of its output (out_smp).
 hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin, const uint32_t *vin,

@@ -826,6 +826,133 @@ __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
     }
 }
 
+// ------------------------------------------------ long ShearSort (h waves)
+//
+// The paper's extension of its base case to M = w^2 h keys sorted by h waves
+// (Sec. 3.1, the ShearSort of a w x wh matrix), kept as a block-sort ablation
+// against the merge rounds of the group sort.  NW waves hold a grid of 64
+// rows and 64 NW columns: lane l of wave v holds, in BLOCKED layout, the
+// segment of row l in columns 64v .. 64v + 63, and after the in-wave
+// transpose, in STRIDED layout, column 64v + l.  Columns are one lane's
+// registers, sorted by Batcher's network.  Rows span the waves: each segment
+// is sorted in registers, then a bitonic network over the NW segments of a
+// row runs with merge-splits in place of comparators (a lane keeps the lower
+// or upper 64 of its own and its partner wave's segment: the elementwise min
+// or max against the partner's reversed segment, then an in-lane bitonic
+// merge), which sorts blocks by the same argument as the 0-1 principle.  Odd
+// rows descend by complementing.  log2(64) = 6 rounds of (rows in snake
+// order, columns) and a last ascending row sort leave the grid sorted
+// row-major; the paper gathers a row into adjacent columns of one wave and
+// sorts it by a segmented ShearSort, here the row stays spread over the waves
+// and meets through LDS.  A line permutation then turns row-major grid order
+// into the BLOCKED sub-tiles the rest of the group sort expects.
+
+constexpr uint32_t kShearPitch = 4100;  // words per source wave in the line permutation
+
+// Sort 64 registers that form a bitonic sequence, ascending.
+__device__ __forceinline__ void bitonic_merge_line(Lines<false> &t)
+{
+#pragma unroll
+    for (int d = kLine / 2; d >= 1; d /= 2)
+#pragma unroll
+        for (int i = 0; i < kLine; ++i)
+            if ((i & d) == 0)
+                cx<false>(t, i, i + d);
+}
+
+// Every row's NW sorted segments (lane l of each wave) into one sorted row,
+// segment v in wave v.  Each step writes the wave's segment to its own LDS
+// slice and reads the partner's (lane-consecutive words, conflict-free).
+template <int NW>
+__device__ __forceinline__ void merge_rows_across_waves(Lines<false> &t, uint32_t *lds, uint32_t lane,
+                                                        uint32_t wave)
+{
+    uint32_t *own = lds + kLdsWords * wave;
+#pragma unroll 1
+    for (int k = 1; k < NW; k *= 2) {
+#pragma unroll 1
+        for (int j = k; j >= 1; j /= 2) {
+            const uint32_t q = wave ^ (uint32_t)j;
+            const bool asc = (wave & (uint32_t)(2 * k)) == 0;
+            const bool keep_low = (wave < q) == asc;
+#pragma unroll
+            for (int r = 0; r < kLine; ++r)
+                own[r * kWave + lane] = t.k[r];
+            __syncthreads();
+            const uint32_t *other = lds + kLdsWords * q;
+#pragma unroll
+            for (int r = 0; r < kLine; ++r) {
+                const uint32_t b = other[(kLine - 1 - r) * kWave + lane];
+                t.k[r] = keep_low ? min(t.k[r], b) : max(t.k[r], b);
+            }
+            __syncthreads();
+            bitonic_merge_line(t);
+        }
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ void shear_rows(Lines<false> &t, uint32_t *lds, uint32_t lane, uint32_t wave, bool snake)
+{
+    if (snake)
+        flip(t, lane);
+    oe_sort<0, kLine - 1, false>(t);
+    merge_rows_across_waves<NW>(t, lds, lane, wave);
+    if (snake)
+        flip(t, lane);
+}
+
+// Entry: any registers (the loaded STRIDED tile read as row segments); exit:
+// BLOCKED sub-tiles of the sorted group (wave v, lane l, register r holds
+// group position 4096 v + 64 l + r).
+template <int NW>
+__device__ __forceinline__ void long_shear_sort(Lines<false> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    static_assert(NW >= 2 && NW <= 8 && (NW & (NW - 1)) == 0, "NW waves, a power of two dividing 64");
+    uint32_t *own = lds + kLdsWords * wave;
+#pragma unroll 1
+    for (int it = 0; it < 6; ++it) {
+        shear_rows<NW>(t, lds, lane, wave, true);
+        to_strided(t, own, lane);
+        oe_sort<0, kLine - 1, false>(t);
+        to_blocked(t, own, lane);
+    }
+    shear_rows<NW>(t, lds, lane, wave, false);
+    // grid position l * 64 NW + 64 v + r is line L = l NW + v of the group;
+    // line L goes to lane L mod 64 of wave L / 64.  Source lines are written
+    // lane-consecutively, 4100 words per wave, so that the gathering reads
+    // (line L = 64 v' + l' from wave L mod NW, lane L / NW) hit 32 banks.
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        lds[kShearPitch * wave + r * kWave + lane] = t.k[r];
+    __syncthreads();
+    const uint32_t line = kWave * wave + lane, sv = line % NW, sl = line / NW;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        t.k[r] = lds[kShearPitch * sv + r * kWave + sl];
+    __syncthreads();
+}
+
+// One group of NW * 4096 keys per work-group: load, long ShearSort, samples, store.
+template <int NW, class Src>
+__global__ __launch_bounds__(kWave *NW) void k_block_sort_shear_group(Src src)
+{
+    static_assert(kShearPitch * (NW - 1) + kTile <= (uint32_t)(NW * kLdsWords), "permutation fits the LDS");
+    __shared__ __align__(16) uint32_t lds[NW * kLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t g = blockIdx.x;
+    if (g >= src.ngroups)
+        return;  // the whole work-group: every wave reaches the same barriers
+    const SortItem it = src.get(g, wave);
+    Lines<false> t;
+    load_tile<false>(t, it.ks, it.count, lane);
+    long_shear_sort<NW>(t, lds, lane, wave);
+    write_samples<false>(t, src.out_smp, src.pos(g, wave), it.count, lane);
+    to_strided(t, lds + kLdsWords * wave, lane);
+    store_tile<false>(t, it.kd, nullptr, it.count, lane);
+}
+
 // Split of every merge tile: splits[t] = co-rank of the tile's first output
 // diagonal in its merge (paper Sec. 3.2: the rank of a splitter in each run,
 // here computed exactly for every tile boundary).  One half-wave per tile.
@@ -1726,6 +1853,18 @@ hipError_t launch_block_sort_group_table(bool pairs, Bufs kb, Bufs vb, const Blo
 }
 
 uint32_t group_run_keys(bool pairs) { return pairs ? kGroupWavesPairs * kTile : kGroupWavesKeys * kTile; }
+
+hipError_t launch_block_sort_shear_group(const uint32_t *kin, uint32_t *kout, uint64_t n, SampleSet out_smp,
+                                         hipStream_t s)
+{
+    constexpr uint32_t keys = kGroupWavesKeys * kTile;
+    RegularGroupSrc src{kin, nullptr, kout, nullptr, n, (uint32_t)((n + keys - 1) / keys), keys, out_smp};
+    if (src.ngroups == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_block_sort_shear_group<kGroupWavesKeys, RegularGroupSrc>), dim3(src.ngroups),
+                       dim3(kWave * kGroupWavesKeys), 0, s, src);
+    return hipGetLastError();
+}
 
 hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
                                    uint32_t *vout, uint64_t n, SampleSet out_smp, hipStream_t s)

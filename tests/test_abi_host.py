@@ -271,11 +271,13 @@ def test_tuning_roundtrip():
     assert bcf.sort_passes(1 << 19) == 1 + 7 and bcf.sort_passes((1 << 19) + 1) == 1 + 5
     with bcf.tuning(merge_fan_in=4):  # 128 runs -> 32 -> 8 -> 2 -> 1; 17 runs -> 5 -> 2 -> 1
         assert bcf.sort_passes(1 << 19) == 1 + 4 and bcf.sort_passes((1 << 19) + 1) == 1 + 3
-    with bcf.tuning(block_sort=3):
-        assert bcf.sort_passes(1 << 16) == 1 + 1 and bcf.sort_passes(1 << 15) == 1
+    for v in (3, 4):  # group tiles (merge rounds or the long ShearSort): runs of 32768 keys
+        with bcf.tuning(block_sort=v):
+            assert bcf.sort_passes(1 << 16) == 1 + 1 and bcf.sort_passes(1 << 15) == 1
+            assert bcf.run_keys() == 32768 and bcf.run_keys(pairs=True) == 16384
     from paper_1306_5076_amd import BcfError
 
-    for bad in ({"merge_variant": 7}, {"block_sort": 4}, {"block_sort": -1}, {"merge_fan_in": 3}):
+    for bad in ({"merge_variant": 7}, {"block_sort": 5}, {"block_sort": -1}, {"merge_fan_in": 3}):
         with pytest.raises(BcfError):
             bcf.set_tuning(**bad)
     assert bcf.get_tuning() == before

@@ -509,15 +509,17 @@ def test_merge_kernel_variants(torch_dev, bcf, mode, nt):
         _check_sorts(torch, dev, bcf)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 def test_block_sort_variants(torch_dev, bcf, variant):
     """Block sorts (wave tiles by merge rounds, wave tiles by the paper's
-    ShearSort, group tiles) against the oracle: single partial tile, exact
-    tile, ragged multi-tile, many passes, keys and stable pairs."""
+    ShearSort, group tiles by merge rounds, group tiles of keys by the paper's
+    long ShearSort over 8 waves) against the oracle: single partial tile,
+    exact tile, ragged multi-tile, partial and full groups, many passes, keys
+    and stable pairs (pairs take merge rounds under variant 4)."""
     torch, dev = torch_dev
     with bcf.tuning(block_sort=variant):
-        assert bcf.run_keys() == (32768 if variant == 3 else 4096)
-        for n in (1, 100, 4095, 4096, 4097, 3 * 4096 + 17, 40000):
+        assert bcf.run_keys() == (32768 if variant >= 3 else 4096)
+        for n in (1, 100, 4095, 4096, 4097, 3 * 4096 + 17, 32768, 40000, 5 * 32768 + 4099):
             for dist in ("uniform", "distinct16", "reverse"):
                 keys = workloads.keys_u32(dist, n, seed=n)
                 got = bcf.sort_u32(to_dev(torch, dev, keys)).cpu().numpy()

@@ -790,3 +790,86 @@ def test_merge4_items_balanced_on_random_keys():
     assert max(sizes) <= 2 * CUT_STEP
     assert np.median(sizes) > 3000
     assert packed >= 0.6 * len(sizes)
+
+
+# ---------------------------------------------- long ShearSort over NW waves
+#
+# Model of the h-wave ShearSort block sort (paper Sec. 3.1, sorting w^2 h keys
+# with h waves): regs[v, l, r] is register r of lane l of wave v.  The grid
+# has 64 rows and 64 NW columns; a lane's BLOCKED registers are its row's
+# segment in that wave, its STRIDED registers (after the in-wave transpose) a
+# column.  Rows are sorted by a register sort per segment and a bitonic
+# network of merge-splits across the waves; the sorted grid, in row-major
+# order, is moved into BLOCKED sub-tiles by a line permutation.
+
+
+def _model_rows(regs, snake):
+    nw = regs.shape[0]
+    odd = (np.arange(64) & 1).astype(bool)
+    if snake:
+        regs[:, odd, :] = ~regs[:, odd, :]
+    regs.sort(axis=2)
+    k = 1
+    while k < nw:
+        j = k
+        while j >= 1:
+            new = regs.copy()
+            for v in range(nw):
+                q = v ^ j
+                asc = (v & (2 * k)) == 0
+                keep_low = (v < q) == asc
+                b = regs[q, :, ::-1]
+                m = np.minimum(regs[v], b) if keep_low else np.maximum(regs[v], b)
+                new[v] = np.sort(m, axis=1)  # the in-lane bitonic merge
+            regs[:] = new
+            j //= 2
+        k *= 2
+    if snake:
+        regs[:, odd, :] = ~regs[:, odd, :]
+
+
+def long_shear_model(keys, nw):
+    assert keys.size == nw * 4096
+    # loaded STRIDED: wave v, lane l, register r holds position 4096 v + 64 r + l
+    regs = keys.reshape(nw, 64, 64).transpose(0, 2, 1).copy()
+    for _ in range(6):
+        _model_rows(regs, True)
+        regs = regs.transpose(0, 2, 1).copy()  # to_strided: lanes hold columns
+        regs.sort(axis=2)
+        regs = regs.transpose(0, 2, 1).copy()  # to_blocked
+    _model_rows(regs, False)
+    # grid position l * 64 NW + 64 v + r -> BLOCKED sub-tiles
+    out = np.empty_like(regs)
+    for vd in range(nw):
+        for ld in range(64):
+            line = 64 * vd + ld
+            out[vd, ld] = regs[line % nw, line // nw]
+    return out.reshape(-1)  # position 4096 v' + 64 l' + r
+
+
+@pytest.mark.parametrize("nw", [2, 8])
+def test_long_shear_model_sorts(nw):
+    rng = np.random.default_rng(nw)
+    n = nw * 4096
+    cases = [rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32),
+             rng.integers(0, 16, size=n).astype(np.uint32),
+             np.arange(n, dtype=np.uint32)[::-1].copy()]
+    padded = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+    padded[n - 5000:] = 0xFFFFFFFF  # padding of a partial group
+    cases.append(padded)
+    for _ in range(6):  # 0-1 inputs with a random number of ones
+        cases.append((rng.random(n) < rng.random()).astype(np.uint32))
+    for keys in cases:
+        assert np.array_equal(long_shear_model(keys, nw), np.sort(keys))
+
+
+def test_long_shear_line_permutation_reads_are_conflict_free():
+    """The line permutation reads word 4100 sv + 64 r + sl (sv = line mod 8,
+    sl = line div 8, line = 64 v' + l'): every 32-lane half touches 32 banks."""
+    for vd in range(8):
+        for half in (0, 32):
+            banks = set()
+            for ld in range(half, half + 32):
+                line = 64 * vd + ld
+                banks.add((4100 * (line % 8) + 64 * 5 + line // 8) % 32)
+            assert len(banks) == 32
