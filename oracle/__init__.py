@@ -50,6 +50,9 @@ def _load():
     lib.oracle_colored_prefix_sums.restype = ctypes.c_int
     lib.oracle_sort_u64.argtypes = [u64p, u64p, ctypes.c_uint64]
     lib.oracle_sort_u64.restype = ctypes.c_int
+    lib.oracle_distribute_runs.argtypes = [u32p, u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_int, u32p, u64p, u32p]
+    lib.oracle_distribute_runs.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -164,3 +167,25 @@ def colored_prefix_sums(values, colors, d):
                                           v.size, d) != 0:
         raise ValueError("colored_prefix_sums: d must be in [1, 256]")
     return out
+
+
+def distribute_runs(keys, run_offsets, P, t, pivot_buckets=False):
+    """Distribution of sorted runs into buckets by sampled splitters (Sec. 3.2).
+
+    Returns (keys rearranged by (bucket, run), piece offsets with nb*s + 1
+    entries, the P-1 splitters); nb = P, or 2P-1 with pivot buckets.
+    """
+    k = _u32(keys)
+    off = np.ascontiguousarray(np.asarray(run_offsets, dtype=np.uint64))
+    s = off.size - 1
+    nb = 2 * P - 1 if pivot_buckets else P
+    out = np.empty_like(k)
+    piece = np.empty(nb * s + 1, dtype=np.uint64)
+    spl = np.empty(max(P - 1, 1), dtype=np.uint32)
+    rc = _load().oracle_distribute_runs(_p32(k), _p64(off), s, P, t, int(bool(pivot_buckets)), _p32(out),
+                                        _p64(piece), _p32(spl))
+    if rc == -2:
+        raise ValueError("distribute_runs: bad arguments")
+    if rc != 0:
+        raise MemoryError("oracle_distribute_runs")
+    return out, piece, spl[: P - 1]

@@ -21,6 +21,10 @@
  *   - oracle_sort_u64            ascending sort of unsigned 64-bit keys.
  *   - oracle_colored_prefix_sums  per-color inclusive prefix sums (the paper's
  *                             bank-conflict example, Sec. 1.2).
+ *   - oracle_distribute_runs  the distribution of sorted runs into buckets by
+ *                             sampled splitters (Sec. 3.2, Lemma 1), optionally
+ *                             with pivot buckets for splitter-equal keys
+ *                             (BCFMergesortPB, Sec. 3.3).
  * Keys compare as unsigned 32-bit integers (the paper does not fix signedness).
  *
  * Algorithm: top-down merge sort (split in halves, sort each, merge taking the
@@ -381,4 +385,120 @@ int oracle_is_sorted_u32(const uint32_t *keys, uint64_t n)
         if (keys[i - 1] > keys[i])
             return 0;
     return 1;
+}
+
+/* ---- distribution of sorted runs into buckets (Sec. 3.2) ----------------- */
+
+/*
+ * The paper's distribution step (Sec. 3.2, "Distribution", with Lemma 1) and
+ * its pivot-bucket form for duplicate keys (Sec. 3.3, "Duplicate keys",
+ * BCFMergesortPB), in the paper's order:
+ *   1. from each nonempty run of length L take t evenly spaced candidates:
+ *      candidate j (j = 0..t-1) is the last key of the j-th of t equal chunks,
+ *      run[max(0, floor((j+1) L / t) - 1)];
+ *   2. sort the candidates into S (the top-down merge sort above);
+ *   3. take P-1 evenly spaced final splitters from S:
+ *      F[c] = S[max(0, floor((c+1) |S| / P) - 1)], c = 0..P-2;
+ *   4. bucket of a key x.  Plain: c = #{F < x}, i.e. bucket c holds
+ *      (F[c-1], F[c]] with F[-1] = -inf and F[P-1] = +inf (P buckets).
+ *      Pivot buckets (pb != 0, 2P-1 buckets): a key equal to some splitter
+ *      goes to bucket 2c+1 for the smallest c with F[c] == x, any other key to
+ *      bucket 2 #{F < x};
+ *   5. rearrange by (bucket, run): the output lists bucket 0's keys of run 0,
+ *      of run 1, ..., then bucket 1's, each piece in its run's order.
+ * piece_off gets nb*s + 1 entries: piece (b, r) starts at piece_off[b*s + r];
+ * the last entry is n.  splitters gets the P-1 final splitters (may be NULL).
+ * The key-to-bucket counts in step 4 use a binary search over the sorted
+ * splitters (the smallest index with F[i] >= x, resp. > x).
+ * Returns 0, -1 on allocation failure, -2 on bad arguments.
+ */
+static uint64_t count_less(const uint32_t *F, uint64_t m, uint32_t x)
+{
+    uint64_t lo = 0, hi = m; /* first i with F[i] >= x */
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (F[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+int oracle_distribute_runs(const uint32_t *keys, const uint64_t *off, uint32_t s, uint32_t P, uint32_t t, int pb,
+                           uint32_t *out, uint64_t *piece_off, uint32_t *splitters)
+{
+    if (s == 0 || P == 0 || t == 0 || off[0] != 0)
+        return -2;
+    for (uint32_t r = 0; r < s; r++)
+        if (off[r + 1] < off[r])
+            return -2;
+    const uint64_t n = off[s];
+    const uint64_t nb = pb ? 2 * (uint64_t)P - 1 : P;
+    uint64_t nonempty = 0;
+    for (uint32_t r = 0; r < s; r++)
+        nonempty += off[r + 1] > off[r];
+    const uint64_t m = nonempty * t;
+    uint32_t *cand = malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t *S = malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t *F = malloc((P > 1 ? P - 1 : 1) * sizeof(uint32_t));
+    uint64_t *cnt = calloc(nb * s + 1, sizeof(uint64_t));
+    uint32_t *bucket = malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!cand || !S || !F || !cnt || !bucket) {
+        free(cand), free(S), free(F), free(cnt), free(bucket);
+        return -1;
+    }
+    /* 1. candidates */
+    uint64_t k = 0;
+    for (uint32_t r = 0; r < s; r++) {
+        const uint64_t L = off[r + 1] - off[r];
+        if (L == 0)
+            continue;
+        for (uint32_t j = 0; j < t; j++) {
+            uint64_t e = ((uint64_t)(j + 1) * L) / t;
+            cand[k++] = keys[off[r] + (e ? e - 1 : 0)];
+        }
+    }
+    /* 2. sort them */
+    if (m && oracle_sort_u32(cand, S, m) != 0) {
+        free(cand), free(S), free(F), free(cnt), free(bucket);
+        return -1;
+    }
+    /* 3. final splitters */
+    for (uint32_t c = 0; c + 1 < P; c++) {
+        uint64_t e = ((uint64_t)(c + 1) * m) / P;
+        F[c] = m ? S[e ? e - 1 : 0] : 0;
+        if (splitters)
+            splitters[c] = F[c];
+    }
+    /* 4. bucket of every key, counted per (bucket, run) */
+    for (uint32_t r = 0; r < s; r++) {
+        for (uint64_t i = off[r]; i < off[r + 1]; i++) {
+            const uint32_t x = keys[i];
+            const uint64_t lt = count_less(F, P - 1, x);
+            uint64_t b;
+            if (!pb)
+                b = lt;
+            else if (lt < P - 1 && F[lt] == x)
+                b = 2 * lt + 1; /* F[lt] is the first splitter equal to x */
+            else
+                b = 2 * lt;
+            bucket[i] = (uint32_t)b;
+            cnt[b * s + r]++;
+        }
+    }
+    /* 5. piece offsets (bucket-major), then the keys in input order per piece */
+    uint64_t acc = 0;
+    for (uint64_t p = 0; p < nb * s; p++) {
+        const uint64_t c = cnt[p];
+        piece_off[p] = acc;
+        cnt[p] = acc; /* now the next free slot of piece p */
+        acc += c;
+    }
+    piece_off[nb * s] = acc;
+    for (uint32_t r = 0; r < s; r++)
+        for (uint64_t i = off[r]; i < off[r + 1]; i++)
+            out[cnt[(uint64_t)bucket[i] * s + r]++] = keys[i];
+    free(cand), free(S), free(F), free(cnt), free(bucket);
+    return 0;
 }
