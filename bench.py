@@ -175,6 +175,38 @@ def bench_u64(bcf, workloads, torch, dev, n=1 << 26, reps=5):
             "method": "two stable 32-bit pair sorts, low halves first, plus split and join passes"}
 
 
+def bench_distribution(bcf, workloads, torch, dev, runs=256, run_len=1 << 18, P=256, t=256, reps=10):
+    """The distribution step (Sec. 3.2; pivot buckets of Sec. 3.3) on 2^26 keys
+    in 256 sorted runs of 2^18 (uniform keys), P = t = 256: whole call and the
+    scatter kernel (one read and one write of every key) against HBM peak."""
+    from paper_1306_5076_amd import autotune
+
+    keys_np, off = workloads.sorted_runs([run_len] * runs, seed=1)
+    keys = torch.from_numpy(keys_np).to(dev)
+    n = keys.numel()
+    out = torch.empty_like(keys)
+    ws = bcf.Workspace(dev)
+    res = {"n": n, "runs": runs, "P": P, "t": t}
+    for pb in (False, True):
+        fn = lambda: bcf.distribute_runs(keys, off, P, t, pivot_buckets=pb, keys_out=out, workspace=ws)  # noqa: E731
+        ms = autotune.time_ms(fn, reps=reps, warmup=2)
+        bcf.profile_collect()
+        bcf.profile_enable(True)
+        for _ in range(3):
+            fn()
+        bcf.profile_enable(False)
+        st = bcf.profile_collect()
+        sc = st.get("dist_scatter")
+        rec = {"ms": round(ms, 4), "Gkeys_per_s": round(n / ms / 1e6, 3), "kernels": _kernel_table(st)}
+        if sc:
+            gbs = sc["bytes"] / (sc["total_ms"] * 1e-3) / 1e9
+            rec["scatter_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                       "avg_launch_us": round(1e3 * sc["total_ms"] / sc["launches"], 2)}
+        res["pivot_buckets" if pb else "plain"] = rec
+    return res
+
+
 def bench_pairs(bcf, workloads, torch, dev, n=1 << 28, steps=5, warmup=2):
     """2^28 stable key/value sorts (value = original index), uniform and Zipf keys."""
     from paper_1306_5076_amd import autotune
@@ -246,6 +278,8 @@ def main():
     ap.add_argument("--no-per-dist", action="store_true", help="skip the per-distribution timing")
     ap.add_argument("--quick", action="store_true",
                     help="headline only: skip the pairs, segmented and serving sections")
+    ap.add_argument("--distribution", action="store_true",
+                    help="only the distribution step at 2^26 keys in 256 runs (one JSON object)")
     ap.add_argument("--block-sort-ablation", action="store_true",
                     help="only the block-sort ablation at 2^26 keys (one JSON object)")
     ap.add_argument("--reps", type=int, default=5, help="repetitions of the ablation timings")
@@ -264,6 +298,14 @@ def main():
             file=sys.stderr,
         )
         sys.exit(2)
+    if args.distribution:
+        import torch
+
+        import paper_1306_5076_amd as bcf
+        import workloads
+
+        print(json.dumps(bench_distribution(bcf, workloads, torch, torch.device("cuda:0"))), flush=True)
+        return
     if args.block_sort_ablation:
         import torch
 
@@ -424,6 +466,8 @@ def main():
         rec["pairs_2p28"] = bench_pairs(bcf, workloads, torch, dev)
         torch.cuda.empty_cache()
         rec["u64_2p26"] = bench_u64(bcf, workloads, torch, dev)
+        torch.cuda.empty_cache()
+        rec["distribution_2p26"] = bench_distribution(bcf, workloads, torch, dev)
         torch.cuda.empty_cache()
         from paper_1306_5076_amd import cps_demo
 

@@ -184,6 +184,39 @@ bcf_status bcf_colored_prefix_sums(const uint32_t *values, const uint8_t *colors
                                    uint32_t d, int conflict_free, void *temp, uint64_t *temp_bytes,
                                    void *stream);
 
+/*
+ * Distribution of sorted runs into buckets by sampled splitters (Sec. 3.2,
+ * "Distribution", whose bucket sizes Lemma 1 bounds for distinct keys), with
+ * the optional pivot buckets of Sec. 3.3 ("Duplicate keys", BCFMergesortPB).
+ * From each nonempty run of length L, t evenly spaced candidates are taken
+ * (candidate j is the run's key at max(0, floor((j+1) L / t) - 1)); the
+ * candidates are sorted into S and the P-1 final splitters are
+ * F[c] = S[max(0, floor((c+1) |S| / P) - 1)].  Plain buckets (nb = P): bucket
+ * c holds the keys x with F[c-1] < x <= F[c].  Pivot buckets (nb = 2P-1):
+ * bucket 2c holds F[c-1] < x < F[c], bucket 2c+1 the keys equal to F[c] when
+ * F[c-1] < F[c] (equal splitters share the first one's bucket).  The output
+ * lists the pieces (bucket b, run r) in bucket-major order, each piece in its
+ * run's order; a piece is a contiguous slice of its run.
+ *   keys_in        device, n = run_offsets[s] u32; run r is [off[r], off[r+1])
+ *                  and must be nondecreasing (not checked: an unsorted run
+ *                  gives unspecified output, but no access outside the buffers)
+ *   run_offsets    HOST, s+1 entries (conventions above); s <= 2^22
+ *   P, t           1..65536 each; (#nonempty runs) * t <= 2^26; nb * s <= 2^24
+ *   pivot_buckets  0: P buckets; nonzero: 2P-1 buckets
+ *   keys_out       device, n u32; must not overlap keys_in (BCF_ERR_INVALID)
+ *   piece_offsets  device, nb*s + 1 u64: piece (b, r) starts at
+ *                  piece_offsets[b*s + r]; the last entry is n
+ *   splitters      device, P-1 u32 (0 when n == 0), or NULL
+ *   temp           as for the sorts (query with temp == NULL); s == 0 is a
+ *                  no-op
+ * Steps run on `stream`: candidates, their sort (bcf_sort_u32), splitters,
+ * piece bounds by binary search, a prefix sum over the pieces, and one
+ * scatter that reads and writes every key once.
+ */
+bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_t *run_offsets, uint32_t s, uint32_t P,
+                               uint32_t t, int pivot_buckets, uint32_t *keys_out, uint64_t *piece_offsets,
+                               uint32_t *splitters, void *temp, uint64_t *temp_bytes, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *bcf_status_string(bcf_status s);
 

@@ -19,6 +19,7 @@ _API = (
     "colored_prefix_sums",
     "sort_u64",
     "merge_runs",
+    "distribute_runs",
     "segmented_sort",
     "SegmentedPlan",
     "tile_keys",

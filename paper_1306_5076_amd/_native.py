@@ -34,6 +34,7 @@ EXPORTED = (
     "bcf_colored_prefix_sums",
     "bcf_sort_u64",
     "bcf_merge_runs",
+    "bcf_distribute_runs",
     "bcf_segmented_sort",
     "bcf_segmented_sort_pairs",
     "bcf_segmented_upload",
@@ -112,11 +113,12 @@ def load(path: str = LIB_PATH):
     lib.bcf_sort_u64.argtypes = [vp, vp, u64, vp, u64p, vp]
     lib.bcf_sort_u64.restype = ctypes.c_int
     lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
+    lib.bcf_distribute_runs.argtypes = [vp, u64p, u32, u32, u32, ctypes.c_int, vp, vp, vp, vp, u64p, vp]
     lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_upload.argtypes = [u64p, u32, ctypes.c_int, vp, u64p, vp]
     lib.bcf_segmented_execute.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
-    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_segmented_sort",
+    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_distribute_runs", "bcf_segmented_sort",
               "bcf_segmented_sort_pairs", "bcf_segmented_upload", "bcf_segmented_execute"):
         getattr(lib, f).restype = ctypes.c_int
     lib.bcf_status_string.argtypes = [ctypes.c_int]

@@ -28,6 +28,7 @@ __all__ = [
     "colored_prefix_sums",
     "sort_u64",
     "merge_runs",
+    "distribute_runs",
     "segmented_sort",
     "SegmentedPlan",
     "tile_keys",
@@ -304,6 +305,43 @@ def merge_runs(keys, run_offsets, vals=None, keys_out=None, vals_out=None, strea
             ),
         )
     return (keys_out, vals_out) if vals is not None else keys_out
+
+
+def distribute_runs(keys, run_offsets, P, t, pivot_buckets=False, keys_out=None, stream=None, workspace=None):
+    """Distribute the sorted runs [off[r], off[r+1]) of ``keys`` into buckets
+    by P-1 sampled splitters (t candidates per run), with 2P-1 pivot buckets
+    when ``pivot_buckets``.
+
+    ``run_offsets`` is a host sequence of s+1 offsets.  Returns
+    ``(keys_out, piece_offsets, splitters)``: the keys by (bucket, run), the
+    nb*s + 1 piece offsets (int64 on the device; piece (b, r) at b*s + r) and
+    the P-1 splitters (uint32 on the device).
+    """
+    lib = load()
+    _check_tensor(keys, "keys")
+    n = keys.numel()
+    off = _offsets(run_offsets, n)
+    s = off.size - 1
+    nb = 2 * P - 1 if pivot_buckets else P
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    pieces = torch.empty(nb * s + 1, dtype=torch.int64, device=keys.device)
+    spl = torch.empty(max(P - 1, 1), dtype=torch.uint32, device=keys.device)
+    stream, sh = _stream(stream, keys.device)
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    need = ctypes.c_uint64(0)
+    check("bcf_distribute_runs", lib.bcf_distribute_runs(None, offp, s, P, t, int(bool(pivot_buckets)), None, None,
+                                                         None, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if s:
+        check(
+            "bcf_distribute_runs",
+            lib.bcf_distribute_runs(
+                _ptr(keys) or ctypes.c_void_p(1), offp, s, P, t, int(bool(pivot_buckets)),
+                _ptr(keys_out) or ctypes.c_void_p(1), _ptr(pieces), _ptr(spl) if P > 1 else None,
+                _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh,
+            ),
+        )
+    return keys_out, pieces, spl[: P - 1]
 
 
 def segmented_sort(keys, seg_offsets, vals=None, keys_out=None, vals_out=None, stream=None, workspace=None,

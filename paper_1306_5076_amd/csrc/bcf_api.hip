@@ -606,6 +606,13 @@ Tuning tuning()
     std::lock_guard<std::mutex> g(g_tune_mu);
     return tuning_locked();
 }
+
+// Host services for the other translation units of the library (the
+// distribution step): descriptor upload through the pinned staging buffers,
+// and a profiling scope around one launch (recorded only while profiling is on).
+bcf_status upload_host(void *dst, const void *src, size_t bytes, hipStream_t s) { return upload(dst, src, bytes, s); }
+void *prof_begin(const char *name, hipStream_t s, double bytes) { return new ProfScope(name, s, bytes); }
+void prof_end(void *scope) { delete static_cast<ProfScope *>(scope); }
 }  // namespace bcf
 
 // ======================================================================= ABI

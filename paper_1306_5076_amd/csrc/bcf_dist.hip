@@ -1,0 +1,337 @@
+// bcf_dist.hip -- distribution of sorted runs into buckets by sampled
+// splitters (paper Sec. 3.2, "Distribution", after Aggarwal and Vitter; the
+// bucket bound is Lemma 1), and the pivot-bucket form of Sec. 3.3 ("Duplicate
+// keys", BCFMergesortPB) in which keys equal to a splitter get a bucket of
+// their own.
+//
+// Steps, each its own launch on the caller's stream:
+//   1. k_dist_candidates  t evenly spaced candidates per nonempty run (the last
+//                         key of each of t equal chunks of the run);
+//   2. bcf_sort_u32       the candidates sorted (the library's own sort);
+//   3. k_dist_splitters   P-1 evenly spaced final splitters from the sorted
+//                         candidates (the last key of each of P equal chunks);
+//   4. k_dist_pieces      per (bucket, run) piece its length and source start,
+//                         from binary searches of the splitters in the run
+//                         (upper bounds; pivot buckets add lower bounds);
+//   5. k_dist_scan        exclusive prefix over the pieces in bucket-major
+//                         order: the output offset of every piece;
+//   6. k_dist_scatter     every output tile of 4096 keys walks the pieces it
+//                         overlaps and copies them: reads contiguous within a
+//                         piece, writes contiguous, one read and one write of
+//                         every key (the HBM-bound step).
+// The paper computes the splitter ranks by parallel scans and then sorts the
+// subsequences by bucket and sequence number; since the runs are sorted, a
+// piece is a contiguous slice of its run, so a binary search per piece end and
+// a prefix sum replace both.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "bcf.h"
+
+namespace bcf {
+bcf_status upload_host(void *dst, const void *src, size_t bytes, hipStream_t s);
+void *prof_begin(const char *name, hipStream_t s, double bytes);
+void prof_end(void *scope);
+}  // namespace bcf
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kScanThreads = 1024;
+constexpr uint32_t kOutTile = 4096;  // output keys per scatter work-group
+constexpr uint32_t kMaxP = 1u << 16, kMaxT = 1u << 16;
+constexpr uint64_t kMaxSamples = 1ull << 26, kMaxPieces = 1ull << 24, kMaxRuns = 1ull << 22;
+
+uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
+
+// first index i in [0, L) with run[i] > x (L if none)
+__device__ __forceinline__ uint64_t upper_bound(const uint32_t *run, uint64_t L, uint32_t x)
+{
+    uint64_t lo = 0, hi = L;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (run[mid] <= x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// first index i in [0, L) with run[i] >= x (L if none)
+__device__ __forceinline__ uint64_t lower_bound(const uint32_t *run, uint64_t L, uint32_t x)
+{
+    uint64_t lo = 0, hi = L;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (run[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dist_candidates(const uint32_t *__restrict__ keys,
+                                                              const uint64_t *__restrict__ off,
+                                                              const uint32_t *__restrict__ nonempty, uint32_t t,
+                                                              uint64_t m, uint32_t *__restrict__ cand)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= m)
+        return;
+    const uint32_t r = nonempty[i / t];
+    const uint64_t j = i % t;
+    const uint64_t L = off[r + 1] - off[r];
+    const uint64_t e = (j + 1) * L / t;  // end of chunk j
+    cand[i] = keys[off[r] + (e ? e - 1 : 0)];
+}
+
+__global__ __launch_bounds__(kThreads) void k_dist_splitters(const uint32_t *__restrict__ S, uint64_t m, uint32_t P,
+                                                             uint32_t *__restrict__ F)
+{
+    const uint32_t c = blockIdx.x * kThreads + threadIdx.x;
+    if (c + 1 >= P)
+        return;
+    const uint64_t e = (uint64_t)(c + 1) * m / P;
+    F[c] = m ? S[e ? e - 1 : 0] : 0u;
+}
+
+// End (exclusive, within run r) of the first q+1 buckets.  Plain buckets:
+// cut q = upper_bound(F[q]), bucket q = (F[q-1], F[q]].  Pivot buckets (2P-1
+// of them, bucket 2c = (F[c-1], F[c]), bucket 2c+1 = {F[c]}):
+// cut 2c = max(lower_bound(F[c]), upper_bound(F[c-1])) and cut 2c+1 =
+// upper_bound(F[c]); the max gives an empty pivot bucket to a splitter equal
+// to its predecessor, whose keys are already in the predecessor's bucket.
+__device__ __forceinline__ uint64_t cut(const uint32_t *run, uint64_t L, const uint32_t *F, uint32_t q, uint32_t nb,
+                                        int pb)
+{
+    if (q + 1 >= nb)
+        return L;
+    if (!pb)
+        return upper_bound(run, L, F[q]);
+    const uint32_t c = q / 2;
+    if (q & 1)
+        return upper_bound(run, L, F[c]);
+    const uint64_t lb = lower_bound(run, L, F[c]);
+    return c ? max(lb, upper_bound(run, L, F[c - 1])) : lb;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dist_pieces(const uint32_t *__restrict__ keys,
+                                                          const uint64_t *__restrict__ off, uint32_t s,
+                                                          const uint32_t *__restrict__ F, uint32_t nb, int pb,
+                                                          uint64_t *__restrict__ len, uint64_t *__restrict__ src)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * kThreads + threadIdx.x;  // piece b*s + r
+    if (p >= (uint64_t)nb * s)
+        return;
+    const uint32_t b = (uint32_t)(p / s), r = (uint32_t)(p % s);
+    const uint32_t *run = keys + off[r];
+    const uint64_t L = off[r + 1] - off[r];
+    const uint64_t lo = b ? cut(run, L, F, b - 1, nb, pb) : 0;
+    const uint64_t hi = cut(run, L, F, b, nb, pb);
+    len[p] = hi - lo;
+    src[p] = off[r] + lo;
+}
+
+// Exclusive prefix of len[0, np) into out[0, np], one work-group: each thread
+// sums a contiguous chunk, the chunk sums are scanned in LDS, then each
+// thread writes its chunk's prefixes.
+__global__ __launch_bounds__(kScanThreads) void k_dist_scan(const uint64_t *__restrict__ len, uint64_t np,
+                                                            uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t part[kScanThreads];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t chunk = (np + kScanThreads - 1) / kScanThreads;
+    const uint64_t a = min(np, tid * chunk), e = min(np, a + chunk);
+    uint64_t sum = 0;
+    for (uint64_t i = a; i < e; ++i)
+        sum += len[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < kScanThreads; d *= 2) {  // inclusive Hillis-Steele scan
+        const uint64_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint64_t acc = part[tid] - sum;  // exclusive prefix of this chunk
+    for (uint64_t i = a; i < e; ++i) {
+        out[i] = acc;
+        acc += len[i];
+    }
+    if (tid == kScanThreads - 1)
+        out[np] = part[tid];
+}
+
+// largest p in [0, np) with pos[p] <= x, for x < pos[np]
+__device__ __forceinline__ uint64_t piece_of(const uint64_t *pos, uint64_t np, uint64_t x)
+{
+    uint64_t lo = 0, hi = np;  // pos[lo] <= x < pos[hi]
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (pos[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Output tile [o0, o1) of kOutTile keys: starting from the piece holding o0,
+// copy each overlapped piece's share.  For sorted runs the piece found for a
+// position below n holds it (pos[p] <= o < pos[p + 1]), so every step copies
+// at least one key.  An unsorted run can make the cuts non-monotone; then the
+// walk stops early (unspecified output) but never reads outside the input.
+__global__ __launch_bounds__(kThreads) void k_dist_scatter(const uint32_t *__restrict__ keys,
+                                                           const uint64_t *__restrict__ pos,
+                                                           const uint64_t *__restrict__ src, uint64_t np, uint64_t n,
+                                                           uint32_t *__restrict__ out)
+{
+    const uint64_t o0 = (uint64_t)blockIdx.x * kOutTile;
+    const uint64_t o1 = min(n, o0 + kOutTile);
+    uint64_t o = o0;
+    while (o < o1) {
+        const uint64_t p = piece_of(pos, np, o);
+        const uint64_t pp = pos[p], pn = pos[p + 1];
+        if (pp > o || pn <= o)
+            break;  // offsets not monotone: only after a run that was not sorted
+        const uint64_t pend = min(pn, o1);
+        const uint64_t cnt = pend - o;
+        const uint64_t f0 = src[p] + (o - pp);
+        if (f0 > n || cnt > n - f0)
+            break;  // likewise: never read past the input
+        const uint32_t *from = keys + f0;
+        uint32_t *to = out + o;
+        for (uint64_t i = threadIdx.x; i < cnt; i += 4 * kThreads) {
+            uint32_t v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t j = i + (uint64_t)k * kThreads;
+                v[k] = j < cnt ? from[j] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t j = i + (uint64_t)k * kThreads;
+                if (j < cnt)
+                    to[j] = v[k];
+            }
+        }
+        o = pend;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dist_zero(uint64_t *__restrict__ a, uint64_t na, uint32_t *__restrict__ b,
+                                                        uint64_t nbw)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < na)
+        a[i] = 0;
+    if (b && i < nbw)
+        b[i] = 0;
+}
+
+uint32_t blocks_for(uint64_t work) { return (uint32_t)((work + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+extern "C" bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_t *run_offsets, uint32_t s,
+                                          uint32_t P, uint32_t t, int pivot_buckets, uint32_t *keys_out,
+                                          uint64_t *piece_offsets, uint32_t *splitters, void *temp,
+                                          uint64_t *temp_bytes, void *stream)
+{
+    if (!temp_bytes)
+        return BCF_ERR_INVALID;
+    if (s == 0) {
+        if (!temp)
+            *temp_bytes = 0;
+        return BCF_OK;
+    }
+    if (!run_offsets || P == 0 || P > kMaxP || t == 0 || t > kMaxT || s > kMaxRuns)
+        return BCF_ERR_INVALID;
+    if (run_offsets[0] != 0)
+        return BCF_ERR_INVALID;
+    uint64_t nonempty = 0;
+    for (uint32_t r = 0; r < s; ++r) {
+        if (run_offsets[r + 1] < run_offsets[r])
+            return BCF_ERR_INVALID;
+        nonempty += run_offsets[r + 1] > run_offsets[r];
+    }
+    const uint64_t n = run_offsets[s];
+    const int pb = pivot_buckets ? 1 : 0;
+    const uint32_t nb = pb ? 2 * P - 1 : P;
+    const uint64_t m = nonempty * t, np = (uint64_t)nb * s;
+    if (n > 0xFFFFFFFFull || m > kMaxSamples || np > kMaxPieces)
+        return BCF_ERR_INVALID;
+    uint64_t sort_need = 0;
+    bcf_status st = bcf_sort_u32(nullptr, nullptr, m, nullptr, &sort_need, stream);
+    if (st != BCF_OK)
+        return st;
+    // temp: run offsets | nonempty run ids | candidates | sorted candidates |
+    //       splitters | piece lengths | piece sources | the candidate sort's temp
+    const uint64_t b_off = align256((uint64_t(s) + 1) * 8), b_nz = align256(std::max<uint64_t>(nonempty, 1) * 4);
+    const uint64_t b_cand = align256(std::max<uint64_t>(m, 1) * 4), b_spl = align256(std::max<uint32_t>(P, 2) * 4);
+    const uint64_t b_piece = align256(np * 8);
+    const uint64_t need = b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece + sort_need;
+    if (!temp) {
+        *temp_bytes = need;
+        return BCF_OK;
+    }
+    if (!keys_in || !keys_out || !piece_offsets)
+        return BCF_ERR_INVALID;
+    if (n && keys_in < keys_out + n && keys_out < keys_in + n)
+        return BCF_ERR_INVALID;  // the scatter cannot run in place
+    if (*temp_bytes < need)
+        return BCF_ERR_TEMP_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    char *tp = static_cast<char *>(temp);
+    uint64_t *off_d = reinterpret_cast<uint64_t *>(tp);
+    uint32_t *nz_d = reinterpret_cast<uint32_t *>(tp + b_off);
+    uint32_t *cand = reinterpret_cast<uint32_t *>(tp + b_off + b_nz);
+    uint32_t *S = reinterpret_cast<uint32_t *>(tp + b_off + b_nz + b_cand);
+    uint32_t *F_int = reinterpret_cast<uint32_t *>(tp + b_off + b_nz + 2 * b_cand);
+    uint64_t *len = reinterpret_cast<uint64_t *>(tp + b_off + b_nz + 2 * b_cand + b_spl);
+    uint64_t *srcp = reinterpret_cast<uint64_t *>(tp + b_off + b_nz + 2 * b_cand + b_spl + b_piece);
+    void *sort_temp = tp + b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece;
+    uint32_t *F = splitters ? splitters : F_int;
+    if (n == 0) {  // no keys: every piece empty, splitters 0
+        const uint64_t w = std::max<uint64_t>(np + 1, P - 1);
+        hipLaunchKernelGGL(k_dist_zero, dim3(blocks_for(w)), dim3(kThreads), 0, hs, piece_offsets, np + 1,
+                           P > 1 ? F : nullptr, (uint64_t)(P - 1));
+        return hipGetLastError() == hipSuccess ? BCF_OK : BCF_ERR_DEVICE;
+    }
+    std::vector<uint32_t> nz;
+    nz.reserve(nonempty);
+    for (uint32_t r = 0; r < s; ++r)
+        if (run_offsets[r + 1] > run_offsets[r])
+            nz.push_back(r);
+    if ((st = bcf::upload_host(off_d, run_offsets, (uint64_t(s) + 1) * 8, hs)) != BCF_OK)
+        return st;
+    if ((st = bcf::upload_host(nz_d, nz.data(), nz.size() * 4, hs)) != BCF_OK)
+        return st;
+    hipLaunchKernelGGL(k_dist_candidates, dim3(blocks_for(m)), dim3(kThreads), 0, hs, keys_in, off_d, nz_d, t, m, cand);
+    if (hipGetLastError() != hipSuccess)
+        return BCF_ERR_DEVICE;
+    uint64_t sb = sort_need;
+    if ((st = bcf_sort_u32(cand, S, m, sort_temp, &sb, stream)) != BCF_OK)
+        return st;
+    if (P > 1)
+        hipLaunchKernelGGL(k_dist_splitters, dim3(blocks_for(P - 1)), dim3(kThreads), 0, hs, S, m, P, F);
+    {
+        void *ps = bcf::prof_begin("dist_pieces", hs, 0.0);
+        hipLaunchKernelGGL(k_dist_pieces, dim3(blocks_for(np)), dim3(kThreads), 0, hs, keys_in, off_d, s, F, nb, pb,
+                           len, srcp);
+        bcf::prof_end(ps);
+    }
+    hipLaunchKernelGGL(k_dist_scan, dim3(1), dim3(kScanThreads), 0, hs, len, np, piece_offsets);
+    {
+        void *ps = bcf::prof_begin("dist_scatter", hs, 8.0 * n);
+        hipLaunchKernelGGL(k_dist_scatter, dim3((uint32_t)((n + kOutTile - 1) / kOutTile)), dim3(kThreads), 0, hs,
+                           keys_in, piece_offsets, srcp, np, n, keys_out);
+        bcf::prof_end(ps);
+    }
+    return hipGetLastError() == hipSuccess ? BCF_OK : BCF_ERR_DEVICE;
+}

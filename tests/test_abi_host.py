@@ -281,3 +281,31 @@ def test_tuning_roundtrip():
         with pytest.raises(BcfError):
             bcf.set_tuning(**bad)
     assert bcf.get_tuning() == before
+
+
+def test_distribute_runs_validation_and_query(lib):
+    need = ctypes.c_uint64(0)
+    q = lambda p, s, P, t, pb=0: lib.bcf_distribute_runs(None, p, s, P, t, pb, None, None, None, None,  # noqa: E731
+                                                           ctypes.byref(need), None)
+    a, p = _offs([0, 5, 3])  # decreasing offset
+    assert q(p, 2, 4, 4) == 1
+    a, p = _offs([1, 5])  # off[0] != 0
+    assert q(p, 1, 4, 4) == 1
+    a, p = _offs([0, 100, 300])
+    assert q(p, 2, 0, 4) == 1 and q(p, 2, 4, 0) == 1  # P, t >= 1
+    assert q(p, 2, (1 << 16) + 1, 4) == 1 and q(p, 2, 4, (1 << 16) + 1) == 1
+    assert q(p, 2, 1 << 16, 1 << 16) == 0  # 2 runs x 65536 candidates
+    assert q(p, 2, 16, 16) == 0 and need.value >= 2 * 16 * 2 * 8
+    small = need.value
+    assert q(p, 2, 16, 16, 1) == 0 and need.value > small  # 31 buckets' pieces
+    a, p = _offs(list(range(0, 1025)))  # 1024 one-key runs
+    assert q(p, 1024, 1 << 16, 1 << 10) == 1  # 1024 * 65536 pieces > 2^24
+    # s == 0 is a no-op
+    assert lib.bcf_distribute_runs(None, None, 0, 4, 4, 0, None, None, None, None, ctypes.byref(need), None) == 0
+    assert need.value == 0
+    # in place is refused before any launch
+    a, p = _offs([0, 64])
+    buf = ctypes.c_void_p(0x100000)
+    tb = ctypes.c_uint64(1 << 30)
+    assert lib.bcf_distribute_runs(buf, p, 1, 4, 4, 0, buf, ctypes.c_void_p(0x200000), None, ctypes.c_void_p(0x300000),
+                                   ctypes.byref(tb), None) == 1
