@@ -52,6 +52,7 @@ def short_name(name: str) -> str:
     name = name.strip()
     if name.startswith("void "):
         name = name[5:]
+    name = name.replace("(anonymous namespace)::", "")
     depth = 0
     for i, ch in enumerate(name):  # cut at the first '(' outside template brackets
         if ch == "<":

@@ -13,8 +13,11 @@
 //   4. k_dist_pieces      per (bucket, run) piece its length and source start,
 //                         from binary searches of the splitters in the run
 //                         (upper bounds; pivot buckets add lower bounds);
-//   5. k_dist_scan        exclusive prefix over the pieces in bucket-major
-//                         order: the output offset of every piece;
+//   5. k_dist_block_sums, k_dist_scan, k_dist_offsets
+//                         exclusive prefix over the pieces in bucket-major
+//                         order (block sums, their scan, the scan inside each
+//                         block): the output offset of every piece, and for
+//                         each output tile the piece holding its first key;
 //   6. k_dist_scatter     every output tile of 4096 keys walks the pieces it
 //                         overlaps and copies them: reads contiguous within a
 //                         piece, writes contiguous, one read and one write of
@@ -42,6 +45,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kScanThreads = 1024;
 constexpr uint32_t kOutTile = 4096;  // output keys per scatter work-group
+constexpr uint32_t kScanBlock = 4096;  // pieces per block of the offset scan
 constexpr uint32_t kMaxP = 1u << 16, kMaxT = 1u << 16;
 constexpr uint64_t kMaxSamples = 1ull << 26, kMaxPieces = 1ull << 24, kMaxRuns = 1ull << 22;
 
@@ -167,10 +171,10 @@ __global__ __launch_bounds__(kScanThreads) void k_dist_scan(const uint64_t *__re
         out[np] = part[tid];
 }
 
-// largest p in [0, np) with pos[p] <= x, for x < pos[np]
-__device__ __forceinline__ uint64_t piece_of(const uint64_t *pos, uint64_t np, uint64_t x)
+// largest p in [lo, np) with pos[p] <= x, for x < pos[np] (lo if none)
+__device__ __forceinline__ uint64_t piece_of(const uint64_t *pos, uint64_t lo, uint64_t np, uint64_t x)
 {
-    uint64_t lo = 0, hi = np;  // pos[lo] <= x < pos[hi]
+    uint64_t hi = np;  // pos[lo] <= x < pos[hi] when the offsets are monotone
     while (hi - lo > 1) {
         const uint64_t mid = lo + (hi - lo) / 2;
         if (pos[mid] <= x)
@@ -181,24 +185,93 @@ __device__ __forceinline__ uint64_t piece_of(const uint64_t *pos, uint64_t np, u
     return lo;
 }
 
-// Output tile [o0, o1) of kOutTile keys: starting from the piece holding o0,
-// copy each overlapped piece's share.  For sorted runs the piece found for a
-// position below n holds it (pos[p] <= o < pos[p + 1]), so every step copies
-// at least one key.  An unsorted run can make the cuts non-monotone; then the
-// walk stops early (unspecified output) but never reads outside the input.
+// Sum of the piece lengths of each block of kScanBlock pieces (coalesced).
+__global__ __launch_bounds__(kThreads) void k_dist_block_sums(const uint64_t *__restrict__ len, uint64_t np,
+                                                              uint64_t *__restrict__ bsum)
+{
+    __shared__ uint64_t red[kThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
+    uint64_t sum = 0;
+    for (uint32_t k = 0; k < kScanBlock / kThreads; ++k) {
+        const uint64_t i = base + threadIdx.x + (uint64_t)k * kThreads;
+        sum += i < np ? len[i] : 0;
+    }
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t d = kThreads / 2; d > 0; d /= 2) {
+        if (threadIdx.x < d)
+            red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        bsum[blockIdx.x] = red[0];
+}
+
+// Output offsets of the pieces of one block (its exclusive prefix boff[b] plus
+// the scan inside the block: each thread takes kScanBlock / kThreads
+// consecutive pieces), and for every output tile whose first key a piece
+// holds, that piece's index in tile_first.
+__global__ __launch_bounds__(kThreads) void k_dist_offsets(const uint64_t *__restrict__ len, uint64_t np,
+                                                           const uint64_t *__restrict__ boff, uint64_t nblk,
+                                                           uint64_t ntiles, uint64_t *__restrict__ pos,
+                                                           uint32_t *__restrict__ tile_first)
+{
+    constexpr uint32_t kPer = kScanBlock / kThreads;
+    __shared__ uint64_t part[kThreads];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t a = min(np, (uint64_t)blockIdx.x * kScanBlock + (uint64_t)tid * kPer), e = min(np, a + kPer);
+    uint64_t sum = 0;
+    for (uint64_t i = a; i < e; ++i)
+        sum += len[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < kThreads; d *= 2) {  // inclusive Hillis-Steele scan
+        const uint64_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint64_t acc = boff[blockIdx.x] + part[tid] - sum;
+    for (uint64_t i = a; i < e; ++i) {
+        const uint64_t l = len[i];
+        pos[i] = acc;
+        if (l) {  // tiles T with acc <= T * kOutTile < acc + l start in piece i
+            for (uint64_t T = (acc + kOutTile - 1) / kOutTile; T < ntiles && T * kOutTile < acc + l; ++T)
+                tile_first[T] = (uint32_t)i;
+        }
+        acc += l;
+    }
+    if (blockIdx.x == 0 && tid == 0)
+        pos[np] = boff[nblk];
+}
+
+// Output tile [o0, o1) of kOutTile keys: starting from the piece holding o0
+// (tile_first), copy each overlapped piece's share; the next piece is p + 1
+// unless that one is empty, then a binary search skips the empty ones.  For
+// sorted runs the piece reached for a position o below n holds it
+// (pos[p] <= o < pos[p + 1]), so every copy moves at least one key.  An
+// unsorted run can make the cuts non-monotone; then the walk stops early
+// (unspecified output) but never reads outside the input.
 __global__ __launch_bounds__(kThreads) void k_dist_scatter(const uint32_t *__restrict__ keys,
                                                            const uint64_t *__restrict__ pos,
-                                                           const uint64_t *__restrict__ src, uint64_t np, uint64_t n,
-                                                           uint32_t *__restrict__ out)
+                                                           const uint64_t *__restrict__ src,
+                                                           const uint32_t *__restrict__ tile_first, uint64_t np,
+                                                           uint64_t n, uint32_t *__restrict__ out)
 {
     const uint64_t o0 = (uint64_t)blockIdx.x * kOutTile;
     const uint64_t o1 = min(n, o0 + kOutTile);
     uint64_t o = o0;
-    while (o < o1) {
-        const uint64_t p = piece_of(pos, np, o);
+    uint64_t p = tile_first[blockIdx.x];
+    while (o < o1 && p < np) {
         const uint64_t pp = pos[p], pn = pos[p + 1];
-        if (pp > o || pn <= o)
-            break;  // offsets not monotone: only after a run that was not sorted
+        if (pn <= o) {  // piece p ends before o
+            p = (p + 1 < np && pos[p + 2] > o) ? p + 1 : piece_of(pos, p + 1, np, o);
+            if (p < np && pos[p + 1] <= o)
+                break;  // offsets not monotone: only after a run that was not sorted
+            continue;
+        }
+        if (pp > o)
+            break;  // likewise
         const uint64_t pend = min(pn, o1);
         const uint64_t cnt = pend - o;
         const uint64_t f0 = src[p] + (o - pp);
@@ -221,6 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_dist_scatter(const uint32_t *__res
             }
         }
         o = pend;
+        ++p;
     }
 }
 
@@ -275,7 +349,9 @@ extern "C" bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_
     const uint64_t b_off = align256((uint64_t(s) + 1) * 8), b_nz = align256(std::max<uint64_t>(nonempty, 1) * 4);
     const uint64_t b_cand = align256(std::max<uint64_t>(m, 1) * 4), b_spl = align256(std::max<uint32_t>(P, 2) * 4);
     const uint64_t b_piece = align256(np * 8);
-    const uint64_t need = b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece + sort_need;
+    const uint64_t nblk = (np + kScanBlock - 1) / kScanBlock, ntiles = (n + kOutTile - 1) / kOutTile;
+    const uint64_t b_blk = align256((nblk + 1) * 8), b_tiles = align256(std::max<uint64_t>(ntiles, 1) * 4);
+    const uint64_t need = b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece + 2 * b_blk + b_tiles + sort_need;
     if (!temp) {
         *temp_bytes = need;
         return BCF_OK;
@@ -295,7 +371,11 @@ extern "C" bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_
     uint32_t *F_int = reinterpret_cast<uint32_t *>(tp + b_off + b_nz + 2 * b_cand);
     uint64_t *len = reinterpret_cast<uint64_t *>(tp + b_off + b_nz + 2 * b_cand + b_spl);
     uint64_t *srcp = reinterpret_cast<uint64_t *>(tp + b_off + b_nz + 2 * b_cand + b_spl + b_piece);
-    void *sort_temp = tp + b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece;
+    char *tail = tp + b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece;
+    uint64_t *bsum = reinterpret_cast<uint64_t *>(tail);
+    uint64_t *boff = reinterpret_cast<uint64_t *>(tail + b_blk);
+    uint32_t *tile_first = reinterpret_cast<uint32_t *>(tail + 2 * b_blk);
+    void *sort_temp = tail + 2 * b_blk + b_tiles;
     uint32_t *F = splitters ? splitters : F_int;
     if (n == 0) {  // no keys: every piece empty, splitters 0
         const uint64_t w = std::max<uint64_t>(np + 1, P - 1);
@@ -326,11 +406,14 @@ extern "C" bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_
                            len, srcp);
         bcf::prof_end(ps);
     }
-    hipLaunchKernelGGL(k_dist_scan, dim3(1), dim3(kScanThreads), 0, hs, len, np, piece_offsets);
+    hipLaunchKernelGGL(k_dist_block_sums, dim3((uint32_t)nblk), dim3(kThreads), 0, hs, len, np, bsum);
+    hipLaunchKernelGGL(k_dist_scan, dim3(1), dim3(kScanThreads), 0, hs, bsum, nblk, boff);
+    hipLaunchKernelGGL(k_dist_offsets, dim3((uint32_t)nblk), dim3(kThreads), 0, hs, len, np, boff, nblk, ntiles,
+                       piece_offsets, tile_first);
     {
         void *ps = bcf::prof_begin("dist_scatter", hs, 8.0 * n);
-        hipLaunchKernelGGL(k_dist_scatter, dim3((uint32_t)((n + kOutTile - 1) / kOutTile)), dim3(kThreads), 0, hs,
-                           keys_in, piece_offsets, srcp, np, n, keys_out);
+        hipLaunchKernelGGL(k_dist_scatter, dim3((uint32_t)ntiles), dim3(kThreads), 0, hs, keys_in, piece_offsets,
+                           srcp, tile_first, np, n, keys_out);
         bcf::prof_end(ps);
     }
     return hipGetLastError() == hipSuccess ? BCF_OK : BCF_ERR_DEVICE;
