@@ -10,9 +10,9 @@
 //   2. bcf_sort_u32       the candidates sorted (the library's own sort);
 //   3. k_dist_splitters   P-1 evenly spaced final splitters from the sorted
 //                         candidates (the last key of each of P equal chunks);
-//   4. k_dist_pieces      per (bucket, run) piece its length and source start,
-//                         from binary searches of the splitters in the run
-//                         (upper bounds; pivot buckets add lower bounds);
+//   4. k_dist_bounds      upper bound of every splitter in every run (pivot
+//                         buckets: lower bounds too), 16 lanes per search;
+//      k_dist_pieces      per (bucket, run) piece its length and source start;
 //   5. k_dist_block_sums, k_dist_scan, k_dist_offsets
 //                         exclusive prefix over the pieces in bucket-major
 //                         order (block sums, their scan, the scan inside each
@@ -51,34 +51,6 @@ constexpr uint64_t kMaxSamples = 1ull << 26, kMaxPieces = 1ull << 24, kMaxRuns =
 
 uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
 
-// first index i in [0, L) with run[i] > x (L if none)
-__device__ __forceinline__ uint64_t upper_bound(const uint32_t *run, uint64_t L, uint32_t x)
-{
-    uint64_t lo = 0, hi = L;
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (run[mid] <= x)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// first index i in [0, L) with run[i] >= x (L if none)
-__device__ __forceinline__ uint64_t lower_bound(const uint32_t *run, uint64_t L, uint32_t x)
-{
-    uint64_t lo = 0, hi = L;
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (run[mid] < x)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(kThreads) void k_dist_candidates(const uint32_t *__restrict__ keys,
                                                               const uint64_t *__restrict__ off,
                                                               const uint32_t *__restrict__ nonempty, uint32_t t,
@@ -104,39 +76,80 @@ __global__ __launch_bounds__(kThreads) void k_dist_splitters(const uint32_t *__r
     F[c] = m ? S[e ? e - 1 : 0] : 0u;
 }
 
-// End (exclusive, within run r) of the first q+1 buckets.  Plain buckets:
-// cut q = upper_bound(F[q]), bucket q = (F[q-1], F[q]].  Pivot buckets (2P-1
-// of them, bucket 2c = (F[c-1], F[c]), bucket 2c+1 = {F[c]}):
-// cut 2c = max(lower_bound(F[c]), upper_bound(F[c-1])) and cut 2c+1 =
-// upper_bound(F[c]); the max gives an empty pivot bucket to a splitter equal
-// to its predecessor, whose keys are already in the predecessor's bucket.
-__device__ __forceinline__ uint64_t cut(const uint32_t *run, uint64_t L, const uint32_t *F, uint32_t q, uint32_t nb,
-                                        int pb)
+// Bounds of every splitter in every run: ub[c*s + r] = the first index of run
+// r with a key > F[c], and (pivot buckets) lb[c*s + r] = the first index with
+// a key >= F[c].  Each 16-lane group of a wave runs one search, narrowing the
+// answer's bracket 16-fold per round with 16 probes (five rounds for a run of
+// 2^18 keys): few dependent loads, and the probes of the first rounds are
+// shared by all splitters of a run in the cache.
+constexpr uint32_t kSearchLanes = 16;
+
+__global__ __launch_bounds__(kThreads) void k_dist_bounds(const uint32_t *__restrict__ keys,
+                                                          const uint64_t *__restrict__ off, uint32_t s,
+                                                          const uint32_t *__restrict__ F, uint32_t nspl, int pb,
+                                                          uint32_t *__restrict__ ub, uint32_t *__restrict__ lb)
+{
+    const uint32_t lane = threadIdx.x & 63, k = lane % kSearchLanes, shift = lane - k;
+    const uint64_t task = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) / kSearchLanes;
+    const uint64_t per = (uint64_t)nspl * s;
+    const bool have = task < (pb ? 2 * per : per);
+    const bool upper = task < per;
+    const uint64_t cr = have ? (upper ? task : task - per) : 0;
+    const uint32_t c = (uint32_t)(cr / s), r = (uint32_t)(cr % s);
+    const uint32_t *run = keys + (have ? off[r] : 0);
+    const uint32_t x = have ? F[c] : 0u;
+    uint64_t lo = 0, hi = have ? off[r + 1] - off[r] : 0;  // answer in [lo, hi]
+    while (__ballot(hi - lo > kSearchLanes) != 0) {
+        const bool act = hi - lo > kSearchLanes;
+        const uint64_t step = act ? (hi - lo + kSearchLanes - 1) / kSearchLanes : 0;
+        const uint64_t q = lo + k * step;
+        const bool before = act && q < hi && (upper ? run[q] <= x : run[q] < x);  // the answer lies after q
+        const uint32_t cnt = (uint32_t)__popcll((__ballot(before) >> shift) & 0xFFFFull);
+        if (act) {  // probes 0..cnt-1 lie before the answer, probe cnt (if any) not
+            const uint64_t nlo = cnt ? lo + (uint64_t)(cnt - 1) * step + 1 : lo;
+            hi = min(hi, lo + (uint64_t)cnt * step);
+            lo = nlo;
+        }
+    }
+    const uint64_t q = lo + k;
+    const bool before = q < hi && (upper ? run[q] <= x : run[q] < x);
+    const uint32_t res = (uint32_t)(lo + __popcll((__ballot(before) >> shift) & 0xFFFFull));
+    if (have && k == 0)
+        (upper ? ub : lb)[cr] = res;
+}
+
+// Piece b*s + r: its length and source start.  Plain buckets: piece b of run r
+// ends at cut b = ub(F[b]), bucket b = (F[b-1], F[b]].  Pivot buckets (2P-1,
+// bucket 2c = (F[c-1], F[c]), bucket 2c+1 = {F[c]}): cut 2c =
+// max(lb(F[c]), ub(F[c-1])), cut 2c+1 = ub(F[c]); the max gives an empty pivot
+// bucket to a splitter equal to its predecessor, whose keys are already in
+// the predecessor's bucket.  The last cut is the run's end.
+__device__ __forceinline__ uint64_t cut_of(const uint32_t *ub, const uint32_t *lb, uint32_t s, uint32_t r, uint32_t q,
+                                           uint32_t nb, int pb, uint64_t L)
 {
     if (q + 1 >= nb)
         return L;
     if (!pb)
-        return upper_bound(run, L, F[q]);
+        return ub[(uint64_t)q * s + r];
     const uint32_t c = q / 2;
     if (q & 1)
-        return upper_bound(run, L, F[c]);
-    const uint64_t lb = lower_bound(run, L, F[c]);
-    return c ? max(lb, upper_bound(run, L, F[c - 1])) : lb;
+        return ub[(uint64_t)c * s + r];
+    const uint64_t l = lb[(uint64_t)c * s + r];
+    return c ? max(l, (uint64_t)ub[(uint64_t)(c - 1) * s + r]) : l;
 }
 
-__global__ __launch_bounds__(kThreads) void k_dist_pieces(const uint32_t *__restrict__ keys,
-                                                          const uint64_t *__restrict__ off, uint32_t s,
-                                                          const uint32_t *__restrict__ F, uint32_t nb, int pb,
+__global__ __launch_bounds__(kThreads) void k_dist_pieces(const uint64_t *__restrict__ off, uint32_t s,
+                                                          const uint32_t *__restrict__ ub,
+                                                          const uint32_t *__restrict__ lb, uint32_t nb, int pb,
                                                           uint64_t *__restrict__ len, uint64_t *__restrict__ src)
 {
     const uint64_t p = (uint64_t)blockIdx.x * kThreads + threadIdx.x;  // piece b*s + r
     if (p >= (uint64_t)nb * s)
         return;
     const uint32_t b = (uint32_t)(p / s), r = (uint32_t)(p % s);
-    const uint32_t *run = keys + off[r];
     const uint64_t L = off[r + 1] - off[r];
-    const uint64_t lo = b ? cut(run, L, F, b - 1, nb, pb) : 0;
-    const uint64_t hi = cut(run, L, F, b, nb, pb);
+    const uint64_t lo = b ? cut_of(ub, lb, s, r, b - 1, nb, pb, L) : 0;
+    const uint64_t hi = cut_of(ub, lb, s, r, b, nb, pb, L);
     len[p] = hi - lo;
     src[p] = off[r] + lo;
 }
@@ -351,7 +364,8 @@ extern "C" bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_
     const uint64_t b_piece = align256(np * 8);
     const uint64_t nblk = (np + kScanBlock - 1) / kScanBlock, ntiles = (n + kOutTile - 1) / kOutTile;
     const uint64_t b_blk = align256((nblk + 1) * 8), b_tiles = align256(std::max<uint64_t>(ntiles, 1) * 4);
-    const uint64_t need = b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece + 2 * b_blk + b_tiles + sort_need;
+    const uint64_t nspl = P - 1, b_bnd = align256(std::max<uint64_t>(nspl * s, 1) * 4);
+    const uint64_t need = b_off + b_nz + 2 * b_cand + b_spl + 2 * b_piece + 2 * b_blk + b_tiles + 2 * b_bnd + sort_need;
     if (!temp) {
         *temp_bytes = need;
         return BCF_OK;
@@ -375,7 +389,9 @@ extern "C" bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_
     uint64_t *bsum = reinterpret_cast<uint64_t *>(tail);
     uint64_t *boff = reinterpret_cast<uint64_t *>(tail + b_blk);
     uint32_t *tile_first = reinterpret_cast<uint32_t *>(tail + 2 * b_blk);
-    void *sort_temp = tail + 2 * b_blk + b_tiles;
+    uint32_t *ub = reinterpret_cast<uint32_t *>(tail + 2 * b_blk + b_tiles);
+    uint32_t *lb = reinterpret_cast<uint32_t *>(tail + 2 * b_blk + b_tiles + b_bnd);
+    void *sort_temp = tail + 2 * b_blk + b_tiles + 2 * b_bnd;
     uint32_t *F = splitters ? splitters : F_int;
     if (n == 0) {  // no keys: every piece empty, splitters 0
         const uint64_t w = std::max<uint64_t>(np + 1, P - 1);
@@ -402,8 +418,13 @@ extern "C" bcf_status bcf_distribute_runs(const uint32_t *keys_in, const uint64_
         hipLaunchKernelGGL(k_dist_splitters, dim3(blocks_for(P - 1)), dim3(kThreads), 0, hs, S, m, P, F);
     {
         void *ps = bcf::prof_begin("dist_pieces", hs, 0.0);
-        hipLaunchKernelGGL(k_dist_pieces, dim3(blocks_for(np)), dim3(kThreads), 0, hs, keys_in, off_d, s, F, nb, pb,
-                           len, srcp);
+        const uint64_t searches = nspl * s * (pb ? 2 : 1);
+        if (searches)
+            hipLaunchKernelGGL(k_dist_bounds, dim3(blocks_for(kSearchLanes * searches)), dim3(kThreads), 0, hs, keys_in,
+                               off_d, s,
+                               F, (uint32_t)nspl, pb, ub, lb);
+        hipLaunchKernelGGL(k_dist_pieces, dim3(blocks_for(np)), dim3(kThreads), 0, hs, off_d, s, ub, lb, nb, pb, len,
+                           srcp);
         bcf::prof_end(ps);
     }
     hipLaunchKernelGGL(k_dist_block_sums, dim3((uint32_t)nblk), dim3(kThreads), 0, hs, len, np, bsum);
