@@ -181,6 +181,9 @@ def bench_distribution(bcf, workloads, torch, dev, runs=256, run_len=1 << 18, P=
     scatter kernel (one read and one write of every key) against HBM peak."""
     from paper_1306_5076_amd import autotune
 
+    def autotime(fn):
+        return autotune.time_ms(fn, reps=5, warmup=1)
+
     keys_np, off = workloads.sorted_runs([run_len] * runs, seed=1)
     keys = torch.from_numpy(keys_np).to(dev)
     n = keys.numel()
@@ -204,6 +207,21 @@ def bench_distribution(bcf, workloads, torch, dev, runs=256, run_len=1 << 18, P=
                                        "frac": round(gbs / HBM_PEAK_GBS, 4),
                                        "avg_launch_us": round(1e3 * sc["total_ms"] / sc["launches"], 2)}
         res["pivot_buckets" if pb else "plain"] = rec
+    # whole sorts through the distribution (runs of 2^18, distribution, one
+    # batched merge of every bucket's pieces; one host read-back of the piece
+    # offsets in between) against the regular sort, same keys
+    del keys, out
+    srt = {}
+    for dist in ("uniform", "distinct16", "zipf"):
+        k = torch.from_numpy(workloads.keys_u32(dist, n, seed=1)).to(dev)
+        o = torch.empty_like(k)
+        row = {"bcf_sort_u32_ms": round(autotime(lambda: bcf.sort_u32(k, out=o, workspace=ws)), 4)}
+        for pb in (False, True):
+            row["pivot_buckets_ms" if pb else "plain_buckets_ms"] = round(autotime(
+                lambda: bcf.sort_u32_pb(k, P=P, run_keys=run_len, pivot_buckets=pb, out=o, workspace=ws)), 4)
+        srt[dist] = row
+        del k, o
+    res["sort_by_distribution_ms"] = srt
     return res
 
 

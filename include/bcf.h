@@ -185,6 +185,22 @@ bcf_status bcf_colored_prefix_sums(const uint32_t *values, const uint8_t *colors
                                    void *stream);
 
 /*
+ * Stable merge of groups of consecutive sorted runs, every group on its own
+ * (the merge of Sec. 3.2 applied to many groups at once, e.g. the final merge
+ * phase after a distribution, where each bucket's pieces are merged).  Group g
+ * is runs [group_starts[g], group_starts[g+1]); its output occupies the same
+ * key range as its runs and equals bcf_merge_runs of those runs.
+ *   run_offsets   HOST, k+1 entries (conventions above)
+ *   group_starts  HOST, ngroups+1 run indexes: group_starts[0] == 0,
+ *                 nondecreasing, group_starts[ngroups] == k (else
+ *                 BCF_ERR_INVALID); empty groups are allowed
+ *   other arguments as for bcf_merge_runs
+ */
+bcf_status bcf_merge_run_groups(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+                                uint32_t k, const uint32_t *group_starts, uint32_t ngroups, uint32_t *keys_out,
+                                uint32_t *vals_out, void *temp, uint64_t *temp_bytes, void *stream);
+
+/*
  * Distribution of sorted runs into buckets by sampled splitters (Sec. 3.2,
  * "Distribution", whose bucket sizes Lemma 1 bounds for distinct keys), with
  * the optional pivot buckets of Sec. 3.3 ("Duplicate keys", BCFMergesortPB).

@@ -20,6 +20,8 @@ _API = (
     "sort_u64",
     "merge_runs",
     "distribute_runs",
+    "merge_run_groups",
+    "sort_u32_pb",
     "segmented_sort",
     "SegmentedPlan",
     "tile_keys",

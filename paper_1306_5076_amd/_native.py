@@ -35,6 +35,7 @@ EXPORTED = (
     "bcf_sort_u64",
     "bcf_merge_runs",
     "bcf_distribute_runs",
+    "bcf_merge_run_groups",
     "bcf_segmented_sort",
     "bcf_segmented_sort_pairs",
     "bcf_segmented_upload",
@@ -114,11 +115,12 @@ def load(path: str = LIB_PATH):
     lib.bcf_sort_u64.restype = ctypes.c_int
     lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
     lib.bcf_distribute_runs.argtypes = [vp, u64p, u32, u32, u32, ctypes.c_int, vp, vp, vp, vp, u64p, vp]
+    lib.bcf_merge_run_groups.argtypes = [vp, vp, u64p, u32, ctypes.POINTER(u32), u32, vp, vp, vp, u64p, vp]
     lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_upload.argtypes = [u64p, u32, ctypes.c_int, vp, u64p, vp]
     lib.bcf_segmented_execute.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
-    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_distribute_runs", "bcf_segmented_sort",
+    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_distribute_runs", "bcf_merge_run_groups", "bcf_segmented_sort",
               "bcf_segmented_sort_pairs", "bcf_segmented_upload", "bcf_segmented_execute"):
         getattr(lib, f).restype = ctypes.c_int
     lib.bcf_status_string.argtypes = [ctypes.c_int]

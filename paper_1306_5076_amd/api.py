@@ -29,6 +29,8 @@ __all__ = [
     "sort_u64",
     "merge_runs",
     "distribute_runs",
+    "merge_run_groups",
+    "sort_u32_pb",
     "segmented_sort",
     "SegmentedPlan",
     "tile_keys",
@@ -342,6 +344,69 @@ def distribute_runs(keys, run_offsets, P, t, pivot_buckets=False, keys_out=None,
             ),
         )
     return keys_out, pieces, spl[: P - 1]
+
+
+def merge_run_groups(keys, run_offsets, group_starts, keys_out=None, stream=None, workspace=None):
+    """Stable merge of every group of consecutive sorted runs on its own: group
+    g is runs [group_starts[g], group_starts[g+1]) (host sequences)."""
+    lib = load()
+    _check_tensor(keys, "keys")
+    n = keys.numel()
+    off = _offsets(run_offsets, n)
+    k = off.size - 1
+    gs = np.ascontiguousarray(np.asarray(group_starts, dtype=np.uint32))
+    ng = gs.size - 1
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    stream, sh = _stream(stream, keys.device)
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    gsp = gs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    need = ctypes.c_uint64(0)
+    check("bcf_merge_run_groups", lib.bcf_merge_run_groups(None, None, offp, k, gsp, ng, None, None, None,
+                                                           ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        check("bcf_merge_run_groups", lib.bcf_merge_run_groups(
+            _ptr(keys), None, offp, k, gsp, ng, _ptr(keys_out), None, _ptr(temp) or ctypes.c_void_p(1),
+            ctypes.byref(tb), sh))
+    return keys_out
+
+
+def sort_u32_pb(keys, P=256, run_keys=1 << 18, pivot_buckets=True, out=None, stream=None, workspace=None):
+    """Sort by distribution (BCFMergesort with the distribution step of Sec. 3.2
+    and, with ``pivot_buckets``, the pivot buckets of Sec. 3.3): sort runs of
+    ``run_keys`` keys, distribute them into buckets by P-1 sampled splitters
+    (t = P candidates per run), then merge every bucket's pieces, all buckets in
+    one batched merge.  A pivot bucket holds one key value, so its pieces are
+    already in place and it is passed on as one run.  The piece offsets are
+    read back to the host between the two device phases (one synchronisation
+    of ``stream``)."""
+    _check_tensor(keys, "keys")
+    n = keys.numel()
+    out = torch.empty_like(keys) if out is None else out
+    if n == 0:
+        return out
+    s = (n + run_keys - 1) // run_keys
+    seg = np.minimum(np.arange(s + 1, dtype=np.uint64) * np.uint64(run_keys), np.uint64(n))
+    runs = segmented_sort(keys, seg, keys_out=out, stream=stream, workspace=workspace)
+    dist, pieces, _ = distribute_runs(runs, seg, P, P, pivot_buckets=pivot_buckets, stream=stream,
+                                      workspace=workspace)
+    stream_, _ = _stream(stream, keys.device)
+    stream_.synchronize()
+    po = pieces.cpu().numpy().astype(np.uint64)
+    nb = 2 * P - 1 if pivot_buckets else P
+    offs, starts = [np.uint64(0)], [0]
+    for b in range(nb):
+        if pivot_buckets and b % 2 == 1:
+            ends = [po[(b + 1) * s]]  # the whole pivot bucket is one run
+        else:
+            ends = list(po[b * s + 1:(b + 1) * s + 1])
+        offs.extend(ends)
+        starts.append(len(offs) - 1)
+    merge_run_groups(dist, np.asarray(offs, dtype=np.uint64), starts, keys_out=out, stream=stream,
+                     workspace=workspace)
+    if stream is not None:
+        dist.record_stream(stream)
+    return out
 
 
 def segmented_sort(keys, seg_offsets, vals=None, keys_out=None, vals_out=None, stream=None, workspace=None,

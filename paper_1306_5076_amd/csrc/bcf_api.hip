@@ -689,9 +689,17 @@ bcf_status bcf_sort_pairs_f32(const float *keys_in, const uint32_t *vals_in, flo
                       static_cast<hipStream_t>(stream));
 }
 
-bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
-                          uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp, uint64_t *temp_bytes,
-                          void *stream)
+}  // extern "C"
+
+namespace {
+
+// Stable merge of groups of consecutive sorted runs, each group on its own:
+// group g is runs [group_starts[g], group_starts[g+1]) (one group of all k runs
+// when group_starts is NULL).  Every pass pairs the current runs of every
+// group; a group left with one run is copied through the remaining passes.
+bcf_status merge_groups_impl(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+                             uint32_t k, const uint32_t *group_starts, uint32_t ngroups, uint32_t *keys_out,
+                             uint32_t *vals_out, void *temp, uint64_t *temp_bytes, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!temp_bytes)
@@ -703,14 +711,28 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
     }
     if (!offsets_valid(run_offsets, k))
         return BCF_ERR_INVALID;
+    if (group_starts) {
+        if (ngroups == 0 || group_starts[0] != 0 || group_starts[ngroups] != k)
+            return BCF_ERR_INVALID;
+        for (uint32_t g = 0; g < ngroups; ++g)
+            if (group_starts[g + 1] < group_starts[g])
+                return BCF_ERR_INVALID;
+    }
+    const uint32_t ng = group_starts ? ngroups : 1;
     const bool pairs = vals_in != nullptr;
     const uint64_t n = run_offsets[k];
-    // nonempty runs, in order (empty runs change nothing, stability included)
-    std::vector<std::pair<uint64_t, uint64_t>> runs;
-    for (uint32_t r = 0; r < k; ++r)
-        if (run_offsets[r + 1] > run_offsets[r])
-            runs.push_back({run_offsets[r], run_offsets[r + 1] - run_offsets[r]});
-    const uint32_t P = runs.size() > 1 ? ceil_log2(runs.size()) : 0;
+    // nonempty runs of every group, in order (empty runs change nothing,
+    // stability included)
+    std::vector<std::vector<std::pair<uint64_t, uint64_t>>> cur(ng);
+    uint32_t P = 0;
+    for (uint32_t g = 0; g < ng; ++g) {
+        const uint32_t r0 = group_starts ? group_starts[g] : 0, r1 = group_starts ? group_starts[g + 1] : k;
+        for (uint32_t r = r0; r < r1; ++r)
+            if (run_offsets[r + 1] > run_offsets[r])
+                cur[g].push_back({run_offsets[r], run_offsets[r + 1] - run_offsets[r]});
+        if (cur[g].size() > 1)
+            P = std::max(P, ceil_log2(cur[g].size()));
+    }
     // In place (keys or values) with an odd pass count would make pass 1 read
     // and write the same buffer; then every pass is shifted by one buffer and
     // a final copy moves the result from temp to the output.
@@ -722,18 +744,19 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
         return at_out ? kBufOut : kBufTemp;
     };
     std::vector<MergePass> passes(P);
-    std::vector<std::pair<uint64_t, uint64_t>> cur = runs;
     for (uint32_t j = 1; j <= P; ++j) {
         const uint32_t src = j == 1 ? kBufIn : buf_after(j - 1);
         const uint32_t dst = buf_after(j);
-        std::vector<std::pair<uint64_t, uint64_t>> next;
-        for (size_t i = 0; i < cur.size(); i += 2) {
-            const uint64_t a = cur[i].first, na = cur[i].second;
-            const uint64_t nb = i + 1 < cur.size() ? cur[i + 1].second : 0;
-            add_job(passes[j - 1], a, na, nb, src, dst);
-            next.push_back({a, na + nb});
+        for (auto &runs : cur) {
+            std::vector<std::pair<uint64_t, uint64_t>> next;
+            for (size_t i = 0; i < runs.size(); i += 2) {
+                const uint64_t a = runs[i].first, na = runs[i].second;
+                const uint64_t nb = i + 1 < runs.size() ? runs[i + 1].second : 0;
+                add_job(passes[j - 1], a, na, nb, src, dst);
+                next.push_back({a, na + nb});
+            }
+            runs.swap(next);
         }
-        cur.swap(next);
     }
     const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
     TablePlan TP;
@@ -794,6 +817,28 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
             return BCF_ERR_DEVICE;
     }
     return BCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+                          uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp, uint64_t *temp_bytes,
+                          void *stream)
+{
+    return merge_groups_impl(keys_in, vals_in, run_offsets, k, nullptr, 0, keys_out, vals_out, temp, temp_bytes,
+                             stream);
+}
+
+bcf_status bcf_merge_run_groups(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+                                uint32_t k, const uint32_t *group_starts, uint32_t ngroups, uint32_t *keys_out,
+                                uint32_t *vals_out, void *temp, uint64_t *temp_bytes, void *stream)
+{
+    if (!group_starts)
+        return BCF_ERR_INVALID;
+    return merge_groups_impl(keys_in, vals_in, run_offsets, k, group_starts, ngroups, keys_out, vals_out, temp,
+                             temp_bytes, stream);
 }
 
 bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,

@@ -309,3 +309,16 @@ def test_distribute_runs_validation_and_query(lib):
     tb = ctypes.c_uint64(1 << 30)
     assert lib.bcf_distribute_runs(buf, p, 1, 4, 4, 0, buf, ctypes.c_void_p(0x200000), None, ctypes.c_void_p(0x300000),
                                    ctypes.byref(tb), None) == 1
+
+
+def test_merge_run_groups_validation_and_query(lib):
+    need = ctypes.c_uint64(0)
+    a, p = _offs([0, 10, 20, 30])
+    g = (ctypes.c_uint32 * 3)(0, 2, 3)
+    assert lib.bcf_merge_run_groups(None, None, p, 3, g, 2, None, None, None, ctypes.byref(need), None) == 0
+    assert need.value >= 30 * 4
+    bad = (ctypes.c_uint32 * 3)(0, 2, 2)  # last start != k
+    assert lib.bcf_merge_run_groups(None, None, p, 3, bad, 2, None, None, None, ctypes.byref(need), None) == 1
+    dec = (ctypes.c_uint32 * 3)(0, 3, 2)  # decreasing
+    assert lib.bcf_merge_run_groups(None, None, p, 3, dec, 2, None, None, None, ctypes.byref(need), None) == 1
+    assert lib.bcf_merge_run_groups(None, None, p, 3, None, 2, None, None, None, ctypes.byref(need), None) == 1

@@ -117,3 +117,33 @@ def test_full_size_2p26_in_256_runs(bcf, torch_dev, pb):
     keys, off = workloads.sorted_runs([1 << 18] * 256, seed=1)
     got, want = _run_both(bcf, torch_dev, keys, off, 256, 256, pb)
     _assert_same(got, want)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "dups"])
+def test_merge_run_groups_matches_per_group_merge(bcf, torch_dev, dist):
+    """Batched merge of groups of runs == the oracle's merge of each group."""
+    torch, dev = torch_dev
+    sizes = [0, 5, 4096, 4097, 1, 0, 12345, 300, 65536, 7, 0, 0, 999, 2048]
+    keys, off = workloads.sorted_runs(sizes, seed=21, dist=dist)
+    starts = [0, 3, 4, 4, 9, 14]  # groups of 3, 1, 0, 5 and 5 runs
+    print(f"merge_run_groups {dist} n={keys.size}", flush=True)
+    got = bcf.merge_run_groups(torch.from_numpy(keys).to(dev), off, starts).cpu().numpy()
+    want = np.empty_like(keys)
+    for g in range(len(starts) - 1):
+        a, b = starts[g], starts[g + 1]
+        lo, hi = int(off[a]), int(off[b])
+        want[lo:hi] = oracle.merge_runs(keys[lo:hi], (off[a:b + 1] - off[a]).astype(np.uint64))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("pb", [False, True])
+@pytest.mark.parametrize("dist,n", [("uniform", 1_000_003), ("distinct16", 1 << 22), ("zipf", 1 << 22),
+                                    ("uniform", 1 << 26)])
+def test_sort_by_distribution_equals_oracle_sort(bcf, torch_dev, dist, n, pb):
+    """Runs, distribution, batched merge of every bucket: the sorted keys."""
+    torch, dev = torch_dev
+    keys = workloads.keys_u32(dist, n, seed=2)
+    print(f"sort_u32_pb {dist} n={n} pb={pb}", flush=True)
+    got = bcf.sort_u32_pb(torch.from_numpy(keys).to(dev), P=256, run_keys=1 << 16 if n < (1 << 24) else 1 << 18,
+                          pivot_buckets=pb).cpu().numpy()
+    assert np.array_equal(got, oracle.sort_u32(keys))
