@@ -394,16 +394,15 @@ def sort_u32_pb(keys, P=256, run_keys=1 << 18, pivot_buckets=True, out=None, str
     stream_.synchronize()
     po = pieces.cpu().numpy().astype(np.uint64)
     nb = 2 * P - 1 if pivot_buckets else P
-    offs, starts = [np.uint64(0)], [0]
-    for b in range(nb):
-        if pivot_buckets and b % 2 == 1:
-            ends = [po[(b + 1) * s]]  # the whole pivot bucket is one run
-        else:
-            ends = list(po[b * s + 1:(b + 1) * s + 1])
-        offs.extend(ends)
-        starts.append(len(offs) - 1)
-    merge_run_groups(dist, np.asarray(offs, dtype=np.uint64), starts, keys_out=out, stream=stream,
-                     workspace=workspace)
+    # group b = the pieces of bucket b, a pivot bucket as one run
+    b = np.arange(nb)
+    one = (b % 2 == 1) if pivot_buckets else np.zeros(nb, dtype=bool)
+    per = np.where(one, 1, s)
+    ends = np.where(one[:, None], (b[:, None] + 1) * s, b[:, None] * s + 1 + np.arange(s)[None, :])
+    keep = np.arange(s)[None, :] < per[:, None]
+    offs = np.concatenate([[0], po[ends[keep]]]).astype(np.uint64)
+    starts = np.concatenate([[0], np.cumsum(per)]).astype(np.uint32)
+    merge_run_groups(dist, offs, starts, keys_out=out, stream=stream, workspace=workspace)
     if stream is not None:
         dist.record_stream(stream)
     return out
