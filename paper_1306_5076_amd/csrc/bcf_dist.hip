@@ -11,7 +11,7 @@
 //   3. k_dist_splitters   P-1 evenly spaced final splitters from the sorted
 //                         candidates (the last key of each of P equal chunks);
 //   4. k_dist_bounds      upper bound of every splitter in every run (pivot
-//                         buckets: lower bounds too), 16 lanes per search;
+//                         buckets: lower bounds too), 8 lanes per search;
 //      k_dist_pieces      per (bucket, run) piece its length and source start;
 //   5. k_dist_block_sums, k_dist_scan, k_dist_offsets
 //                         exclusive prefix over the pieces in bucket-major
@@ -78,11 +78,13 @@ __global__ __launch_bounds__(kThreads) void k_dist_splitters(const uint32_t *__r
 
 // Bounds of every splitter in every run: ub[c*s + r] = the first index of run
 // r with a key > F[c], and (pivot buckets) lb[c*s + r] = the first index with
-// a key >= F[c].  Each 16-lane group of a wave runs one search, narrowing the
-// answer's bracket 16-fold per round with 16 probes (five rounds for a run of
+// a key >= F[c].  Each 8-lane group of a wave runs one search, narrowing the
+// answer's bracket 8-fold per round with 8 probes (six rounds for a run of
 // 2^18 keys): few dependent loads, and the probes of the first rounds are
-// shared by all splitters of a run in the cache.
-constexpr uint32_t kSearchLanes = 16;
+// shared by all splitters of a run in the cache.  (Measured at 2^26 keys in
+// 256 runs, P = 256: 8 lanes beat 16 and whole-wave searches.)
+constexpr uint32_t kSearchLanes = 8;
+constexpr uint64_t kSearchMask = (1ull << kSearchLanes) - 1;
 
 __global__ __launch_bounds__(kThreads) void k_dist_bounds(const uint32_t *__restrict__ keys,
                                                           const uint64_t *__restrict__ off, uint32_t s,
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_dist_bounds(const uint32_t *__rest
         const uint64_t step = act ? (hi - lo + kSearchLanes - 1) / kSearchLanes : 0;
         const uint64_t q = lo + k * step;
         const bool before = act && q < hi && (upper ? run[q] <= x : run[q] < x);  // the answer lies after q
-        const uint32_t cnt = (uint32_t)__popcll((__ballot(before) >> shift) & 0xFFFFull);
+        const uint32_t cnt = (uint32_t)__popcll((__ballot(before) >> shift) & kSearchMask);
         if (act) {  // probes 0..cnt-1 lie before the answer, probe cnt (if any) not
             const uint64_t nlo = cnt ? lo + (uint64_t)(cnt - 1) * step + 1 : lo;
             hi = min(hi, lo + (uint64_t)cnt * step);
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_dist_bounds(const uint32_t *__rest
     }
     const uint64_t q = lo + k;
     const bool before = q < hi && (upper ? run[q] <= x : run[q] < x);
-    const uint32_t res = (uint32_t)(lo + __popcll((__ballot(before) >> shift) & 0xFFFFull));
+    const uint32_t res = (uint32_t)(lo + __popcll((__ballot(before) >> shift) & kSearchMask));
     if (have && k == 0)
         (upper ? ub : lb)[cr] = res;
 }
