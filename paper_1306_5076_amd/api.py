@@ -371,6 +371,23 @@ def merge_run_groups(keys, run_offsets, group_starts, keys_out=None, stream=None
     return keys_out
 
 
+def bucket_groups(piece_offsets, s, P, pivot_buckets):
+    """Run offsets and group starts for the merge of every bucket's pieces
+    after a distribution of s runs into P (2P-1 with pivot buckets) buckets:
+    group b holds the s pieces of bucket b, except that a pivot bucket, whose
+    keys are all equal, is one run (its pieces are already in merged order)."""
+    po = np.asarray(piece_offsets, dtype=np.uint64)
+    nb = 2 * P - 1 if pivot_buckets else P
+    b = np.arange(nb)
+    one = (b % 2 == 1) if pivot_buckets else np.zeros(nb, dtype=bool)
+    per = np.where(one, 1, s)
+    ends = np.where(one[:, None], (b[:, None] + 1) * s, b[:, None] * s + 1 + np.arange(s)[None, :])
+    keep = np.arange(s)[None, :] < per[:, None]
+    offs = np.concatenate([[0], po[ends[keep]]]).astype(np.uint64)
+    starts = np.concatenate([[0], np.cumsum(per)]).astype(np.uint32)
+    return offs, starts
+
+
 def sort_u32_pb(keys, P=256, run_keys=1 << 18, pivot_buckets=True, out=None, stream=None, workspace=None):
     """Sort by distribution (BCFMergesort with the distribution step of Sec. 3.2
     and, with ``pivot_buckets``, the pivot buckets of Sec. 3.3): sort runs of
@@ -393,15 +410,7 @@ def sort_u32_pb(keys, P=256, run_keys=1 << 18, pivot_buckets=True, out=None, str
     stream_, _ = _stream(stream, keys.device)
     stream_.synchronize()
     po = pieces.cpu().numpy().astype(np.uint64)
-    nb = 2 * P - 1 if pivot_buckets else P
-    # group b = the pieces of bucket b, a pivot bucket as one run
-    b = np.arange(nb)
-    one = (b % 2 == 1) if pivot_buckets else np.zeros(nb, dtype=bool)
-    per = np.where(one, 1, s)
-    ends = np.where(one[:, None], (b[:, None] + 1) * s, b[:, None] * s + 1 + np.arange(s)[None, :])
-    keep = np.arange(s)[None, :] < per[:, None]
-    offs = np.concatenate([[0], po[ends[keep]]]).astype(np.uint64)
-    starts = np.concatenate([[0], np.cumsum(per)]).astype(np.uint32)
+    offs, starts = bucket_groups(po, s, P, pivot_buckets)
     merge_run_groups(dist, offs, starts, keys_out=out, stream=stream, workspace=workspace)
     if stream is not None:
         dist.record_stream(stream)
