@@ -322,7 +322,15 @@ def main():
         import paper_1306_5076_amd as bcf
         import workloads
 
-        print(json.dumps(bench_distribution(bcf, workloads, torch, torch.device("cuda:0"))), flush=True)
+        dev = torch.device("cuda:0")
+        if args.copy_calibration:  # a plain copy of n u32 keys, 3 times, for the traffic counters
+            a = torch.zeros(args.n, dtype=torch.int32, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
+        print(json.dumps(bench_distribution(bcf, workloads, torch, dev)), flush=True)
         return
     if args.block_sort_ablation:
         import torch

@@ -93,11 +93,15 @@ def traffic(fetch_dir: str, write_dir: str, n_copy_keys: int, command: str = "")
     cf, cw = fetch.get(COPY_KERNEL), write.get(COPY_KERNEL)
     if not cf or not cw:
         raise ValueError(f"no {COPY_KERNEL} dispatch to calibrate with (run bench.py --copy-calibration)")
+    # the calibration copies are the largest copy dispatches; small host-device
+    # copies of descriptors in the same run are left out
+    cf = [x for x in cf if x >= 0.5 * max(cf)]
+    cw = [x for x in cw if x >= 0.5 * max(cw)]
     fetch_scale = copy_bytes / (statistics.mean(cf) * 1024.0)
     write_scale = copy_bytes / (statistics.mean(cw) * 1024.0)
     per = {}
     for k in sorted(set(fetch) & set(write)):
-        if k == COPY_KERNEL or not k.startswith("bcf::"):
+        if k == COPY_KERNEL or not k.startswith(("bcf::", "k_dist_")):
             continue
         fk, wk = statistics.mean(fetch[k]), statistics.mean(write[k])
         per[k] = {
@@ -123,7 +127,7 @@ def lds(directory: str, command: str = "") -> dict:
     insts = counter_per_kernel(directory, "SQ_INSTS_LDS")
     per = {}
     for k in sorted(set(conf) & set(insts)):
-        if not k.startswith("bcf::"):
+        if not k.startswith(("bcf::", "k_dist_")):
             continue
         per[k] = {"SQ_LDS_BANK_CONFLICT": statistics.mean(conf[k]), "SQ_INSTS_LDS": statistics.mean(insts[k]),
                   "dispatches": len(conf[k])}
