@@ -124,8 +124,121 @@ def multiset_hash(keys, vals=None):
 
 
 def is_sorted_u32(keys) -> bool:
+    """True when the keys are nondecreasing."""
     k = _u32(keys)
     return bool(_load().oracle_is_sorted_u32(_p32(k), k.size))
+
+
+# ---------------------------------------------------------- chunked (all cores)
+#
+# The same results on several host cores: the input is cut into `threads`
+# equal chunks, every chunk is sorted by the plain merge sort above in its own
+# thread (ctypes releases the GIL during the C call), then a pairwise merge
+# tree joins the sorted chunks, the merges of one level running in parallel.
+# Each merge is the stable k-cursor merge of two adjacent runs, so the result
+# is the stable sort of the whole input: equal to sort_u32 / sort_pairs_u32.
+
+
+def _chunk_bounds(n, threads):
+    threads = max(1, min(int(threads), n if n else 1))
+    return [n * c // threads for c in range(threads + 1)]
+
+
+def _merge_tree(ks, vs, bounds, pool):
+    """Merge the adjacent sorted runs [bounds[i], bounds[i+1]) pairwise, level
+    by level; ks/vs are swapped with same-size scratch arrays between levels."""
+    src_k, src_v = ks, vs
+    dst_k = np.empty_like(ks)
+    dst_v = np.empty_like(vs) if vs is not None else None
+    while len(bounds) > 2:
+        jobs, nb = [], [bounds[0]]
+        for i in range(0, len(bounds) - 1, 2):
+            lo = bounds[i]
+            mid = bounds[i + 1]
+            hi = bounds[i + 2] if i + 2 < len(bounds) else mid
+            jobs.append((lo, mid, hi))
+            nb.append(hi)
+
+        def merge_one(job, sk=src_k, sv=src_v, dk=dst_k, dv=dst_v):
+            lo, mid, hi = job
+            off = np.array([0, mid - lo, hi - lo], dtype=np.uint64)
+            vin = sv[lo:hi] if sv is not None else None
+            r = merge_runs(sk[lo:hi], off, vin)
+            if sv is not None:
+                dk[lo:hi], dv[lo:hi] = r
+            else:
+                dk[lo:hi] = r
+
+        list(pool.map(merge_one, jobs))
+        src_k, dst_k = dst_k, src_k
+        if vs is not None:
+            src_v, dst_v = dst_v, src_v
+        bounds = nb
+    return src_k, src_v
+
+
+def sort_u32_chunked(keys, threads: int) -> np.ndarray:
+    """sort_u32 on `threads` host threads (chunk sorts + pairwise merge tree)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    k = _u32(keys)
+    bounds = _chunk_bounds(k.size, threads)
+    out = np.empty_like(k)
+    with ThreadPoolExecutor(max_workers=len(bounds) - 1) as pool:
+        def sort_one(c):
+            out[bounds[c]:bounds[c + 1]] = sort_u32(k[bounds[c]:bounds[c + 1]])
+
+        list(pool.map(sort_one, range(len(bounds) - 1)))
+        res, _ = _merge_tree(out, None, bounds, pool)
+    return res
+
+
+def sort_pairs_u32_chunked(keys, vals, threads: int):
+    """sort_pairs_u32 (stable) on `threads` host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    k, v = _u32(keys), _u32(vals)
+    assert k.shape == v.shape
+    bounds = _chunk_bounds(k.size, threads)
+    ko, vo = np.empty_like(k), np.empty_like(v)
+    with ThreadPoolExecutor(max_workers=len(bounds) - 1) as pool:
+        def sort_one(c):
+            lo, hi = bounds[c], bounds[c + 1]
+            ko[lo:hi], vo[lo:hi] = sort_pairs_u32(k[lo:hi], v[lo:hi])
+
+        list(pool.map(sort_one, range(len(bounds) - 1)))
+        return _merge_tree(ko, vo, bounds, pool)
+
+
+def segmented_sort_threads(keys, offsets, threads: int, vals=None):
+    """segmented_sort (or, with vals, the stable pair sort of every segment),
+    segments spread over `threads` host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    k = _u32(keys)
+    off = np.asarray(offsets, dtype=np.uint64)
+    ko = np.empty_like(k)
+    v = _u32(vals) if vals is not None else None
+    vo = np.empty_like(v) if v is not None else None
+    nseg = off.size - 1
+    # contiguous slices of segments with about equal key counts
+    cuts = np.searchsorted(off, np.linspace(0, int(off[-1]), max(1, threads) * 4 + 1), side="left")
+    cuts = sorted(set(int(c) for c in np.clip(cuts, 0, nseg)) | {0, nseg})
+
+    def one(i):
+        s0, s1 = cuts[i], cuts[i + 1]
+        lo, hi = int(off[s0]), int(off[s1])
+        sub = off[s0:s1 + 1] - off[s0]
+        if v is None:
+            ko[lo:hi] = segmented_sort(k[lo:hi], sub)
+        else:
+            for sg in range(s0, s1):
+                a, b = int(off[sg]), int(off[sg + 1])
+                ko[a:b], vo[a:b] = sort_pairs_u32(k[a:b], v[a:b])
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as pool:
+        list(pool.map(one, range(len(cuts) - 1)))
+    return (ko, vo) if v is not None else ko
 
 
 def _sort_typed(kind, dtype, keys, vals):

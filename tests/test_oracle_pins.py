@@ -170,6 +170,82 @@ def test_segmented_sort(oracle_mod):
         assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi]))
 
 
+# ---------------------------------------------------------------- is_sorted (a checker)
+
+
+@pytest.mark.parametrize("n", range(0, 8))
+def test_is_sorted_every_ternary_word(oracle_mod, n):
+    # a sequence is sorted exactly when it equals its order-statistic sort
+    for word in itertools.product((0, 1, 2), repeat=n):
+        want = list(word) == order_statistics(word)
+        assert oracle_mod.is_sorted_u32(np.array(word, dtype=np.uint32)) == want, word
+
+
+def test_is_sorted_rejects_one_inversion_anywhere(oracle_mod):
+    base = np.sort(workloads.keys_u32("uniform", 10_000, seed=12))
+    base = np.unique(base)  # strictly increasing, so any swap is an inversion
+    m = base.size
+    assert oracle_mod.is_sorted_u32(base)
+    for i in (0, 1, m // 2, m - 3, m - 2):  # first pair, middle, last pair
+        bad = base.copy()
+        bad[i], bad[i + 1] = bad[i + 1], bad[i]
+        assert not oracle_mod.is_sorted_u32(bad), i
+    # the last element alone out of place, and the first alone
+    bad = base.copy()
+    bad[-1] = 0
+    assert not oracle_mod.is_sorted_u32(bad)
+    bad = base.copy()
+    bad[0] = 0xFFFFFFFF
+    assert not oracle_mod.is_sorted_u32(bad)
+
+
+def test_is_sorted_accepts_equal_neighbours_and_extremes(oracle_mod):
+    assert oracle_mod.is_sorted_u32(np.array([], dtype=np.uint32))
+    assert oracle_mod.is_sorted_u32(np.array([7], dtype=np.uint32))
+    assert oracle_mod.is_sorted_u32(np.array([5, 5, 5, 5], dtype=np.uint32))
+    assert oracle_mod.is_sorted_u32(np.array([0, 0, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFF, 0xFFFFFFFF],
+                                             dtype=np.uint32))
+    # unsigned order: 0x80000000 is above 0x7FFFFFFF
+    assert not oracle_mod.is_sorted_u32(np.array([0x80000000, 0x7FFFFFFF], dtype=np.uint32))
+
+
+# ---------------------------------------------------------------- chunked (all cores)
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 5, 8, 64])
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 1000, 4097, 100_003])
+def test_chunked_sorts_match_numpy(oracle_mod, threads, n):
+    keys = workloads.keys_u32("zipf", n, seed=n + threads)
+    assert np.array_equal(oracle_mod.sort_u32_chunked(keys, threads), np.sort(keys))
+    vals = np.arange(n, dtype=np.uint32) ^ np.uint32(0x5A5A5A5A)
+    ko, vo = oracle_mod.sort_pairs_u32_chunked(keys, vals, threads)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(ko, keys[order]) and np.array_equal(vo, vals[order])
+
+
+def test_chunked_sort_every_ternary_word(oracle_mod):
+    for n in range(1, 8):
+        for word in itertools.product((0, 1, 2), repeat=n):
+            got = oracle_mod.sort_u32_chunked(np.array(word, dtype=np.uint32), 3).tolist()
+            assert got == order_statistics(word), word
+
+
+def test_segmented_threads_match_numpy(oracle_mod):
+    sizes = [0, 1, 2, 0, 37, 4096, 5000, 1, 0, 20_000, 3]
+    offs = workloads.segment_offsets(sizes)
+    keys = workloads.keys_u32("distinct16", int(offs[-1]), seed=9)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    for threads in (1, 3, 16):
+        got = oracle_mod.segmented_sort_threads(keys, offs, threads)
+        gk, gv = oracle_mod.segmented_sort_threads(keys, offs, threads, vals)
+        for s in range(len(sizes)):
+            lo, hi = int(offs[s]), int(offs[s + 1])
+            order = np.argsort(keys[lo:hi], kind="stable")
+            assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi]))
+            assert np.array_equal(gk[lo:hi], keys[lo:hi][order])
+            assert np.array_equal(gv[lo:hi], vals[lo:hi][order])
+
+
 # ---------------------------------------------------------------- multiset hash
 
 
@@ -330,6 +406,15 @@ MUTANTS = {
     "u64_low_half_only": ("        if (x <= y)\n", "        if ((uint32_t)x <= (uint32_t)y)\n"),
     # u64 keys compared by their high halves only
     "u64_high_half_only": ("        if (x <= y)\n", "        if ((x >> 32) <= (y >> 32))\n"),
+    # sortedness check that accepts everything
+    "is_sorted_always_true": ("        if (keys[i - 1] > keys[i])\n            return 0;\n",
+                              "        if (keys[i - 1] > keys[i])\n            return 1;\n"),
+    # sortedness check that never looks at the last pair
+    "is_sorted_skips_last_pair": ("for (uint64_t i = 1; i < n; i++)\n        if (keys[i - 1] > keys[i])",
+                                  "for (uint64_t i = 1; i + 1 < n; i++)\n        if (keys[i - 1] > keys[i])"),
+    # sortedness check that never looks at the first pair
+    "is_sorted_skips_first_pair": ("for (uint64_t i = 1; i < n; i++)\n        if (keys[i - 1] > keys[i])",
+                                   "for (uint64_t i = 2; i < n; i++)\n        if (keys[i - 1] > keys[i])"),
     # colored prefix sums made exclusive (each output misses its own value)
     "cps_exclusive": ("        run[c] += values[i];\n        out[i] = run[c];\n",
                       "        out[i] = run[c];\n        run[c] += values[i];\n"),
@@ -392,6 +477,19 @@ def _pins_pass(lib) -> bool:
             lib.oracle_sort_u64(k.ctypes.data_as(u64), o.ctypes.data_as(u64), ctypes.c_uint64(4))
             if o.tolist() != order_statistics(word):
                 return False
+    # sortedness check: ternary words against the order-statistic definition,
+    # and one inversion at the first, a middle and the last pair
+    if ok:
+        for word in itertools.product((0, 1, 2), repeat=5):
+            k = np.array(word, dtype=np.uint32)
+            if bool(lib.oracle_is_sorted_u32(p(k), ctypes.c_uint64(5))) != (list(word) == order_statistics(word)):
+                return False
+        inc = np.arange(10, 20, dtype=np.uint32)
+        for i in (0, 4, 8):
+            bad = inc.copy()
+            bad[i], bad[i + 1] = bad[i + 1], bad[i]
+            if lib.oracle_is_sorted_u32(p(bad), ctypes.c_uint64(bad.size)):
+                return False
     # colored prefix sums: brute force over ternary color words, with colors
     # 2 and 3 folded into the last color of d = 2 half the time
     if ok:
@@ -427,6 +525,8 @@ def _build_variant(tmp_path, name, src_text):
     lib.oracle_colored_prefix_sums.argtypes = [u32p, ctypes.POINTER(ctypes.c_uint8), u32p, ctypes.c_uint64,
                                                ctypes.c_uint32]
     lib.oracle_sort_u64.argtypes = [u64p, u64p, ctypes.c_uint64]
+    lib.oracle_is_sorted_u32.argtypes = [u32p, ctypes.c_uint64]
+    lib.oracle_is_sorted_u32.restype = ctypes.c_int
     return lib
 
 
