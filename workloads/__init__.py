@@ -1,9 +1,11 @@
 """Seeded synthetic inputs shared by the GPU path's tests/bench and the CPU oracle.
 
 This module only draws numbers; it contains none of the sorting or merging
-arithmetic of the method.  Every generator is counter based: element ``i`` of a
-stream with seed ``s`` depends only on ``(s, i)``, so any slice can be
-regenerated independently and both sides see bit-identical inputs.
+arithmetic of the method (the ``sorted`` inputs are ordered by numpy's own
+sort, a library routine neither side under test uses).  Every generator but
+``sorted``/``reverse`` is counter based: element ``i`` of a stream with seed
+``s`` depends only on ``(s, i)``, so any slice can be regenerated
+independently; both sides always see bit-identical inputs.
 
 Base generator: the SplitMix64 output function (Steele, Lea & Flood, OOPSLA
 2014; the constants are those of Vigna's public-domain reference), applied to
@@ -14,10 +16,11 @@ Distributions (the paper's data sets are described in its experimental
 section; the MI355X workloads add sorted, reverse, 16-distinct and Zipf):
 
 * ``uniform``   -- u32 uniform over [0, 2^32).
-* ``sorted``    -- a nondecreasing sequence spread over [0, 2^32): element i is
-                   ``i * step + (draw mod step)`` with ``step = 2^32 // n``
-                   (strictly increasing; produced without sorting anything).
-* ``reverse``   -- ``sorted`` read backwards.
+* ``sorted``    -- the ``uniform`` draws in ascending order (numpy's library
+                   sort of the same sample), so the multiset and its ties are
+                   those of ``uniform``.  This one distribution is not counter
+                   based: element i depends on the whole sample.
+* ``reverse``   -- ``sorted`` read backwards (descending).
 * ``distinct16``-- 16 distinct u32 values; each key picks one by the top 4 bits
                    of its draw.
 * ``zipf``      -- Zipf(s=1.2) over 2^20 ranks by inverse CDF; rank r maps to
@@ -32,7 +35,8 @@ section; the MI355X workloads add sorted, reverse, 16-distinct and Zipf):
 64-bit keys (``keys_u64``): ``uniform`` (a full 64-bit draw), ``hi16`` (high half
 one of 16 values, low half uniform: ties in the high half), ``lo16`` (the
 reverse), ``equal`` (one key), ``sorted`` / ``reverse`` (``sorted`` u32 in the high
-half, a uniform low half), ``extremes`` (drawn from 0, 1, 2^32 - 1, 2^32,
+half, a uniform low half: equal high halves are not in low-half order),
+``extremes`` (drawn from 0, 1, 2^32 - 1, 2^32,
 2^63 and 2^64 - 1).
 
 Colored prefix sums take u32 values uniform over [0, 2^32) and uint8 colors
@@ -122,10 +126,7 @@ def keys_u32(dist: str, n: int, seed: int = 1) -> np.ndarray:
     if dist == "uniform":
         return draws_u32(seed, n)
     if dist in ("sorted", "reverse"):
-        step = max(1, (1 << 32) // n)
-        jitter = draws_u64(seed, n) % np.uint64(step)
-        k = (np.arange(n, dtype=np.uint64) * np.uint64(step) + jitter)
-        k = np.minimum(k, np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        k = np.sort(draws_u32(seed, n))
         return k if dist == "sorted" else k[::-1].copy()
     if dist == "distinct16":
         vals = draws_u32(seed ^ 0x16, 16)
