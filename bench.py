@@ -59,23 +59,71 @@ def counted_kernel(rec, prefix: str):
     return name, rec["per_kernel"][name]
 
 
-def cpu_baseline(keys_np):
-    """The CPU oracle (single-threaded merge sort) on one full 2^26-key array."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# Worker threads of the all-cores leg: the host cores this process may run on,
+# at most 16 (the host-core share of one GPU on a shared GPU node).
+CPU_THREADS_MAX = 16
+
+
+def cpu_baseline(keys_np, reps=3):
+    """The CPU oracle on one full 2^26-key uniform array, median of `reps` runs:
+    its plain top-down merge sort pinned to one core (the calling thread's
+    affinity set to a single core, as `taskset -c` would), and its chunked form
+    on all allowed host cores (one chunk sort per thread, then a pairwise merge
+    tree), each checked against the other."""
+    import numpy as np
+
     import oracle
 
-    reps = []
-    for _ in range(2):
+    allowed = sorted(os.sched_getaffinity(0))
+    threads = max(1, min(CPU_THREADS_MAX, len(allowed)))
+    pin = allowed[0]
+    single = []
+    os.sched_setaffinity(0, {pin})
+    try:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ref = oracle.sort_u32(keys_np)
+            single.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    multi = []
+    for _ in range(reps):
         t0 = time.perf_counter()
-        oracle.sort_u32(keys_np)
-        reps.append(time.perf_counter() - t0)
-    t = sorted(reps)[len(reps) // 2]
+        got = oracle.sort_u32_chunked(keys_np, threads)
+        multi.append(time.perf_counter() - t0)
+    if not np.array_equal(got, ref):
+        raise RuntimeError("chunked oracle disagrees with the plain oracle")
+    t1 = sorted(single)[len(single) // 2]
+    tm = sorted(multi)[len(multi) // 2]
     return {
-        "value": round(keys_np.size / t / 1e9, 4),
+        "value": round(keys_np.size / t1 / 1e9, 4),
         "unit": "Gkeys/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"one {keys_np.size}-key uniform u32 array (seed 1), top-down merge sort, "
-        f"best of {len(reps)} runs = {min(reps):.2f} s",
+        "sample": f"one {keys_np.size}-key uniform u32 array (seed 1), the oracle's top-down merge sort "
+        f"pinned to host core {pin}, median of {reps} runs = {t1:.2f} s (runs {', '.join(f'{x:.2f}' for x in single)} s)",
+        "all_cores": {
+            "value": round(keys_np.size / tm / 1e9, 4),
+            "unit": "Gkeys/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"the same array cut into {threads} chunks, each sorted by the oracle in its own thread, "
+            f"then a pairwise merge tree of the oracle's stable merge; median of {reps} runs = {tm:.2f} s",
+        },
+        "nproc": os.cpu_count(),
+        "allowed_cores": len(allowed),
+        "cpu_model": _cpu_model(),
     }
 
 
