@@ -497,22 +497,48 @@ bcf_status launch_tables(Bufs kb, Bufs vb, char *temp, const TablePlan &P, hipSt
 }
 
 // Segments at least this long are block-sorted in multi-wave group tiles
-// (fewer merge passes); shorter ones in 4096-key wave tiles.
-uint64_t group_min_keys(bool pairs)
+// (fewer merge passes); shorter ones in 4096-key wave tiles.  `knob` is the
+// tuning's group_min_keys (0: the library default).
+uint64_t group_min_keys(bool pairs, uint64_t knob)
 {
-    const uint64_t g = tuning().group_min_keys;
-    return g ? g : group_run_keys(pairs) / 2;
+    return knob ? knob : group_run_keys(pairs) / 2;
+}
+
+// Plans uploaded by bcf_segmented_upload, by temp buffer: a fingerprint of the
+// offsets and flags, and the tuning the plan was made under.  The execute call
+// replans on the host with that same tuning (never the tuning current at
+// execute time) and refuses offsets that differ from the uploaded ones.
+struct UploadedPlan {
+    uint64_t fingerprint;
+    uint64_t group_min_keys;
+};
+std::mutex g_plans_mu;
+std::map<const void *, UploadedPlan> g_plans;
+
+uint64_t plan_fingerprint(const uint64_t *off, uint32_t nseg, bool pairs)
+{
+    uint64_t h = 0xcbf29ce484222325ull ^ (pairs ? 0x9e37u : 0u);  // FNV-1a over the offsets
+    auto mix = [&h](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 0x100000001b3ull;
+        }
+    };
+    mix(nseg);
+    for (uint32_t i = 0; i <= nseg; ++i)
+        mix(off[i]);
+    return h;
 }
 
 // Plan of a segmented sort: every segment is block-sorted into runs that
 // never cross its boundaries, then merged pairwise until one run remains.
 // X_j(s), the buffer holding segment s after its pass j, alternates so that
 // its last pass lands in the output.
-bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, TablePlan &P)
+bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, uint64_t gmin_knob, TablePlan &P)
 {
     P.pairs = pairs;
     const uint64_t n = off[nseg];
-    const uint64_t gmin = group_min_keys(pairs);
+    const uint64_t gmin = group_min_keys(pairs, gmin_knob);
     const uint64_t grun = group_run_keys(pairs);
     std::vector<uint32_t> ps(nseg, 0);
     std::vector<uint64_t> run0(nseg, kTile);
@@ -573,8 +599,17 @@ bcf_status segmented_impl(SegMode mode, bool pairs, const uint32_t *kin, const u
     }
     if (!offsets_valid(off, nseg))
         return BCF_ERR_INVALID;
+    uint64_t gmin = tuning().group_min_keys;
+    if (mode == kSegExecute && temp && off[nseg] != 0) {
+        // the tuning of the upload into this temp buffer, for the same offsets
+        std::lock_guard<std::mutex> g(g_plans_mu);
+        auto it = g_plans.find(temp);
+        if (it == g_plans.end() || it->second.fingerprint != plan_fingerprint(off, nseg, pairs))
+            return BCF_ERR_INVALID;
+        gmin = it->second.group_min_keys;
+    }
     TablePlan P;
-    BCF_TRY(plan_segmented(off, nseg, pairs, P));
+    BCF_TRY(plan_segmented(off, nseg, pairs, gmin, P));
     const uint64_t n = off[nseg];
     if (!temp) {
         *temp_bytes = P.L.total;
@@ -587,8 +622,11 @@ bcf_status segmented_impl(SegMode mode, bool pairs, const uint32_t *kin, const u
     char *tb = static_cast<char *>(temp);
     if (mode != kSegExecute)
         BCF_TRY(upload_tables(tb, P, s));
-    if (mode == kSegUpload)
+    if (mode == kSegUpload) {
+        std::lock_guard<std::mutex> g(g_plans_mu);
+        g_plans[temp] = UploadedPlan{plan_fingerprint(off, nseg, pairs), gmin};
         return BCF_OK;
+    }
     if (!kin || !kout || (pairs && (!vin || !vout)))
         return BCF_ERR_INVALID;
     Bufs kb{kin, kout, reinterpret_cast<uint32_t *>(tb)};
@@ -695,8 +733,11 @@ namespace {
 
 // Stable merge of groups of consecutive sorted runs, each group on its own:
 // group g is runs [group_starts[g], group_starts[g+1]) (one group of all k runs
-// when group_starts is NULL).  Every pass pairs the current runs of every
-// group; a group left with one run is copied through the remaining passes.
+// when group_starts is NULL).  Every group takes its own number of binary
+// passes, ceil(log2(its nonempty runs)), with its own buffer parity so that its
+// last pass lands in the output: a group of one run is copied once (not at
+// all when merging in place), and a group that finishes early is not read and
+// written again by the passes other groups still need.
 bcf_status merge_groups_impl(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
                              uint32_t k, const uint32_t *group_starts, uint32_t ngroups, uint32_t *keys_out,
                              uint32_t *vals_out, void *temp, uint64_t *temp_bytes, void *stream)
@@ -721,51 +762,63 @@ bcf_status merge_groups_impl(const uint32_t *keys_in, const uint32_t *vals_in, c
     const uint32_t ng = group_starts ? ngroups : 1;
     const bool pairs = vals_in != nullptr;
     const uint64_t n = run_offsets[k];
+    // In place (keys or values), a group whose pass count is odd would make its
+    // first pass read and write the same buffer; such a group takes one more
+    // pass, a copy from temp into the output.
+    const bool inplace = keys_in == keys_out || (pairs && vals_in == vals_out);
     // nonempty runs of every group, in order (empty runs change nothing,
     // stability included)
-    std::vector<std::vector<std::pair<uint64_t, uint64_t>>> cur(ng);
-    uint32_t P = 0;
+    std::vector<std::vector<std::pair<uint64_t, uint64_t>>> runs0(ng);
     for (uint32_t g = 0; g < ng; ++g) {
         const uint32_t r0 = group_starts ? group_starts[g] : 0, r1 = group_starts ? group_starts[g + 1] : k;
         for (uint32_t r = r0; r < r1; ++r)
             if (run_offsets[r + 1] > run_offsets[r])
-                cur[g].push_back({run_offsets[r], run_offsets[r + 1] - run_offsets[r]});
-        if (cur[g].size() > 1)
-            P = std::max(P, ceil_log2(cur[g].size()));
+                runs0[g].push_back({run_offsets[r], run_offsets[r + 1] - run_offsets[r]});
     }
-    // In place (keys or values) with an odd pass count would make pass 1 read
-    // and write the same buffer; then every pass is shifted by one buffer and
-    // a final copy moves the result from temp to the output.
-    const bool inplace = keys_in == keys_out || (pairs && vals_in == vals_out);
-    const bool shift = inplace && (P % 2 == 1);
-    // buffer after pass j (j >= 1): counted back from the last pass
-    auto buf_after = [&](uint32_t j) -> uint32_t {
-        const bool at_out = ((P - j) % 2 == 0) != shift;
-        return at_out ? kBufOut : kBufTemp;
-    };
-    std::vector<MergePass> passes(P);
-    for (uint32_t j = 1; j <= P; ++j) {
-        const uint32_t src = j == 1 ? kBufIn : buf_after(j - 1);
-        const uint32_t dst = buf_after(j);
-        for (auto &runs : cur) {
-            std::vector<std::pair<uint64_t, uint64_t>> next;
-            for (size_t i = 0; i < runs.size(); i += 2) {
-                const uint64_t a = runs[i].first, na = runs[i].second;
-                const uint64_t nb = i + 1 < runs.size() ? runs[i + 1].second : 0;
-                add_job(passes[j - 1], a, na, nb, src, dst);
-                next.push_back({a, na + nb});
-            }
-            runs.swap(next);
+    // The plan for in-place or separate buffers (worst: every extra copy pass
+    // of either, so that the temp size does not depend on the pointers).
+    auto plan = [&](bool in_place, bool worst, TablePlan &TP) {
+        std::vector<std::vector<std::pair<uint64_t, uint64_t>>> cur = runs0;
+        std::vector<uint32_t> gp(ng, 0);
+        uint32_t P = 0;
+        for (uint32_t g = 0; g < ng; ++g) {
+            const uint32_t merges = cur[g].size() > 1 ? ceil_log2(cur[g].size()) : 0;
+            if (cur[g].empty())
+                gp[g] = 0;
+            else if (merges == 0)
+                gp[g] = (in_place && !worst) ? 0 : 1;  // one copy into the output
+            else
+                gp[g] = merges + ((merges % 2 == 1 && (in_place || worst)) ? 1 : 0);
+            P = std::max(P, gp[g]);
         }
-    }
-    const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
-    TablePlan TP;
-    TP.pairs = pairs;
-    TP.passes = passes;
-    TP.L = layout_tables(P ? data : 0, 0, 0, TP.passes);
-    const TableLayout &L = TP.L;
+        std::vector<MergePass> passes(P);
+        for (uint32_t g = 0; g < ng; ++g) {
+            // buffer of group g after its pass j (j >= 1): its last pass lands in the output
+            auto buf_after = [&](uint32_t j) -> uint32_t { return ((gp[g] - j) % 2 == 0) ? kBufOut : kBufTemp; };
+            auto &runs = cur[g];
+            for (uint32_t j = 1; j <= gp[g]; ++j) {
+                const uint32_t src = j == 1 ? kBufIn : buf_after(j - 1);
+                const uint32_t dst = buf_after(j);
+                const bool copy = runs.size() == 1;  // one run left: this pass copies it
+                std::vector<std::pair<uint64_t, uint64_t>> next;
+                for (size_t i = 0; i < runs.size(); i += (copy ? 1 : 2)) {
+                    const uint64_t a = runs[i].first, na = runs[i].second;
+                    const uint64_t nb = (!copy && i + 1 < runs.size()) ? runs[i + 1].second : 0;
+                    add_job(passes[j - 1], a, na, nb, src, dst);
+                    next.push_back({a, na + nb});
+                }
+                runs.swap(next);
+            }
+        }
+        const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
+        TP.pairs = pairs;
+        TP.passes = std::move(passes);
+        TP.L = layout_tables(P ? data : 0, 0, 0, TP.passes);
+    };
+    TablePlan worst;
+    plan(false, true, worst);
     // small area for the optional sortedness check: run offsets and a flag
-    const uint64_t check_off = L.total;
+    const uint64_t check_off = worst.L.total;
     const uint64_t need = check_off + align256((uint64_t(k) + 1) * sizeof(uint64_t)) + 256;
     if (!temp) {
         *temp_bytes = need;
@@ -777,6 +830,8 @@ bcf_status merge_groups_impl(const uint32_t *keys_in, const uint32_t *vals_in, c
         return BCF_ERR_INVALID;
     if (*temp_bytes < need)
         return BCF_ERR_TEMP_TOO_SMALL;
+    TablePlan TP;
+    plan(inplace, false, TP);
     char *tb = static_cast<char *>(temp);
     uint32_t *kt = reinterpret_cast<uint32_t *>(tb);
     uint32_t *vt = pairs ? reinterpret_cast<uint32_t *>(tb + align256(n * 4)) : nullptr;
@@ -797,26 +852,12 @@ bcf_status merge_groups_impl(const uint32_t *keys_in, const uint32_t *vals_in, c
             return BCF_ERR_UNSORTED_RUN;
     }
 
-    if (P == 0) {
-        // zero or one nonempty run: the merge is a copy
-        if (keys_out != keys_in && hipMemcpyAsync(keys_out, keys_in, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return BCF_ERR_DEVICE;
-        if (pairs && vals_out != vals_in &&
-            hipMemcpyAsync(vals_out, vals_in, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return BCF_ERR_DEVICE;
-        return BCF_OK;
-    }
+    if (TP.passes.empty())
+        return BCF_OK;  // merged in place: every group is already one run
     Bufs kb{keys_in, keys_out, kt};
     Bufs vb{vals_in, vals_out, vt};
     BCF_TRY(upload_tables(tb, TP, s));
-    BCF_TRY(launch_tables(kb, vb, tb, TP, s));
-    if (shift) {
-        if (hipMemcpyAsync(keys_out, kt, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return BCF_ERR_DEVICE;
-        if (pairs && hipMemcpyAsync(vals_out, vt, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return BCF_ERR_DEVICE;
-    }
-    return BCF_OK;
+    return launch_tables(kb, vb, tb, TP, s);
 }
 
 }  // namespace

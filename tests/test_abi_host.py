@@ -243,6 +243,18 @@ def test_segmented_validation_and_query(lib):
     assert need.value > 0
 
 
+def test_segmented_execute_needs_its_upload(lib):
+    """bcf_segmented_execute into a temp buffer that no upload planned (for
+    these offsets) is refused before any launch."""
+    a, p = _offs([0, 100, 5000, 40000])
+    need = ctypes.c_uint64(0)
+    assert lib.bcf_segmented_upload(p, 3, 0, None, ctypes.byref(need), None) == 0
+    fake_temp = ctypes.c_void_p(0x10000)  # never dereferenced: refused first
+    tb = ctypes.c_uint64(need.value)
+    dummy = ctypes.c_void_p(0x20000)
+    assert lib.bcf_segmented_execute(dummy, None, dummy, None, p, 3, fake_temp, ctypes.byref(tb), None) == 1
+
+
 def test_tuning_roundtrip():
     import paper_1306_5076_amd as bcf
 

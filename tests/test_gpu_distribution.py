@@ -120,14 +120,19 @@ def test_full_size_2p26_in_256_runs(bcf, torch_dev, pb):
 
 
 @pytest.mark.parametrize("dist", ["uniform", "dups"])
-def test_merge_run_groups_matches_per_group_merge(bcf, torch_dev, dist):
-    """Batched merge of groups of runs == the oracle's merge of each group."""
+@pytest.mark.parametrize("in_place", [False, True])
+def test_merge_run_groups_matches_per_group_merge(bcf, torch_dev, dist, in_place):
+    """Batched merge of groups of runs == the oracle's merge of each group.
+    Groups of 3, 1, 0, 5, 5, 2 and 1 runs (one with only empty runs) take 2,
+    0, 0, 3, 3, 1 and 0 merge passes of their own (in place, odd counts take
+    one more pass, a copy out of the scratch buffer)."""
     torch, dev = torch_dev
-    sizes = [0, 5, 4096, 4097, 1, 0, 12345, 300, 65536, 7, 0, 0, 999, 2048]
+    sizes = [0, 5, 4096, 4097, 1, 0, 12345, 300, 65536, 7, 0, 0, 999, 2048, 70000, 3, 0, 0, 40000]
     keys, off = workloads.sorted_runs(sizes, seed=21, dist=dist)
-    starts = [0, 3, 4, 4, 9, 14]  # groups of 3, 1, 0, 5 and 5 runs
-    print(f"merge_run_groups {dist} n={keys.size}", flush=True)
-    got = bcf.merge_run_groups(torch.from_numpy(keys).to(dev), off, starts).cpu().numpy()
+    starts = [0, 3, 4, 4, 9, 14, 16, 17, 19]
+    print(f"merge_run_groups {dist} n={keys.size} in_place={in_place}", flush=True)
+    kd = torch.from_numpy(keys).to(dev)
+    got = bcf.merge_run_groups(kd, off, starts, keys_out=kd if in_place else None).cpu().numpy()
     want = np.empty_like(keys)
     for g in range(len(starts) - 1):
         a, b = starts[g], starts[g + 1]
