@@ -34,14 +34,18 @@ import os
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(PKG, "csrc", f) for f in ("bcf_device.hpp", "bcf_kernels.hip", "bcf_internal.hpp")]
+# every source of the library (kernels and the host code that picks launch
+# shapes), so that any change to them marks committed counter summaries stale
+KERNEL_SOURCES = sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")) + glob.glob(os.path.join(PKG, "csrc", "*.hpp")))
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
 def kernel_source_hash() -> str:
-    """First 16 hex digits of the SHA-256 of the device sources."""
+    """First 16 hex digits of the SHA-256 of the library's sources (file names
+    and contents, in name order)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
+        h.update(os.path.basename(p).encode())
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
