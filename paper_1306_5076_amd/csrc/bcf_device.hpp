@@ -295,6 +295,88 @@ __device__ __forceinline__ void to_strided_reversed(Lines<false> &t, uint32_t *l
     exchange<1, -kLdsStride>(t.k, lds, kLdsStride * lane, kLdsStride * (kLine - 1) + (kWave - 1) - lane);
 }
 
+// ------------------------------------------ half-width transposes (9 KiB LDS)
+//
+// The same STRIDED <-> BLOCKED transposes with half the LDS: view the tile as
+// the 64 x 64 matrix M[register][lane].  v_permlane32_swap on registers r and
+// r + 32 (r < 32) exchanges the upper half-wave of register r with the lower
+// half-wave of register r + 32, which swaps the off-diagonal 32 x 32 quadrants
+// of M; afterwards each half-wave holds two 32 x 32 blocks (registers 0..31
+// and 32..63) that only need transposing inside the half-wave.  Each block
+// goes through a 32-row LDS matrix per half-wave (rows of 36 words), one
+// block after the other, so a wave needs 2 x 32 x 36 words instead of
+// 64 x 68.  Accesses stay conflict-free on the measured geometry: 4-byte
+// writes / reads of word 36r + l' (32 consecutive words per half-wave), and
+// 16-byte reads / writes of word 36l' + c, c a multiple of 4 (36 = 4 mod 32:
+// any 8 consecutive lanes cover the 32 banks once).
+constexpr int kHalfRows = 32;
+constexpr int kHalfStride = 36;
+constexpr int kHalfLdsWords = 2 * kHalfRows * kHalfStride;  // per wave: 9 KiB
+
+// Exchange the upper half-wave of register r with the lower half-wave of
+// register r + 32, for r = 0..31.
+__device__ __forceinline__ void swap_quadrants(uint32_t (&x)[kLine])
+{
+#pragma unroll
+    for (int r = 0; r < kLine / 2; ++r) {
+        const auto p = __builtin_amdgcn_permlane32_swap(x[r], x[r + kLine / 2], false, false);
+        x[r] = p[0];
+        x[r + kLine / 2] = p[1];
+    }
+}
+
+// This half-wave's 32 x 36-word LDS matrix.
+__device__ __forceinline__ uint32_t *half_matrix(uint32_t *lds, uint32_t lane)
+{
+    return lds + (lane >> 5) * (kHalfRows * kHalfStride);
+}
+
+// Transpose the 32 x 32 block in registers R0..R0+31 inside each half-wave:
+// the STRIDED side (register r, lane l') at word 36r + l', the BLOCKED side
+// (lane l', register c) at word 36l' + c.  S2B: STRIDED side in, BLOCKED
+// side out; else the reverse.
+template <int R0, bool S2B>
+__device__ __forceinline__ void half_block_transpose(uint32_t (&x)[kLine], uint32_t *lds, uint32_t lane)
+{
+    uint32_t *m = half_matrix(lds, lane);
+    const uint32_t l = lane & 31;
+    uint32_t *row = static_cast<uint32_t *>(__builtin_assume_aligned(m + kHalfStride * l, 16));
+    if constexpr (S2B) {
+#pragma unroll
+        for (int r = 0; r < kHalfRows; ++r)
+            m[kHalfStride * r + l] = x[R0 + r];
+        wave_lds_fence();
+#pragma unroll
+        for (int c = 0; c < kHalfRows; ++c)
+            x[R0 + c] = row[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < kHalfRows; ++c)
+            row[c] = x[R0 + c];
+        wave_lds_fence();
+#pragma unroll
+        for (int r = 0; r < kHalfRows; ++r)
+            x[R0 + r] = m[kHalfStride * r + l];
+    }
+    wave_lds_fence();
+}
+
+// STRIDED -> BLOCKED (keys) through the half-width matrices.
+__device__ __forceinline__ void to_blocked_half(Lines<false> &t, uint32_t *lds, uint32_t lane)
+{
+    swap_quadrants(t.k);
+    half_block_transpose<0, true>(t.k, lds, lane);
+    half_block_transpose<kLine / 2, true>(t.k, lds, lane);
+}
+
+// BLOCKED -> STRIDED (keys) through the half-width matrices.
+__device__ __forceinline__ void to_strided_half(Lines<false> &t, uint32_t *lds, uint32_t lane)
+{
+    half_block_transpose<0, false>(t.k, lds, lane);
+    half_block_transpose<kLine / 2, false>(t.k, lds, lane);
+    swap_quadrants(t.k);
+}
+
 // ---------------------------------------------------------------- wave utils
 
 // The value of x, hidden from the optimiser.  Persistent kernels re-derive

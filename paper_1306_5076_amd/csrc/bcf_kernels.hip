@@ -1214,37 +1214,44 @@ __global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src 
 // merge(AB, CD), equal keys in run order) for one read and one write of the
 // data instead of two of each.  Neither AB nor CD is ever written.
 //
-// Work split.  The four-way merge path of a group is cut at every multiple
-// of kCutStep of AB and at every multiple of kCutStep plus kCutOffset of CD.
-// An AB cut at x takes the A/B split of x from the binary co-rank, reads the
-// key k = AB[x] and counts the C and D keys below k (C and D keys equal to k
-// come after it): two searches in single sorted runs, no search inside a
-// virtual sequence.  A CD cut is the same with the roles swapped (A and B
-// keys equal to k come before it).  Consecutive cuts bound one merge item:
-// at most kCutStep elements of AB and at most kCutStep of CD, found without
-// any nested search.  The offset puts the CD cuts between the AB cuts when
-// the runs interleave, so that an item's two sides often hold at most 2048
-// keys each; such an item takes two merge networks instead of three.
-//
-// Positions in path order: an AB cut (x, y) comes after exactly the CD cuts
-// with kCutStep c' + kCutOffset < y, a CD cut (x, y) after exactly the AB
-// cuts with kCutStep c < x, so every cut computes its own slot in the list.
+// Work split.  Point (x, y) of a group's four-way merge path is the moment
+// when x elements of AB and y of CD have been output.  The path is cut
+//   * at every AB position x = kAbStep j (an AB cut: the binary co-rank of A
+//     and B at x gives the A/B split, the key k = AB[x] is read, and y counts
+//     the C and D keys below k, which come after it), and
+//   * at every CD position y = kCdStep m (a CD cut: the same with the roles
+//     swapped; A and B keys equal to its key come before it).
+// Both kinds need only searches in single sorted runs, none inside a virtual
+// sequence.  Consecutive AB cuts bound a segment: kAbStep elements of AB (the
+// last one fewer) and any number of CD.  A segment whose CD side holds at most
+// kCdStep keys is one merge item; a longer segment is cut again at the CD
+// cuts strictly inside it.  So every item holds at most kAbStep keys of AB and
+// kCdStep of CD and fits one tile, AB in its lower half and CD in its upper
+// half (two networks), and where the runs interleave evenly a segment is one
+// item of about 2 kAbStep outputs however far the path strays from the
+// diagonal.  A CD cut that does not lie strictly inside a long segment starts
+// no item.
 
-constexpr uint32_t kCutStep = 3840;    // a multiple of 64 (block samples)
-constexpr uint32_t kCutOffset = 1920;  // a multiple of 64
 constexpr uint32_t kHalfTile = kTile / 2;
+constexpr uint32_t kAbStep = 1920;  // a multiple of 64 (block samples), at most kHalfTile
+constexpr uint32_t kCdStep = 2048;  // a multiple of 64, at most kHalfTile
+static_assert(kAbStep % kLine == 0 && kCdStep % kLine == 0 && kAbStep <= kHalfTile && kCdStep <= kHalfTile,
+              "cut steps");
 
-// Cut searches of a full group of four runs of L keys.
-__host__ __device__ constexpr uint64_t cuts_per_group(uint64_t L)
+// AB segments of a group whose AB side holds nab keys (at least one, so that
+// a group with an empty AB side still has an item), and its interior CD cuts
+// (CD positions kCdStep m with 0 < kCdStep m < ncd).
+__host__ __device__ constexpr uint32_t ab_segments(uint64_t nab)
 {
-    return (2 * L + kCutStep - 1) / kCutStep + (2 * L - kCutOffset + kCutStep - 1) / kCutStep;
+    return nab > kAbStep ? (uint32_t)((nab + kAbStep - 1) / kAbStep) : 1u;
 }
+__host__ __device__ constexpr uint32_t cd_cuts(uint64_t ncd) { return ncd ? (uint32_t)((ncd - 1) / kCdStep) : 0u; }
 
 // The runs of group g of a fan-in 4 pass over n keys with runs of L.
 struct Group4 {
     uint64_t start;  // array position of A[0]
     uint32_t n[4];   // lengths of A, B, C, D (runs past the end are empty)
-    uint32_t ab_cuts, cd_cuts;
+    uint32_t J, M;   // AB segments, interior CD cuts
     __device__ Group4(uint64_t nkeys, uint64_t L, uint32_t g)
     {
         start = (uint64_t)g * 4 * L;
@@ -1254,20 +1261,23 @@ struct Group4 {
             const uint64_t rem = nkeys > s ? nkeys - s : 0;
             n[r] = (uint32_t)(rem < L ? rem : L);
         }
-        const uint32_t nab = n[0] + n[1], ncd = n[2] + n[3];
-        ab_cuts = (nab + kCutStep - 1) / kCutStep;
-        cd_cuts = ncd > kCutOffset ? (ncd - kCutOffset + kCutStep - 1) / kCutStep : 0;
+        J = ab_segments((uint64_t)n[0] + n[1]);
+        M = cd_cuts((uint64_t)n[2] + n[3]);
     }
 };
 
+// Cut list of a pass: per group, the AB cuts P[0..jfull] (P[0] = nothing
+// taken, P[J] = everything) followed by the CD cuts Q[0..mfull] (Q[0] unused),
+// each as the counts (a, b, c, d) taken from A, B, C and D before the cut.
 struct Merge4Src {
     const uint32_t *ksrc;
     uint32_t *kdst;
     uint64_t n, run;
     uint32_t groups;
-    uint32_t per_group;  // cut searches per full group; merge items are one more
-    uint4 *cuts;         // per group: per_group + 2 cuts of (a, b, c, d)
+    uint32_t jfull, mfull;  // AB segments and interior CD cuts of a full group
+    uint4 *cuts;
     SampleSet in_smp, out_smp;
+    __host__ __device__ uint32_t stride() const { return jfull + mfull + 2; }
 };
 
 // One level of a monotone search by groups of 2^LOGP lanes, each group with
@@ -1308,31 +1318,38 @@ __device__ __forceinline__ void search_level(uint32_t &lo, uint32_t &hi, uint32_
 }
 
 // Cut searches, two per wave: lanes 0..31 take task 2w, lanes 32..63 task
-// 2w + 1; task j of group g is AB cut j (j < ab_cuts) or CD cut j - ab_cuts.
-// A half-wave first finds the binary split of its cut's own side (three
-// sampled levels, 32 probes per round; the diagonal is a multiple of 64, so
-// the first two levels read block samples), reads the cut's key, then counts
-// that key in the other side's two runs with one 16-lane group per run at
-// the same time.  The task with j == 0 also writes the group's first cut
-// (nothing taken) and last cut (all taken).
+// 2w + 1; task t of group g is AB cut t + 1 (t < jfull - 1) or CD cut
+// t - jfull + 2.  A half-wave first finds the binary split of its cut's own
+// side (three sampled levels, 32 probes per round; the cut position is a
+// multiple of 64, so the first two levels read block samples), reads the
+// cut's key, then counts that key in the other side's two runs with one
+// 16-lane group per run at the same time.  Task 0 of a group also writes the
+// group's end points P[0] and P[J].
 __global__ __launch_bounds__(256) void k_cuts4(Merge4Src src)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t half = lane >> 5;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    const uint32_t per = src.jfull - 1 + src.mfull;  // cut searches of a full group
     const uint32_t task = 2 * wave + half;
-    const uint32_t g = task / src.per_group, j = task % src.per_group;
+    const uint32_t g = task / per, t = task % per;
     const bool in_range = g < src.groups;
     const Group4 G(src.n, src.run, in_range ? g : 0);
-    const bool valid = in_range && j < G.ab_cuts + G.cd_cuts;
+    uint4 *cuts = src.cuts + (uint64_t)(in_range ? g : 0) * src.stride();
+    if (in_range && t == 0 && (lane & 31) == 0) {
+        cuts[0] = make_uint4(0, 0, 0, 0);
+        cuts[G.J] = make_uint4(G.n[0], G.n[1], G.n[2], G.n[3]);
+    }
+    const bool ab = t + 1 < src.jfull;
+    const uint32_t idx = ab ? t + 1 : t + 2 - src.jfull;  // AB cut j or CD cut m
+    const bool valid = in_range && (ab ? idx < G.J : idx <= G.M);
     if (__ballot(valid) == 0)
         return;
     const uint64_t L = src.run;
     const SampleSet &sm = src.in_smp;
-    const bool ab = j < G.ab_cuts;
     const uint32_t r0 = ab ? 0 : 2;  // first run of the cut's own side
     const uint32_t n0 = ab ? G.n[0] : G.n[2], n1 = ab ? G.n[1] : G.n[3];
-    const uint32_t d = ab ? j * kCutStep : (j - G.ab_cuts) * kCutStep + kCutOffset;
+    const uint32_t d = ab ? idx * kAbStep : idx * kCdStep;
     const uint64_t apos = G.start + r0 * L, bpos = apos + n0;
     const uint32_t *A = src.ksrc + apos, *B = A + n0;
     uint32_t lo = d > n1 ? d - n1 : 0, hi = d < n0 ? d : n0;
@@ -1365,233 +1382,203 @@ __global__ __launch_bounds__(256) void k_cuts4(Merge4Src src)
     const uint32_t q0 = __builtin_amdgcn_readlane(rlo, 0), q1 = __builtin_amdgcn_readlane(rlo, 16);
     const uint32_t q2 = __builtin_amdgcn_readlane(rlo, 32), q3 = __builtin_amdgcn_readlane(rlo, 48);
     const uint32_t o0 = half ? q2 : q0, o1 = half ? q3 : q1;
-    if (!valid || (lane & 31) > 2)
+    if (!valid || (lane & 31) != 0)
         return;
-    uint4 cut;
-    uint32_t slot;
-    if (ab) {
-        const uint32_t y = o0 + o1;
-        const uint32_t before = y > kCutOffset ? (y - kCutOffset + kCutStep - 1) / kCutStep : 0;
-        cut = make_uint4(s0, s1, o0, o1);
-        slot = 1 + j + (before < G.cd_cuts ? before : G.cd_cuts);
-    } else {
-        const uint32_t x = o0 + o1;
-        const uint32_t before = (x + kCutStep - 1) / kCutStep;
-        cut = make_uint4(o0, o1, s0, s1);
-        slot = 1 + (j - G.ab_cuts) + (before < G.ab_cuts ? before : G.ab_cuts);
-    }
-    uint4 *cuts = src.cuts + (uint64_t)g * (src.per_group + 2);
-    if ((lane & 31) == 0)
-        cuts[slot] = cut;
-    if (j == 0 && (lane & 31) == 1)
-        cuts[0] = make_uint4(0, 0, 0, 0);
-    if (j == 0 && (lane & 31) == 2)
-        cuts[1 + G.ab_cuts + G.cd_cuts] = make_uint4(G.n[0], G.n[1], G.n[2], G.n[3]);
+    if (ab)
+        cuts[idx] = make_uint4(s0, s1, o0, o1);
+    else
+        cuts[src.jfull + 1 + idx] = make_uint4(o0, o1, s0, s1);
 }
 
-// The merge network of a bitonic STRIDED tile, ending in STRIDED order
-// (REV: with the positions reversed).
-template <bool REV>
+// The four-way merge works with the half-width transposes (9 KiB of LDS per
+// wave, see to_blocked_half): with its registers held to 128 four waves fit
+// per SIMD, so loads of some items overlap the networks of others.
+
+// Half-cleaners on position bits 11..6 of a STRIDED tile (register bits),
+// then the transpose to BLOCKED and bits 5..0: a bitonic tile ends sorted in
+// BLOCKED layout.
 __device__ __forceinline__ void merge4_network(Lines<false> &t, uint32_t *lds, uint32_t lane)
 {
     half_clean<kLine / 2, -1, false>(t);
-    to_blocked(t, lds, lane);
+    to_blocked_half(t, lds, lane);
     half_clean<kLine / 2, -1, false>(t);
-    if constexpr (REV)
-        to_strided_reversed(t, lds, lane);
-    else
-        to_strided(t, lds, lane);
 }
 
-// Store `count` sorted keys of a STRIDED tile at array position gpos and the
-// samples of the output that fall inside it: the first and last key of every
-// 64-key block and every 4096-key tile of the array.  The tile's last
-// to_strided left tile position 64q + r in LDS word 68q + r.
-template <bool NT>
-__device__ __forceinline__ void emit4(const Lines<false> &t, const uint32_t *lds, uint32_t *kdst, uint64_t gpos,
-                                      uint32_t count, const SampleSet &smp, uint32_t lane)
+// Word i (0..3) of a 16-byte LDS read, for a wave-uniform i.
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, uint32_t i)
 {
-    if (smp.f != nullptr) {
-        const uint32_t bf = (uint32_t)((kLine - gpos % kLine) % kLine);  // first block start in the tile
-        const uint32_t bl = (bf + kLine - 1) % kLine;                    // first block end
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// A sorted BLOCKED tile to the array: back to STRIDED through the half-width
+// matrices, then `count` keys stored at array position gpos, with the samples
+// of the output that fall inside it (first and last key of every 64-key block
+// and every 4096-key tile of the array).  Tile position bf + 64k starts a
+// block of the array and bl + 64k ends one (bf = -gpos mod 64, bl = bf - 1
+// mod 64): in BLOCKED layout that is register bf (bl) of lane k, read back
+// from the LDS matrix while it holds the lane's registers (16-byte reads, one
+// per sample: no bank conflicts).
+template <bool NT>
+__device__ __forceinline__ void emit_blocked(Lines<false> &t, uint32_t *lds, uint32_t *kdst, uint64_t gpos,
+                                             uint32_t count, const SampleSet &smp, uint32_t lane)
+{
+    const uint32_t bf = (uint32_t)((kLine - gpos % kLine) % kLine);
+    const uint32_t bl = (bf + kLine - 1) % kLine;
+    uint32_t *m = half_matrix(lds, lane);
+    const uint32_t li = lane & 31;
+    uint32_t *row = static_cast<uint32_t *>(__builtin_assume_aligned(m + kHalfStride * li, 16));
+    const uint4 *row4 = reinterpret_cast<const uint4 *>(row);
+    const bool want = smp.f != nullptr;
+    uint32_t f = 0, l = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        constexpr int H = kLine / 2;
+#pragma unroll
+        for (int c = 0; c < H; ++c)
+            row[c] = t.k[h * H + c];
+        wave_lds_fence();
+        if (want && bf / H == (uint32_t)h)
+            f = word_of(row4[(bf % H) / 4], bf % 4);
+        if (want && bl / H == (uint32_t)h)
+            l = word_of(row4[(bl % H) / 4], bl % 4);
+#pragma unroll
+        for (int r = 0; r < H; ++r)
+            t.k[h * H + r] = m[kHalfStride * r + li];
+        wave_lds_fence();
+    }
+    swap_quadrants(t.k);
+    lane = opaque(lane);
+    if (want) {
         const uint32_t pf = bf + kLine * lane, pl = bl + kLine * lane;
-        if (pf < count)
-            smp.f[(gpos + pf) / kLine] = lds[kLdsStride * lane + bf];
-        if (pl < count)
-            smp.l[(gpos + pl) / kLine] = lds[kLdsStride * lane + bl];
-        if (smp.cf != nullptr) {
-            const uint32_t tf = (uint32_t)((kTile - gpos % kTile) % kTile);
-            const uint32_t tl = (tf + kTile - 1) % kTile;
-            if (lane == 0 && tf < count)
-                smp.cf[(gpos + tf) / kTile] = lds[kLdsStride * (tf / kLine) + tf % kLine];
-            if (lane == 1 && tl < count)
-                smp.cl[(gpos + tl) / kTile] = lds[kLdsStride * (tl / kLine) + tl % kLine];
+        if (pf < count) {
+            const uint64_t gp = gpos + pf;
+            smp.f[gp / kLine] = f;
+            if (smp.cf != nullptr && gp % kTile == 0)
+                smp.cf[gp / kTile] = f;
+        }
+        if (pl < count) {
+            const uint64_t gp = gpos + pl;
+            smp.l[gp / kLine] = l;
+            if (smp.cf != nullptr && gp % kTile == kTile - 1)
+                smp.cl[gp / kTile] = l;
         }
     }
     store_tile<false, NT>(t, kdst + gpos, nullptr, count, lane);
 }
 
-// The padding tile (every position the maximum key).
-__device__ __forceinline__ void pad_tile(Lines<false> &t)
-{
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        t.k[r] = kMaxKey;
-}
+// Keys that padding positions load: every one the maximum key.
+__device__ const uint32_t kPadKeys[kWave] = {
+    kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey,
+    kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey,
+    kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey,
+    kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey,
+    kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey,
+    kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey};
 
-// Put a STRIDED tile in LDS the way to_strided leaves it (word 68q + r holds
-// position 64q + r), for emit4 after a side that needed no network.
-__device__ __forceinline__ void stage_tile(const Lines<false> &t, uint32_t *lds, uint32_t lane)
-{
-    lds_put<kLdsStride>(lds + lane, t.k);
-    wave_lds_fence();
-}
+// A merge item's tile: each half of 2048 positions takes a front piece
+// (front[h], fn[h] keys, ascending at positions [0, fn)) and a back piece
+// (bn[h] keys, reversed at [2048 - bn, 2048): position q reads element
+// bend[h] - q), with padding (the maximum key) between; offsets count from
+// the group's first key.  The upper half is XORed with xm (0, or ~0 to
+// complement it: an order-reversing bijection that turns padding into 0).
+struct HalfPieces {
+    uint32_t front[2], fn[2], bend[2], bn[2];
+    uint32_t xm;
+};
 
-// Load pieces X = [x, x + nx) and Y = [y, y + ny) of one array as a bitonic
-// tile (X ascending at the front, Y reversed at the back).  With one piece
-// empty the other is loaded ascending (REV = false: already sorted) or
-// reversed at the back (REV = true: already in the order the final merge of
-// the two sides takes it), and no network is needed.
+// Load an item's tile in STRIDED layout.  Every lane computes one address
+// per register, from the pieces or from kPadKeys, and issues every load
+// before any of them is used.
 template <bool NT>
-__device__ __forceinline__ bool load_side(Lines<false> &t, const uint32_t *x, uint32_t nx, const uint32_t *y,
-                                          uint32_t ny, bool rev, uint32_t lane)
+__device__ __forceinline__ void load_item(Lines<false> &t, const uint32_t *K, const HalfPieces &hp, uint32_t lane)
 {
-    MergeTask<false> m;
-    m.count = nx + ny;
-    if (nx != 0 && ny != 0) {
-        m.ka = x;
-        m.kb = y;
-        m.pa = nx;
-        m.pb = ny;
-        merge_load<false, NT>(t, m, lane);
-        return true;  // two pieces: the side needs its merge network
-    }
-    const uint32_t *one = nx ? x : y;
-    m.ka = one;
-    m.kb = one;
-    m.pa = rev ? 0 : m.count;
-    m.pb = rev ? m.count : 0;
-    merge_load<false, NT>(t, m, lane);
-    return false;
-}
-
-// The high half of an item whose count exceeds 4096 by at most 64: its keys
-// are positions [4096 - sy, sx) of `hi` (V-shaped: reversed T2 falls, T1
-// rises), gathered into one register across the lanes and sorted by a
-// cross-lane bitonic merge (6 stages), then stored with their samples.
-template <bool NT>
-__device__ __forceinline__ void emit_small_hi(const Lines<false> &hi, uint32_t *lds, uint32_t *kdst, uint64_t gpos,
-                                              uint32_t first, uint32_t count, const SampleSet &smp, uint32_t lane)
-{
-    stage_tile(hi, lds, lane);
-    const uint32_t p = first + lane;
-    uint32_t v = lane < count ? lds[kLdsStride * (p / kLine) + p % kLine] : kMaxKey;
-#pragma unroll
-    for (int dist = kWave / 2; dist >= 1; dist /= 2) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, dist);
-        const uint32_t mn = v < o ? v : o, mx = v < o ? o : v;
-        v = (lane & dist) ? mx : mn;
-    }
-    if (lane < count) {
-        const uint64_t gp = gpos + lane;
-        st<NT>(kdst + gp, v);
-        if (smp.f != nullptr) {
-            if (gp % kLine == 0)
-                smp.f[gp / kLine] = v;
-            if (gp % kLine == kLine - 1)
-                smp.l[gp / kLine] = v;
-            if (smp.cf != nullptr && gp % kTile == 0)
-                smp.cf[gp / kTile] = v;
-            if (smp.cf != nullptr && gp % kTile == kTile - 1)
-                smp.cl[gp / kTile] = v;
-        }
-    }
-}
-
-// Load an item whose two sides hold at most 2048 keys each as one tile: AB
-// in positions [0, 2048) (A ascending at the front, B reversed at the back)
-// and CD in [2048, 4096) the same way; padding between.  Offsets are 32-bit
-// from the side's first run (a side spans two runs: less than 2^31 keys).
-template <bool NT>
-__device__ __forceinline__ void load_packed(Lines<false> &t, const uint32_t *K, uint64_t L, const uint4 &c0,
-                                            uint32_t pa, uint32_t pb, uint32_t pc, uint32_t pd, uint32_t lane)
-{
-    const uint32_t *ab = K, *cd = K + 2 * L;
-    const uint32_t bx = (uint32_t)L + c0.y + (kHalfTile - 1), by = (uint32_t)L + c0.w + (kHalfTile - 1);
-    const uint32_t safe_ab = pa ? c0.x : (uint32_t)L + c0.y, safe_cd = pc ? c0.z : (uint32_t)L + c0.w;
-    uint32_t key[kLine];
+    typedef __attribute__((address_space(1))) const uint32_t gkey;
+    const uint32_t ln = opaque(lane);  // positions are not kept for the stores
+    gkey *kg = (gkey *)K, *pad = (gkey *)kPadKeys + ln;
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
-        const uint32_t q = kWave * (r % (kLine / 2)) + lane;  // position in the half
-        const bool lower = r < kLine / 2;
-        const uint32_t n0 = lower ? pa : pc, n1 = lower ? pb : pd;
-        const uint32_t off = q < n0 ? (lower ? c0.x : c0.z) + q
-                                    : (q >= kHalfTile - n1 ? (lower ? bx : by) - q : (lower ? safe_ab : safe_cd));
-        key[r] = ld<NT>((lower ? ab : cd) + off);
+        const int h = r / (kLine / 2);
+        const uint32_t q = kWave * (r % (kLine / 2)) + ln;  // position in the half
+        const bool in_f = q < hp.fn[h], in_b = q >= kHalfTile - hp.bn[h];
+        const uint32_t off = in_f ? hp.front[h] + q : hp.bend[h] - q;
+        gkey *a = (in_f || in_b) ? kg + off : pad;
+        if constexpr (NT)
+            t.k[r] = __builtin_nontemporal_load(a);
+        else
+            t.k[r] = *a;
+        // each address right before its load: only the loaded keys stay live
+        __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int r = 0; r < kLine; ++r) {
-        const uint32_t q = kWave * (r % (kLine / 2)) + lane;
-        const bool lower = r < kLine / 2;
-        const uint32_t n0 = lower ? pa : pc, n1 = lower ? pb : pd;
-        t.k[r] = (q < n0 || q >= kHalfTile - n1) ? key[r] : kMaxKey;
-    }
-}
-
-// BLOCKED -> STRIDED with positions [2048, 4096) reversed (position 2048 + q
-// takes position 4095 - q; the lower half is unchanged).
-__device__ __forceinline__ void to_strided_upper_reversed(Lines<false> &t, uint32_t *lds, uint32_t lane)
-{
-    lds_put<1>(lds + kLdsStride * lane, t.k);
-    wave_lds_fence();
-#pragma unroll
-    for (int r = 0; r < kLine / 2; ++r)
-        t.k[r] = lds[kLdsStride * r + lane];
 #pragma unroll
     for (int r = kLine / 2; r < kLine; ++r)
-        t.k[r] = lds[kLdsStride * (3 * kLine / 2 - 1 - r) + (kWave - 1) - lane];
-    wave_lds_fence();
+        t.k[r] ^= hp.xm;
 }
 
 // Both halves of a packed item merged at once (the network without its top
-// stage: position bits 10..0), the upper half then reversed, so that the
-// tile is AB ascending followed by CD descending: one bitonic sequence.
+// stage: position bits 10..0), back to STRIDED, and the CD half complemented
+// back: AB ascending followed by CD descending, one bitonic sequence.
 __device__ __forceinline__ void packed_network(Lines<false> &t, uint32_t *lds, uint32_t lane)
 {
     half_clean<kLine / 4, -1, false>(t);
-    to_blocked(t, lds, lane);
+    to_blocked_half(t, lds, lane);
     half_clean<kLine / 2, -1, false>(t);
-    to_strided_upper_reversed(t, lds, lane);
+    to_strided_half(t, lds, lane);
+#pragma unroll
+    for (int r = kLine / 2; r < kLine; ++r)
+        t.k[r] = ~t.k[r];
 }
 
 constexpr int kMerge4Waves = 1;  // one wave per work-group (see kMergeTileWaves)
 
-// One wave per merge item: the item's A and B pieces merge into T1 (sorted,
-// padding after), its C and D pieces into T2.  T1 followed by T2 reversed is
-// a bitonic sequence of 8192 slots; its first half-cleaner stage is an
-// elementwise min / max of T1 and reversed T2, and each half is then merged
-// by the 4096-slot network (a high half of at most 64 keys by a cross-lane
-// merge).  A side with one piece is sorted as loaded; an item with one side
-// empty is that side's merge.
+// One wave per merge item (at most kAbStep keys of AB and kCdStep of CD).
+// Items of one nonempty piece are copied; items of two pieces are one binary
+// merge (the first piece ascending, the second reversed, one network); items
+// of three or four pieces load AB into the lower and CD into the upper half
+// of one tile and take two networks (both halves merged at once, then the
+// whole tile).  Keys only: equal keys are indistinguishable, so only the cuts
+// (exact counts) decide which keys an item holds.
 template <bool NT>
-__global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4(Merge4Src src)
+__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(3))) void k_merge4(
+    Merge4Src src)
 {
-    __shared__ __align__(16) uint32_t lds_all[kMerge4Waves][kLdsWords];
+    __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    uint32_t *lds = lds_all[wave];
-    const uint32_t item = blockIdx.x * kMerge4Waves + wave;
-    const uint32_t per = src.per_group + 1;
-    const uint32_t g = item / per, i = item % per;
+    const uint32_t per = src.jfull + src.mfull;  // item slots of a full group
+    const uint32_t g = blockIdx.x / per, i = blockIdx.x % per;
     if (g >= src.groups)
         return;
     const Group4 G(src.n, src.run, g);
-    if (i > G.ab_cuts + G.cd_cuts)
-        return;
-    const uint4 *cuts = src.cuts + (uint64_t)g * (src.per_group + 2);
-    const uint4 c0 = cuts[i], c1 = cuts[i + 1];
-    // every piece inside its run and at most 4096 keys per side (holds for
+    const uint4 *P = src.cuts + (uint64_t)g * src.stride();
+    const uint4 *Q = P + src.jfull + 1;
+    uint4 c0, c1;
+    if (i < src.jfull) {
+        if (i >= G.J)
+            return;
+        c0 = P[i];
+        const uint4 pe = P[i + 1];
+        const uint32_t y0 = c0.z + c0.w, y1 = pe.z + pe.w;
+        if (y1 < y0)
+            return;
+        c1 = y1 - y0 > kCdStep ? Q[y0 / kCdStep + 1] : pe;
+    } else {
+        const uint32_t m = i - src.jfull + 1;
+        if (m > G.M)
+            return;
+        c0 = Q[m];
+        const uint4 qn = m < G.M ? Q[m + 1] : c0;
+        const uint32_t xq = c0.x + c0.y, gm = kCdStep * m;
+        // the segment holding Q[m]: jc, or jc - 1 when P[jc] sits at Q[m]'s AB
+        // position but after it (more CD taken)
+        const uint32_t jc = min(G.J - 1, xq / kAbStep);
+        const uint4 pm = P[jc > 0 ? jc - 1 : 0], pc = P[jc], pn = P[jc + 1];
+        const bool before = jc > 0 && pc.x + pc.y == xq && pc.z + pc.w > gm;
+        const uint4 p0 = before ? pm : pc, p1 = before ? pc : pn;
+        const uint32_t y0 = p0.z + p0.w, y1 = p1.z + p1.w;
+        if (!(y1 > y0 + kCdStep && y0 < gm && gm < y1))
+            return;  // not inside a long segment: the AB item covers it
+        c1 = (m < G.M && kCdStep * (m + 1) < y1) ? qn : p1;
+    }
+    // every piece inside its run, each side within its half tile (holds for
     // cuts written by k_cuts4; checked so that no cut can move a load or a
     // store outside the group)
     if (c0.x > c1.x || c0.y > c1.y || c0.z > c1.z || c0.w > c1.w || c1.x > G.n[0] || c1.y > G.n[1] ||
@@ -1599,68 +1586,37 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4(Merge4Src src)
         return;
     const uint32_t pa = c1.x - c0.x, pb = c1.y - c0.y, pc = c1.z - c0.z, pd = c1.w - c0.w;
     const uint32_t sx = pa + pb, sy = pc + pd, count = sx + sy;
-    if (count == 0 || sx > (uint32_t)kTile || sy > (uint32_t)kTile)
+    if (count == 0 || sx > kHalfTile || sy > kHalfTile)
         return;
     const uint64_t L = src.run;
-    const uint32_t *K = src.ksrc + G.start;
     const uint64_t gpos = G.start + c0.x + c0.y + c0.z + c0.w;
-    if (sx != 0 && sy != 0 && sx <= kHalfTile && sy <= kHalfTile) {
-        // both sides fit half a tile: two networks for the whole item
-        Lines<false> t;
-        load_packed<NT>(t, K, L, c0, pa, pb, pc, pd, lane);
+    const uint32_t pieces = (pa != 0) + (pb != 0) + (pc != 0) + (pd != 0);
+    // offsets from A[0] of the four pieces' first keys
+    const uint32_t oa = c0.x, ob = (uint32_t)L + c0.y, oc = 2 * (uint32_t)L + c0.z, od = 3 * (uint32_t)L + c0.w;
+    HalfPieces hp;
+    if (pieces >= 3) {
+        // A ascending and B reversed in the lower half, C and D likewise in
+        // the upper half, complemented
+        hp = HalfPieces{{oa, oc}, {pa, pc}, {ob + kHalfTile - 1, od + kHalfTile - 1}, {pb, pd}, ~0u};
+    } else {
+        // the first nonempty piece X ascending at the front of the lower half,
+        // the second one Y (if any) reversed at the back of the upper half: a
+        // bitonic tile (one piece: already sorted)
+        const uint32_t ox = pa ? oa : pb ? ob : pc ? oc : od;
+        const uint32_t nx = pa ? pa : pb ? pb : pc ? pc : pd;
+        const uint32_t oy = (pa && pb) ? ob : ((pa || pb) && pc) ? oc : od;
+        const uint32_t ny = pieces == 2 ? count - nx : 0;
+        hp = HalfPieces{{ox, 0}, {nx, 0}, {0, oy + kHalfTile - 1}, {0, ny}, 0u};
+    }
+    Lines<false> t;
+    load_item<NT>(t, src.ksrc + G.start, hp, lane);
+    if (pieces >= 3)
         packed_network(t, lds, lane);
-        merge4_network<false>(t, lds, lane);
-        emit4<NT>(t, lds, src.kdst, gpos, count, src.out_smp, lane);
-        return;
-    }
-    Lines<false> t1, t2;
-    // all loads of both sides first
-    bool net1 = false, net2 = false;
-    if (sx)
-        net1 = load_side<NT>(t1, K + c0.x, pa, K + L + c0.y, pb, false, lane);
+    if (pieces >= 2)
+        merge4_network(t, lds, lane);
     else
-        pad_tile(t1);
-    if (sy)
-        net2 = load_side<NT>(t2, K + 2 * L + c0.z, pc, K + 3 * L + c0.w, pd, sx != 0, lane);
-    else
-        pad_tile(t2);
-    if (sy == 0) {
-        if (net1)
-            merge4_network<false>(t1, lds, lane);
-        else
-            stage_tile(t1, lds, lane);
-        emit4<NT>(t1, lds, src.kdst, gpos, count, src.out_smp, lane);
-        return;
-    }
-    if (sx == 0) {
-        if (net2)
-            merge4_network<false>(t2, lds, lane);
-        else
-            stage_tile(t2, lds, lane);
-        emit4<NT>(t2, lds, src.kdst, gpos, count, src.out_smp, lane);
-        return;
-    }
-    if (net1)
-        merge4_network<false>(t1, lds, lane);
-    if (net2)
-        merge4_network<true>(t2, lds, lane);
-#pragma unroll
-    for (int r = 0; r < kLine; ++r) {
-        const uint32_t a = t1.k[r], b = t2.k[r];
-        t1.k[r] = a < b ? a : b;
-        t2.k[r] = a < b ? b : a;
-    }
-    merge4_network<false>(t1, lds, lane);
-    emit4<NT>(t1, lds, src.kdst, gpos, count < (uint32_t)kTile ? count : (uint32_t)kTile, src.out_smp, lane);
-    if (count > (uint32_t)kTile) {
-        const uint32_t extra = count - kTile;
-        if (extra <= (uint32_t)kWave) {
-            emit_small_hi<NT>(t2, lds, src.kdst, gpos + kTile, kTile - sy, extra, src.out_smp, lane);
-        } else {
-            merge4_network<false>(t2, lds, lane);
-            emit4<NT>(t2, lds, src.kdst, gpos + kTile, extra, src.out_smp, lane);
-        }
-    }
+        to_blocked_half(t, lds, lane);
+    emit_blocked<NT>(t, lds, src.kdst, gpos, count, src.out_smp, lane);
 }
 
 // Order-preserving maps between other 32-bit key types and u32: signed
@@ -1916,7 +1872,7 @@ uint64_t merge4_cut_bytes(uint64_t n, uint64_t run)
     if (run == 0 || run % kTile != 0)
         return 0;
     const uint64_t groups = (n + 4 * run - 1) / (4 * run);
-    return groups * (cuts_per_group(run) + 2) * sizeof(uint4);
+    return groups * ((uint64_t)ab_segments(2 * run) + cd_cuts(2 * run) + 2) * sizeof(uint4);
 }
 
 uint64_t merge4_cut_bytes_max(uint64_t n)
@@ -1937,15 +1893,14 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
     if (n == 0 || run % kTile != 0 || in_smp.f == nullptr || in_smp.l == nullptr || cuts == nullptr)
         return hipErrorInvalidValue;
     const uint64_t groups = (n + 4 * run - 1) / (4 * run);
-    const uint64_t per_group = cuts_per_group(run);
-    Merge4Src src{ksrc, kdst, n, run, (uint32_t)groups, (uint32_t)per_group, static_cast<uint4 *>(cuts), in_smp,
-                  out_smp};
+    Merge4Src src{ksrc, kdst, n, run, (uint32_t)groups, ab_segments(2 * run), cd_cuts(2 * run),
+                  static_cast<uint4 *>(cuts), in_smp, out_smp};
     if (cut_phase) {
-        const uint64_t tasks = groups * per_group;  // two per wave, four waves per block
+        const uint64_t tasks = groups * (src.jfull - 1 + src.mfull);  // two per wave, four waves per block
         hipLaunchKernelGGL(k_cuts4, dim3((uint32_t)((tasks + 7) / 8)), dim3(256), 0, s, src);
         return hipGetLastError();
     }
-    const uint64_t items = groups * (per_group + 1);
+    const uint64_t items = groups * (src.jfull + src.mfull);
     const dim3 grid((uint32_t)((items + kMerge4Waves - 1) / kMerge4Waves)), block(kWave * kMerge4Waves);
     // nontemporal tile traffic only when a pass streams more than the last-level cache
     if (tuning().nontemporal && n * 4.0 * 2 > kLastLevelCacheBytes)

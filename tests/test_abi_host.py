@@ -100,15 +100,17 @@ def test_pass_count_binary_fan_in(lib):
 
 
 def merge4_cut_bytes_max(n):
-    """Cut lists of the four-way passes: per group of four runs of L keys, one
-    cut every 3840 keys of each side (the second side's first at 1920) plus
-    the two ends, 16 bytes each; the largest over both block-sort run lengths."""
+    """Cut lists of the four-way passes: per group of four runs of L keys, the
+    AB cuts (one every 1920 keys of A and B, and both ends) and the CD cuts
+    (one every 2048 keys of C and D strictly inside, one unused slot), 16
+    bytes each; the largest over both block-sort run lengths."""
     most = 0
     for run0 in (4096, 32768):
         run = run0
         while n > 2 * run:
-            per = -(-2 * run // 3840) + -(-(2 * run - 1920) // 3840)
-            most = max(most, -(-n // (4 * run)) * (per + 2) * 16)
+            ab_segments = -(-2 * run // 1920)
+            cd_cuts = (2 * run - 1) // 2048
+            most = max(most, -(-n // (4 * run)) * (ab_segments + 1 + cd_cuts + 1) * 16)
             run *= 4
     return most
 
@@ -334,3 +336,4 @@ def test_merge_run_groups_validation_and_query(lib):
     dec = (ctypes.c_uint32 * 3)(0, 3, 2)  # decreasing
     assert lib.bcf_merge_run_groups(None, None, p, 3, dec, 2, None, None, None, ctypes.byref(need), None) == 1
     assert lib.bcf_merge_run_groups(None, None, p, 3, None, 2, None, None, None, ctypes.byref(need), None) == 1
+

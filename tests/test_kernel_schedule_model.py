@@ -257,6 +257,77 @@ def b128_conflict_free(words):
     return True
 
 
+# Half-width transposes (9 KiB of LDS per wave): v_permlane32_swap on
+# registers r and r + 32 gives register r the lower half-waves of both and
+# register r + 32 their upper half-waves (the swap of the off-diagonal 32 x 32
+# quadrants of M[register][lane]); each half-wave then transposes its two
+# 32 x 32 blocks (registers 0..31, then 32..63) through a 32-row LDS matrix with
+# rows of HALF_STRIDE words: STRIDED side word 36 r + l', BLOCKED side 36 l' + c.
+
+HALF_STRIDE = 36
+
+
+def permlane32_swap(x, y):
+    """v_permlane32_swap_b32 on one register pair (lanes are array rows)."""
+    nx, ny = x.copy(), y.copy()
+    nx[HALF:], ny[:HALF] = y[:HALF], x[HALF:]
+    return nx, ny
+
+
+def swap_quadrants(regs):
+    out = regs.copy()
+    for r in range(E // 2):
+        out[:, r], out[:, r + E // 2] = permlane32_swap(regs[:, r], regs[:, r + E // 2])
+    return out
+
+
+def half_word(lane, row, col):
+    """LDS word of (row, col) of the lane's half-wave matrix."""
+    return (lane // HALF) * HALF * HALF_STRIDE + HALF_STRIDE * row + col
+
+
+def half_block_transpose(regs, r0, s2b):
+    lanes = np.arange(W)
+    lds = {}
+    out = regs.copy()
+    for k in range(HALF):
+        for l in lanes:
+            w = half_word(l, k, l % HALF) if s2b else half_word(l, l % HALF, k)
+            lds[w] = regs[l, r0 + k]
+    for k in range(HALF):
+        for l in lanes:
+            w = half_word(l, l % HALF, k) if s2b else half_word(l, k, l % HALF)
+            out[l, r0 + k] = lds[w]
+    return out
+
+
+def to_blocked_half(regs):
+    x = swap_quadrants(regs)
+    return half_block_transpose(half_block_transpose(x, 0, True), E // 2, True)
+
+
+def to_strided_half(regs):
+    x = half_block_transpose(half_block_transpose(regs, 0, False), E // 2, False)
+    return swap_quadrants(x)
+
+
+def test_half_width_transposes_match_index_permutation():
+    regs = np.arange(T, dtype=np.uint32).reshape(W, E)
+    assert np.array_equal(to_blocked_half(regs), fast_to_blocked(regs))
+    assert np.array_equal(to_strided_half(regs), fast_to_strided(regs))
+    assert np.array_equal(to_strided_half(to_blocked_half(regs)), regs)
+
+
+def test_half_width_transposes_conflict_free_and_fit():
+    lanes = np.arange(W)
+    for k in range(HALF):  # 4-byte STRIDED-side accesses
+        assert b32_conflict_free(half_word(lanes, k, lanes % HALF)), k
+    for c in range(0, HALF, 4):  # 16-byte BLOCKED-side accesses
+        assert b128_conflict_free(half_word(lanes, lanes % HALF, c)), c
+    words = {half_word(l, k, l % HALF) for l in range(W) for k in range(HALF)}
+    assert len(words) == W * HALF and max(words) < 2 * HALF * HALF_STRIDE  # 2304 words = 9 KiB
+
+
 def test_lds_transposes_conflict_free_on_gfx950_geometry():
     lanes = np.arange(W)
     for r in range(E):
@@ -549,13 +620,15 @@ def test_shear_sort_schedule_01_principle_sampled():
 # Model of the four-way merge pass: the merge of runs A, B, C, D (a group of
 # four consecutive runs of length L) is the binary merge of AB = merge(A, B)
 # and CD = merge(C, D).  The pass cuts the four-way merge path at every
-# multiple of CUT_STEP of AB and at every multiple of CUT_STEP plus
-# CUT_OFFSET of CD; each cut is found with binary co-ranks and single-run
-# rank searches only, and the span between consecutive cuts (one merge item)
-# holds at most CUT_STEP elements of AB and at most CUT_STEP of CD.
+# multiple of AB_STEP of AB (AB cuts) and at every multiple of CD_STEP of CD
+# (CD cuts); each cut is found with binary co-ranks and single-run rank
+# searches only.  Consecutive AB cuts bound a segment; a segment whose CD side
+# is longer than CD_STEP is cut again at the CD cuts strictly inside it, so
+# every merge item holds at most AB_STEP elements of AB and CD_STEP of CD and
+# fits one tile (AB in the lower half, CD in the upper half).
 
-CUT_STEP = 3840
-CUT_OFFSET = 1920
+AB_STEP = 1920
+CD_STEP = 2048
 
 
 def bitonic_tile_network(tile):
@@ -603,6 +676,22 @@ def corank_blocks(arr, apos, na, nb, d, probes_per_round=64):
     return lo
 
 
+def tile_from_strided(regs):
+    out = np.empty(W * E, dtype=regs.dtype)
+    lanes = np.arange(W)
+    for r in range(E):
+        out[W * r + lanes] = regs[:, r]
+    return out
+
+
+def strided_from_tile(tile):
+    lanes = np.arange(W)
+    regs = np.empty((W, E), dtype=tile.dtype)
+    for r in range(E):
+        regs[:, r] = tile[W * r + lanes]
+    return regs
+
+
 def packed_item_model(pieces):
     """Both sides of at most 2048 keys: A ascending at the front of the lower
     half, B reversed at its back, C and D the same in the upper half; one
@@ -618,17 +707,12 @@ def packed_item_model(pieces):
     tile[2048:2048 + len(c)] = c
     if len(d):
         tile[T - len(d):] = d[::-1]
-    lanes = np.arange(W)
-    regs = np.empty((W, E), dtype=tile.dtype)
-    for r in range(E):
-        regs[:, r] = tile[W * r + lanes]
+    regs = strided_from_tile(tile)
     apply(regs, half_clean(E // 4, -1))  # register bits 4..0 = position bits 10..6
     regs = fast_to_blocked(regs)
     apply(regs, half_clean(E // 2, -1))
     regs = fast_to_strided(regs)
-    mid = np.empty_like(tile)
-    for r in range(E):
-        mid[W * r + lanes] = regs[:, r]
+    mid = tile_from_strided(regs)
     assert np.array_equal(mid[:2048], np.sort(tile[:2048]))
     assert np.array_equal(mid[2048:], np.sort(tile[2048:]))
     mid[2048:] = mid[2048:][::-1].copy()
@@ -644,80 +728,95 @@ def ceil_div(a, b):
     return -(-a // b)
 
 
+def ab_segments(nab):
+    return ceil_div(nab, AB_STEP) if nab > AB_STEP else 1
+
+
+def cd_cuts(ncd):
+    return (ncd - 1) // CD_STEP if ncd else 0
+
+
 def cuts4_model(arr, n, L, g):
-    """Cut list of group g (start, every AB and CD cut in path order, end)."""
+    """AB cuts P[0..J] and CD cuts Q[1..M] of group g, each as the counts
+    (a, b, c, d) taken from A, B, C and D before the cut."""
     base, (na, nb, nc, nd) = group_runs(n, L, g)
     A, B, C, D = (base + r * L for r in range(4))
-    nab_t, ncd_t = ceil_div(na + nb, CUT_STEP), ceil_div(max(nc + nd - CUT_OFFSET, 0), CUT_STEP)
-    cuts = [None] * (nab_t + ncd_t + 2)
-    cuts[0] = (0, 0, 0, 0)
-    cuts[-1] = (na, nb, nc, nd)
-    for j in range(nab_t):
-        x = CUT_STEP * j
+    J, M = ab_segments(na + nb), cd_cuts(nc + nd)
+    P = [None] * (J + 1)
+    P[0], P[J] = (0, 0, 0, 0), (na, nb, nc, nd)
+    for j in range(1, J):
+        x = AB_STEP * j
         a = corank_blocks(arr, A, na, nb, x)
         b = x - a
         k = arr[A + a] if a < na and (b >= nb or arr[A + a] <= arr[B + b]) else arr[B + b]
-        c, e = rank_sampled(arr, C, nc, k, False), rank_sampled(arr, D, nd, k, False)
-        y = c + e
-        before = min(ceil_div(max(y - CUT_OFFSET, 0), CUT_STEP), ncd_t)
-        assert cuts[1 + j + before] is None
-        cuts[1 + j + before] = (a, b, c, e)
-    for j in range(ncd_t):
-        y = CUT_STEP * j + CUT_OFFSET
+        P[j] = (a, b, rank_sampled(arr, C, nc, k, False), rank_sampled(arr, D, nd, k, False))
+    Q = [None] * (M + 1)
+    for m in range(1, M + 1):
+        y = CD_STEP * m
         c = corank_blocks(arr, C, nc, nd, y)
         e = y - c
         k = arr[C + c] if c < nc and (e >= nd or arr[C + c] <= arr[D + e]) else arr[D + e]
-        a, b = rank_sampled(arr, A, na, k, True), rank_sampled(arr, B, nb, k, True)
-        before = min(ceil_div(a + b, CUT_STEP), nab_t)
-        assert cuts[1 + j + before] is None
-        cuts[1 + j + before] = (a, b, c, e)
-    return cuts
+        Q[m] = (rank_sampled(arr, A, na, k, True), rank_sampled(arr, B, nb, k, True), c, e)
+    return P, Q
+
+
+def items4_model(P, Q):
+    """The merge items of one group, as (first cut, last cut), the way the
+    work-group slots of the merge launch decode them: AB item j for every
+    segment, CD item m for every CD cut strictly inside a long segment."""
+    J, M = len(P) - 1, len(Q) - 1
+    ycd = lambda p: p[2] + p[3]
+    items = []
+    for j in range(J):
+        y0, y1 = ycd(P[j]), ycd(P[j + 1])
+        items.append((P[j], Q[y0 // CD_STEP + 1] if y1 - y0 > CD_STEP else P[j + 1]))
+    for m in range(1, M + 1):
+        xq, gm = Q[m][0] + Q[m][1], CD_STEP * m
+        jc = min(J - 1, xq // AB_STEP)
+        before = jc > 0 and P[jc][0] + P[jc][1] == xq and ycd(P[jc]) > gm
+        js = jc - 1 if before else jc
+        y0, y1 = ycd(P[js]), ycd(P[js + 1])
+        if not (y1 > y0 + CD_STEP and y0 < gm < y1):
+            continue
+        items.append((Q[m], Q[m + 1] if m < M and CD_STEP * (m + 1) < y1 else P[js + 1]))
+    return items
 
 
 def merge4_item_model(arr, n, L, g, c0, c1, out, smp):
-    """One merge item: two half merges, the lo/hi split of their bitonic
-    concatenation, one network per output half, samples at global positions."""
+    """One merge item: a copy (one piece), one binary merge network (two
+    pieces) or the packed tile's two networks (three or four); samples at
+    global positions."""
     base, _ = group_runs(n, L, g)
-    A, B, C, D = (base + r * L for r in range(4))
-    pa, pb, pc, pe = (c1[i] - c0[i] for i in range(4))
-    assert min(pa, pb, pc, pe) >= 0
-    sx, sy = pa + pb, pc + pe
-    assert sx <= CUT_STEP and sy <= CUT_STEP
-    pad = np.iinfo(arr.dtype).max
-    t1 = np.full(T, pad, dtype=arr.dtype)
-    t2 = np.full(T, pad, dtype=arr.dtype)
-    if sx:
-        t1[:sx] = merge_tile_model(arr[A + c0[0]:A + c1[0]], arr[B + c0[1]:B + c1[1]])
-    if sy:
-        t2[:sy] = merge_tile_model(arr[C + c0[2]:C + c1[2]], arr[D + c0[3]:D + c1[3]])
+    starts = [base + r * L for r in range(4)]
+    lens = [c1[i] - c0[i] for i in range(4)]
+    assert min(lens) >= 0
+    pieces = [arr[starts[r] + c0[r]:starts[r] + c0[r] + lens[r]] for r in range(4)]
+    sx, sy = lens[0] + lens[1], lens[2] + lens[3]
+    assert sx <= 2048 and sy <= 2048
     cnt = sx + sy
-    obase = base + sum(c0)
-    if sy == 0:
-        halves = [t1]
-    elif sx == 0:
-        halves = [t2]
-    elif sx <= 2048 and sy <= 2048:
-        halves = [packed_item_model([arr[A + c0[0]:A + c1[0]], arr[B + c0[1]:B + c1[1]],
-                                     arr[C + c0[2]:C + c1[2]], arr[D + c0[3]:D + c1[3]]])]
+    nonempty = [p for p in pieces if len(p)]
+    pad = np.iinfo(arr.dtype).max
+    if len(nonempty) >= 3:
+        tile = packed_item_model(pieces)
         smp["packed"] = smp.get("packed", 0) + 1
+    elif len(nonempty) == 2:
+        tile = np.full(T, pad, dtype=arr.dtype)
+        tile[:cnt] = merge_tile_model(nonempty[0], nonempty[1])[:cnt]
     else:
-        r2 = t2[::-1]
-        halves = [bitonic_tile_network(np.minimum(t1, r2))]
-        if cnt > 4096:
-            halves.append(bitonic_tile_network(np.maximum(t1, r2)))
-    for h, tile in enumerate(halves):
-        hb, hc = obase + 4096 * h, min(cnt - 4096 * h, 4096)
-        out[hb:hb + hc] = tile[:hc]
-        for p in range(hc):  # the kernel writes exactly these sample words
-            gp = hb + p
-            if gp % 64 == 0:
-                smp["f"][gp // 64] = tile[p]
-            if gp % 64 == 63:
-                smp["l"][gp // 64] = tile[p]
-            if gp % 4096 == 0:
-                smp["cf"][gp // 4096] = tile[p]
-            if gp % 4096 == 4095:
-                smp["cl"][gp // 4096] = tile[p]
+        tile = np.full(T, pad, dtype=arr.dtype)
+        tile[:cnt] = nonempty[0]
+    obase = base + sum(c0)
+    out[obase:obase + cnt] = tile[:cnt]
+    for p in range(cnt):  # the kernel writes exactly these sample words
+        gp = obase + p
+        if gp % 64 == 0:
+            smp["f"][gp // 64] = tile[p]
+        if gp % 64 == 63:
+            smp["l"][gp // 64] = tile[p]
+        if gp % 4096 == 0:
+            smp["cf"][gp // 4096] = tile[p]
+        if gp % 4096 == 4095:
+            smp["cl"][gp // 4096] = tile[p]
 
 
 def merge4_pass_model(arr, n, L):
@@ -727,10 +826,16 @@ def merge4_pass_model(arr, n, L):
                                                                           ("cl", 4096))}
     smp["packed"] = 0
     for g in range(ceil_div(n, 4 * L)):
-        cuts = cuts4_model(arr, n, L, g)
-        for i in range(len(cuts) - 1):
-            assert all(cuts[i][r] <= cuts[i + 1][r] for r in range(4)), (g, i)
-            merge4_item_model(arr, n, L, g, cuts[i], cuts[i + 1], out, smp)
+        P, Q = cuts4_model(arr, n, L, g)
+        items = sorted(items4_model(P, Q), key=lambda it: sum(it[0]))
+        cur = (0, 0, 0, 0)
+        for c0, c1 in items:  # the items tile the group's merge path exactly once
+            assert c0 == cur, (g, c0, cur)
+            assert all(c0[r] <= c1[r] for r in range(4)), (g, c0, c1)
+            assert c1[0] + c1[1] - c0[0] - c0[1] <= AB_STEP and c1[2] + c1[3] - c0[2] - c0[3] <= CD_STEP
+            merge4_item_model(arr, n, L, g, c0, c1, out, smp)
+            cur = c1
+        assert cur == P[-1]
     return out, smp
 
 
@@ -753,7 +858,8 @@ def _runs_input(n, L, dist, seed):
 
 
 @pytest.mark.parametrize("n,L", [(4 * 8192, 8192), (4 * 8192 * 2 + 3 * 8192 + 100, 8192), (8192 + 5, 8192),
-                                 (2 * 16384 + 4096, 16384), (4 * 4096 * 3 + 4096 * 2 + 1, 4096)])
+                                 (2 * 16384 + 4096, 16384), (4 * 4096 * 3 + 4096 * 2 + 1, 4096),
+                                 (4 * 4096 + 2 * 4096 + 1000, 4096)])
 @pytest.mark.parametrize("dist", ["random", "dups", "ascending", "descending"])
 def test_merge4_pass_plan(n, L, dist):
     arr = _runs_input(n, L, dist, seed=n + L)
@@ -772,24 +878,36 @@ def test_merge4_pass_plan(n, L, dist):
     del smp["packed"]
 
 
-def test_merge4_items_balanced_on_random_keys():
-    """With CD cuts offset by half a step, random runs give items of about
-    CUT_STEP outputs whose two sides mostly fit 2048 keys each (the packed
-    path: two networks per item).  The share falls for longer runs, whose
-    merge path strays further from the diagonal (about 0.55 at 2^21 keys)."""
-    n, L = 4 * 65536, 65536
+@pytest.mark.parametrize("L", [65536, 1 << 19])
+def test_merge4_items_balanced_on_random_keys(L):
+    """Random runs: nearly every segment is one packed item of about
+    2 AB_STEP outputs, however far the merge path strays from the diagonal
+    (the CD side of a segment stays near AB_STEP keys)."""
+    n = 4 * L
     arr = _runs_input(n, L, "random", seed=5)
-    sizes, packed = [], 0
-    cuts = cuts4_model(arr, n, L, 0)
-    for i in range(len(cuts) - 1):
-        sizes.append(sum(cuts[i + 1]) - sum(cuts[i]))
-        sx = cuts[i + 1][0] + cuts[i + 1][1] - cuts[i][0] - cuts[i][1]
-        sy = cuts[i + 1][2] + cuts[i + 1][3] - cuts[i][2] - cuts[i][3]
-        packed += 0 < sx <= 2048 and 0 < sy <= 2048
+    P, Q = cuts4_model(arr, n, L, 0)
+    items = items4_model(P, Q)
+    sizes = [sum(c1) - sum(c0) for c0, c1 in items]
     assert sum(sizes) == n
-    assert max(sizes) <= 2 * CUT_STEP
-    assert np.median(sizes) > 3000
-    assert packed >= 0.6 * len(sizes)
+    assert len(items) <= 1.02 * len(P)
+    assert np.median(sizes) > 3700
+    packed = sum(1 for c0, c1 in items if sum(1 for r in range(4) if c1[r] > c0[r]) >= 3)
+    assert packed >= 0.98 * len(items)
+
+
+def test_merge4_long_segments_split_at_cd_cuts():
+    """Runs that do not interleave (every C and D key below every A and B key,
+    and the reverse): the segments with a long CD side are cut at every CD cut
+    inside them, so no item exceeds CD_STEP keys of CD, and the items still
+    tile the path exactly once."""
+    L = 32768
+    n = 4 * L
+    for dist in ("ascending", "descending"):
+        arr = _runs_input(n, L, dist, seed=3)
+        P, Q = cuts4_model(arr, n, L, 0)
+        items = items4_model(P, Q)
+        assert len(items) >= ceil_div(2 * L, AB_STEP) + ceil_div(2 * L, CD_STEP) - 2
+        assert all(c1[2] + c1[3] - c0[2] - c0[3] <= CD_STEP for c0, c1 in items)
 
 
 # ---------------------------------------------- long ShearSort over NW waves
