@@ -63,6 +63,26 @@ bcf_status bcf_sort_u32(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n,
                         uint64_t *temp_bytes, void *stream);
 
 /*
+ * bcf_sort_u32 for callers that cannot allocate device memory: code under
+ * hipGraph capture, tight serving loops, harnesses that forbid allocation.
+ * The temporary storage is a library-owned device array of 18 MiB per GPU
+ * (each GPU the library runs on holds its own copy until the process ends),
+ * so the call takes no temp argument and calls no allocating routine.
+ *   keys_in, keys_out  device, n u32 each, as for bcf_sort_u32 (keys_out may
+ *                      equal keys_in); the result is bcf_sort_u32's
+ *   n                  at most BCF_NOALLOC_MAX_KEYS (else BCF_ERR_INVALID,
+ *                      before anything is launched); n == 0 is a no-op
+ *   stream             as for the other calls; its device must be the
+ *                      current device
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other threads) race and give undefined results; calls
+ * ordered on one stream are safe.  Nothing in the array needs to start at
+ * zero.  No per-launch timing events are recorded for this call.
+ */
+#define BCF_NOALLOC_MAX_KEYS (1ull << 22)
+bcf_status bcf_sort_u32_noalloc(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n, void *stream);
+
+/*
  * Stable sort of key/value pairs by key: equal keys keep their input order,
  * i.e. the result is ordered by (key, original index).  An extension of the
  * paper, whose data sets are keys only.

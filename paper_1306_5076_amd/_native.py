@@ -26,6 +26,7 @@ STATUS_NAMES = {
 # every symbol include/bcf.h declares
 EXPORTED = (
     "bcf_sort_u32",
+    "bcf_sort_u32_noalloc",
     "bcf_sort_pairs_u32",
     "bcf_sort_i32",
     "bcf_sort_f32",
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH):
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.bcf_sort_u32.argtypes = [vp, vp, u64, vp, u64p, vp]
     lib.bcf_sort_pairs_u32.argtypes = [vp, vp, vp, vp, u64, vp, u64p, vp]
+    lib.bcf_sort_u32_noalloc.argtypes = [vp, vp, u64, vp]
+    lib.bcf_sort_u32_noalloc.restype = ctypes.c_int
     for f in ("bcf_sort_i32", "bcf_sort_f32"):
         getattr(lib, f).argtypes = [vp, vp, u64, vp, u64p, vp]
         getattr(lib, f).restype = ctypes.c_int

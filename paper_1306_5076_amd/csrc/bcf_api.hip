@@ -52,6 +52,7 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::map<std::string, std::vector<ProfRec>> g_prof;
+thread_local int t_prof_off = 0;  // > 0: this thread's calls record no timing events
 
 struct ProfScope {
     const char *name;
@@ -63,7 +64,7 @@ struct ProfScope {
     {
         {
             std::lock_guard<std::mutex> g(g_prof_mu);
-            on = g_prof_on;
+            on = g_prof_on && t_prof_off == 0;
         }
         if (on) {
             if (hipEventCreate(&a) != hipSuccess) {
@@ -650,6 +651,8 @@ Tuning tuning()
 // and a profiling scope around one launch (recorded only while profiling is on).
 bcf_status upload_host(void *dst, const void *src, size_t bytes, hipStream_t s) { return upload(dst, src, bytes, s); }
 void *prof_begin(const char *name, hipStream_t s, double bytes) { return new ProfScope(name, s, bytes); }
+ProfilingOff::ProfilingOff() { ++t_prof_off; }
+ProfilingOff::~ProfilingOff() { --t_prof_off; }
 void prof_end(void *scope) { delete static_cast<ProfScope *>(scope); }
 }  // namespace bcf
 

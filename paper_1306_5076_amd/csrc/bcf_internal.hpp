@@ -121,6 +121,16 @@ struct Tuning {
 };
 Tuning tuning();
 
+// While an object of this type lives, the calling thread's library calls
+// create and record no per-launch timing events (bcf_profile_enable): for
+// entry points that must not create runtime objects.
+struct ProfilingOff {
+    ProfilingOff();
+    ~ProfilingOff();
+    ProfilingOff(const ProfilingOff &) = delete;
+    ProfilingOff &operator=(const ProfilingOff &) = delete;
+};
+
 // Names used for per-kernel timing records.
 const char *kname_block_sort(bool pairs, bool table);
 const char *kname_partition(bool pairs, bool table);

@@ -337,3 +337,18 @@ def test_merge_run_groups_validation_and_query(lib):
     assert lib.bcf_merge_run_groups(None, None, p, 3, dec, 2, None, None, None, ctypes.byref(need), None) == 1
     assert lib.bcf_merge_run_groups(None, None, p, 3, None, 2, None, None, None, ctypes.byref(need), None) == 1
 
+
+def test_noalloc_sort_limits_without_gpu(lib):
+    """bcf_sort_u32_noalloc refuses sizes past BCF_NOALLOC_MAX_KEYS and NULL
+    pointers before touching the device; n == 0 is a no-op."""
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+BCF_NOALLOC_MAX_KEYS\s+\(1ull\s*<<\s*(\d+)\)", text)
+    assert m is not None
+    max_keys = 1 << int(m.group(1))
+    assert lib.bcf_sort_u32_noalloc(None, None, 0, None) == 0
+    assert lib.bcf_sort_u32_noalloc(None, None, max_keys + 1, None) == 1
+    assert lib.bcf_sort_u32_noalloc(None, None, 2**40, None) == 1
+    assert lib.bcf_sort_u32_noalloc(None, None, 5, None) == 1
+    # the library array holds bcf_sort_u32's temp for the largest size it serves
+    st, need = q_sort(lib, max_keys)
+    assert st == 0 and need <= 18 << 20
