@@ -1404,9 +1404,15 @@ __device__ __forceinline__ void merge4_network(Lines<false> &t, uint32_t *lds, u
     half_clean<kLine / 2, -1, false>(t);
 }
 
-// Word i (0..3) of a 16-byte LDS read, for a wave-uniform i.
-__device__ __forceinline__ uint32_t word_of(const uint4 &v, uint32_t i)
+// Word i (0..3) of the 16 bytes at LDS word w (w a multiple of 4), for a
+// wave-uniform i.  The read is volatile so that the compiler keeps it one
+// 16-byte read: narrowed to the one 4-byte word, lanes 36 words apart would
+// meet 4-way in the banks.
+__device__ __forceinline__ uint32_t lds_word_of_quad(const uint32_t *w, uint32_t i)
 {
+    typedef uint32_t quad __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) const volatile quad lds_quad;
+    const quad v = *(lds_quad *)w;
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
 
@@ -1427,7 +1433,6 @@ __device__ __forceinline__ void emit_blocked(Lines<false> &t, uint32_t *lds, uin
     uint32_t *m = half_matrix(lds, lane);
     const uint32_t li = lane & 31;
     uint32_t *row = static_cast<uint32_t *>(__builtin_assume_aligned(m + kHalfStride * li, 16));
-    const uint4 *row4 = reinterpret_cast<const uint4 *>(row);
     const bool want = smp.f != nullptr;
     uint32_t f = 0, l = 0;
 #pragma unroll
@@ -1438,9 +1443,9 @@ __device__ __forceinline__ void emit_blocked(Lines<false> &t, uint32_t *lds, uin
             row[c] = t.k[h * H + c];
         wave_lds_fence();
         if (want && bf / H == (uint32_t)h)
-            f = word_of(row4[(bf % H) / 4], bf % 4);
+            f = lds_word_of_quad(row + (bf % H) / 4 * 4, bf % 4);
         if (want && bl / H == (uint32_t)h)
-            l = word_of(row4[(bl % H) / 4], bl % 4);
+            l = lds_word_of_quad(row + (bl % H) / 4 * 4, bl % 4);
 #pragma unroll
         for (int r = 0; r < H; ++r)
             t.k[h * H + r] = m[kHalfStride * r + li];
@@ -1466,6 +1471,40 @@ __device__ __forceinline__ void emit_blocked(Lines<false> &t, uint32_t *lds, uin
     store_tile<false, NT>(t, kdst + gpos, nullptr, count, lane);
 }
 
+// An item of one piece (count <= 2048 keys, already sorted) copied to array
+// position gpos with the samples that fall inside it, by coalesced loads and
+// stores: every lane moves the elements lane + 64 k.
+template <bool NT>
+__device__ __forceinline__ void copy4(const uint32_t *x, uint32_t *kdst, uint64_t gpos, uint32_t count,
+                                      const SampleSet &smp, uint32_t lane)
+{
+    constexpr int kRows = kHalfTile / kWave;
+    uint32_t v[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const uint32_t i = kWave * k + lane;
+        v[k] = ld<NT>(x + (i < count ? i : count - 1));  // clamped: always inside the piece
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const uint32_t i = kWave * k + lane;
+        if (i < count) {
+            const uint64_t gp = gpos + i;
+            st<NT>(kdst + gp, v[k]);
+            if (smp.f != nullptr) {
+                if (gp % kLine == 0)
+                    smp.f[gp / kLine] = v[k];
+                if (gp % kLine == kLine - 1)
+                    smp.l[gp / kLine] = v[k];
+                if (smp.cf != nullptr && gp % kTile == 0)
+                    smp.cf[gp / kTile] = v[k];
+                if (smp.cf != nullptr && gp % kTile == kTile - 1)
+                    smp.cl[gp / kTile] = v[k];
+            }
+        }
+    }
+}
+
 // Keys that padding positions load: every one the maximum key.
 __device__ const uint32_t kPadKeys[kWave] = {
     kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey, kMaxKey,
@@ -1488,7 +1527,7 @@ struct HalfPieces {
 
 // Load an item's tile in STRIDED layout.  Every lane computes one address
 // per register, from the pieces or from kPadKeys, and issues every load
-// before any of them is used.
+// before any of them is used (branch-free: one select of two addresses).
 template <bool NT>
 __device__ __forceinline__ void load_item(Lines<false> &t, const uint32_t *K, const HalfPieces &hp, uint32_t lane)
 {
@@ -1531,46 +1570,63 @@ __device__ __forceinline__ void packed_network(Lines<false> &t, uint32_t *lds, u
 constexpr int kMerge4Waves = 1;  // one wave per work-group (see kMergeTileWaves)
 
 // One wave per merge item (at most kAbStep keys of AB and kCdStep of CD).
-// Items of one nonempty piece are copied; items of two pieces are one binary
-// merge (the first piece ascending, the second reversed, one network); items
-// of three or four pieces load AB into the lower and CD into the upper half
-// of one tile and take two networks (both halves merged at once, then the
-// whole tile).  Keys only: equal keys are indistinguishable, so only the cuts
-// (exact counts) decide which keys an item holds.
+// Items of three or four pieces load AB into the lower and CD into the upper
+// half of one tile and take two networks (both halves merged at once, then
+// the whole tile); items of one or two pieces load the first piece ascending
+// at the front and the second reversed at the back (one bitonic tile, already
+// sorted for one piece) and take the second network only; items of one piece
+// are copied (copy4).  The tile code has one branch (around the first
+// network), so the kernel fits 110 registers: four waves per SIMD, as many as
+// the 9 KiB of LDS per wave allow.  Keys only:
+// equal keys are indistinguishable, so only the cuts (exact counts) decide
+// which keys an item holds.
 template <bool NT>
-__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(3))) void k_merge4(
+__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(4))) void k_merge4(
     Merge4Src src)
 {
     __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t per = src.jfull + src.mfull;  // item slots of a full group
-    const uint32_t g = blockIdx.x / per, i = blockIdx.x % per;
+    const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x / per);
+    const uint32_t i = __builtin_amdgcn_readfirstlane(blockIdx.x % per);
     if (g >= src.groups)
         return;
-    const Group4 G(src.n, src.run, g);
+    Group4 G(src.n, src.run, g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        G.n[r] = __builtin_amdgcn_readfirstlane(G.n[r]);
+    G.J = __builtin_amdgcn_readfirstlane(G.J);
+    G.M = __builtin_amdgcn_readfirstlane(G.M);
     const uint4 *P = src.cuts + (uint64_t)g * src.stride();
     const uint4 *Q = P + src.jfull + 1;
+    // a cut is the same in every lane: scalar values, so that every branch
+    // below is a scalar one
+    auto cut = [](const uint4 *p) {
+        const uint4 c = *p;
+        return make_uint4(__builtin_amdgcn_readfirstlane(c.x), __builtin_amdgcn_readfirstlane(c.y),
+                          __builtin_amdgcn_readfirstlane(c.z), __builtin_amdgcn_readfirstlane(c.w));
+    };
     uint4 c0, c1;
     if (i < src.jfull) {
         if (i >= G.J)
             return;
-        c0 = P[i];
-        const uint4 pe = P[i + 1];
+        c0 = cut(P + i);
+        const uint4 pe = cut(P + i + 1);
         const uint32_t y0 = c0.z + c0.w, y1 = pe.z + pe.w;
         if (y1 < y0)
             return;
-        c1 = y1 - y0 > kCdStep ? Q[y0 / kCdStep + 1] : pe;
+        c1 = y1 - y0 > kCdStep ? cut(Q + y0 / kCdStep + 1) : pe;
     } else {
         const uint32_t m = i - src.jfull + 1;
         if (m > G.M)
             return;
-        c0 = Q[m];
-        const uint4 qn = m < G.M ? Q[m + 1] : c0;
+        c0 = cut(Q + m);
+        const uint4 qn = cut(Q + (m < G.M ? m + 1 : m));
         const uint32_t xq = c0.x + c0.y, gm = kCdStep * m;
         // the segment holding Q[m]: jc, or jc - 1 when P[jc] sits at Q[m]'s AB
         // position but after it (more CD taken)
         const uint32_t jc = min(G.J - 1, xq / kAbStep);
-        const uint4 pm = P[jc > 0 ? jc - 1 : 0], pc = P[jc], pn = P[jc + 1];
+        const uint4 pm = cut(P + (jc > 0 ? jc - 1 : 0)), pc = cut(P + jc), pn = cut(P + jc + 1);
         const bool before = jc > 0 && pc.x + pc.y == xq && pc.z + pc.w > gm;
         const uint4 p0 = before ? pm : pc, p1 = before ? pc : pn;
         const uint32_t y0 = p0.z + p0.w, y1 = p1.z + p1.w;
@@ -1593,6 +1649,11 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
     const uint32_t pieces = (pa != 0) + (pb != 0) + (pc != 0) + (pd != 0);
     // offsets from A[0] of the four pieces' first keys
     const uint32_t oa = c0.x, ob = (uint32_t)L + c0.y, oc = 2 * (uint32_t)L + c0.z, od = 3 * (uint32_t)L + c0.w;
+    if (pieces == 1) {
+        // one piece: already sorted, copied as it is (no network, no LDS)
+        copy4<NT>(src.ksrc + G.start + (pa ? oa : pb ? ob : pc ? oc : od), src.kdst, gpos, count, src.out_smp, lane);
+        return;
+    }
     HalfPieces hp;
     if (pieces >= 3) {
         // A ascending and B reversed in the lower half, C and D likewise in
@@ -1600,8 +1661,7 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
         hp = HalfPieces{{oa, oc}, {pa, pc}, {ob + kHalfTile - 1, od + kHalfTile - 1}, {pb, pd}, ~0u};
     } else {
         // the first nonempty piece X ascending at the front of the lower half,
-        // the second one Y (if any) reversed at the back of the upper half: a
-        // bitonic tile (one piece: already sorted)
+        // the second one Y (if any) reversed at the back of the upper half
         const uint32_t ox = pa ? oa : pb ? ob : pc ? oc : od;
         const uint32_t nx = pa ? pa : pb ? pb : pc ? pc : pd;
         const uint32_t oy = (pa && pb) ? ob : ((pa || pb) && pc) ? oc : od;
@@ -1612,10 +1672,7 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
     load_item<NT>(t, src.ksrc + G.start, hp, lane);
     if (pieces >= 3)
         packed_network(t, lds, lane);
-    if (pieces >= 2)
-        merge4_network(t, lds, lane);
-    else
-        to_blocked_half(t, lds, lane);
+    merge4_network(t, lds, lane);
     emit_blocked<NT>(t, lds, src.kdst, gpos, count, src.out_smp, lane);
 }
 
