@@ -1404,6 +1404,24 @@ __device__ __forceinline__ void merge4_network(Lines<false> &t, uint32_t *lds, u
     half_clean<kLine / 2, -1, false>(t);
 }
 
+// Store the first `count` positions of a STRIDED tile (count <= 4096) at dst
+// through a raw buffer resource whose range is those count keys: the memory
+// system drops every store past the range, so no lane is masked per
+// register.  The whole offset of a register (lane + 64 r keys) is passed in the
+// vector offset, the part of the address that the range check covers.
+template <bool NT>
+__device__ __forceinline__ void store_bounded(const Lines<false> &t, uint32_t *dst, uint32_t count, uint32_t lane)
+{
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)(count * 4u), 0x00020000);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        if ((uint32_t)(kWave * r) >= count)
+            break;  // wave-uniform: rows past the end hold padding only
+        const uint32_t off = opaque(4u * (kWave * r + lane));
+        __builtin_amdgcn_raw_buffer_store_b32(t.k[r], rs, (int)off, 0, NT ? 2 : 0);
+    }
+}
+
 // Word i (0..3) of the 16 bytes at LDS word w (w a multiple of 4), for a
 // wave-uniform i.  The read is volatile so that the compiler keeps it one
 // 16-byte read: narrowed to the one 4-byte word, lanes 36 words apart would
@@ -1468,7 +1486,7 @@ __device__ __forceinline__ void emit_blocked(Lines<false> &t, uint32_t *lds, uin
                 smp.cl[gp / kTile] = l;
         }
     }
-    store_tile<false, NT>(t, kdst + gpos, nullptr, count, lane);
+    store_bounded<NT>(t, kdst + gpos, count, lane);
 }
 
 // An item of one piece (count <= 2048 keys, already sorted) copied to array
