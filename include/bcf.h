@@ -11,12 +11,16 @@
  * ---------------------------------------
  *  - Keys are uint32_t compared as unsigned integers; order is ascending
  *    (int32 and float keys: bcf_sort_i32 / bcf_sort_f32 and their pair forms).
- *  - Key/value arrays are device pointers (HBM) owned by the caller.  Offset
- *    arrays (run_offsets, seg_offsets) are HOST pointers: the library plans the
- *    launches on the host from them.
+ *  - Key/value arrays are device pointers (HBM) owned by the caller.  The
+ *    offsets of bcf_merge_runs and bcf_segmented_sort[_pairs] are DEVICE
+ *    pointers: their launch plans are computed on the device (see
+ *    bcf_merge_runs).  The *_host variants, bcf_merge_run_groups,
+ *    bcf_distribute_runs and bcf_segmented_upload / _execute take HOST offset
+ *    arrays and plan on the host.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
  *    call only enqueues work on that stream and returns; it never synchronises
- *    the device.  Faults of earlier asynchronous work can surface as
+ *    the device (except the temp queries of the calls with device offsets,
+ *    which read the total from the device, and BCF_CHECK run checks).  Faults of earlier asynchronous work can surface as
  *    BCF_ERR_DEVICE on a later call.
  *  - Temporary storage: call once with temp == NULL to receive the number of
  *    bytes needed in *temp_bytes (nothing is launched, BCF_OK is returned);
@@ -31,7 +35,9 @@
  *  - n == 0 (or k == 0 / nseg == 0) is a no-op returning BCF_OK.  Sizes above
  *    2^32 - 1 elements return BCF_ERR_INVALID.
  *  - Offsets: off[0] == 0, nondecreasing, off[last] == total length.  Empty
- *    runs / segments are allowed.  Violations return BCF_ERR_INVALID.
+ *    runs / segments are allowed.  Violations of host offsets return
+ *    BCF_ERR_INVALID; device offsets are checked on the device (see
+ *    bcf_merge_runs).
  *  - No C++ exception crosses this boundary.
  */
 #ifndef BCF_H
@@ -139,9 +145,18 @@ bcf_status bcf_sort_u64(const uint64_t *keys_in, uint64_t *keys_out, uint64_t n,
  * earlier position.
  *   keys_in      device, run r occupies [run_offsets[r], run_offsets[r+1])
  *   vals_in      device values carried with the keys, or NULL for keys only
- *   run_offsets  HOST, k+1 entries
+ *   run_offsets  DEVICE, k+1 entries (u64)
  *   keys_out     device, run_offsets[k] u32
  *   vals_out     device (ignored when vals_in is NULL)
+ * The launch plan (every pass's merge jobs and tile map) is computed on the
+ * device from run_offsets, so nothing is read back and the call can be
+ * captured in a graph whose replays see new offsets.  Temp: the query
+ * (temp == NULL) reads run_offsets[k] from the device (it synchronises the
+ * stream) and returns the size for that many keys; at run time the size of
+ * the buffer passed sets the capacity, the most keys the call merges with it
+ * (run_offsets[k] may change between calls and replays within that).
+ * Offsets that are not nondecreasing from 0, or whose total exceeds the
+ * capacity, are found on the device: then nothing is written.
  * Every run must be sorted ascending (precondition).  With the tuning knob
  * check_runs set (environment BCF_CHECK=1) the library checks it and returns
  * BCF_ERR_UNSORTED_RUN (this check synchronises the stream).
@@ -150,11 +165,21 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
                           uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp,
                           uint64_t *temp_bytes, void *stream);
 
+/* bcf_merge_runs with HOST offsets, planned on the host (the plan goes to the
+ * device with one copy through pinned staging); empty runs are dropped from
+ * the plan.  The temp size depends on the offsets, not only on their total. */
+bcf_status bcf_merge_runs_host(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+                               uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp,
+                               uint64_t *temp_bytes, void *stream);
+
 /*
  * Sort every segment [seg_offsets[s], seg_offsets[s+1]) of keys_in
- * independently, with one block-sort launch for all segments and one launch
- * per merge level shared by all segments still being merged.
- *   seg_offsets  HOST, nseg+1 entries
+ * independently (segments of up to 4096 keys in one wave tile, longer ones
+ * block-sorted and then merged within the segment; all segments in one
+ * block-sort launch and one launch per merge level).
+ *   seg_offsets  DEVICE, nseg+1 entries (u64)
+ * Planned on the device, with the temp and capacity conventions of
+ * bcf_merge_runs.
  */
 bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
                               uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream);
@@ -167,6 +192,33 @@ bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const
 bcf_status bcf_segmented_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
                                     uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg,
                                     void *temp, uint64_t *temp_bytes, void *stream);
+
+/* The segmented sorts with HOST offsets, planned on the host. */
+bcf_status bcf_segmented_sort_host(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
+                                   uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream);
+bcf_status bcf_segmented_sort_pairs_host(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                                         uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg,
+                                         void *temp, uint64_t *temp_bytes, void *stream);
+
+/*
+ * Sort by distribution: BCFMergesort with the distribution step of Sec. 3.2
+ * and, with pivot_buckets, the pivot buckets of Sec. 3.3 (BCFMergesortPB).
+ * Runs of run_keys keys are sorted (the segmented sort), distributed into P
+ * buckets by P-1 splitters sampled from P candidates per run
+ * (bcf_distribute_runs; 2P-1 buckets with pivot buckets), and every bucket's
+ * pieces are merged on their own into keys_out, all buckets in the same
+ * passes.  The piece offsets never leave the device: the bucket merge is
+ * planned there (a pivot bucket, one key value, is copied as it is).
+ *   keys_in, keys_out  device, n u32 each; keys_out must not equal keys_in
+ *   n                  at most 2^32 - 1
+ *   P                  1..65536; run_keys >= 1; the distribution's limits
+ *                      apply (ceil(n / run_keys) runs at most 2^22, runs * P
+ *                      at most 2^26, buckets * runs at most 2^24), else
+ *                      BCF_ERR_INVALID
+ *   temp               as for the sorts (the query needs no device access)
+ */
+bcf_status bcf_sort_u32_pb(const uint32_t *keys_in, uint32_t *keys_out, uint64_t n, uint32_t P, uint32_t run_keys,
+                           int pivot_buckets, void *temp, uint64_t *temp_bytes, void *stream);
 
 /*
  * The segmented sort split in two so that the device part can be captured in

@@ -35,10 +35,14 @@ EXPORTED = (
     "bcf_colored_prefix_sums",
     "bcf_sort_u64",
     "bcf_merge_runs",
+    "bcf_merge_runs_host",
     "bcf_distribute_runs",
     "bcf_merge_run_groups",
+    "bcf_sort_u32_pb",
     "bcf_segmented_sort",
     "bcf_segmented_sort_pairs",
+    "bcf_segmented_sort_host",
+    "bcf_segmented_sort_pairs_host",
     "bcf_segmented_upload",
     "bcf_segmented_execute",
     "bcf_status_string",
@@ -116,15 +120,21 @@ def load(path: str = LIB_PATH):
     lib.bcf_colored_prefix_sums.restype = ctypes.c_int
     lib.bcf_sort_u64.argtypes = [vp, vp, u64, vp, u64p, vp]
     lib.bcf_sort_u64.restype = ctypes.c_int
-    lib.bcf_merge_runs.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
+    lib.bcf_merge_runs.argtypes = [vp, vp, vp, u32, vp, vp, vp, u64p, vp]  # device offsets
+    lib.bcf_merge_runs_host.argtypes = [vp, vp, u64p, u32, vp, vp, vp, u64p, vp]
+    lib.bcf_sort_u32_pb.argtypes = [vp, vp, u64, u32, u32, ctypes.c_int, vp, u64p, vp]
     lib.bcf_distribute_runs.argtypes = [vp, u64p, u32, u32, u32, ctypes.c_int, vp, vp, vp, vp, u64p, vp]
     lib.bcf_merge_run_groups.argtypes = [vp, vp, u64p, u32, ctypes.POINTER(u32), u32, vp, vp, vp, u64p, vp]
-    lib.bcf_segmented_sort.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
-    lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
+    lib.bcf_segmented_sort.argtypes = [vp, vp, vp, u32, vp, u64p, vp]  # device offsets
+    lib.bcf_segmented_sort_pairs.argtypes = [vp, vp, vp, vp, vp, u32, vp, u64p, vp]
+    lib.bcf_segmented_sort_host.argtypes = [vp, vp, u64p, u32, vp, u64p, vp]
+    lib.bcf_segmented_sort_pairs_host.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
     lib.bcf_segmented_upload.argtypes = [u64p, u32, ctypes.c_int, vp, u64p, vp]
     lib.bcf_segmented_execute.argtypes = [vp, vp, vp, vp, u64p, u32, vp, u64p, vp]
-    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_distribute_runs", "bcf_merge_run_groups", "bcf_segmented_sort",
-              "bcf_segmented_sort_pairs", "bcf_segmented_upload", "bcf_segmented_execute"):
+    for f in ("bcf_sort_u32", "bcf_sort_pairs_u32", "bcf_merge_runs", "bcf_merge_runs_host", "bcf_distribute_runs",
+              "bcf_merge_run_groups", "bcf_sort_u32_pb", "bcf_segmented_sort", "bcf_segmented_sort_pairs",
+              "bcf_segmented_sort_host", "bcf_segmented_sort_pairs_host", "bcf_segmented_upload",
+              "bcf_segmented_execute"):
         getattr(lib, f).restype = ctypes.c_int
     lib.bcf_status_string.argtypes = [ctypes.c_int]
     lib.bcf_status_string.restype = ctypes.c_char_p

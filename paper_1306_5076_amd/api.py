@@ -69,6 +69,20 @@ def _check_tensor(t, name, device=None):
         raise ValueError(f"{name} is on {t.device}, expected {device}")
 
 
+def _device_offsets(off, device):
+    """Offsets given as a device tensor (int64 or uint64, contiguous): the
+    device-planned entry points take them as they are."""
+    if not isinstance(off, torch.Tensor) or not off.is_cuda:
+        return None
+    if off.dtype not in (torch.int64, torch.uint64) or off.dim() != 1 or not off.is_contiguous():
+        raise TypeError("device offsets must be a contiguous 1-D int64 / uint64 CUDA tensor")
+    if off.device != device:
+        raise ValueError(f"offsets are on {off.device}, expected {device}")
+    if off.numel() < 1:
+        raise ValueError("offsets must have at least one entry")
+    return off
+
+
 def _offsets(off, total=None):
     a = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
     if a.ndim != 1 or a.size < 1:
@@ -279,12 +293,18 @@ def colored_prefix_sums(values, colors, d, conflict_free=True, out=None, stream=
 def merge_runs(keys, run_offsets, vals=None, keys_out=None, vals_out=None, stream=None, workspace=None):
     """Stable merge of the sorted runs [off[r], off[r+1]) of ``keys``.
 
-    ``run_offsets`` is a host sequence of k+1 offsets.  Returns ``keys_out``,
-    or ``(keys_out, vals_out)`` when ``vals`` is given.
+    ``run_offsets`` holds k+1 offsets: a CUDA tensor (int64 / uint64) takes the
+    device-planned ``bcf_merge_runs`` (nothing read back while merging), a host
+    sequence ``bcf_merge_runs_host``.  Returns ``keys_out``, or
+    ``(keys_out, vals_out)`` when ``vals`` is given.
     """
     lib = load()
     _check_tensor(keys, "keys")
     n = keys.numel()
+    doff = _device_offsets(run_offsets, keys.device)
+    if doff is not None:
+        return _planned(lib.bcf_merge_runs, "bcf_merge_runs", keys, doff, vals, keys_out, vals_out, stream, workspace,
+                        merge=True)
     off = _offsets(run_offsets, n)
     k = off.size - 1
     if vals is not None:
@@ -296,16 +316,49 @@ def merge_runs(keys, run_offsets, vals=None, keys_out=None, vals_out=None, strea
     offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     need = ctypes.c_uint64(0)
     vdummy = ctypes.c_void_p(1) if vals is not None else None
-    check("bcf_merge_runs", lib.bcf_merge_runs(None, vdummy, offp, k, None, None, None, ctypes.byref(need), None))
+    check("bcf_merge_runs_host", lib.bcf_merge_runs_host(None, vdummy, offp, k, None, None, None, ctypes.byref(need),
+                                                         None))
     temp, tb = _temp(workspace, need.value, keys.device, stream)
     if n:
         check(
-            "bcf_merge_runs",
-            lib.bcf_merge_runs(
+            "bcf_merge_runs_host",
+            lib.bcf_merge_runs_host(
                 _ptr(keys), _ptr(vals), offp, k, _ptr(keys_out), _ptr(vals_out),
                 _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh,
             ),
         )
+    return (keys_out, vals_out) if vals is not None else keys_out
+
+
+def _planned(fn, fname, keys, off, vals, keys_out, vals_out, stream, workspace, merge):
+    """A call of a device-planned entry point (offsets in device memory)."""
+    k = off.numel() - 1
+    if vals is not None:
+        _check_tensor(vals, "vals", keys.device)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    _check_tensor(keys_out, "keys_out", keys.device)
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    stream, sh = _stream(stream, keys.device)
+    need = ctypes.c_uint64(0)
+    vdummy = ctypes.c_void_p(1) if vals is not None else None
+    if merge:
+        check(fname, fn(None, vdummy, _ptr(off), k, None, None, None, ctypes.byref(need), sh))
+    elif vals is None:
+        check(fname, fn(None, None, _ptr(off), k, None, ctypes.byref(need), sh))
+    else:
+        check(fname, fn(None, None, None, None, _ptr(off), k, None, ctypes.byref(need), sh))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if keys.numel() and k:
+        tp = _ptr(temp) or ctypes.c_void_p(1)
+        if merge:
+            check(fname, fn(_ptr(keys), _ptr(vals), _ptr(off), k, _ptr(keys_out), _ptr(vals_out), tp, ctypes.byref(tb),
+                            sh))
+        elif vals is None:
+            check(fname, fn(_ptr(keys), _ptr(keys_out), _ptr(off), k, tp, ctypes.byref(tb), sh))
+        else:
+            check(fname, fn(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), _ptr(off), k, tp,
+                            ctypes.byref(tb), sh))
     return (keys_out, vals_out) if vals is not None else keys_out
 
 
@@ -389,31 +442,27 @@ def bucket_groups(piece_offsets, s, P, pivot_buckets):
 
 
 def sort_u32_pb(keys, P=256, run_keys=1 << 18, pivot_buckets=True, out=None, stream=None, workspace=None):
-    """Sort by distribution (BCFMergesort with the distribution step of Sec. 3.2
-    and, with ``pivot_buckets``, the pivot buckets of Sec. 3.3): sort runs of
-    ``run_keys`` keys, distribute them into buckets by P-1 sampled splitters
-    (t = P candidates per run), then merge every bucket's pieces, all buckets in
-    one batched merge.  A pivot bucket holds one key value, so its pieces are
-    already in place and it is passed on as one run.  The piece offsets are
-    read back to the host between the two device phases (one synchronisation
-    of ``stream``)."""
+    """Sort by distribution (``bcf_sort_u32_pb``: BCFMergesort with the
+    distribution step of Sec. 3.2 and, with ``pivot_buckets``, the pivot
+    buckets of Sec. 3.3): sort runs of ``run_keys`` keys, distribute them into
+    buckets by P-1 sampled splitters (P candidates per run), then merge every
+    bucket's pieces, all buckets in one batched merge planned on the device (no
+    read-back).  Returns ``out``."""
+    lib = load()
     _check_tensor(keys, "keys")
     n = keys.numel()
     out = torch.empty_like(keys) if out is None else out
-    if n == 0:
-        return out
-    s = (n + run_keys - 1) // run_keys
-    seg = np.minimum(np.arange(s + 1, dtype=np.uint64) * np.uint64(run_keys), np.uint64(n))
-    runs = segmented_sort(keys, seg, keys_out=out, stream=stream, workspace=workspace)
-    dist, pieces, _ = distribute_runs(runs, seg, P, P, pivot_buckets=pivot_buckets, stream=stream,
-                                      workspace=workspace)
-    stream_, _ = _stream(stream, keys.device)
-    stream_.synchronize()
-    po = pieces.cpu().numpy().astype(np.uint64)
-    offs, starts = bucket_groups(po, s, P, pivot_buckets)
-    merge_run_groups(dist, offs, starts, keys_out=out, stream=stream, workspace=workspace)
-    if stream is not None:
-        dist.record_stream(stream)
+    _check_tensor(out, "out", keys.device)
+    if out.data_ptr() == keys.data_ptr() and n:
+        raise ValueError("sort_u32_pb does not sort in place")
+    stream, sh = _stream(stream, keys.device)
+    need = ctypes.c_uint64(0)
+    piv = int(bool(pivot_buckets))
+    check("bcf_sort_u32_pb", lib.bcf_sort_u32_pb(None, None, n, P, run_keys, piv, None, ctypes.byref(need), None))
+    temp, tb = _temp(workspace, need.value, keys.device, stream)
+    if n:
+        check("bcf_sort_u32_pb", lib.bcf_sort_u32_pb(_ptr(keys), _ptr(out), n, P, run_keys, piv,
+                                                     _ptr(temp) or ctypes.c_void_p(1), ctypes.byref(tb), sh))
     return out
 
 
@@ -427,9 +476,16 @@ def segmented_sort(keys, seg_offsets, vals=None, keys_out=None, vals_out=None, s
     lib = load()
     _check_tensor(keys, "keys")
     n = keys.numel()
+    keys_out = out if keys_out is None else keys_out
+    doff = _device_offsets(seg_offsets, keys.device)
+    if doff is not None:
+        if vals is None:
+            return _planned(lib.bcf_segmented_sort, "bcf_segmented_sort", keys, doff, None, keys_out, None, stream,
+                            workspace, merge=False)
+        return _planned(lib.bcf_segmented_sort_pairs, "bcf_segmented_sort_pairs", keys, doff, vals, keys_out,
+                        vals_out, stream, workspace, merge=False)
     off = _offsets(seg_offsets, n)
     nseg = off.size - 1
-    keys_out = out if keys_out is None else keys_out
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
     if vals is not None:
         _check_tensor(vals, "vals", keys.device)
@@ -438,18 +494,19 @@ def segmented_sort(keys, seg_offsets, vals=None, keys_out=None, vals_out=None, s
     offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     need = ctypes.c_uint64(0)
     if vals is None:
-        check("bcf_segmented_sort", lib.bcf_segmented_sort(None, None, offp, nseg, None, ctypes.byref(need), None))
+        check("bcf_segmented_sort_host", lib.bcf_segmented_sort_host(None, None, offp, nseg, None, ctypes.byref(need),
+                                                                     None))
     else:
-        check("bcf_segmented_sort_pairs", lib.bcf_segmented_sort_pairs(
+        check("bcf_segmented_sort_pairs_host", lib.bcf_segmented_sort_pairs_host(
             None, None, None, None, offp, nseg, None, ctypes.byref(need), None))
     temp, tb = _temp(workspace, need.value, keys.device, stream)
     if n:
         tp = _ptr(temp) or ctypes.c_void_p(1)
         if vals is None:
-            check("bcf_segmented_sort", lib.bcf_segmented_sort(
+            check("bcf_segmented_sort_host", lib.bcf_segmented_sort_host(
                 _ptr(keys), _ptr(keys_out), offp, nseg, tp, ctypes.byref(tb), sh))
         else:
-            check("bcf_segmented_sort_pairs", lib.bcf_segmented_sort_pairs(
+            check("bcf_segmented_sort_pairs_host", lib.bcf_segmented_sort_pairs_host(
                 _ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), offp, nseg, tp, ctypes.byref(tb), sh))
     return (keys_out, vals_out) if vals is not None else keys_out
 

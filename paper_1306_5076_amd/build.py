@@ -31,7 +31,7 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"),
     "-I", CSRC,
 ]
-SOURCES = ["bcf_kernels.hip", "bcf_api.hip", "bcf_cps.hip", "bcf_u64.hip", "bcf_dist.hip", "bcf_noalloc.hip"]
+SOURCES = ["bcf_kernels.hip", "bcf_api.hip", "bcf_cps.hip", "bcf_u64.hip", "bcf_dist.hip", "bcf_noalloc.hip", "bcf_plan.hip"]
 # The key/value networks compare elements as doubles (v_min_f64 / v_max_f64)
 # that are never NaN; with the IEEE mode bit clear the compiler does not
 # quieten (canonicalise) every value read back from LDS before comparing it.

@@ -867,7 +867,7 @@ bcf_status merge_groups_impl(const uint32_t *keys_in, const uint32_t *vals_in, c
 
 extern "C" {
 
-bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
+bcf_status bcf_merge_runs_host(const uint32_t *keys_in, const uint32_t *vals_in, const uint64_t *run_offsets,
                           uint32_t k, uint32_t *keys_out, uint32_t *vals_out, void *temp, uint64_t *temp_bytes,
                           void *stream)
 {
@@ -885,14 +885,14 @@ bcf_status bcf_merge_run_groups(const uint32_t *keys_in, const uint32_t *vals_in
                              temp_bytes, stream);
 }
 
-bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
+bcf_status bcf_segmented_sort_host(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
                               uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream)
 {
     return segmented_impl(kSegFull, false, keys_in, nullptr, keys_out, nullptr, seg_offsets, nseg, temp, temp_bytes,
                           static_cast<hipStream_t>(stream));
 }
 
-bcf_status bcf_segmented_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+bcf_status bcf_segmented_sort_pairs_host(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
                                     uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg, void *temp,
                                     uint64_t *temp_bytes, void *stream)
 {

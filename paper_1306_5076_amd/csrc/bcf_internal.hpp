@@ -95,14 +95,17 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
 // Order-preserving key map to u32 (inverse = false) or back (true), in place
 // allowed: kind 1 = int32, 2 = IEEE binary32 (totalOrder).
 hipError_t launch_map_keys(const uint32_t *in, uint32_t *out, uint64_t n, int kind, bool inverse, hipStream_t s);
+// Table launches: the grid covers ntiles (ngroups) tiles; with count_dev set
+// the kernels take the actual count from that device word (at most the bound),
+// so that a device planner can size the work after the launch was enqueued.
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
-                                   uint32_t ntiles, hipStream_t s);
+                                   uint32_t ntiles, hipStream_t s, const uint32_t *count_dev = nullptr);
 // Group tiles (count <= group_run_keys(pairs)) sorted by a multi-wave work-group.
 hipError_t launch_block_sort_group_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles,
-                                         uint32_t ngroups, hipStream_t s);
+                                         uint32_t ngroups, hipStream_t s, const uint32_t *count_dev = nullptr);
 hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs,
                               const uint32_t *tile_job, uint32_t ntiles, uint32_t *splits,
-                              bool partition, hipStream_t s);
+                              bool partition, hipStream_t s, const uint32_t *count_dev = nullptr);
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);
 

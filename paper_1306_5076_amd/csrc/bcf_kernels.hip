@@ -490,6 +490,7 @@ struct SortItem {
 };
 
 struct RegularSortSrc {
+    __device__ void resolve() {}
     const uint32_t *kin, *vin;
     uint32_t *kout, *vout;
     uint64_t n;
@@ -510,11 +511,24 @@ struct RegularSortSrc {
     }
 };
 
+// Table sources take their tile count from the launch (ntiles, the most the
+// grid covers) and, when count_dev is set, from device memory (the count a
+// device planner wrote; at most ntiles).
+__device__ __forceinline__ uint32_t resolved_count(uint32_t bound, const uint32_t *count_dev)
+{
+    if (count_dev == nullptr)
+        return bound;
+    const uint32_t c = __builtin_amdgcn_readfirstlane(*count_dev);
+    return c < bound ? c : bound;
+}
+
 struct TableSortSrc {
     Bufs kb, vb;
     const BlockTile *tiles;
     uint32_t ntiles;
     SampleSet out_smp;  // always empty: table tiles start anywhere
+    const uint32_t *count_dev;
+    __device__ void resolve() { ntiles = resolved_count(ntiles, count_dev); }
     __device__ uint64_t pos(uint32_t) const { return 0; }
     __device__ SortItem get(uint32_t t) const
     {
@@ -541,6 +555,7 @@ struct MergeItem {
 // Runs of length `run` (a multiple of kTile) cover [0, n); runs 2s and 2s+1
 // are merged into [2s*run, min(2(s+1)*run, n)).
 struct RegularMergeSrc {
+    __device__ void resolve() {}
     const uint32_t *ksrc, *vsrc;
     uint32_t *kdst, *vdst;
     uint64_t n, run;
@@ -573,6 +588,8 @@ struct TableMergeSrc {
     const uint32_t *tile_job;
     uint32_t ntiles;
     SampleSet out_smp;  // always empty: table runs start anywhere
+    const uint32_t *count_dev;
+    __device__ void resolve() { ntiles = resolved_count(ntiles, count_dev); }
 
     __device__ MergeItem get(uint32_t t) const
     {
@@ -655,6 +672,7 @@ __device__ __forceinline__ void wave_tile(Lines<P> &a, const SortItem &it, const
 template <bool P, class Src, bool SHEAR = false>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
 {
+    src.resolve();
     __shared__ __align__(16) uint32_t lds_all[kWavesPerGroup][kLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -701,6 +719,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
 }
 
 struct RegularGroupSrc {
+    __device__ void resolve() {}
     const uint32_t *kin, *vin;
     uint32_t *kout, *vout;
     uint64_t n;
@@ -734,6 +753,8 @@ struct TableGroupSrc {
     const BlockTile *tiles;
     uint32_t ngroups;
     SampleSet out_smp;  // always empty
+    const uint32_t *count_dev;
+    __device__ void resolve() { ngroups = resolved_count(ngroups, count_dev); }
     __device__ uint64_t pos(uint32_t, uint32_t) const { return 0; }
     __device__ uint32_t group_count(uint32_t g) const { return tiles[g].count; }
     __device__ SortItem get(uint32_t g, uint32_t w) const
@@ -783,6 +804,7 @@ __device__ __forceinline__ void group_tile(Lines<P> &t, const SortItem &it, cons
 template <int NW, bool P, class Src>
 __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
 {
+    src.resolve();
     __shared__ __align__(16) uint32_t lds[NW * kLdsWords];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -959,6 +981,9 @@ __global__ __launch_bounds__(kWave *NW) void k_block_sort_shear_group(Src src)
 template <class Src>
 __global__ __launch_bounds__(256) void k_partition(Src src, uint32_t *__restrict__ splits)
 {
+    src.resolve();
+    if (blockIdx.x * 2 * (256 / kWave) >= src.ntiles)
+        return;  // no tile of this block (the grid covers the most a planner allows)
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t t = (blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * 2 + (lane >> 5);
     const bool valid = t < src.ntiles;
@@ -968,6 +993,26 @@ __global__ __launch_bounds__(256) void k_partition(Src src, uint32_t *__restrict
     const uint32_t split = corank_halfwave(m.ka, m.na, m.ka + m.na, m.nb, m.d0, lane);
     if (valid && (lane & 31) == 0)
         splits[t] = split;
+}
+
+// The same partition by persistent waves (tiles t, t + 2 x grid waves, ...),
+// for launches whose tile count is only known on the device.
+template <class Src>
+__global__ __launch_bounds__(256) void k_partition_persist(Src src, uint32_t *__restrict__ splits)
+{
+    src.resolve();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t stride = gridDim.x * (256 / kWave) * 2;
+    for (uint32_t t0 = (blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * 2; t0 < src.ntiles; t0 += stride) {
+        const uint32_t t = t0 + (lane >> 5);
+        const bool valid = t < src.ntiles;
+        MergeItem m = src.get(valid ? t : src.ntiles - 1);
+        if (!valid)
+            m.na = m.nb = m.d0 = 0;
+        const uint32_t split = corank_halfwave(m.ka, m.na, m.ka + m.na, m.nb, m.d0, lane);
+        if (valid && (lane & 31) == 0)
+            splits[t] = split;
+    }
 }
 
 // MODE 0: persistent waves, next tile's loads issued before the current tile
@@ -1132,6 +1177,7 @@ constexpr int merge_group_waves() { return MODE == 2 ? kMergeTileWaves : kWavesP
 template <bool P, class Src, int MODE, bool NT = false, bool FUSED = false>
 __global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src src, const uint32_t *__restrict__ splits)
 {
+    src.resolve();
     constexpr int W = merge_group_waves<MODE>();  // waves per work-group
     // per wave: the transpose area, then (pairs) the tile's staged values
     constexpr int kWaveWords = kLdsWords + (P ? kTile : 0);
@@ -1875,11 +1921,11 @@ static hipError_t launch_group(const uint32_t *kin, const uint32_t *vin, uint32_
 }
 
 hipError_t launch_block_sort_group_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles, uint32_t ngroups,
-                                         hipStream_t s)
+                                         hipStream_t s, const uint32_t *count_dev)
 {
     if (!pairs)
         vb = Bufs{nullptr, nullptr, nullptr};
-    TableGroupSrc src{kb, vb, tiles, ngroups, SampleSet{nullptr, nullptr, nullptr, nullptr}};
+    TableGroupSrc src{kb, vb, tiles, ngroups, SampleSet{nullptr, nullptr, nullptr, nullptr}, count_dev};
     return pairs ? launch_group_src<kGroupWavesPairs, true>(src, s) : launch_group_src<kGroupWavesKeys, false>(src, s);
 }
 
@@ -2010,20 +2056,38 @@ hipError_t launch_map_keys(const uint32_t *in, uint32_t *out, uint64_t n, int ki
 }
 
 hipError_t launch_block_sort_table(bool pairs, Bufs kb, Bufs vb, const BlockTile *tiles, uint32_t ntiles,
-                                   hipStream_t s)
+                                   hipStream_t s, const uint32_t *count_dev)
 {
     if (!pairs)
         vb = Bufs{nullptr, nullptr, nullptr};
-    TableSortSrc src{kb, vb, tiles, ntiles, SampleSet{nullptr, nullptr, nullptr, nullptr}};
+    TableSortSrc src{kb, vb, tiles, ntiles, SampleSet{nullptr, nullptr, nullptr, nullptr}, count_dev};
     return pairs ? launch_sort<true>(src, s) : launch_sort<false>(src, s);
 }
 
 hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs, const uint32_t *tile_job,
-                              uint32_t ntiles, uint32_t *splits, bool partition, hipStream_t s)
+                              uint32_t ntiles, uint32_t *splits, bool partition, hipStream_t s,
+                              const uint32_t *count_dev)
 {
     if (!pairs)
         vb = Bufs{nullptr, nullptr, nullptr};
-    TableMergeSrc src{kb, vb, jobs, tile_job, ntiles, SampleSet{nullptr, nullptr, nullptr, nullptr}};
+    TableMergeSrc src{kb, vb, jobs, tile_job, ntiles, SampleSet{nullptr, nullptr, nullptr, nullptr}, count_dev};
+    if (count_dev != nullptr) {
+        // the count is known only on the device: persistent waves (a grid the
+        // size of the chip, not of the bound)
+        if (ntiles == 0)
+            return hipSuccess;
+        if (partition) {
+            const uint32_t pg = persistent_groups(k_partition_persist<TableMergeSrc>, ntiles);
+            hipLaunchKernelGGL((k_partition_persist<TableMergeSrc>), dim3(pg), dim3(256), 0, s, src, splits);
+            return hipGetLastError();
+        }
+        const bool nt = tuning().nontemporal;
+        if (pairs)
+            return nt ? launch_merge_mode<true, TableMergeSrc, 1, true>(src, splits, s)
+                      : launch_merge_mode<true, TableMergeSrc, 1>(src, splits, s);
+        return nt ? launch_merge_mode<false, TableMergeSrc, 1, true>(src, splits, s)
+                  : launch_merge_mode<false, TableMergeSrc, 1>(src, splits, s);
+    }
     if (partition)
         return launch_partition(src, splits, s);
     return pairs ? launch_merge<true>(src, splits, s) : launch_merge<false>(src, splits, s);

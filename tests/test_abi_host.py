@@ -226,22 +226,63 @@ def _offs(a):
 def test_merge_runs_validation_and_query(lib):
     need = ctypes.c_uint64(0)
     a, p = _offs([0, 5, 3, 9])  # decreasing offset
-    assert lib.bcf_merge_runs(None, None, p, 3, None, None, None, ctypes.byref(need), None) == 1
+    assert lib.bcf_merge_runs_host(None, None, p, 3, None, None, None, ctypes.byref(need), None) == 1
     a, p = _offs([1, 5])  # off[0] != 0
-    assert lib.bcf_merge_runs(None, None, p, 1, None, None, None, ctypes.byref(need), None) == 1
+    assert lib.bcf_merge_runs_host(None, None, p, 1, None, None, None, ctypes.byref(need), None) == 1
     a, p = _offs([0, 5000, 5000, 9000])
-    assert lib.bcf_merge_runs(None, None, p, 3, None, None, None, ctypes.byref(need), None) == 0
+    assert lib.bcf_merge_runs_host(None, None, p, 3, None, None, None, ctypes.byref(need), None) == 0
     assert need.value >= 9000 * 4
     # k == 0 is a no-op
+    assert lib.bcf_merge_runs_host(None, None, None, 0, None, None, None, ctypes.byref(need), None) == 0
+
+
+def test_device_offset_calls_refuse_before_any_device_access(lib):
+    """The calls with device offsets: k == 0 / nseg == 0 are no-ops with a zero
+    temp size, and a NULL offset array or NULL temp_bytes is refused, all
+    without touching the device."""
+    need = ctypes.c_uint64(7)
     assert lib.bcf_merge_runs(None, None, None, 0, None, None, None, ctypes.byref(need), None) == 0
+    assert need.value == 0
+    assert lib.bcf_merge_runs(None, None, None, 3, None, None, None, ctypes.byref(need), None) == 1
+    assert lib.bcf_merge_runs(None, None, ctypes.c_void_p(0x1000), 3, None, None, None, None, None) == 1
+    for f in (lib.bcf_segmented_sort,):
+        need = ctypes.c_uint64(7)
+        assert f(None, None, None, 0, None, ctypes.byref(need), None) == 0 and need.value == 0
+        assert f(None, None, None, 4, None, ctypes.byref(need), None) == 1
+        assert f(None, None, ctypes.c_void_p(0x1000), 4, None, None, None) == 1
+    need = ctypes.c_uint64(7)
+    assert lib.bcf_segmented_sort_pairs(None, None, None, None, None, 0, None, ctypes.byref(need), None) == 0
+    assert need.value == 0
+    assert lib.bcf_segmented_sort_pairs(None, None, None, None, None, 2, None, ctypes.byref(need), None) == 1
+
+
+def test_sort_pb_query_and_validation(lib):
+    """bcf_sort_u32_pb: the temp query is host-only (the run offsets are
+    uniform); sizes and the distribution's limits are checked first."""
+    need = ctypes.c_uint64(0)
+    q = lambda n, P, rk, pb: lib.bcf_sort_u32_pb(None, None, n, P, rk, pb, None, ctypes.byref(need), None)  # noqa
+    assert q(0, 256, 1 << 18, 1) == 0 and need.value == 0
+    assert q(1 << 26, 256, 1 << 18, 1) == 0
+    n = 1 << 26
+    assert need.value >= 2 * n * 4  # the distributed keys and the bucket merge's ping-pong buffer
+    with_pivots = need.value
+    assert q(1 << 26, 256, 1 << 18, 0) == 0 and need.value < with_pivots  # P instead of 2P - 1 buckets' pieces
+    assert q(1 << 26, 0, 1 << 18, 0) == 1 and q(1 << 26, 65537, 1 << 18, 0) == 1  # P in 1..65536
+    assert q(1 << 26, 256, 0, 0) == 1  # run_keys >= 1
+    assert q(1 << 26, 65536, 1 << 12, 1) == 1  # 16384 runs x 65536 candidates > 2^26
+    assert q(1 << 32, 256, 1 << 18, 1) == 1  # more than 2^32 - 1 keys
+    buf = ctypes.c_void_p(0x100000)
+    tb = ctypes.c_uint64(1 << 40)
+    assert lib.bcf_sort_u32_pb(buf, buf, 1 << 20, 16, 1 << 16, 1, ctypes.c_void_p(0x200000), ctypes.byref(tb),
+                               None) == 1  # in place is refused
 
 
 def test_segmented_validation_and_query(lib):
     need = ctypes.c_uint64(0)
     a, p = _offs([0, 10, 5])
-    assert lib.bcf_segmented_sort(None, None, p, 2, None, ctypes.byref(need), None) == 1
+    assert lib.bcf_segmented_sort_host(None, None, p, 2, None, ctypes.byref(need), None) == 1
     a, p = _offs([0, 0, 1, 4096, 4096 + 8193])
-    assert lib.bcf_segmented_sort(None, None, p, 4, None, ctypes.byref(need), None) == 0
+    assert lib.bcf_segmented_sort_host(None, None, p, 4, None, ctypes.byref(need), None) == 0
     assert need.value > 0
 
 
