@@ -6,18 +6,26 @@ fastest, and caches the winner in a JSON file keyed by a workload signature
 (kind, size bucket, key/value or keys only).  The knobs it searches are the
 ones the kernels expose at run time:
 
+* block_sort        -- (sorts) the block size: wave tiles of 4096 keys (one
+                       wave, E = 64 keys per lane) or group tiles of 32768
+                       keys (8 waves; 16384 pairs by 4 waves), both sorted by
+                       merge rounds;
+* group_min_keys    -- (segmented sorts) the same block-size choice per
+                       segment: the segment length from which a segment is
+                       block-sorted in group tiles instead of wave tiles;
+* merge_fan_in      -- (sorts) runs merged per pass: 2 (binary passes), 4
+                       (four-way passes, two merge levels per read and write of
+                       the data), or 0 for the size-based default;
 * merge_variant     -- persistent waves with / without next-tile prefetch, one
                        tile per wave, or the per-kind default;
 * nontemporal       -- nontemporal hints on the merge passes' tile traffic;
 * fused_partition   -- whether one-tile-per-wave merge passes search their
                        own splits (one launch per pass) or a partition
-                       launch does;
-* group_min_keys    -- (segmented sorts) the segment length from which a
-                       segment is block-sorted by multi-wave work-groups.
+                       launch does.
 
-The tile shape (w x w = 64 x 64 keys per wave, 64 keys per lane) and the
-binary fan-in of the merge passes are fixed by the conflict-free layout and
-the bitonic merge network, so they are not searched.
+The keys per lane (E = 64, one line of the 64 x 64 wave tile) are fixed by the
+conflict-free layout: the register index of a key is a compile-time constant,
+so E is a property of the compiled kernels, not a run-time knob.
 """
 
 from __future__ import annotations
@@ -33,7 +41,8 @@ from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bcf_sort", "autotune.json")
 
-SORT_SPACE = {"merge_fan_in": [0, 4, 2], "merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0], "fused_partition": [1, 0]}
+SORT_SPACE = {"block_sort": [3, 1], "merge_fan_in": [0, 4, 2], "merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0],
+              "fused_partition": [1, 0]}
 SEGMENTED_SPACE = {"merge_variant": [3, 1, 2], "nontemporal": [1, 0],
                    "group_min_keys": [4097, 16384, 65536, 1 << 40]}
 

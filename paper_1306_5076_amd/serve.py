@@ -1,15 +1,19 @@
 """Continuous-batching sort service on one GPU, and its one-call-per-request baseline.
 
 :class:`SortServer` accepts sort requests (u32 keys, or u32/u32 pairs sorted
-stably by key) from any thread.  A launch thread
+stably by key) and merge requests (k sorted runs of keys or pairs, merged
+stably by run) from any thread.  A launch thread
 
-* admits waiting requests in arrival order while their device bytes fit the
-  HBM budget (a request larger than the whole budget is rejected) and the
-  batch stays under ``max_batch_keys``;
-* packs the admitted requests into one batch: requests of at least
-  ``solo_keys`` keys, and a request alone in its batch, are sorted on their
-  own (``bcf_sort_u32`` / ``bcf_sort_pairs_u32``, no launch plan to build),
-  the smaller ones of each kind share one segmented sort
+* admits waiting requests in arrival order while their device bytes fit both
+  the HBM budget and the HBM that is actually free on the device
+  (``torch.cuda.mem_get_info`` plus what torch's caching allocator holds
+  unused), and the batch stays under ``max_batch_keys``; a request larger
+  than the whole budget, or larger than the free HBM while nothing else is
+  in flight, is rejected with ``MemoryError``;
+* packs the admitted requests into one batch: merge requests, requests of at
+  least ``solo_keys`` keys, and a request alone in its batch, run on their
+  own (``bcf_merge_runs``, ``bcf_sort_u32`` / ``bcf_sort_pairs_u32``), the
+  smaller sorts of each kind share one segmented sort
   (``bcf_segmented_sort`` / ``bcf_segmented_sort_pairs``) in which each
   request is a segment;
 * runs each batch (host-to-device copy, sorts, device-to-host copy) on the
@@ -18,6 +22,10 @@ stably by key) from any thread.  A launch thread
   arrive meanwhile join the next batch;
 * keeps its device buffers and pinned host staging resident between batches
   (they grow on demand and are reused, never freed per request).
+
+A request that arrives while the server is idle (nothing queued, nothing in
+flight, no launch under way) is launched on the submitting thread itself, so
+a lone request does not wait for the launch thread to wake up.
 
 A completion thread waits for each batch's device-to-host copy, hands every
 request its result, records its latency from arrival to completion and
@@ -59,6 +67,7 @@ class _Request:
     vals: object | None
     arrival: float
     ready: object = None    # device request: event recorded on the submitting stream
+    runs: object = None     # merge request: its k+1 run offsets (numpy uint64)
     future: SortFuture = field(default_factory=SortFuture)
     submitted: float = 0.0  # perf_counter() when submit() queued it
     admitted: float = 0.0   # ... when the launch thread took it into a batch
@@ -78,10 +87,16 @@ class _Request:
     def pairs(self) -> bool:
         return self.vals is not None
 
+    @property
+    def merge(self) -> bool:
+        return self.runs is not None
+
     def device_bytes(self) -> int:
         words = 2 if self.pairs else 1
         # input + output arrays, plus merge scratch of the same size and a margin for descriptors
-        return self.n * 4 * words * 3 + 64 * 1024
+        # (a merge's tables grow with its run count)
+        runs = 32 * (len(self.runs) if self.merge else 0)
+        return self.n * 4 * words * 3 + 64 * 1024 + runs
 
 
 class _Grow:
@@ -123,11 +138,16 @@ class SortServer:
     """Continuous-batching sort server (see module docstring)."""
 
     def __init__(self, device="cuda:0", hbm_budget: int = 16 << 30, max_batch_keys: int = 1 << 24,
-                 slots: int = 3, reserve_keys: int = 0, solo_keys: int = 1 << 20):
+                 slots: int = 3, reserve_keys: int = 0, solo_keys: int = 1 << 20, hbm_headroom: int = 256 << 20,
+                 inline: bool = True):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
         self.max_batch_keys = int(max_batch_keys)
         self.solo_keys = int(solo_keys)
+        self.headroom = int(hbm_headroom)  # free HBM left untouched by admission
+        self.inline = bool(inline)
+        self.launching = 0                 # launches under way (launch thread or an inline submit)
+        self.min_free_hbm = None           # least device-free HBM seen at an admission
         self.slots = [_Slot(self.device, reserve_keys) for _ in range(slots)]
         self.free_slots = collections.deque(self.slots)
         self.busy = collections.deque()
@@ -161,6 +181,27 @@ class SortServer:
         when the future resolves (a consumer on another stream should call
         ``record_stream`` on them).
         """
+        keys, vals, ready = self._inputs(keys, vals)
+        return self._enqueue(_Request(keys, vals, time.perf_counter() if arrival is None else arrival, ready))
+
+    def submit_merge(self, keys, run_offsets, vals=None, arrival: float | None = None) -> Future:
+        """Queue one merge request: ``keys`` holds k sorted runs, run r at
+        [run_offsets[r], run_offsets[r+1]); the result is their stable merge
+        (equal keys: lower run first), keys or (keys, values), host or device
+        as for :meth:`submit`.  ``run_offsets`` is a host sequence of k+1
+        offsets (a CUDA tensor is read back here, on the submitting thread);
+        it must rise from 0 to the number of keys."""
+        keys, vals, ready = self._inputs(keys, vals)
+        if isinstance(run_offsets, torch.Tensor):
+            run_offsets = run_offsets.cpu().numpy()
+        offs = np.ascontiguousarray(np.asarray(run_offsets, dtype=np.uint64))
+        n = int(keys.numel()) if ready is not None else int(keys.size)
+        if offs.ndim != 1 or offs.size < 1 or int(offs[0]) != 0 or int(offs[-1]) != n or np.any(offs[1:] < offs[:-1]):
+            raise ValueError("run_offsets must rise from 0 to the number of keys")
+        r = _Request(keys, vals, time.perf_counter() if arrival is None else arrival, ready, runs=offs)
+        return self._enqueue(r)
+
+    def _inputs(self, keys, vals):
         ready = None
         if isinstance(keys, torch.Tensor) and keys.is_cuda:
             if keys.dtype != torch.uint32 or keys.device != self.device or not keys.is_contiguous():
@@ -177,7 +218,9 @@ class SortServer:
                 vals = np.ascontiguousarray(np.asarray(vals, dtype=np.uint32))
                 if vals.shape != keys.shape:
                     raise ValueError("keys and vals must have the same length")
-        r = _Request(keys, vals, time.perf_counter() if arrival is None else arrival, ready)
+        return keys, vals, ready
+
+    def _enqueue(self, r: _Request) -> Future:
         if r.device_bytes() > self.budget:
             r.future.set_exception(MemoryError(f"request of {r.n} keys exceeds the HBM budget"))
             return r.future
@@ -186,7 +229,22 @@ class SortServer:
             if self.stop:
                 raise RuntimeError("server is closed")
             self.pending.append(r)
-            self.cv.notify_all()
+            # an idle server launches the request on this thread (no hand-off
+            # to the launch thread); otherwise the launch thread admits it
+            inline = (self.inline and len(self.pending) == 1 and not self.busy and not self.launching
+                      and not self.holds and len(self.free_slots) == len(self.slots))
+            if inline:
+                batch = self._take_batch()
+                inline = bool(batch)
+                if inline:
+                    slot = self._begin_launch(batch)
+            if not inline:
+                self.cv.notify_all()
+                return r.future
+        try:
+            self._run_launch(slot, batch)
+        except Exception:
+            pass  # the batch's futures hold the error
         return r.future
 
     @contextlib.contextmanager
@@ -239,50 +297,100 @@ class SortServer:
                 self.pending.clear()
                 self.cv.notify_all()
 
+    def _free_hbm(self) -> int:
+        """HBM a new allocation can take now: what the device reports free plus
+        what torch's caching allocator holds without using it."""
+        free, _ = torch.cuda.mem_get_info(self.device)
+        cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+        return int(free) + int(cached)
+
     def _take_batch(self):
-        """Admit requests in arrival order while they fit the batch and the HBM
-        budget (called with the lock held)."""
+        """Admit requests in arrival order while they fit the batch, the HBM
+        budget and the HBM free on the device (called with the lock held).
+        Requests already in flight hold their memory, so the free figure
+        already excludes them."""
         batch, keys = [], 0
+        avail = None
         while self.pending:
             r = self.pending[0]
             if batch and keys + r.n > self.max_batch_keys:
                 break
-            if self.used + r.device_bytes() > self.budget:
-                break  # admission by free-HBM budget: wait for completions
+            need = r.device_bytes()
+            if self.used + need > self.budget:
+                break  # over the budget: wait for completions
+            if avail is None:
+                free = self._free_hbm()
+                self.min_free_hbm = free if self.min_free_hbm is None else min(self.min_free_hbm, free)
+                avail = free - self.headroom
+            if need > avail:
+                if not batch and not self.busy and not self.launching:
+                    # nothing in flight holds memory that could come back
+                    self.pending.popleft()
+                    r.future.set_exception(MemoryError(
+                        f"request of {r.n} keys needs {need} bytes, {max(avail, 0)} bytes of HBM are free"))
+                    continue
+                break  # wait for completions to free device memory
             self.pending.popleft()
             batch.append(r)
             keys += r.n
-            self.used += r.device_bytes()
+            avail -= need
+            self.used += need
         return batch
+
+    def _begin_launch(self, batch):
+        """Take a slot for an admitted batch (lock held)."""
+        slot = self.free_slots.popleft()
+        self.launching += 1
+        self.peak_used = max(self.peak_used, self.used)
+        self.batches += 1
+        self.batch_sizes.append(len(batch))
+        return slot
+
+    def _run_launch(self, slot, batch):
+        """Enqueue a batch (lock not held) and hand it to the completion thread."""
+        now = time.perf_counter()
+        for r in batch:
+            r.admitted = now
+        try:
+            self._launch(slot, batch)
+        except BaseException as e:
+            # nothing of this batch reaches the completion thread: fail its
+            # requests and give back the slot and the budget share
+            with self.cv:
+                self.launching -= 1
+                self.used -= sum(r.device_bytes() for r in batch)
+                slot.reqs, slot.loc, slot.out, slot.done = [], [], None, None
+                self.free_slots.append(slot)
+                self.cv.notify_all()
+            for r in batch:
+                if not r.future.done():
+                    r.future.set_exception(e)
+            raise
+        now = time.perf_counter()
+        for r in batch:
+            r.launched = now
+        with self.cv:
+            self.launching -= 1
+            self.busy.append(slot)
+            self.cv.notify_all()
 
     def _launch_loop(self):
         while True:
             with self.cv:
                 while True:
-                    if self.stop and not self.pending:
+                    if self.stop and not self.pending and not self.launching:
                         self.launcher_done = True
                         self.cv.notify_all()
                         return
                     batch = []
-                    if self.pending and self.free_slots and (not self.holds or self.stop):
+                    # one launch at a time: the library's host-planned calls share staging
+                    if self.pending and self.free_slots and not self.launching and (not self.holds or self.stop):
                         batch = self._take_batch()
                     if batch:
                         break
                     self.cv.wait()
-                slot = self.free_slots.popleft()
-                self.peak_used = max(self.peak_used, self.used)
-                self.batches += 1
-                self.batch_sizes.append(len(batch))
-            now = time.perf_counter()
-            for r in batch:
-                r.admitted = now
-            self._launch(slot, batch)
-            now = time.perf_counter()
-            for r in batch:
-                r.launched = now
-            with self.cv:
-                self.busy.append(slot)
-                self.cv.notify_all()
+                slot = self._begin_launch(batch)
+            self._run_launch(slot, batch)
 
     def _complete_loop(self):
         while True:
@@ -321,7 +429,7 @@ class SortServer:
         # part is one span (one copy each way) and the small requests of each
         # (residence, kind) group are contiguous; values exist for key/value
         # requests only and follow the same order
-        solo = lambda r: r.n >= self.solo_keys
+        solo = lambda r: r.merge or r.n >= self.solo_keys
         slot.reqs = sorted(batch, key=lambda r: (r.on_device, r.pairs, solo(r)))
         slot.loc = []
         pos, vpos, nh, nvh = 0, 0, 0, 0
@@ -365,7 +473,15 @@ class SortServer:
             # segmented sort
             groups = {}
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
-                if alone or solo(r):
+                if r.merge:
+                    ki = r.keys if r.on_device else dk[lo:hi]
+                    if r.pairs:
+                        vi = r.vals if r.on_device else dv[vlo:vlo + r.n]
+                        api.merge_runs(ki, r.runs, vals=vi, keys_out=rk[lo:hi], vals_out=rv[vlo:vlo + r.n], stream=st,
+                                       workspace=slot.ws)
+                    else:
+                        api.merge_runs(ki, r.runs, keys_out=rk[lo:hi], stream=st, workspace=slot.ws)
+                elif alone or solo(r):
                     ki = r.keys if r.on_device else dk[lo:hi]
                     if r.pairs:
                         vi = r.vals if r.on_device else dv[vlo:vlo + r.n]
@@ -396,8 +512,10 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True, keep_results:
     """Baseline: each request alone (copy in, sort, copy out, synchronise), FIFO.
 
     ``requests`` is a list of ``(arrival_offset_s, keys, vals_or_None)``, keys
-    and values host arrays or CUDA tensors (no copies then); with ``realtime``
-    a request is not started before its arrival time.  Host staging is pinned
+    and values host arrays or CUDA tensors (no copies then), or of
+    ``(arrival_offset_s, keys, vals_or_None, run_offsets)`` for a merge of the
+    sorted runs ``run_offsets`` delimits (``bcf_merge_runs``); with
+    ``realtime`` a request is not started before its arrival time.  Host staging is pinned
     and resident, as in :class:`SortServer`.  Returns ``(results,
     latencies_s, wall_s)``; without ``keep_results`` each result is dropped
     once complete (a client that consumes its results; memory stays flat).
@@ -408,7 +526,8 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True, keep_results:
     dk, dv, rk, rv = (_Grow(dev) for _ in range(4))
     out, lat = [], []
     t0 = time.perf_counter()
-    for arr, keys, vals in requests:
+    for arr, keys, vals, *runs in requests:
+        runs = runs[0] if runs else None
         if realtime:
             _wait_until(t0 + arr)
         arrival = t0 + arr if realtime else time.perf_counter()
@@ -416,8 +535,13 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True, keep_results:
             ko = torch.empty_like(keys)
             if vals is not None:
                 vo = torch.empty_like(vals)
-                api.sort_pairs_u32(keys, vals, ko, vo, workspace=ws)
+                if runs is not None:
+                    api.merge_runs(keys, runs, vals=vals, keys_out=ko, vals_out=vo, workspace=ws)
+                else:
+                    api.sort_pairs_u32(keys, vals, ko, vo, workspace=ws)
                 res = (ko, vo)
+            elif runs is not None:
+                res = api.merge_runs(keys, runs, keys_out=ko, workspace=ws)
             else:
                 res = api.sort_u32(keys, out=ko, workspace=ws)
             torch.cuda.synchronize(dev)
@@ -432,11 +556,17 @@ def serve_serial(requests, device="cuda:0", realtime: bool = True, keep_results:
             hvv, dvv, rvv, ovv = hv.get(n), dv.get(n), rv.get(n), ov.get(n)
             hvv.copy_(torch.from_numpy(vals))
             dvv.copy_(hvv, non_blocking=True)
-            api.sort_pairs_u32(dkk, dvv, rkk, rvv, workspace=ws)
+            if runs is not None:
+                api.merge_runs(dkk, runs, vals=dvv, keys_out=rkk, vals_out=rvv, workspace=ws)
+            else:
+                api.sort_pairs_u32(dkk, dvv, rkk, rvv, workspace=ws)
             okk.copy_(rkk, non_blocking=True)
             ovv.copy_(rvv, non_blocking=True)
         else:
-            api.sort_u32(dkk, out=rkk, workspace=ws)
+            if runs is not None:
+                api.merge_runs(dkk, runs, keys_out=rkk, workspace=ws)
+            else:
+                api.sort_u32(dkk, out=rkk, workspace=ws)
             okk.copy_(rkk, non_blocking=True)
         torch.cuda.synchronize(dev)
         res = (okk.clone().numpy(), ovv.clone().numpy()) if vals is not None else okk.clone().numpy()
@@ -464,33 +594,54 @@ def latency_stats(lat_s):
 
 
 def make_requests(count: int, lo: int = 1 << 10, hi: int = 1 << 24, seed: int = 1, pool_keys: int = 1 << 25,
-                  device=None):
-    """Seeded serving workload: (arrival_at_qps_1, keys, vals_or_None) per request.
+                  device=None, merge_fraction: float = 0.0, max_runs: int = 16):
+    """Seeded serving workload: (arrival_at_qps_1, keys, vals_or_None) per sort
+    request, (arrival_at_qps_1, keys, vals_or_None, run_offsets) per merge
+    request.
 
     Sizes are log-uniform in [lo, hi]; half the requests are key/value pairs
     (value = position in the request); keys are slices of one seeded uniform
-    pool so that the request set is cheap to build.  With ``device`` the keys
-    and values are CUDA tensors there (requests already resident in HBM),
-    else numpy arrays.
+    pool so that the request set is cheap to build.  A ``merge_fraction`` of
+    the requests (chosen by a seeded draw) are merges of 2..``max_runs``
+    sorted runs of uneven lengths, each run a slice of the sorted pool.  With
+    ``device`` the keys and values are CUDA tensors there (requests already
+    resident in HBM), else numpy arrays.
     """
     import workloads
 
+    host_pool = workloads.keys_u32("uniform", pool_keys, seed=seed)
     if device is None:
-        pool = workloads.keys_u32("uniform", pool_keys, seed=seed)
+        pool = host_pool
     else:
         pool = workloads.keys_u32_torch("uniform", pool_keys, torch.device(device), seed=seed)
     spec = workloads.request_stream(count, qps=1.0, lo=lo, hi=hi, seed=seed)
     offs = workloads.draws_u64(seed ^ 0x0FF, count) % np.uint64(max(1, pool_keys - hi))
+    mdraw = workloads.draws_u64(seed ^ 0x3E6, count)
+    is_merge = (mdraw >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) < merge_fraction
+    sorted_pool = None
+    if is_merge.any():
+        sorted_pool = np.sort(host_pool)  # input preparation: runs are slices of a sorted pool
+        if device is not None:
+            sorted_pool = torch.from_numpy(sorted_pool).to(device)
     reqs = []
     for i, (t, size, pairs, _) in enumerate(spec):
         size = min(size, pool_keys)
         o = int(offs[i])
-        keys = pool[o:o + size]
         if device is None:
             vals = np.arange(size, dtype=np.uint32) if pairs else None
         else:
             vals = torch.arange(size, dtype=torch.int32, device=device).view(torch.uint32) if pairs else None
-        reqs.append((t, keys, vals))
+        if not is_merge[i]:
+            reqs.append((t, pool[o:o + size], vals))
+            continue
+        k = 2 + int(mdraw[i] % np.uint64(max_runs - 1))
+        d = workloads.draws_u64(seed * 7919 + i, 2 * k)
+        cuts = np.sort(d[:k - 1] % np.uint64(size + 1)).astype(np.int64)
+        run_off = np.concatenate([[0], cuts, [size]]).astype(np.uint64)
+        starts = (d[k:] % np.uint64(max(1, pool_keys - size))).astype(np.int64)
+        pieces = [sorted_pool[int(starts[j]):int(starts[j]) + int(run_off[j + 1] - run_off[j])] for j in range(k)]
+        keys = np.concatenate(pieces) if device is None else torch.cat(pieces)
+        reqs.append((t, keys, vals, run_off))
     return reqs
 
 
@@ -527,16 +678,20 @@ def serve_batched(requests, qps: float, device="cuda:0", hbm_budget: int = 16 <<
     t0 = time.perf_counter()
     if not requests:
         all_done.set()
-    for i, (t, keys, vals) in enumerate(requests):
+    for i, (t, keys, vals, *runs) in enumerate(requests):
         at = t0 + t / qps
         _wait_until(at)
         arrivals.append(at)
-        server.submit(keys, vals, arrival=at).add_done_callback(lambda f, i=i: on_done(i, f))
+        if runs:
+            fut = server.submit_merge(keys, runs[0], vals, arrival=at)
+        else:
+            fut = server.submit(keys, vals, arrival=at)
+        fut.add_done_callback(lambda f, i=i: on_done(i, f))
     all_done.wait()
     wall = time.perf_counter() - t0
     stats = {"batches": server.batches, "mean_batch": round(float(np.mean(server.batch_sizes)), 2),
              "peak_hbm_bytes": server.peak_used, "hbm_budget": server.budget,
-             "max_batch_keys": server.max_batch_keys}
+             "min_free_hbm_bytes": server.min_free_hbm, "max_batch_keys": server.max_batch_keys}
     if own:
         server.close()
     if any(tm is None for tm in timings):  # a request failed: its future holds the error
@@ -557,7 +712,7 @@ def _p50(xs):
 
 def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.8, 0.95, 1.5), seed: int = 1, device="cuda:0",
                           hbm_budget: int = 16 << 30, lo: int = 1 << 10, hi: int = 1 << 24,
-                          max_batch_keys: int = 1 << 24, resident: str = "host"):
+                          max_batch_keys: int = 1 << 24, resident: str = "host", merge_fraction: float = 0.0):
     """p50/p99 latency and Gkeys/s of the batched server and of the serial
     baseline at fractions of the baseline's saturation request rate (above 1:
     more requests per second than one-at-a-time serving can complete), and
@@ -565,11 +720,13 @@ def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.8, 0.95, 1.5), seed: i
 
     ``resident="host"``: requests and results are host arrays (every request
     crosses PCIe twice); ``"device"``: they are CUDA tensors already in HBM.
+    ``merge_fraction`` of the requests are merges of sorted runs.
     """
-    reqs = make_requests(count, lo=lo, hi=hi, seed=seed, device=device if resident == "device" else None)
-    total_keys = sum(int(k.numel()) if isinstance(k, torch.Tensor) else k.size for _, k, _ in reqs)
+    reqs = make_requests(count, lo=lo, hi=hi, seed=seed, device=device if resident == "device" else None,
+                         merge_fraction=merge_fraction)
+    total_keys = sum(int(k.numel()) if isinstance(k, torch.Tensor) else k.size for _, k, *_ in reqs)
     out = {"requests": count, "resident": resident, "total_keys": int(total_keys), "sizes": [lo, hi],
-           "pairs_fraction": 0.5, "hbm_budget_bytes": hbm_budget, "runs": []}
+           "pairs_fraction": 0.5, "merge_fraction": merge_fraction, "hbm_budget_bytes": hbm_budget, "runs": []}
     reserve = 0 if resident == "device" else min(max(hi, max_batch_keys), total_keys)
     with SortServer(device, hbm_budget=hbm_budget, max_batch_keys=max_batch_keys, reserve_keys=reserve) as server:
         # warm up both paths over the whole request set (library load, buffer growth)
@@ -582,7 +739,7 @@ def run_serving_benchmark(count: int = 400, fracs=(0.5, 0.8, 0.95, 1.5), seed: i
         out["batched_saturation_qps"] = round(count / bsat_wall, 2)
         for frac in fracs:
             qps = frac * sat_qps
-            timed = [(t / qps, k, v) for t, k, v in reqs]
+            timed = [(t / qps, *rest) for t, *rest in reqs]
             _, slat, swall = serve_serial(timed, device, realtime=True, keep_results=False)
             _, blat, bwall, bst = serve_batched(reqs, qps=qps, server=server, keep_results=False)
             out["runs"].append({

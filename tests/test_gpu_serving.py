@@ -109,3 +109,108 @@ def test_device_serving_benchmark_small(serve):
     out = serve.run_serving_benchmark(count=40, fracs=(0.8,), lo=1 << 10, hi=1 << 18, resident="device")
     run = out["runs"][0]
     assert run["batched"]["p99_ms"] > 0 and run["serial"]["p99_ms"] > 0
+
+
+def _merge_requests(count, seed, hi=1 << 17):
+    """Merge requests: k sorted runs of uneven length (some empty), keys with
+    heavy ties every third request so that the stable order by run matters."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for i in range(count):
+        k = int(rng.integers(1, 12))
+        lens = rng.integers(0, hi // k + 1, size=k)
+        if i % 4 == 0:
+            lens[0] = 0  # an empty run
+        runs = []
+        for j, ln in enumerate(lens):
+            dist = "distinct16" if i % 3 == 0 else "uniform"
+            runs.append(np.sort(workloads.keys_u32(dist, int(ln), seed=seed * 1000 + 17 * i + j)))
+        keys = np.concatenate(runs).astype(np.uint32)
+        offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+        vals = workloads.draws_u32(seed * 11 + i, keys.size) if i % 2 else None
+        reqs.append((0.0, keys, vals, offs))
+    return reqs
+
+
+def test_merge_requests_mixed_with_sorts(serve):
+    """Merge requests (host and device, keys and pairs) batched together with
+    sort requests: each result equals the serial path's and the oracle's
+    (tolerance 0)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    reqs = _requests(12, seed=21) + _merge_requests(12, seed=22)
+    order = np.random.Generator(np.random.PCG64(23)).permutation(len(reqs))
+    reqs = [reqs[i] for i in order]
+    alone, _, _ = serve.serve_serial(reqs, realtime=False)
+    with serve.SortServer(hbm_budget=1 << 30, solo_keys=1 << 16) as srv:
+        with srv.held():
+            futs = []
+            for i, (_, k, v, *runs) in enumerate(reqs):
+                on_dev = i % 3 == 1
+                if on_dev:
+                    k = torch.from_numpy(k).to(dev)
+                    v = torch.from_numpy(v).to(dev) if v is not None else None
+                futs.append(srv.submit_merge(k, runs[0], v) if runs else srv.submit(k, v))
+        got = [f.result(timeout=120) for f in futs]
+        assert srv.batches == 1
+    for i, ((_, k, v, *runs), a, g) in enumerate(zip(reqs, alone, got)):
+        host = lambda x: x.cpu().numpy() if isinstance(x, torch.Tensor) else x
+        if runs:
+            want = oracle.merge_runs(k, runs[0], v)
+        else:
+            want = oracle.sort_u32(k) if v is None else oracle.sort_pairs_u32(k, v)
+        if v is None:
+            assert np.array_equal(host(g), want) and np.array_equal(a, want), i
+        else:
+            assert np.array_equal(host(g[0]), want[0]) and np.array_equal(host(g[1]), want[1]), i
+            assert np.array_equal(a[0], want[0]) and np.array_equal(a[1], want[1]), i
+
+
+def test_merge_request_offsets_validated(serve):
+    with serve.SortServer(hbm_budget=1 << 30) as srv:
+        keys = np.arange(10, dtype=np.uint32)
+        with pytest.raises(ValueError):
+            srv.submit_merge(keys, [0, 5, 9])      # does not end at n
+        with pytest.raises(ValueError):
+            srv.submit_merge(keys, [0, 6, 5, 10])  # not monotone
+        with pytest.raises(ValueError):
+            srv.submit_merge(keys, [1, 10])        # does not start at 0
+        assert np.array_equal(srv.submit_merge(keys, [0, 10]).result(timeout=60), keys)
+
+
+def test_admission_by_free_hbm(serve):
+    """Admission takes the smaller of the budget and the HBM free on the
+    device: with the free figure pinned low, a request that fits the budget
+    but not the free HBM is rejected while nothing is in flight, a smaller one
+    is served, and the real figure is within the device's memory."""
+    import torch
+
+    with serve.SortServer(hbm_budget=1 << 40, hbm_headroom=0) as srv:
+        real = srv._free_hbm()
+        assert 0 < real <= torch.cuda.get_device_properties(0).total_memory
+        srv._free_hbm = lambda: 4 << 20  # 4 MiB "free"
+        big = workloads.keys_u32("uniform", 1 << 19, seed=4)     # 6 MiB + margin: does not fit
+        small = workloads.keys_u32("uniform", 1 << 16, seed=5)   # 0.8 MiB: fits
+        with pytest.raises(MemoryError):
+            srv.submit(big).result(timeout=60)
+        assert np.array_equal(srv.submit(small).result(timeout=60), oracle.sort_u32(small))
+        assert srv.min_free_hbm == 4 << 20
+
+
+def test_inline_launch_when_idle(serve):
+    """A lone request on an idle server is launched on the submitting thread:
+    its admission and launch timestamps fall inside the submit call."""
+    import time
+
+    keys = workloads.keys_u32("uniform", 3000, seed=8)
+    with serve.SortServer(hbm_budget=1 << 30) as srv:
+        srv.submit(keys).result(timeout=60)  # warm-up
+        t0 = time.perf_counter()
+        f = srv.submit(keys)
+        t1 = time.perf_counter()
+        assert np.array_equal(f.result(timeout=60), oracle.sort_u32(keys))
+        tm = f.timing
+        assert t0 <= tm["admitted"] <= tm["launched"] <= t1
+    with serve.SortServer(hbm_budget=1 << 30, inline=False) as srv:
+        assert np.array_equal(srv.submit(keys).result(timeout=60), oracle.sort_u32(keys))
