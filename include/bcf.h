@@ -125,15 +125,13 @@ bcf_status bcf_sort_pairs_f32(const float *keys_in, const uint32_t *vals_in, flo
 
 /*
  * Sort of unsigned 64-bit keys (an extension: the paper's keys are 32-bit),
- * ascending.  A key is two 32-bit digits, sorted least significant first by
- * two stable pair sorts on bcf_sort_pairs_u32's path: by the low halves
- * carrying the high halves, then by the high halves carrying the low halves
- * (stability keeps equal high halves in low-half order); two streaming passes
- * split the keys into halves and join them back.
+ * ascending, on the design of bcf_sort_u32 with a key held in a register pair
+ * and compared as one 64-bit integer: the block sort of the paper's base case
+ * (Sec. 3.1) into runs of 4096 keys, then binary merge passes (Sec. 3.2).
  *   keys_in, keys_out  device, n u64 each, 8-byte aligned (keys_out may equal keys_in)
  *   n                  at most 2^32 - 1 (else BCF_ERR_INVALID)
- *   temp               four arrays of n u32 (256-byte aligned each) plus the pair
- *                      sort's temp for n; query with temp == NULL as for the other sorts
+ *   temp               one array of n u64 (256-byte aligned size) when n > 4096,
+ *                      none otherwise; query with temp == NULL as for the other sorts
  */
 bcf_status bcf_sort_u64(const uint64_t *keys_in, uint64_t *keys_out, uint64_t n, void *temp,
                         uint64_t *temp_bytes, void *stream);

@@ -244,8 +244,9 @@ def sort_pairs_f32(keys, vals, keys_out=None, vals_out=None, stream=None, worksp
 
 
 def sort_u64(keys, out=None, stream=None, workspace=None):
-    """Ascending sort of a contiguous torch.uint64 CUDA tensor (two stable
-    32-bit pair sorts, low halves first).  Returns ``out``."""
+    """Ascending sort of a contiguous torch.uint64 CUDA tensor (``bcf_sort_u64``:
+    keys in register pairs, block sort and binary merge passes).  Returns
+    ``out``."""
     lib = load()
     for name, t in (("keys", keys), ("out", out)):
         if t is not None and (not isinstance(t, torch.Tensor) or t.dtype != torch.uint64 or not t.is_cuda

@@ -241,8 +241,10 @@ std::vector<uint32_t> sort_fan_ins(bool pairs, uint64_t n, const Tuning &tu)
     return fi;
 }
 
+// kind 0: u32 keys; 1 int32, 2 float: keys are mapped in order to u32 as the
+// block sort loads them and mapped back as the last pass stores them.
 bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
-                     uint64_t n, void *temp, uint64_t *temp_bytes, hipStream_t s)
+                     uint64_t n, void *temp, uint64_t *temp_bytes, hipStream_t s, int kind = 0)
 {
     if (!temp_bytes || n > kMaxN)
         return BCF_ERR_INVALID;
@@ -291,16 +293,20 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     auto kbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? kout : kt; };
     auto vbuf = [&](uint32_t j) { return ((passes - j) % 2 == 0) ? vout : vt; };
     const double elem_bytes = pairs ? 8.0 : 4.0;
+    const KeyMap fwd = key_map(kind, false), inv = key_map(kind, true);
+    // the pass that writes the output stores through the inverse map
+    auto out_map = [&](uint32_t j) { return j == passes ? inv : KeyMap{}; };
     {
         ProfScope p(kname_block_sort(pairs, false), s, 2.0 * elem_bytes * n);
         const SampleSet smp = (passes && sampled) ? sample_set(0) : none;
-        if (sort_uses_groups(n, tu) && tu.block_sort == 4 && !pairs)
+        if (sort_uses_groups(n, tu) && tu.block_sort == 4 && !pairs && kind == 0)
             BCF_TRY(dev_status(launch_block_sort_shear_group(kin, kbuf(0), n, smp, s)));
         else if (sort_uses_groups(n, tu))
-            BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, smp, s)));
+            BCF_TRY(dev_status(launch_block_sort_group(pairs, kin, vin, kbuf(0), pairs ? vbuf(0) : nullptr, n, smp, s,
+                                                       fwd, out_map(0))));
         else
             BCF_TRY(dev_status(launch_block_sort_regular(pairs, tu.block_sort == 2, kin, vin, kbuf(0),
-                                                         pairs ? vbuf(0) : nullptr, n, smp, s)));
+                                                         pairs ? vbuf(0) : nullptr, n, smp, s, fwd, out_map(0))));
     }
     void *cuts = static_cast<char *>(temp) + data + align256(tiles * 4) + 2 * set_bytes;
     uint64_t run = run0;
@@ -312,7 +318,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
                 const bool cut = phase == 0;
                 ProfScope p(cut ? "cuts4_keys" : "merge4_keys", s, cut ? 0.0 : 2.0 * elem_bytes * n);
                 BCF_TRY(dev_status(launch_merge4_regular(kbuf(j - 1), kbuf(j), n, run, cuts, in_smp, out_smp, cut,
-                                                         s)));
+                                                         s, out_map(j))));
             }
             continue;
         }
@@ -328,7 +334,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
             const SampleSet out_smp = (sampled && j < passes) ? sample_set(j & 1) : none;
             BCF_TRY(dev_status(launch_merge_regular(pairs, kbuf(j - 1), pairs ? vbuf(j - 1) : nullptr, kbuf(j),
                                                     pairs ? vbuf(j) : nullptr, n, run, splits, in_smp, out_smp,
-                                                    part, fused, s)));
+                                                    part, fused, s, out_map(j))));
         }
     }
     return BCF_OK;
@@ -336,33 +342,15 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
 
 // ---------------------------------------------------- other key types
 
-// Sort of int32 (kind 1) or float (kind 2) keys: the keys are mapped in order
-// into the output, sorted there in place as u32, and mapped back.  The temp
-// size is that of the u32 sort; everything is checked before the first launch.
+// Sort of int32 (kind 1) or float (kind 2) keys: the u32 sort with the
+// order-preserving key map fused into its first and last pass (no extra pass
+// over the keys).  The temp size is that of the u32 sort.
 bcf_status sort_typed(int kind, bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
                       uint32_t *vout, uint64_t n, void *temp, uint64_t *temp_bytes, hipStream_t s)
 {
-    if (!temp_bytes || n > kMaxN)
+    if (kind != 1 && kind != 2)
         return BCF_ERR_INVALID;
-    uint64_t need = 0;
-    BCF_TRY(sort_impl(pairs, nullptr, nullptr, nullptr, nullptr, n, nullptr, &need, s));
-    if (!temp) {
-        *temp_bytes = need;
-        return BCF_OK;
-    }
-    if (n == 0)
-        return BCF_OK;
-    if (!kin || !kout || (pairs && (!vin || !vout)))
-        return BCF_ERR_INVALID;
-    if (*temp_bytes < need)
-        return BCF_ERR_TEMP_TOO_SMALL;
-    {
-        ProfScope p("map_keys", s, 8.0 * n);
-        BCF_TRY(dev_status(launch_map_keys(kin, kout, n, kind, false, s)));
-    }
-    BCF_TRY(sort_impl(pairs, kout, vin, kout, vout, n, temp, temp_bytes, s));
-    ProfScope p("map_keys", s, 8.0 * n);
-    return dev_status(launch_map_keys(kout, kout, n, kind, true, s));
+    return sort_impl(pairs, kin, vin, kout, vout, n, temp, temp_bytes, s, kind);
 }
 
 // ---------------------------------------------------- table-driven plans

@@ -63,6 +63,13 @@ struct Lines<true> {
     double e[kLine];
 };
 
+// Unsigned 64-bit keys: one key per position in a register pair, compared as
+// integers (no values, no ranks: equal keys are indistinguishable).
+struct Lines64 {
+    uint64_t e[kLine];
+};
+constexpr uint64_t kMaxKey64 = ~0ull;
+
 constexpr uint32_t kRankBits = 15;                    // group tiles of up to 32768 positions
 constexpr uint32_t kPadRank = (1u << kRankBits) - 1;  // rank of padding (never a real rank)
 constexpr int kRankShift = 52 - 32 - (int)kRankBits;  // payload in mantissa bits 51 .. 5
@@ -114,6 +121,15 @@ __device__ __forceinline__ void cx(Lines<P> &t, int a, int b)
     }
 }
 
+// 64-bit keys: one unsigned 64-bit compare and four 32-bit selects.
+__device__ __forceinline__ void cx(Lines64 &t, int a, int b)
+{
+    const uint64_t x = t.e[a], y = t.e[b];
+    const bool lt = x < y;
+    t.e[a] = lt ? x : y;
+    t.e[b] = lt ? y : x;
+}
+
 // Reverse the order of every element of a lane when `bit` is 1: the key (or
 // the element's payload) is replaced by its bitwise complement, an
 // order-reversing bijection, so an ascending network run on complemented data
@@ -132,13 +148,24 @@ __device__ __forceinline__ void flip(Lines<P> &t, uint32_t bit)
     }
 }
 
+__device__ __forceinline__ void flip(Lines64 &t, uint32_t bit)
+{
+    const uint64_t m = 0ull - (uint64_t)(bit & 1u);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        t.e[r] ^= m;
+}
+
 // ---------------------------------------------------- register-local networks
+//
+// Written once for any line type L (Lines<false>, Lines<true>, Lines64): the
+// compare-exchange cx(t, a, b) is chosen by overload.
 
 // One bitonic half-cleaner step at register distance D: registers r and r+D
 // (r with bit D clear) are compare-exchanged, ascending, or descending where
 // register bit DB of r is set (DB < 0: ascending everywhere).
-template <int D, int DB, bool P>
-__device__ __forceinline__ void half_clean_step(Lines<P> &t)
+template <int D, int DB, class L>
+__device__ __forceinline__ void half_clean_step_lines(L &t)
 {
 #pragma unroll
     for (int r = 0; r < kLine; ++r) {
@@ -153,24 +180,24 @@ __device__ __forceinline__ void half_clean_step(Lines<P> &t)
 
 // Half-cleaner cascade D, D/2, ..., 1: sorts every aligned group of 2D
 // registers that holds a bitonic sequence.
-template <int D, int DB, bool P>
-__device__ __forceinline__ void half_clean(Lines<P> &t)
+template <int D, int DB, class L>
+__device__ __forceinline__ void half_clean_lines(L &t)
 {
-    half_clean_step<D, DB, P>(t);
+    half_clean_step_lines<D, DB>(t);
     if constexpr (D > 1)
-        half_clean<D / 2, DB, P>(t);
+        half_clean_lines<D / 2, DB>(t);
 }
 
 // Batcher's odd-even merge of registers LO..HI (inclusive) whose two halves
 // are sorted, considering every R-th register (Batcher 1968; the recursive
 // formulation in Knuth, TAOCP vol. 3, Sec. 5.3.4).
-template <int LO, int HI, int R, bool P>
-__device__ __forceinline__ void oe_merge(Lines<P> &t)
+template <int LO, int HI, int R, class L>
+__device__ __forceinline__ void oe_merge_lines(L &t)
 {
     constexpr int STEP = 2 * R;
     if constexpr (STEP < HI - LO) {
-        oe_merge<LO, HI, STEP, P>(t);
-        oe_merge<LO + R, HI, STEP, P>(t);
+        oe_merge_lines<LO, HI, STEP>(t);
+        oe_merge_lines<LO + R, HI, STEP>(t);
 #pragma unroll
         for (int i = LO + R; i < HI - R; i += STEP)
             cx(t, i, i + R);
@@ -181,15 +208,37 @@ __device__ __forceinline__ void oe_merge(Lines<P> &t)
 
 // Batcher's odd-even merge sort of registers LO..HI (inclusive), ascending:
 // the per-thread line sort of the paper (Sec. 3.1; 543 comparators for 64).
-template <int LO, int HI, bool P>
-__device__ __forceinline__ void oe_sort(Lines<P> &t)
+template <int LO, int HI, class L>
+__device__ __forceinline__ void oe_sort_lines(L &t)
 {
     if constexpr (HI - LO >= 1) {
         constexpr int MID = LO + (HI - LO) / 2;
-        oe_sort<LO, MID, P>(t);
-        oe_sort<MID + 1, HI, P>(t);
-        oe_merge<LO, HI, 1, P>(t);
+        oe_sort_lines<LO, MID>(t);
+        oe_sort_lines<MID + 1, HI>(t);
+        oe_merge_lines<LO, HI, 1>(t);
     }
+}
+
+// The same networks for the 32-bit element kinds, named by the pairs flag.
+template <int D, int DB, bool P>
+__device__ __forceinline__ void half_clean_step(Lines<P> &t)
+{
+    half_clean_step_lines<D, DB>(t);
+}
+template <int D, int DB, bool P>
+__device__ __forceinline__ void half_clean(Lines<P> &t)
+{
+    half_clean_lines<D, DB>(t);
+}
+template <int LO, int HI, int R, bool P>
+__device__ __forceinline__ void oe_merge(Lines<P> &t)
+{
+    oe_merge_lines<LO, HI, R>(t);
+}
+template <int LO, int HI, bool P>
+__device__ __forceinline__ void oe_sort(Lines<P> &t)
+{
+    oe_sort_lines<LO, HI>(t);
 }
 
 // ------------------------------------------------------------ LDS transposes
@@ -263,6 +312,25 @@ __device__ __forceinline__ void exchange(double (&x)[kLine], uint32_t *lds, uint
         x[r] = elem_of(((uint64_t)hi[r] << 32) | lo[r]);
 }
 
+// The same for 64-bit keys.
+template <int WS, int RS>
+__device__ __forceinline__ void exchange(uint64_t (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
+{
+    uint32_t hi[kLine], lo[kLine];
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        hi[r] = (uint32_t)(x[r] >> 32);
+        lo[r] = (uint32_t)x[r];
+    }
+    exchange<WS, RS>(hi, lds, wbase, rbase);
+    exchange<WS, RS>(lo, lds, wbase, rbase);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = ((uint64_t)hi[r] << 32) | lo[r];
+}
+
+__device__ __forceinline__ uint64_t (&elems(Lines64 &t))[kLine] { return t.e; }
+
 template <bool P>
 __device__ __forceinline__ auto &elems(Lines<P> &t)
 {
@@ -273,16 +341,16 @@ __device__ __forceinline__ auto &elems(Lines<P> &t)
 }
 
 // STRIDED -> BLOCKED: write word 68r + lane, read word 68 lane + r.
-template <bool P>
-__device__ __forceinline__ void to_blocked(Lines<P> &t, uint32_t *lds, uint32_t lane)
+template <class L>
+__device__ __forceinline__ void to_blocked(L &t, uint32_t *lds, uint32_t lane)
 {
     exchange<kLdsStride, 1>(elems(t), lds, lane, kLdsStride * lane);
 }
 
 // BLOCKED -> STRIDED: write word 68 lane + r, read word 68r + lane.  Afterwards
 // LDS word 68q + r holds tile position 64q + r.
-template <bool P>
-__device__ __forceinline__ void to_strided(Lines<P> &t, uint32_t *lds, uint32_t lane)
+template <class L>
+__device__ __forceinline__ void to_strided(L &t, uint32_t *lds, uint32_t lane)
 {
     exchange<1, kLdsStride>(elems(t), lds, kLdsStride * lane, lane);
 }
@@ -398,9 +466,9 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 // theirs; each round probes 32 evenly spaced candidates per half and keeps
 // the bracket between the last failing and the first passing probe, so a
 // search over 2^25 candidates takes 5 rounds of loads.
-__device__ __forceinline__ uint32_t corank_halfwave(const uint32_t *__restrict__ A, uint32_t na,
-                                                    const uint32_t *__restrict__ B, uint32_t nb,
-                                                    uint32_t d, uint32_t lane)
+template <class K>
+__device__ __forceinline__ uint32_t corank_halfwave(const K *__restrict__ A, uint32_t na, const K *__restrict__ B,
+                                                    uint32_t nb, uint32_t d, uint32_t lane)
 {
     const uint32_t k = lane & 31;
     const uint32_t shift = lane & 32;  // 0 or 32: position of this half in the ballot

@@ -26,6 +26,16 @@ struct SampleSet {
     uint32_t *f, *l, *cf, *cl;
 };
 
+// Order-preserving map between another 32-bit key type and u32, applied to a
+// key as it is loaded (forward) or stored (inverse): x ^ (sign | (s & rest))
+// with s the arithmetic sign extension of x (forward) or of ~x (inverse).
+// int32: (sign, rest) = (0x80000000, 0); IEEE binary32 ordered by totalOrder:
+// (0x80000000, 0x7fffffff).  sign == 0 is the identity (u32 keys).
+struct KeyMap {
+    uint32_t sign = 0, rest = 0, inverse = 0;
+};
+KeyMap key_map(int kind, bool inverse);  // kind 0 (identity), 1 int32, 2 float
+
 // One tile of the block sort: `count` (<= kTile) keys starting at element
 // `start` of the input, sorted into buffer `dst` at the same offset.
 struct BlockTile {
@@ -54,9 +64,11 @@ constexpr int kGroupWavesPairs = 4;
 uint32_t group_run_keys(bool pairs);
 
 // Launchers (enqueue only; return the launch status).
+// in_map is applied to the keys as they are loaded, out_map as they are stored
+// (the block sort writes the output itself when it is the only pass).
 hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin,
                                    uint32_t *kout, uint32_t *vout, uint64_t n, SampleSet out_smp,
-                                   hipStream_t s);
+                                   hipStream_t s, KeyMap in_map = {}, KeyMap out_map = {});
 // Keys only: group tiles sorted by the paper's long ShearSort over the waves
 // of a work-group (block-sort ablation); same runs and samples as the group
 // sort of launch_block_sort_group.
@@ -66,7 +78,7 @@ hipError_t launch_block_sort_shear_group(const uint32_t *kin, uint32_t *kout, ui
 // shear, by the paper's ShearSort; writes the samples of its output (out_smp).
 hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin, const uint32_t *vin,
                                      uint32_t *kout, uint32_t *vout, uint64_t n, SampleSet out_smp,
-                                     hipStream_t s);
+                                     hipStream_t s, KeyMap in_map = {}, KeyMap out_map = {});
 // A merge pass is two launches: with partition = true the split of every
 // tile is written to `splits` (one u32 per tile of the pass); with
 // partition = false the tiles are merged using those splits.
@@ -82,7 +94,7 @@ bool merge_fuses_partition(bool pairs, const SampleSet &in_smp, const Tuning &tu
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc,
                                 uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
                                 uint32_t *splits, SampleSet in_smp, SampleSet out_smp,
-                                bool partition, bool fused, hipStream_t s);
+                                bool partition, bool fused, hipStream_t s, KeyMap out_map = {});
 // Fan-in 4 merge pass of a regular keys-only sort: groups of four runs of
 // `run` keys (a multiple of 4096) become runs of 4 run.  The cut phase
 // (cut_phase = true) searches the pass's work split from the samples of the
@@ -91,10 +103,8 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
 uint64_t merge4_cut_bytes(uint64_t n, uint64_t run);
 uint64_t merge4_cut_bytes_max(uint64_t n);  // the largest over every plan of an n-key sort
 hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t n, uint64_t run, void *cuts,
-                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s);
-// Order-preserving key map to u32 (inverse = false) or back (true), in place
-// allowed: kind 1 = int32, 2 = IEEE binary32 (totalOrder).
-hipError_t launch_map_keys(const uint32_t *in, uint32_t *out, uint64_t n, int kind, bool inverse, hipStream_t s);
+                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s,
+                                 KeyMap out_map = {});
 // Table launches: the grid covers ntiles (ngroups) tiles; with count_dev set
 // the kernels take the actual count from that device word (at most the bound),
 // so that a device planner can size the work after the launch was enqueued.

@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bcf_device.hpp"
 #include "bcf_internal.hpp"
@@ -51,13 +52,39 @@ __device__ __forceinline__ void st(uint32_t *p, uint32_t v)
         *p = v;
 }
 
+// Order-preserving maps between other 32-bit key types and u32: signed
+// integers flip the sign bit; IEEE binary32 floats flip the sign bit of a
+// non-negative value and every bit of a negative one, which orders the bit
+// patterns by IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf
+// < +NaN).  With (sign, rest) = (0x80000000, 0) for i32 and (0x80000000,
+// 0x7fffffff) for f32 the map is x ^ (sign | (x >> 31 arithmetic) & rest) and
+// its inverse t ^ (sign | (~t >> 31 arithmetic) & rest).
+__device__ __forceinline__ uint32_t map_key(uint32_t x, uint32_t sign, uint32_t rest, uint32_t inverse)
+{
+    const uint32_t s = (uint32_t)((int32_t)(inverse ? ~x : x) >> 31);
+    return x ^ (sign | (s & rest));
+}
+
+KeyMap key_map(int kind, bool inverse)
+{
+    KeyMap m;
+    if (kind == 1 || kind == 2) {
+        m.sign = 0x80000000u;
+        m.rest = kind == 2 ? 0x7fffffffu : 0u;
+        m.inverse = inverse ? 1u : 0u;
+    }
+    return m;
+}
+
 // Load `count` keys starting at `ksrc` into STRIDED layout (position
-// p = 64r + lane); positions >= count become padding (max key, max rank).
+// p = 64r + lane); positions >= count become padding (key `pad`, max rank).
 // For pairs the element's rank is rank0 + p, its position in the input order;
-// values are not loaded here (see permute_values_lds / gather_values).
+// values are not loaded here (see permute_values_lds / gather_values).  The
+// pad is the maximum key, or for keys that go through a key map the key that
+// the map sends to the maximum, so that the map applies to every position.
 template <bool P>
 __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restrict__ ksrc, uint32_t count,
-                                          uint32_t lane, uint32_t rank0 = 0)
+                                          uint32_t lane, uint32_t rank0 = 0, uint32_t pad = kMaxKey)
 {
     const uint32_t *kp = ksrc + lane;
     if constexpr (P) {
@@ -79,7 +106,7 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
 #pragma unroll
         for (int r = 0; r < kLine; ++r) {
             const uint32_t p = kWave * r + lane;
-            t.e[r] = p < count ? make_elem(key[r], rank0 + p) : make_elem(kMaxKey, kPadRank);
+            t.e[r] = p < count ? make_elem(key[r], rank0 + p) : make_elem(pad, kPadRank);
         }
     } else if (count >= (uint32_t)kTile) {
 #pragma unroll
@@ -91,8 +118,8 @@ __device__ __forceinline__ void load_tile(Lines<P> &t, const uint32_t *__restric
         for (int r = 0; r < kLine; ++r) {
             const uint32_t p = kWave * r + lane;
             const uint32_t q = p < count ? p : last;  // clamped: always a valid address
-            const uint32_t key = count ? ksrc[q] : kMaxKey;
-            t.k[r] = p < count ? key : kMaxKey;
+            const uint32_t key = count ? ksrc[q] : pad;
+            t.k[r] = p < count ? key : pad;
         }
     }
 }
@@ -127,6 +154,83 @@ __device__ __forceinline__ void store_tile(const Lines<P> &t, uint32_t *__restri
                 }
             }
         }
+    }
+}
+
+// A work source whose keys go through a key map: the forward map as the block
+// sort loads them, the inverse as the pass that writes the output stores
+// them.  A separate type so that sources of u32 sorts compile without the
+// map (kMapped = false): a run-time test alone costs the kernels registers.
+template <class Base>
+struct Mapped : Base {
+    static constexpr bool kMapped = true;
+    KeyMap in_map, out_map;
+};
+
+// The forward key map on a freshly loaded STRIDED tile, every position: the
+// tile was padded with pad_key(src), which the map sends to the maximum key.
+template <bool P>
+__device__ __forceinline__ void map_tile_in(Lines<P> &t, const KeyMap &m);
+
+template <bool P, class Src>
+__device__ __forceinline__ void map_tile_in(Lines<P> &t, const Src &src)
+{
+    if constexpr (Src::kMapped)
+        map_tile_in<P>(t, src.in_map);
+}
+
+// The padding key of a block-sort tile: the maximum, or its preimage under
+// the source's forward key map.
+template <class Src>
+__device__ __forceinline__ uint32_t pad_key(const Src &src)
+{
+    if constexpr (Src::kMapped)
+        return map_key(kMaxKey, src.in_map.sign, src.in_map.rest, 1u - src.in_map.inverse);
+    else
+        return kMaxKey;
+}
+
+template <bool P>
+__device__ __forceinline__ void map_tile_in(Lines<P> &t, const KeyMap &m)
+{
+    if (m.sign == 0)
+        return;
+    // one register at a time (the scheduling barrier keeps the compiler from
+    // computing every register's map before storing any: 64 temporaries)
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        if constexpr (P)
+            t.e[r] = make_elem(map_key(elem_key(t.e[r]), m.sign, m.rest, m.inverse), elem_rank(t.e[r]));
+        else
+            t.k[r] = map_key(t.k[r], m.sign, m.rest, m.inverse);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The inverse key map on a tile about to be stored (pairs: in output form,
+// key in the high half).  Padding positions are never stored.
+template <bool P>
+__device__ __forceinline__ void map_tile_out(Lines<P> &t, const KeyMap &m);
+
+template <bool P, class Src>
+__device__ __forceinline__ void map_tile_out(Lines<P> &t, const Src &src)
+{
+    if constexpr (Src::kMapped)
+        map_tile_out<P>(t, src.out_map);
+}
+
+template <bool P>
+__device__ __forceinline__ void map_tile_out(Lines<P> &t, const KeyMap &m)
+{
+    if (m.sign == 0)
+        return;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        if constexpr (P)
+            t.e[r] = make_out(map_key(out_key(t.e[r]), m.sign, m.rest, m.inverse), out_value(t.e[r]));
+        else
+            t.k[r] = map_key(t.k[r], m.sign, m.rest, m.inverse);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -496,6 +600,7 @@ struct RegularSortSrc {
     uint64_t n;
     uint32_t ntiles;
     SampleSet out_smp;
+    static constexpr bool kMapped = false;
     __device__ uint64_t pos(uint32_t t) const { return (uint64_t)t * kTile; }
     __device__ SortItem get(uint32_t t) const
     {
@@ -528,6 +633,7 @@ struct TableSortSrc {
     uint32_t ntiles;
     SampleSet out_smp;  // always empty: table tiles start anywhere
     const uint32_t *count_dev;
+    static constexpr bool kMapped = false;
     __device__ void resolve() { ntiles = resolved_count(ntiles, count_dev); }
     __device__ uint64_t pos(uint32_t) const { return 0; }
     __device__ SortItem get(uint32_t t) const
@@ -561,6 +667,7 @@ struct RegularMergeSrc {
     uint64_t n, run;
     uint32_t ntiles;
     SampleSet in_smp, out_smp;
+    static constexpr bool kMapped = false;
     __device__ MergeItem get(uint32_t t) const
     {
         const uint64_t gstart = (uint64_t)t * kTile;
@@ -589,6 +696,7 @@ struct TableMergeSrc {
     uint32_t ntiles;
     SampleSet out_smp;  // always empty: table runs start anywhere
     const uint32_t *count_dev;
+    static constexpr bool kMapped = false;
     __device__ void resolve() { ntiles = resolved_count(ntiles, count_dev); }
 
     __device__ MergeItem get(uint32_t t) const
@@ -658,6 +766,7 @@ template <bool P, bool SHEAR, class Src>
 __device__ __forceinline__ void wave_tile(Lines<P> &a, const SortItem &it, const Src &src, uint32_t t, uint32_t *lds,
                                           uint32_t lane)
 {
+    map_tile_in<P>(a, src);
     if constexpr (SHEAR)
         shear_sort_blocked<P>(a, lds, lane);
     else
@@ -666,6 +775,7 @@ __device__ __forceinline__ void wave_tile(Lines<P> &a, const SortItem &it, const
     to_strided(a, lds, lane);
     if constexpr (P)
         permute_values_lds(a, it.vs, it.count, lds, 0, it.count, lane, wave_lds_fence);
+    map_tile_out<P>(a, src);
     store_tile<P>(a, it.kd, it.vd, it.count, lane);
 }
 
@@ -686,20 +796,20 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
             const uint32_t ln = opaque(lane);
             const SortItem it = src.get(t);
             Lines<P> a;
-            load_tile<P>(a, it.ks, it.count, ln);
+            load_tile<P>(a, it.ks, it.count, ln, 0, pad_key(src));
             wave_tile<P, SHEAR>(a, it, src, t, lds, ln);
         }
     } else {
         Lines<P> a, b;
         SortItem ia = src.get(t), ib;
-        load_tile<P>(a, ia.ks, ia.count, lane);
+        load_tile<P>(a, ia.ks, ia.count, lane, 0, pad_key(src));
         for (;;) {
             uint32_t ln = opaque(lane);
             const uint32_t tb = t + G;
             const bool hb = tb < src.ntiles;
             if (hb) {
                 ib = src.get(tb);
-                load_tile<P>(b, ib.ks, ib.count, ln);
+                load_tile<P>(b, ib.ks, ib.count, ln, 0, pad_key(src));
             }
             wave_tile<P, SHEAR>(a, ia, src, t, lds, ln);
             if (!hb)
@@ -709,7 +819,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_block_sort(Src src)
             const bool ha = t < src.ntiles;
             if (ha) {
                 ia = src.get(t);
-                load_tile<P>(a, ia.ks, ia.count, ln);
+                load_tile<P>(a, ia.ks, ia.count, ln, 0, pad_key(src));
             }
             wave_tile<P, SHEAR>(b, ib, src, tb, lds, ln);
             if (!ha)
@@ -726,6 +836,7 @@ struct RegularGroupSrc {
     uint32_t ngroups;
     uint32_t group_keys;
     SampleSet out_smp;
+    static constexpr bool kMapped = false;
     __device__ uint64_t pos(uint32_t g, uint32_t w) const { return (uint64_t)g * group_keys + (uint64_t)w * kTile; }
     __device__ uint32_t group_count(uint32_t g) const
     {
@@ -754,6 +865,7 @@ struct TableGroupSrc {
     uint32_t ngroups;
     SampleSet out_smp;  // always empty
     const uint32_t *count_dev;
+    static constexpr bool kMapped = false;
     __device__ void resolve() { ngroups = resolved_count(ngroups, count_dev); }
     __device__ uint64_t pos(uint32_t, uint32_t) const { return 0; }
     __device__ uint32_t group_count(uint32_t g) const { return tiles[g].count; }
@@ -779,6 +891,7 @@ __device__ __forceinline__ void group_tile(Lines<P> &t, const SortItem &it, cons
                                            uint32_t *lds, uint32_t lane, uint32_t wave)
 {
     uint32_t *own = lds + kLdsWords * wave;
+    map_tile_in<P>(t, src);
     flip(t, wave);  // odd sub-tiles descending
     sort_tile_blocked<P>(t, own, lane);
     flip(t, wave);
@@ -793,6 +906,7 @@ __device__ __forceinline__ void group_tile(Lines<P> &t, const SortItem &it, cons
         permute_values_lds(t, i0.vs, src.group_count(g), lds, kTile * wave, it.count, lane,
                            [] { __syncthreads(); });
     }
+    map_tile_out<P>(t, src);
     store_tile<P>(t, it.kd, it.vd, it.count, lane);
 }
 
@@ -816,20 +930,20 @@ __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
             const uint32_t ln = opaque(lane);
             const SortItem it = src.get(g, wave);
             Lines<P> t;
-            load_tile<P>(t, it.ks, it.count, ln, wave * kTile);
+            load_tile<P>(t, it.ks, it.count, ln, wave * kTile, pad_key(src));
             group_tile<NW, P>(t, it, src, g, lds, ln, wave);
         }
     } else {
         Lines<P> a, b;
         SortItem ia = src.get(g, wave), ib;
-        load_tile<P>(a, ia.ks, ia.count, lane);
+        load_tile<P>(a, ia.ks, ia.count, lane, 0, pad_key(src));
         for (;;) {
             uint32_t ln = opaque(lane);
             const uint32_t gb = g + gridDim.x;
             const bool hb = gb < src.ngroups;
             if (hb) {
                 ib = src.get(gb, wave);
-                load_tile<P>(b, ib.ks, ib.count, ln);
+                load_tile<P>(b, ib.ks, ib.count, ln, 0, pad_key(src));
             }
             group_tile<NW, P>(a, ia, src, g, lds, ln, wave);
             if (!hb)
@@ -839,7 +953,7 @@ __global__ __launch_bounds__(kWave *NW) void k_block_sort_group(Src src)
             const bool ha = g < src.ngroups;
             if (ha) {
                 ia = src.get(g, wave);
-                load_tile<P>(a, ia.ks, ia.count, ln);
+                load_tile<P>(a, ia.ks, ia.count, ln, 0, pad_key(src));
             }
             group_tile<NW, P>(b, ib, src, gb, lds, ln, wave);
             if (!ha)
@@ -1160,9 +1274,14 @@ __device__ __forceinline__ void fused_splits(const RegularMergeSrc &src, const M
     a1 = __builtin_amdgcn_readlane(lo, 32);
 }
 
+// Other sources (tables) never fuse; a regular source that carries a key map
+// (derived from RegularMergeSrc) searches like its base.
 template <class Src>
-__device__ __forceinline__ void fused_splits(const Src &, const MergeItem &, uint32_t, uint32_t &, uint32_t &)
+__device__ __forceinline__ void fused_splits(const Src &src, const MergeItem &m, uint32_t lane, uint32_t &a0,
+                                             uint32_t &a1)
 {
+    if constexpr (std::is_base_of_v<RegularMergeSrc, Src>)
+        fused_splits(static_cast<const RegularMergeSrc &>(src), m, lane, a0, a1);
 }
 
 // Work-groups of the one-tile-per-wave merge (MODE 2) hold a single wave: the
@@ -1207,6 +1326,7 @@ __global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src 
         merge_network<P>(a, lds, lane, src.out_smp, m.gpos, m.count);
         if constexpr (P)
             gather_values(a, m, vals, lane);
+        map_tile_out<P>(a, src);
         store_tile<P, NT>(a, m.kd, m.vd, m.count, lane);
     } else if constexpr (P || MODE == 1) {
         for (; t < src.ntiles; t += G) {
@@ -1219,6 +1339,7 @@ __global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src 
             merge_network<P>(a, lds, ln, src.out_smp, m.gpos, m.count);
             if constexpr (P)
                 gather_values(a, m, vals, ln);
+            map_tile_out<P>(a, src);
             store_tile<P, NT>(a, m.kd, m.vd, m.count, ln);
         }
     } else {
@@ -1234,6 +1355,7 @@ __global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src 
                 merge_load<P>(b, mb, ln);
             }
             merge_network<P>(a, lds, ln, src.out_smp, ma.gpos, ma.count);
+            map_tile_out<P>(a, src);
             store_tile<P>(a, ma.kd, ma.vd, ma.count, ln);
             if (!hb)
                 break;
@@ -1245,6 +1367,7 @@ __global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src 
                 merge_load<P>(a, ma, ln);
             }
             merge_network<P>(b, lds, ln, src.out_smp, mb.gpos, mb.count);
+            map_tile_out<P>(b, src);
             store_tile<P>(b, mb.kd, mb.vd, mb.count, ln);
             if (!ha)
                 break;
@@ -1323,6 +1446,7 @@ struct Merge4Src {
     uint32_t jfull, mfull;  // AB segments and interior CD cuts of a full group
     uint4 *cuts;
     SampleSet in_smp, out_smp;
+    KeyMap out_map;
     __host__ __device__ uint32_t stride() const { return jfull + mfull + 2; }
 };
 
@@ -1488,9 +1612,9 @@ __device__ __forceinline__ uint32_t lds_word_of_quad(const uint32_t *w, uint32_t
 // mod 64): in BLOCKED layout that is register bf (bl) of lane k, read back
 // from the LDS matrix while it holds the lane's registers (16-byte reads, one
 // per sample: no bank conflicts).
-template <bool NT>
+template <bool NT, bool MAP>
 __device__ __forceinline__ void emit_blocked(Lines<false> &t, uint32_t *lds, uint32_t *kdst, uint64_t gpos,
-                                             uint32_t count, const SampleSet &smp, uint32_t lane)
+                                             uint32_t count, const SampleSet &smp, const KeyMap &km, uint32_t lane)
 {
     const uint32_t bf = (uint32_t)((kLine - gpos % kLine) % kLine);
     const uint32_t bl = (bf + kLine - 1) % kLine;
@@ -1532,15 +1656,17 @@ __device__ __forceinline__ void emit_blocked(Lines<false> &t, uint32_t *lds, uin
                 smp.cl[gp / kTile] = l;
         }
     }
+    if constexpr (MAP)
+        map_tile_out<false>(t, km);
     store_bounded<NT>(t, kdst + gpos, count, lane);
 }
 
 // An item of one piece (count <= 2048 keys, already sorted) copied to array
 // position gpos with the samples that fall inside it, by coalesced loads and
 // stores: every lane moves the elements lane + 64 k.
-template <bool NT>
+template <bool NT, bool MAP>
 __device__ __forceinline__ void copy4(const uint32_t *x, uint32_t *kdst, uint64_t gpos, uint32_t count,
-                                      const SampleSet &smp, uint32_t lane)
+                                      const SampleSet &smp, const KeyMap &km, uint32_t lane)
 {
     constexpr int kRows = kHalfTile / kWave;
     uint32_t v[kRows];
@@ -1548,6 +1674,11 @@ __device__ __forceinline__ void copy4(const uint32_t *x, uint32_t *kdst, uint64_
     for (int k = 0; k < kRows; ++k) {
         const uint32_t i = kWave * k + lane;
         v[k] = ld<NT>(x + (i < count ? i : count - 1));  // clamped: always inside the piece
+    }
+    if constexpr (MAP) {
+#pragma unroll
+        for (int k = 0; k < kRows; ++k)
+            v[k] = map_key(v[k], km.sign, km.rest, km.inverse);
     }
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
@@ -1644,7 +1775,7 @@ constexpr int kMerge4Waves = 1;  // one wave per work-group (see kMergeTileWaves
 // the 9 KiB of LDS per wave allow.  Keys only:
 // equal keys are indistinguishable, so only the cuts (exact counts) decide
 // which keys an item holds.
-template <bool NT>
+template <bool NT, bool MAP = false>
 __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(4))) void k_merge4(
     Merge4Src src)
 {
@@ -1715,7 +1846,8 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
     const uint32_t oa = c0.x, ob = (uint32_t)L + c0.y, oc = 2 * (uint32_t)L + c0.z, od = 3 * (uint32_t)L + c0.w;
     if (pieces == 1) {
         // one piece: already sorted, copied as it is (no network, no LDS)
-        copy4<NT>(src.ksrc + G.start + (pa ? oa : pb ? ob : pc ? oc : od), src.kdst, gpos, count, src.out_smp, lane);
+        copy4<NT, MAP>(src.ksrc + G.start + (pa ? oa : pb ? ob : pc ? oc : od), src.kdst, gpos, count, src.out_smp,
+                       src.out_map, lane);
         return;
     }
     HalfPieces hp;
@@ -1737,40 +1869,7 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
     if (pieces >= 3)
         packed_network(t, lds, lane);
     merge4_network(t, lds, lane);
-    emit_blocked<NT>(t, lds, src.kdst, gpos, count, src.out_smp, lane);
-}
-
-// Order-preserving maps between other 32-bit key types and u32: signed
-// integers flip the sign bit; IEEE binary32 floats flip the sign bit of a
-// non-negative value and every bit of a negative one, which orders the bit
-// patterns by IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf
-// < +NaN).  With (sign, rest) = (0x80000000, 0) for i32 and (0x80000000,
-// 0x7fffffff) for f32 the map is x ^ (sign | (x >> 31 arithmetic) & rest) and
-// its inverse t ^ (sign | (~t >> 31 arithmetic) & rest).
-__device__ __forceinline__ uint32_t map_key(uint32_t x, uint32_t sign, uint32_t rest, uint32_t inverse)
-{
-    const uint32_t s = (uint32_t)((int32_t)(inverse ? ~x : x) >> 31);
-    return x ^ (sign | (s & rest));
-}
-
-__global__ __launch_bounds__(256) void k_map_keys(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t sign,
-                                                  uint32_t rest, uint32_t inverse)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        out[i] = map_key(in[i], sign, rest, inverse);
-}
-
-// The same, four keys per 16-byte access (both arrays 16-byte aligned).
-__global__ __launch_bounds__(256) void k_map_keys4(const uint4 *in, uint4 *out, uint64_t n4, uint32_t sign,
-                                                   uint32_t rest, uint32_t inverse)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-        const uint4 x = in[i];
-        out[i] = make_uint4(map_key(x.x, sign, rest, inverse), map_key(x.y, sign, rest, inverse),
-                            map_key(x.z, sign, rest, inverse), map_key(x.w, sign, rest, inverse));
-    }
+    emit_blocked<NT, MAP>(t, lds, src.kdst, gpos, count, src.out_smp, src.out_map, lane);
 }
 
 // Sortedness check of the runs of a merge input: sets *flag when some
@@ -1879,10 +1978,15 @@ bool merge_fuses_partition(bool pairs, const SampleSet &in_smp, const Tuning &tu
 }
 
 hipError_t launch_block_sort_regular(bool pairs, bool shear, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
-                                     uint32_t *vout, uint64_t n, SampleSet out_smp, hipStream_t s)
+                                     uint32_t *vout, uint64_t n, SampleSet out_smp, hipStream_t s, KeyMap in_map,
+                                     KeyMap out_map)
 {
     RegularSortSrc src{kin, pairs ? vin : nullptr, kout, pairs ? vout : nullptr, n,
                        (uint32_t)((n + kTile - 1) / kTile), out_smp};
+    if (in_map.sign || out_map.sign) {  // other key types: merge rounds only
+        const Mapped<RegularSortSrc> ms{src, in_map, out_map};
+        return pairs ? launch_sort<true>(ms, s) : launch_sort<false>(ms, s);
+    }
     return pairs ? launch_sort<true>(src, s, shear) : launch_sort<false>(src, s, shear);
 }
 
@@ -1912,11 +2016,13 @@ static hipError_t launch_group_src(const Src &src, hipStream_t s)
 
 template <int NW, bool P>
 static hipError_t launch_group(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
-                               uint64_t n, SampleSet smp, hipStream_t s)
+                               uint64_t n, SampleSet smp, hipStream_t s, KeyMap in_map, KeyMap out_map)
 {
     constexpr uint32_t keys = NW * kTile;
     RegularGroupSrc src{kin, P ? vin : nullptr, kout, P ? vout : nullptr, n, (uint32_t)((n + keys - 1) / keys), keys,
                         smp};
+    if (in_map.sign || out_map.sign)
+        return launch_group_src<NW, P>(Mapped<RegularGroupSrc>{src, in_map, out_map}, s);
     return launch_group_src<NW, P>(src, s);
 }
 
@@ -1944,18 +2050,40 @@ hipError_t launch_block_sort_shear_group(const uint32_t *kin, uint32_t *kout, ui
 }
 
 hipError_t launch_block_sort_group(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
-                                   uint32_t *vout, uint64_t n, SampleSet out_smp, hipStream_t s)
+                                   uint32_t *vout, uint64_t n, SampleSet out_smp, hipStream_t s, KeyMap in_map,
+                                   KeyMap out_map)
 {
-    return pairs ? launch_group<kGroupWavesPairs, true>(kin, vin, kout, vout, n, out_smp, s)
-                 : launch_group<kGroupWavesKeys, false>(kin, vin, kout, vout, n, out_smp, s);
+    return pairs ? launch_group<kGroupWavesPairs, true>(kin, vin, kout, vout, n, out_smp, s, in_map, out_map)
+                 : launch_group<kGroupWavesKeys, false>(kin, vin, kout, vout, n, out_smp, s, in_map, out_map);
 }
 
 hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t *vsrc, uint32_t *kdst,
                                 uint32_t *vdst, uint64_t n, uint64_t run, uint32_t *splits, SampleSet in_smp,
-                                SampleSet out_smp, bool partition, bool fused, hipStream_t s)
+                                SampleSet out_smp, bool partition, bool fused, hipStream_t s, KeyMap out_map)
 {
     RegularMergeSrc src{ksrc, pairs ? vsrc : nullptr, kdst, pairs ? vdst : nullptr, n, run,
                         (uint32_t)((n + kTile - 1) / kTile), in_smp, out_smp};
+    if (out_map.sign && !(partition && !fused)) {
+        // the pass that writes the output of another key type: one tile per
+        // wave, its split searched by the merge itself (fused) or read from
+        // the partition launch before it
+        if (fused && (run % kTile != 0 || in_smp.f == nullptr))
+            return hipErrorInvalidValue;
+        if (partition)
+            return hipSuccess;
+        const Mapped<RegularMergeSrc> ms{src, KeyMap{}, out_map};
+        const bool nt = tuning().nontemporal && n * (pairs ? 8.0 : 4.0) * 2 > kLastLevelCacheBytes;
+        using M = Mapped<RegularMergeSrc>;
+        if (fused)
+            return pairs ? (nt ? launch_merge_mode<true, M, 2, true, true>(ms, splits, s)
+                               : launch_merge_mode<true, M, 2, false, true>(ms, splits, s))
+                         : (nt ? launch_merge_mode<false, M, 2, true, true>(ms, splits, s)
+                               : launch_merge_mode<false, M, 2, false, true>(ms, splits, s));
+        return pairs ? (nt ? launch_merge_mode<true, M, 2, true>(ms, splits, s)
+                           : launch_merge_mode<true, M, 2, false>(ms, splits, s))
+                     : (nt ? launch_merge_mode<false, M, 2, true>(ms, splits, s)
+                           : launch_merge_mode<false, M, 2, false>(ms, splits, s));
+    }
     if (fused) {
         // one launch per pass: the merge kernel searches its own splits
         if (partition)
@@ -2008,14 +2136,14 @@ uint64_t merge4_cut_bytes_max(uint64_t n)
 }
 
 hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t n, uint64_t run, void *cuts,
-                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s)
+                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s, KeyMap out_map)
 {
     // the cut searches read the samples of the input; runs start at multiples of 4096
     if (n == 0 || run % kTile != 0 || in_smp.f == nullptr || in_smp.l == nullptr || cuts == nullptr)
         return hipErrorInvalidValue;
     const uint64_t groups = (n + 4 * run - 1) / (4 * run);
     Merge4Src src{ksrc, kdst, n, run, (uint32_t)groups, ab_segments(2 * run), cd_cuts(2 * run),
-                  static_cast<uint4 *>(cuts), in_smp, out_smp};
+                  static_cast<uint4 *>(cuts), in_smp, out_smp, out_map};
     if (cut_phase) {
         const uint64_t tasks = groups * (src.jfull - 1 + src.mfull);  // two per wave, four waves per block
         hipLaunchKernelGGL(k_cuts4, dim3((uint32_t)((tasks + 7) / 8)), dim3(256), 0, s, src);
@@ -2024,34 +2152,15 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
     const uint64_t items = groups * (src.jfull + src.mfull);
     const dim3 grid((uint32_t)((items + kMerge4Waves - 1) / kMerge4Waves)), block(kWave * kMerge4Waves);
     // nontemporal tile traffic only when a pass streams more than the last-level cache
-    if (tuning().nontemporal && n * 4.0 * 2 > kLastLevelCacheBytes)
-        hipLaunchKernelGGL(k_merge4<true>, grid, block, 0, s, src);
+    const bool nt = tuning().nontemporal && n * 4.0 * 2 > kLastLevelCacheBytes;
+    if (out_map.sign && nt)
+        hipLaunchKernelGGL((k_merge4<true, true>), grid, block, 0, s, src);
+    else if (out_map.sign)
+        hipLaunchKernelGGL((k_merge4<false, true>), grid, block, 0, s, src);
+    else if (nt)
+        hipLaunchKernelGGL((k_merge4<true, false>), grid, block, 0, s, src);
     else
-        hipLaunchKernelGGL(k_merge4<false>, grid, block, 0, s, src);
-    return hipGetLastError();
-}
-
-hipError_t launch_map_keys(const uint32_t *in, uint32_t *out, uint64_t n, int kind, bool inverse, hipStream_t s)
-{
-    if (n == 0)
-        return hipSuccess;
-    if (kind != 1 && kind != 2)
-        return hipErrorInvalidValue;
-    const uint32_t rest = kind == 2 ? 0x7fffffffu : 0u, inv = inverse ? 1u : 0u;
-    auto grid_for = [](uint64_t items) {
-        const uint64_t want = (items + 255) / 256;
-        return (uint32_t)(want < 8 * 1024 ? want : 8 * 1024);
-    };
-    uint64_t done = 0;
-    if (((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0 && n >= 4) {
-        const uint64_t n4 = n / 4;
-        hipLaunchKernelGGL(k_map_keys4, dim3(grid_for(n4)), dim3(256), 0, s, reinterpret_cast<const uint4 *>(in),
-                           reinterpret_cast<uint4 *>(out), n4, 0x80000000u, rest, inv);
-        done = 4 * n4;
-    }
-    if (done < n)
-        hipLaunchKernelGGL(k_map_keys, dim3(grid_for(n - done)), dim3(256), 0, s, in + done, out + done, n - done,
-                           0x80000000u, rest, inv);
+        hipLaunchKernelGGL((k_merge4<false, false>), grid, block, 0, s, src);
     return hipGetLastError();
 }
 

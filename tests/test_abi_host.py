@@ -187,13 +187,13 @@ def test_colored_prefix_sums_queries_and_errors(lib):
 
 
 def test_u64_sort_queries_and_errors(lib):
-    """Temp = four 256-aligned u32 arrays + the pair sort's temp; errors before any launch."""
+    """Temp = one 256-aligned u64 ping-pong array once there is a merge pass
+    (more than one 4096-key tile); errors before any launch."""
     f = lib.bcf_sort_u64
-    for n in (0, 1, 4097, 2**20 + 3, 2**26, 2**32 - 1):
-        need, pn = ctypes.c_uint64(7), ctypes.c_uint64(0)
+    for n in (0, 1, 4096, 4097, 2**20 + 3, 2**26, 2**32 - 1):
+        need = ctypes.c_uint64(7)
         assert f(None, None, n, None, ctypes.byref(need), None) == 0
-        assert lib.bcf_sort_pairs_u32(None, None, None, None, n, None, ctypes.byref(pn), None) == 0
-        assert need.value == (0 if n == 0 else 4 * (-(-4 * n // 256) * 256) + pn.value), n
+        assert need.value == (0 if n <= 4096 else -(-8 * n // 256) * 256), n
     need = ctypes.c_uint64(0)
     assert f(None, None, 2**32, None, ctypes.byref(need), None) == 1  # too many keys
     fake = ctypes.c_void_p(4096)

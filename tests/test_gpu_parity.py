@@ -700,7 +700,7 @@ def _typed_keys(kind, n, dist, seed):
 
 
 @pytest.mark.parametrize("kind", ["i32", "f32"])
-@pytest.mark.parametrize("n", [1, 4097, 100003, (1 << 20) + 7, (1 << 25) + 5])
+@pytest.mark.parametrize("n", [1, 4096, 4097, 100003, (1 << 20) + 7, 1 << 25, (1 << 25) + 5])
 def test_typed_sorts_vs_oracle(torch_dev, bcf, kind, n):
     torch, dev = torch_dev
     sort = bcf.sort_f32 if kind == "f32" else bcf.sort_i32
@@ -723,6 +723,31 @@ def test_typed_pairs_stable_vs_oracle(torch_dev, bcf, kind, n):
     wk, wv = ref(keys, vals)
     assert first_diff(ko.cpu().numpy().view(np.uint32), wk.view(np.uint32)) is None
     assert first_diff(vo.cpu().numpy(), wv) is None
+
+
+@pytest.mark.parametrize("knobs", [
+    {"block_sort": 1}, {"block_sort": 3, "merge_fan_in": 4}, {"merge_fan_in": 2, "fused_partition": 0},
+    {"merge_fan_in": 2, "merge_variant": 1}, {"block_sort": 2}, {"block_sort": 4, "merge_fan_in": 4}])
+def test_typed_sorts_under_tunings(torch_dev, bcf, knobs):
+    """The key maps are fused into the first and the last pass: every block
+    sort and merge kernel that can be either (wave or group tiles, binary or
+    four-way last pass, fused or separate split search) maps correctly."""
+    torch, dev = torch_dev
+    n = 3 * (1 << 18) + 11
+    for kind in ("i32", "f32"):
+        keys = _typed_keys(kind, n, "bits", seed=5)
+        ref = oracle.sort_f32 if kind == "f32" else oracle.sort_i32
+        sort = bcf.sort_f32 if kind == "f32" else bcf.sort_i32
+        with bcf.tuning(**knobs):
+            got = sort(torch.from_numpy(keys).to(dev)).cpu().numpy()
+        assert first_diff(got.view(np.uint32), ref(keys).view(np.uint32)) is None, (kind, knobs)
+        psort = bcf.sort_pairs_f32 if kind == "f32" else bcf.sort_pairs_i32
+        vals = np.arange(n, dtype=np.uint32)
+        with bcf.tuning(**knobs):
+            ko, vo = psort(torch.from_numpy(keys).to(dev), to_dev(torch, dev, vals))
+        wk, wv = ref(keys, vals)
+        assert first_diff(ko.cpu().numpy().view(np.uint32), wk.view(np.uint32)) is None, (kind, knobs)
+        assert first_diff(vo.cpu().numpy(), wv) is None, (kind, knobs)
 
 
 def test_typed_sort_in_place_and_errors(torch_dev, bcf):
