@@ -218,9 +218,15 @@ def bench_u64(bcf, workloads, torch, dev, n=1 << 26, reps=5):
     keys = workloads.draws_u64_torch(1, n, dev).view(torch.uint64)
     out = torch.empty_like(keys)
     ws = bcf.Workspace(dev)
-    ms = autotune.time_ms(lambda: bcf.sort_u64(keys, out=out, workspace=ws), reps=reps, warmup=1)
+    fn = lambda: bcf.sort_u64(keys, out=out, workspace=ws)  # noqa: E731
+    ms = autotune.time_ms(fn, reps=reps, warmup=1)
+    bcf.profile_collect()
+    bcf.profile_enable(True)
+    fn()
+    bcf.profile_enable(False)
     return {"n": n, "ms": round(ms, 4), "Gkeys_per_s": round(n / ms / 1e6, 3),
-            "method": "two stable 32-bit pair sorts, low halves first, plus split and join passes"}
+            "method": "keys in register pairs: group block sort into runs of 16384, binary merge passes",
+            "kernels": _kernel_table(bcf.profile_collect())}
 
 
 def bench_distribution(bcf, workloads, torch, dev, runs=256, run_len=1 << 18, P=256, t=256, reps=10):
@@ -325,12 +331,56 @@ def bench_segmented(bcf, workloads, torch, dev, count=10000, lo=32, hi=1 << 20, 
                 bcf.sort_u32(keys[a:b], out=out[a:b], workspace=wsa)
 
         ms_per = autotune.time_ms(per_array, reps=1, warmup=1)
+        del plan, graph
+        # the same sort through the device-offset entry point: planned on the
+        # device from offsets in HBM (eager, and one captured graph)
+        ms_dev, ms_dev_graph = _segmented_device_offsets(bcf, torch, dev, keys, out, offs, reps)
     res["per_array_calls"] = {"ms": round(ms_per, 3), "Gkeys_per_s": round(n / ms_per / 1e6, 3)}
     res["batched_eager"] = {"ms": round(ms_eager, 3), "Gkeys_per_s": round(n / ms_eager / 1e6, 3)}
     res["batched_graph"] = {"ms": round(ms_graph, 3), "Gkeys_per_s": round(n / ms_graph / 1e6, 3)}
+    res["device_offsets_eager"] = {"ms": round(ms_dev, 3), "Gkeys_per_s": round(n / ms_dev / 1e6, 3)}
+    res["device_offsets_graph"] = {"ms": round(ms_dev_graph, 3), "Gkeys_per_s": round(n / ms_dev_graph / 1e6, 3)}
     res["speedup_graph_vs_per_array"] = round(ms_per / ms_graph, 2)
-    del keys, out, plan, graph
+    del keys, out
     return res
+
+
+def _segmented_device_offsets(bcf, torch, dev, keys, out, offs, reps):
+    """Device time of bcf_segmented_sort with its offsets in device memory
+    (temp sized once by a query), eager and replayed from one graph."""
+    import ctypes
+
+    from paper_1306_5076_amd import _native, autotune
+
+    lib = _native.load()
+    vp = ctypes.c_void_p
+    nseg = len(offs) - 1
+    doff = torch.from_numpy(offs.astype("int64")).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    need = ctypes.c_uint64(0)
+    _native.check("bcf_segmented_sort", lib.bcf_segmented_sort(None, None, vp(doff.data_ptr()), nseg, None,
+                                                                ctypes.byref(need), vp(stream.cuda_stream)))
+    temp = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    tb = ctypes.c_uint64(temp.numel())
+
+    def run():
+        _native.check("bcf_segmented_sort", lib.bcf_segmented_sort(
+            vp(keys.data_ptr()), vp(out.data_ptr()), vp(doff.data_ptr()), nseg, vp(temp.data_ptr()),
+            ctypes.byref(tb), vp(torch.cuda.current_stream(dev).cuda_stream)))
+
+    ms_eager = autotune.time_ms(run, reps=reps)
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        run()  # warm-up outside capture
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    ms_graph = autotune.time_ms(g.replay, reps=reps)
+    del g, temp, doff
+    return ms_eager, ms_graph
 
 
 def main():

@@ -445,6 +445,112 @@ __device__ __forceinline__ void to_strided_half(Lines<false> &t, uint32_t *lds, 
     swap_quadrants(t.k);
 }
 
+// ------------------------------------------------------ group (multi-wave) sort
+//
+// NW waves of a work-group (NW = 2^LW) sort a group tile of NW * 4096 keys:
+// every wave sorts its 4096-key sub-tile (odd waves descending, by
+// complementing around the wave sort), then LW more bitonic rounds
+// (J = 7 .. 6+LW) merge across waves.  Wave w holds group positions with
+// bits 12.. equal to w.  A third layout brings the wave bits into registers:
+//   CROSS  lane = p bits 0..5, wave = p bits 6..5+LW, register = p bits 6+LW..11+LW
+// Round J: BLOCKED -> CROSS (shared LDS, barriers), stages on bits 5+J..6+LW
+// in registers, CROSS -> STRIDED, stages on bits 5+LW..6, STRIDED -> BLOCKED
+// (the wave's own LDS slice), stages on bits 5..0.  The LDS word of position
+// p is p + 4 (p/64) in all three layouts, so every access keeps the 68-word
+// rows of the single-wave transposes: lane-consecutive 4-byte accesses (CROSS,
+// STRIDED) touch 32 distinct banks per 32-lane half, and BLOCKED accesses are
+// 16-byte, four registers at a time, 8 lanes covering the 32 banks.
+
+// x[r] -> lds[wbase + WS*r]; barrier; x[r] <- lds[rbase + RS*r]; barrier.
+template <int WS, int RS>
+__device__ __forceinline__ void group_exchange(uint32_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
+                                               uint32_t rbase)
+{
+    lds_put<WS>(lds + wbase, x);
+    __syncthreads();
+    lds_get<RS>(x, lds + rbase);
+    __syncthreads();
+}
+
+// The same for 64-bit elements, one 32-bit half at a time.
+template <int WS, int RS>
+__device__ __forceinline__ void group_exchange(double (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
+{
+    uint32_t hi[kLine], lo[kLine];
+    split_halves(x, hi, lo);
+    group_exchange<WS, RS>(hi, lds, wbase, rbase);
+    group_exchange<WS, RS>(lo, lds, wbase, rbase);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = elem_of(((uint64_t)hi[r] << 32) | lo[r]);
+}
+
+// The same for 64-bit keys.
+template <int WS, int RS>
+__device__ __forceinline__ void group_exchange(uint64_t (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
+{
+    uint32_t hi[kLine], lo[kLine];
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        hi[r] = (uint32_t)(x[r] >> 32);
+        lo[r] = (uint32_t)x[r];
+    }
+    group_exchange<WS, RS>(hi, lds, wbase, rbase);
+    group_exchange<WS, RS>(lo, lds, wbase, rbase);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        x[r] = ((uint64_t)hi[r] << 32) | lo[r];
+}
+
+// BLOCKED p = 4096w + 64 lane + r  ->  CROSS p = lane + 64w + 64*NW*r
+template <int NW, class L>
+__device__ __forceinline__ void blocked_to_cross(L &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    const uint32_t wb = kLdsStride * (kWave * wave + lane), rb = kLdsStride * wave + lane;
+    group_exchange<1, kLdsStride * NW>(elems(t), lds, wb, rb);
+}
+
+// CROSS p = lane + 64w + 64*NW*r  ->  STRIDED p = 4096w + 64r + lane
+template <int NW, class L>
+__device__ __forceinline__ void cross_to_strided(L &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    const uint32_t wb = kLdsStride * wave + lane, rb = kLdsStride * kWave * wave + lane;
+    group_exchange<kLdsStride * NW, kLdsStride>(elems(t), lds, wb, rb);
+}
+
+constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
+
+// Round J (7 .. 6+LW) of the group sort; on entry and exit the tile is
+// BLOCKED and every run of 2^(6+J) positions is sorted, descending where bit
+// 6+J is set (the last round sorts ascending).
+template <int NW, int J, class L>
+__device__ __forceinline__ void group_round(L &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    constexpr int LW = log2i(NW);
+    constexpr bool last = J == 6 + LW;
+    blocked_to_cross<NW>(t, lds, lane, wave);
+    // bits 5+J .. 6+LW = CROSS register bits J-1-LW .. 0; direction bit 6+J = register bit J-LW
+    half_clean_lines<(1 << (J - 1 - LW)), (last ? -1 : J - LW)>(t);
+    cross_to_strided<NW>(t, lds, lane, wave);
+    // bits 5+LW .. 6 = STRIDED register bits LW-1 .. 0; direction bit 6+J = wave bit J-6
+    if constexpr (!last)
+        flip(t, wave >> (J - 6));
+    half_clean_lines<(1 << (LW - 1)), -1>(t);
+    to_blocked(t, lds + kLdsWords * wave, lane);
+    half_clean_lines<kLine / 2, -1>(t);
+    if constexpr (!last)
+        flip(t, wave >> (J - 6));
+}
+
+// Rounds J .. 6 + log2(NW) of a group tile (any line type).
+template <int NW, int J, class L>
+__device__ __forceinline__ void group_rounds(L &t, uint32_t *lds, uint32_t lane, uint32_t wave)
+{
+    group_round<NW, J>(t, lds, lane, wave);
+    if constexpr (J < 6 + log2i(NW))
+        group_rounds<NW, J + 1>(t, lds, lane, wave);
+}
+
 // ---------------------------------------------------------------- wave utils
 
 // The value of x, hidden from the optimiser.  Persistent kernels re-derive

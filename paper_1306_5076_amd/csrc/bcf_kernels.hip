@@ -349,94 +349,6 @@ __device__ __forceinline__ void shear_sort_blocked(Lines<P> &t, uint32_t *lds, u
     oe_sort<0, kLine - 1, P>(t);
 }
 
-// ------------------------------------------------------ group (multi-wave) sort
-//
-// NW waves of a work-group (NW = 2^LW) sort a group tile of NW * 4096 keys:
-// every wave sorts its 4096-key sub-tile (odd waves descending, by
-// complementing around the wave sort), then LW more bitonic rounds
-// (J = 7 .. 6+LW) merge across waves.  Wave w holds group positions with
-// bits 12.. equal to w.  A third layout brings the wave bits into registers:
-//   CROSS  lane = p bits 0..5, wave = p bits 6..5+LW, register = p bits 6+LW..11+LW
-// Round J: BLOCKED -> CROSS (shared LDS, barriers), stages on bits 5+J..6+LW
-// in registers, CROSS -> STRIDED, stages on bits 5+LW..6, STRIDED -> BLOCKED
-// (the wave's own LDS slice), stages on bits 5..0.  The LDS word of position
-// p is p + 4 (p/64) in all three layouts, so every access keeps the 68-word
-// rows of the single-wave transposes: lane-consecutive 4-byte accesses (CROSS,
-// STRIDED) touch 32 distinct banks per 32-lane half, and BLOCKED accesses are
-// 16-byte, four registers at a time, 8 lanes covering the 32 banks.
-
-// x[r] -> lds[wbase + WS*r]; barrier; x[r] <- lds[rbase + RS*r]; barrier.
-template <int WS, int RS>
-__device__ __forceinline__ void group_exchange(uint32_t (&x)[kLine], uint32_t *lds, uint32_t wbase,
-                                               uint32_t rbase)
-{
-    lds_put<WS>(lds + wbase, x);
-    __syncthreads();
-    lds_get<RS>(x, lds + rbase);
-    __syncthreads();
-}
-
-// The same for 64-bit elements, one 32-bit half at a time.
-template <int WS, int RS>
-__device__ __forceinline__ void group_exchange(double (&x)[kLine], uint32_t *lds, uint32_t wbase, uint32_t rbase)
-{
-    uint32_t hi[kLine], lo[kLine];
-    split_halves(x, hi, lo);
-    group_exchange<WS, RS>(hi, lds, wbase, rbase);
-    group_exchange<WS, RS>(lo, lds, wbase, rbase);
-#pragma unroll
-    for (int r = 0; r < kLine; ++r)
-        x[r] = elem_of(((uint64_t)hi[r] << 32) | lo[r]);
-}
-
-// BLOCKED p = 4096w + 64 lane + r  ->  CROSS p = lane + 64w + 64*NW*r
-template <int NW, bool P>
-__device__ __forceinline__ void blocked_to_cross(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
-{
-    const uint32_t wb = kLdsStride * (kWave * wave + lane), rb = kLdsStride * wave + lane;
-    group_exchange<1, kLdsStride * NW>(elems(t), lds, wb, rb);
-}
-
-// CROSS p = lane + 64w + 64*NW*r  ->  STRIDED p = 4096w + 64r + lane
-template <int NW, bool P>
-__device__ __forceinline__ void cross_to_strided(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
-{
-    const uint32_t wb = kLdsStride * wave + lane, rb = kLdsStride * kWave * wave + lane;
-    group_exchange<kLdsStride * NW, kLdsStride>(elems(t), lds, wb, rb);
-}
-
-constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
-
-// Round J (7 .. 6+LW) of the group sort; on entry and exit the tile is
-// BLOCKED and every run of 2^(6+J) positions is sorted, descending where bit
-// 6+J is set (the last round sorts ascending).
-template <int NW, int J, bool P>
-__device__ __forceinline__ void group_round(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
-{
-    constexpr int LW = log2i(NW);
-    constexpr bool last = J == 6 + LW;
-    blocked_to_cross<NW>(t, lds, lane, wave);
-    // bits 5+J .. 6+LW = CROSS register bits J-1-LW .. 0; direction bit 6+J = register bit J-LW
-    half_clean<(1 << (J - 1 - LW)), (last ? -1 : J - LW), P>(t);
-    cross_to_strided<NW>(t, lds, lane, wave);
-    // bits 5+LW .. 6 = STRIDED register bits LW-1 .. 0; direction bit 6+J = wave bit J-6
-    if constexpr (!last)
-        flip(t, wave >> (J - 6));
-    half_clean<(1 << (LW - 1)), -1, P>(t);
-    to_blocked(t, lds + kLdsWords * wave, lane);
-    half_clean<kLine / 2, -1, P>(t);
-    if constexpr (!last)
-        flip(t, wave >> (J - 6));
-}
-
-template <int NW, int J, bool P>
-__device__ __forceinline__ void group_rounds(Lines<P> &t, uint32_t *lds, uint32_t lane, uint32_t wave)
-{
-    group_round<NW, J, P>(t, lds, lane, wave);
-    if constexpr (J < 6 + log2i(NW))
-        group_rounds<NW, J + 1, P>(t, lds, lane, wave);
-}
-
 // --------------------------------------------------------------- merge body
 
 // The inputs of one merge work item: the A-piece [0, pa) and B-piece [0, pb)
@@ -895,7 +807,7 @@ __device__ __forceinline__ void group_tile(Lines<P> &t, const SortItem &it, cons
     flip(t, wave);  // odd sub-tiles descending
     sort_tile_blocked<P>(t, own, lane);
     flip(t, wave);
-    group_rounds<NW, 7, P>(t, lds, lane, wave);
+    group_rounds<NW, 7>(t, lds, lane, wave);
     write_samples<P>(t, src.out_smp, src.pos(g, wave), it.count, lane);
     to_strided(t, own, lane);
     if constexpr (P) {

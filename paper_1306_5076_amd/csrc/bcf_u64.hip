@@ -9,7 +9,10 @@
 //   4096 keys.  Every compare-exchange is between two registers of one lane;
 //   the switches between the STRIDED and BLOCKED layouts go through LDS as
 //   two 32-bit halves, each with the conflict-free 68-word rows of the 32-bit
-//   tiles.
+//   tiles.  Above 2^19 keys four waves of a work-group then merge their
+//   sorted sub-tiles in two more rounds through the shared CROSS layout (the
+//   group tiles of the 32-bit sort), for runs of 16384 keys: two merge passes
+//   fewer.
 // * Merge passes (Sec. 3.2, binary merging): every wave produces one
 //   4096-key output tile of one merge of two runs.  Its two half-waves find
 //   the co-ranks of the tile's first and last output (the merge-path split,
@@ -27,6 +30,11 @@
 #include "bcf_device.hpp"
 
 namespace bcf {
+
+// Host services of bcf_api.hip: a profiling scope around one launch.
+void *prof_begin(const char *name, hipStream_t s, double bytes);
+void prof_end(void *scope);
+
 namespace {
 
 constexpr uint64_t kMaxN64 = 0xFFFFFFFFull;
@@ -96,6 +104,24 @@ __device__ __forceinline__ void merge_round64(Lines64 &t, uint32_t *lds, uint32_
         flip(t, lane >> J);
 }
 
+// Sort a wave tile: on entry as loaded (read as BLOCKED: lane l's line), on
+// exit sorted in BLOCKED layout.
+__device__ __forceinline__ void sort_tile_blocked64(Lines64 &t, uint32_t *lds, uint32_t lane)
+{
+    flip(t, lane);  // lines: even lanes ascending, odd lanes descending
+    oe_sort_lines<0, kLine - 1>(t);
+    flip(t, lane);
+    merge_round64<1>(t, lds, lane);
+    merge_round64<2>(t, lds, lane);
+    merge_round64<3>(t, lds, lane);
+    merge_round64<4>(t, lds, lane);
+    merge_round64<5>(t, lds, lane);
+    merge_round64<6>(t, lds, lane);
+}
+
+constexpr int kGroupWaves64 = 4;  // group tiles of 16384 keys
+constexpr uint64_t kGroupMinN64 = 1ull << 19;
+
 // One 4096-key tile per wave, one wave per work-group.
 template <bool NT>
 __global__ __launch_bounds__(kWave) void k_u64_block_sort(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
@@ -109,17 +135,35 @@ __global__ __launch_bounds__(kWave) void k_u64_block_sort(const uint64_t *__rest
     const uint32_t count = n - start < (uint64_t)kTile ? (uint32_t)(n - start) : (uint32_t)kTile;
     Lines64 t;
     load_tile64(t, in + start, count, lane);
-    // the tile as loaded, read as BLOCKED: lane l's line; even lanes ascending
-    flip(t, lane);
-    oe_sort_lines<0, kLine - 1>(t);
-    flip(t, lane);
-    merge_round64<1>(t, lds, lane);
-    merge_round64<2>(t, lds, lane);
-    merge_round64<3>(t, lds, lane);
-    merge_round64<4>(t, lds, lane);
-    merge_round64<5>(t, lds, lane);
-    merge_round64<6>(t, lds, lane);
+    sort_tile_blocked64(t, lds, lane);
     to_strided(t, lds, lane);
+    store_tile64<NT>(t, out + start, count, lane);
+}
+
+// One group tile of kGroupWaves64 sub-tiles per work-group: each wave sorts
+// its sub-tile (odd waves descending, by complementing around the sort), then
+// the group rounds merge across the waves.  Every wave of a work-group reaches
+// the same barriers: waves whose sub-tile lies past the end hold padding only.
+template <bool NT>
+__global__ __launch_bounds__(kWave *kGroupWaves64) void k_u64_block_sort_group(const uint64_t *__restrict__ in,
+                                                                             uint64_t *__restrict__ out, uint64_t n)
+{
+    __shared__ __align__(16) uint32_t lds[kGroupWaves64 * kLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint64_t gstart = (uint64_t)blockIdx.x * (kGroupWaves64 * kTile);
+    if (gstart >= n)
+        return;
+    const uint64_t start = gstart + (uint64_t)wave * kTile;
+    const uint32_t count = start >= n ? 0u : (n - start < (uint64_t)kTile ? (uint32_t)(n - start) : (uint32_t)kTile);
+    Lines64 t;
+    load_tile64(t, in + start, count, lane);  // count 0: padding only, nothing loaded
+    uint32_t *own = lds + kLdsWords * wave;
+    flip(t, wave);
+    sort_tile_blocked64(t, own, lane);
+    flip(t, wave);
+    group_rounds<kGroupWaves64, 7>(t, lds, lane, wave);
+    to_strided(t, own, lane);
     store_tile64<NT>(t, out + start, count, lane);
 }
 
@@ -180,10 +224,14 @@ __global__ __launch_bounds__(kWave) void k_u64_merge(const uint64_t *__restrict_
 
 uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
 
+// Run length after the block sort, and the binary merge passes after it.
+uint64_t run0_for(uint64_t n) { return n > kGroupMinN64 ? (uint64_t)kGroupWaves64 * kTile : (uint64_t)kTile; }
+
 uint32_t passes_for(uint64_t n)
 {
     uint32_t p = 0;
-    for (uint64_t runs = (n + kTile - 1) / kTile; runs > 1; runs = (runs + 1) / 2)
+    const uint64_t run0 = run0_for(n);
+    for (uint64_t runs = (n + run0 - 1) / run0; runs > 1; runs = (runs + 1) / 2)
         ++p;
     return p;
 }
@@ -217,18 +265,31 @@ extern "C" bcf_status bcf_sort_u64(const uint64_t *keys_in, uint64_t *keys_out, 
     const uint32_t tiles = (uint32_t)((n + kTile - 1) / kTile);
     // MI355X's last-level cache holds 256 MiB; a pass reads and writes 16 B per key
     const bool nt = 16.0 * n > 256.0 * 1024 * 1024;
-    if (nt)
+    const uint64_t run0 = run0_for(n);
+    void *scope = prof_begin("block_sort_u64", s, 16.0 * n);
+    if (run0 > (uint64_t)kTile) {
+        const uint32_t groups = (uint32_t)((n + run0 - 1) / run0);
+        const dim3 block(kWave * kGroupWaves64);
+        if (nt)
+            hipLaunchKernelGGL(k_u64_block_sort_group<true>, dim3(groups), block, 0, s, keys_in, buf(0), n);
+        else
+            hipLaunchKernelGGL(k_u64_block_sort_group<false>, dim3(groups), block, 0, s, keys_in, buf(0), n);
+    } else if (nt) {
         hipLaunchKernelGGL(k_u64_block_sort<true>, dim3(tiles), dim3(kWave), 0, s, keys_in, buf(0), n);
-    else
+    } else {
         hipLaunchKernelGGL(k_u64_block_sort<false>, dim3(tiles), dim3(kWave), 0, s, keys_in, buf(0), n);
+    }
+    prof_end(scope);
     if (hipGetLastError() != hipSuccess)
         return BCF_ERR_DEVICE;
-    uint64_t run = kTile;
+    uint64_t run = run0;
     for (uint32_t j = 1; j <= passes; ++j, run *= 2) {
+        scope = prof_begin("merge_u64", s, 16.0 * n);
         if (nt)
             hipLaunchKernelGGL(k_u64_merge<true>, dim3(tiles), dim3(kWave), 0, s, buf(j - 1), buf(j), n, run);
         else
             hipLaunchKernelGGL(k_u64_merge<false>, dim3(tiles), dim3(kWave), 0, s, buf(j - 1), buf(j), n, run);
+        prof_end(scope);
         if (hipGetLastError() != hipSuccess)
             return BCF_ERR_DEVICE;
     }

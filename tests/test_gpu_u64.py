@@ -1,6 +1,8 @@
 """GPU parity of the unsigned 64-bit key sort against the CPU oracle: bit-exact
 on every u64 distribution (ties in either half, one key, extreme values) at
-edge sizes, a 2^24 and the 2^26 benchmark size, in place, and argument errors."""
+edge sizes (one tile, wave tiles up to 2^19 keys, group tiles of 16384 above,
+partial last groups), a 2^24 and the 2^26 benchmark size, in place, and
+argument errors."""
 
 import numpy as np
 import pytest
@@ -34,7 +36,8 @@ def first_diff(got, want):
 
 
 @pytest.mark.parametrize("dist", workloads.U64_DISTRIBUTIONS)
-@pytest.mark.parametrize("n", [1, 2, 3, 4095, 4096, 4097, 16385, 100_003, (1 << 20) + 7])
+@pytest.mark.parametrize("n", [1, 2, 3, 4095, 4096, 4097, 16385, 100_003, 1 << 19, (1 << 19) + 1,
+                               (1 << 19) + 3 * 4096 + 5, (1 << 20) + 7])
 def test_sort_u64_vs_oracle(torch_dev, bcf, n, dist):
     torch, dev = torch_dev
     keys = workloads.keys_u64(dist, n, seed=n % 101)
