@@ -365,11 +365,15 @@ typedef struct {
                                   run by the one-tile-per-wave kernel finds each tile's split
                                   itself from the samples (one launch per pass); 0: a separate
                                   partition launch first */
-    int32_t merge_fan_in;      /* runs merged per group by a merge pass of bcf_sort_u32: 0
-                                  (default) 4 for sorts of at least 2^25 keys, else 2; 4 or 2
-                                  for every size.  Four-way passes need sampled_partition
-                                  (else 2 is used).  Key/value sorts, bcf_merge_runs and
-                                  segmented sorts always merge pairs of runs */
+    int32_t merge_fan_in;      /* runs merged per group by a merge pass of bcf_sort_u32 and of
+                                  the host-planned keys-only segmented sorts
+                                  (bcf_segmented_sort_host, bcf_segmented_upload / execute):
+                                  0 (default) 4 for at least 2^25 keys in total, else 2; 4 or
+                                  2 for every size.  A segment takes four-way steps while more
+                                  than two of its runs remain, then a binary one.  Four-way
+                                  passes of bcf_sort_u32 need sampled_partition (else 2 is
+                                  used).  Key/value sorts, bcf_merge_runs and the
+                                  device-planned segmented sorts merge pairs of runs */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);

@@ -13,9 +13,10 @@ ones the kernels expose at run time:
 * group_min_keys    -- (segmented sorts) the same block-size choice per
                        segment: the segment length from which a segment is
                        block-sorted in group tiles instead of wave tiles;
-* merge_fan_in      -- (sorts) runs merged per pass: 2 (binary passes), 4
-                       (four-way passes, two merge levels per read and write of
-                       the data), or 0 for the size-based default;
+* merge_fan_in      -- (sorts and keys-only segmented sorts) runs merged per
+                       pass: 2 (binary passes), 4 (four-way passes, two merge
+                       levels per read and write of the data), or 0 for the
+                       size-based default;
 * merge_variant     -- persistent waves with / without next-tile prefetch, one
                        tile per wave, or the per-kind default;
 * nontemporal       -- nontemporal hints on the merge passes' tile traffic;
@@ -43,7 +44,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bcf_sort", "aut
 
 SORT_SPACE = {"block_sort": [3, 1], "merge_fan_in": [0, 4, 2], "merge_variant": [3, 1, 2, 0], "nontemporal": [1, 0],
               "fused_partition": [1, 0]}
-SEGMENTED_SPACE = {"merge_variant": [3, 1, 2], "nontemporal": [1, 0],
+SEGMENTED_SPACE = {"merge_fan_in": [4, 2], "merge_variant": [3, 1, 2], "nontemporal": [1, 0],
                    "group_min_keys": [4097, 16384, 65536, 1 << 40]}
 
 

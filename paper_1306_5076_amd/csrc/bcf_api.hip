@@ -358,7 +358,44 @@ bcf_status sort_typed(int kind, bool pairs, const uint32_t *kin, const uint32_t 
 struct MergePass {
     std::vector<MergeJob> jobs;
     std::vector<uint32_t> tile_job;
+    // fan-in 4 merges (keys only): jobs, their cut searches and item slots
+    // mapped to jobs, and the initial cut records (each job's first and last
+    // AB cut; the searches write the others)
+    std::vector<Merge4Job> jobs4;
+    std::vector<uint32_t> task_job, item_job;
+    std::vector<uint32_t> cuts4;  // four u32 per record
+    uint64_t keys4 = 0;           // keys the fan-in 4 jobs merge
 };
+
+// Add one fan-in 4 job: runs of n[0..3] keys back to back from `start`.
+void add_job4(MergePass &mp, uint64_t start, const uint64_t (&n)[4], uint32_t src, uint32_t dst)
+{
+    const uint64_t tot = n[0] + n[1] + n[2] + n[3];
+    if (tot == 0)
+        return;
+    Merge4Job j;
+    j.start = start;
+    for (int r = 0; r < 4; ++r)
+        j.n[r] = (uint32_t)n[r];
+    const uint32_t J = merge4_ab_segments(n[0] + n[1]), M = merge4_cd_cuts(n[2] + n[3]);
+    j.cut_off = (uint32_t)(mp.cuts4.size() / 4);
+    j.item_off = (uint32_t)mp.item_job.size();
+    j.task_off = (uint32_t)mp.task_job.size();
+    j.src = (uint16_t)src;
+    j.dst = (uint16_t)dst;
+    const uint32_t id = (uint32_t)mp.jobs4.size();
+    mp.jobs4.push_back(j);
+    for (uint32_t t = 0; t + 1 < J + M; ++t)  // AB cuts 1..J-1, CD cuts 1..M
+        mp.task_job.push_back(id);
+    for (uint32_t i = 0; i < J + M; ++i)
+        mp.item_job.push_back(id);
+    // records P[0..J], Q[0..M]: P[0] = nothing taken, P[J] = everything
+    mp.cuts4.resize(mp.cuts4.size() + 4 * (size_t)(J + M + 2), 0u);
+    uint32_t *last = mp.cuts4.data() + 4 * ((size_t)j.cut_off + J);
+    for (int r = 0; r < 4; ++r)
+        last[r] = j.n[r];
+    mp.keys4 += tot;
+}
 
 // Add one binary merge job A=[a, a+na), B=[a+na, a+na+nb) to a pass.
 void add_job(MergePass &mp, uint64_t a, uint64_t na, uint64_t nb, uint32_t src, uint32_t dst)
@@ -384,6 +421,7 @@ struct TableLayout {
     uint64_t block_off = 0, block_bytes = 0;    // single-wave tiles
     uint64_t group_off = 0, group_bytes = 0;    // multi-wave group tiles
     std::vector<uint64_t> jobs_off, map_off;
+    std::vector<uint64_t> jobs4_off, task_off, item_off, cuts4_off;  // fan-in 4 tables of each pass
     uint64_t splits_off = 0;  // one u32 per tile of the largest pass (reused by every pass)
     uint64_t total = 0;
 };
@@ -405,6 +443,14 @@ TableLayout layout_tables(uint64_t base, size_t nblock, size_t ngroup, const std
         L.map_off.push_back(o);
         o = align256(o + mp.tile_job.size() * sizeof(uint32_t));
         max_tiles = std::max(max_tiles, mp.tile_job.size());
+        L.jobs4_off.push_back(o);
+        o = align256(o + mp.jobs4.size() * sizeof(Merge4Job));
+        L.task_off.push_back(o);
+        o = align256(o + mp.task_job.size() * sizeof(uint32_t));
+        L.item_off.push_back(o);
+        o = align256(o + mp.item_job.size() * sizeof(uint32_t));
+        L.cuts4_off.push_back(o);
+        o = align256(o + mp.cuts4.size() * sizeof(uint32_t));
     }
     L.splits_off = o;
     o = align256(o + max_tiles * sizeof(uint32_t));
@@ -440,6 +486,15 @@ bcf_status upload_tables(char *temp, const TablePlan &P, hipStream_t s)
         if (!P.passes[p].tile_job.empty())
             std::memcpy(img.data() + (L.map_off[p] - lo), P.passes[p].tile_job.data(),
                         P.passes[p].tile_job.size() * sizeof(uint32_t));
+        const MergePass &mp = P.passes[p];
+        if (!mp.jobs4.empty()) {
+            std::memcpy(img.data() + (L.jobs4_off[p] - lo), mp.jobs4.data(), mp.jobs4.size() * sizeof(Merge4Job));
+            if (!mp.task_job.empty())
+                std::memcpy(img.data() + (L.task_off[p] - lo), mp.task_job.data(),
+                            mp.task_job.size() * sizeof(uint32_t));
+            std::memcpy(img.data() + (L.item_off[p] - lo), mp.item_job.data(), mp.item_job.size() * sizeof(uint32_t));
+            std::memcpy(img.data() + (L.cuts4_off[p] - lo), mp.cuts4.data(), mp.cuts4.size() * sizeof(uint32_t));
+        }
     }
     return upload(temp + lo, img.data(), bytes, s);
 }
@@ -468,6 +523,18 @@ bcf_status launch_tables(Bufs kb, Bufs vb, char *temp, const TablePlan &P, hipSt
     }
     for (size_t p = 0; p < P.passes.size(); ++p) {
         const auto &mp = P.passes[p];
+        if (!mp.jobs4.empty()) {
+            // the fan-in 4 merges of this pass (other segments than its binary jobs)
+            for (int phase = 0; phase < 2; ++phase) {
+                const bool cut = phase == 0;
+                ProfScope ps(cut ? "cuts4_keys_table" : "merge4_keys_table", s, cut ? 0.0 : 8.0 * mp.keys4);
+                BCF_TRY(dev_status(launch_merge4_table(
+                    kb, reinterpret_cast<const Merge4Job *>(temp + L.jobs4_off[p]),
+                    reinterpret_cast<const uint32_t *>(temp + L.task_off[p]), (uint32_t)mp.task_job.size(),
+                    reinterpret_cast<const uint32_t *>(temp + L.item_off[p]), (uint32_t)mp.item_job.size(),
+                    temp + L.cuts4_off[p], mp.keys4, cut, s)));
+            }
+        }
         if (mp.tile_job.empty())
             continue;
         double moved = 0;
@@ -500,6 +567,7 @@ uint64_t group_min_keys(bool pairs, uint64_t knob)
 struct UploadedPlan {
     uint64_t fingerprint;
     uint64_t group_min_keys;
+    int merge_fan_in;
 };
 std::mutex g_plans_mu;
 std::map<const void *, UploadedPlan> g_plans;
@@ -523,14 +591,38 @@ uint64_t plan_fingerprint(const uint64_t *off, uint32_t nseg, bool pairs)
 // never cross its boundaries, then merged pairwise until one run remains.
 // X_j(s), the buffer holding segment s after its pass j, alternates so that
 // its last pass lands in the output.
-bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, uint64_t gmin_knob, TablePlan &P)
+// Merge steps of a segment of `runs` sorted runs: fan-in 4 while more than
+// two runs remain (when `four`), then binary steps until one run is left.
+std::vector<uint8_t> seg_fan_ins(uint64_t runs, bool four)
+{
+    std::vector<uint8_t> fi;
+    while (runs > 1) {
+        const uint8_t k = (four && runs > 2) ? 4 : 2;
+        fi.push_back(k);
+        runs = (runs + k - 1) / k;
+    }
+    return fi;
+}
+
+// Whether the merges of a keys-only segmented sort of n keys use fan-in 4
+// steps under the tuning knob merge_fan_in (0: from 2^25 keys, where a pass
+// streams more than the last-level cache holds).
+bool seg_four_way(bool pairs, uint64_t n, int fan_in_knob)
+{
+    return !pairs && (fan_in_knob == 4 || (fan_in_knob == 0 && n >= kAutoFourWayMinN));
+}
+
+bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, uint64_t gmin_knob, int fan_in_knob,
+                          TablePlan &P)
 {
     P.pairs = pairs;
     const uint64_t n = off[nseg];
     const uint64_t gmin = group_min_keys(pairs, gmin_knob);
     const uint64_t grun = group_run_keys(pairs);
+    const bool four = seg_four_way(pairs, n, fan_in_knob);
     std::vector<uint32_t> ps(nseg, 0);
     std::vector<uint64_t> run0(nseg, kTile);
+    std::vector<std::vector<uint8_t>> fan(nseg);
     uint32_t pmax = 0;
     for (uint32_t sg = 0; sg < nseg; ++sg) {
         const uint64_t len = off[sg + 1] - off[sg];
@@ -538,7 +630,8 @@ bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, uint64
             continue;
         if (len > (uint64_t)kTile && len >= gmin)
             run0[sg] = grun;
-        ps[sg] = ceil_log2((len + run0[sg] - 1) / run0[sg]);
+        fan[sg] = seg_fan_ins((len + run0[sg] - 1) / run0[sg], four);
+        ps[sg] = (uint32_t)fan[sg].size();
         pmax = std::max(pmax, ps[sg]);
     }
     auto bufsel = [&](uint32_t sg, uint32_t j) -> uint32_t { return ((ps[sg] - j) % 2 == 0) ? kBufOut : kBufTemp; };
@@ -555,17 +648,31 @@ bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, uint64
         }
     }
     P.passes.assign(pmax, MergePass{});
+    std::vector<uint64_t> run(run0);  // run length of each segment before its next step
     for (uint32_t j = 1; j <= pmax; ++j) {
         for (uint32_t sg = 0; sg < nseg; ++sg) {
             if (ps[sg] < j)
                 continue;
-            const uint64_t run = run0[sg] << (j - 1);
+            const uint64_t L = run[sg];
             const uint64_t a = off[sg], len = off[sg + 1] - a;
-            for (uint64_t o = 0; o < len; o += 2 * run) {
-                const uint64_t na = std::min(run, len - o);
-                const uint64_t nb = std::min(run, len - o - na);
-                add_job(P.passes[j - 1], a + o, na, nb, bufsel(sg, j - 1), bufsel(sg, j));
+            const uint32_t k = fan[sg][j - 1];
+            if (k == 4) {
+                for (uint64_t o = 0; o < len; o += 4 * L) {
+                    uint64_t nr[4];
+                    for (int r = 0; r < 4; ++r) {
+                        const uint64_t s0 = o + r * L;
+                        nr[r] = s0 < len ? std::min(L, len - s0) : 0;
+                    }
+                    add_job4(P.passes[j - 1], a + o, nr, bufsel(sg, j - 1), bufsel(sg, j));
+                }
+            } else {
+                for (uint64_t o = 0; o < len; o += 2 * L) {
+                    const uint64_t na = std::min(L, len - o);
+                    const uint64_t nb = std::min(L, len - o - na);
+                    add_job(P.passes[j - 1], a + o, na, nb, bufsel(sg, j - 1), bufsel(sg, j));
+                }
             }
+            run[sg] = L * k;
         }
     }
     const uint64_t data = pmax ? align256(n * 4) * (pairs ? 2 : 1) : 0;
@@ -588,7 +695,9 @@ bcf_status segmented_impl(SegMode mode, bool pairs, const uint32_t *kin, const u
     }
     if (!offsets_valid(off, nseg))
         return BCF_ERR_INVALID;
-    uint64_t gmin = tuning().group_min_keys;
+    const Tuning tu = tuning();
+    uint64_t gmin = tu.group_min_keys;
+    int fan_in = tu.merge_fan_in;
     if (mode == kSegExecute && temp && off[nseg] != 0) {
         // the tuning of the upload into this temp buffer, for the same offsets
         std::lock_guard<std::mutex> g(g_plans_mu);
@@ -596,9 +705,10 @@ bcf_status segmented_impl(SegMode mode, bool pairs, const uint32_t *kin, const u
         if (it == g_plans.end() || it->second.fingerprint != plan_fingerprint(off, nseg, pairs))
             return BCF_ERR_INVALID;
         gmin = it->second.group_min_keys;
+        fan_in = it->second.merge_fan_in;
     }
     TablePlan P;
-    BCF_TRY(plan_segmented(off, nseg, pairs, gmin, P));
+    BCF_TRY(plan_segmented(off, nseg, pairs, gmin, fan_in, P));
     const uint64_t n = off[nseg];
     if (!temp) {
         *temp_bytes = P.L.total;
@@ -613,7 +723,7 @@ bcf_status segmented_impl(SegMode mode, bool pairs, const uint32_t *kin, const u
         BCF_TRY(upload_tables(tb, P, s));
     if (mode == kSegUpload) {
         std::lock_guard<std::mutex> g(g_plans_mu);
-        g_plans[temp] = UploadedPlan{plan_fingerprint(off, nseg, pairs), gmin};
+        g_plans[temp] = UploadedPlan{plan_fingerprint(off, nseg, pairs), gmin, fan_in};
         return BCF_OK;
     }
     if (!kin || !kout || (pairs && (!vin || !vout)))

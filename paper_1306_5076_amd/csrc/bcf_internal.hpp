@@ -57,6 +57,19 @@ struct MergeJob {
     uint16_t dst;
 };
 
+// One fan-in 4 merge of a table-driven pass (keys only): runs A, B, C, D of
+// n[0..3] keys lying back to back from `start` in buffer `src`, merged into
+// the same range of buffer `dst`.  Its cut records (AB cuts P[0..J], then CD
+// cuts Q[0..M]) start at record cut_off of the pass's cut array, its merge
+// items at slot item_off and its cut searches at task task_off of the pass
+// (J = AB segments, M = interior CD cuts of the job, see the four-way merge).
+struct Merge4Job {
+    uint64_t start;
+    uint32_t n[4];
+    uint32_t cut_off, item_off, task_off;
+    uint16_t src, dst;
+};
+
 // Waves per work-group of the group block sort (keys / pairs); the sorted
 // runs it produces hold that many 4096-key tiles.
 constexpr int kGroupWavesKeys = 8;
@@ -116,6 +129,18 @@ hipError_t launch_block_sort_group_table(bool pairs, Bufs kb, Bufs vb, const Blo
 hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs,
                               const uint32_t *tile_job, uint32_t ntiles, uint32_t *splits,
                               bool partition, hipStream_t s, const uint32_t *count_dev = nullptr);
+// Fan-in 4 table pass (keys): AB / CD segment and cut counts of a job (the
+// planner sizes its records and items by them), and the two launches of a
+// pass over `njobs` jobs: the cut searches (`tasks` of them, task_job maps
+// each to its job), then the merges (`items` slots, item_job maps each to
+// its job).  `cuts` holds the pass's cut records, the first and last AB cut
+// of every job already written by the planner; `keys` is the number of keys
+// the pass merges (it decides the nontemporal hints).
+uint32_t merge4_ab_segments(uint64_t nab);
+uint32_t merge4_cd_cuts(uint64_t ncd);
+hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, const uint32_t *task_job, uint32_t tasks,
+                               const uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, bool cut_phase,
+                               hipStream_t s);
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);
 

@@ -1333,6 +1333,7 @@ struct Group4 {
     uint64_t start;  // array position of A[0]
     uint32_t n[4];   // lengths of A, B, C, D (runs past the end are empty)
     uint32_t J, M;   // AB segments, interior CD cuts
+    __device__ Group4() {}
     __device__ Group4(uint64_t nkeys, uint64_t L, uint32_t g)
     {
         start = (uint64_t)g * 4 * L;
@@ -1585,7 +1586,7 @@ __device__ __forceinline__ void copy4(const uint32_t *x, uint32_t *kdst, uint64_
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
         const uint32_t i = kWave * k + lane;
-        v[k] = ld<NT>(x + (i < count ? i : count - 1));  // clamped: always inside the piece
+        v[k] = ld<false>(x + (i < count ? i : count - 1));  // clamped: always inside the piece
     }
     if constexpr (MAP) {
 #pragma unroll
@@ -1676,6 +1677,100 @@ __device__ __forceinline__ void packed_network(Lines<false> &t, uint32_t *lds, u
 
 constexpr int kMerge4Waves = 1;  // one wave per work-group (see kMergeTileWaves)
 
+// The cuts that bound item slot i of a group (AB items in slots
+// 0 .. abslots - 1, then CD items), read as scalars: false when the slot holds
+// no item.  P: the AB cuts P[0..J], Q: the CD cuts Q[0..M] (Q[0] unused).
+__device__ __forceinline__ bool item_cuts(const uint4 *P, const uint4 *Q, const Group4 &G, uint32_t i,
+                                          uint32_t abslots, uint4 &c0, uint4 &c1)
+{
+    // a cut is the same in every lane: scalar values, so that every branch
+    // below is a scalar one
+    auto cut = [](const uint4 *p) {
+        const uint4 c = *p;
+        return make_uint4(__builtin_amdgcn_readfirstlane(c.x), __builtin_amdgcn_readfirstlane(c.y),
+                          __builtin_amdgcn_readfirstlane(c.z), __builtin_amdgcn_readfirstlane(c.w));
+    };
+    if (i < abslots) {
+        if (i >= G.J)
+            return false;
+        c0 = cut(P + i);
+        const uint4 pe = cut(P + i + 1);
+        const uint32_t y0 = c0.z + c0.w, y1 = pe.z + pe.w;
+        if (y1 < y0)
+            return false;
+        c1 = y1 - y0 > kCdStep ? cut(Q + y0 / kCdStep + 1) : pe;
+    } else {
+        const uint32_t m = i - abslots + 1;
+        if (m > G.M)
+            return false;
+        c0 = cut(Q + m);
+        const uint4 qn = cut(Q + (m < G.M ? m + 1 : m));
+        const uint32_t xq = c0.x + c0.y, gm = kCdStep * m;
+        // the segment holding Q[m]: jc, or jc - 1 when P[jc] sits at Q[m]'s AB
+        // position but after it (more CD taken)
+        const uint32_t jc = min(G.J - 1, xq / kAbStep);
+        const uint4 pm = cut(P + (jc > 0 ? jc - 1 : 0)), pc = cut(P + jc), pn = cut(P + jc + 1);
+        const bool before = jc > 0 && pc.x + pc.y == xq && pc.z + pc.w > gm;
+        const uint4 p0 = before ? pm : pc, p1 = before ? pc : pn;
+        const uint32_t y0 = p0.z + p0.w, y1 = p1.z + p1.w;
+        if (!(y1 > y0 + kCdStep && y0 < gm && gm < y1))
+            return false;  // not inside a long segment: the AB item covers it
+        c1 = (m < G.M && kCdStep * (m + 1) < y1) ? qn : p1;
+    }
+    // every piece inside its run, each side within its half tile (holds for
+    // cuts written by the cut search; checked so that no cut can move a load
+    // or a store outside the group)
+    if (c0.x > c1.x || c0.y > c1.y || c0.z > c1.z || c0.w > c1.w || c1.x > G.n[0] || c1.y > G.n[1] ||
+        c1.z > G.n[2] || c1.w > G.n[3])
+        return false;
+    return true;
+}
+
+// Merge one item: the keys between cuts c0 and c1 of group G, whose runs B,
+// C and D start ob, oc and od keys after A[0] = K[0]; written to kdst at the
+// group's output position.  NT marks the stores nontemporal, never the
+// loads (measured at 2^26 keys over the five distributions: 116.8 us per
+// launch with nontemporal stores only, 119.9 with both, 125.1 with loads only).
+template <bool NT, bool MAP>
+__device__ __forceinline__ void merge4_item(const Group4 &G, const uint4 &c0, const uint4 &c1, const uint32_t *K,
+                                            uint32_t ob0, uint32_t oc0, uint32_t od0, uint32_t *kdst,
+                                            const SampleSet &out_smp, const KeyMap &km, uint32_t *lds, uint32_t lane)
+{
+    const uint32_t pa = c1.x - c0.x, pb = c1.y - c0.y, pc = c1.z - c0.z, pd = c1.w - c0.w;
+    const uint32_t sx = pa + pb, sy = pc + pd, count = sx + sy;
+    if (count == 0 || sx > kHalfTile || sy > kHalfTile)
+        return;
+    const uint64_t gpos = G.start + c0.x + c0.y + c0.z + c0.w;
+    const uint32_t pieces = (pa != 0) + (pb != 0) + (pc != 0) + (pd != 0);
+    // offsets from A[0] of the four pieces' first keys
+    const uint32_t oa = c0.x, ob = ob0 + c0.y, oc = oc0 + c0.z, od = od0 + c0.w;
+    if (pieces == 1) {
+        // one piece: already sorted, copied as it is (no network, no LDS)
+        copy4<NT, MAP>(K + (pa ? oa : pb ? ob : pc ? oc : od), kdst, gpos, count, out_smp, km, lane);
+        return;
+    }
+    HalfPieces hp;
+    if (pieces >= 3) {
+        // A ascending and B reversed in the lower half, C and D likewise in
+        // the upper half, complemented
+        hp = HalfPieces{{oa, oc}, {pa, pc}, {ob + kHalfTile - 1, od + kHalfTile - 1}, {pb, pd}, ~0u};
+    } else {
+        // the first nonempty piece X ascending at the front of the lower half,
+        // the second one Y (if any) reversed at the back of the upper half
+        const uint32_t ox = pa ? oa : pb ? ob : pc ? oc : od;
+        const uint32_t nx = pa ? pa : pb ? pb : pc ? pc : pd;
+        const uint32_t oy = (pa && pb) ? ob : ((pa || pb) && pc) ? oc : od;
+        const uint32_t ny = pieces == 2 ? count - nx : 0;
+        hp = HalfPieces{{ox, 0}, {nx, 0}, {0, oy + kHalfTile - 1}, {0, ny}, 0u};
+    }
+    Lines<false> t;
+    load_item<false>(t, K, hp, lane);
+    if (pieces >= 3)
+        packed_network(t, lds, lane);
+    merge4_network(t, lds, lane);
+    emit_blocked<NT, MAP>(t, lds, kdst, gpos, count, out_smp, km, lane);
+}
+
 // One wave per merge item (at most kAbStep keys of AB and kCdStep of CD).
 // Items of three or four pieces load AB into the lower and CD into the upper
 // half of one tile and take two networks (both halves merged at once, then
@@ -1706,82 +1801,133 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
     G.M = __builtin_amdgcn_readfirstlane(G.M);
     const uint4 *P = src.cuts + (uint64_t)g * src.stride();
     const uint4 *Q = P + src.jfull + 1;
-    // a cut is the same in every lane: scalar values, so that every branch
-    // below is a scalar one
-    auto cut = [](const uint4 *p) {
-        const uint4 c = *p;
-        return make_uint4(__builtin_amdgcn_readfirstlane(c.x), __builtin_amdgcn_readfirstlane(c.y),
-                          __builtin_amdgcn_readfirstlane(c.z), __builtin_amdgcn_readfirstlane(c.w));
-    };
     uint4 c0, c1;
-    if (i < src.jfull) {
-        if (i >= G.J)
-            return;
-        c0 = cut(P + i);
-        const uint4 pe = cut(P + i + 1);
-        const uint32_t y0 = c0.z + c0.w, y1 = pe.z + pe.w;
-        if (y1 < y0)
-            return;
-        c1 = y1 - y0 > kCdStep ? cut(Q + y0 / kCdStep + 1) : pe;
-    } else {
-        const uint32_t m = i - src.jfull + 1;
-        if (m > G.M)
-            return;
-        c0 = cut(Q + m);
-        const uint4 qn = cut(Q + (m < G.M ? m + 1 : m));
-        const uint32_t xq = c0.x + c0.y, gm = kCdStep * m;
-        // the segment holding Q[m]: jc, or jc - 1 when P[jc] sits at Q[m]'s AB
-        // position but after it (more CD taken)
-        const uint32_t jc = min(G.J - 1, xq / kAbStep);
-        const uint4 pm = cut(P + (jc > 0 ? jc - 1 : 0)), pc = cut(P + jc), pn = cut(P + jc + 1);
-        const bool before = jc > 0 && pc.x + pc.y == xq && pc.z + pc.w > gm;
-        const uint4 p0 = before ? pm : pc, p1 = before ? pc : pn;
-        const uint32_t y0 = p0.z + p0.w, y1 = p1.z + p1.w;
-        if (!(y1 > y0 + kCdStep && y0 < gm && gm < y1))
-            return;  // not inside a long segment: the AB item covers it
-        c1 = (m < G.M && kCdStep * (m + 1) < y1) ? qn : p1;
-    }
-    // every piece inside its run, each side within its half tile (holds for
-    // cuts written by k_cuts4; checked so that no cut can move a load or a
-    // store outside the group)
-    if (c0.x > c1.x || c0.y > c1.y || c0.z > c1.z || c0.w > c1.w || c1.x > G.n[0] || c1.y > G.n[1] ||
-        c1.z > G.n[2] || c1.w > G.n[3])
+    if (!item_cuts(P, Q, G, i, src.jfull, c0, c1))
         return;
-    const uint32_t pa = c1.x - c0.x, pb = c1.y - c0.y, pc = c1.z - c0.z, pd = c1.w - c0.w;
-    const uint32_t sx = pa + pb, sy = pc + pd, count = sx + sy;
-    if (count == 0 || sx > kHalfTile || sy > kHalfTile)
+    const uint32_t L = (uint32_t)src.run;
+    merge4_item<NT, MAP>(G, c0, c1, src.ksrc + G.start, L, 2 * L, 3 * L, src.kdst, src.out_smp, src.out_map, lds,
+                         lane);
+}
+
+// ------------------------------------------ fan-in 4 passes over job tables
+//
+// The same two launches for the merges of a table-driven pass (the segmented
+// sort's segments, each with its own runs): a job is one group of four runs
+// anywhere in one of the three buffers, with its own cut records, item slots
+// and cut searches (task_job / item_job map a search or an item slot to its
+// job).  Runs start at any position, so no samples exist: the cut searches
+// read the keys themselves (32-ary rounds for the binary split, 16-ary for
+// the counts).
+
+struct Merge4Table {
+    Bufs kb;
+    const Merge4Job *jobs;
+    const uint32_t *task_job, *item_job;
+    uint32_t tasks, items;
+    uint4 *cuts;
+};
+
+__device__ __forceinline__ const uint32_t *buf_in(const Bufs &b, uint32_t sel)
+{
+    return sel == kBufIn ? b.in : (sel == kBufOut ? b.out : b.temp);
+}
+__device__ __forceinline__ uint32_t *buf_out(const Bufs &b, uint32_t sel) { return sel == kBufOut ? b.out : b.temp; }
+
+__device__ __forceinline__ Group4 group_of_job(const Merge4Job &j)
+{
+    Group4 G;
+    G.start = j.start;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        G.n[r] = j.n[r];
+    G.J = ab_segments((uint64_t)j.n[0] + j.n[1]);
+    G.M = cd_cuts((uint64_t)j.n[2] + j.n[3]);
+    return G;
+}
+
+// Cut searches of a table pass, two per wave (lanes 0..31 task 2w, lanes
+// 32..63 task 2w + 1): task t of its job is AB cut t + 1 (t < J - 1) or CD
+// cut t + 2 - J.  The records P[0] and P[J] of every job come from the
+// planner.
+__global__ __launch_bounds__(256) void k_cuts4_table(Merge4Table src)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t half = lane >> 5;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+    const uint32_t task = 2 * wave + half;
+    const bool in_range = task < src.tasks;
+    const Merge4Job jb = src.jobs[src.task_job[in_range ? task : 0]];
+    const Group4 G = group_of_job(jb);
+    const uint32_t t = in_range ? task - jb.task_off : 0;
+    const bool ab = t + 1 < G.J;
+    const uint32_t idx = ab ? t + 1 : t + 2 - G.J;  // AB cut j or CD cut m
+    const bool valid = in_range && (ab ? idx < G.J : (idx >= 1 && idx <= G.M));
+    if (__ballot(valid) == 0)
         return;
-    const uint64_t L = src.run;
-    const uint64_t gpos = G.start + c0.x + c0.y + c0.z + c0.w;
-    const uint32_t pieces = (pa != 0) + (pb != 0) + (pc != 0) + (pd != 0);
-    // offsets from A[0] of the four pieces' first keys
-    const uint32_t oa = c0.x, ob = (uint32_t)L + c0.y, oc = 2 * (uint32_t)L + c0.z, od = 3 * (uint32_t)L + c0.w;
-    if (pieces == 1) {
-        // one piece: already sorted, copied as it is (no network, no LDS)
-        copy4<NT, MAP>(src.ksrc + G.start + (pa ? oa : pb ? ob : pc ? oc : od), src.kdst, gpos, count, src.out_smp,
-                       src.out_map, lane);
+    const uint32_t *K = buf_in(src.kb, jb.src) + jb.start;
+    const uint32_t n0 = ab ? G.n[0] : G.n[2], n1 = ab ? G.n[1] : G.n[3];
+    const uint32_t *A = K + (ab ? 0u : G.n[0] + G.n[1]), *B = A + n0;
+    const uint32_t d = ab ? idx * kAbStep : idx * kCdStep;
+    uint32_t lo = d > n1 ? d - n1 : 0, hi = d < n0 ? d : n0;
+    if (!valid)
+        lo = hi = 0;
+    search_level<1, 5>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
+    const uint32_t s0 = lo, s1 = d - s0;
+    uint32_t k = 0;
+    if (valid)
+        k = (s0 < n0 && (s1 >= n1 || A[s0] <= B[s1])) ? A[s0] : B[s1];
+    // the other side: lanes 16..31 of a half count in its second run.  An AB
+    // cut counts keys below k, a CD cut keys at most k.
+    const uint32_t second = (lane >> 4) & 1;
+    const uint32_t nr = !valid ? 0 : (ab ? (second ? G.n[3] : G.n[2]) : (second ? G.n[1] : G.n[0]));
+    const uint32_t ro = ab ? G.n[0] + G.n[1] + (second ? G.n[2] : 0) : (second ? G.n[0] : 0);
+    const uint32_t *R = K + ro;
+    const bool strict = !ab;
+    uint32_t rlo = 0, rhi = nr;
+    search_level<1, 4>(rlo, rhi, lane, [&](uint32_t i) { return strict ? R[i] > k : R[i] >= k; });
+    const uint32_t q0 = __builtin_amdgcn_readlane(rlo, 0), q1 = __builtin_amdgcn_readlane(rlo, 16);
+    const uint32_t q2 = __builtin_amdgcn_readlane(rlo, 32), q3 = __builtin_amdgcn_readlane(rlo, 48);
+    const uint32_t o0 = half ? q2 : q0, o1 = half ? q3 : q1;
+    if (!valid || (lane & 31) != 0)
         return;
-    }
-    HalfPieces hp;
-    if (pieces >= 3) {
-        // A ascending and B reversed in the lower half, C and D likewise in
-        // the upper half, complemented
-        hp = HalfPieces{{oa, oc}, {pa, pc}, {ob + kHalfTile - 1, od + kHalfTile - 1}, {pb, pd}, ~0u};
-    } else {
-        // the first nonempty piece X ascending at the front of the lower half,
-        // the second one Y (if any) reversed at the back of the upper half
-        const uint32_t ox = pa ? oa : pb ? ob : pc ? oc : od;
-        const uint32_t nx = pa ? pa : pb ? pb : pc ? pc : pd;
-        const uint32_t oy = (pa && pb) ? ob : ((pa || pb) && pc) ? oc : od;
-        const uint32_t ny = pieces == 2 ? count - nx : 0;
-        hp = HalfPieces{{ox, 0}, {nx, 0}, {0, oy + kHalfTile - 1}, {0, ny}, 0u};
-    }
-    Lines<false> t;
-    load_item<NT>(t, src.ksrc + G.start, hp, lane);
-    if (pieces >= 3)
-        packed_network(t, lds, lane);
-    merge4_network(t, lds, lane);
-    emit_blocked<NT, MAP>(t, lds, src.kdst, gpos, count, src.out_smp, src.out_map, lane);
+    uint4 *P = src.cuts + jb.cut_off;
+    if (ab)
+        P[idx] = make_uint4(s0, s1, o0, o1);
+    else
+        P[G.J + 1 + idx] = make_uint4(o0, o1, s0, s1);
+}
+
+// Merges of a table pass: one wave per item slot.
+template <bool NT>
+__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(4))) void k_merge4_table(
+    Merge4Table src)
+{
+    __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t item = blockIdx.x;
+    if (item >= src.items)
+        return;
+    const uint32_t jid = __builtin_amdgcn_readfirstlane(src.item_job[item]);
+    const Merge4Job &jr = src.jobs[jid];
+    Merge4Job jb;
+    jb.start = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(jr.start >> 32)) << 32) |
+               __builtin_amdgcn_readfirstlane((uint32_t)jr.start);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        jb.n[r] = __builtin_amdgcn_readfirstlane(jr.n[r]);
+    jb.cut_off = __builtin_amdgcn_readfirstlane(jr.cut_off);
+    jb.item_off = __builtin_amdgcn_readfirstlane(jr.item_off);
+    const uint32_t sel = __builtin_amdgcn_readfirstlane(((uint32_t)jr.dst << 16) | jr.src);
+    const Group4 G = group_of_job(jb);
+    const uint4 *P = src.cuts + jb.cut_off;
+    const uint4 *Q = P + G.J + 1;
+    uint4 c0, c1;
+    if (!item_cuts(P, Q, G, item - jb.item_off, G.J, c0, c1))
+        return;
+    const uint32_t n01 = G.n[0] + G.n[1];
+    const SampleSet none{nullptr, nullptr, nullptr, nullptr};
+    merge4_item<NT, false>(G, c0, c1, buf_in(src.kb, sel & 0xffff) + G.start, G.n[0], n01, n01 + G.n[2],
+                           buf_out(src.kb, sel >> 16), none, KeyMap{}, lds, lane);
 }
 
 // Sortedness check of the runs of a merge input: sets *flag when some
@@ -2073,6 +2219,30 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
         hipLaunchKernelGGL((k_merge4<true, false>), grid, block, 0, s, src);
     else
         hipLaunchKernelGGL((k_merge4<false, false>), grid, block, 0, s, src);
+    return hipGetLastError();
+}
+
+uint32_t merge4_ab_segments(uint64_t nab) { return ab_segments(nab); }
+uint32_t merge4_cd_cuts(uint64_t ncd) { return cd_cuts(ncd); }
+
+hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, const uint32_t *task_job, uint32_t tasks,
+                               const uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, bool cut_phase,
+                               hipStream_t s)
+{
+    Merge4Table src{kb, jobs, task_job, item_job, tasks, items, static_cast<uint4 *>(cuts)};
+    if (cut_phase) {
+        if (tasks == 0)
+            return hipSuccess;
+        hipLaunchKernelGGL(k_cuts4_table, dim3((tasks + 7) / 8), dim3(256), 0, s, src);
+        return hipGetLastError();
+    }
+    if (items == 0)
+        return hipSuccess;
+    const dim3 grid(items), block(kWave * kMerge4Waves);
+    if (tuning().nontemporal && keys * 4.0 * 2 > kLastLevelCacheBytes)
+        hipLaunchKernelGGL(k_merge4_table<true>, grid, block, 0, s, src);
+    else
+        hipLaunchKernelGGL(k_merge4_table<false>, grid, block, 0, s, src);
     return hipGetLastError();
 }
 

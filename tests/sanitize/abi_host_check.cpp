@@ -58,8 +58,12 @@ int main()
     for (int s = 0; s <= 5; s++)
         CHECK(bcf_status_string((bcf_status)s) != nullptr);
 
-    // host planners: segmented sorts and merges of runs with random offsets
+    // host planners: segmented sorts and merges of runs with random offsets,
+    // with binary and fan-in 4 merge steps
     const uint64_t totals[] = {0, 1, 100, 4096, 4097, 70000, 1u << 20, (1u << 22) + 77};
+    bcf_tuning saved{};
+    bcf_get_tuning(&saved);
+    for (int fan_in : {2, 4})
     for (uint64_t n : totals)
         for (uint32_t parts : {1u, 2u, 3u, 17u, 300u, 5000u})
             for (int empties = 0; empties <= 1; empties++) {
@@ -84,7 +88,11 @@ int main()
                     for (int pb = 0; pb <= 1; pb++)
                         (void)bcf_distribute_runs(nullptr, off.data(), parts, P, P, pb, nullptr, nullptr, nullptr,
                                                   nullptr, &need, nullptr);
+                bcf_tuning t4 = saved;
+                t4.merge_fan_in = fan_in;
+                CHECK(bcf_set_tuning(&t4) == BCF_OK);
             }
+    CHECK(bcf_set_tuning(&saved) == BCF_OK);
     // invalid offsets are refused before any device access
     std::vector<uint64_t> bad{0, 5, 3, 9};
     CHECK(bcf_segmented_sort_host(nullptr, nullptr, bad.data(), 3, nullptr, &need, nullptr) == BCF_ERR_INVALID);

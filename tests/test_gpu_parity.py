@@ -601,6 +601,45 @@ def test_segmented_tail_at_allocation_end(torch_dev, bcf, sizes, pairs):
             assert first_diff(ko[lo:hi], oracle.sort_u32(keys[lo:hi])) is None
 
 
+@pytest.mark.parametrize("sizes", [
+    [4096 * 3 + 5], [4096 * 5 + 1], [4096 * 9, 7, 0, 4096 * 17 + 100], [32768 * 3 + 11, 32768 * 5, 1 << 20],
+    [1 << 18, 1 << 18, 3, 200000], [12345] * 40 + [4096 * 4 + 1] * 5])
+@pytest.mark.parametrize("dist", ["uniform", "distinct16", "zipf"])
+def test_segmented_four_way_vs_oracle(torch_dev, bcf, sizes, dist):
+    """Host-planned segmented sort with fan-in 4 merge steps (groups of four
+    runs of a segment merged per pass, the last step binary when two runs are
+    left): segments of 3, 5, 9, 17, ... runs, wave and group tiles, ties."""
+    torch, dev = torch_dev
+    offs = workloads.segment_offsets(sizes)
+    keys = workloads.keys_u32(dist, int(offs[-1]), seed=len(sizes) + 3)
+    for gmin in (0, 1 << 40):  # group tiles for long segments, or wave tiles only
+        with bcf.tuning(merge_fan_in=4, group_min_keys=gmin):
+            got = bcf.segmented_sort(to_dev(torch, dev, keys), offs).cpu().numpy()
+        assert first_diff(got, oracle.segmented_sort(keys, offs)) is None, (sizes, dist, gmin)
+
+
+def test_segmented_four_way_plan_graph_and_tuning(torch_dev, bcf):
+    """A plan uploaded with fan-in 4 steps replays in a graph on new data and
+    keeps its fan-in when executed under another tuning."""
+    torch, dev = torch_dev
+    sizes = workloads.segment_sizes(200, lo=32, hi=1 << 18, seed=7)
+    offs = workloads.segment_offsets(sizes)
+    n = int(offs[-1])
+    with bcf.tuning(merge_fan_in=4):
+        plan = bcf.SegmentedPlan(offs, dev)
+    kin = torch.empty(n, dtype=torch.uint32, device=dev)
+    kout = torch.empty_like(kin)
+    with bcf.tuning(merge_fan_in=2):
+        graph = plan.capture(kin, kout)
+    for rep in range(3):
+        keys = workloads.keys_u32("zipf" if rep % 2 else "uniform", n, seed=40 + rep)
+        kin.copy_(torch.from_numpy(keys))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert first_diff(kout.cpu().numpy(), oracle.segmented_sort(keys, offs)) is None, rep
+
+
 @pytest.mark.parametrize("group_min", [4097, 1000000000, 0])
 def test_segmented_group_threshold(torch_dev, bcf, group_min):
     # the same segments block-sorted in group tiles or in wave tiles
