@@ -358,13 +358,12 @@ bcf_status sort_typed(int kind, bool pairs, const uint32_t *kin, const uint32_t 
 struct MergePass {
     std::vector<MergeJob> jobs;
     std::vector<uint32_t> tile_job;
-    // fan-in 4 merges (keys only): jobs, their cut searches and item slots
-    // mapped to jobs, and the initial cut records (each job's first and last
-    // AB cut; the searches write the others)
+    // fan-in 4 merges (keys only): the jobs, and the totals of their cut
+    // searches, item slots and cut records (the maps from searches and slots
+    // to jobs, and the records, are written on the device)
     std::vector<Merge4Job> jobs4;
-    std::vector<uint32_t> task_job, item_job;
-    std::vector<uint32_t> cuts4;  // four u32 per record
-    uint64_t keys4 = 0;           // keys the fan-in 4 jobs merge
+    uint32_t tasks4 = 0, items4 = 0, records4 = 0;
+    uint64_t keys4 = 0;  // keys the fan-in 4 jobs merge
 };
 
 // Add one fan-in 4 job: runs of n[0..3] keys back to back from `start`.
@@ -378,22 +377,17 @@ void add_job4(MergePass &mp, uint64_t start, const uint64_t (&n)[4], uint32_t sr
     for (int r = 0; r < 4; ++r)
         j.n[r] = (uint32_t)n[r];
     const uint32_t J = merge4_ab_segments(n[0] + n[1]), M = merge4_cd_cuts(n[2] + n[3]);
-    j.cut_off = (uint32_t)(mp.cuts4.size() / 4);
-    j.item_off = (uint32_t)mp.item_job.size();
-    j.task_off = (uint32_t)mp.task_job.size();
+    j.cut_off = mp.records4;
+    j.item_off = mp.items4;
+    j.task_off = mp.tasks4;
     j.src = (uint16_t)src;
     j.dst = (uint16_t)dst;
-    const uint32_t id = (uint32_t)mp.jobs4.size();
     mp.jobs4.push_back(j);
-    for (uint32_t t = 0; t + 1 < J + M; ++t)  // AB cuts 1..J-1, CD cuts 1..M
-        mp.task_job.push_back(id);
-    for (uint32_t i = 0; i < J + M; ++i)
-        mp.item_job.push_back(id);
-    // records P[0..J], Q[0..M]: P[0] = nothing taken, P[J] = everything
-    mp.cuts4.resize(mp.cuts4.size() + 4 * (size_t)(J + M + 2), 0u);
-    uint32_t *last = mp.cuts4.data() + 4 * ((size_t)j.cut_off + J);
-    for (int r = 0; r < 4; ++r)
-        last[r] = j.n[r];
+    // searches: AB cuts 1..J-1 and CD cuts 1..M, at least one (the first
+    // writes the records P[0] and P[J]); records P[0..J] and Q[0..M]
+    mp.tasks4 += std::max(J - 1 + M, 1u);
+    mp.items4 += J + M;
+    mp.records4 += J + M + 2;
     mp.keys4 += tot;
 }
 
@@ -446,11 +440,11 @@ TableLayout layout_tables(uint64_t base, size_t nblock, size_t ngroup, const std
         L.jobs4_off.push_back(o);
         o = align256(o + mp.jobs4.size() * sizeof(Merge4Job));
         L.task_off.push_back(o);
-        o = align256(o + mp.task_job.size() * sizeof(uint32_t));
+        o = align256(o + (uint64_t)mp.tasks4 * sizeof(uint32_t));
         L.item_off.push_back(o);
-        o = align256(o + mp.item_job.size() * sizeof(uint32_t));
+        o = align256(o + (uint64_t)mp.items4 * sizeof(uint32_t));
         L.cuts4_off.push_back(o);
-        o = align256(o + mp.cuts4.size() * sizeof(uint32_t));
+        o = align256(o + (uint64_t)mp.records4 * 4 * sizeof(uint32_t));
     }
     L.splits_off = o;
     o = align256(o + max_tiles * sizeof(uint32_t));
@@ -487,14 +481,8 @@ bcf_status upload_tables(char *temp, const TablePlan &P, hipStream_t s)
             std::memcpy(img.data() + (L.map_off[p] - lo), P.passes[p].tile_job.data(),
                         P.passes[p].tile_job.size() * sizeof(uint32_t));
         const MergePass &mp = P.passes[p];
-        if (!mp.jobs4.empty()) {
+        if (!mp.jobs4.empty())
             std::memcpy(img.data() + (L.jobs4_off[p] - lo), mp.jobs4.data(), mp.jobs4.size() * sizeof(Merge4Job));
-            if (!mp.task_job.empty())
-                std::memcpy(img.data() + (L.task_off[p] - lo), mp.task_job.data(),
-                            mp.task_job.size() * sizeof(uint32_t));
-            std::memcpy(img.data() + (L.item_off[p] - lo), mp.item_job.data(), mp.item_job.size() * sizeof(uint32_t));
-            std::memcpy(img.data() + (L.cuts4_off[p] - lo), mp.cuts4.data(), mp.cuts4.size() * sizeof(uint32_t));
-        }
     }
     return upload(temp + lo, img.data(), bytes, s);
 }
@@ -524,15 +512,16 @@ bcf_status launch_tables(Bufs kb, Bufs vb, char *temp, const TablePlan &P, hipSt
     for (size_t p = 0; p < P.passes.size(); ++p) {
         const auto &mp = P.passes[p];
         if (!mp.jobs4.empty()) {
-            // the fan-in 4 merges of this pass (other segments than its binary jobs)
-            for (int phase = 0; phase < 2; ++phase) {
-                const bool cut = phase == 0;
-                ProfScope ps(cut ? "cuts4_keys_table" : "merge4_keys_table", s, cut ? 0.0 : 8.0 * mp.keys4);
+            // the fan-in 4 merges of this pass (other segments than its binary
+            // jobs): maps, cut searches, merges
+            for (int phase = 0; phase < 3; ++phase) {
+                static const char *const names[3] = {"map4_keys_table", "cuts4_keys_table", "merge4_keys_table"};
+                ProfScope ps(names[phase], s, phase == 2 ? 8.0 * mp.keys4 : 0.0);
                 BCF_TRY(dev_status(launch_merge4_table(
-                    kb, reinterpret_cast<const Merge4Job *>(temp + L.jobs4_off[p]),
-                    reinterpret_cast<const uint32_t *>(temp + L.task_off[p]), (uint32_t)mp.task_job.size(),
-                    reinterpret_cast<const uint32_t *>(temp + L.item_off[p]), (uint32_t)mp.item_job.size(),
-                    temp + L.cuts4_off[p], mp.keys4, cut, s)));
+                    kb, reinterpret_cast<const Merge4Job *>(temp + L.jobs4_off[p]), (uint32_t)mp.jobs4.size(),
+                    reinterpret_cast<uint32_t *>(temp + L.task_off[p]), mp.tasks4,
+                    reinterpret_cast<uint32_t *>(temp + L.item_off[p]), mp.items4, temp + L.cuts4_off[p], mp.keys4,
+                    phase, s)));
             }
         }
         if (mp.tile_job.empty())

@@ -130,16 +130,16 @@ hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs
                               const uint32_t *tile_job, uint32_t ntiles, uint32_t *splits,
                               bool partition, hipStream_t s, const uint32_t *count_dev = nullptr);
 // Fan-in 4 table pass (keys): AB / CD segment and cut counts of a job (the
-// planner sizes its records and items by them), and the two launches of a
-// pass over `njobs` jobs: the cut searches (`tasks` of them, task_job maps
-// each to its job), then the merges (`items` slots, item_job maps each to
-// its job).  `cuts` holds the pass's cut records, the first and last AB cut
-// of every job already written by the planner; `keys` is the number of keys
-// the pass merges (it decides the nontemporal hints).
+// planner sizes its records and items by them), and the three launches of a
+// pass over `njobs` jobs (phase 0: the maps from cut searches and item slots
+// to jobs, task_job and item_job, from the jobs' first indices; 1: the
+// `tasks` cut searches, which also write every job's first and last AB cut
+// into `cuts`; 2: the merges of the `items` slots).  `keys` is the number of
+// keys the pass merges (it decides the nontemporal hints).
 uint32_t merge4_ab_segments(uint64_t nab);
 uint32_t merge4_cd_cuts(uint64_t ncd);
-hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, const uint32_t *task_job, uint32_t tasks,
-                               const uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, bool cut_phase,
+hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, uint32_t *task_job, uint32_t tasks,
+                               uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, int phase,
                                hipStream_t s);
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);

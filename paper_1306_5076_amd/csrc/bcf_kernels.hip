@@ -1400,26 +1400,33 @@ __device__ __forceinline__ void search_level(uint32_t &lo, uint32_t &hi, uint32_
     }
 }
 
-// Cut searches, two per wave: lanes 0..31 take task 2w, lanes 32..63 task
-// 2w + 1; task t of group g is AB cut t + 1 (t < jfull - 1) or CD cut
-// t - jfull + 2.  A half-wave first finds the binary split of its cut's own
-// side (three sampled levels, 32 probes per round; the cut position is a
+// Cut searches, four per wave: the 16-lane quarter q of wave w takes task
+// 4w + q; task t of group g is AB cut t + 1 (t < jfull - 1) or CD cut
+// t - jfull + 2.  A quarter first finds the binary split of its cut's own
+// side (three sampled levels, 16 probes per round; the cut position is a
 // multiple of 64, so the first two levels read block samples), reads the
 // cut's key, then counts that key in the other side's two runs with one
-// 16-lane group per run at the same time.  Task 0 of a group also writes the
-// group's end points P[0] and P[J].
+// 8-lane group per run at the same time.  Task 0 of a group also writes the
+// group's end points P[0] and P[J].  The searches are bound by how many
+// waves are in flight more than by their rounds: measured at 2^26 keys, four
+// searches per wave take 13-24 us per launch, two (32-lane quarters) 18-32
+// us, one (64-lane rounds) 28-41 us.
+constexpr int kCutLanesLog = 4;                     // 16 lanes per search
+constexpr uint32_t kCutLanes = 1u << kCutLanesLog;
+constexpr uint32_t kCutsPerWave = kWave / kCutLanes;
+
 __global__ __launch_bounds__(256) void k_cuts4(Merge4Src src)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t half = lane >> 5;
+    const uint32_t part = lane / kCutLanes;  // this search's lanes: kCutLanes part .. + kCutLanes - 1
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
     const uint32_t per = src.jfull - 1 + src.mfull;  // cut searches of a full group
-    const uint32_t task = 2 * wave + half;
+    const uint32_t task = kCutsPerWave * wave + part;
     const uint32_t g = task / per, t = task % per;
     const bool in_range = g < src.groups;
     const Group4 G(src.n, src.run, in_range ? g : 0);
     uint4 *cuts = src.cuts + (uint64_t)(in_range ? g : 0) * src.stride();
-    if (in_range && t == 0 && (lane & 31) == 0) {
+    if (in_range && t == 0 && (lane & (kCutLanes - 1)) == 0) {
         cuts[0] = make_uint4(0, 0, 0, 0);
         cuts[G.J] = make_uint4(G.n[0], G.n[1], G.n[2], G.n[3]);
     }
@@ -1439,33 +1446,33 @@ __global__ __launch_bounds__(256) void k_cuts4(Merge4Src src)
     if (!valid)
         lo = hi = 0;
     auto block_pred = [&](uint32_t i) { return sm.f[(apos + i) / kLine] > sm.l[(bpos + d - 1 - i) / kLine]; };
-    search_level<kTile, 5>(lo, hi, lane, block_pred);  // 4096 candidates apart
-    search_level<kLine, 5>(lo, hi, lane, block_pred);
-    search_level<1, 5>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
+    search_level<kTile, kCutLanesLog>(lo, hi, lane, block_pred);  // 4096 candidates apart
+    search_level<kLine, kCutLanesLog>(lo, hi, lane, block_pred);
+    search_level<1, kCutLanesLog>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
     const uint32_t s0 = lo, s1 = d - s0;
     uint32_t k = 0;
     if (valid)
         k = (s0 < n0 && (s1 >= n1 || A[s0] <= B[s1])) ? A[s0] : B[s1];
-    // the other side: lanes 16..31 of a half count in its second run.  An AB
-    // cut counts keys below k (C and D keys equal to k follow it), a CD cut
-    // keys at most k (A and B keys equal to k precede it).
-    const uint32_t ro = (ab ? 2 : 0) + ((lane >> 4) & 1);
+    // the other side: the upper half of a search's lanes counts in its second
+    // run.  An AB cut counts keys below k (C and D keys equal to k follow it),
+    // a CD cut keys at most k (A and B keys equal to k precede it).
+    const uint32_t ro = (ab ? 2 : 0) + ((lane / (kCutLanes / 2)) & 1);
     const uint32_t nr = valid ? (ro == 0 ? G.n[0] : ro == 1 ? G.n[1] : ro == 2 ? G.n[2] : G.n[3]) : 0;
     const uint64_t rpos = G.start + ro * L;
     const uint32_t *R = src.ksrc + rpos;
     const bool strict = !ab;
     auto above = [&](uint32_t v) { return strict ? v > k : v >= k; };
     uint32_t rlo = 0, rhi = nr;
-    search_level<kTile, 4>(rlo, rhi, lane, [&](uint32_t i) {
+    search_level<kTile, kCutLanesLog - 1>(rlo, rhi, lane, [&](uint32_t i) {
         return sm.cf != nullptr ? above(sm.cf[(rpos + i) / kTile]) : above(sm.f[(rpos + i) / kLine]);
     });
-    search_level<kLine, 4>(rlo, rhi, lane, [&](uint32_t i) { return above(sm.f[(rpos + i) / kLine]); });
-    search_level<1, 4>(rlo, rhi, lane, [&](uint32_t i) { return above(R[i]); });
-    // the counts of this half's two groups (lanes 32h and 32h + 16)
-    const uint32_t q0 = __builtin_amdgcn_readlane(rlo, 0), q1 = __builtin_amdgcn_readlane(rlo, 16);
-    const uint32_t q2 = __builtin_amdgcn_readlane(rlo, 32), q3 = __builtin_amdgcn_readlane(rlo, 48);
-    const uint32_t o0 = half ? q2 : q0, o1 = half ? q3 : q1;
-    if (!valid || (lane & 31) != 0)
+    search_level<kLine, kCutLanesLog - 1>(rlo, rhi, lane, [&](uint32_t i) { return above(sm.f[(rpos + i) / kLine]); });
+    search_level<1, kCutLanesLog - 1>(rlo, rhi, lane, [&](uint32_t i) { return above(R[i]); });
+    // the counts of this search's two groups (its first lane and the one half
+    // way up), fetched from those lanes
+    const uint32_t first = lane & ~(kCutLanes - 1);
+    const uint32_t o0 = __shfl(rlo, first), o1 = __shfl(rlo, first + kCutLanes / 2);
+    if (!valid || (lane & (kCutLanes - 1)) != 0)
         return;
     if (ab)
         cuts[idx] = make_uint4(s0, s1, o0, o1);
@@ -1822,7 +1829,7 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
 struct Merge4Table {
     Bufs kb;
     const Merge4Job *jobs;
-    const uint32_t *task_job, *item_job;
+    uint32_t *task_job, *item_job;
     uint32_t tasks, items;
     uint4 *cuts;
 };
@@ -1845,16 +1852,39 @@ __device__ __forceinline__ Group4 group_of_job(const Merge4Job &j)
     return G;
 }
 
-// Cut searches of a table pass, two per wave (lanes 0..31 task 2w, lanes
-// 32..63 task 2w + 1): task t of its job is AB cut t + 1 (t < J - 1) or CD
-// cut t + 2 - J.  The records P[0] and P[J] of every job come from the
-// planner.
+// The maps of a table pass: search t and item slot i to the job whose range
+// (task_off, item_off; ascending, every job has at least one of each) holds
+// them, by binary search over the job list.
+__global__ __launch_bounds__(256) void k_map4_table(Merge4Table src, uint32_t njobs)
+{
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    auto owner = [&](uint32_t x, bool items) {
+        uint32_t lo = 0, hi = njobs;  // the job's first index <= x, in [lo, hi)
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if ((items ? src.jobs[mid].item_off : src.jobs[mid].task_off) <= x)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        return lo;
+    };
+    if (i < src.items)
+        src.item_job[i] = owner(i, true);
+    if (i < src.tasks)
+        src.task_job[i] = owner(i, false);
+}
+
+// Cut searches of a table pass, kCutsPerWave per wave like k_cuts4: task t
+// of its job is AB cut t + 1 (t < J - 1) or CD cut t + 2 - J; the job's task
+// 0 also writes its records P[0] and P[J] (a job with no cut to search has
+// one task for that alone).
 __global__ __launch_bounds__(256) void k_cuts4_table(Merge4Table src)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t half = lane >> 5;
+    const uint32_t part = lane / kCutLanes;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
-    const uint32_t task = 2 * wave + half;
+    const uint32_t task = kCutsPerWave * wave + part;
     const bool in_range = task < src.tasks;
     const Merge4Job jb = src.jobs[src.task_job[in_range ? task : 0]];
     const Group4 G = group_of_job(jb);
@@ -1862,6 +1892,11 @@ __global__ __launch_bounds__(256) void k_cuts4_table(Merge4Table src)
     const bool ab = t + 1 < G.J;
     const uint32_t idx = ab ? t + 1 : t + 2 - G.J;  // AB cut j or CD cut m
     const bool valid = in_range && (ab ? idx < G.J : (idx >= 1 && idx <= G.M));
+    if (in_range && t == 0 && (lane & (kCutLanes - 1)) == 0) {
+        uint4 *P = src.cuts + jb.cut_off;
+        P[0] = make_uint4(0, 0, 0, 0);
+        P[G.J] = make_uint4(G.n[0], G.n[1], G.n[2], G.n[3]);
+    }
     if (__ballot(valid) == 0)
         return;
     const uint32_t *K = buf_in(src.kb, jb.src) + jb.start;
@@ -1871,24 +1906,23 @@ __global__ __launch_bounds__(256) void k_cuts4_table(Merge4Table src)
     uint32_t lo = d > n1 ? d - n1 : 0, hi = d < n0 ? d : n0;
     if (!valid)
         lo = hi = 0;
-    search_level<1, 5>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
+    search_level<1, kCutLanesLog>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
     const uint32_t s0 = lo, s1 = d - s0;
     uint32_t k = 0;
     if (valid)
         k = (s0 < n0 && (s1 >= n1 || A[s0] <= B[s1])) ? A[s0] : B[s1];
-    // the other side: lanes 16..31 of a half count in its second run.  An AB
-    // cut counts keys below k, a CD cut keys at most k.
-    const uint32_t second = (lane >> 4) & 1;
+    // the other side: the upper half of a search's lanes counts in its second
+    // run.  An AB cut counts keys below k, a CD cut keys at most k.
+    const uint32_t second = (lane / (kCutLanes / 2)) & 1;
     const uint32_t nr = !valid ? 0 : (ab ? (second ? G.n[3] : G.n[2]) : (second ? G.n[1] : G.n[0]));
     const uint32_t ro = ab ? G.n[0] + G.n[1] + (second ? G.n[2] : 0) : (second ? G.n[0] : 0);
     const uint32_t *R = K + ro;
     const bool strict = !ab;
     uint32_t rlo = 0, rhi = nr;
-    search_level<1, 4>(rlo, rhi, lane, [&](uint32_t i) { return strict ? R[i] > k : R[i] >= k; });
-    const uint32_t q0 = __builtin_amdgcn_readlane(rlo, 0), q1 = __builtin_amdgcn_readlane(rlo, 16);
-    const uint32_t q2 = __builtin_amdgcn_readlane(rlo, 32), q3 = __builtin_amdgcn_readlane(rlo, 48);
-    const uint32_t o0 = half ? q2 : q0, o1 = half ? q3 : q1;
-    if (!valid || (lane & 31) != 0)
+    search_level<1, kCutLanesLog - 1>(rlo, rhi, lane, [&](uint32_t i) { return strict ? R[i] > k : R[i] >= k; });
+    const uint32_t first = lane & ~(kCutLanes - 1);
+    const uint32_t o0 = __shfl(rlo, first), o1 = __shfl(rlo, first + kCutLanes / 2);
+    if (!valid || (lane & (kCutLanes - 1)) != 0)
         return;
     uint4 *P = src.cuts + jb.cut_off;
     if (ab)
@@ -2203,8 +2237,9 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
     Merge4Src src{ksrc, kdst, n, run, (uint32_t)groups, ab_segments(2 * run), cd_cuts(2 * run),
                   static_cast<uint4 *>(cuts), in_smp, out_smp, out_map};
     if (cut_phase) {
-        const uint64_t tasks = groups * (src.jfull - 1 + src.mfull);  // two per wave, four waves per block
-        hipLaunchKernelGGL(k_cuts4, dim3((uint32_t)((tasks + 7) / 8)), dim3(256), 0, s, src);
+        const uint64_t tasks = groups * (src.jfull - 1 + src.mfull);  // kCutsPerWave per wave, four waves per block
+        const uint64_t per_block = kCutsPerWave * (256 / kWave);
+        hipLaunchKernelGGL(k_cuts4, dim3((uint32_t)((tasks + per_block - 1) / per_block)), dim3(256), 0, s, src);
         return hipGetLastError();
     }
     const uint64_t items = groups * (src.jfull + src.mfull);
@@ -2225,15 +2260,22 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
 uint32_t merge4_ab_segments(uint64_t nab) { return ab_segments(nab); }
 uint32_t merge4_cd_cuts(uint64_t ncd) { return cd_cuts(ncd); }
 
-hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, const uint32_t *task_job, uint32_t tasks,
-                               const uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, bool cut_phase,
-                               hipStream_t s)
+hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, uint32_t *task_job, uint32_t tasks,
+                               uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, int phase, hipStream_t s)
 {
     Merge4Table src{kb, jobs, task_job, item_job, tasks, items, static_cast<uint4 *>(cuts)};
-    if (cut_phase) {
+    if (njobs == 0)
+        return hipSuccess;
+    if (phase == 0) {
+        const uint32_t most = tasks > items ? tasks : items;
+        hipLaunchKernelGGL(k_map4_table, dim3((most + 255) / 256), dim3(256), 0, s, src, njobs);
+        return hipGetLastError();
+    }
+    if (phase == 1) {
         if (tasks == 0)
             return hipSuccess;
-        hipLaunchKernelGGL(k_cuts4_table, dim3((tasks + 7) / 8), dim3(256), 0, s, src);
+        const uint32_t per_block = kCutsPerWave * (256 / kWave);
+        hipLaunchKernelGGL(k_cuts4_table, dim3((tasks + per_block - 1) / per_block), dim3(256), 0, s, src);
         return hipGetLastError();
     }
     if (items == 0)
