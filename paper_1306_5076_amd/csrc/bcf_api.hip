@@ -215,13 +215,6 @@ uint64_t sort_run_keys(bool pairs, uint64_t n, const Tuning &tu)
     return sort_uses_groups(n, tu) ? group_run_keys(pairs) : (uint64_t)kTile;
 }
 
-// Sorts of at least this many keys take four-way merge passes under the
-// default (auto) fan-in.  Below it a pass's data mostly stays in the 256 MiB
-// last-level cache, binary passes stream from there, and halving their
-// number does not pay for the four-way pass's second launch and heavier
-// merge (measured: binary passes faster or equal up to 2^24 uniform keys).
-constexpr uint64_t kAutoFourWayMinN = 1ull << 25;
-
 // Fan-in of every merge pass of an n-key regular sort, first pass first:
 // four-way passes while more than two runs remain (keys only; their work
 // split is searched from key samples), then at most one binary pass.
@@ -385,9 +378,9 @@ void add_job4(MergePass &mp, uint64_t start, const uint64_t (&n)[4], uint32_t sr
     mp.jobs4.push_back(j);
     // searches: AB cuts 1..J-1 and CD cuts 1..M, at least one (the first
     // writes the records P[0] and P[J]); records P[0..J] and Q[0..M]
-    mp.tasks4 += std::max(J - 1 + M, 1u);
-    mp.items4 += J + M;
-    mp.records4 += J + M + 2;
+    mp.tasks4 += merge4_tasks(J, M);
+    mp.items4 += merge4_items(J, M);
+    mp.records4 += merge4_records(J, M);
     mp.keys4 += tot;
 }
 

@@ -136,13 +136,41 @@ hipError_t launch_merge_table(bool pairs, Bufs kb, Bufs vb, const MergeJob *jobs
 // `tasks` cut searches, which also write every job's first and last AB cut
 // into `cuts`; 2: the merges of the `items` slots).  `keys` is the number of
 // keys the pass merges (it decides the nontemporal hints).
-uint32_t merge4_ab_segments(uint64_t nab);
-uint32_t merge4_cd_cuts(uint64_t ncd);
+// Cut steps of the four-way merge (multiples of the 64-key sample blocks, at
+// most half a 4096-key tile): AB cuts every kAbStep keys, CD cuts every
+// kCdStep keys.  AB segments of a group whose AB side holds nab keys (at
+// least one, so that a group with an empty AB side still has an item), and
+// its interior CD cuts (CD positions kCdStep m with 0 < kCdStep m < ncd).
+constexpr uint32_t kAbStep = 1920;
+constexpr uint32_t kCdStep = 2048;
+__host__ __device__ constexpr uint32_t ab_segments(uint64_t nab)
+{
+    return nab > kAbStep ? (uint32_t)((nab + kAbStep - 1) / kAbStep) : 1u;
+}
+__host__ __device__ constexpr uint32_t cd_cuts(uint64_t ncd) { return ncd ? (uint32_t)((ncd - 1) / kCdStep) : 0u; }
+__host__ __device__ constexpr uint32_t merge4_ab_segments(uint64_t nab) { return ab_segments(nab); }
+__host__ __device__ constexpr uint32_t merge4_cd_cuts(uint64_t ncd) { return cd_cuts(ncd); }
+// Cut searches, item slots and cut records of one fan-in 4 job (J AB
+// segments, M interior CD cuts): at least one search (the first writes the
+// job's end records).
+__host__ __device__ constexpr uint32_t merge4_tasks(uint32_t J, uint32_t M) { return J - 1 + M > 0 ? J - 1 + M : 1u; }
+__host__ __device__ constexpr uint32_t merge4_items(uint32_t J, uint32_t M) { return J + M; }
+__host__ __device__ constexpr uint32_t merge4_records(uint32_t J, uint32_t M) { return J + M + 2; }
+// With counts_dev set the three counts come from device words (jobs,
+// searches, item slots) and njobs / tasks / items are their bounds: the
+// launches then stride over the counts with grids sized by the chip.
 hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, uint32_t *task_job, uint32_t tasks,
                                uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, int phase,
-                               hipStream_t s);
+                               hipStream_t s, const uint32_t *counts_dev = nullptr);
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);
+
+// Sorts of at least this many keys take four-way merge passes under the
+// default (auto) fan-in.  Below it a pass's data mostly stays in the 256 MiB
+// last-level cache, binary passes stream from there, and halving their
+// number does not pay for the four-way pass's second launch and heavier
+// merge (measured: binary passes faster or equal up to 2^24 uniform keys).
+constexpr uint64_t kAutoFourWayMinN = 1ull << 25;
 
 // Current process-wide tuning (see bcf_tuning in bcf.h); a copy.
 struct Tuning {

@@ -1314,19 +1314,8 @@ __global__ __launch_bounds__(kWave *merge_group_waves<MODE>()) void k_merge(Src 
 // no item.
 
 constexpr uint32_t kHalfTile = kTile / 2;
-constexpr uint32_t kAbStep = 1920;  // a multiple of 64 (block samples), at most kHalfTile
-constexpr uint32_t kCdStep = 2048;  // a multiple of 64, at most kHalfTile
 static_assert(kAbStep % kLine == 0 && kCdStep % kLine == 0 && kAbStep <= kHalfTile && kCdStep <= kHalfTile,
               "cut steps");
-
-// AB segments of a group whose AB side holds nab keys (at least one, so that
-// a group with an empty AB side still has an item), and its interior CD cuts
-// (CD positions kCdStep m with 0 < kCdStep m < ncd).
-__host__ __device__ constexpr uint32_t ab_segments(uint64_t nab)
-{
-    return nab > kAbStep ? (uint32_t)((nab + kAbStep - 1) / kAbStep) : 1u;
-}
-__host__ __device__ constexpr uint32_t cd_cuts(uint64_t ncd) { return ncd ? (uint32_t)((ncd - 1) / kCdStep) : 0u; }
 
 // The runs of group g of a fan-in 4 pass over n keys with runs of L.
 struct Group4 {
@@ -1830,8 +1819,18 @@ struct Merge4Table {
     Bufs kb;
     const Merge4Job *jobs;
     uint32_t *task_job, *item_job;
-    uint32_t tasks, items;
+    uint32_t njobs, tasks, items;  // bounds when counts is set
     uint4 *cuts;
+    const uint32_t *counts;        // device words (jobs, searches, item slots), or nullptr
+    // the counts of a plan made on the device, never past the bounds the grid covers
+    __device__ void resolve()
+    {
+        if (counts != nullptr) {
+            njobs = min(njobs, counts[0]);
+            tasks = min(tasks, counts[1]);
+            items = min(items, counts[2]);
+        }
+    }
 };
 
 __device__ __forceinline__ const uint32_t *buf_in(const Bufs &b, uint32_t sel)
@@ -1855,9 +1854,10 @@ __device__ __forceinline__ Group4 group_of_job(const Merge4Job &j)
 // The maps of a table pass: search t and item slot i to the job whose range
 // (task_off, item_off; ascending, every job has at least one of each) holds
 // them, by binary search over the job list.
-__global__ __launch_bounds__(256) void k_map4_table(Merge4Table src, uint32_t njobs)
+__global__ __launch_bounds__(256) void k_map4_table(Merge4Table src)
 {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    src.resolve();
+    const uint32_t njobs = src.njobs;
     auto owner = [&](uint32_t x, bool items) {
         uint32_t lo = 0, hi = njobs;  // the job's first index <= x, in [lo, hi)
         while (hi - lo > 1) {
@@ -1869,22 +1869,21 @@ __global__ __launch_bounds__(256) void k_map4_table(Merge4Table src, uint32_t nj
         }
         return lo;
     };
-    if (i < src.items)
-        src.item_job[i] = owner(i, true);
-    if (i < src.tasks)
-        src.task_job[i] = owner(i, false);
+    const uint32_t most = src.items > src.tasks ? src.items : src.tasks;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < most; i += gridDim.x * 256) {
+        if (i < src.items)
+            src.item_job[i] = owner(i, true);
+        if (i < src.tasks)
+            src.task_job[i] = owner(i, false);
+    }
 }
 
 // Cut searches of a table pass, kCutsPerWave per wave like k_cuts4: task t
 // of its job is AB cut t + 1 (t < J - 1) or CD cut t + 2 - J; the job's task
 // 0 also writes its records P[0] and P[J] (a job with no cut to search has
 // one task for that alone).
-__global__ __launch_bounds__(256) void k_cuts4_table(Merge4Table src)
+__device__ __forceinline__ void cut4_table_task(const Merge4Table &src, uint32_t task, uint32_t lane, uint32_t part)
 {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t part = lane / kCutLanes;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
-    const uint32_t task = kCutsPerWave * wave + part;
     const bool in_range = task < src.tasks;
     const Merge4Job jb = src.jobs[src.task_job[in_range ? task : 0]];
     const Group4 G = group_of_job(jb);
@@ -1931,16 +1930,22 @@ __global__ __launch_bounds__(256) void k_cuts4_table(Merge4Table src)
         P[G.J + 1 + idx] = make_uint4(o0, o1, s0, s1);
 }
 
-// Merges of a table pass: one wave per item slot.
-template <bool NT>
-__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(4))) void k_merge4_table(
-    Merge4Table src)
+__global__ __launch_bounds__(256) void k_cuts4_table(Merge4Table src)
 {
-    __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
+    src.resolve();
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t item = blockIdx.x;
-    if (item >= src.items)
-        return;
+    const uint32_t part = lane / kCutLanes;
+    const uint32_t waves = gridDim.x * (256 / kWave);
+    for (uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (256 / kWave) + threadIdx.x / kWave);
+         kCutsPerWave * wave < src.tasks; wave += waves)
+        cut4_table_task(src, kCutsPerWave * wave + part, lane, part);
+}
+
+// One item slot of a table pass.
+template <bool NT>
+__device__ __forceinline__ void merge4_table_item(const Merge4Table &src, uint32_t item, uint32_t *lds,
+                                                  uint32_t lane)
+{
     const uint32_t jid = __builtin_amdgcn_readfirstlane(src.item_job[item]);
     const Merge4Job &jr = src.jobs[jid];
     Merge4Job jb;
@@ -1962,6 +1967,23 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
     const SampleSet none{nullptr, nullptr, nullptr, nullptr};
     merge4_item<NT, false>(G, c0, c1, buf_in(src.kb, sel & 0xffff) + G.start, G.n[0], n01, n01 + G.n[2],
                            buf_out(src.kb, sel >> 16), none, KeyMap{}, lds, lane);
+}
+
+// Merges of a table pass: one wave per item slot, the grid striding over the
+// slots when it is smaller (plans made on the device size it by the chip).
+template <bool NT>
+__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(4))) void k_merge4_table(
+    Merge4Table src)
+{
+    __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
+    src.resolve();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    for (uint32_t item = blockIdx.x; item < src.items; item += gridDim.x) {
+        // the lane index re-derived per item keeps the compiler from hoisting
+        // the per-register addresses out of the loop (registers held across it)
+        merge4_table_item<NT>(src, item, lds, opaque(lane));
+        wave_lds_fence();  // the next item writes the LDS this one read
+    }
 }
 
 // Sortedness check of the runs of a merge input: sets *flag when some
@@ -2257,34 +2279,57 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
     return hipGetLastError();
 }
 
-uint32_t merge4_ab_segments(uint64_t nab) { return ab_segments(nab); }
-uint32_t merge4_cd_cuts(uint64_t ncd) { return cd_cuts(ncd); }
+// Work-groups of a launch whose count is known only on the device: enough to
+// fill every CU at the kernel's occupancy, never more than the bound needs.
+template <class K>
+static uint32_t resident_blocks(K kernel, int threads, uint64_t need)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1, cus = 256;
+    const uint64_t most = (uint64_t)cus * per_cu;
+    return (uint32_t)(need < most ? need : most);
+}
 
 hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, uint32_t *task_job, uint32_t tasks,
-                               uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, int phase, hipStream_t s)
+                               uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, int phase, hipStream_t s,
+                               const uint32_t *counts_dev)
 {
-    Merge4Table src{kb, jobs, task_job, item_job, tasks, items, static_cast<uint4 *>(cuts)};
+    Merge4Table src{kb, jobs, task_job, item_job, njobs, tasks, items, static_cast<uint4 *>(cuts), counts_dev};
     if (njobs == 0)
         return hipSuccess;
+    const bool dev_counts = counts_dev != nullptr;
     if (phase == 0) {
         const uint32_t most = tasks > items ? tasks : items;
-        hipLaunchKernelGGL(k_map4_table, dim3((most + 255) / 256), dim3(256), 0, s, src, njobs);
+        const uint64_t need = (most + 255) / 256;
+        const uint32_t grid = dev_counts ? resident_blocks(k_map4_table, 256, need) : (uint32_t)need;
+        if (grid == 0)
+            return hipSuccess;
+        hipLaunchKernelGGL(k_map4_table, dim3(grid), dim3(256), 0, s, src);
         return hipGetLastError();
     }
     if (phase == 1) {
         if (tasks == 0)
             return hipSuccess;
         const uint32_t per_block = kCutsPerWave * (256 / kWave);
-        hipLaunchKernelGGL(k_cuts4_table, dim3((tasks + per_block - 1) / per_block), dim3(256), 0, s, src);
+        const uint64_t need = (tasks + per_block - 1) / per_block;
+        const uint32_t grid = dev_counts ? resident_blocks(k_cuts4_table, 256, need) : (uint32_t)need;
+        hipLaunchKernelGGL(k_cuts4_table, dim3(grid), dim3(256), 0, s, src);
         return hipGetLastError();
     }
     if (items == 0)
         return hipSuccess;
-    const dim3 grid(items), block(kWave * kMerge4Waves);
-    if (tuning().nontemporal && keys * 4.0 * 2 > kLastLevelCacheBytes)
-        hipLaunchKernelGGL(k_merge4_table<true>, grid, block, 0, s, src);
-    else
-        hipLaunchKernelGGL(k_merge4_table<false>, grid, block, 0, s, src);
+    const bool nt = tuning().nontemporal && keys * 4.0 * 2 > kLastLevelCacheBytes;
+    const dim3 block(kWave * kMerge4Waves);
+    if (nt) {
+        const uint32_t grid = dev_counts ? resident_blocks(k_merge4_table<true>, kWave * kMerge4Waves, items) : items;
+        hipLaunchKernelGGL(k_merge4_table<true>, dim3(grid), block, 0, s, src);
+    } else {
+        const uint32_t grid = dev_counts ? resident_blocks(k_merge4_table<false>, kWave * kMerge4Waves, items) : items;
+        hipLaunchKernelGGL(k_merge4_table<false>, dim3(grid), block, 0, s, src);
+    }
     return hipGetLastError();
 }
 

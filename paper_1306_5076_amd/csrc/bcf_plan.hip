@@ -46,6 +46,7 @@ namespace {
     } while (0)
 
 constexpr int kMaxPlanPasses = 24;  // 4096 << 24 keys > 2^32
+constexpr int kMaxPlan4Passes = 12; // fan-in 4 steps: 4096 << 24 keys > 2^32
 constexpr uint32_t kPlanBlock = 256;
 constexpr uint64_t kMaxKeys = 0xFFFFFFFFull;
 
@@ -69,12 +70,15 @@ __host__ __device__ inline uint32_t ceil_log2_u(uint64_t x)
 
 enum GroupKind : uint32_t { kKindRuns = 0, kKindBuckets = 1, kKindSegments = 2 };
 
-// One group as the planner sees it.
+// One group as the planner sees it.  A segment (keys, fan-in 4 on) first
+// takes `steps4` fan-in 4 steps while more than two runs remain, then its
+// binary steps.
 struct GroupInfo {
     uint32_t first;   // explicit runs: index of the group's first offset
     uint32_t nruns;   // runs before the merge passes
-    uint32_t merges;  // binary merge passes, ceil(log2(nruns))
-    uint32_t passes;  // merges, or merges + 1 with a final copy, or 1 copy
+    uint32_t steps4;  // fan-in 4 steps (segments only)
+    uint32_t merges;  // binary merge passes after them
+    uint32_t passes;  // steps4 + merges, or merges + 1 with a final copy, or 1 copy
     uint32_t run0;    // segments: run length after the block sort (0: explicit runs)
     uint64_t start, end;
 };
@@ -92,6 +96,8 @@ struct PlanArgs {
     uint64_t gmin;       // segments: group tiles from this many keys (and more than 4096)
     uint32_t grun;       // segments: keys per group tile
     uint32_t PM;         // merge passes planned
+    uint32_t four;       // segments: fan-in 4 steps 0 off, 1 on, 2 from kAutoFourWayMinN keys in all
+    uint32_t PM4;        // passes with fan-in 4 tables (at most kMaxPlan4Passes)
     uint64_t cap;        // the most keys the temp buffer holds
     uint32_t *status;    // 0: plan valid; 1: offsets invalid or past the capacity
     // block-sort tiles (segments): counts per group, prefix, lists, totals
@@ -106,7 +112,17 @@ struct PlanArgs {
     uint32_t *tjob[kMaxPlanPasses];
     uint32_t jb[kMaxPlanPasses], tb[kMaxPlanPasses];  // bounds
     uint32_t *tcount;    // [PM] tiles of each pass
+    // fan-in 4 pass j: job counts per group (prefix), jobs, per-job searches /
+    // item slots / cut records (prefix: the jobs' first indices), and the
+    // pass's counts (jobs, searches, item slots); bounds
+    uint32_t *gjob4[kMaxPlan4Passes];
+    Merge4Job *jobs4[kMaxPlan4Passes];
+    uint32_t *jt4[kMaxPlan4Passes], *ji4[kMaxPlan4Passes], *jr4[kMaxPlan4Passes];
+    uint32_t *c4[kMaxPlan4Passes];
+    uint32_t j4b[kMaxPlan4Passes];
+    uint32_t t4b, i4b, r4b;
 };
+static_assert(sizeof(PlanArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 __device__ GroupInfo group_info(const PlanArgs &a, uint32_t g)
 {
@@ -117,11 +133,19 @@ __device__ GroupInfo group_info(const PlanArgs &a, uint32_t g)
         const uint64_t len = gi.end - gi.start;
         gi.run0 = (len > (uint64_t)kTile && len >= a.gmin) ? a.grun : (uint32_t)kTile;
         gi.nruns = (uint32_t)((len + gi.run0 - 1) / gi.run0);
-        gi.merges = ceil_log2_u(gi.nruns);
-        gi.passes = gi.merges;
+        uint32_t r = gi.nruns;
+        gi.steps4 = 0;
+        const bool four = a.four == 1 || (a.four == 2 && a.off[a.G] >= kAutoFourWayMinN);
+        while (four && r > 2 && gi.steps4 < a.PM4) {
+            r = (r + 3) / 4;
+            ++gi.steps4;
+        }
+        gi.merges = ceil_log2_u(r);
+        gi.passes = gi.steps4 + gi.merges;
         gi.first = 0;
     } else {
         gi.run0 = 0;
+        gi.steps4 = 0;
         if (a.kind == kKindRuns) {
             gi.first = 0;
             gi.nruns = a.k;
@@ -151,13 +175,30 @@ __device__ uint64_t run_bound(const PlanArgs &a, const GroupInfo &gi, uint32_t r
     return a.off[gi.first + r];
 }
 
-__device__ uint32_t jobs_in(const GroupInfo &gi, uint32_t j)  // j: 1-based pass
+// Runs (of run0 keys, segments) a binary step after the fan-in 4 steps
+// merges per pair: 4^steps4 2^(b - 1) for binary step b (1-based).
+__device__ uint64_t binary_unit(const GroupInfo &gi, uint32_t b) { return (1ull << (2 * gi.steps4)) << (b - 1); }
+
+// Binary jobs of pass j (1-based).
+__device__ uint32_t jobs_in(const GroupInfo &gi, uint32_t j)
 {
-    if (gi.end == gi.start || j > gi.passes)
+    if (gi.end == gi.start || j > gi.passes || j <= gi.steps4)
         return 0;
-    if (j <= gi.merges)
-        return (gi.nruns + (1u << j) - 1) >> j;
+    const uint32_t b = j - gi.steps4;
+    if (b <= gi.merges) {
+        const uint64_t span = 2 * binary_unit(gi, b);
+        return (uint32_t)((gi.nruns + span - 1) / span);
+    }
     return 1;  // the copy pass
+}
+
+// Fan-in 4 jobs of pass j (1-based): groups of four runs of 4^(j-1) run0 keys.
+__device__ uint32_t jobs4_in(const GroupInfo &gi, uint32_t j)
+{
+    if (gi.end == gi.start || j > gi.steps4)
+        return 0;
+    const uint64_t span = 1ull << (2 * j);
+    return (uint32_t)((gi.nruns + span - 1) / span);
 }
 
 // Buffer of group gi after its pass j (0: after the block sort, segments);
@@ -191,7 +232,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_check(PlanArgs a, uint32_t 
         *a.status = 1;
 }
 
-// Per-group counts: x = 0 wave tiles, 1 group tiles, 2 + j job counts of pass j.
+// Per-group counts: x = 0 wave tiles, 1 group tiles, 2 + j binary job counts
+// of pass j, 2 + PM + j fan-in 4 job counts of pass j.
 __global__ __launch_bounds__(kPlanBlock) void k_plan_count(PlanArgs a, uint32_t arrays)
 {
     const uint64_t t = (uint64_t)blockIdx.x * kPlanBlock + threadIdx.x;
@@ -204,9 +246,12 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_count(PlanArgs a, uint32_t 
         a.bw[g] = (ok && gi.run0 == (uint32_t)kTile) ? gi.nruns : 0;
     } else if (x == 1) {
         a.bg[g] = (ok && gi.run0 > (uint32_t)kTile) ? gi.nruns : 0;
-    } else {
+    } else if (x < 2 + a.PM) {
         const uint32_t j = x - 1;  // 1-based pass
         a.gjob[j - 1][g] = ok ? jobs_in(gi, j) : 0;
+    } else {
+        const uint32_t j = x - 1 - a.PM;  // 1-based pass
+        a.gjob4[j - 1][g] = ok ? jobs4_in(gi, j) : 0;
     }
 }
 
@@ -248,7 +293,7 @@ __device__ void block_scan(uint32_t *v, uint32_t len, uint32_t *total)
 }
 
 // Scans of the per-group counts: block y = 0 wave tiles, 1 group tiles,
-// 2 + j the job counts of pass j.
+// 2 + j the binary job counts of pass j, 2 + PM + j the fan-in 4 ones.
 __global__ __launch_bounds__(kPlanBlock) void k_plan_scan_groups(PlanArgs a, uint32_t first_array)
 {
     const uint32_t x = blockIdx.x + first_array;
@@ -256,8 +301,10 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan_groups(PlanArgs a, uin
         block_scan(a.bw, a.G, a.wcount);
     else if (x == 1)
         block_scan(a.bg, a.G, a.gcount);
-    else
+    else if (x < 2 + a.PM)
         block_scan(a.gjob[x - 2], a.G, nullptr);
+    else
+        block_scan(a.gjob4[x - 2 - a.PM], a.G, nullptr);
 }
 
 // Largest i in [0, n) with v[i] <= x (v nondecreasing, v[0] <= x).
@@ -308,11 +355,12 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_jobs(PlanArgs a)
     const GroupInfo gi = group_info(a, g);
     const uint32_t pass = j + 1;
     MergeJob m;
-    if (pass <= gi.merges) {
-        const uint32_t span = 1u << pass, half = span >> 1;
-        const uint32_t r0 = q * span;
-        const uint32_t rm = min(r0 + half, gi.nruns), r1 = min(r0 + span, gi.nruns);
-        const uint64_t b0 = run_bound(a, gi, r0), bm = run_bound(a, gi, rm), b1 = run_bound(a, gi, r1);
+    if (pass - gi.steps4 <= gi.merges) {  // pass > steps4: binary jobs exist only then
+        const uint64_t half = binary_unit(gi, pass - gi.steps4), span = 2 * half;
+        const uint64_t r0 = q * span;
+        const uint32_t rm = (uint32_t)min<uint64_t>(r0 + half, gi.nruns);
+        const uint32_t r1 = (uint32_t)min<uint64_t>(r0 + span, gi.nruns);
+        const uint64_t b0 = run_bound(a, gi, (uint32_t)r0), bm = run_bound(a, gi, rm), b1 = run_bound(a, gi, r1);
         m.a_start = b0;
         m.na = (uint32_t)(bm - b0);
         m.nb = (uint32_t)(b1 - bm);
@@ -352,6 +400,67 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_tile_map(PlanArgs a)
     a.tjob[j][t] = upper_index(a.jtile[j], njobs, t);
 }
 
+// Fan-in 4 jobs of every pass: thread (j, slot) builds job `slot` of pass j
+// (four runs of 4^j run0 / 4 keys of its segment) and its counts of cut
+// searches, item slots and cut records.
+__global__ __launch_bounds__(kPlanBlock) void k_plan_jobs4(PlanArgs a)
+{
+    const uint32_t j = blockIdx.y;  // 0-based pass
+    const uint32_t slot = blockIdx.x * kPlanBlock + threadIdx.x;
+    const uint32_t *pre = a.gjob4[j];
+    const uint32_t total = min(pre[a.G], a.j4b[j]);
+    if (slot >= total)
+        return;
+    const uint32_t g = upper_index(pre, a.G, slot);
+    const uint32_t q = slot - pre[g];
+    const GroupInfo gi = group_info(a, g);
+    const uint32_t pass = j + 1;
+    const uint64_t unit = 1ull << (2 * j), span = 4 * unit;  // runs of run0 keys
+    uint64_t b[5];
+    for (int t = 0; t <= 4; ++t)
+        b[t] = run_bound(a, gi, (uint32_t)min<uint64_t>(q * span + t * unit, gi.nruns));
+    Merge4Job m;
+    m.start = b[0];
+    for (int t = 0; t < 4; ++t)
+        m.n[t] = (uint32_t)(b[t + 1] - b[t]);
+    m.cut_off = m.item_off = m.task_off = 0;
+    m.src = pass == 1 ? buf_after(gi, 0) : buf_after(gi, pass - 1);
+    m.dst = buf_after(gi, pass);
+    a.jobs4[j][slot] = m;
+    const uint32_t J = merge4_ab_segments((uint64_t)m.n[0] + m.n[1]), M = merge4_cd_cuts((uint64_t)m.n[2] + m.n[3]);
+    a.jt4[j][slot] = merge4_tasks(J, M);
+    a.ji4[j][slot] = merge4_items(J, M);
+    a.jr4[j][slot] = merge4_records(J, M);
+}
+
+// The fan-in 4 jobs' first search, item slot and cut record of every pass
+// (one work-group per pass), and the pass's counts.  Counts past the bounds
+// the launches and areas were sized for (never, by the bounds' construction)
+// leave the pass with no job: nothing is read or written out of range.
+__global__ __launch_bounds__(kPlanBlock) void k_plan_scan_jobs4(PlanArgs a)
+{
+    const uint32_t j = blockIdx.x;
+    const uint32_t njobs = min(a.gjob4[j][a.G], a.j4b[j]);
+    __shared__ uint32_t tot[3];
+    block_scan(a.jt4[j], njobs, &tot[0]);
+    __syncthreads();
+    block_scan(a.ji4[j], njobs, &tot[1]);
+    __syncthreads();
+    block_scan(a.jr4[j], njobs, &tot[2]);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < njobs; i += kPlanBlock) {
+        a.jobs4[j][i].task_off = a.jt4[j][i];
+        a.jobs4[j][i].item_off = a.ji4[j][i];
+        a.jobs4[j][i].cut_off = a.jr4[j][i];
+    }
+    if (threadIdx.x == 0) {
+        const bool fits = tot[0] <= a.t4b && tot[1] <= a.i4b && tot[2] <= a.r4b;
+        a.c4[j][0] = fits ? njobs : 0;
+        a.c4[j][1] = fits ? tot[0] : 0;
+        a.c4[j][2] = fits ? tot[1] : 0;
+    }
+}
+
 // ------------------------------------------------------------- host side
 
 struct PlanSpec {
@@ -361,6 +470,7 @@ struct PlanSpec {
     uint32_t grun;
     bool pairs;
     uint32_t noff;  // offsets read (validity check)
+    uint32_t four;  // segments: fan-in 4 steps (PlanArgs::four); the areas are reserved for every keys-only plan
 };
 
 // Bounds of a plan for at most cap keys.
@@ -368,7 +478,21 @@ struct PlanBounds {
     uint32_t PM;
     uint64_t wb, gb;
     uint64_t jb[kMaxPlanPasses], tb[kMaxPlanPasses];
+    // fan-in 4 steps (keys-only segments): passes, jobs per pass, and cut
+    // searches / item slots / cut records of any one pass
+    uint32_t PM4;
+    uint64_t j4b[kMaxPlan4Passes];
+    uint64_t t4b, i4b, r4b;
 };
+
+// Fan-in 4 steps of a segment of `runs` runs: while more than two remain.
+uint32_t four_steps(uint64_t runs)
+{
+    uint32_t st = 0;
+    for (; runs > 2; runs = (runs + 3) / 4)
+        ++st;
+    return st;
+}
 
 PlanBounds plan_bounds(const PlanSpec &sp, uint64_t cap)
 {
@@ -380,6 +504,18 @@ PlanBounds plan_bounds(const PlanSpec &sp, uint64_t cap)
         b.gb = (cap + sp.grun - 1) / sp.grun + sp.G;
         for (uint32_t j = 1; j <= b.PM; ++j)
             b.jb[j - 1] = ((tiles + sp.G) >> j) + 1 + sp.G;
+        if (!sp.pairs) {
+            // segment g has at most ceil(len_g / 4096) runs, so step j (of four
+            // runs of 4^(j-1) each) at most (tiles + G) / 4^j + G jobs; a job of
+            // t keys takes at most t / kAbStep + 1 searches and item slots, and
+            // two more cut records
+            b.PM4 = four_steps(tiles);
+            for (uint32_t j = 1; j <= b.PM4; ++j)
+                b.j4b[j - 1] = ((tiles + sp.G) >> (2 * j)) + sp.G + 1;
+            const uint64_t most = b.PM4 ? b.j4b[0] : 0;
+            b.t4b = b.i4b = (cap + kAbStep - 1) / kAbStep + most;
+            b.r4b = b.i4b + 2 * most;
+        }
     } else {
         const uint32_t nr = sp.kind == kKindRuns ? sp.k : sp.s;
         const uint32_t merges = clog2(std::max<uint32_t>(nr, 1));
@@ -404,6 +540,11 @@ PlanBounds plan_bounds(const PlanSpec &sp, uint64_t cap)
 struct PlanLayout {
     uint64_t data, splits, status, bw, bg, wtiles, gtiles, wcount, gcount, tcount;
     uint64_t gjob[kMaxPlanPasses], jobs[kMaxPlanPasses], jtile[kMaxPlanPasses], tjob[kMaxPlanPasses];
+    // fan-in 4 steps: per pass the job counts, jobs, per-job counts and pass
+    // counts; one search map, item map and cut record area all passes share
+    uint64_t gjob4[kMaxPlan4Passes], jobs4[kMaxPlan4Passes];
+    uint64_t jt4[kMaxPlan4Passes], ji4[kMaxPlan4Passes], jr4[kMaxPlan4Passes], c4;
+    uint64_t tmap4, imap4, cuts4;
     uint64_t total;
 };
 
@@ -442,6 +583,28 @@ PlanLayout plan_layout(const PlanSpec &sp, const PlanBounds &b, uint64_t cap)
         L.tjob[j] = o;
         o = a256(o + b.tb[j] * 4);
     }
+    if (b.PM4) {
+        for (uint32_t j = 0; j < b.PM4; ++j) {
+            L.gjob4[j] = o;
+            o = a256(o + ((uint64_t)sp.G + 1) * 4);
+            L.jobs4[j] = o;
+            o = a256(o + b.j4b[j] * sizeof(Merge4Job));
+            L.jt4[j] = o;
+            o = a256(o + (b.j4b[j] + 1) * 4);
+            L.ji4[j] = o;
+            o = a256(o + (b.j4b[j] + 1) * 4);
+            L.jr4[j] = o;
+            o = a256(o + (b.j4b[j] + 1) * 4);
+        }
+        L.c4 = o;
+        o = a256(o + kMaxPlan4Passes * 4 * 4);
+        L.tmap4 = o;
+        o = a256(o + b.t4b * 4);
+        L.imap4 = o;
+        o = a256(o + b.i4b * 4);
+        L.cuts4 = o;
+        o = a256(o + b.r4b * 16);
+    }
     L.total = o;
     return L;
 }
@@ -478,6 +641,11 @@ bcf_status plan_and_run(const PlanSpec &sp, const uint64_t *off_dev, Bufs kb, Bu
     for (uint32_t j = 0; j < b.PM; ++j)
         if (b.jb[j] > 0xFFFFFFFFull || b.tb[j] > 0xFFFFFFFFull)
             return BCF_ERR_INVALID;
+    if (b.PM4 > kMaxPlan4Passes || b.t4b > 0xFFFFFFFFull || b.r4b > 0xFFFFFFFFull)
+        return BCF_ERR_INVALID;
+    // fan-in 4 launches only when some segment may take them: on, or auto with
+    // a capacity that reaches the threshold
+    const uint32_t P4 = (sp.four == 1 || (sp.four == 2 && cap >= kAutoFourWayMinN)) ? b.PM4 : 0;
     PlanArgs a{};
     a.off = off_dev;
     a.kind = sp.kind;
@@ -489,6 +657,8 @@ bcf_status plan_and_run(const PlanSpec &sp, const uint64_t *off_dev, Bufs kb, Bu
     a.gmin = sp.gmin;
     a.grun = sp.grun;
     a.PM = b.PM;
+    a.four = P4 ? sp.four : 0;
+    a.PM4 = P4;
     a.cap = cap;
     a.status = reinterpret_cast<uint32_t *>(temp + L.status);
     a.bw = reinterpret_cast<uint32_t *>(temp + L.bw);
@@ -508,6 +678,18 @@ bcf_status plan_and_run(const PlanSpec &sp, const uint64_t *off_dev, Bufs kb, Bu
         a.jb[j] = (uint32_t)b.jb[j];
         a.tb[j] = (uint32_t)b.tb[j];
     }
+    for (uint32_t j = 0; j < P4; ++j) {
+        a.gjob4[j] = reinterpret_cast<uint32_t *>(temp + L.gjob4[j]);
+        a.jobs4[j] = reinterpret_cast<Merge4Job *>(temp + L.jobs4[j]);
+        a.jt4[j] = reinterpret_cast<uint32_t *>(temp + L.jt4[j]);
+        a.ji4[j] = reinterpret_cast<uint32_t *>(temp + L.ji4[j]);
+        a.jr4[j] = reinterpret_cast<uint32_t *>(temp + L.jr4[j]);
+        a.c4[j] = reinterpret_cast<uint32_t *>(temp + L.c4) + 4 * j;
+        a.j4b[j] = (uint32_t)b.j4b[j];
+    }
+    a.t4b = (uint32_t)b.t4b;
+    a.i4b = (uint32_t)b.i4b;
+    a.r4b = (uint32_t)b.r4b;
     // status, the block-tile totals and the pass totals start at zero (a small
     // fill kernel rather than a memset: the sequence may be captured in a graph)
     hipLaunchKernelGGL(k_plan_zero, dim3(1), dim3(64), 0, s, a);
@@ -518,7 +700,7 @@ bcf_status plan_and_run(const PlanSpec &sp, const uint64_t *off_dev, Bufs kb, Bu
         BCF_PLAN_TRY(dev(hipGetLastError()));
     }
     const bool segs = sp.kind == kKindSegments;
-    const uint32_t arrays = 2 + b.PM;
+    const uint32_t arrays = 2 + b.PM + P4;
     {
         const uint64_t threads = (uint64_t)arrays * sp.G;
         hipLaunchKernelGGL(k_plan_count, dim3((uint32_t)((threads + kPlanBlock - 1) / kPlanBlock)), dim3(kPlanBlock),
@@ -551,6 +733,13 @@ bcf_status plan_and_run(const PlanSpec &sp, const uint64_t *off_dev, Bufs kb, Bu
                            dim3(kPlanBlock), 0, s, a);
         BCF_PLAN_TRY(dev(hipGetLastError()));
     }
+    if (P4) {
+        hipLaunchKernelGGL(k_plan_jobs4, dim3((uint32_t)((b.j4b[0] + kPlanBlock - 1) / kPlanBlock), P4),
+                           dim3(kPlanBlock), 0, s, a);
+        BCF_PLAN_TRY(dev(hipGetLastError()));
+        hipLaunchKernelGGL(k_plan_scan_jobs4, dim3(P4), dim3(kPlanBlock), 0, s, a);
+        BCF_PLAN_TRY(dev(hipGetLastError()));
+    }
     const bool pairs = sp.pairs;
     if (segs) {
         {
@@ -567,7 +756,19 @@ bcf_status plan_and_run(const PlanSpec &sp, const uint64_t *off_dev, Bufs kb, Bu
         }
     }
     uint32_t *splits = reinterpret_cast<uint32_t *>(temp + L.splits);
+    uint32_t *tmap4 = reinterpret_cast<uint32_t *>(temp + L.tmap4);
+    uint32_t *imap4 = reinterpret_cast<uint32_t *>(temp + L.imap4);
     for (uint32_t j = 0; j < b.PM; ++j) {
+        // the fan-in 4 jobs of the pass (segments still taking fan-in 4 steps),
+        // then its binary jobs (the other segments); they touch disjoint ranges
+        for (int phase = 0; j < P4 && phase < 3; ++phase) {
+            static const char *const names[3] = {"map4_keys_table", "cuts4_keys_table", "merge4_keys_table"};
+            void *p = prof_begin(names[phase], s, 0.0);
+            const hipError_t e = launch_merge4_table(kb, a.jobs4[j], a.j4b[j], tmap4, a.t4b, imap4, a.i4b,
+                                                     temp + L.cuts4, cap, phase, s, a.c4[j]);
+            prof_end(p);
+            BCF_PLAN_TRY(dev(e));
+        }
         for (int phase = 0; phase < 2; ++phase) {
             const bool part = phase == 0;
             void *p = prof_begin(part ? kname_partition(pairs, true) : kname_merge(pairs, true), s, 0.0);
@@ -642,6 +843,8 @@ bcf_status segmented_device(bool pairs, const uint32_t *kin, const uint32_t *vin
     sp.grun = group_run_keys(pairs);
     sp.pairs = pairs;
     sp.noff = nseg + 1;
+    const int fan_in = tuning().merge_fan_in;
+    sp.four = pairs ? 0u : (fan_in == 4 ? 1u : (fan_in == 0 ? 2u : 0u));
     return planned_call(sp, sp, off, kin, vin, kout, vout, temp, temp_bytes, s);
 }
 

@@ -92,6 +92,30 @@ def test_segmented_device_offsets(env, sizes, pairs):
         assert np.array_equal(out.cpu().numpy(), oracle.segmented_sort(keys, offs))
 
 
+@pytest.mark.parametrize("sizes", [
+    [4096 * 3 + 5], [4096 * 5 + 1], [4096 * 9, 7, 0, 4096 * 17 + 100], [32768 * 3 + 11, 32768 * 5, 1 << 20],
+    [1 << 18, 1 << 18, 3, 200000], [12345] * 40 + [4096 * 4 + 1] * 5])
+@pytest.mark.parametrize("dist", ["uniform", "distinct16", "zipf"])
+def test_segmented_device_offsets_four_way(env, sizes, dist):
+    """Device-planned segmented sort with fan-in 4 merge steps (four runs of a
+    segment per job while more than two remain, then binary): segments of 3,
+    5, 9, 17, ... runs, wave and group tiles, ties; equal to the oracle and to
+    the host-planned sort under the same tuning."""
+    torch, dev, bcf = env
+    print(f"segmented device offsets four-way: sizes={sizes[:6]} dist={dist}", flush=True)
+    offs = workloads.segment_offsets(np.asarray(sizes))
+    keys = workloads.keys_u32(dist, int(offs[-1]), seed=len(sizes) + 5)
+    kin = torch.from_numpy(keys).to(dev)
+    doff = _dev_offsets(torch, dev, offs)
+    want = oracle.segmented_sort(keys, offs)
+    for gmin in (0, 1 << 40):  # group tiles for long segments, or wave tiles only
+        with bcf.tuning(merge_fan_in=4, group_min_keys=gmin):
+            got = bcf.segmented_sort(kin, doff).cpu().numpy()
+            host = bcf.segmented_sort(kin, offs).cpu().numpy()
+        assert np.array_equal(got, want), (sizes[:6], dist, gmin)
+        assert np.array_equal(host, want), (sizes[:6], dist, gmin)
+
+
 def test_segmented_device_offsets_full_size(env):
     """The configured batch: 10,000 arrays of 32..2^20 keys (log-uniform), keys,
     segment by segment against the oracle."""
@@ -107,13 +131,14 @@ def test_segmented_device_offsets_full_size(env):
     assert np.array_equal(out.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("pairs", [False, True])
-def test_segmented_graph_replay_with_new_offsets(env, pairs):
+@pytest.mark.parametrize("pairs,fan_in", [(False, 0), (False, 4), (True, 0)])
+def test_segmented_graph_replay_with_new_offsets(env, pairs, fan_in):
     """One captured graph of the device-planned segmented sort, replayed with
     new segment offsets (same total) written into the same device tensor:
-    every replay equals the oracle for its own segmentation."""
+    every replay equals the oracle for its own segmentation.  Fan-in 4 keeps
+    its per-segment step counts on the device too (segments of 1 to ~60 runs)."""
     torch, dev, bcf = env
-    n = 300_000
+    n = 300_000 if fan_in != 4 else 1_500_000
     from paper_1306_5076_amd import _native
 
     lib = _native.load()
@@ -157,13 +182,15 @@ def test_segmented_graph_replay_with_new_offsets(env, pairs):
     kin.copy_(workloads.keys_u32_torch("uniform", n, dev, seed=1))
     side = torch.cuda.Stream(dev)
     side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        assert run(side) == 0  # warm-up outside capture
-    stream.wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        assert run(torch.cuda.current_stream(dev)) == 0
+    # fan-in 4 with wave tiles only: segments of up to ~60 runs of 4096 keys
+    with bcf.tuning(merge_fan_in=fan_in, group_min_keys=(1 << 40) if fan_in == 4 else 0):
+        with torch.cuda.stream(side):
+            assert run(side) == 0  # warm-up outside capture
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            assert run(torch.cuda.current_stream(dev)) == 0
     for rep in range(3):
         offs = new_offsets()
         doff.copy_(torch.from_numpy(offs))
@@ -181,9 +208,10 @@ def test_segmented_graph_replay_with_new_offsets(env, pairs):
             assert np.array_equal(kout.cpu().numpy(), oracle.segmented_sort(keys, offs.astype(np.uint64))), rep
 
 
-def test_invalid_device_offsets_write_nothing(env):
+@pytest.mark.parametrize("fan_in", [2, 4])
+def test_invalid_device_offsets_write_nothing(env, fan_in):
     """Decreasing device offsets, or a total past the capacity, are found by the
-    planner on the device: nothing is written."""
+    planner on the device: nothing is written (binary or fan-in 4 steps)."""
     torch, dev, bcf = env
     n = 50_000
     kin = workloads.keys_u32_torch("uniform", n, dev, seed=2)
@@ -201,8 +229,9 @@ def test_invalid_device_offsets_write_nothing(env):
     for bad in ([0, 30_000, 20_000], [0, 20_000, 10 * n]):
         doff = _dev_offsets(torch, dev, bad)
         sh = vp(torch.cuda.current_stream(dev).cuda_stream)
-        assert lib.bcf_segmented_sort(vp(kin.data_ptr()), vp(out.data_ptr()), vp(doff.data_ptr()), 2,
-                                      vp(temp.data_ptr()), ctypes.byref(tb), sh) == 0
+        with bcf.tuning(merge_fan_in=fan_in):
+            assert lib.bcf_segmented_sort(vp(kin.data_ptr()), vp(out.data_ptr()), vp(doff.data_ptr()), 2,
+                                          vp(temp.data_ptr()), ctypes.byref(tb), sh) == 0
         torch.cuda.synchronize()
         assert bool((out == 7).all()), bad
 
