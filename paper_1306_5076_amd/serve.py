@@ -25,9 +25,10 @@ stably by run) from any thread.  A launch thread
 
 A request that arrives while nothing is queued before it, no launch is under
 way and a slot is free is launched on the submitting thread itself, so a
-request at light load does not wait for the launch thread to wake up;
-requests that arrive during a launch, or while every slot is in flight,
-queue and are batched by the launch thread.
+request at light load does not wait for the launch thread to wake up (a
+device request then runs on the submitting stream, after the work already
+there, and needs no event); requests that arrive during a launch, or while
+every slot is in flight, queue and are batched by the launch thread.
 
 A completion thread waits for each batch's device-to-host copy, hands every
 request its result, records its latency from arrival to completion and
@@ -68,7 +69,9 @@ class _Request:
     keys: object            # numpy array (host request) or CUDA tensor (device request)
     vals: object | None
     arrival: float
-    ready: object = None    # device request: event recorded on the submitting stream
+    src: object = None      # device request: the submitting thread's current stream
+    ready: object = None    # device request: event recorded on `src` at submission (none when
+                            # launched inline: then its work is enqueued on `src` itself)
     runs: object = None     # merge request: its k+1 run offsets (numpy uint64)
     future: SortFuture = field(default_factory=SortFuture)
     submitted: float = 0.0  # perf_counter() when submit() queued it
@@ -83,7 +86,7 @@ class _Request:
 
     @property
     def on_device(self) -> bool:
-        return self.ready is not None
+        return self.src is not None
 
     @property
     def pairs(self) -> bool:
@@ -160,7 +163,14 @@ class SortServer:
         self.peak_used = 0
         self.batches = 0
         self.batch_sizes = []
-        self.cv = threading.Condition()
+        # one lock, two conditions: the launch thread waits on `cv` (new
+        # requests, freed slots, released holds), the completion thread on
+        # `cv_done` (batches in flight), so that neither wakes for the other's
+        # events
+        self.lock = threading.RLock()
+        self.cv = threading.Condition(self.lock)
+        self.cv_done = threading.Condition(self.lock)
+        self._no_values = torch.empty(0, dtype=torch.uint32, device=self.device)
         self.stop = False
         self.launcher_done = False
         self.holds = 0
@@ -185,8 +195,8 @@ class SortServer:
         when the future resolves (a consumer on another stream should call
         ``record_stream`` on them).
         """
-        keys, vals, ready = self._inputs(keys, vals)
-        return self._enqueue(_Request(keys, vals, time.perf_counter() if arrival is None else arrival, ready))
+        keys, vals, src = self._inputs(keys, vals)
+        return self._enqueue(_Request(keys, vals, time.perf_counter() if arrival is None else arrival, src=src))
 
     def submit_merge(self, keys, run_offsets, vals=None, arrival: float | None = None) -> Future:
         """Queue one merge request: ``keys`` holds k sorted runs, run r at
@@ -195,18 +205,18 @@ class SortServer:
         as for :meth:`submit`.  ``run_offsets`` is a host sequence of k+1
         offsets (a CUDA tensor is read back here, on the submitting thread);
         it must rise from 0 to the number of keys."""
-        keys, vals, ready = self._inputs(keys, vals)
+        keys, vals, src = self._inputs(keys, vals)
         if isinstance(run_offsets, torch.Tensor):
             run_offsets = run_offsets.cpu().numpy()
         offs = np.ascontiguousarray(np.asarray(run_offsets, dtype=np.uint64))
-        n = int(keys.numel()) if ready is not None else int(keys.size)
+        n = int(keys.numel()) if src is not None else int(keys.size)
         if offs.ndim != 1 or offs.size < 1 or int(offs[0]) != 0 or int(offs[-1]) != n or np.any(offs[1:] < offs[:-1]):
             raise ValueError("run_offsets must rise from 0 to the number of keys")
-        r = _Request(keys, vals, time.perf_counter() if arrival is None else arrival, ready, runs=offs)
+        r = _Request(keys, vals, time.perf_counter() if arrival is None else arrival, src=src, runs=offs)
         return self._enqueue(r)
 
     def _inputs(self, keys, vals):
-        ready = None
+        src = None
         if isinstance(keys, torch.Tensor) and keys.is_cuda:
             if keys.dtype != torch.uint32 or keys.device != self.device or not keys.is_contiguous():
                 raise ValueError("device keys must be a contiguous uint32 tensor on the server's device")
@@ -214,15 +224,14 @@ class SortServer:
                                      or vals.device != self.device or vals.shape != keys.shape
                                      or not vals.is_contiguous()):
                 raise ValueError("device values must be a contiguous uint32 tensor shaped like the keys")
-            ready = torch.cuda.Event()
-            ready.record(torch.cuda.current_stream(self.device))
+            src = torch.cuda.current_stream(self.device)
         else:
             keys = np.ascontiguousarray(np.asarray(keys, dtype=np.uint32))
             if vals is not None:
                 vals = np.ascontiguousarray(np.asarray(vals, dtype=np.uint32))
                 if vals.shape != keys.shape:
                     raise ValueError("keys and vals must have the same length")
-        return keys, vals, ready
+        return keys, vals, src
 
     def _enqueue(self, r: _Request) -> Future:
         if r.device_bytes() > self.budget:
@@ -243,6 +252,11 @@ class SortServer:
                 if inline:
                     slot = self._begin_launch(batch)
             if not inline:
+                if r.on_device:
+                    # the server reads the keys after the work the submitter has
+                    # enqueued so far (recorded before the launch thread can see r)
+                    r.ready = torch.cuda.Event()
+                    r.ready.record(r.src)
                 self.cv.notify_all()
                 return r.future
         try:
@@ -273,6 +287,7 @@ class SortServer:
         with self.cv:
             self.stop = True
             self.cv.notify_all()
+            self.cv_done.notify_all()
         self.launcher.join()
         self.completer.join()
         if self.error:
@@ -300,6 +315,7 @@ class SortServer:
                         r.future.set_exception(e)
                 self.pending.clear()
                 self.cv.notify_all()
+                self.cv_done.notify_all()
 
     def _free_hbm(self) -> int:
         """HBM a new allocation can take now: what the device reports free plus
@@ -389,7 +405,9 @@ class SortServer:
         with self.cv:
             self.launching -= 1
             self.busy.append(slot)
-            self.cv.notify_all()
+            self.cv_done.notify()
+            if self.pending or self.stop:  # requests that queued meanwhile, or a closing launch thread
+                self.cv.notify_all()
 
     def _launch_loop(self):
         while True:
@@ -397,7 +415,7 @@ class SortServer:
                 while True:
                     if self.stop and not self.pending and not self.launching:
                         self.launcher_done = True
-                        self.cv.notify_all()
+                        self.cv_done.notify_all()
                         return
                     batch = []
                     # one launch at a time: the library's host-planned calls share staging
@@ -415,7 +433,7 @@ class SortServer:
                 while not self.busy:
                     if self.launcher_done:
                         return
-                    self.cv.wait()
+                    self.cv_done.wait()
                 slot = self.busy[0]
             slot.done.synchronize()  # releases the GIL while the device finishes the batch
             done = time.perf_counter()
@@ -438,9 +456,13 @@ class SortServer:
                 self.used -= sum(r.device_bytes() for r in slot.reqs)
                 slot.reqs, slot.loc, slot.out = [], [], None
                 self.free_slots.append(slot)
-                self.cv.notify_all()
+                if self.pending:  # requests waiting for a slot or budget
+                    self.cv.notify_all()
 
     def _launch(self, slot: _Slot, batch):
+        if len(batch) == 1 and batch[0].on_device:
+            self._launch_alone(slot, batch[0])
+            return
         # order in the batch buffers: host requests before device requests, within
         # each keys-only before key/value, small before large, so that the host
         # part is one span (one copy each way) and the small requests of each
@@ -477,6 +499,8 @@ class SortServer:
             alone = len(slot.reqs) == 1
             for r, (lo, hi, vlo) in zip(slot.reqs, slot.loc):
                 if r.on_device:
+                    if r.ready is None:
+                        raise RuntimeError("a device request launched inline must be alone in its batch")
                     st.wait_event(r.ready)
                     if not (alone or solo(r)):  # sorted from its own buffer otherwise
                         dk[lo:hi].copy_(r.keys, non_blocking=True)
@@ -522,6 +546,35 @@ class SortServer:
                 slot.ov.get(nvh).copy_(rv[:nvh], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
+        slot.done = ev
+
+    def _launch_alone(self, slot: _Slot, r: _Request):
+        """A device request alone in its batch: sorted or merged from its own
+        buffer into fresh outputs, with none of the batch buffers (the common
+        case at light load).  Launched inline it runs on the submitting
+        stream itself, after the work already there; from the launch thread
+        on the slot's stream, after the request's ready event.  The slot's
+        workspace is reused only after the batch's done event has completed,
+        whichever stream it ran on."""
+        slot.reqs, slot.loc = [r], [(0, r.n, 0)]
+        st = slot.stream if r.ready is not None else r.src
+        with torch.cuda.stream(st):
+            if r.ready is not None:
+                st.wait_event(r.ready)
+            rk = torch.empty(r.n, dtype=torch.uint32, device=self.device)
+            rv = torch.empty(r.n, dtype=torch.uint32, device=self.device) if r.pairs else self._no_values
+            if r.merge:
+                if r.pairs:
+                    api.merge_runs(r.keys, r.runs, vals=r.vals, keys_out=rk, vals_out=rv, stream=st, workspace=slot.ws)
+                else:
+                    api.merge_runs(r.keys, r.runs, keys_out=rk, stream=st, workspace=slot.ws)
+            elif r.pairs:
+                api.sort_pairs_u32(r.keys, r.vals, rk, rv, stream=st, workspace=slot.ws)
+            else:
+                api.sort_u32(r.keys, out=rk, stream=st, workspace=slot.ws)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        slot.out = (rk, rv)
         slot.done = ev
 
 

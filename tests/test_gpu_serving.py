@@ -214,3 +214,41 @@ def test_inline_launch_when_idle(serve):
         assert t0 <= tm["admitted"] <= tm["launched"] <= t1
     with serve.SortServer(hbm_budget=1 << 30, inline=False) as srv:
         assert np.array_equal(srv.submit(keys).result(timeout=60), oracle.sort_u32(keys))
+
+
+@pytest.mark.parametrize("inline", [True, False])
+def test_device_request_from_side_stream(serve, inline):
+    """Device keys (and values) written on a side stream right before submit:
+    the server reads them after that work, whether the request is launched
+    inline on the submitting stream or queued for the launch thread (sorts,
+    key/value sorts and merges)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    side = torch.cuda.Stream(dev)
+    n = 200_000
+    keys = workloads.keys_u32("uniform", n, seed=21)
+    vals = workloads.draws_u32(22, n)
+    runs, offs = workloads.sorted_runs([70_000, 1, 90_000, 39_999], seed=23)
+    with serve.SortServer(hbm_budget=1 << 30, inline=inline) as srv:
+        for rep in range(3):
+            hk = torch.from_numpy(keys).pin_memory()
+            hv = torch.from_numpy(vals).pin_memory()
+            hr = torch.from_numpy(runs).pin_memory()
+            with torch.cuda.stream(side):
+                kd = torch.empty(n, dtype=torch.uint32, device=dev)
+                vd = torch.empty(n, dtype=torch.uint32, device=dev)
+                rd = torch.empty(runs.size, dtype=torch.uint32, device=dev)
+                kd.copy_(hk, non_blocking=True)
+                vd.copy_(hv, non_blocking=True)
+                rd.copy_(hr, non_blocking=True)
+                f1 = srv.submit(kd)
+                f2 = srv.submit(kd, vd)
+                f3 = srv.submit_merge(rd, offs)
+            g1 = f1.result(timeout=120).cpu().numpy()
+            gk, gv = f2.result(timeout=120)
+            g3 = f3.result(timeout=120).cpu().numpy()
+            assert np.array_equal(g1, oracle.sort_u32(keys)), rep
+            wk, wv = oracle.sort_pairs_u32(keys, vals)
+            assert np.array_equal(gk.cpu().numpy(), wk) and np.array_equal(gv.cpu().numpy(), wv), rep
+            assert np.array_equal(g3, oracle.merge_runs(runs, offs)), rep
