@@ -319,13 +319,13 @@ uint32_t bcf_run_keys(int pairs);
 
 /* Passes over the data in HBM of a sort of n keys under the current tuning:
  * the block sort plus the merge passes (the paper's Lemma 2: O(1 + log(N/M))
- * scans).  With binary passes (pairs always; keys under fan-in 2, or below
- * 2^25 keys under the default) there are ceil(log2(R)) merge passes for
- * R = ceil(n / bcf_run_keys(pairs)) runs.  With fan-in 4 (keys-only sorts) a
- * pass merges groups of four runs while more than two remain, two levels of
- * the paper's binary merging (Sec. 3.2) per read and write of the data, and a
- * last binary pass merges the final two runs if needed: 2^11 runs take 6
- * passes instead of 11.  Each merge pass finds its work split by reading
+ * scans).  With binary passes (fan-in 2, or below 2^25 keys under the
+ * default) there are ceil(log2(R)) merge passes for R = ceil(n /
+ * bcf_run_keys(pairs)) runs.  With fan-in 4 (keys or pairs) a pass merges
+ * groups of four runs while more than two remain, two levels of the paper's
+ * binary merging (Sec. 3.2) per read and write of the data, and a last binary
+ * pass merges the final two runs if needed: 2^11 runs take 6 passes instead
+ * of 11.  Each merge pass finds its work split by reading
  * O(log n) key samples and keys, in a small launch before it or (see
  * bcf_tuning.fused_partition) in the merge kernel. */
 uint32_t bcf_sort_passes(uint64_t n, int pairs);
@@ -365,15 +365,15 @@ typedef struct {
                                   run by the one-tile-per-wave kernel finds each tile's split
                                   itself from the samples (one launch per pass); 0: a separate
                                   partition launch first */
-    int32_t merge_fan_in;      /* runs merged per group by a merge pass of bcf_sort_u32 and of
-                                  the host-planned keys-only segmented sorts
-                                  (bcf_segmented_sort_host, bcf_segmented_upload / execute):
-                                  0 (default) 4 for at least 2^25 keys in total, else 2; 4 or
-                                  2 for every size.  A segment takes four-way steps while more
-                                  than two of its runs remain, then a binary one.  Four-way
-                                  passes of bcf_sort_u32 need sampled_partition (else 2 is
-                                  used).  Key/value sorts, bcf_merge_runs and the
-                                  device-planned segmented sorts merge pairs of runs */
+    int32_t merge_fan_in;      /* runs merged per group by a merge pass of the sorts
+                                  (bcf_sort_u32, bcf_sort_pairs_u32 and the int32 / float
+                                  forms) and of the keys-only segmented sorts (device- or
+                                  host-planned): 0 (default) 4 for at least 2^25 keys in
+                                  total, else 2; 4 or 2 for every size.  A segment takes
+                                  four-way steps while more than two of its runs remain, then
+                                  a binary one.  Four-way passes of the sorts need
+                                  sampled_partition (else 2 is used).  Key/value segmented
+                                  sorts and bcf_merge_runs merge pairs of runs */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);

@@ -216,8 +216,9 @@ uint64_t sort_run_keys(bool pairs, uint64_t n, const Tuning &tu)
 }
 
 // Fan-in of every merge pass of an n-key regular sort, first pass first:
-// four-way passes while more than two runs remain (keys only; their work
-// split is searched from key samples), then at most one binary pass.
+// four-way passes while more than two runs remain (keys or key/value pairs;
+// their work split is searched from key samples), then at most one binary
+// pass.
 std::vector<uint32_t> sort_fan_ins(bool pairs, uint64_t n, const Tuning &tu)
 {
     std::vector<uint32_t> fi;
@@ -225,7 +226,7 @@ std::vector<uint32_t> sort_fan_ins(bool pairs, uint64_t n, const Tuning &tu)
         return fi;
     const uint64_t run0 = sort_run_keys(pairs, n, tu);
     const bool want4 = tu.merge_fan_in == 4 || (tu.merge_fan_in == 0 && n >= kAutoFourWayMinN);
-    const bool four = !pairs && want4 && tu.sampled_partition;
+    const bool four = want4 && tu.sampled_partition;
     for (uint64_t runs = (n + run0 - 1) / run0; runs > 1;) {
         const uint32_t k = (four && runs > 2) ? 4 : 2;
         fi.push_back(k);
@@ -253,7 +254,7 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
     const uint64_t data = align256(n * 4) * (pairs ? 2 : 1);
     const uint64_t blocks64 = (n + kLine - 1) / kLine;
     const uint64_t set_bytes = 2 * align256(blocks64 * 4) + 2 * align256(tiles * 4);
-    const uint64_t cut_bytes = pairs ? 0 : align256(merge4_cut_bytes_max(n));
+    const uint64_t cut_bytes = align256(merge4_cut_bytes_max(n));
     const uint64_t need = passes ? data + align256(tiles * 4) + 2 * set_bytes + cut_bytes : 0;
     if (!temp) {
         *temp_bytes = need;
@@ -309,9 +310,11 @@ bcf_status sort_impl(bool pairs, const uint32_t *kin, const uint32_t *vin, uint3
             const SampleSet out_smp = j < passes ? sample_set(j & 1) : none;
             for (int phase = 0; phase < 2; ++phase) {
                 const bool cut = phase == 0;
-                ProfScope p(cut ? "cuts4_keys" : "merge4_keys", s, cut ? 0.0 : 2.0 * elem_bytes * n);
+                ProfScope p(cut ? (pairs ? "cuts4_pairs" : "cuts4_keys") : (pairs ? "merge4_pairs" : "merge4_keys"), s,
+                            cut ? 0.0 : 2.0 * elem_bytes * n);
                 BCF_TRY(dev_status(launch_merge4_regular(kbuf(j - 1), kbuf(j), n, run, cuts, in_smp, out_smp, cut,
-                                                         s, out_map(j))));
+                                                         s, out_map(j), pairs ? vbuf(j - 1) : nullptr,
+                                                         pairs ? vbuf(j) : nullptr)));
             }
             continue;
         }

@@ -445,6 +445,38 @@ __device__ __forceinline__ void to_strided_half(Lines<false> &t, uint32_t *lds, 
     swap_quadrants(t.k);
 }
 
+// The same two transposes for 64-bit elements, one 32-bit half after the
+// other through the same matrices.
+__device__ __forceinline__ void to_blocked_half(Lines<true> &t, uint32_t *lds, uint32_t lane)
+{
+    uint32_t hi[kLine], lo[kLine];
+    split_halves(t.e, hi, lo);
+    swap_quadrants(hi);
+    half_block_transpose<0, true>(hi, lds, lane);
+    half_block_transpose<kLine / 2, true>(hi, lds, lane);
+    swap_quadrants(lo);
+    half_block_transpose<0, true>(lo, lds, lane);
+    half_block_transpose<kLine / 2, true>(lo, lds, lane);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        t.e[r] = elem_of(((uint64_t)hi[r] << 32) | lo[r]);
+}
+
+__device__ __forceinline__ void to_strided_half(Lines<true> &t, uint32_t *lds, uint32_t lane)
+{
+    uint32_t hi[kLine], lo[kLine];
+    split_halves(t.e, hi, lo);
+    half_block_transpose<0, false>(hi, lds, lane);
+    half_block_transpose<kLine / 2, false>(hi, lds, lane);
+    swap_quadrants(hi);
+    half_block_transpose<0, false>(lo, lds, lane);
+    half_block_transpose<kLine / 2, false>(lo, lds, lane);
+    swap_quadrants(lo);
+#pragma unroll
+    for (int r = 0; r < kLine; ++r)
+        t.e[r] = elem_of(((uint64_t)hi[r] << 32) | lo[r]);
+}
+
 // ------------------------------------------------------ group (multi-wave) sort
 //
 // NW waves of a work-group (NW = 2^LW) sort a group tile of NW * 4096 keys:

@@ -108,16 +108,17 @@ hipError_t launch_merge_regular(bool pairs, const uint32_t *ksrc, const uint32_t
                                 uint32_t *kdst, uint32_t *vdst, uint64_t n, uint64_t run,
                                 uint32_t *splits, SampleSet in_smp, SampleSet out_smp,
                                 bool partition, bool fused, hipStream_t s, KeyMap out_map = {});
-// Fan-in 4 merge pass of a regular keys-only sort: groups of four runs of
-// `run` keys (a multiple of 4096) become runs of 4 run.  The cut phase
-// (cut_phase = true) searches the pass's work split from the samples of the
-// input (in_smp, required) into `cuts` (merge4_cut_bytes(n, run) bytes); the
-// merge phase then merges and writes the samples of its output (out_smp).
+// Fan-in 4 merge pass of a regular sort: groups of four runs of `run` keys
+// (a multiple of 4096) become runs of 4 run.  The cut phase (cut_phase =
+// true) searches the pass's work split from the samples of the input (in_smp,
+// required) into `cuts` (merge4_cut_bytes(n, run) bytes); the merge phase then
+// merges and writes the samples of its output (out_smp).  With vsrc / vdst the
+// pass is a stable key/value pass (values laid out like the keys).
 uint64_t merge4_cut_bytes(uint64_t n, uint64_t run);
-uint64_t merge4_cut_bytes_max(uint64_t n);  // the largest over every plan of an n-key sort
+uint64_t merge4_cut_bytes_max(uint64_t n);  // the largest over every plan of an n-key sort (keys or pairs)
 hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t n, uint64_t run, void *cuts,
                                  SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s,
-                                 KeyMap out_map = {});
+                                 KeyMap out_map = {}, const uint32_t *vsrc = nullptr, uint32_t *vdst = nullptr);
 // Table launches: the grid covers ntiles (ngroups) tiles; with count_dev set
 // the kernels take the actual count from that device word (at most the bound),
 // so that a device planner can size the work after the launch was enqueued.

@@ -1349,6 +1349,8 @@ struct Merge4Src {
     uint4 *cuts;
     SampleSet in_smp, out_smp;
     KeyMap out_map;
+    const uint32_t *vsrc = nullptr;  // key/value passes: the values, laid out like the keys
+    uint32_t *vdst = nullptr;
     __host__ __device__ uint32_t stride() const { return jfull + mfull + 2; }
 };
 
@@ -1489,7 +1491,8 @@ __device__ __forceinline__ void merge4_network(Lines<false> &t, uint32_t *lds, u
 // register.  The whole offset of a register (lane + 64 r keys) is passed in the
 // vector offset, the part of the address that the range check covers.
 template <bool NT>
-__device__ __forceinline__ void store_bounded(const Lines<false> &t, uint32_t *dst, uint32_t count, uint32_t lane)
+__device__ __forceinline__ void store_bounded(const uint32_t (&x)[kLine], uint32_t *dst, uint32_t count,
+                                              uint32_t lane)
 {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)(count * 4u), 0x00020000);
 #pragma unroll
@@ -1497,8 +1500,13 @@ __device__ __forceinline__ void store_bounded(const Lines<false> &t, uint32_t *d
         if ((uint32_t)(kWave * r) >= count)
             break;  // wave-uniform: rows past the end hold padding only
         const uint32_t off = opaque(4u * (kWave * r + lane));
-        __builtin_amdgcn_raw_buffer_store_b32(t.k[r], rs, (int)off, 0, NT ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b32(x[r], rs, (int)off, 0, NT ? 2 : 0);
     }
+}
+template <bool NT>
+__device__ __forceinline__ void store_bounded(const Lines<false> &t, uint32_t *dst, uint32_t count, uint32_t lane)
+{
+    store_bounded<NT>(t.k, dst, count, lane);
 }
 
 // Word i (0..3) of the 16 bytes at LDS word w (w a multiple of 4), for a
@@ -1803,6 +1811,200 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
     const uint32_t L = (uint32_t)src.run;
     merge4_item<NT, MAP>(G, c0, c1, src.ksrc + G.start, L, 2 * L, 3 * L, src.kdst, src.out_smp, src.out_map, lds,
                          lane);
+}
+
+// ---------------------------------------------- fan-in 4 passes, key/value
+//
+// The same pass for stable key/value sorts.  Cuts and items are those of the
+// keys-only pass (the cuts count exact stable positions: equal keys of A and
+// B before those of C and D, and the binary splits keep A before B, C before
+// D), and an item's tile holds (key, rank) elements in the keys' places.  The
+// rank is the element's place in the item's input taken run after run (A,
+// then B, C, D), so ties leave in run order and the rank names the element's
+// source.  After the networks (on 64-bit elements, each transpose one 32-bit
+// half at a time) the tile is back in STRIDED layout, where neighbouring
+// lanes hold neighbouring outputs; every output fetches its value from the
+// input by its rank (reads spread over at most four runs), and keys and
+// values are stored.  The tile takes 128 registers: two waves per SIMD.
+
+// Rank layout of an item's pieces: piece q holds ranks [s[q], s[q + 1]) and
+// starts o[q] keys after the group's first key (s[4] = 4096: no rank reaches
+// it).
+struct ItemRanks {
+    uint32_t s[4], o[4];
+};
+
+__device__ __forceinline__ uint32_t rank_offset(const ItemRanks &ir, uint32_t rank)
+{
+    return rank < ir.s[1] ? ir.o[0] + rank
+                          : rank < ir.s[2] ? ir.o[1] + (rank - ir.s[1])
+                                           : rank < ir.s[3] ? ir.o[2] + (rank - ir.s[2]) : ir.o[3] + (rank - ir.s[3]);
+}
+
+// Load an item's tile as (key, rank) elements in STRIDED layout, keys placed
+// as load_item places them; the front piece of half h has ranks from rf[h],
+// the back piece (read backwards) from rb[h].  All 64 loads are issued before
+// any is used; the upper half is complemented when hp.xm is set.  (Values
+// are fetched after the networks, by rank: staging them in LDS beside the
+// keys measured slower, 1.86 against 1.71 ms per pass of 2^28 pairs.)
+__device__ __forceinline__ void load_item_pairs(Lines<true> &t, const uint32_t *K, const HalfPieces &hp,
+                                                const uint32_t (&rf)[2], const uint32_t (&rb)[2], uint32_t lane)
+{
+    typedef __attribute__((address_space(1))) const uint32_t gkey;
+    const uint32_t ln = opaque(lane);
+    gkey *kg = (gkey *)K, *pad = (gkey *)kPadKeys + ln;
+    uint32_t key[kLine];
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const int h = r / (kLine / 2);
+        const uint32_t q = kWave * (r % (kLine / 2)) + ln;
+        const bool in_f = q < hp.fn[h], in_b = q >= kHalfTile - hp.bn[h];
+        const uint32_t off = in_f ? hp.front[h] + q : hp.bend[h] - q;
+        key[r] = *((in_f || in_b) ? kg + off : pad);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const uint64_t cm = hp.xm ? kPayloadMask : 0ull;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const int h = r / (kLine / 2);
+        const uint32_t q = kWave * (r % (kLine / 2)) + ln;
+        const bool in_f = q < hp.fn[h], in_b = q >= kHalfTile - hp.bn[h];
+        const uint32_t rank = in_f ? rf[h] + q : (in_b ? rb[h] + (kHalfTile - 1 - q) : kPadRank);
+        const double e = make_elem(key[r], rank);
+        t.e[r] = h ? elem_of(bits_of(e) ^ cm) : e;
+    }
+}
+
+// Lane k receives register k of lane `src` (a wave-uniform lane).
+__device__ __forceinline__ uint32_t column_of_lane(const uint32_t (&x)[kLine], uint32_t src, uint32_t lane)
+{
+    uint32_t v = 0;
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t s = __builtin_amdgcn_readlane(x[r], src);
+        v = lane == (uint32_t)r ? s : v;
+    }
+    return v;
+}
+
+template <bool NT, bool MAP>
+__device__ __forceinline__ void merge4_item_pairs(const Group4 &G, const uint4 &c0, const uint4 &c1, const uint32_t *K,
+                                                  const uint32_t *V, uint32_t ob0, uint32_t oc0, uint32_t od0,
+                                                  uint32_t *kdst, uint32_t *vdst, const SampleSet &out_smp,
+                                                  const KeyMap &km, uint32_t *lds, uint32_t lane)
+{
+    const uint32_t pa = c1.x - c0.x, pb = c1.y - c0.y, pc = c1.z - c0.z, pd = c1.w - c0.w;
+    const uint32_t sx = pa + pb, sy = pc + pd, count = sx + sy;
+    if (count == 0 || sx > kHalfTile || sy > kHalfTile)
+        return;
+    const uint64_t gpos = G.start + c0.x + c0.y + c0.z + c0.w;
+    const uint32_t pieces = (pa != 0) + (pb != 0) + (pc != 0) + (pd != 0);
+    const uint32_t oa = c0.x, ob = ob0 + c0.y, oc = oc0 + c0.z, od = od0 + c0.w;
+    if (pieces == 1) {
+        const uint32_t o = pa ? oa : pb ? ob : pc ? oc : od;
+        const SampleSet none{nullptr, nullptr, nullptr, nullptr};
+        copy4<NT, MAP>(K + o, kdst, gpos, count, out_smp, km, lane);
+        copy4<NT, false>(V + o, vdst, gpos, count, none, KeyMap{}, lane);
+        return;
+    }
+    HalfPieces hp;
+    ItemRanks ir;
+    uint32_t rf[2], rb[2];
+    if (pieces >= 3) {
+        hp = HalfPieces{{oa, oc}, {pa, pc}, {ob + kHalfTile - 1, od + kHalfTile - 1}, {pb, pd}, ~0u};
+        ir = ItemRanks{{0, pa, pa + pb, pa + pb + pc}, {oa, ob, oc, od}};
+        rf[0] = 0, rb[0] = pa, rf[1] = pa + pb, rb[1] = pa + pb + pc;
+    } else {
+        const uint32_t ox = pa ? oa : pb ? ob : pc ? oc : od;
+        const uint32_t nx = pa ? pa : pb ? pb : pc ? pc : pd;
+        const uint32_t oy = (pa && pb) ? ob : ((pa || pb) && pc) ? oc : od;
+        hp = HalfPieces{{ox, 0}, {nx, 0}, {0, oy + kHalfTile - 1}, {0, count - nx}, 0u};
+        ir = ItemRanks{{0, nx, kTile, kTile}, {ox, oy, 0, 0}};
+        rf[0] = 0, rb[0] = 0, rf[1] = 0, rb[1] = nx;
+    }
+    Lines<true> t;
+    load_item_pairs(t, K, hp, rf, rb, lane);
+    if (pieces >= 3) {
+        // both halves merged at once, back to STRIDED, the CD half complemented back
+        half_clean<kLine / 4, -1, true>(t);
+        to_blocked_half(t, lds, lane);
+        half_clean<kLine / 2, -1, true>(t);
+        to_strided_half(t, lds, lane);
+#pragma unroll
+        for (int r = kLine / 2; r < kLine; ++r)
+            t.e[r] = elem_of(bits_of(t.e[r]) ^ kPayloadMask);
+    }
+    half_clean<kLine / 2, -1, true>(t);
+    to_blocked_half(t, lds, lane);
+    half_clean<kLine / 2, -1, true>(t);
+    to_strided_half(t, lds, lane);
+    // keys, and values fetched by rank (positions past the item read its first value)
+    typedef __attribute__((address_space(1))) const uint32_t gval;
+    gval *vg = (gval *)V;
+    uint32_t kk[kLine], vv[kLine];
+#pragma unroll
+    for (int r = 0; r < kLine; ++r) {
+        const uint32_t p = kWave * r + lane;
+        kk[r] = elem_key(t.e[r]);
+        const uint32_t off = p < count ? rank_offset(ir, elem_rank(t.e[r])) : ir.o[0];
+        vv[r] = vg[off];
+    }
+    if (out_smp.f != nullptr) {
+        // the first and last key of every 64-key block of the array inside the
+        // item: positions bf + 64k and bl + 64k, register k of lanes bf and bl
+        const uint32_t bf = (uint32_t)((kLine - gpos % kLine) % kLine);
+        const uint32_t bl = (bf + kLine - 1) % kLine;
+        const uint32_t f = column_of_lane(kk, bf, lane), l = column_of_lane(kk, bl, lane);
+        const uint32_t pf = bf + kLine * lane, pl = bl + kLine * lane;
+        if (pf < count) {
+            const uint64_t gp = gpos + pf;
+            out_smp.f[gp / kLine] = f;
+            if (out_smp.cf != nullptr && gp % kTile == 0)
+                out_smp.cf[gp / kTile] = f;
+        }
+        if (pl < count) {
+            const uint64_t gp = gpos + pl;
+            out_smp.l[gp / kLine] = l;
+            if (out_smp.cf != nullptr && gp % kTile == kTile - 1)
+                out_smp.cl[gp / kTile] = l;
+        }
+    }
+    if constexpr (MAP) {
+#pragma unroll
+        for (int r = 0; r < kLine; ++r)
+            kk[r] = map_key(kk[r], km.sign, km.rest, km.inverse);
+    }
+    const uint32_t ln = opaque(lane);
+    store_bounded<NT>(kk, kdst + gpos, count, ln);
+    store_bounded<NT>(vv, vdst + gpos, count, ln);
+}
+
+// One wave per merge item, as k_merge4.
+template <bool NT, bool MAP = false>
+__global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4_pairs(
+    Merge4Src src)
+{
+    __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t per = src.jfull + src.mfull;
+    const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x / per);
+    const uint32_t i = __builtin_amdgcn_readfirstlane(blockIdx.x % per);
+    if (g >= src.groups)
+        return;
+    Group4 G(src.n, src.run, g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        G.n[r] = __builtin_amdgcn_readfirstlane(G.n[r]);
+    G.J = __builtin_amdgcn_readfirstlane(G.J);
+    G.M = __builtin_amdgcn_readfirstlane(G.M);
+    const uint4 *P = src.cuts + (uint64_t)g * src.stride();
+    const uint4 *Q = P + src.jfull + 1;
+    uint4 c0, c1;
+    if (!item_cuts(P, Q, G, i, src.jfull, c0, c1))
+        return;
+    const uint32_t L = (uint32_t)src.run;
+    merge4_item_pairs<NT, MAP>(G, c0, c1, src.ksrc + G.start, src.vsrc + G.start, L, 2 * L, 3 * L, src.kdst,
+                               src.vdst, src.out_smp, src.out_map, lds, lane);
 }
 
 // ------------------------------------------ fan-in 4 passes over job tables
@@ -2241,23 +2443,27 @@ uint64_t merge4_cut_bytes(uint64_t n, uint64_t run)
 uint64_t merge4_cut_bytes_max(uint64_t n)
 {
     // four-way passes run while more than two runs remain (n > 2 run), on
-    // runs of 4096 * 4^i or 32768 * 4^i keys
+    // runs of 4096 * 4^i keys, or of a keys or pairs group tile times 4^i
     uint64_t most = 0;
-    for (uint64_t run0 : {(uint64_t)kTile, (uint64_t)kGroupWavesKeys * kTile})
+    for (uint64_t run0 : {(uint64_t)kTile, (uint64_t)kGroupWavesKeys * kTile, (uint64_t)kGroupWavesPairs * kTile})
         for (uint64_t run = run0; n > 2 * run; run *= 4)
             most = std::max(most, merge4_cut_bytes(n, run));
     return most;
 }
 
 hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t n, uint64_t run, void *cuts,
-                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s, KeyMap out_map)
+                                 SampleSet in_smp, SampleSet out_smp, bool cut_phase, hipStream_t s, KeyMap out_map,
+                                 const uint32_t *vsrc, uint32_t *vdst)
 {
     // the cut searches read the samples of the input; runs start at multiples of 4096
     if (n == 0 || run % kTile != 0 || in_smp.f == nullptr || in_smp.l == nullptr || cuts == nullptr)
         return hipErrorInvalidValue;
     const uint64_t groups = (n + 4 * run - 1) / (4 * run);
+    const bool pairs = vsrc != nullptr;
+    if (pairs != (vdst != nullptr))
+        return hipErrorInvalidValue;
     Merge4Src src{ksrc, kdst, n, run, (uint32_t)groups, ab_segments(2 * run), cd_cuts(2 * run),
-                  static_cast<uint4 *>(cuts), in_smp, out_smp, out_map};
+                  static_cast<uint4 *>(cuts), in_smp, out_smp, out_map, vsrc, vdst};
     if (cut_phase) {
         const uint64_t tasks = groups * (src.jfull - 1 + src.mfull);  // kCutsPerWave per wave, four waves per block
         const uint64_t per_block = kCutsPerWave * (256 / kWave);
@@ -2267,7 +2473,18 @@ hipError_t launch_merge4_regular(const uint32_t *ksrc, uint32_t *kdst, uint64_t 
     const uint64_t items = groups * (src.jfull + src.mfull);
     const dim3 grid((uint32_t)((items + kMerge4Waves - 1) / kMerge4Waves)), block(kWave * kMerge4Waves);
     // nontemporal tile traffic only when a pass streams more than the last-level cache
-    const bool nt = tuning().nontemporal && n * 4.0 * 2 > kLastLevelCacheBytes;
+    const bool nt = tuning().nontemporal && n * (pairs ? 8.0 : 4.0) * 2 > kLastLevelCacheBytes;
+    if (pairs) {
+        if (out_map.sign && nt)
+            hipLaunchKernelGGL((k_merge4_pairs<true, true>), grid, block, 0, s, src);
+        else if (out_map.sign)
+            hipLaunchKernelGGL((k_merge4_pairs<false, true>), grid, block, 0, s, src);
+        else if (nt)
+            hipLaunchKernelGGL((k_merge4_pairs<true, false>), grid, block, 0, s, src);
+        else
+            hipLaunchKernelGGL((k_merge4_pairs<false, false>), grid, block, 0, s, src);
+        return hipGetLastError();
+    }
     if (out_map.sign && nt)
         hipLaunchKernelGGL((k_merge4<true, true>), grid, block, 0, s, src);
     else if (out_map.sign)

@@ -55,14 +55,13 @@ def test_tile_run_and_pass_count(lib):
         assert lib.bcf_sort_passes(4096, pairs) == 1
         assert lib.bcf_sort_passes(4097, pairs) == 2
         # Lemma 2: 1 + O(log(n / M)) passes over the data, M the block-sort run:
-        # binary passes for pairs and (default) for keys below 2^25; from 2^25
-        # keys four-way passes while more than two runs remain, then at most
-        # one binary pass
+        # binary passes (default) below 2^25 keys or pairs; from 2^25 four-way
+        # passes while more than two runs remain, then at most one binary pass
         for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**25 - 1, 2**25, 2**26, 2**28, 3 * R + 5 + small,
                   2**32 - 1]:
             m = 4096 if n <= small else R
             runs = -(-n // m)
-            if pairs or n < 2**25:
+            if n < 2**25:
                 want = int(np.ceil(np.log2(runs)))
             else:
                 want = 0
@@ -71,6 +70,7 @@ def test_tile_run_and_pass_count(lib):
                     want += 1
             assert lib.bcf_sort_passes(n, pairs) == 1 + want, (n, pairs)
     assert lib.bcf_sort_passes(2**26, 0) == 1 + 6  # 2^11 runs: five four-way passes and one binary
+    assert lib.bcf_sort_passes(2**28, 1) == 1 + 7  # 2^14 runs of pairs: seven four-way passes
     assert lib.bcf_sort_passes(3 * 4096, 0) == 3  # three runs, default below 2^25 keys: two binary passes
 
 
@@ -103,9 +103,10 @@ def merge4_cut_bytes_max(n):
     """Cut lists of the four-way passes: per group of four runs of L keys, the
     AB cuts (one every 1920 keys of A and B, and both ends) and the CD cuts
     (one every 2048 keys of C and D strictly inside, one unused slot), 16
-    bytes each; the largest over both block-sort run lengths."""
+    bytes each; the largest over the block-sort run lengths (wave tiles, key
+    group tiles, pair group tiles)."""
     most = 0
-    for run0 in (4096, 32768):
+    for run0 in (4096, 32768, 16384):
         run = run0
         while n > 2 * run:
             ab_segments = -(-2 * run // 1920)
@@ -122,13 +123,14 @@ def test_temp_queries(lib):
     st, need = q_sort(lib, 4097)
     assert st == 0 and need >= 4097 * 4 and need % 256 == 0
     st, need = q_sort(lib, 2**26, pairs=True)
-    # two ping-pong arrays (keys, values), one u32 split per merge tile, and
-    # two sets of key samples (every 64-block: first and last; every tile: first and last)
+    # two ping-pong arrays (keys, values), one u32 split per merge tile, two
+    # sets of key samples (every 64-block: first and last; every tile: first
+    # and last), and the four-way cut lists
     tiles, blocks = 2**26 // 4096, 2**26 // 64
-    assert st == 0 and need == 2 * 2**26 * 4 + tiles * 4 + 2 * (2 * blocks * 4 + 2 * tiles * 4)
-    # keys: one ping-pong array, the splits, the samples, and the four-way cut lists
-    st, need = q_sort(lib, 2**26)
     cuts = -(-merge4_cut_bytes_max(2**26) // 256) * 256
+    assert st == 0 and need == 2 * 2**26 * 4 + tiles * 4 + 2 * (2 * blocks * 4 + 2 * tiles * 4) + cuts
+    # keys: one ping-pong array, the splits, the samples, and the cut lists
+    st, need = q_sort(lib, 2**26)
     assert st == 0 and need == 2**26 * 4 + tiles * 4 + 2 * (2 * blocks * 4 + 2 * tiles * 4) + cuts
     assert cuts < 2**26 * 4 // 64
     assert q_sort(lib, 2**32)[0] == 1  # above 2^32 - 1 keys: invalid
@@ -316,7 +318,7 @@ def test_tuning_roundtrip():
         assert bcf.run_keys() == 4096 and bcf.run_keys(pairs=True) == 4096
         assert bcf.sort_passes(1 << 26) == 1 + 14
     with bcf.tuning(block_sort=2):  # 2^14 runs: seven four-way passes
-        assert bcf.sort_passes(1 << 26) == 1 + 7 and bcf.sort_passes(1 << 26, pairs=True) == 1 + 14
+        assert bcf.sort_passes(1 << 26) == 1 + 7 and bcf.sort_passes(1 << 26, pairs=True) == 1 + 7
     assert bcf.get_tuning() == before
     assert bcf.run_keys() == 32768 and bcf.sort_passes(1 << 26) == 1 + 6
     with bcf.tuning(merge_fan_in=2):

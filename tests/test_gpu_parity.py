@@ -453,6 +453,53 @@ def test_four_way_same_as_binary(torch_dev, bcf, nt):
             assert first_diff(a.cpu().numpy(), oracle.sort_u32(make(n))) is None, n
 
 
+# key/value sorts: runs of 4096 (wave tiles) or 16384 (group tiles of four waves)
+FOUR_WAY_PAIR_CASES = [(3 * 4096, 1), (3 * 4096 - 7, 1), (5 * 4096 + 1, 1), (17 * 4096, 1), (61 * 4096 + 100, 1),
+                       (3 * 16384 + 5, 3), (9 * 16384, 3), ((1 << 20) + 3, 0), ((1 << 22) + 12345, 0)]
+
+
+@pytest.mark.parametrize("n,block_sort", FOUR_WAY_PAIR_CASES)
+def test_four_way_pair_passes(torch_dev, bcf, n, block_sort):
+    """Stable key/value sorts whose merge passes take four runs at a time
+    against the oracle; the value is the input index, so equal keys must leave
+    in input order (many, few and no ties)."""
+    torch, dev = torch_dev
+    print(f"four-way pairs: n={n} block_sort={block_sort}", flush=True)
+    with bcf.tuning(block_sort=block_sort, merge_fan_in=4):
+        for dist in ("uniform", "distinct16", "sorted", "reverse", "zipf"):
+            keys, vals = workloads.pairs_u32(dist, n, seed=n % 1000 + 5)
+            ko, vo = bcf.sort_pairs_u32(to_dev(torch, dev, keys), to_dev(torch, dev, vals))
+            wk, wv = oracle.sort_pairs_u32(keys, vals)
+            assert first_diff(ko.cpu().numpy(), wk) is None, (n, block_sort, dist)
+            assert first_diff(vo.cpu().numpy(), wv) is None, (n, block_sort, dist)
+
+
+@pytest.mark.parametrize("nt", [0, 1])
+def test_four_way_pairs_same_as_binary(torch_dev, bcf, nt):
+    """Four-way and binary key/value passes give the same bytes (random values;
+    all keys equal; two key values; a sort large enough for nontemporal
+    traffic)."""
+    torch, dev = torch_dev
+    for n, kmake in [((1 << 21) + 999, lambda n: workloads.keys_u32("uniform", n, seed=9)),
+                     (400000, lambda n: np.full(n, 7, dtype=np.uint32)),
+                     (700001, lambda n: (workloads.draws_u32(4, n) & 1).astype(np.uint32)),
+                     ((1 << 25) + 4097, None)]:
+        print(f"four-way pairs vs binary: n={n} nt={nt}", flush=True)
+        if kmake is None:
+            kd = workloads.draws_u32_torch(12, n, dev)
+        else:
+            kd = to_dev(torch, dev, kmake(n))
+        vd = workloads.draws_u32_torch(13, n, dev)
+        with bcf.tuning(merge_fan_in=4, nontemporal=nt):
+            ak, av = bcf.sort_pairs_u32(kd, vd)
+        with bcf.tuning(merge_fan_in=2, nontemporal=nt):
+            bk, bv = bcf.sort_pairs_u32(kd, vd)
+        assert bool(torch.equal(ak, bk)) and bool(torch.equal(av, bv)), n
+        if kmake is not None:
+            wk, wv = oracle.sort_pairs_u32(kmake(n), vd.cpu().numpy())
+            assert first_diff(ak.cpu().numpy(), wk) is None and first_diff(av.cpu().numpy(), wv) is None, n
+
+
 @pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("variant", [2, 3])
 def test_fused_partition_parity(torch_dev, bcf, fused, variant):
