@@ -1825,7 +1825,8 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
 // half at a time) the tile is back in STRIDED layout, where neighbouring
 // lanes hold neighbouring outputs; every output fetches its value from the
 // input by its rank (reads spread over at most four runs), and keys and
-// values are stored.  The tile takes 128 registers: two waves per SIMD.
+// values are stored.  The tile takes 128 registers, the kernel 230: two
+// waves per SIMD.
 
 // Rank layout of an item's pieces: piece q holds ranks [s[q], s[q + 1]) and
 // starts o[q] keys after the group's first key (s[4] = 4096: no rank reaches
@@ -1907,33 +1908,23 @@ __device__ __forceinline__ void merge4_item_pairs(const Group4 &G, const uint4 &
         copy4<NT, false>(V + o, vdst, gpos, count, none, KeyMap{}, lane);
         return;
     }
-    HalfPieces hp;
-    ItemRanks ir;
-    uint32_t rf[2], rb[2];
-    if (pieces >= 3) {
-        hp = HalfPieces{{oa, oc}, {pa, pc}, {ob + kHalfTile - 1, od + kHalfTile - 1}, {pb, pd}, ~0u};
-        ir = ItemRanks{{0, pa, pa + pb, pa + pb + pc}, {oa, ob, oc, od}};
-        rf[0] = 0, rb[0] = pa, rf[1] = pa + pb, rb[1] = pa + pb + pc;
-    } else {
-        const uint32_t ox = pa ? oa : pb ? ob : pc ? oc : od;
-        const uint32_t nx = pa ? pa : pb ? pb : pc ? pc : pd;
-        const uint32_t oy = (pa && pb) ? ob : ((pa || pb) && pc) ? oc : od;
-        hp = HalfPieces{{ox, 0}, {nx, 0}, {0, oy + kHalfTile - 1}, {0, count - nx}, 0u};
-        ir = ItemRanks{{0, nx, kTile, kTile}, {ox, oy, 0, 0}};
-        rf[0] = 0, rb[0] = 0, rf[1] = 0, rb[1] = nx;
-    }
+    // every item of two or more pieces takes the four-piece layout and both
+    // networks (empty pieces are padding): one code path, which keeps the
+    // kernel at 256 registers, two waves per SIMD (a separate two-piece path
+    // without the first network spilled at that bound)
+    const HalfPieces hp{{oa, oc}, {pa, pc}, {ob + kHalfTile - 1, od + kHalfTile - 1}, {pb, pd}, ~0u};
+    const ItemRanks ir{{0, pa, pa + pb, pa + pb + pc}, {pa ? oa : ob, ob, oc, od}};
+    const uint32_t rf[2] = {0, pa + pb}, rb[2] = {pa, pa + pb + pc};
     Lines<true> t;
     load_item_pairs(t, K, hp, rf, rb, lane);
-    if (pieces >= 3) {
-        // both halves merged at once, back to STRIDED, the CD half complemented back
-        half_clean<kLine / 4, -1, true>(t);
-        to_blocked_half(t, lds, lane);
-        half_clean<kLine / 2, -1, true>(t);
-        to_strided_half(t, lds, lane);
+    // both halves merged at once, back to STRIDED, the CD half complemented back
+    half_clean<kLine / 4, -1, true>(t);
+    to_blocked_half(t, lds, lane);
+    half_clean<kLine / 2, -1, true>(t);
+    to_strided_half(t, lds, lane);
 #pragma unroll
-        for (int r = kLine / 2; r < kLine; ++r)
-            t.e[r] = elem_of(bits_of(t.e[r]) ^ kPayloadMask);
-    }
+    for (int r = kLine / 2; r < kLine; ++r)
+        t.e[r] = elem_of(bits_of(t.e[r]) ^ kPayloadMask);
     half_clean<kLine / 2, -1, true>(t);
     to_blocked_half(t, lds, lane);
     half_clean<kLine / 2, -1, true>(t);
@@ -1981,7 +1972,7 @@ __device__ __forceinline__ void merge4_item_pairs(const Group4 &G, const uint4 &
 
 // One wave per merge item, as k_merge4.
 template <bool NT, bool MAP = false>
-__global__ __launch_bounds__(kWave *kMerge4Waves) void k_merge4_pairs(
+__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(2))) void k_merge4_pairs(
     Merge4Src src)
 {
     __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
