@@ -319,7 +319,7 @@ uint32_t bcf_run_keys(int pairs);
 
 /* Passes over the data in HBM of a sort of n keys under the current tuning:
  * the block sort plus the merge passes (the paper's Lemma 2: O(1 + log(N/M))
- * scans).  With binary passes (fan-in 2, or below 2^25 keys under the
+ * scans).  With binary passes (fan-in 2, or below 2^24 keys under the
  * default) there are ceil(log2(R)) merge passes for R = ceil(n /
  * bcf_run_keys(pairs)) runs.  With fan-in 4 (keys or pairs) a pass merges
  * groups of four runs while more than two remain, two levels of the paper's
@@ -368,8 +368,9 @@ typedef struct {
     int32_t merge_fan_in;      /* runs merged per group by a merge pass of the sorts
                                   (bcf_sort_u32, bcf_sort_pairs_u32 and the int32 / float
                                   forms) and of the keys-only segmented sorts (device- or
-                                  host-planned): 0 (default) 4 for at least 2^25 keys in
-                                  total, else 2; 4 or 2 for every size.  A segment takes
+                                  host-planned): 0 (default) 4 for key/value sorts, for sorts
+                                  of at least 2^24 keys and for segmented sorts of at least
+                                  2^25 keys in total, else 2; 4 or 2 for every size.  A segment takes
                                   four-way steps while more than two of its runs remain, then
                                   a binary one.  Four-way passes of the sorts need
                                   sampled_partition (else 2 is used).  Key/value segmented

@@ -225,7 +225,7 @@ std::vector<uint32_t> sort_fan_ins(bool pairs, uint64_t n, const Tuning &tu)
     if (n == 0)
         return fi;
     const uint64_t run0 = sort_run_keys(pairs, n, tu);
-    const bool want4 = tu.merge_fan_in == 4 || (tu.merge_fan_in == 0 && n >= kAutoFourWayMinN);
+    const bool want4 = tu.merge_fan_in == 4 || (tu.merge_fan_in == 0 && (pairs || n >= kAutoFourWayMinKeys));
     const bool four = want4 && tu.sampled_partition;
     for (uint64_t runs = (n + run0 - 1) / run0; runs > 1;) {
         const uint32_t k = (four && runs > 2) ? 4 : 2;

@@ -166,12 +166,17 @@ hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, u
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);
 
-// Sorts of at least this many keys take four-way merge passes under the
-// default (auto) fan-in.  Below it a pass's data mostly stays in the 256 MiB
-// last-level cache, binary passes stream from there, and halving their
-// number does not pay for the four-way pass's second launch and heavier
-// merge (measured: binary passes faster or equal up to 2^24 uniform keys).
+// Segmented sorts of at least this many keys in all take four-way merge
+// steps under the default (auto) fan-in.
 constexpr uint64_t kAutoFourWayMinN = 1ull << 25;
+// Sorts of keys take four-way merge passes under the default fan-in from
+// this many keys (uniform keys, binary / four-way: 2^18 0.072 / 0.076 ms,
+// 2^20 0.102 / 0.104, 2^22 0.168 / 0.156, 2^23 0.196 / 0.198, 2^24 0.365 /
+// 0.311, 2^25 0.709 / 0.558); below it a pass's data stays in the 256 MiB
+// last-level cache and halving the passes barely pays for the second launch
+// and the heavier merge.  Key/value sorts take them at every size (2^18
+// pairs 0.169 / 0.135 ms, 2^20 0.197 / 0.163, 2^24 1.021 / 0.702).
+constexpr uint64_t kAutoFourWayMinKeys = 1ull << 24;
 
 // Current process-wide tuning (see bcf_tuning in bcf.h); a copy.
 struct Tuning {

@@ -55,13 +55,14 @@ def test_tile_run_and_pass_count(lib):
         assert lib.bcf_sort_passes(4096, pairs) == 1
         assert lib.bcf_sort_passes(4097, pairs) == 2
         # Lemma 2: 1 + O(log(n / M)) passes over the data, M the block-sort run:
-        # binary passes (default) below 2^25 keys or pairs; from 2^25 four-way
-        # passes while more than two runs remain, then at most one binary pass
-        for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**25 - 1, 2**25, 2**26, 2**28, 3 * R + 5 + small,
-                  2**32 - 1]:
+        # binary passes (default) below 2^24 keys; from 2^24 keys, and for pairs
+        # at every size, four-way passes while more than two runs remain, then
+        # at most one binary pass
+        for n in [2**12 + 1, 2**16, small, small + 1, 2**20, 2**24 - 1, 2**24, 2**25, 2**26, 2**28,
+                  3 * R + 5 + small, 2**32 - 1]:
             m = 4096 if n <= small else R
             runs = -(-n // m)
-            if n < 2**25:
+            if not pairs and n < 2**24:
                 want = int(np.ceil(np.log2(runs)))
             else:
                 want = 0
@@ -71,7 +72,8 @@ def test_tile_run_and_pass_count(lib):
             assert lib.bcf_sort_passes(n, pairs) == 1 + want, (n, pairs)
     assert lib.bcf_sort_passes(2**26, 0) == 1 + 6  # 2^11 runs: five four-way passes and one binary
     assert lib.bcf_sort_passes(2**28, 1) == 1 + 7  # 2^14 runs of pairs: seven four-way passes
-    assert lib.bcf_sort_passes(3 * 4096, 0) == 3  # three runs, default below 2^25 keys: two binary passes
+    assert lib.bcf_sort_passes(3 * 4096, 0) == 3  # three runs, default below 2^24 keys: two binary passes
+    assert lib.bcf_sort_passes(3 * 4096, 1) == 2  # three runs of pairs: one four-way pass
 
 
 def test_pass_count_binary_fan_in(lib):
@@ -324,7 +326,7 @@ def test_tuning_roundtrip():
     with bcf.tuning(merge_fan_in=2):
         assert bcf.sort_passes(1 << 26) == 1 + 11
     # default block sort: wave tiles up to 2^19 keys, group tiles above; binary
-    # passes below 2^25 keys
+    # passes below 2^24 keys
     assert bcf.sort_passes(1 << 19) == 1 + 7 and bcf.sort_passes((1 << 19) + 1) == 1 + 5
     with bcf.tuning(merge_fan_in=4):  # 128 runs -> 32 -> 8 -> 2 -> 1; 17 runs -> 5 -> 2 -> 1
         assert bcf.sort_passes(1 << 19) == 1 + 4 and bcf.sort_passes((1 << 19) + 1) == 1 + 3
