@@ -398,6 +398,8 @@ def main():
                     help="only the distribution step at 2^26 keys in 256 runs (one JSON object)")
     ap.add_argument("--block-sort-ablation", action="store_true",
                     help="only the block-sort ablation at 2^26 keys (one JSON object)")
+    ap.add_argument("--pairs", action="store_true",
+                    help="only the 2^28 stable key/value sorts, uniform and Zipf keys (one JSON object)")
     ap.add_argument("--reps", type=int, default=5, help="repetitions of the ablation timings")
     ap.add_argument(
         "--copy-calibration",
@@ -429,6 +431,15 @@ def main():
             torch.cuda.synchronize()
             del a, b
         print(json.dumps(bench_distribution(bcf, workloads, torch, dev)), flush=True)
+        return
+    if args.pairs:
+        import torch
+
+        import paper_1306_5076_amd as bcf
+        import workloads
+
+        rec = bench_pairs(bcf, workloads, torch, torch.device("cuda:0"), steps=args.steps, warmup=args.warmup)
+        print(json.dumps(rec), flush=True)
         return
     if args.block_sort_ablation:
         import torch

@@ -169,7 +169,7 @@ def _is(kind: str, name: str) -> bool:
     return False
 
 
-def trace_markdown(directory: str, command: str, title: str, n_keys: int | None = None) -> str:
+def trace_markdown(directory: str, command: str, title: str, n_keys: int | None = None, elem_bytes: int = 4) -> str:
     stats = _rows(directory, "kernel_stats.csv")
     lines = [f"# {title}", "", "Command (repository root on the GPU box, library built in-tree beforehand):", "",
              "    " + command.replace("\n", "\n    "), "", f"Kernel source hash: `{kernel_source_hash()}`", "",
@@ -198,11 +198,11 @@ def trace_markdown(directory: str, command: str, title: str, n_keys: int | None 
                       "| launch | kernel | median us |" + (" algorithmic GB/s |" if n_keys else ""),
                       "|---|---|---|" + ("---|" if n_keys else "")]
             med = statistics.median(s["block"] for s in full) / 1e3
-            gbs = f" {2 * 4 * n_keys / (med * 1e-6) / 1e9:.0f} |" if n_keys else ""
+            gbs = f" {2 * elem_bytes * n_keys / (med * 1e-6) / 1e9:.0f} |" if n_keys else ""
             lines.append(f"| 0 | block sort | {med:.1f} |{gbs}")
             for i in range(npass):
                 med = statistics.median(s["merges"][i] for s in full) / 1e3
-                gbs = f" {2 * 4 * n_keys / (med * 1e-6) / 1e9:.0f} |" if n_keys else ""
+                gbs = f" {2 * elem_bytes * n_keys / (med * 1e-6) / 1e9:.0f} |" if n_keys else ""
                 lines.append(f"| {i + 1} | merge pass {i + 1} | {med:.1f} |{gbs}")
     return "\n".join(lines) + "\n"
 
@@ -216,6 +216,7 @@ def main(argv=None):
     t.add_argument("--command", default="")
     t.add_argument("--title", default="Kernel trace")
     t.add_argument("--n", type=int, default=None, help="keys per sort, for algorithmic GB/s")
+    t.add_argument("--elem-bytes", type=int, default=4, help="bytes per element moved (keys 4, key/value pairs 8)")
     f = sub.add_parser("traffic")
     f.add_argument("fetch_dir")
     f.add_argument("write_dir")
@@ -237,7 +238,7 @@ def main(argv=None):
         with open(a.out, "w") as fh:
             fh.write(counters_markdown(a.traffic_json, a.lds_json, a.algorithmic_bytes))
     elif a.what == "trace":
-        text = trace_markdown(a.dir, a.command, a.title, a.n)
+        text = trace_markdown(a.dir, a.command, a.title, a.n, a.elem_bytes)
         with open(a.out, "w") as fh:
             fh.write(text)
     else:
