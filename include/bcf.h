@@ -174,10 +174,12 @@ bcf_status bcf_merge_runs_host(const uint32_t *keys_in, const uint32_t *vals_in,
  * Sort every segment [seg_offsets[s], seg_offsets[s+1]) of keys_in
  * independently (segments of up to 4096 keys in one wave tile, longer ones
  * block-sorted and then merged within the segment; all segments in one
- * block-sort launch and one launch per merge level).
+ * block-sort launch per tile kind and one set of launches per merge level).
+ * A segment's runs are merged four at a time while more than two remain
+ * (bcf_tuning.merge_fan_in), then pairwise.
  *   seg_offsets  DEVICE, nseg+1 entries (u64)
  * Planned on the device, with the temp and capacity conventions of
- * bcf_merge_runs.
+ * bcf_merge_runs: the temp size does not depend on the tuning.
  */
 bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const uint64_t *seg_offsets,
                               uint32_t nseg, void *temp, uint64_t *temp_bytes, void *stream);
@@ -185,7 +187,8 @@ bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const
 /*
  * Stable segmented sort of key/value pairs: every segment is sorted by key,
  * equal keys keeping their input order.  Same conventions as
- * bcf_segmented_sort, with values carried alongside the keys.
+ * bcf_segmented_sort, with values carried alongside the keys (merged
+ * pairwise).
  */
 bcf_status bcf_segmented_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
                                     uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg,
