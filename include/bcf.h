@@ -187,8 +187,7 @@ bcf_status bcf_segmented_sort(const uint32_t *keys_in, uint32_t *keys_out, const
 /*
  * Stable segmented sort of key/value pairs: every segment is sorted by key,
  * equal keys keeping their input order.  Same conventions as
- * bcf_segmented_sort, with values carried alongside the keys (merged
- * pairwise).
+ * bcf_segmented_sort, with values carried alongside the keys.
  */
 bcf_status bcf_segmented_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
                                     uint32_t *vals_out, const uint64_t *seg_offsets, uint32_t nseg,
@@ -370,14 +369,14 @@ typedef struct {
                                   partition launch first */
     int32_t merge_fan_in;      /* runs merged per group by a merge pass of the sorts
                                   (bcf_sort_u32, bcf_sort_pairs_u32 and the int32 / float
-                                  forms) and of the keys-only segmented sorts (device- or
-                                  host-planned): 0 (default) 4 for key/value sorts, for sorts
+                                  forms) and of the segmented sorts (device- or host-planned,
+                                  keys or pairs): 0 (default) 4 for key/value sorts, for sorts
                                   of at least 2^24 keys and for segmented sorts of at least
                                   2^25 keys in total, else 2; 4 or 2 for every size.  A segment takes
                                   four-way steps while more than two of its runs remain, then
                                   a binary one.  Four-way passes of the sorts need
-                                  sampled_partition (else 2 is used).  Key/value segmented
-                                  sorts and bcf_merge_runs merge pairs of runs */
+                                  sampled_partition (else 2 is used).  bcf_merge_runs and the
+                                  bucket merge of bcf_sort_u32_pb merge pairs of runs */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);

@@ -13,7 +13,7 @@ ones the kernels expose at run time:
 * group_min_keys    -- (segmented sorts) the same block-size choice per
                        segment: the segment length from which a segment is
                        block-sorted in group tiles instead of wave tiles;
-* merge_fan_in      -- (sorts of keys or pairs, keys-only segmented sorts) runs merged per
+* merge_fan_in      -- (sorts and segmented sorts, keys or pairs) runs merged per
                        pass: 2 (binary passes), 4 (four-way passes, two merge
                        levels per read and write of the data), or 0 for the
                        size-based default;

@@ -354,7 +354,7 @@ bcf_status sort_typed(int kind, bool pairs, const uint32_t *kin, const uint32_t 
 struct MergePass {
     std::vector<MergeJob> jobs;
     std::vector<uint32_t> tile_job;
-    // fan-in 4 merges (keys only): the jobs, and the totals of their cut
+    // fan-in 4 merges: the jobs, and the totals of their cut
     // searches, item slots and cut records (the maps from searches and slots
     // to jobs, and the records, are written on the device)
     std::vector<Merge4Job> jobs4;
@@ -511,13 +511,14 @@ bcf_status launch_tables(Bufs kb, Bufs vb, char *temp, const TablePlan &P, hipSt
             // the fan-in 4 merges of this pass (other segments than its binary
             // jobs): maps, cut searches, merges
             for (int phase = 0; phase < 3; ++phase) {
-                static const char *const names[3] = {"map4_keys_table", "cuts4_keys_table", "merge4_keys_table"};
-                ProfScope ps(names[phase], s, phase == 2 ? 8.0 * mp.keys4 : 0.0);
+                static const char *const names[2][3] = {{"map4_keys_table", "cuts4_keys_table", "merge4_keys_table"},
+                                                        {"map4_pairs_table", "cuts4_pairs_table", "merge4_pairs_table"}};
+                ProfScope ps(names[pairs][phase], s, phase == 2 ? 2.0 * eb * mp.keys4 : 0.0);
                 BCF_TRY(dev_status(launch_merge4_table(
                     kb, reinterpret_cast<const Merge4Job *>(temp + L.jobs4_off[p]), (uint32_t)mp.jobs4.size(),
                     reinterpret_cast<uint32_t *>(temp + L.task_off[p]), mp.tasks4,
                     reinterpret_cast<uint32_t *>(temp + L.item_off[p]), mp.items4, temp + L.cuts4_off[p], mp.keys4,
-                    phase, s)));
+                    phase, s, nullptr, pairs ? vb : Bufs{nullptr, nullptr, nullptr})));
             }
         }
         if (mp.tile_job.empty())
@@ -589,12 +590,13 @@ std::vector<uint8_t> seg_fan_ins(uint64_t runs, bool four)
     return fi;
 }
 
-// Whether the merges of a keys-only segmented sort of n keys use fan-in 4
+// Whether the merges of a segmented sort of n keys (or pairs) use fan-in 4
 // steps under the tuning knob merge_fan_in (0: from 2^25 keys, where a pass
 // streams more than the last-level cache holds).
 bool seg_four_way(bool pairs, uint64_t n, int fan_in_knob)
 {
-    return !pairs && (fan_in_knob == 4 || (fan_in_knob == 0 && n >= kAutoFourWayMinN));
+    (void)pairs;
+    return fan_in_knob == 4 || (fan_in_knob == 0 && n >= kAutoFourWayMinN);
 }
 
 bcf_status plan_segmented(const uint64_t *off, uint32_t nseg, bool pairs, uint64_t gmin_knob, int fan_in_knob,

@@ -160,9 +160,12 @@ __host__ __device__ constexpr uint32_t merge4_records(uint32_t J, uint32_t M) { 
 // With counts_dev set the three counts come from device words (jobs,
 // searches, item slots) and njobs / tasks / items are their bounds: the
 // launches then stride over the counts with grids sized by the chip.
+// With vb.in set the merges carry values (stable key/value jobs, values laid
+// out like the keys in vb's three buffers).
 hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, uint32_t *task_job, uint32_t tasks,
                                uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, int phase,
-                               hipStream_t s, const uint32_t *counts_dev = nullptr);
+                               hipStream_t s, const uint32_t *counts_dev = nullptr,
+                               Bufs vb = Bufs{nullptr, nullptr, nullptr});
 hipError_t launch_check_runs(const uint32_t *keys, const uint64_t *run_ends_dev, uint32_t k,
                              uint64_t n, uint32_t *flag, hipStream_t s);
 

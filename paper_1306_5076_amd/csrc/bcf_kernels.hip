@@ -2015,6 +2015,7 @@ struct Merge4Table {
     uint32_t njobs, tasks, items;  // bounds when counts is set
     uint4 *cuts;
     const uint32_t *counts;        // device words (jobs, searches, item slots), or nullptr
+    Bufs vb;                       // key/value jobs: the values' buffers (vb.in == nullptr for keys)
     // the counts of a plan made on the device, never past the bounds the grid covers
     __device__ void resolve()
     {
@@ -2162,6 +2163,36 @@ __device__ __forceinline__ void merge4_table_item(const Merge4Table &src, uint32
                            buf_out(src.kb, sel >> 16), none, KeyMap{}, lds, lane);
 }
 
+// One item slot of a key/value table pass (values in src.vb, laid out like
+// the keys).
+template <bool NT>
+__device__ __forceinline__ void merge4_table_item_pairs(const Merge4Table &src, uint32_t item, uint32_t *lds,
+                                                        uint32_t lane)
+{
+    const uint32_t jid = __builtin_amdgcn_readfirstlane(src.item_job[item]);
+    const Merge4Job &jr = src.jobs[jid];
+    Merge4Job jb;
+    jb.start = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(jr.start >> 32)) << 32) |
+               __builtin_amdgcn_readfirstlane((uint32_t)jr.start);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        jb.n[r] = __builtin_amdgcn_readfirstlane(jr.n[r]);
+    jb.cut_off = __builtin_amdgcn_readfirstlane(jr.cut_off);
+    jb.item_off = __builtin_amdgcn_readfirstlane(jr.item_off);
+    const uint32_t sel = __builtin_amdgcn_readfirstlane(((uint32_t)jr.dst << 16) | jr.src);
+    const Group4 G = group_of_job(jb);
+    const uint4 *P = src.cuts + jb.cut_off;
+    const uint4 *Q = P + G.J + 1;
+    uint4 c0, c1;
+    if (!item_cuts(P, Q, G, item - jb.item_off, G.J, c0, c1))
+        return;
+    const uint32_t n01 = G.n[0] + G.n[1];
+    const SampleSet none{nullptr, nullptr, nullptr, nullptr};
+    merge4_item_pairs<NT, false>(G, c0, c1, buf_in(src.kb, sel & 0xffff) + G.start,
+                                 buf_in(src.vb, sel & 0xffff) + G.start, G.n[0], n01, n01 + G.n[2],
+                                 buf_out(src.kb, sel >> 16), buf_out(src.vb, sel >> 16), none, KeyMap{}, lds, lane);
+}
+
 // Merges of a table pass: one wave per item slot, the grid striding over the
 // slots when it is smaller (plans made on the device size it by the chip).
 template <bool NT>
@@ -2175,6 +2206,20 @@ __global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_pe
         // the lane index re-derived per item keeps the compiler from hoisting
         // the per-register addresses out of the loop (registers held across it)
         merge4_table_item<NT>(src, item, lds, opaque(lane));
+        wave_lds_fence();  // the next item writes the LDS this one read
+    }
+}
+
+// The same for key/value table passes (two waves per SIMD, as k_merge4_pairs).
+template <bool NT>
+__global__ __launch_bounds__(kWave *kMerge4Waves) __attribute__((amdgpu_waves_per_eu(2))) void k_merge4_table_pairs(
+    Merge4Table src)
+{
+    __shared__ __align__(16) uint32_t lds[kHalfLdsWords];
+    src.resolve();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    for (uint32_t item = blockIdx.x; item < src.items; item += gridDim.x) {
+        merge4_table_item_pairs<NT>(src, item, lds, opaque(lane));
         wave_lds_fence();  // the next item writes the LDS this one read
     }
 }
@@ -2503,9 +2548,10 @@ static uint32_t resident_blocks(K kernel, int threads, uint64_t need)
 
 hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, uint32_t *task_job, uint32_t tasks,
                                uint32_t *item_job, uint32_t items, void *cuts, uint64_t keys, int phase, hipStream_t s,
-                               const uint32_t *counts_dev)
+                               const uint32_t *counts_dev, Bufs vb)
 {
-    Merge4Table src{kb, jobs, task_job, item_job, njobs, tasks, items, static_cast<uint4 *>(cuts), counts_dev};
+    Merge4Table src{kb, jobs, task_job, item_job, njobs, tasks, items, static_cast<uint4 *>(cuts), counts_dev, vb};
+    const bool pairs = vb.in != nullptr;
     if (njobs == 0)
         return hipSuccess;
     const bool dev_counts = counts_dev != nullptr;
@@ -2529,8 +2575,20 @@ hipError_t launch_merge4_table(Bufs kb, const Merge4Job *jobs, uint32_t njobs, u
     }
     if (items == 0)
         return hipSuccess;
-    const bool nt = tuning().nontemporal && keys * 4.0 * 2 > kLastLevelCacheBytes;
+    const bool nt = tuning().nontemporal && keys * (pairs ? 8.0 : 4.0) * 2 > kLastLevelCacheBytes;
     const dim3 block(kWave * kMerge4Waves);
+    if (pairs) {
+        if (nt) {
+            const uint32_t grid =
+                dev_counts ? resident_blocks(k_merge4_table_pairs<true>, kWave * kMerge4Waves, items) : items;
+            hipLaunchKernelGGL(k_merge4_table_pairs<true>, dim3(grid), block, 0, s, src);
+        } else {
+            const uint32_t grid =
+                dev_counts ? resident_blocks(k_merge4_table_pairs<false>, kWave * kMerge4Waves, items) : items;
+            hipLaunchKernelGGL(k_merge4_table_pairs<false>, dim3(grid), block, 0, s, src);
+        }
+        return hipGetLastError();
+    }
     if (nt) {
         const uint32_t grid = dev_counts ? resident_blocks(k_merge4_table<true>, kWave * kMerge4Waves, items) : items;
         hipLaunchKernelGGL(k_merge4_table<true>, dim3(grid), block, 0, s, src);

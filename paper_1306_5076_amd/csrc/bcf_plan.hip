@@ -470,7 +470,7 @@ struct PlanSpec {
     uint32_t grun;
     bool pairs;
     uint32_t noff;  // offsets read (validity check)
-    uint32_t four;  // segments: fan-in 4 steps (PlanArgs::four); the areas are reserved for every keys-only plan
+    uint32_t four;  // segments: fan-in 4 steps (PlanArgs::four); the areas are reserved for every segmented plan
 };
 
 // Bounds of a plan for at most cap keys.
@@ -478,7 +478,7 @@ struct PlanBounds {
     uint32_t PM;
     uint64_t wb, gb;
     uint64_t jb[kMaxPlanPasses], tb[kMaxPlanPasses];
-    // fan-in 4 steps (keys-only segments): passes, jobs per pass, and cut
+    // fan-in 4 steps (segments): passes, jobs per pass, and cut
     // searches / item slots / cut records of any one pass
     uint32_t PM4;
     uint64_t j4b[kMaxPlan4Passes];
@@ -504,7 +504,7 @@ PlanBounds plan_bounds(const PlanSpec &sp, uint64_t cap)
         b.gb = (cap + sp.grun - 1) / sp.grun + sp.G;
         for (uint32_t j = 1; j <= b.PM; ++j)
             b.jb[j - 1] = ((tiles + sp.G) >> j) + 1 + sp.G;
-        if (!sp.pairs) {
+        {
             // segment g has at most ceil(len_g / 4096) runs, so step j (of four
             // runs of 4^(j-1) each) at most (tiles + G) / 4^j + G jobs; a job of
             // t keys takes at most t / kAbStep + 1 searches and item slots, and
@@ -762,10 +762,11 @@ bcf_status plan_and_run(const PlanSpec &sp, const uint64_t *off_dev, Bufs kb, Bu
         // the fan-in 4 jobs of the pass (segments still taking fan-in 4 steps),
         // then its binary jobs (the other segments); they touch disjoint ranges
         for (int phase = 0; j < P4 && phase < 3; ++phase) {
-            static const char *const names[3] = {"map4_keys_table", "cuts4_keys_table", "merge4_keys_table"};
-            void *p = prof_begin(names[phase], s, 0.0);
+            static const char *const names[2][3] = {{"map4_keys_table", "cuts4_keys_table", "merge4_keys_table"},
+                                                    {"map4_pairs_table", "cuts4_pairs_table", "merge4_pairs_table"}};
+            void *p = prof_begin(names[sp.pairs][phase], s, 0.0);
             const hipError_t e = launch_merge4_table(kb, a.jobs4[j], a.j4b[j], tmap4, a.t4b, imap4, a.i4b,
-                                                     temp + L.cuts4, cap, phase, s, a.c4[j]);
+                                                     temp + L.cuts4, cap, phase, s, a.c4[j], vb);
             prof_end(p);
             BCF_PLAN_TRY(dev(e));
         }
@@ -844,7 +845,7 @@ bcf_status segmented_device(bool pairs, const uint32_t *kin, const uint32_t *vin
     sp.pairs = pairs;
     sp.noff = nseg + 1;
     const int fan_in = tuning().merge_fan_in;
-    sp.four = pairs ? 0u : (fan_in == 4 ? 1u : (fan_in == 0 ? 2u : 0u));
+    sp.four = fan_in == 4 ? 1u : (fan_in == 0 ? 2u : 0u);
     return planned_call(sp, sp, off, kin, vin, kout, vout, temp, temp_bytes, s);
 }
 

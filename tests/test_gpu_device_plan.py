@@ -96,20 +96,34 @@ def test_segmented_device_offsets(env, sizes, pairs):
     [4096 * 3 + 5], [4096 * 5 + 1], [4096 * 9, 7, 0, 4096 * 17 + 100], [32768 * 3 + 11, 32768 * 5, 1 << 20],
     [1 << 18, 1 << 18, 3, 200000], [12345] * 40 + [4096 * 4 + 1] * 5])
 @pytest.mark.parametrize("dist", ["uniform", "distinct16", "zipf"])
-def test_segmented_device_offsets_four_way(env, sizes, dist):
+@pytest.mark.parametrize("pairs", [False, True])
+def test_segmented_device_offsets_four_way(env, sizes, dist, pairs):
     """Device-planned segmented sort with fan-in 4 merge steps (four runs of a
     segment per job while more than two remain, then binary): segments of 3,
     5, 9, 17, ... runs, wave and group tiles, ties; equal to the oracle and to
     the host-planned sort under the same tuning."""
     torch, dev, bcf = env
-    print(f"segmented device offsets four-way: sizes={sizes[:6]} dist={dist}", flush=True)
+    print(f"segmented device offsets four-way: sizes={sizes[:6]} dist={dist} pairs={pairs}", flush=True)
     offs = workloads.segment_offsets(np.asarray(sizes))
-    keys = workloads.keys_u32(dist, int(offs[-1]), seed=len(sizes) + 5)
+    n = int(offs[-1])
+    keys = workloads.keys_u32(dist, n, seed=len(sizes) + 5)
     kin = torch.from_numpy(keys).to(dev)
     doff = _dev_offsets(torch, dev, offs)
-    want = oracle.segmented_sort(keys, offs)
+    if pairs:
+        vals = np.arange(n, dtype=np.uint32)  # value = input index: ties must keep their order
+        vin = torch.from_numpy(vals).to(dev)
+        wk, wv = oracle.segmented_sort_threads(keys, offs, THREADS, vals=vals)
+    else:
+        want = oracle.segmented_sort(keys, offs)
     for gmin in (0, 1 << 40):  # group tiles for long segments, or wave tiles only
         with bcf.tuning(merge_fan_in=4, group_min_keys=gmin):
+            if pairs:
+                dk, dv = bcf.segmented_sort(kin, doff, vals=vin)
+                hk, hv = bcf.segmented_sort(kin, offs, vals=vin)
+                for gk, gv in ((dk, dv), (hk, hv)):
+                    assert np.array_equal(gk.cpu().numpy(), wk), (sizes[:6], dist, gmin)
+                    assert np.array_equal(gv.cpu().numpy(), wv), (sizes[:6], dist, gmin)
+                continue
             got = bcf.segmented_sort(kin, doff).cpu().numpy()
             host = bcf.segmented_sort(kin, offs).cpu().numpy()
         assert np.array_equal(got, want), (sizes[:6], dist, gmin)
@@ -131,7 +145,7 @@ def test_segmented_device_offsets_full_size(env):
     assert np.array_equal(out.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("pairs,fan_in", [(False, 0), (False, 4), (True, 0)])
+@pytest.mark.parametrize("pairs,fan_in", [(False, 0), (False, 4), (True, 0), (True, 4)])
 def test_segmented_graph_replay_with_new_offsets(env, pairs, fan_in):
     """One captured graph of the device-planned segmented sort, replayed with
     new segment offsets (same total) written into the same device tensor:

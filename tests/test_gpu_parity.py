@@ -665,6 +665,27 @@ def test_segmented_four_way_vs_oracle(torch_dev, bcf, sizes, dist):
         assert first_diff(got, oracle.segmented_sort(keys, offs)) is None, (sizes, dist, gmin)
 
 
+@pytest.mark.parametrize("sizes", [
+    [4096 * 3 + 5], [4096 * 9, 7, 0, 4096 * 17 + 100], [16384 * 3 + 11, 16384 * 5, 1 << 20],
+    [12345] * 20 + [4096 * 4 + 1] * 3])
+@pytest.mark.parametrize("dist", ["uniform", "distinct16", "zipf"])
+def test_segmented_pairs_four_way_vs_oracle(torch_dev, bcf, sizes, dist):
+    """Host-planned stable key/value segmented sort with fan-in 4 steps: the
+    value is the input index, so equal keys must keep their order."""
+    torch, dev = torch_dev
+    print(f"segmented pairs four-way: sizes={sizes[:4]} dist={dist}", flush=True)
+    offs = workloads.segment_offsets(sizes)
+    n = int(offs[-1])
+    keys = workloads.keys_u32(dist, n, seed=len(sizes) + 13)
+    vals = np.arange(n, dtype=np.uint32)
+    wk, wv = oracle.segmented_sort_threads(keys, offs, ORACLE_THREADS, vals=vals)
+    for gmin in (0, 1 << 40):
+        with bcf.tuning(merge_fan_in=4, group_min_keys=gmin):
+            ko, vo = bcf.segmented_sort(to_dev(torch, dev, keys), offs, vals=to_dev(torch, dev, vals))
+        assert first_diff(ko.cpu().numpy(), wk) is None, (sizes[:4], dist, gmin)
+        assert first_diff(vo.cpu().numpy(), wv) is None, (sizes[:4], dist, gmin)
+
+
 def test_segmented_four_way_plan_graph_and_tuning(torch_dev, bcf):
     """A plan uploaded with fan-in 4 steps replays in a graph on new data and
     keeps its fan-in when executed under another tuning."""
