@@ -376,7 +376,8 @@ typedef struct {
                                   four-way steps while more than two of its runs remain, then
                                   a binary one.  Four-way passes of the sorts need
                                   sampled_partition (else 2 is used).  bcf_merge_runs and the
-                                  bucket merge of bcf_sort_u32_pb merge pairs of runs */
+                                  bucket merge of bcf_sort_u32_pb take four-way steps under 4,
+                                  and under 0 when a merge (a bucket) has at least 16 runs */
 } bcf_tuning;
 
 void bcf_get_tuning(bcf_tuning *out);

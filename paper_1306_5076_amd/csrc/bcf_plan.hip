@@ -154,11 +154,19 @@ __device__ GroupInfo group_info(const PlanArgs &a, uint32_t g)
             gi.nruns = a.s;
         }
         const bool pivot = a.kind == kKindBuckets && a.pivot && (g & 1u);
-        gi.merges = pivot ? 0 : ceil_log2_u(gi.nruns);
+        // explicit runs: fan-in 4 steps only when the host asked for them (it
+        // plans the pass count, and the extra copy of an in-place merge, the same way)
+        uint32_t r = gi.nruns;
+        while (a.four == 1 && !pivot && r > 2 && gi.steps4 < a.PM4) {
+            r = (r + 3) / 4;
+            ++gi.steps4;
+        }
+        gi.merges = pivot ? 0 : ceil_log2_u(r);
+        const uint32_t levels = gi.steps4 + gi.merges;
         if (a.kind == kKindRuns)
-            gi.passes = gi.merges + (a.extra_copy ? 1 : 0);
+            gi.passes = levels + (a.extra_copy ? 1 : 0);
         else
-            gi.passes = gi.merges ? gi.merges : 1;  // a group of one run (or a pivot bucket) is copied
+            gi.passes = levels ? levels : 1;  // a group of one run (or a pivot bucket) is copied
         gi.start = a.off[gi.first];
         gi.end = a.off[gi.first + gi.nruns];
     }
@@ -424,7 +432,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_jobs4(PlanArgs a)
     for (int t = 0; t < 4; ++t)
         m.n[t] = (uint32_t)(b[t + 1] - b[t]);
     m.cut_off = m.item_off = m.task_off = 0;
-    m.src = pass == 1 ? buf_after(gi, 0) : buf_after(gi, pass - 1);
+    // the first pass of explicit runs reads the caller's input
+    m.src = pass == 1 ? (gi.run0 ? buf_after(gi, 0) : (uint16_t)kBufIn) : buf_after(gi, pass - 1);
     m.dst = buf_after(gi, pass);
     a.jobs4[j][slot] = m;
     const uint32_t J = merge4_ab_segments((uint64_t)m.n[0] + m.n[1]), M = merge4_cd_cuts((uint64_t)m.n[2] + m.n[3]);
@@ -470,7 +479,8 @@ struct PlanSpec {
     uint32_t grun;
     bool pairs;
     uint32_t noff;  // offsets read (validity check)
-    uint32_t four;  // segments: fan-in 4 steps (PlanArgs::four); the areas are reserved for every segmented plan
+    uint32_t four;  // fan-in 4 steps (PlanArgs::four); the areas are reserved for every segmented plan
+    bool reserve_four;  // explicit runs / buckets: size the areas of both fan-ins (temp queries)
 };
 
 // Bounds of a plan for at most cap keys.
@@ -492,6 +502,16 @@ uint32_t four_steps(uint64_t runs)
     for (; runs > 2; runs = (runs + 3) / 4)
         ++st;
     return st;
+}
+
+// Merge levels of a group of `runs` runs: fan-in 4 steps (when `four`) while
+// more than two remain, then binary ones.
+uint32_t merge_levels(uint64_t runs, bool four)
+{
+    const uint32_t st = four ? four_steps(runs) : 0;
+    for (uint32_t i = 0; i < st; ++i)
+        runs = (runs + 3) / 4;
+    return st + clog2(std::max<uint64_t>(runs, 1));
 }
 
 PlanBounds plan_bounds(const PlanSpec &sp, uint64_t cap)
@@ -518,15 +538,27 @@ PlanBounds plan_bounds(const PlanSpec &sp, uint64_t cap)
         }
     } else {
         const uint32_t nr = sp.kind == kKindRuns ? sp.k : sp.s;
-        const uint32_t merges = clog2(std::max<uint32_t>(nr, 1));
+        // a query reserves the binary pass count (the larger) and the fan-in 4 areas
+        const uint32_t levels = merge_levels(nr, sp.four == 1 && !sp.reserve_four);
         if (sp.kind == kKindRuns)
-            b.PM = merges + (sp.extra_copy ? 1 : 0);
+            b.PM = levels + (sp.extra_copy ? 1 : 0);
         else
-            b.PM = std::max<uint32_t>(merges, 1);
+            b.PM = std::max<uint32_t>(levels, 1);
         for (uint32_t j = 1; j <= b.PM; ++j) {
-            // every group: ceil(nr / 2^j) jobs while merging, else one copy
-            const uint64_t per = j <= merges ? ((uint64_t)nr + (1ull << j) - 1) >> j : 1;
+            // every group: at most ceil(nr / 2^j) binary jobs while merging
+            // (after fan-in 4 steps fewer), else one copy
+            const uint64_t per = j <= levels ? ((uint64_t)nr + (1ull << j) - 1) >> j : 1;
             b.jb[j - 1] = per * sp.G;
+        }
+        if ((sp.four == 1 || sp.reserve_four) && four_steps(nr) <= (uint32_t)kMaxPlan4Passes) {
+            // step j: ceil(nr / 4^j) jobs per group, every job of t keys at most
+            // t / kAbStep + 1 searches and item slots and two more cut records
+            b.PM4 = four_steps(nr);
+            for (uint32_t j = 1; j <= b.PM4; ++j)
+                b.j4b[j - 1] = (((uint64_t)nr + (1ull << (2 * j)) - 1) >> (2 * j)) * sp.G + 1;
+            const uint64_t most = b.PM4 ? b.j4b[0] : 0;
+            b.t4b = b.i4b = (cap + kAbStep - 1) / kAbStep + most;
+            b.r4b = b.i4b + 2 * most;
         }
     }
     for (uint32_t j = 1; j <= b.PM; ++j)
@@ -825,6 +857,19 @@ bcf_status planned_call(const PlanSpec &worst, const PlanSpec &actual, const uin
 
 uint64_t seg_group_min(bool pairs, uint64_t knob) { return knob ? knob : group_run_keys(pairs) / 2; }
 
+// Fan-in 4 steps for the merges of explicit runs (bcf_merge_runs) or of the
+// buckets of the sort by distribution, groups of nr runs: tuning knob
+// merge_fan_in 4 on, 2 off, 0 (auto) from 16 runs per group (decided on the
+// host, which does not know the key count: 2^20 keys in 8 runs merge in
+// 0.146 ms binary against 0.166 ms four-way, 2^24 keys in 16 runs alike, 2^26
+// keys in 16 / 256 / 4096 runs 0.72 / 1.30 / 1.77 ms binary against 0.58 /
+// 1.02 / 1.41 ms); never for more runs than kMaxPlan4Passes steps reduce.
+bool runs_four_way(uint32_t nr)
+{
+    const int f = tuning().merge_fan_in;
+    return (f == 4 || (f == 0 && nr >= 16)) && four_steps(nr) <= (uint32_t)kMaxPlan4Passes;
+}
+
 bcf_status segmented_device(bool pairs, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                             const uint64_t *off, uint32_t nseg, void *temp, uint64_t *temp_bytes, hipStream_t s)
 {
@@ -871,19 +916,24 @@ bcf_status bcf_merge_runs(const uint32_t *keys_in, const uint32_t *vals_in, cons
     if (!run_offsets || k == 0xFFFFFFFFu)
         return BCF_ERR_INVALID;
     const bool pairs = vals_in != nullptr;
-    const uint32_t merges = clog2(k);
+    const bool four = runs_four_way(k);
+    const uint32_t merges = merge_levels(k, four);
     PlanSpec sp{};
     sp.kind = kKindRuns;
     sp.G = 1;
     sp.k = k;
     sp.pairs = pairs;
     sp.noff = k + 1;
+    sp.four = four ? 1u : 0u;
     PlanSpec worst = sp;
-    worst.extra_copy = 1;  // the temp size does not depend on whether the call is in place
+    // the temp size depends neither on whether the call is in place nor on the fan-in
+    worst.extra_copy = 1;
+    worst.four = 0;
+    worst.reserve_four = true;
     const bool inplace = keys_in == keys_out || (pairs && vals_in == vals_out);
-    // in place, a run count whose merges are odd would make the first pass read
-    // and write the output: one more pass copies the result from temp; a lone
-    // run not in place is one copy
+    // in place, a run count whose merge levels are odd would make the first pass
+    // read and write the output: one more pass copies the result from temp; a
+    // lone run not in place is one copy
     sp.extra_copy = merges == 0 ? (inplace ? 0u : 1u) : ((inplace && merges % 2 == 1) ? 1u : 0u);
     if (temp && tuning().check_runs && keys_in) {
         // sortedness of every run, flagged in a spare word of the plan's
@@ -955,7 +1005,11 @@ bcf_status bcf_sort_u32_pb(const uint32_t *keys_in, uint32_t *keys_out, uint64_t
     sp.s = s;
     sp.pivot = pivot_buckets ? 1 : 0;
     sp.noff = nb * s + 1;
-    const uint64_t need_merge = plan_need(sp, n);
+    sp.four = runs_four_way(s) ? 1u : 0u;
+    PlanSpec worst = sp;  // the temp size does not depend on the fan-in
+    worst.four = 0;
+    worst.reserve_four = true;
+    const uint64_t need_merge = plan_need(worst, n);
     const uint64_t d_bytes = a256(n * 4), p_bytes = a256(((uint64_t)nb * s + 1) * 8);
     const uint64_t scratch = std::max(need_runs, std::max(need_dist, need_merge));
     const uint64_t need = d_bytes + p_bytes + scratch;

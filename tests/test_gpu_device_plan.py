@@ -71,6 +71,33 @@ def test_merge_runs_device_offsets_in_place(env, sizes):
     assert np.array_equal(kin.cpu().numpy(), wk) and np.array_equal(vin.cpu().numpy(), wv)
 
 
+@pytest.mark.parametrize("fan_in", [2, 4])
+@pytest.mark.parametrize("k", [3, 4, 5, 16, 17, 64, 200])
+def test_merge_runs_device_offsets_fan_in(env, fan_in, k):
+    """bcf_merge_runs under either fan-in (four-way steps over runs of uneven
+    length, some empty, ties across runs; then binary ones), keys and stable
+    pairs, out of place and in place (an odd level count takes a final copy)."""
+    torch, dev, bcf = env
+    print(f"merge_runs fan_in={fan_in} k={k}", flush=True)
+    rng = np.random.default_rng(k * 10 + fan_in)
+    sizes = [int(x) for x in rng.integers(0, 9000, size=k)]
+    sizes[k // 2] = 0
+    keys, offs = workloads.sorted_runs(sizes, seed=k + 31, dist="dups")
+    n = keys.size
+    vals = np.arange(n, dtype=np.uint32)
+    doff = _dev_offsets(torch, dev, offs)
+    wk, wv = oracle.merge_runs(keys, offs, vals=vals)
+    with bcf.tuning(merge_fan_in=fan_in):
+        out = bcf.merge_runs(torch.from_numpy(keys).to(dev), doff)
+        ko, vo = bcf.merge_runs(torch.from_numpy(keys).to(dev), doff, vals=torch.from_numpy(vals).to(dev))
+        kin = torch.from_numpy(keys).to(dev)
+        vin = torch.from_numpy(vals).to(dev)
+        bcf.merge_runs(kin, doff, vals=vin, keys_out=kin, vals_out=vin)
+    assert np.array_equal(out.cpu().numpy(), wk)
+    assert np.array_equal(ko.cpu().numpy(), wk) and np.array_equal(vo.cpu().numpy(), wv)
+    assert np.array_equal(kin.cpu().numpy(), wk) and np.array_equal(vin.cpu().numpy(), wv)
+
+
 @pytest.mark.parametrize("sizes", [[0], [1], [4096], [4097], [100, 0, 5000, 16384, 16385, 40000, 3],
                                    [70000, 200000, 1, 0, 4096 * 3 + 5], [32768 * 3 + 7]])
 @pytest.mark.parametrize("pairs", [False, True])
@@ -252,13 +279,16 @@ def test_invalid_device_offsets_write_nothing(env, fan_in):
 
 @pytest.mark.parametrize("dist", ["uniform", "distinct16", "zipf", "sorted"])
 @pytest.mark.parametrize("pivot", [True, False])
-def test_sort_pb_c_abi(env, dist, pivot):
-    """The sort by distribution through the C ABI (device-planned bucket merge)
+@pytest.mark.parametrize("fan_in", [0, 2])
+def test_sort_pb_c_abi(env, dist, pivot, fan_in):
+    """The sort by distribution through the C ABI (device-planned bucket merge,
+    four-way steps over each bucket's 33 pieces by default, or binary ones)
     equals the oracle sort."""
     torch, dev, bcf = env
     n = (1 << 21) + 12345
     keys = workloads.keys_u32(dist, n, seed=5)
-    out = bcf.sort_u32_pb(torch.from_numpy(keys).to(dev), P=64, run_keys=1 << 16, pivot_buckets=pivot)
+    with bcf.tuning(merge_fan_in=fan_in):
+        out = bcf.sort_u32_pb(torch.from_numpy(keys).to(dev), P=64, run_keys=1 << 16, pivot_buckets=pivot)
     assert np.array_equal(out.cpu().numpy(), oracle.sort_u32(keys))
 
 
