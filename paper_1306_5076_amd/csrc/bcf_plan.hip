@@ -264,8 +264,11 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_count(PlanArgs a, uint32_t 
 }
 
 // Exclusive prefix sum of v[0, len) in place, v[len] = total (also to *total
-// when set); len = *len_dev when len_dev is set, clamped to cap.  One
-// work-group per array, in chunks of kPlanBlock.
+// when set).  One work-group per array, in chunks of kPlanBlock * kScanPer
+// elements: each thread sums kScanPer consecutive elements, the work-group
+// scans those sums, and each thread writes its elements' prefixes.
+constexpr uint32_t kScanPer = 4;
+
 __device__ void block_scan(uint32_t *v, uint32_t len, uint32_t *total)
 {
     __shared__ uint32_t sh[kPlanBlock];
@@ -273,10 +276,15 @@ __device__ void block_scan(uint32_t *v, uint32_t len, uint32_t *total)
     if (threadIdx.x == 0)
         carry = 0;
     __syncthreads();
-    for (uint32_t base = 0; base < len; base += kPlanBlock) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t x = i < len ? v[i] : 0;
-        sh[threadIdx.x] = x;
+    for (uint32_t base = 0; base < len; base += kPlanBlock * kScanPer) {
+        const uint32_t i0 = base + threadIdx.x * kScanPer;
+        uint32_t x[kScanPer], sum = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < kScanPer; ++e) {
+            x[e] = i0 + e < len ? v[i0 + e] : 0;
+            sum += x[e];
+        }
+        sh[threadIdx.x] = sum;
         __syncthreads();
         for (uint32_t d = 1; d < kPlanBlock; d <<= 1) {
             const uint32_t y = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
@@ -286,8 +294,13 @@ __device__ void block_scan(uint32_t *v, uint32_t len, uint32_t *total)
         }
         const uint32_t incl = sh[threadIdx.x];
         const uint32_t c = carry;
-        if (i < len)
-            v[i] = c + incl - x;
+        uint32_t run = c + incl - sum;  // prefix of this thread's first element
+#pragma unroll
+        for (uint32_t e = 0; e < kScanPer; ++e) {
+            if (i0 + e < len)
+                v[i0 + e] = run;
+            run += x[e];
+        }
         __syncthreads();
         if (threadIdx.x == kPlanBlock - 1)
             carry = c + incl;
