@@ -72,7 +72,7 @@ def test_merge_runs_device_offsets_in_place(env, sizes):
 
 
 @pytest.mark.parametrize("fan_in", [2, 4])
-@pytest.mark.parametrize("k", [3, 4, 5, 16, 17, 64, 200])
+@pytest.mark.parametrize("k", [3, 4, 5, 16, 17, 64, 200, 1000])
 def test_merge_runs_device_offsets_fan_in(env, fan_in, k):
     """bcf_merge_runs under either fan-in (four-way steps over runs of uneven
     length, some empty, ties across runs; then binary ones), keys and stable
