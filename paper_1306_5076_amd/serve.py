@@ -134,6 +134,7 @@ class _Slot:
         self.out = None     # the batch's device outputs (keys, values)
         self.ws = api.Workspace(device)
         self.stream = torch.cuda.Stream(device)
+        self.event = torch.cuda.Event()  # recorded again only once the slot's last batch is complete
         self.done = None
         self.reqs = []
         self.loc = []       # per request: (key lo, key hi, value lo) in the batch buffers
@@ -557,9 +558,11 @@ class SortServer:
         workspace is reused only after the batch's done event has completed,
         whichever stream it ran on."""
         slot.reqs, slot.loc = [r], [(0, r.n, 0)]
-        st = slot.stream if r.ready is not None else r.src
-        with torch.cuda.stream(st):
-            if r.ready is not None:
+        queued = r.ready is not None
+        st = slot.stream if queued else r.src
+        # inline, the submitting stream is already the current one
+        with torch.cuda.stream(st) if queued else contextlib.nullcontext():
+            if queued:
                 st.wait_event(r.ready)
             rk = torch.empty(r.n, dtype=torch.uint32, device=self.device)
             rv = torch.empty(r.n, dtype=torch.uint32, device=self.device) if r.pairs else self._no_values
@@ -572,10 +575,9 @@ class SortServer:
                 api.sort_pairs_u32(r.keys, r.vals, rk, rv, stream=st, workspace=slot.ws)
             else:
                 api.sort_u32(r.keys, out=rk, stream=st, workspace=slot.ws)
-            ev = torch.cuda.Event()
-            ev.record(st)
+            slot.event.record(st)
         slot.out = (rk, rv)
-        slot.done = ev
+        slot.done = slot.event
 
 
 def serve_serial(requests, device="cuda:0", realtime: bool = True, keep_results: bool = True):
