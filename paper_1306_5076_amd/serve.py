@@ -545,9 +545,8 @@ class SortServer:
                 slot.ok.get(nh).copy_(rk[:nh], non_blocking=True)
             if nvh:
                 slot.ov.get(nvh).copy_(rv[:nvh], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(st)
-        slot.done = ev
+            slot.event.record(st)
+        slot.done = slot.event
 
     def _launch_alone(self, slot: _Slot, r: _Request):
         """A device request alone in its batch: sorted or merged from its own
