@@ -370,11 +370,11 @@ typedef struct {
     int32_t merge_fan_in;      /* runs merged per group by a merge pass of the sorts
                                   (bcf_sort_u32, bcf_sort_pairs_u32 and the int32 / float
                                   forms) and of the segmented sorts (device- or host-planned,
-                                  keys or pairs): 0 (default) 4 for key/value sorts, for sorts
+                                  keys or pairs).  0 (default): 4 for key/value sorts, for sorts
                                   of at least 2^24 keys and for segmented sorts of at least
-                                  2^25 keys in total, else 2; 4 or 2 for every size.  A segment takes
-                                  four-way steps while more than two of its runs remain, then
-                                  a binary one.  Four-way passes of the sorts need
+                                  2^25 keys in total, else 2.  4 or 2: that fan-in at every
+                                  size.  A segment takes four-way steps while more than two
+                                  of its runs remain, then a binary one.  Four-way passes of the sorts need
                                   sampled_partition (else 2 is used).  bcf_merge_runs and the
                                   bucket merge of bcf_sort_u32_pb take four-way steps under 4,
                                   and under 0 when a merge (a bucket) has at least 16 runs */
