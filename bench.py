@@ -345,6 +345,22 @@ def bench_segmented(bcf, workloads, torch, dev, count=10000, lo=32, hi=1 << 20, 
     return res
 
 
+def bench_segmented_device(bcf, workloads, torch, dev, count=10000, lo=32, hi=1 << 20, seed=1, reps=3):
+    """The segmented workload of bench_segmented (same arrays) through the
+    device-offset entry point only, under the default tuning: eager calls and
+    graph replays, for a kernel trace of that sort alone."""
+    sizes = workloads.segment_sizes(count, lo=lo, hi=hi, seed=seed)
+    offs = workloads.segment_offsets(sizes)
+    n = int(offs[-1])
+    keys = workloads.draws_u32_torch(seed, n, dev)
+    out = torch.empty_like(keys)
+    ms_dev, ms_graph = _segmented_device_offsets(bcf, torch, dev, keys, out, offs, reps)
+    del keys, out
+    return {"arrays": count, "sizes": [lo, hi], "total_keys": n, "reps": reps,
+            "device_offsets_eager": {"ms": round(ms_dev, 3), "Gkeys_per_s": round(n / ms_dev / 1e6, 3)},
+            "device_offsets_graph": {"ms": round(ms_graph, 3), "Gkeys_per_s": round(n / ms_graph / 1e6, 3)}}
+
+
 def _segmented_device_offsets(bcf, torch, dev, keys, out, offs, reps):
     """Device time of bcf_segmented_sort with its offsets in device memory
     (temp sized once by a query), eager and replayed from one graph."""
@@ -400,6 +416,10 @@ def main():
                     help="only the block-sort ablation at 2^26 keys (one JSON object)")
     ap.add_argument("--pairs", action="store_true",
                     help="only the 2^28 stable key/value sorts, uniform and Zipf keys (one JSON object)")
+    ap.add_argument("--segmented", action="store_true",
+                    help="only the segmented sort (10000 arrays of 32 .. 2^20 keys) through the "
+                         "device-offset entry point (one JSON object)")
+    ap.add_argument("--u64", action="store_true", help="only the 2^26 u64 key sort (one JSON object)")
     ap.add_argument("--reps", type=int, default=5, help="repetitions of the ablation timings")
     ap.add_argument(
         "--copy-calibration",
@@ -439,6 +459,19 @@ def main():
         import workloads
 
         rec = bench_pairs(bcf, workloads, torch, torch.device("cuda:0"), steps=args.steps, warmup=args.warmup)
+        print(json.dumps(rec), flush=True)
+        return
+    if args.segmented or args.u64:
+        import torch
+
+        import paper_1306_5076_amd as bcf
+        import workloads
+
+        dev = torch.device("cuda:0")
+        if args.segmented:
+            rec = bench_segmented_device(bcf, workloads, torch, dev, reps=args.reps)
+        else:
+            rec = bench_u64(bcf, workloads, torch, dev, reps=args.reps)
         print(json.dumps(rec), flush=True)
         return
     if args.block_sort_ablation:

@@ -169,7 +169,36 @@ def _is(kind: str, name: str) -> bool:
     return False
 
 
-def trace_markdown(directory: str, command: str, title: str, n_keys: int | None = None, elem_bytes: int = 4) -> str:
+def _per_call_lines(trace) -> list[str]:
+    """Library launches grouped into calls: a call starts at each launch of
+    the run's first library kernel.  Per kernel: launches per call and median
+    time per call over the calls with the most common launch count."""
+    lib = [r for r in trace if short_name(r["Kernel_Name"]).startswith("bcf::")]
+    if not lib:
+        return []
+    first = lib[0]["Kernel_Name"]
+    calls = []
+    for r in lib:
+        if r["Kernel_Name"] == first:
+            calls.append([])
+        calls[-1].append((short_name(r["Kernel_Name"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    size = statistics.mode(len(c) for c in calls)
+    full = [c for c in calls if len(c) == size]
+    names = list(dict.fromkeys(n for n, _ in full[0]))
+    per = {n: [sum(t for m, t in c if m == n) for c in full] for n in names}
+    count = {n: sum(1 for m, _ in full[0] if m == n) for n in names}
+    total = statistics.median(sum(t for _, t in c) for c in full)
+    lines = ["", f"## One call, by kernel (median over {len(full)} calls of {size} launches)", "",
+             "| kernel | launches per call | median us per call | share of the call |", "|---|---|---|---|"]
+    for n in sorted(names, key=lambda n: -statistics.median(per[n])):
+        med = statistics.median(per[n])
+        lines.append(f"| `{n}` | {count[n]} | {med / 1e3:.1f} | {100 * med / total:.1f} % |")
+    lines.append(f"| all library kernels | {size} | {total / 1e3:.1f} | 100 % |")
+    return lines
+
+
+def trace_markdown(directory: str, command: str, title: str, n_keys: int | None = None, elem_bytes: int = 4,
+                   per_call: bool = False) -> str:
     stats = _rows(directory, "kernel_stats.csv")
     lines = [f"# {title}", "", "Command (repository root on the GPU box, library built in-tree beforehand):", "",
              "    " + command.replace("\n", "\n    "), "", f"Kernel source hash: `{kernel_source_hash()}`", "",
@@ -182,7 +211,10 @@ def trace_markdown(directory: str, command: str, title: str, n_keys: int | None 
         trace = _rows(directory, "kernel_trace.csv")
     except FileNotFoundError:
         trace = []
-    if trace:
+    if trace and per_call:
+        trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+        lines += _per_call_lines(trace)
+    elif trace:
         trace.sort(key=lambda r: int(r["Start_Timestamp"]))
         sorts, cur = [], None
         for r in trace:
@@ -217,6 +249,9 @@ def main(argv=None):
     t.add_argument("--title", default="Kernel trace")
     t.add_argument("--n", type=int, default=None, help="keys per sort, for algorithmic GB/s")
     t.add_argument("--elem-bytes", type=int, default=4, help="bytes per element moved (keys 4, key/value pairs 8)")
+    t.add_argument("--per-call", action="store_true",
+                   help="group the library's launches into calls (each starting at the run's first library "
+                        "kernel) and list time per kernel per call, in place of the block-sort / merge-pass table")
     f = sub.add_parser("traffic")
     f.add_argument("fetch_dir")
     f.add_argument("write_dir")
@@ -238,7 +273,7 @@ def main(argv=None):
         with open(a.out, "w") as fh:
             fh.write(counters_markdown(a.traffic_json, a.lds_json, a.algorithmic_bytes))
     elif a.what == "trace":
-        text = trace_markdown(a.dir, a.command, a.title, a.n, a.elem_bytes)
+        text = trace_markdown(a.dir, a.command, a.title, a.n, a.elem_bytes, a.per_call)
         with open(a.out, "w") as fh:
             fh.write(text)
     else:
