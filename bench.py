@@ -468,6 +468,13 @@ def main():
         import workloads
 
         dev = torch.device("cuda:0")
+        if args.copy_calibration:  # a plain copy of n u32 keys, 3 times, for the traffic counters
+            a = torch.zeros(args.n, dtype=torch.int32, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
         if args.segmented:
             rec = bench_segmented_device(bcf, workloads, torch, dev, reps=args.reps)
         else:
