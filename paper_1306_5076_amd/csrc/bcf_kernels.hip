@@ -1391,18 +1391,18 @@ __device__ __forceinline__ void search_level(uint32_t &lo, uint32_t &hi, uint32_
     }
 }
 
-// Cut searches, four per wave: the 16-lane quarter q of wave w takes task
-// 4w + q; task t of group g is AB cut t + 1 (t < jfull - 1) or CD cut
-// t - jfull + 2.  A quarter first finds the binary split of its cut's own
-// side (three sampled levels, 16 probes per round; the cut position is a
-// multiple of 64, so the first two levels read block samples), reads the
-// cut's key, then counts that key in the other side's two runs with one
-// 8-lane group per run at the same time.  Task 0 of a group also writes the
-// group's end points P[0] and P[J].  The searches are bound by how many
-// waves are in flight more than by their rounds: measured at 2^26 keys, four
-// searches per wave take 13-24 us per launch, two (32-lane quarters) 18-32
-// us, one (64-lane rounds) 28-41 us.
-constexpr int kCutLanesLog = 4;                     // 16 lanes per search
+// Cut searches, eight per wave: the 8-lane part q of wave w takes task
+// 8w + q; task t of group g is AB cut t + 1 (t < jfull - 1) or CD cut
+// t - jfull + 2.  A part first finds the binary split of its cut's own side
+// (three sampled levels, 8 probes per round; the cut position is a multiple
+// of 64, so the first two levels read block samples), reads the cut's key,
+// then counts that key in the other side's two runs with one 4-lane group
+// per run at the same time.  Task 0 of a group also writes the group's end
+// points P[0] and P[J].  The searches are bound by how many are in flight
+// more than by their rounds: measured at 2^26 keys, eight searches per wave
+// take 12-21 us per launch, four (16 lanes each) 13-24 us, two 18-32 us, one
+// (64-lane rounds) 28-41 us, sixteen (4 lanes each) between eight and four.
+constexpr int kCutLanesLog = 3;                     // 8 lanes per search
 constexpr uint32_t kCutLanes = 1u << kCutLanesLog;
 constexpr uint32_t kCutsPerWave = kWave / kCutLanes;
 
