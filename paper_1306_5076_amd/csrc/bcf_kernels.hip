@@ -1021,26 +1021,6 @@ __global__ __launch_bounds__(256) void k_partition(Src src, uint32_t *__restrict
         splits[t] = split;
 }
 
-// The same partition by persistent waves (tiles t, t + 2 x grid waves, ...),
-// for launches whose tile count is only known on the device.
-template <class Src>
-__global__ __launch_bounds__(256) void k_partition_persist(Src src, uint32_t *__restrict__ splits)
-{
-    src.resolve();
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t stride = gridDim.x * (256 / kWave) * 2;
-    for (uint32_t t0 = (blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * 2; t0 < src.ntiles; t0 += stride) {
-        const uint32_t t = t0 + (lane >> 5);
-        const bool valid = t < src.ntiles;
-        MergeItem m = src.get(valid ? t : src.ntiles - 1);
-        if (!valid)
-            m.na = m.nb = m.d0 = 0;
-        const uint32_t split = corank_halfwave(m.ka, m.na, m.ka + m.na, m.nb, m.d0, lane);
-        if (valid && (lane & 31) == 0)
-            splits[t] = split;
-    }
-}
-
 // MODE 0: persistent waves, next tile's loads issued before the current tile
 //         is merged (keys only; pairs fall back to MODE 1);
 // MODE 1: persistent waves, one tile at a time;
@@ -1388,6 +1368,36 @@ __device__ __forceinline__ void search_level(uint32_t &lo, uint32_t &hi, uint32_
                 c0 = cf + 1;
             }
         }
+    }
+}
+
+// The same partition by persistent waves, for launches whose tile count is
+// only known on the device (the binary steps of device-planned segmented
+// sorts and run merges): each split is searched on the keys by four lanes
+// (4-ary rounds, sixteen searches per wave), which fetch fewer lines per
+// round than a half-wave's 32 probes, as for the table cut searches.
+constexpr int kPartLanesLog = 2;
+constexpr uint32_t kPartsPerWave = kWave >> kPartLanesLog;
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_partition_persist(Src src, uint32_t *__restrict__ splits)
+{
+    src.resolve();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t stride = gridDim.x * (256 / kWave) * kPartsPerWave;
+    for (uint32_t t0 = (blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * kPartsPerWave; t0 < src.ntiles;
+         t0 += stride) {
+        const uint32_t t = t0 + (lane >> kPartLanesLog);
+        const bool valid = t < src.ntiles;
+        MergeItem m = src.get(valid ? t : src.ntiles - 1);
+        if (!valid)
+            m.na = m.nb = m.d0 = 0;
+        const uint32_t *A = m.ka, *B = m.ka + m.na;
+        const uint32_t d = m.d0;
+        uint32_t lo = d > m.nb ? d - m.nb : 0, hi = d < m.na ? d : m.na;
+        search_level<1, kPartLanesLog>(lo, hi, lane, [&](uint32_t i) { return A[i] > B[d - 1 - i]; });
+        if (valid && (lane & ((1u << kPartLanesLog) - 1)) == 0)
+            splits[t] = lo;
     }
 }
 
